@@ -1,0 +1,249 @@
+"""Seeded synthetic inputs for the k-point ISDF path.
+
+This module is shared by the FP64 oracle (``oracle/``) and by the HIP path's
+tests and benchmark.  It holds no ISDF arithmetic: it only draws the cell,
+the Bloch orbitals on the unit-cell grid, the interpolation-point indices, the
+fragment coefficients and the request arrival times, all from fixed seeds.
+
+Recipe (stand-ins for the paper's GTO/GTH workloads, which need PySCF):
+
+* cell: cubic, lattice constant ``a`` bohr, uniform grid ``n^3`` in C order,
+  ``r = (i1/n1) a1 + (i2/n2) a2 + (i3/n3) a3``;
+* k-mesh: Gamma-centred ``m1 x m2 x m3``, ``k_j = sum_i (j_i/m_i) b_i`` with
+  ``b = 2 pi A^-T``; k index in C order over ``j``;
+* orbitals: ``phi^k_mu(r) = exp(i k.r) u^k_mu(r)`` with
+  ``u = sum_{|g| <= gmax} c_g exp(i G.r)``, ``G = (2 pi/a) g``,
+  ``c_g ~ N(0,1) exp(-|G|^2 / env)`` (complex normal with Re, Im ~ N(0,1/2)
+  for complex orbitals; real orbitals take Re of the sum), then Loewdin
+  orthonormalised per k with the grid metric ``S = (Omega/N_g) Phi^H Phi``;
+* interpolation points: ``N_IP`` grid indices drawn without replacement with
+  probability proportional to ``rho(r) = sum_k sum_mu |phi^k_mu(r)|^2``,
+  returned sorted;
+* fragments: ``C = Q`` of the QR factorisation of a complex Gaussian
+  ``(N_k N_orb) x n_f`` matrix with the column phases fixed by ``diag(R)``
+  (Haar-distributed orthonormal columns); ``C^k_{mu p} = Q[(k, mu), p]``;
+  sizes uniform on the stated inclusive range;
+* arrivals: exponential inter-arrival times at the stated rate (Poisson).
+
+Every stream is seeded from ``numpy.random.SeedSequence([cfg_id, stream, ...])``.
+"""
+from __future__ import annotations
+
+import dataclasses
+import hashlib
+from typing import Optional
+
+import numpy as np
+
+__all__ = ["Config", "CONFIGS", "get_config", "Inputs", "make_inputs",
+           "make_fragments", "make_arrivals", "kmesh_indices"]
+
+STREAM_ORBITALS = 1
+STREAM_IPS = 2
+STREAM_FRAG_SIZES = 3
+STREAM_FRAG_COEFFS = 4
+STREAM_ARRIVALS = 5
+
+
+@dataclasses.dataclass(frozen=True)
+class Config:
+    name: str
+    cfg_id: int
+    a: float                 # cubic lattice constant, bohr
+    grid: tuple              # (n1, n2, n3)
+    kmesh: tuple             # (m1, m2, m3)
+    n_orb: int
+    n_ip: int
+    gmax: float = 8.0        # plane-wave cutoff |g| <= gmax (integer units)
+    env: float = 4.0         # envelope exp(-|G|^2/env), |G| in bohr^-1
+    real: bool = False       # real orbitals (Gamma-only workloads)
+    n_frag: int = 1
+    frag_lo: int = 0         # fragment sizes uniform on [frag_lo, frag_hi]
+    frag_hi: int = 0
+    arrival_rate: float = 0.0
+
+    @property
+    def n_k(self) -> int:
+        return int(np.prod(self.kmesh))
+
+    @property
+    def n_g(self) -> int:
+        return int(np.prod(self.grid))
+
+    @property
+    def volume(self) -> float:
+        return self.a ** 3
+
+
+# The five workload shapes, plus small cases that the oracle finishes in
+# seconds while still spanning several GPU tiles and ragged tails.
+CONFIGS = {
+    "c1_gamma_16": Config("c1_gamma_16", 1, 6.0, (16, 16, 16), (1, 1, 1), 8, 64,
+                          real=True, n_frag=1, frag_lo=8, frag_hi=8),
+    "c2_k2_24": Config("c2_k2_24", 2, 6.0, (24, 24, 24), (2, 2, 2), 16, 256,
+                       n_frag=1, frag_lo=16, frag_hi=16),
+    "c3_k4_32": Config("c3_k4_32", 3, 6.0, (32, 32, 32), (4, 4, 4), 26, 520,
+                       n_frag=64, frag_lo=12, frag_hi=40),
+    "c4_k6_36": Config("c4_k6_36", 4, 6.0, (36, 36, 36), (6, 6, 6), 40, 800,
+                       n_frag=2000, frag_lo=20, frag_hi=80, arrival_rate=200.0),
+    "c5_k10_40": Config("c5_k10_40", 5, 6.0, (40, 40, 40), (10, 10, 10), 52, 1040,
+                        n_frag=500, frag_lo=20, frag_hi=120),
+    # small parity cases
+    "t_tiny_k1": Config("t_tiny_k1", 101, 4.0, (6, 6, 6), (1, 1, 1), 3, 12,
+                        gmax=1.5, env=2.0, n_frag=1, frag_lo=3, frag_hi=3),
+    "t_tiny_k2": Config("t_tiny_k2", 102, 4.0, (8, 8, 8), (2, 1, 2), 3, 14,
+                        gmax=1.5, env=2.0, n_frag=2, frag_lo=2, frag_hi=4),
+    "t_small_k2": Config("t_small_k2", 103, 5.0, (12, 12, 12), (2, 2, 2), 6, 72,
+                         gmax=2.0, env=3.0, n_frag=3, frag_lo=5, frag_hi=9),
+    "t_small_k3": Config("t_small_k3", 104, 5.0, (12, 12, 12), (3, 2, 3), 7, 90,
+                         gmax=2.0, env=3.0, n_frag=4, frag_lo=4, frag_hi=11),
+    "t_mid_k4": Config("t_mid_k4", 105, 6.0, (16, 16, 16), (2, 2, 4), 10, 150,
+                       gmax=5.0, env=4.0, n_frag=6, frag_lo=6, frag_hi=14),
+}
+
+
+def get_config(name: str) -> Config:
+    return CONFIGS[name]
+
+
+def kmesh_indices(kmesh) -> np.ndarray:
+    """Mesh integers ``j`` of every k point, C order, shape ``[N_k, 3]``."""
+    m1, m2, m3 = kmesh
+    j = np.stack(np.meshgrid(np.arange(m1), np.arange(m2), np.arange(m3),
+                             indexing="ij"), axis=-1)
+    return j.reshape(-1, 3)
+
+
+@dataclasses.dataclass
+class Inputs:
+    cfg: Config
+    lattice: np.ndarray      # [3, 3] rows a1, a2, a3 (bohr)
+    orbitals: np.ndarray     # complex128 [N_k, N_orb, N_g]
+    ip_index: np.ndarray     # int32 [N_IP], sorted grid indices
+
+    def sha256(self) -> str:
+        h = hashlib.sha256()
+        h.update(np.ascontiguousarray(self.orbitals).view(np.uint8).tobytes())
+        h.update(self.ip_index.astype(np.int32).tobytes())
+        return h.hexdigest()
+
+
+def _seed(cfg: Config, *stream) -> np.random.Generator:
+    return np.random.default_rng(np.random.SeedSequence([cfg.cfg_id, *stream]))
+
+
+def _plane_wave_set(cfg: Config):
+    gm = int(np.floor(cfg.gmax))
+    rng = np.arange(-gm, gm + 1)
+    g = np.stack(np.meshgrid(rng, rng, rng, indexing="ij"), -1).reshape(-1, 3)
+    g = g[np.einsum("ij,ij->i", g, g) <= cfg.gmax ** 2 + 1e-9]
+    gvec = g * (2.0 * np.pi / cfg.a)
+    envelope = np.exp(-np.einsum("ij,ij->i", gvec, gvec) / cfg.env)
+    return g, envelope
+
+
+def _orbitals_at_k(cfg: Config, kidx: int, jk: np.ndarray, g, envelope) -> np.ndarray:
+    n1, n2, n3 = cfg.grid
+    rng = _seed(cfg, STREAM_ORBITALS, kidx)
+    npw = g.shape[0]
+    if cfg.real:
+        coef = rng.standard_normal((cfg.n_orb, npw)) * envelope
+    else:
+        coef = (rng.standard_normal((cfg.n_orb, npw))
+                + 1j * rng.standard_normal((cfg.n_orb, npw))) * np.sqrt(0.5) * envelope
+    # Evaluate sum_g c_g exp(2 pi i g.i/n) on the grid by placing the
+    # coefficients (aliased modulo n) and taking an unnormalised inverse DFT.
+    box = np.zeros((cfg.n_orb, n1, n2, n3), dtype=np.complex128)
+    np.add.at(box, (slice(None), g[:, 0] % n1, g[:, 1] % n2, g[:, 2] % n3), coef)
+    u = np.fft.ifftn(box, axes=(1, 2, 3)) * (n1 * n2 * n3)
+    if cfg.real:
+        u = u.real.astype(np.complex128)
+    # Bloch phase exp(i k.r) = exp(2 pi i sum_d j_d i_d / (m_d n_d))
+    m = cfg.kmesh
+    ph = [np.exp(2j * np.pi * jk[d] * np.arange(cfg.grid[d]) / (m[d] * cfg.grid[d]))
+          for d in range(3)]
+    phase = ph[0][:, None, None] * ph[1][None, :, None] * ph[2][None, None, :]
+    phi = (u * phase[None]).reshape(cfg.n_orb, -1)
+    # Loewdin orthonormalisation with the grid metric (Omega/N_g) Phi^H Phi
+    s = (cfg.volume / cfg.n_g) * (phi.conj() @ phi.T)
+    w, v = np.linalg.eigh(s)
+    s_inv_half = (v * (1.0 / np.sqrt(w))) @ v.conj().T
+    return (s_inv_half.T @ phi)
+
+
+def make_orbitals(cfg: Config, k_subset: Optional[np.ndarray] = None) -> np.ndarray:
+    """Bloch orbitals ``[len(k_subset) or N_k, N_orb, N_g]`` (complex128)."""
+    g, envelope = _plane_wave_set(cfg)
+    jks = kmesh_indices(cfg.kmesh)
+    ks = np.arange(cfg.n_k) if k_subset is None else np.asarray(k_subset)
+    out = np.empty((len(ks), cfg.n_orb, cfg.n_g), dtype=np.complex128)
+    for i, k in enumerate(ks):
+        out[i] = _orbitals_at_k(cfg, int(k), jks[k], g, envelope)
+    return out
+
+
+def make_ip_index(cfg: Config, orbitals: np.ndarray) -> np.ndarray:
+    rho = np.einsum("kmr,kmr->r", orbitals.conj(), orbitals).real
+    p = rho / rho.sum()
+    rng = _seed(cfg, STREAM_IPS)
+    idx = rng.choice(cfg.n_g, size=cfg.n_ip, replace=False, p=p)
+    return np.sort(idx).astype(np.int32)
+
+
+def make_inputs(cfg, n_ip: Optional[int] = None) -> Inputs:
+    """Cell, orbitals and interpolation points of a workload.
+
+    ``n_ip`` overrides the configured count (``n_ip = N_g`` selects the whole
+    grid, in order)."""
+    if isinstance(cfg, str):
+        cfg = get_config(cfg)
+    orb = make_orbitals(cfg)
+    if n_ip is not None and n_ip != cfg.n_ip:
+        cfg = dataclasses.replace(cfg, n_ip=int(n_ip))
+    if cfg.n_ip == cfg.n_g:
+        ip = np.arange(cfg.n_g, dtype=np.int32)
+    else:
+        ip = make_ip_index(cfg, orb)
+    lattice = np.eye(3) * cfg.a
+    return Inputs(cfg, lattice, orb, ip)
+
+
+def fragment_sizes(cfg: Config, n_frag: Optional[int] = None) -> np.ndarray:
+    n = cfg.n_frag if n_frag is None else n_frag
+    rng = _seed(cfg, STREAM_FRAG_SIZES)
+    return rng.integers(cfg.frag_lo, cfg.frag_hi + 1, size=n).astype(np.int64)
+
+
+def make_fragment(cfg: Config, f: int, n_f: int) -> np.ndarray:
+    """Coefficients ``C[k, mu, p]`` (complex128 ``[N_k, N_orb, n_f]``)."""
+    rng = _seed(cfg, STREAM_FRAG_COEFFS, f)
+    n = cfg.n_k * cfg.n_orb
+    if n_f > n:
+        raise ValueError("fragment larger than the orbital space")
+    z = (rng.standard_normal((n, n_f)) + 1j * rng.standard_normal((n, n_f))) * np.sqrt(0.5)
+    q, r = np.linalg.qr(z)
+    d = np.diag(r)
+    q = q * (d / np.abs(d))[None, :]
+    if cfg.real and cfg.n_k == 1:
+        # Real Gamma-only workloads: the fragment of all orbitals is the
+        # identity; smaller ones use real orthonormal coefficients.
+        if n_f == n:
+            return np.eye(n, dtype=np.complex128).reshape(1, n, n)
+        zr = rng.standard_normal((n, n_f))
+        q, r = np.linalg.qr(zr)
+        q = (q * np.sign(np.diag(r))[None, :]).astype(np.complex128)
+    return q.reshape(cfg.n_k, cfg.n_orb, n_f)
+
+
+def make_fragments(cfg: Config, n_frag: Optional[int] = None):
+    sizes = fragment_sizes(cfg, n_frag)
+    return [make_fragment(cfg, f, int(nf)) for f, nf in enumerate(sizes)]
+
+
+def make_arrivals(cfg: Config, n: int, rate: Optional[float] = None) -> np.ndarray:
+    """Arrival times (seconds, from 0) of ``n`` requests, Poisson at ``rate``/s."""
+    lam = cfg.arrival_rate if rate is None else rate
+    rng = _seed(cfg, STREAM_ARRIVALS)
+    if lam <= 0:
+        return np.zeros(n)
+    return np.cumsum(rng.exponential(1.0 / lam, size=n)) - 0.0

@@ -1,0 +1,335 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test is chosen so that a plausible mistake in the oracle (a dropped
+term, a wrong sign or index, a transposed operand, a missing conjugate or
+normalisation) fails at least one of them:
+
+* Poisson normalisation: the periodised Gaussian self-energy closed form
+  (Ewald identity, Madelung constant from an explicit lattice sum);
+* DFT conventions and the G+q box: explicit double sums on tiny cells;
+* exactness: interpolation points = the whole grid (or a set spanning the
+  pair space) reproduce FFT-Poisson ERIs (eqs. (2)-(3) with zero residual);
+* k machinery: k-point results (eqs. (4)-(8), (17)-(20)) equal the plain
+  Gamma-point supercell ISDF, which has no k sums at all;
+* eq. (8): the xi route equals the Pi W Pi = V route;
+* invariants: Hermiticity / PSD, q -> -q conjugation, ERI permutational
+  symmetry, crystal-momentum conservation (eq. (9)), covariance.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import isdf_inputs as inp
+from oracle import geometry as geo
+from oracle import kpoint as ko
+from oracle import poisson
+from oracle import supercell as sc
+
+
+def _case(name, n_ip=None):
+    d = inp.make_inputs(name, n_ip=n_ip)
+    return d
+
+
+def _rel(a, b):
+    return np.max(np.abs(a - b)) / np.max(np.abs(b))
+
+
+# --------------------------------------------------------------------------
+# Poisson normalisation
+# --------------------------------------------------------------------------
+def test_madelung_independent_of_split():
+    z1 = poisson.madelung_simple_cubic(eta=2.0)
+    z2 = poisson.madelung_simple_cubic(eta=3.0, nreal=5, nrec=10)
+    assert abs(z1 - z2) < 1e-11
+    assert 2.83 < z1 < 2.84
+
+
+def test_gaussian_self_energy_closed_form():
+    length, sigma, n = 10.0, 0.5, 64
+    lattice = np.eye(3) * length
+    frac = geo.grid_frac((n, n, n))
+    pos = frac * length
+    rho = np.zeros(n ** 3)
+    norm = (2 * np.pi * sigma ** 2) ** -1.5
+    for i in (-1, 0, 1):
+        for j in (-1, 0, 1):
+            for k in (-1, 0, 1):
+                d = pos - (np.array([i, j, k]) + 0.5) * length
+                rho += norm * np.exp(-np.einsum("ij,ij->i", d, d) / (2 * sigma ** 2))
+    shape = (n, n, n)
+    rhat = np.fft.fftn(rho.reshape(shape)).reshape(-1)
+    kern = geo.coulomb_supercell(lattice, shape, (1, 1, 1), "supercell")
+    refl = poisson.reflect_index(shape)
+    val = poisson.coulomb_pair_sum(rhat[refl], rhat, kern, length ** 3, n ** 3).real
+    ref = poisson.gaussian_self_energy_closed_form(
+        sigma, length, poisson.madelung_simple_cubic())
+    assert abs(val - ref) / abs(ref) < 1e-10
+
+
+# --------------------------------------------------------------------------
+# DFT conventions / box: explicit sums on a tiny cell
+# --------------------------------------------------------------------------
+def _explicit_kpoint_box_eri(d, coeffs):
+    """(pq|rs) with the G+q box summed explicitly (no FFT, no index tables)."""
+    cfg = d.cfg
+    lat = d.lattice
+    phi_s = sc.supercell_orbitals(d.orbitals, cfg.grid, cfg.kmesh)
+    psi = sc.fragment_orbitals(phi_s, coeffs)
+    shape = tuple(cfg.grid[i] * cfg.kmesh[i] for i in range(3))
+    xs_frac = geo.grid_frac(shape)                      # supercell fractions
+    x_cart = xs_frac @ geo.supercell_lattice(lat, cfg.kmesh)
+    b = geo.reciprocal(lat)
+    nf = psi.shape[0]
+    rho = (psi.conj()[:, None, :] * psi[None, :, :]).reshape(nf * nf, -1)
+    vol_s = abs(np.linalg.det(geo.supercell_lattice(lat, cfg.kmesh)))
+    ns = psi.shape[1]
+    eri = np.zeros((nf * nf, nf * nf), dtype=np.complex128)
+    for jq in geo.kmesh_indices(cfg.kmesh):
+        qf = np.array([((jq[a] + cfg.kmesh[a] // 2) % cfg.kmesh[a] - cfg.kmesh[a] // 2)
+                       / cfg.kmesh[a] for a in range(3)])
+        for g1 in range(-(cfg.grid[0] // 2), cfg.grid[0] - cfg.grid[0] // 2):
+            for g2 in range(-(cfg.grid[1] // 2), cfg.grid[1] - cfg.grid[1] // 2):
+                for g3 in range(-(cfg.grid[2] // 2), cfg.grid[2] - cfg.grid[2] // 2):
+                    kv = (np.array([g1, g2, g3]) + qf) @ b
+                    k2 = kv @ kv
+                    if k2 < 1e-14:
+                        continue
+                    e = np.exp(-1j * (x_cart @ kv))
+                    fk = rho @ e                       # rhohat(K)
+                    fmk = rho @ e.conj()               # rhohat(-K)
+                    eri += (4 * np.pi / k2) * np.outer(fk, fmk)
+    return (vol_s / ns ** 2) * eri.reshape(nf, nf, nf, nf)
+
+
+def test_exact_eri_matches_explicit_sums_tiny():
+    d = _case("t_tiny_k2")
+    coeffs = inp.make_fragment(d.cfg, 0, 3)
+    phi_s = sc.supercell_orbitals(d.orbitals, d.cfg.grid, d.cfg.kmesh)
+    psi = sc.fragment_orbitals(phi_s, coeffs)
+    fft_eri = sc.exact_eri(psi, d.lattice, d.cfg.grid, d.cfg.kmesh, box="kpoint")
+    brute = _explicit_kpoint_box_eri(d, coeffs)
+    assert _rel(fft_eri, brute) < 1e-13
+
+
+def test_coulomb_kernel_matches_explicit_dft_tiny():
+    d = _case("t_tiny_k2")
+    cfg = d.cfg
+    rng = np.random.default_rng(7)
+    f = rng.standard_normal((5, cfg.n_g)) + 1j * rng.standard_normal((5, cfg.n_g))
+    b = geo.reciprocal(d.lattice)
+    r_cart = geo.grid_frac(cfg.grid) @ d.lattice
+    for q in range(cfg.n_k):
+        w = ko.coulomb_kernel_of(f, d.lattice, cfg.grid, cfg.kmesh, q)
+        jq = geo.kmesh_indices(cfg.kmesh)[q]
+        qf = np.array([((jq[a] + cfg.kmesh[a] // 2) % cfg.kmesh[a] - cfg.kmesh[a] // 2)
+                       / cfg.kmesh[a] for a in range(3)])
+        ref = np.zeros((5, 5), dtype=np.complex128)
+        h = cfg.grid[0] // 2
+        for g1 in range(-h, h):
+            for g2 in range(-h, h):
+                for g3 in range(-h, h):
+                    kv = (np.array([g1, g2, g3]) + qf) @ b
+                    k2 = kv @ kv
+                    if k2 < 1e-14:
+                        continue
+                    fh = f @ np.exp(-1j * (r_cart @ kv))
+                    ref += (4 * np.pi / k2) * np.outer(fh, fh.conj())
+        ref *= cfg.volume / cfg.n_g ** 2
+        assert _rel(w, ref) < 1e-13
+
+
+# --------------------------------------------------------------------------
+# Exactness limits
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("name", ["t_tiny_k1", "t_tiny_k2"])
+def test_full_grid_ips_reproduce_exact_eri(name):
+    cfg = inp.get_config(name)
+    d = _case(name, n_ip=cfg.n_g)
+    coeffs = inp.make_fragment(d.cfg, 0, 3)
+    x, pi, eta, w = ko.fit_and_kernel(d.orbitals, d.ip_index, d.lattice,
+                                      d.cfg.grid, d.cfg.kmesh)
+    isdf = ko.fragment_eri(x, coeffs, w, d.cfg.kmesh)
+    phi_s = sc.supercell_orbitals(d.orbitals, d.cfg.grid, d.cfg.kmesh)
+    psi = sc.fragment_orbitals(phi_s, coeffs)
+    exact = sc.exact_eri(psi, d.lattice, d.cfg.grid, d.cfg.kmesh, box="kpoint")
+    assert _rel(isdf, exact) < 1e-12
+    # The Gamma-point supercell form with the plain supercell box is exact too.
+    ex_s = sc.exact_eri(psi, d.lattice, d.cfg.grid, d.cfg.kmesh, box="supercell")
+    g_s = sc.gamma_isdf_eri(d.orbitals, d.ip_index, coeffs, d.lattice, d.cfg.grid,
+                            d.cfg.kmesh, box="supercell")
+    assert _rel(g_s, ex_s) < 1e-12
+
+
+def test_c1_ips_span_pair_space_exact():
+    """Workload 1 (Gamma, 8 real orbitals, 64 points): the metric has rank
+    36 = 8*9/2 and the ISDF ERIs equal the FFT-Poisson ERIs."""
+    d = _case("c1_gamma_16")
+    coeffs = inp.make_fragment(d.cfg, 0, 8)
+    x, pi, eta, w = ko.fit_and_kernel(d.orbitals, d.ip_index, d.lattice,
+                                      d.cfg.grid, d.cfg.kmesh)
+    wv = np.linalg.eigvalsh(pi[0])
+    assert int((wv > 1e-12 * wv.max()).sum()) == 36
+    isdf = ko.fragment_eri(x, coeffs, w, d.cfg.kmesh)
+    phi_s = sc.supercell_orbitals(d.orbitals, d.cfg.grid, d.cfg.kmesh)
+    psi = sc.fragment_orbitals(phi_s, coeffs)
+    exact = sc.exact_eri(psi, d.lattice, d.cfg.grid, d.cfg.kmesh, box="kpoint")
+    assert np.max(np.abs(isdf - exact)) < 1e-12
+    # real orbitals: 8-fold symmetry and a real tensor
+    assert np.max(np.abs(isdf.imag)) < 1e-14
+    v = isdf.real
+    for perm in [(1, 0, 2, 3), (0, 1, 3, 2), (2, 3, 0, 1), (1, 0, 3, 2)]:
+        assert np.max(np.abs(v - v.transpose(perm))) < 1e-14
+
+
+# --------------------------------------------------------------------------
+# k machinery: k-point form == Gamma-point supercell form
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("name", ["t_tiny_k1", "t_tiny_k2", "t_small_k2"])
+def test_kpoint_equals_supercell_isdf(name):
+    d = _case(name)
+    cfg = d.cfg
+    coeffs = inp.make_fragment(cfg, 0, min(4, cfg.n_k * cfg.n_orb))
+    x, pi, eta, w = ko.fit_and_kernel(d.orbitals, d.ip_index, d.lattice, cfg.grid, cfg.kmesh)
+    kp = ko.fragment_eri(x, coeffs, w, cfg.kmesh)
+    gs = sc.gamma_isdf_eri(d.orbitals, d.ip_index, coeffs, d.lattice, cfg.grid,
+                           cfg.kmesh, box="kpoint")
+    assert _rel(kp, gs) < 1e-11
+
+
+def test_metric_blocks_are_supercell_metric():
+    """Pi^q / N_k are the Fourier blocks of the block-circulant supercell
+    metric: sum_D Pcal_{(I,D),(J,0)} exp(i q.D) = Pi^q_{IJ} / N_k."""
+    d = _case("t_small_k2")
+    cfg = d.cfg
+    x = ko.ip_values(d.orbitals, d.ip_index)
+    pi = ko.metric_k(x, cfg.kmesh)
+    phi_s = sc.supercell_orbitals(d.orbitals, cfg.grid, cfg.kmesh)
+    psi_c = phi_s.reshape(-1, phi_s.shape[-1]) / np.sqrt(cfg.n_k)
+    xs = sc.supercell_ip_index(d.ip_index, cfg.grid, cfg.kmesh).reshape(cfg.n_k, cfg.n_ip)
+    j = geo.kmesh_indices(cfg.kmesh)
+    m = np.asarray(cfg.kmesh)
+    for q in range(cfg.n_k):
+        blk = np.zeros((cfg.n_ip, cfg.n_ip), dtype=np.complex128)
+        for dd in range(cfg.n_k):
+            g = psi_c[:, xs[dd]].T @ psi_c[:, xs[0]].conj()
+            ph = np.exp(2j * np.pi * np.sum(j[q] * j[dd] / m))
+            blk += np.abs(g) ** 2 * ph
+        assert _rel(blk, pi[q] / cfg.n_k) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# eq. (8): both routes to W
+# --------------------------------------------------------------------------
+def test_zeta_route_equals_v_route():
+    d = _case("t_small_k3")
+    cfg = d.cfg
+    x = ko.ip_values(d.orbitals, d.ip_index)
+    pi = ko.metric_k(x, cfg.kmesh)
+    eta = ko.rhs(x, d.orbitals, cfg.kmesh, list(range(cfg.n_k)))
+    wz = ko.kernel_zeta_route(pi, eta, d.lattice, cfg.grid, cfg.kmesh)
+    wv = ko.kernel_v_route(pi, eta, d.lattice, cfg.grid, cfg.kmesh)
+    assert _rel(wz, wv) < 1e-10
+
+
+# --------------------------------------------------------------------------
+# invariants
+# --------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def small_fit():
+    d = _case("t_small_k3")
+    cfg = d.cfg
+    x, pi, eta, w = ko.fit_and_kernel(d.orbitals, d.ip_index, d.lattice, cfg.grid, cfg.kmesh)
+    return d, x, pi, eta, w
+
+
+def test_metric_and_kernel_hermitian_psd(small_fit):
+    d, x, pi, eta, w = small_fit
+    # W = Pi^+ V Pi^+ carries the rounding of the pseudo-inverse, amplified by
+    # cond(Pi) (~1e3 here): Hermitian to ~1e-11 relative, Pi to ~1e-15.
+    for q in range(pi.shape[0]):
+        for mat, tol in ((pi[q], 1e-14), (w[q], 1e-11)):
+            assert np.max(np.abs(mat - mat.conj().T)) < tol * np.max(np.abs(mat))
+            ev = np.linalg.eigvalsh(0.5 * (mat + mat.conj().T))
+            assert ev.min() > -1e-12 * ev.max()
+
+
+def test_minus_q_conjugation(small_fit):
+    d, x, pi, eta, w = small_fit
+    cfg = d.cfg
+    mq = geo.minus_q(cfg.kmesh)
+    jq = geo.kmesh_indices(cfg.kmesh)
+    m = np.asarray(cfg.kmesh)
+    for q in range(cfg.n_k):
+        assert _rel(pi[mq[q]], pi[q].conj()) < 1e-13
+        assert _rel(eta[mq[q]], eta[q].conj()) < 1e-13
+        on_boundary = np.any((m % 2 == 0) & (jq[q] == m // 2))
+        if not on_boundary:
+            assert _rel(w[mq[q]], w[q].conj()) < 1e-11
+
+
+def test_eri_symmetries_and_psd(small_fit):
+    d, x, pi, eta, w = small_fit
+    coeffs = inp.make_fragment(d.cfg, 1, 7)
+    v = ko.fragment_eri(x, coeffs, w, d.cfg.kmesh)
+    nf = v.shape[0]
+    assert _rel(v.transpose(2, 3, 0, 1), v) < 1e-12           # (pq|rs) = (rs|pq)
+    assert _rel(v.transpose(1, 0, 3, 2).conj(), v) < 1e-12    # (qp|sr)^* = (pq|rs)
+    m = v.transpose(0, 1, 3, 2).reshape(nf * nf, nf * nf)     # M_{(pq),(sr)}
+    assert np.max(np.abs(m - m.conj().T)) < 1e-12 * np.max(np.abs(m))
+    ev = np.linalg.eigvalsh(0.5 * (m + m.conj().T))
+    assert ev.min() > -1e-12 * ev.max()
+
+
+def test_crystal_momentum_conservation(small_fit):
+    d, x, pi, eta, w = small_fit
+    cfg = d.cfg
+    nk, norb = cfg.n_k, cfg.n_orb
+    rng = np.random.default_rng(3)
+    picks = [(int(rng.integers(nk)), int(rng.integers(norb))) for _ in range(5)]
+    coeffs = np.zeros((nk, norb, len(picks)), dtype=np.complex128)
+    for p, (k, mu) in enumerate(picks):
+        coeffs[k, mu, p] = 1.0
+    v = ko.fragment_eri(x, coeffs, w, cfg.kmesh)
+    j = geo.kmesh_indices(cfg.kmesh)
+    m = np.asarray(cfg.kmesh)
+    nz = 0
+    for p in range(5):
+        for q in range(5):
+            for r in range(5):
+                for s in range(5):
+                    kp, kq, kr, ks = (picks[i][0] for i in (p, q, r, s))
+                    cons = np.all((j[kq] - j[kp] + j[ks] - j[kr]) % m == 0)
+                    if not cons:
+                        assert abs(v[p, q, r, s]) < 1e-15
+                    else:
+                        nz += 1
+                        ref = ko.thc_kpoint_eri(x, w, cfg.kmesh, kp, picks[p][1], kq,
+                                                picks[q][1], kr, picks[r][1], ks,
+                                                picks[s][1]) / nk
+                        assert abs(v[p, q, r, s] - ref) < 1e-13 * max(1.0, abs(ref))
+    assert nz > 0
+
+
+def test_covariance(small_fit):
+    d, x, pi, eta, w = small_fit
+    cfg = d.cfg
+    c = inp.make_fragment(cfg, 2, 6)
+    v = ko.fragment_eri(x, c, w, cfg.kmesh)
+    # lattice translation R0: C^k -> exp(i k.R0) C^k leaves V unchanged
+    j = geo.kmesh_indices(cfg.kmesh)
+    r0 = np.array([1, 0, 2])
+    ph = np.exp(2j * np.pi * (j * r0 / np.asarray(cfg.kmesh)).sum(-1))
+    vt = ko.fragment_eri(x, c * ph[:, None, None], w, cfg.kmesh)
+    assert _rel(vt, v) < 1e-12
+    # unitary rotation of the fragment orbitals
+    rng = np.random.default_rng(11)
+    z = rng.standard_normal((6, 6)) + 1j * rng.standard_normal((6, 6))
+    u, _ = np.linalg.qr(z)
+    vu = ko.fragment_eri(x, np.einsum("kmp,pa->kma", c, u), w, cfg.kmesh)
+    ref = np.einsum("pqrs,pa,qb,rc,sd->abcd", v, u.conj(), u, u.conj(), u)
+    assert _rel(vu, ref) < 1e-12
+    # sub-fragment = sub-block
+    vs = ko.fragment_eri(x, c[:, :, 1:4], w, cfg.kmesh)
+    assert _rel(vs, v[1:4, 1:4, 1:4, 1:4]) < 1e-12
