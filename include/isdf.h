@@ -1,0 +1,202 @@
+/*
+ * isdf.h -- C ABI of the MI355X (gfx950) k-point ISDF library.
+ *
+ * The library evaluates, on one GPU, the hot path of translational-symmetry
+ * adapted interpolative separable density fitting (k-point FFTISDF):
+ *
+ *   isdf_create          orbitals phi^k_mu(r) on the unit-cell grid plus the
+ *                        interpolation points r_I (section "Periodic k-point
+ *                        FFTISDF representation of integrals", eq. (1)-(2));
+ *   isdf_fit             interpolating vectors X^k, metric Pi^q (eq. (4)),
+ *                        right-hand side eta^q (eq. (5)), both as convolutions
+ *                        over k (Algorithm 1), and the FP64 pivoted Cholesky
+ *                        factor of every Pi^q (the solve of eq. (3));
+ *   isdf_coulomb_kernel  W^q from V^q = Coulomb(eta^q) and Pi W Pi = V
+ *                        (eqs. (6)-(8)), grid FFTs with the 4 pi/|G+q|^2 kernel;
+ *   isdf_fragment_eri    fragment ERIs from W^q and fragment coefficients
+ *                        C^k_{mu p} (eqs. (17), (19)-(20), Algorithm 2);
+ *   isdf_submit/poll     the same as served requests (continuous batching).
+ *
+ * Conventions (the paper leaves them implicit; they are fixed here):
+ *   - complex numbers are interleaved (re, im) float64 pairs ("c128");
+ *   - lattice rows a1, a2, a3 in bohr; grid index i = (i1*n2 + i2)*n3 + i3 is
+ *     the point (i1/n1) a1 + (i2/n2) a2 + (i3/n3) a3;
+ *   - the k mesh is Gamma-centred, k index = (j1*m2 + j2)*m3 + j3 is the point
+ *     sum_d (j_d/m_d) b_d; q is the mesh difference of pair momenta (mod m),
+ *     wrapped to [-1/2, 1/2) per axis inside the Coulomb kernel, G runs over
+ *     the unit-cell DFT box [-n/2, n/2) and the G+q = 0 term is dropped;
+ *   - a superscript -k in the paper is read as the complex conjugate at k;
+ *   - ERIs are in Hartree, chemists' notation with the conjugate on p and r:
+ *       (pq|rs) = int int conj(psi_p) psi_q (x) conj(psi_r) psi_s (y) / |x-y|,
+ *     psi_p = N_k^{-1/2} sum_k sum_mu C^k_{mu p} phi^k_mu (eq. (17)), output
+ *     layout [p][q][r][s] C order (the paper's V_pqrs is (qp|sr) here).
+ *
+ * Every call returns an isdf_status; 0 is success.  Calls never abort and
+ * never throw; on failure the context records a message that
+ * isdf_last_error() returns.  A context is used by one host thread at a time,
+ * except isdf_submit / isdf_poll / isdf_cancel, which are thread-safe.
+ */
+#ifndef ISDF_H
+#define ISDF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct isdf_ctx_s* isdf_ctx;
+
+typedef enum {
+  ISDF_OK = 0,
+  ISDF_E_INVALID = -1,   /* bad argument (null pointer, size, layout)           */
+  ISDF_E_NOMEM = -2,     /* memory planner or device allocation refused         */
+  ISDF_E_STATE = -3,     /* call out of order (e.g. ERIs before the kernel)     */
+  ISDF_E_NUMERIC = -4,   /* Cholesky breakdown, non-finite value (q in message) */
+  ISDF_E_DEVICE = -5,    /* HIP runtime error                                   */
+  ISDF_E_BUSY = -6,      /* request queue full                                  */
+  ISDF_E_NOTFOUND = -7,  /* unknown ticket                                      */
+  ISDF_E_CANCELLED = -8  /* request was cancelled                               */
+} isdf_status;
+
+typedef enum {
+  ISDF_FP64 = 0,        /* all GEMMs in FP64 MFMA                                  */
+  ISDF_MIXED_FP32 = 1,  /* W^q and fragment GEMMs in FP32 MFMA, FP32 accumulation
+                           within one q (or one K segment), FP64 across them     */
+  ISDF_MIXED_BF16X3 = 2 /* same GEMMs with operands split hi+lo in bf16 and three
+                           bf16 MFMA products (hi*hi + hi*lo + lo*hi)           */
+} isdf_precision;
+
+/* flags for isdf_create */
+#define ISDF_INPUT_DEVICE 0x1u   /* orbitals / ip_index are device pointers      */
+#define ISDF_NO_PIVOT 0x2u       /* plain Cholesky: a singular Pi^q is an error  */
+
+/* request states reported by isdf_poll */
+#define ISDF_REQ_QUEUED 0
+#define ISDF_REQ_RUNNING 1
+#define ISDF_REQ_DONE 2
+#define ISDF_REQ_FAILED 3
+#define ISDF_REQ_CANCELLED 4
+
+/* fragment buffers: C and eri are device pointers when this bit is set in
+ * isdf_fragment_eri's flags / isdf_request.flags, host pointers otherwise */
+#define ISDF_FRAG_DEVICE 0x1u
+
+/*
+ * Create a context (eq. (1)-(2) inputs).
+ *   lattice   [3][3] float64, rows a1 a2 a3 (bohr), host memory.
+ *   grid      [3] grid points per axis (each 2..64, factorisable into 2,3,5,7).
+ *   kmesh     [3] k points per axis (each 1..16).
+ *   n_orb     orbitals per k point (1..256).
+ *   orbitals  c128 [N_k][n_orb][N_g], host or device (ISDF_INPUT_DEVICE).
+ *   ip_index  int32 [n_ip] grid indices r_I (0 <= r_I < N_g, distinct), caller
+ *             selected (the paper selects them by pivoted Cholesky).
+ *   n_ip      number of interpolation points (1..4096).
+ *   hip_stream  hipStream_t every call of this context launches on (0 = null
+ *               stream); the caller keeps it alive until isdf_destroy.
+ * The library copies orbitals and ip_index into its own device memory; the
+ * caller may free them on return.  Error: ISDF_E_INVALID, ISDF_E_NOMEM,
+ * ISDF_E_DEVICE; *out is NULL on failure.
+ */
+isdf_status isdf_create(isdf_ctx* out, const double* lattice, const int32_t grid[3],
+                        const int32_t kmesh[3], int32_t n_orb, const void* orbitals,
+                        const int32_t* ip_index, int32_t n_ip, uint32_t flags,
+                        void* hip_stream);
+
+/*
+ * The fit: X^k_{I mu} = phi^k_mu(r_I); T^k = X^k X^{k H}; Pi^q by the k
+ * convolution of Algorithm 1 (|FFT_k^{-1} T|^2, FFT_k); eta^q_I(r) by the same
+ * convolution of T^k_I(r) = sum_mu X^k_{I mu} conj(phi^k_mu(r)), r-tiled; then
+ * the FP64 Cholesky factor of every Pi^q with diagonal pivoting (relative
+ * tolerance 1e-13; the rank is reported by isdf_stats).  Synchronous.
+ * Error: ISDF_E_NUMERIC when ISDF_NO_PIVOT is set and a Pi^q is singular.
+ */
+isdf_status isdf_fit(isdf_ctx ctx);
+
+/*
+ * W^q for all q (eqs. (6)-(8)): grid FFT of eta^q(r) exp(-i q.r), scaled by
+ * sqrt(Omega 4 pi/|G+q|^2)/N_g (FP64), V^q = eta~ eta~^H (GEMM in `prec`),
+ * W^q = Pi^{q+} V^q Pi^{q+} by FP64 triangular solves with the factor of
+ * isdf_fit.  Consumes eta (overwritten in place).  Synchronous.
+ * Error: ISDF_E_STATE before isdf_fit.
+ */
+isdf_status isdf_coulomb_kernel(isdf_ctx ctx, isdf_precision prec);
+
+/* Test hooks: copy Pi^q / W^q (c128 [n_ip][n_ip]) or X^k (c128 [n_ip][n_orb])
+ * to host memory `out`.  Error: ISDF_E_STATE if not computed yet,
+ * ISDF_E_INVALID for q or k out of range. */
+isdf_status isdf_get_metric(isdf_ctx ctx, int32_t q, void* out);
+isdf_status isdf_get_kernel(isdf_ctx ctx, int32_t q, void* out);
+isdf_status isdf_get_ivs(isdf_ctx ctx, int32_t k, void* out);
+/* Copy eta^q (c128 [n_ip][N_g]) to host; valid between isdf_fit and
+ * isdf_coulomb_kernel. */
+isdf_status isdf_get_rhs(isdf_ctx ctx, int32_t q, void* out);
+
+/*
+ * Fragment ERIs for a batch of fragments in one pass (eqs. (19)-(20),
+ * Algorithm 2): T^k = X^k C^k, k -> R transform, outer products, R -> q
+ * transform giving R^q_{I,pq}, U^q = W^q R^q, then the Hermitian contraction
+ * sum_q R^{q H}-weighted products accumulated over q (FP64 accumulation across
+ * q in every precision), one grouped persistent launch for all fragments.
+ *   n_frag    number of fragments (>= 1).
+ *   n_f       [n_frag] orbitals per fragment (>= 1), host memory.
+ *   C         [n_frag] pointers, fragment f: c128 [N_k][n_orb][n_f[f]].
+ *   eri       [n_frag] pointers, fragment f: c128 [n_f]^4 output.
+ *   flags     ISDF_FRAG_DEVICE if C[f] / eri[f] are device pointers.
+ * Synchronous.  Error: ISDF_E_STATE before isdf_coulomb_kernel,
+ * ISDF_E_NOMEM if the batch exceeds the memory budget (split it).
+ */
+isdf_status isdf_fragment_eri(isdf_ctx ctx, isdf_precision prec, int32_t n_frag,
+                              const int32_t* n_f, const void* const* C, void* const* eri,
+                              uint32_t flags);
+
+/*
+ * Served requests (continuous batching).  isdf_serve_start launches the
+ * serving thread; isdf_submit queues one fragment (non-blocking) and returns
+ * a ticket; the thread admits queued requests into batches while their HBM
+ * footprint fits the budget and up to `max_inflight` batches are on the GPU,
+ * so requests that arrive while others run join the next batch.  C and eri
+ * are caller-owned and must stay valid until poll reports DONE, FAILED or
+ * CANCELLED.  latency = submit -> completion observed (host monotonic clock).
+ */
+typedef struct {
+  int32_t n_f;
+  const void* C;        /* c128 [N_k][n_orb][n_f] */
+  void* eri;            /* c128 [n_f]^4           */
+  int32_t prec;         /* isdf_precision         */
+  uint32_t flags;       /* ISDF_FRAG_DEVICE       */
+} isdf_request;
+
+isdf_status isdf_serve_start(isdf_ctx ctx, int32_t max_inflight, int32_t max_batch,
+                             int64_t budget_bytes);
+isdf_status isdf_submit(isdf_ctx ctx, const isdf_request* req, uint64_t* ticket);
+isdf_status isdf_poll(isdf_ctx ctx, uint64_t ticket, int32_t* state, double* latency_s);
+isdf_status isdf_cancel(isdf_ctx ctx, uint64_t ticket);
+/* Stops accepting requests, waits for everything queued, joins the thread. */
+isdf_status isdf_serve_stop(isdf_ctx ctx);
+
+/* JSON summary: sizes, ranks of Pi^q, per-stage device milliseconds of the
+ * last call of each stage, served request counts.  Truncated to cap bytes. */
+isdf_status isdf_stats(isdf_ctx ctx, char* json, int64_t cap);
+
+/* Device milliseconds of the named kernel family over the last call that ran
+ * it, measured with HIP events on the context stream ("metric_kconv",
+ * "rhs_kconv", "grid_fft", "v_gemm", "chol", "w_solve", "frag_t", "frag_pair",
+ * "frag_u", "frag_eri"); -1 if unknown. */
+double isdf_stage_ms(isdf_ctx ctx, const char* name);
+
+/* Memory planner: device bytes that isdf_create/fit/coulomb_kernel would hold
+ * for these sizes (no allocation), and the storage model of the paper's
+ * section on diamond, N_k N_IP^2 + N_k N_IP N_AO complex128 elements. */
+int64_t isdf_plan_bytes(const int32_t grid[3], const int32_t kmesh[3], int32_t n_orb,
+                        int32_t n_ip);
+int64_t isdf_storage_model_bytes(int64_t n_k, int64_t n_ip, int64_t n_ao);
+
+isdf_status isdf_destroy(isdf_ctx ctx);
+const char* isdf_last_error(isdf_ctx ctx);
+const char* isdf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ISDF_H */

@@ -1,0 +1,34 @@
+// Shared device helpers of the gfx950 ISDF library: complex arithmetic on
+// interleaved float64 pairs and small launch utilities.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef double2 cplx;   // (re, im)
+
+__host__ __device__ inline cplx cmk(double r, double i) { cplx z; z.x = r; z.y = i; return z; }
+__host__ __device__ inline cplx cadd(cplx a, cplx b) { return cmk(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline cplx csub(cplx a, cplx b) { return cmk(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline cplx cmul(cplx a, cplx b) {
+  return cmk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+__host__ __device__ inline cplx cmulc(cplx a, cplx b) {
+  return cmk(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__host__ __device__ inline cplx cconj(cplx a) { return cmk(a.x, -a.y); }
+__host__ __device__ inline cplx cscale(cplx a, double s) { return cmk(a.x * s, a.y * s); }
+// acc += a * b
+__host__ __device__ inline void cfma(cplx& acc, cplx a, cplx b) {
+  acc.x = fma(a.x, b.x, fma(-a.y, b.y, acc.x));
+  acc.y = fma(a.x, b.y, fma(a.y, b.x, acc.y));
+}
+
+// exp(i * pi * x) in FP64
+__device__ inline cplx cexpipi(double x) {
+  double s, c;
+  sincospi(x, &s, &c);
+  return cmk(c, s);
+}
+
+static inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }

@@ -1,0 +1,175 @@
+// Unit-cell 3-D FFT with the Bloch phase and the Coulomb kernel fused in
+// (eqs. (6)-(7) "computed by FFT").
+//
+// For every (q, I) the function f(r) exp(-i q.r) on the n1 x n2 x n3 grid is
+// transformed, and each coefficient at G is scaled by
+// sqrt(Omega 4 pi/|G+q|^2)/N_g (0 at G+q = 0), so that the Coulomb matrix of
+// eq. (7) is a plain Hermitian product of the result.  Two HBM passes:
+//   pass A: one or more contiguous (i2, i3) slabs per workgroup, phase applied
+//           on load, FFT along i3 then i2 inside LDS;
+//   pass B: 64 consecutive (i2, i3) columns per workgroup, FFT along i1
+//           inside LDS, Coulomb factor applied on store.
+// Every HBM access is a contiguous row.  Each 1-D transform of length
+// n = na * nb is a two-factor Cooley-Tukey (na-point DFTs, twiddle, nb-point
+// DFTs) read from and written to LDS, with the twiddles in an LDS table.
+#include "kernels.hpp"
+
+namespace {
+
+__device__ inline void factor2(int n, int& na, int& nb) {
+  na = 1;
+  for (int f = 2; f * f <= n; ++f)
+    if (n % f == 0) na = f;
+  nb = n / na;
+}
+
+// Forward DFT (exp(-2 pi i jk/n)) of nlines lines held in buf; element j of
+// line l at buf[base(l) + j*estride], base(l) = (l / L1)*S1 + (l % L1)*S2.
+// tmp has the same layout; tw[t] = exp(-2 pi i t/n).  Result back in buf.
+__device__ void fft_lines(cplx* buf, cplx* tmp, const cplx* tw, int n, int nlines, int L1,
+                          int S1, int S2, int estride) {
+  int na, nb;
+  factor2(n, na, nb);
+  const int total = nlines * n;
+  for (int o = threadIdx.x; o < total; o += blockDim.x) {
+    const int l = o / n, r = o - (o / n) * n;
+    const int base = (l / L1) * S1 + (l % L1) * S2;
+    const int j2 = r / na, k1 = r - (r / na) * na;
+    cplx acc = cmk(0.0, 0.0);
+    for (int j1 = 0; j1 < na; ++j1)
+      cfma(acc, buf[base + (nb * j1 + j2) * estride], tw[(j1 * k1 * nb) % n]);
+    tmp[base + r * estride] = cmul(acc, tw[(j2 * k1) % n]);
+  }
+  __syncthreads();
+  for (int o = threadIdx.x; o < total; o += blockDim.x) {
+    const int l = o / n, r = o - (o / n) * n;
+    const int base = (l / L1) * S1 + (l % L1) * S2;
+    const int k1 = r % na, k2 = r / na;
+    cplx acc = cmk(0.0, 0.0);
+    for (int j2 = 0; j2 < nb; ++j2)
+      cfma(acc, tmp[base + (j2 * na + k1) * estride], tw[(j2 * k2 * na) % n]);
+    buf[base + r * estride] = acc;
+  }
+  __syncthreads();
+}
+
+__device__ inline double wrap_frac(int j, int m) {
+  // representative of j modulo m in [-m/2, m/2), divided by m
+  int w = ((j + m / 2) % m) - m / 2;
+  return (double)w / (double)m;
+}
+
+__device__ inline int wrap_int(int g, int n) { return ((g + n / 2) % n) - n / 2; }
+
+__device__ inline void q_frac(const GridFftArgs& a, int q, double qf[3]) {
+  const int j1 = q / (a.m2 * a.m3), j2 = (q / a.m3) % a.m2, j3 = q % a.m3;
+  qf[0] = wrap_frac(j1, a.m1);
+  qf[1] = wrap_frac(j2, a.m2);
+  qf[2] = wrap_frac(j3, a.m3);
+}
+
+__global__ __launch_bounds__(256) void slab_kernel(GridFftArgs a, int S) {
+  extern __shared__ cplx sm[];
+  const int n23 = a.n2 * a.n3;
+  cplx* buf = sm;
+  cplx* tmp = sm + S * n23;
+  cplx* tw2 = tmp + S * n23;
+  cplx* tw3 = tw2 + a.n2;
+  for (int t = threadIdx.x; t < a.n2; t += blockDim.x) tw2[t] = cexpipi(-2.0 * t / a.n2);
+  for (int t = threadIdx.x; t < a.n3; t += blockDim.x) tw3[t] = cexpipi(-2.0 * t / a.n3);
+  const long long nslab = (long long)a.nq * a.n_ip * a.n1;
+  const long long s0 = (long long)blockIdx.x * S;
+  const int ns = (int)((nslab - s0) < S ? (nslab - s0) : S);
+  for (int idx = threadIdx.x; idx < ns * n23; idx += blockDim.x) {
+    const int s = idx / n23, p = idx - (idx / n23) * n23;
+    const long long slab = s0 + s;
+    const int i1 = (int)(slab % a.n1);
+    const long long qI = slab / a.n1;
+    const int I = (int)(qI % a.n_ip);
+    const int qi = (int)(qI / a.n_ip);
+    double qf[3];
+    q_frac(a, a.q0 + qi, qf);
+    const int i2 = p / a.n3, i3 = p - (p / a.n3) * a.n3;
+    const double ph = qf[0] * i1 / a.n1 + qf[1] * i2 / a.n2 + qf[2] * i3 / a.n3;
+    const cplx v = a.data[(long long)qi * a.q_stride + ((long long)I * a.n1 + i1) * n23 + p];
+    buf[idx] = cmul(v, cexpipi(-2.0 * ph));
+  }
+  __syncthreads();
+  fft_lines(buf, tmp, tw3, a.n3, ns * a.n2, 1, a.n3, 0, 1);          // along i3
+  fft_lines(buf, tmp, tw2, a.n2, ns * a.n3, a.n3, n23, 1, a.n3);     // along i2
+  for (int idx = threadIdx.x; idx < ns * n23; idx += blockDim.x) {
+    const int s = idx / n23, p = idx - (idx / n23) * n23;
+    const long long slab = s0 + s;
+    const int i1 = (int)(slab % a.n1);
+    const long long qI = slab / a.n1;
+    const int I = (int)(qI % a.n_ip);
+    const int qi = (int)(qI / a.n_ip);
+    a.data[(long long)qi * a.q_stride + ((long long)I * a.n1 + i1) * n23 + p] = buf[idx];
+  }
+}
+
+constexpr int COLS = 64;
+
+__global__ __launch_bounds__(256) void col_kernel(GridFftArgs a) {
+  extern __shared__ cplx sm[];
+  const int n23 = a.n2 * a.n3;
+  const int ncb = (n23 + COLS - 1) / COLS;
+  cplx* buf = sm;
+  cplx* tmp = sm + a.n1 * COLS;
+  cplx* tw1 = tmp + a.n1 * COLS;
+  for (int t = threadIdx.x; t < a.n1; t += blockDim.x) tw1[t] = cexpipi(-2.0 * t / a.n1);
+  const int cb = blockIdx.x % ncb;
+  const long long qI = blockIdx.x / ncb;
+  const int I = (int)(qI % a.n_ip);
+  const int qi = (int)(qI / a.n_ip);
+  const int c0 = cb * COLS;
+  const int nc = (n23 - c0) < COLS ? (n23 - c0) : COLS;
+  cplx* base = a.data + (long long)qi * a.q_stride + (long long)I * a.n1 * n23;
+  for (int idx = threadIdx.x; idx < a.n1 * COLS; idx += blockDim.x) {
+    const int i1 = idx / COLS, c = idx - (idx / COLS) * COLS;
+    buf[idx] = (c < nc) ? base[(long long)i1 * n23 + c0 + c] : cmk(0.0, 0.0);
+  }
+  __syncthreads();
+  fft_lines(buf, tmp, tw1, a.n1, COLS, 1, 1, 0, COLS);                 // along i1
+  double qf[3];
+  q_frac(a, a.q0 + qi, qf);
+  const double coef = sqrt(4.0 * M_PI * a.volume) / ((double)a.n1 * n23);
+  for (int idx = threadIdx.x; idx < a.n1 * COLS; idx += blockDim.x) {
+    const int i1 = idx / COLS, c = idx - (idx / COLS) * COLS;
+    if (c >= nc) continue;
+    const int col = c0 + c;
+    const double g1 = wrap_int(i1, a.n1) + qf[0];
+    const double g2 = wrap_int(col / a.n3, a.n2) + qf[1];
+    const double g3 = wrap_int(col % a.n3, a.n3) + qf[2];
+    const double kx = g1 * a.recip[0] + g2 * a.recip[3] + g3 * a.recip[6];
+    const double ky = g1 * a.recip[1] + g2 * a.recip[4] + g3 * a.recip[7];
+    const double kz = g1 * a.recip[2] + g2 * a.recip[5] + g3 * a.recip[8];
+    const double k2 = kx * kx + ky * ky + kz * kz;
+    const double f = (k2 > 1e-20) ? coef / sqrt(k2) : 0.0;
+    base[(long long)i1 * n23 + col] = cscale(buf[idx], f);
+  }
+}
+
+}  // namespace
+
+hipError_t gridfft_launch(const GridFftArgs& a, hipStream_t s) {
+  const int n23 = a.n2 * a.n3;
+  int S = 2048 / n23;
+  if (S < 1) S = 1;
+  size_t ldsA = (2 * (size_t)S * n23 + a.n2 + a.n3) * sizeof(cplx);
+  while (ldsA > 150 * 1024 && S > 1) {
+    --S;
+    ldsA = (2 * (size_t)S * n23 + a.n2 + a.n3) * sizeof(cplx);
+  }
+  if (ldsA > 160 * 1024) return hipErrorInvalidValue;
+  const long long nslab = (long long)a.nq * a.n_ip * a.n1;
+  if (nslab <= 0) return hipSuccess;
+  hipLaunchKernelGGL(slab_kernel, dim3((unsigned)((nslab + S - 1) / S)), dim3(256), ldsA, s, a, S);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const size_t ldsB = (2 * (size_t)a.n1 * COLS + a.n1) * sizeof(cplx);
+  if (ldsB > 160 * 1024) return hipErrorInvalidValue;
+  const long long ncb = (n23 + COLS - 1) / COLS;
+  hipLaunchKernelGGL(col_kernel, dim3((unsigned)(ncb * a.nq * a.n_ip)), dim3(256), ldsB, s, a);
+  return hipGetLastError();
+}

@@ -1,0 +1,1041 @@
+// Host side of the ISDF library: context, memory planner, the fit / Coulomb
+// kernel / fragment-ERI pipelines and the serving thread, behind the C ABI
+// declared in include/isdf.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/isdf.h"
+#include "kernels.hpp"
+
+namespace {
+
+const char* kVersion = "isdf-gfx950 0.1";
+
+struct Fail {
+  isdf_status st;
+  std::string msg;
+};
+
+#define HIPCHK(call)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      throw Fail{ISDF_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)};        \
+  } while (0)
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Device allocation that is freed with its owner.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  void alloc(size_t b) {
+    release();
+    if (b == 0) return;
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      throw Fail{ISDF_E_NOMEM, "device allocation of " + std::to_string(b) + " bytes failed"};
+    }
+    bytes = b;
+  }
+  void ensure(size_t b) {
+    if (b > bytes) alloc(b);
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  ~DevBuf() { release(); }
+  template <class T> T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+struct PinnedBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  void ensure(size_t b) {
+    if (b <= bytes) return;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+    if (hipHostMalloc(&p, b, 0) != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      throw Fail{ISDF_E_NOMEM, "pinned host allocation failed"};
+    }
+    bytes = b;
+  }
+  ~PinnedBuf() {
+    if (p) (void)hipHostFree(p);
+  }
+};
+
+// Descriptor arena: GEMM descriptors and small tables are written to pinned
+// host memory and copied to device memory on the launching stream.  Reset
+// only after the stream has drained.
+struct Arena {
+  PinnedBuf host;
+  DevBuf dev;
+  size_t used = 0;
+  void reset() { used = 0; }
+  template <class T> T* put(const T* src, size_t n, hipStream_t s) {
+    size_t bytes = n * sizeof(T);
+    size_t off = (used + 255) & ~size_t(255);
+    if (off + bytes > host.bytes || off + bytes > dev.bytes) {
+      if (used != 0) throw Fail{ISDF_E_NOMEM, "descriptor arena exhausted"};
+      size_t cap = std::max<size_t>(1 << 20, 2 * bytes);
+      host.ensure(cap);
+      dev.ensure(cap);
+      off = 0;
+    }
+    memcpy((char*)host.p + off, src, bytes);
+    HIPCHK(hipMemcpyAsync((char*)dev.p + off, (char*)host.p + off, bytes, hipMemcpyHostToDevice, s));
+    used = off + bytes;
+    return reinterpret_cast<T*>((char*)dev.p + off);
+  }
+};
+
+int g_max_blocks = 0;
+int max_gemm_blocks() {
+  if (g_max_blocks == 0) {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+      hipDeviceProp_t pr;
+      if (hipGetDeviceProperties(&pr, dev) == hipSuccess) cus = pr.multiProcessorCount;
+    }
+    g_max_blocks = cus * 8;
+  }
+  return g_max_blocks;
+}
+
+void run_gemm(Arena& ar, int prec, int layout, std::vector<GemmDesc>& d, hipStream_t s) {
+  long long total = gemm_plan(d.data(), (int)d.size());
+  if (total == 0) return;
+  GemmDesc* dd = ar.put(d.data(), d.size(), s);
+  HIPCHK(gemm_launch(prec, layout, dd, (int)d.size(), total, max_gemm_blocks(), s));
+}
+
+GemmDesc mkdesc(const cplx* A, long long lda, const cplx* B, long long ldb, cplx* C, long long ldc,
+                int M, int N, int K) {
+  GemmDesc d;
+  memset(&d, 0, sizeof(d));
+  d.A = A;
+  d.B = B;
+  d.C = C;
+  d.lda = lda;
+  d.ldb = ldb;
+  d.ldc = ldc;
+  d.M = M;
+  d.N = N;
+  d.Kseg = K;
+  d.Klast = K;
+  d.nseg = 1;
+  d.batch = 1;
+  return d;
+}
+
+// Stage timer: HIP events on the context stream.
+struct StageTimer {
+  std::map<std::string, std::pair<hipEvent_t, hipEvent_t>> ev;
+  std::map<std::string, float> ms;
+  void begin(const std::string& n, hipStream_t s) {
+    auto it = ev.find(n);
+    if (it == ev.end()) {
+      hipEvent_t a, b;
+      HIPCHK(hipEventCreate(&a));
+      HIPCHK(hipEventCreate(&b));
+      it = ev.emplace(n, std::make_pair(a, b)).first;
+    }
+    HIPCHK(hipEventRecord(it->second.first, s));
+  }
+  void end(const std::string& n, hipStream_t s) { HIPCHK(hipEventRecord(ev[n].second, s)); }
+  void collect() {
+    for (auto& kv : ev) {
+      float t = -1.f;
+      if (hipEventElapsedTime(&t, kv.second.first, kv.second.second) == hipSuccess) ms[kv.first] = t;
+      else (void)hipGetLastError();
+    }
+  }
+  ~StageTimer() {
+    for (auto& kv : ev) {
+      (void)hipEventDestroy(kv.second.first);
+      (void)hipEventDestroy(kv.second.second);
+    }
+  }
+};
+
+// One fragment of a batch.
+struct FragIn {
+  int nf;
+  const void* C;
+  void* eri;
+  uint32_t flags;
+};
+
+// Workspace of one fragment batch (one in flight per workspace).
+struct Workspace {
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  DevBuf mem;     // C_all | Tf | M | U | eri staging
+  PinnedBuf hostc;  // staging for host C
+  Arena arena;
+  hipEvent_t done = nullptr;
+  std::vector<uint64_t> tickets;
+  std::vector<FragIn> frags;
+  ~Workspace() {
+    if (done) (void)hipEventDestroy(done);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+};
+
+struct Request {
+  isdf_request req;
+  int state = ISDF_REQ_QUEUED;
+  double t_submit = 0, t_done = 0;
+  std::string err;
+};
+
+}  // namespace
+
+struct isdf_ctx_s {
+  // sizes
+  int n[3], m[3];
+  int nk = 0, norb = 0, nip = 0;
+  long long ng = 0;
+  double lattice[9], recip[9], volume = 0;
+  uint32_t flags = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  // resident device data
+  DevBuf phi, ip, xt, pi, eta, lt, w, work1, work2, perm, rank, rchunk, flag;
+  bool fitted = false, kernel_ready = false, eta_valid = false;
+  std::vector<int> rank_h;
+  long long rc = 0;   // r-chunk of the RHS
+  Arena arena;
+  StageTimer timer;
+  std::string err;
+  // fragment workspace of the synchronous call
+  Workspace sync_ws;
+  // serving
+  std::mutex mu;
+  std::condition_variable cv;
+  std::thread worker;
+  bool serving = false, stop = false;
+  int max_inflight = 2, max_batch = 64;
+  long long budget = 0;
+  uint64_t next_ticket = 1;
+  std::unordered_map<uint64_t, Request> reqs;
+  std::deque<uint64_t> queue;
+  std::vector<Workspace*> ws_pool;
+  long long served = 0, batches = 0;
+  std::string serve_err;
+};
+
+namespace {
+
+isdf_status fail(isdf_ctx c, isdf_status st, const std::string& msg) {
+  if (c) c->err = msg;
+  return st;
+}
+
+template <class F> isdf_status guarded(isdf_ctx c, F&& f) {
+  if (!c) return ISDF_E_INVALID;
+  try {
+    f();
+    return ISDF_OK;
+  } catch (const Fail& e) {
+    c->err = e.msg;
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    c->err = "host allocation failed";
+    return ISDF_E_NOMEM;
+  } catch (...) {
+    c->err = "unexpected exception";
+    return ISDF_E_INVALID;
+  }
+}
+
+bool good_grid(int n) {
+  if (n < 2 || n > 64) return false;
+  int x = n;
+  for (int f : {2, 3, 5, 7})
+    while (x % f == 0) x /= f;
+  return x == 1;
+}
+
+long long nip2(const isdf_ctx c) { return (long long)c->nip * c->nip; }
+
+// --------------------------------------------------------------------------
+// fit
+// --------------------------------------------------------------------------
+void do_fit(isdf_ctx c) {
+  hipStream_t s = c->stream;
+  const int nk = c->nk, norb = c->norb, nip = c->nip;
+  const long long ng = c->ng;
+  c->arena.reset();
+  // X^k (IV gather)
+  HIPCHK(gather_launch(c->phi.as<cplx>(), c->ip.as<int>(), c->xt.as<cplx>(), nk, norb, ng, nip, s));
+  // T^k_IJ = sum_mu X^k_{I mu} conj(X^k_{J mu})  (Algorithm 1, Y = X)
+  c->timer.begin("metric_t", s);
+  {
+    std::vector<GemmDesc> d(1);
+    d[0] = mkdesc(c->xt.as<cplx>(), nip, c->xt.as<cplx>(), nip, c->work1.as<cplx>(), nip, nip, nip, norb);
+    d[0].batch = nk;
+    d[0].sA_bat = d[0].sB_bat = (long long)norb * nip;
+    d[0].sC_bat = nip2(c);
+    d[0].herm = 1;
+    run_gemm(c->arena, 0, GEMM_A_KM | GEMM_B_KN | GEMM_B_CONJ, d, s);
+  }
+  c->timer.end("metric_t", s);
+  // Pi^q = N_k^-1 sum_R exp(iq.R) |sum_k exp(ik.R) T^k|^2   (eq. (4), Algorithm 1)
+  c->timer.begin("metric_kconv", s);
+  {
+    KconvArgs a;
+    memset(&a, 0, sizeof(a));
+    a.in = c->work1.as<cplx>();
+    a.out = c->pi.as<cplx>();
+    a.in_kstride = a.out_qstride = nip2(c);
+    a.n_elem = nip2(c);
+    a.in_inner = a.out_inner = a.n_elem;
+    a.in_outer = a.out_outer = 0;
+    a.m1 = c->m[0]; a.m2 = c->m[1]; a.m3 = c->m[2];
+    a.mode = 0;
+    a.scale = 1.0 / nk;
+    HIPCHK(kconv_launch(a, s));
+  }
+  c->timer.end("metric_kconv", s);
+  // eta^q_I(r), r-tiled: T^k_I(r) = sum_mu X^k_{I mu} conj(phi^k_mu(r)), then the
+  // same k convolution (eq. (5), Algorithm 1 with Y = phi)
+  c->timer.begin("rhs", s);
+  for (long long r0 = 0; r0 < ng; r0 += c->rc) {
+    const int rcur = (int)std::min<long long>(c->rc, ng - r0);
+    std::vector<GemmDesc> d(1);
+    d[0] = mkdesc(c->xt.as<cplx>(), nip, c->phi.as<cplx>() + r0, ng, c->rchunk.as<cplx>(), rcur,
+                  nip, rcur, norb);
+    d[0].batch = nk;
+    d[0].sA_bat = (long long)norb * nip;
+    d[0].sB_bat = (long long)norb * ng;
+    d[0].sC_bat = (long long)nip * rcur;
+    run_gemm(c->arena, 0, GEMM_A_KM | GEMM_B_KN | GEMM_B_CONJ, d, s);
+    KconvArgs a;
+    memset(&a, 0, sizeof(a));
+    a.in = c->rchunk.as<cplx>();
+    a.out = c->eta.as<cplx>() + r0;
+    a.in_kstride = (long long)nip * rcur;
+    a.out_qstride = (long long)nip * ng;
+    a.n_elem = (long long)nip * rcur;
+    a.in_inner = a.n_elem;
+    a.in_outer = 0;
+    a.out_inner = rcur;
+    a.out_outer = ng;
+    a.m1 = c->m[0]; a.m2 = c->m[1]; a.m3 = c->m[2];
+    a.mode = 0;
+    a.scale = 1.0 / nk;
+    HIPCHK(kconv_launch(a, s));
+  }
+  c->timer.end("rhs", s);
+  // FP64 pivoted Cholesky of every Pi^q (solve of eq. (3))
+  c->timer.begin("chol", s);
+  HIPCHK(chol_launch(c->pi.as<cplx>(), c->work2.as<cplx>(), c->lt.as<cplx>(), c->perm.as<int>(),
+                     c->rank.as<int>(), nip, nk, 1e-13, (c->flags & ISDF_NO_PIVOT) ? 0 : 1, s));
+  c->timer.end("chol", s);
+  c->rank_h.assign(nk, 0);
+  HIPCHK(hipMemcpyAsync(c->rank_h.data(), c->rank.p, sizeof(int) * nk, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  c->timer.collect();
+  for (int q = 0; q < nk; ++q) {
+    if (c->rank_h[q] <= 0)
+      throw Fail{ISDF_E_NUMERIC, "metric Pi^q is zero or not finite at q = " + std::to_string(q)};
+    if ((c->flags & ISDF_NO_PIVOT) && c->rank_h[q] < nip)
+      throw Fail{ISDF_E_NUMERIC, "Cholesky breakdown of Pi^q (singular metric) at q = " +
+                                     std::to_string(q) + ", column " + std::to_string(c->rank_h[q])};
+  }
+  c->fitted = true;
+  c->eta_valid = true;
+  c->kernel_ready = false;
+}
+
+// --------------------------------------------------------------------------
+// Coulomb kernel
+// --------------------------------------------------------------------------
+void do_kernel(isdf_ctx c, int prec) {
+  if (!c->fitted || !c->eta_valid) throw Fail{ISDF_E_STATE, "isdf_fit must run before isdf_coulomb_kernel"};
+  hipStream_t s = c->stream;
+  const int nk = c->nk, nip = c->nip;
+  const long long ng = c->ng;
+  c->arena.reset();
+  // eta~^q_I(G) = sqrt(Omega 4pi/|G+q|^2)/N_g FFT[eta^q_I(r) exp(-iq.r)]   (eqs. (6)-(7))
+  c->timer.begin("grid_fft", s);
+  {
+    GridFftArgs a;
+    memset(&a, 0, sizeof(a));
+    a.data = c->eta.as<cplx>();
+    a.n1 = c->n[0]; a.n2 = c->n[1]; a.n3 = c->n[2];
+    a.m1 = c->m[0]; a.m2 = c->m[1]; a.m3 = c->m[2];
+    a.q0 = 0;
+    a.nq = nk;
+    a.n_ip = nip;
+    a.q_stride = (long long)nip * ng;
+    memcpy(a.recip, c->recip, sizeof(a.recip));
+    a.volume = c->volume;
+    HIPCHK(gridfft_launch(a, s));
+  }
+  c->timer.end("grid_fft", s);
+  c->eta_valid = false;
+  // V^q = eta~ eta~^H  (Hermitian; lower tiles computed and mirrored)
+  c->timer.begin("v_gemm", s);
+  {
+    std::vector<GemmDesc> d(1);
+    d[0] = mkdesc(c->eta.as<cplx>(), ng, c->eta.as<cplx>(), ng, c->work1.as<cplx>(), nip, nip, nip,
+                  (int)ng);
+    if (prec != ISDF_FP64) {
+      const int kseg = 2048;
+      d[0].Kseg = (int)std::min<long long>(kseg, ng);
+      d[0].nseg = (int)((ng + d[0].Kseg - 1) / d[0].Kseg);
+      d[0].Klast = (int)(ng - (long long)(d[0].nseg - 1) * d[0].Kseg);
+      d[0].sA_seg = d[0].sB_seg = d[0].Kseg;
+    }
+    d[0].batch = nk;
+    d[0].sA_bat = d[0].sB_bat = (long long)nip * ng;
+    d[0].sC_bat = nip2(c);
+    d[0].herm = 1;
+    run_gemm(c->arena, prec, GEMM_B_CONJ, d, s);
+  }
+  c->timer.end("v_gemm", s);
+  // W^q = Pi^{q+} V^q Pi^{q+}   (eq. (8)), FP64 triangular solves
+  c->timer.begin("w_solve", s);
+  HIPCHK(wsolve_launch(c->work1.as<cplx>(), c->work2.as<cplx>(), c->w.as<cplx>(), c->lt.as<cplx>(),
+                       c->perm.as<int>(), c->rank.as<int>(), nip, nk, s));
+  c->timer.end("w_solve", s);
+  HIPCHK(hipMemsetAsync(c->flag.p, 0, sizeof(int), s));
+  HIPCHK(nonfinite_launch(c->w.as<cplx>(), (long long)nk * nip2(c), c->flag.as<int>(), s));
+  int bad = 0;
+  HIPCHK(hipMemcpyAsync(&bad, c->flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  c->timer.collect();
+  if (bad) throw Fail{ISDF_E_NUMERIC, "non-finite entries in W^q"};
+  c->kernel_ready = true;
+}
+
+// --------------------------------------------------------------------------
+// fragment ERIs
+// --------------------------------------------------------------------------
+struct BatchPlan {
+  int ncol = 0;
+  long long ptot = 0;
+  std::vector<int> col, nf;
+  std::vector<long long> poff, eoff;
+  size_t off_c = 0, off_tf = 0, off_m = 0, off_u = 0, off_e = 0, bytes = 0;
+};
+
+BatchPlan plan_batch(isdf_ctx c, const std::vector<FragIn>& fr) {
+  BatchPlan p;
+  long long ecount = 0;
+  for (const FragIn& f : fr) {
+    p.col.push_back(p.ncol);
+    p.nf.push_back(f.nf);
+    p.poff.push_back(p.ptot);
+    p.ncol += f.nf;
+    p.ptot += (long long)f.nf * f.nf;
+    long long e4 = (long long)f.nf * f.nf * f.nf * f.nf;
+    p.eoff.push_back((f.flags & ISDF_FRAG_DEVICE) ? -1 : ecount);
+    if (!(f.flags & ISDF_FRAG_DEVICE)) ecount += e4;
+  }
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  size_t off = 0;
+  p.off_c = off; off += al((size_t)c->nk * c->norb * p.ncol * sizeof(cplx));
+  p.off_tf = off; off += al((size_t)c->nk * c->nip * p.ncol * sizeof(cplx));
+  p.off_m = off; off += al((size_t)c->nk * c->nip * p.ptot * sizeof(cplx));
+  // U also stages host fragment coefficients before step 13 overwrites it
+  p.off_u = off;
+  off += al(std::max<size_t>((size_t)c->nk * c->nip * p.ptot, (size_t)c->nk * c->norb * p.ncol) * sizeof(cplx));
+  p.off_e = off; off += al((size_t)ecount * sizeof(cplx));
+  p.bytes = off;
+  return p;
+}
+
+size_t request_bytes(isdf_ctx c, int nf, bool host_out) {
+  size_t b = (size_t)c->nk * c->norb * nf + (size_t)c->nk * c->nip * nf +
+             2 * (size_t)c->nk * c->nip * nf * nf;
+  if (host_out) b += (size_t)nf * nf * nf * nf;
+  return b * sizeof(cplx) + 4 * 256;
+}
+
+// Enqueue the whole fragment pipeline of one batch on ws.stream.
+void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn>& fr,
+                   bool timed) {
+  if (!c->kernel_ready) throw Fail{ISDF_E_STATE, "isdf_coulomb_kernel must run before fragment ERIs"};
+  hipStream_t s = ws.stream;
+  const int nk = c->nk, norb = c->norb, nip = c->nip;
+  BatchPlan p = plan_batch(c, fr);
+  ws.mem.ensure(p.bytes);
+  ws.arena.reset();
+  char* base = ws.mem.as<char>();
+  cplx* Call = (cplx*)(base + p.off_c);
+  cplx* Tf = (cplx*)(base + p.off_tf);
+  cplx* Mq = (cplx*)(base + p.off_m);
+  cplx* Uq = (cplx*)(base + p.off_u);
+  cplx* Est = (cplx*)(base + p.off_e);
+  // upload / gather the fragment coefficients into C_all[k][mu][col]
+  size_t host_bytes = 0;
+  for (const FragIn& f : fr)
+    if (!(f.flags & ISDF_FRAG_DEVICE)) host_bytes += (size_t)nk * norb * f.nf * sizeof(cplx);
+  if (host_bytes) ws.hostc.ensure(host_bytes);
+  // the staged host copies land in the U region first (free until step 13)
+  size_t hoff = 0;
+  for (size_t i = 0; i < fr.size(); ++i) {
+    const FragIn& f = fr[i];
+    const size_t fb = (size_t)nk * norb * f.nf * sizeof(cplx);
+    const cplx* src = (const cplx*)f.C;
+    if (!(f.flags & ISDF_FRAG_DEVICE)) {
+      memcpy((char*)ws.hostc.p + hoff, f.C, fb);
+      HIPCHK(hipMemcpyAsync((char*)Uq + hoff, (char*)ws.hostc.p + hoff, fb, hipMemcpyHostToDevice, s));
+      src = (const cplx*)((char*)Uq + hoff);
+      hoff += fb;
+    }
+    HIPCHK(copy_cols_launch(src, Call, nk, norb, f.nf, p.ncol, p.col[i], s));
+  }
+  if (timed) c->timer.begin("frag_t", s);
+  // T^k_{Ip} = sum_mu X^k_{I mu} C^k_{mu p}   (Algorithm 2)
+  {
+    std::vector<GemmDesc> d(1);
+    d[0] = mkdesc(c->xt.as<cplx>(), nip, Call, p.ncol, Tf, p.ncol, nip, p.ncol, norb);
+    d[0].batch = nk;
+    d[0].sA_bat = (long long)norb * nip;
+    d[0].sB_bat = (long long)norb * p.ncol;
+    d[0].sC_bat = (long long)nip * p.ncol;
+    run_gemm(ws.arena, 0, GEMM_A_KM | GEMM_B_KN, d, s);
+  }
+  // psi_p(r_I + R) = N_k^{-1/2} sum_k exp(ik.R) T^k_{Ip}
+  {
+    KconvArgs a;
+    memset(&a, 0, sizeof(a));
+    a.in = Tf;
+    a.out = Tf;
+    a.in_kstride = a.out_qstride = (long long)nip * p.ncol;
+    a.n_elem = (long long)nip * p.ncol;
+    a.in_inner = a.out_inner = a.n_elem;
+    a.m1 = c->m[0]; a.m2 = c->m[1]; a.m3 = c->m[2];
+    a.mode = 1;
+    a.sign = +1;
+    a.scale = 1.0 / std::sqrt((double)nk);
+    HIPCHK(kconv_launch(a, s));
+  }
+  if (timed) c->timer.end("frag_t", s);
+  // R^q_{I,pq} = N_k^{-1/2} sum_R exp(-iq.R) conj(psi_p) psi_q   (eq. (20))
+  if (timed) c->timer.begin("frag_pair", s);
+  {
+    int pbmax = 4096 / nk;
+    if (pbmax > 256) pbmax = 256;
+    if (pbmax < 1) pbmax = 1;
+    std::vector<PairBlock> blocks;
+    for (size_t f = 0; f < fr.size(); ++f) {
+      const int np = p.nf[f] * p.nf[f];
+      for (int p0 = 0; p0 < np; p0 += pbmax) blocks.push_back(PairBlock{(int)f, p0, std::min(pbmax, np - p0)});
+    }
+    PairArgs a;
+    memset(&a, 0, sizeof(a));
+    a.psi = Tf;
+    a.out = Mq;
+    a.blocks = ws.arena.put(blocks.data(), blocks.size(), s);
+    a.frag_nf = ws.arena.put(p.nf.data(), p.nf.size(), s);
+    a.frag_col = ws.arena.put(p.col.data(), p.col.size(), s);
+    a.frag_pair = ws.arena.put(p.poff.data(), p.poff.size(), s);
+    a.nblocks = (int)blocks.size();
+    a.n_ip = nip;
+    a.ncol = p.ncol;
+    a.pb_max = pbmax;
+    a.ptot = p.ptot;
+    a.m1 = c->m[0]; a.m2 = c->m[1]; a.m3 = c->m[2];
+    a.scale = 1.0 / std::sqrt((double)nk);
+    HIPCHK(pair_launch(a, s));
+  }
+  if (timed) c->timer.end("frag_pair", s);
+  // U^q_{J,P} = sum_I W^q_{IJ} R^q_{I,P}   (eq. (19), first contraction)
+  if (timed) c->timer.begin("frag_u", s);
+  {
+    std::vector<GemmDesc> d(1);
+    d[0] = mkdesc(c->w.as<cplx>(), nip, Mq, p.ptot, Uq, p.ptot, nip, (int)p.ptot, nip);
+    d[0].batch = nk;
+    d[0].sA_bat = nip2(c);
+    d[0].sB_bat = d[0].sC_bat = (long long)nip * p.ptot;
+    run_gemm(ws.arena, prec, GEMM_A_KM | GEMM_B_KN, d, s);
+  }
+  if (timed) c->timer.end("frag_u", s);
+  // (pq|rs) = sum_q sum_J U^q_{J,(pq)} conj(R^q_{J,(sr)})  (eq. (19), R^{-q}_{rs} = conj R^q_{sr}),
+  // one grouped persistent launch over all fragments, FP64 sum over q
+  if (timed) c->timer.begin("frag_eri", s);
+  {
+    std::vector<GemmDesc> d;
+    for (size_t f = 0; f < fr.size(); ++f) {
+      const int nf2 = p.nf[f] * p.nf[f];
+      cplx* out = (fr[f].flags & ISDF_FRAG_DEVICE) ? (cplx*)fr[f].eri : Est + p.eoff[f];
+      GemmDesc g = mkdesc(Uq + p.poff[f], p.ptot, Mq + p.poff[f], p.ptot, out, 0, nf2, nf2, nip);
+      g.nseg = nk;
+      g.sA_seg = g.sB_seg = (long long)nip * p.ptot;
+      g.herm = 1;
+      g.epi = 2;
+      g.nf = p.nf[f];
+      d.push_back(g);
+    }
+    // largest fragments first so the persistent launch ends balanced
+    std::stable_sort(d.begin(), d.end(), [](const GemmDesc& a, const GemmDesc& b) { return a.M > b.M; });
+    run_gemm(ws.arena, prec, GEMM_A_KM | GEMM_B_KN | GEMM_B_CONJ, d, s);
+  }
+  if (timed) c->timer.end("frag_eri", s);
+  for (size_t f = 0; f < fr.size(); ++f) {
+    if (fr[f].flags & ISDF_FRAG_DEVICE) continue;
+    const long long e4 = (long long)p.nf[f] * p.nf[f] * p.nf[f] * p.nf[f];
+    HIPCHK(hipMemcpyAsync(fr[f].eri, Est + p.eoff[f], e4 * sizeof(cplx), hipMemcpyDeviceToHost, s));
+  }
+}
+
+// --------------------------------------------------------------------------
+// serving thread
+// --------------------------------------------------------------------------
+void serve_loop(isdf_ctx c) {
+  std::vector<Workspace*> inflight;
+  while (true) {
+    // retire finished batches
+    for (size_t i = 0; i < inflight.size();) {
+      Workspace* ws = inflight[i];
+      hipError_t q = hipEventQuery(ws->done);
+      if (q == hipErrorNotReady) { ++i; continue; }
+      const double t = now_s();
+      std::lock_guard<std::mutex> lk(c->mu);
+      for (uint64_t tk : ws->tickets) {
+        auto it = c->reqs.find(tk);
+        if (it == c->reqs.end()) continue;
+        if (q == hipSuccess) {
+          it->second.state = ISDF_REQ_DONE;
+        } else {
+          it->second.state = ISDF_REQ_FAILED;
+          it->second.err = hipGetErrorString(q);
+        }
+        it->second.t_done = t;
+        ++c->served;
+      }
+      ws->tickets.clear();
+      c->ws_pool.push_back(ws);
+      inflight.erase(inflight.begin() + i);
+      c->cv.notify_all();
+    }
+    // admit a new batch
+    Workspace* ws = nullptr;
+    std::vector<FragIn> fr;
+    std::vector<uint64_t> tks;
+    int prec = 0;
+    {
+      std::unique_lock<std::mutex> lk(c->mu);
+      if (c->stop && c->queue.empty() && inflight.empty()) break;
+      if (!c->ws_pool.empty() && !c->queue.empty()) {
+        const long long cap = c->budget / c->max_inflight;
+        long long used = 0;
+        while (!c->queue.empty() && (int)fr.size() < c->max_batch) {
+          uint64_t tk = c->queue.front();
+          auto it = c->reqs.find(tk);
+          if (it == c->reqs.end() || it->second.state != ISDF_REQ_QUEUED) {
+            c->queue.pop_front();
+            continue;
+          }
+          const isdf_request& r = it->second.req;
+          if (!fr.empty() && r.prec != prec) break;
+          long long b = (long long)request_bytes(c, r.n_f, !(r.flags & ISDF_FRAG_DEVICE));
+          if (!fr.empty() && used + b > cap) break;
+          if (fr.empty()) prec = r.prec;
+          used += b;
+          fr.push_back(FragIn{r.n_f, r.C, r.eri, r.flags});
+          tks.push_back(tk);
+          it->second.state = ISDF_REQ_RUNNING;
+          c->queue.pop_front();
+        }
+        if (!fr.empty()) {
+          ws = c->ws_pool.back();
+          c->ws_pool.pop_back();
+        }
+      } else if (inflight.empty()) {
+        c->cv.wait_for(lk, std::chrono::microseconds(200));
+        continue;
+      }
+    }
+    if (ws) {
+      try {
+        enqueue_batch(c, *ws, prec, fr, false);
+        HIPCHK(hipEventRecord(ws->done, ws->stream));
+        ws->tickets = tks;
+        inflight.push_back(ws);
+        std::lock_guard<std::mutex> lk(c->mu);
+        ++c->batches;
+      } catch (const Fail& e) {
+        (void)hipStreamSynchronize(ws->stream);
+        std::lock_guard<std::mutex> lk(c->mu);
+        for (uint64_t tk : tks) {
+          auto& r = c->reqs[tk];
+          r.state = ISDF_REQ_FAILED;
+          r.err = e.msg;
+          r.t_done = now_s();
+        }
+        c->serve_err = e.msg;
+        c->ws_pool.push_back(ws);
+      }
+    } else {
+      std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+  }
+}
+
+}  // namespace
+
+// ==========================================================================
+// C ABI
+// ==========================================================================
+extern "C" {
+
+const char* isdf_version(void) { return kVersion; }
+
+int64_t isdf_storage_model_bytes(int64_t n_k, int64_t n_ip, int64_t n_ao) {
+  return (n_k * n_ip * n_ip + n_k * n_ip * n_ao) * 16;
+}
+
+static long long rchunk_len(long long ng, int nk, int nip) {
+  // r tile of the right-hand side: T^k_I(r) for all k of one tile <= 2 GiB
+  long long rc = (2LL << 30) / ((long long)nk * nip * (long long)sizeof(cplx));
+  rc = std::max<long long>(64, std::min<long long>(rc, ng));
+  return rc;
+}
+
+int64_t isdf_plan_bytes(const int32_t grid[3], const int32_t kmesh[3], int32_t n_orb, int32_t n_ip) {
+  if (!grid || !kmesh) return -1;
+  const long long ng = (long long)grid[0] * grid[1] * grid[2];
+  const long long nk = (long long)kmesh[0] * kmesh[1] * kmesh[2];
+  const long long e = sizeof(cplx);
+  long long b = 0;
+  b += nk * n_orb * ng * e;              // orbitals
+  b += nk * n_orb * n_ip * e;            // X
+  b += 5 * nk * (long long)n_ip * n_ip * e;  // Pi, L, W, two work buffers
+  b += nk * (long long)n_ip * ng * e;    // eta
+  b += nk * (long long)n_ip * rchunk_len(ng, (int)nk, n_ip) * e;  // RHS tile
+  b += n_ip * 4 + 2 * nk * (long long)n_ip * 4;
+  return b;
+}
+
+isdf_status isdf_create(isdf_ctx* out, const double* lattice, const int32_t grid[3],
+                        const int32_t kmesh[3], int32_t n_orb, const void* orbitals,
+                        const int32_t* ip_index, int32_t n_ip, uint32_t flags, void* hip_stream) {
+  if (!out) return ISDF_E_INVALID;
+  *out = nullptr;
+  if (!lattice || !grid || !kmesh || !orbitals || !ip_index) return ISDF_E_INVALID;
+  for (int d = 0; d < 3; ++d) {
+    if (!good_grid(grid[d])) return ISDF_E_INVALID;
+    if (kmesh[d] < 1 || kmesh[d] > 16) return ISDF_E_INVALID;
+  }
+  if (n_orb < 1 || n_orb > 256 || n_ip < 1 || n_ip > 2048) return ISDF_E_INVALID;
+  isdf_ctx c = new (std::nothrow) isdf_ctx_s();
+  if (!c) return ISDF_E_NOMEM;
+  isdf_status st = guarded(c, [&] {
+    for (int d = 0; d < 3; ++d) { c->n[d] = grid[d]; c->m[d] = kmesh[d]; }
+    c->nk = kmesh[0] * kmesh[1] * kmesh[2];
+    c->ng = (long long)grid[0] * grid[1] * grid[2];
+    c->norb = n_orb;
+    c->nip = n_ip;
+    c->flags = flags;
+    c->stream = (hipStream_t)hip_stream;
+    HIPCHK(hipGetDevice(&c->device));
+    memcpy(c->lattice, lattice, sizeof(c->lattice));
+    // reciprocal rows b_i: 2 pi (A^-1)^T
+    const double* A = lattice;
+    const double det = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+                       A[2] * (A[3] * A[7] - A[4] * A[6]);
+    if (!(std::fabs(det) > 1e-12)) throw Fail{ISDF_E_INVALID, "singular lattice"};
+    c->volume = std::fabs(det);
+    double inv[9];
+    inv[0] = (A[4] * A[8] - A[5] * A[7]) / det;
+    inv[1] = (A[2] * A[7] - A[1] * A[8]) / det;
+    inv[2] = (A[1] * A[5] - A[2] * A[4]) / det;
+    inv[3] = (A[5] * A[6] - A[3] * A[8]) / det;
+    inv[4] = (A[0] * A[8] - A[2] * A[6]) / det;
+    inv[5] = (A[2] * A[3] - A[0] * A[5]) / det;
+    inv[6] = (A[3] * A[7] - A[4] * A[6]) / det;
+    inv[7] = (A[1] * A[6] - A[0] * A[7]) / det;
+    inv[8] = (A[0] * A[4] - A[1] * A[3]) / det;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) c->recip[3 * i + j] = 2.0 * M_PI * inv[3 * j + i];
+    // validate interpolation points (host copy if needed)
+    std::vector<int32_t> iph(n_ip);
+    if (flags & ISDF_INPUT_DEVICE) {
+      HIPCHK(hipMemcpy(iph.data(), ip_index, sizeof(int32_t) * n_ip, hipMemcpyDeviceToHost));
+    } else {
+      memcpy(iph.data(), ip_index, sizeof(int32_t) * n_ip);
+    }
+    {
+      std::vector<int32_t> srt(iph);
+      std::sort(srt.begin(), srt.end());
+      if (srt.front() < 0 || srt.back() >= c->ng)
+        throw Fail{ISDF_E_INVALID, "interpolation point index out of range"};
+      for (int i = 1; i < n_ip; ++i)
+        if (srt[i] == srt[i - 1]) throw Fail{ISDF_E_INVALID, "duplicate interpolation point"};
+    }
+    const int nk = c->nk;
+    const long long ng = c->ng;
+    const size_t e = sizeof(cplx);
+    c->rc = rchunk_len(ng, nk, n_ip);
+    c->phi.alloc((size_t)nk * n_orb * ng * e);
+    c->ip.alloc(sizeof(int) * n_ip);
+    c->xt.alloc((size_t)nk * n_orb * n_ip * e);
+    const size_t m2 = (size_t)nk * n_ip * n_ip * e;
+    c->pi.alloc(m2);
+    c->lt.alloc(m2);
+    c->w.alloc(m2);
+    c->work1.alloc(m2);
+    c->work2.alloc(m2);
+    c->eta.alloc((size_t)nk * n_ip * ng * e);
+    c->rchunk.alloc((size_t)nk * n_ip * c->rc * e);
+    c->perm.alloc(sizeof(int) * nk * n_ip);
+    c->rank.alloc(sizeof(int) * nk);
+    c->flag.alloc(sizeof(int));
+    const hipMemcpyKind kind = (flags & ISDF_INPUT_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    HIPCHK(hipMemcpyAsync(c->phi.p, orbitals, (size_t)nk * n_orb * ng * e, kind, c->stream));
+    HIPCHK(hipMemcpyAsync(c->ip.p, iph.data(), sizeof(int) * n_ip, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->sync_ws.stream = c->stream;
+    HIPCHK(hipEventCreateWithFlags(&c->sync_ws.done, hipEventDisableTiming));
+  });
+  if (st != ISDF_OK) {
+    delete c;
+    return st;
+  }
+  *out = c;
+  return ISDF_OK;
+}
+
+isdf_status isdf_fit(isdf_ctx ctx) {
+  return guarded(ctx, [&] {
+    if (ctx->serving) throw Fail{ISDF_E_STATE, "stop serving before refitting"};
+    do_fit(ctx);
+  });
+}
+
+isdf_status isdf_coulomb_kernel(isdf_ctx ctx, isdf_precision prec) {
+  return guarded(ctx, [&] {
+    if (prec < ISDF_FP64 || prec > ISDF_MIXED_BF16X3) throw Fail{ISDF_E_INVALID, "bad precision"};
+    if (ctx->serving) throw Fail{ISDF_E_STATE, "stop serving before rebuilding W"};
+    do_kernel(ctx, prec);
+  });
+}
+
+static isdf_status get_mat(isdf_ctx ctx, const DevBuf& b, long long off, size_t bytes, void* out) {
+  return guarded(ctx, [&] {
+    HIPCHK(hipMemcpyAsync(out, b.as<char>() + off, bytes, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+isdf_status isdf_get_metric(isdf_ctx ctx, int32_t q, void* out) {
+  if (!ctx) return ISDF_E_INVALID;
+  if (!ctx->fitted) return fail(ctx, ISDF_E_STATE, "metric not computed");
+  if (q < 0 || q >= ctx->nk || !out) return fail(ctx, ISDF_E_INVALID, "bad q");
+  const size_t b = (size_t)ctx->nip * ctx->nip * sizeof(cplx);
+  return get_mat(ctx, ctx->pi, (long long)q * b, b, out);
+}
+
+isdf_status isdf_get_kernel(isdf_ctx ctx, int32_t q, void* out) {
+  if (!ctx) return ISDF_E_INVALID;
+  if (!ctx->kernel_ready) return fail(ctx, ISDF_E_STATE, "Coulomb kernel not computed");
+  if (q < 0 || q >= ctx->nk || !out) return fail(ctx, ISDF_E_INVALID, "bad q");
+  const size_t b = (size_t)ctx->nip * ctx->nip * sizeof(cplx);
+  return get_mat(ctx, ctx->w, (long long)q * b, b, out);
+}
+
+isdf_status isdf_get_ivs(isdf_ctx ctx, int32_t k, void* out) {
+  if (!ctx) return ISDF_E_INVALID;
+  if (!ctx->fitted) return fail(ctx, ISDF_E_STATE, "X not computed");
+  if (k < 0 || k >= ctx->nk || !out) return fail(ctx, ISDF_E_INVALID, "bad k");
+  // device layout Xt[k][mu][I]; return [I][mu]
+  std::vector<cplx> t((size_t)ctx->norb * ctx->nip);
+  const size_t b = t.size() * sizeof(cplx);
+  isdf_status st = get_mat(ctx, ctx->xt, (long long)k * b, b, t.data());
+  if (st != ISDF_OK) return st;
+  cplx* o = (cplx*)out;
+  for (int mu = 0; mu < ctx->norb; ++mu)
+    for (int I = 0; I < ctx->nip; ++I) o[(size_t)I * ctx->norb + mu] = t[(size_t)mu * ctx->nip + I];
+  return ISDF_OK;
+}
+
+isdf_status isdf_get_rhs(isdf_ctx ctx, int32_t q, void* out) {
+  if (!ctx) return ISDF_E_INVALID;
+  if (!ctx->eta_valid) return fail(ctx, ISDF_E_STATE, "eta not available (fit first; consumed by the kernel)");
+  if (q < 0 || q >= ctx->nk || !out) return fail(ctx, ISDF_E_INVALID, "bad q");
+  const size_t b = (size_t)ctx->nip * ctx->ng * sizeof(cplx);
+  return get_mat(ctx, ctx->eta, (long long)q * b, b, out);
+}
+
+isdf_status isdf_fragment_eri(isdf_ctx ctx, isdf_precision prec, int32_t n_frag, const int32_t* n_f,
+                              const void* const* C, void* const* eri, uint32_t flags) {
+  return guarded(ctx, [&] {
+    if (n_frag < 1 || !n_f || !C || !eri) throw Fail{ISDF_E_INVALID, "bad fragment arguments"};
+    if (prec < ISDF_FP64 || prec > ISDF_MIXED_BF16X3) throw Fail{ISDF_E_INVALID, "bad precision"};
+    std::vector<FragIn> fr;
+    for (int f = 0; f < n_frag; ++f) {
+      if (n_f[f] < 1 || n_f[f] > ctx->nk * ctx->norb || !C[f] || !eri[f])
+        throw Fail{ISDF_E_INVALID, "bad fragment " + std::to_string(f)};
+      fr.push_back(FragIn{n_f[f], C[f], eri[f], flags});
+    }
+    enqueue_batch(ctx, ctx->sync_ws, prec, fr, true);
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->timer.collect();
+  });
+}
+
+isdf_status isdf_serve_start(isdf_ctx ctx, int32_t max_inflight, int32_t max_batch, int64_t budget_bytes) {
+  return guarded(ctx, [&] {
+    if (ctx->serving) throw Fail{ISDF_E_STATE, "already serving"};
+    if (!ctx->kernel_ready) throw Fail{ISDF_E_STATE, "isdf_coulomb_kernel must run before serving"};
+    if (max_inflight < 1 || max_inflight > 8 || max_batch < 1 || budget_bytes <= 0)
+      throw Fail{ISDF_E_INVALID, "bad serving parameters"};
+    ctx->max_inflight = max_inflight;
+    ctx->max_batch = max_batch;
+    ctx->budget = budget_bytes;
+    ctx->stop = false;
+    for (Workspace* w : ctx->ws_pool) delete w;
+    ctx->ws_pool.clear();
+    for (int i = 0; i < max_inflight; ++i) {
+      Workspace* w = new Workspace();
+      HIPCHK(hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking));
+      w->own_stream = true;
+      HIPCHK(hipEventCreateWithFlags(&w->done, hipEventDisableTiming));
+      ctx->ws_pool.push_back(w);
+    }
+    ctx->serving = true;
+    ctx->worker = std::thread([ctx] {
+      (void)hipSetDevice(ctx->device);
+      serve_loop(ctx);
+    });
+  });
+}
+
+isdf_status isdf_submit(isdf_ctx ctx, const isdf_request* req, uint64_t* ticket) {
+  if (!ctx) return ISDF_E_INVALID;
+  if (!req || !ticket || req->n_f < 1 || req->n_f > ctx->nk * ctx->norb || !req->C || !req->eri ||
+      req->prec < ISDF_FP64 || req->prec > ISDF_MIXED_BF16X3)
+    return fail(ctx, ISDF_E_INVALID, "bad request");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (!ctx->serving || ctx->stop) return fail(ctx, ISDF_E_STATE, "not serving");
+  if (ctx->queue.size() >= 100000) return fail(ctx, ISDF_E_BUSY, "request queue full");
+  const bool host_out = !(req->flags & ISDF_FRAG_DEVICE);
+  if ((long long)request_bytes(ctx, req->n_f, host_out) > ctx->budget / ctx->max_inflight)
+    return fail(ctx, ISDF_E_NOMEM, "request exceeds the per-batch memory budget");
+  const uint64_t t = ctx->next_ticket++;
+  Request r;
+  r.req = *req;
+  r.t_submit = now_s();
+  ctx->reqs.emplace(t, r);
+  ctx->queue.push_back(t);
+  *ticket = t;
+  ctx->cv.notify_all();
+  return ISDF_OK;
+}
+
+isdf_status isdf_poll(isdf_ctx ctx, uint64_t ticket, int32_t* state, double* latency_s) {
+  if (!ctx) return ISDF_E_INVALID;
+  if (!state) return fail(ctx, ISDF_E_INVALID, "null state");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  auto it = ctx->reqs.find(ticket);
+  if (it == ctx->reqs.end()) return fail(ctx, ISDF_E_NOTFOUND, "unknown ticket");
+  *state = it->second.state;
+  if (latency_s) {
+    const Request& r = it->second;
+    *latency_s = (r.state == ISDF_REQ_DONE || r.state == ISDF_REQ_FAILED) ? r.t_done - r.t_submit : -1.0;
+  }
+  return ISDF_OK;
+}
+
+isdf_status isdf_cancel(isdf_ctx ctx, uint64_t ticket) {
+  if (!ctx) return ISDF_E_INVALID;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  auto it = ctx->reqs.find(ticket);
+  if (it == ctx->reqs.end()) return fail(ctx, ISDF_E_NOTFOUND, "unknown ticket");
+  if (it->second.state != ISDF_REQ_QUEUED)
+    return fail(ctx, ISDF_E_STATE, "request already running or finished");
+  it->second.state = ISDF_REQ_CANCELLED;
+  return ISDF_OK;
+}
+
+isdf_status isdf_serve_stop(isdf_ctx ctx) {
+  if (!ctx) return ISDF_E_INVALID;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (!ctx->serving) return ISDF_OK;
+    ctx->stop = true;
+    ctx->cv.notify_all();
+  }
+  if (ctx->worker.joinable()) ctx->worker.join();
+  ctx->serving = false;
+  for (Workspace* w : ctx->ws_pool) delete w;
+  ctx->ws_pool.clear();
+  if (!ctx->serve_err.empty()) return fail(ctx, ISDF_E_DEVICE, ctx->serve_err);
+  return ISDF_OK;
+}
+
+isdf_status isdf_stats(isdf_ctx ctx, char* json, int64_t cap) {
+  if (!ctx) return ISDF_E_INVALID;
+  if (!json || cap <= 0) return fail(ctx, ISDF_E_INVALID, "bad buffer");
+  std::string s = "{\"n_k\":" + std::to_string(ctx->nk) + ",\"n_g\":" + std::to_string(ctx->ng) +
+                  ",\"n_orb\":" + std::to_string(ctx->norb) + ",\"n_ip\":" + std::to_string(ctx->nip) +
+                  ",\"r_tile\":" + std::to_string(ctx->rc) + ",\"rank\":[";
+  for (size_t i = 0; i < ctx->rank_h.size(); ++i) s += (i ? "," : "") + std::to_string(ctx->rank_h[i]);
+  s += "],\"stage_ms\":{";
+  bool first = true;
+  for (auto& kv : ctx->timer.ms) {
+    char b[64];
+    snprintf(b, sizeof(b), "%.6f", kv.second);
+    s += std::string(first ? "" : ",") + "\"" + kv.first + "\":" + b;
+    first = false;
+  }
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    s += "},\"served\":" + std::to_string(ctx->served) + ",\"batches\":" + std::to_string(ctx->batches) + "}";
+  }
+  strncpy(json, s.c_str(), (size_t)cap - 1);
+  json[cap - 1] = 0;
+  return ISDF_OK;
+}
+
+double isdf_stage_ms(isdf_ctx ctx, const char* name) {
+  if (!ctx || !name) return -1.0;
+  auto it = ctx->timer.ms.find(name);
+  return it == ctx->timer.ms.end() ? -1.0 : (double)it->second;
+}
+
+isdf_status isdf_destroy(isdf_ctx ctx) {
+  if (!ctx) return ISDF_E_INVALID;
+  (void)isdf_serve_stop(ctx);
+  (void)hipStreamSynchronize(ctx->stream);
+  delete ctx;
+  return ISDF_OK;
+}
+
+const char* isdf_last_error(isdf_ctx ctx) {
+  if (!ctx) return "null context";
+  return ctx->err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,64 @@
+// Small data-movement kernels of the path.
+#include "kernels.hpp"
+
+namespace {
+
+// Interpolating vectors X^k_{I mu} = phi^k_mu(r_I) (below eq. (2)), stored
+// k-major as Xt[k][mu][I] so that they are the K-major operand of the GEMMs.
+__global__ void gather_kernel(const cplx* __restrict__ phi, const int* __restrict__ ip, cplx* xt,
+                              int nk, int norb, long long ng, int nip) {
+  const long long total = (long long)nk * norb * nip;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const long long km = idx / nip;
+    const int I = (int)(idx - km * nip);
+    xt[idx] = phi[km * ng + ip[I]];
+  }
+}
+
+__global__ void copy_cols_kernel(const cplx* __restrict__ in, cplx* out, int nk, int norb, int nf,
+                                 int ncol, int col0) {
+  const long long total = (long long)nk * norb * nf;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const long long km = idx / nf;
+    const int p = (int)(idx - km * nf);
+    out[km * ncol + col0 + p] = in[idx];
+  }
+}
+
+__global__ void nonfinite_kernel(const cplx* __restrict__ x, long long n, int* flag) {
+  int bad = 0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const cplx v = x[i];
+    if (!isfinite(v.x) || !isfinite(v.y)) bad = 1;
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
+inline int grid_for(long long n) {
+  long long b = (n + 255) / 256;
+  return (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
+}
+
+}  // namespace
+
+hipError_t gather_launch(const cplx* phi, const int* ip, cplx* xt, int nk, int norb, long long ng,
+                         int nip, hipStream_t s) {
+  hipLaunchKernelGGL(gather_kernel, dim3(grid_for((long long)nk * norb * nip)), dim3(256), 0, s,
+                     phi, ip, xt, nk, norb, ng, nip);
+  return hipGetLastError();
+}
+
+hipError_t copy_cols_launch(const cplx* in, cplx* out, int nk, int norb, int nf, int ncol, int col0,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(copy_cols_kernel, dim3(grid_for((long long)nk * norb * nf)), dim3(256), 0, s,
+                     in, out, nk, norb, nf, ncol, col0);
+  return hipGetLastError();
+}
+
+hipError_t nonfinite_launch(const cplx* x, long long n, int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(nonfinite_kernel, dim3(grid_for(n)), dim3(256), 0, s, x, n, flag);
+  return hipGetLastError();
+}

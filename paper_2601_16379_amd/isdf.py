@@ -1,0 +1,264 @@
+"""ctypes binding of the C ABI in ``include/isdf.h`` (argument marshalling only).
+
+Every step of the path runs in the gfx950 library ``libisdf_gfx950.so``; this
+module converts numpy arrays / torch tensors to pointers and status codes to
+exceptions.  It fails loudly when the library is missing: there is no CPU
+fallback.  PyTorch, when given, only supplies device memory and the HIP
+stream.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libisdf_gfx950.so")
+
+ISDF_OK = 0
+STATUS = {0: "ISDF_OK", -1: "ISDF_E_INVALID", -2: "ISDF_E_NOMEM", -3: "ISDF_E_STATE",
+          -4: "ISDF_E_NUMERIC", -5: "ISDF_E_DEVICE", -6: "ISDF_E_BUSY",
+          -7: "ISDF_E_NOTFOUND", -8: "ISDF_E_CANCELLED"}
+ISDF_FP64, ISDF_MIXED_FP32, ISDF_MIXED_BF16X3 = 0, 1, 2
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+ISDF_INPUT_DEVICE = 0x1
+ISDF_NO_PIVOT = 0x2
+ISDF_FRAG_DEVICE = 0x1
+REQ_STATES = {0: "QUEUED", 1: "RUNNING", 2: "DONE", 3: "FAILED", 4: "CANCELLED"}
+
+EXPORTS = ["isdf_create", "isdf_fit", "isdf_coulomb_kernel", "isdf_get_metric",
+           "isdf_get_kernel", "isdf_get_ivs", "isdf_get_rhs", "isdf_fragment_eri",
+           "isdf_serve_start", "isdf_submit", "isdf_poll", "isdf_cancel", "isdf_serve_stop",
+           "isdf_stats", "isdf_stage_ms", "isdf_plan_bytes", "isdf_storage_model_bytes",
+           "isdf_destroy", "isdf_last_error", "isdf_version"]
+
+
+class IsdfError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("n_f", ctypes.c_int32), ("C", ctypes.c_void_p), ("eri", ctypes.c_void_p),
+                ("prec", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load the gfx950 library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libisdf_gfx950.so not found at %s; build it with "
+                           "`python -m paper_2601_16379_amd.build`" % path)
+    lib = ctypes.CDLL(path)
+    P, I32, U32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "isdf_create": (I32, [ctypes.POINTER(P), P, P, P, I32, P, P, I32, U32, P]),
+        "isdf_fit": (I32, [P]),
+        "isdf_coulomb_kernel": (I32, [P, I32]),
+        "isdf_get_metric": (I32, [P, I32, P]),
+        "isdf_get_kernel": (I32, [P, I32, P]),
+        "isdf_get_ivs": (I32, [P, I32, P]),
+        "isdf_get_rhs": (I32, [P, I32, P]),
+        "isdf_fragment_eri": (I32, [P, I32, I32, P, P, P, U32]),
+        "isdf_serve_start": (I32, [P, I32, I32, I64]),
+        "isdf_submit": (I32, [P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
+        "isdf_poll": (I32, [P, ctypes.c_uint64, ctypes.POINTER(I32), ctypes.POINTER(D)]),
+        "isdf_cancel": (I32, [P, ctypes.c_uint64]),
+        "isdf_serve_stop": (I32, [P]),
+        "isdf_stats": (I32, [P, ctypes.c_char_p, I64]),
+        "isdf_stage_ms": (D, [P, ctypes.c_char_p]),
+        "isdf_plan_bytes": (I64, [P, P, I32, I32]),
+        "isdf_storage_model_bytes": (I64, [I64, I64, I64]),
+        "isdf_destroy": (I32, [P]),
+        "isdf_last_error": (ctypes.c_char_p, [P]),
+        "isdf_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(x):
+    """(pointer, is_device) of a numpy array or torch tensor."""
+    if isinstance(x, np.ndarray):
+        if not x.flags["C_CONTIGUOUS"]:
+            raise ValueError("array must be C contiguous")
+        return x.ctypes.data, False
+    if hasattr(x, "data_ptr"):
+        if not x.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return x.data_ptr(), x.device.type != "cpu"
+    raise TypeError("expected numpy array or torch tensor, got %r" % type(x))
+
+
+def current_stream():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return torch.cuda.current_stream().cuda_stream
+    except Exception:
+        pass
+    return 0
+
+
+def isdf_plan_bytes(grid, kmesh, n_orb, n_ip):
+    lib = load_library()
+    g = np.asarray(grid, dtype=np.int32)
+    k = np.asarray(kmesh, dtype=np.int32)
+    return int(lib.isdf_plan_bytes(g.ctypes.data, k.ctypes.data, int(n_orb), int(n_ip)))
+
+
+def isdf_storage_model_bytes(n_k, n_ip, n_ao):
+    return int(load_library().isdf_storage_model_bytes(int(n_k), int(n_ip), int(n_ao)))
+
+
+def isdf_version():
+    return load_library().isdf_version().decode()
+
+
+class Isdf:
+    """One library context: ``isdf_create`` at construction, the other calls
+    as methods with the C names (``fit``, ``coulomb_kernel``, ...)."""
+
+    def __init__(self, lattice, grid, kmesh, orbitals, ip_index, no_pivot=False, stream=None):
+        self.lib = load_library()
+        lat = np.ascontiguousarray(np.asarray(lattice, dtype=np.float64))
+        self.grid = np.ascontiguousarray(np.asarray(grid, dtype=np.int32))
+        self.kmesh = np.ascontiguousarray(np.asarray(kmesh, dtype=np.int32))
+        self.n_k = int(np.prod(self.kmesh))
+        self.n_g = int(np.prod(self.grid))
+        optr, odev = _ptr(orbitals)
+        if isinstance(ip_index, np.ndarray):
+            ip_index = np.ascontiguousarray(ip_index, dtype=np.int32)
+        iptr, idev = _ptr(ip_index)
+        if odev != idev:
+            raise ValueError("orbitals and ip_index must both be host or both device")
+        shape = tuple(orbitals.shape)
+        if len(shape) != 3 or shape[0] != self.n_k or shape[2] != self.n_g:
+            raise ValueError("orbitals must be [N_k, n_orb, N_g]")
+        self.n_orb = int(shape[1])
+        self.n_ip = int(ip_index.shape[0])
+        flags = (ISDF_INPUT_DEVICE if odev else 0) | (ISDF_NO_PIVOT if no_pivot else 0)
+        self.stream = current_stream() if stream is None else stream
+        h = ctypes.c_void_p()
+        st = self.lib.isdf_create(ctypes.byref(h), lat.ctypes.data, self.grid.ctypes.data,
+                                  self.kmesh.ctypes.data, self.n_orb, optr, iptr, self.n_ip,
+                                  flags, self.stream)
+        if st != ISDF_OK:
+            raise IsdfError(st, "isdf_create failed")
+        self.h = h
+
+    # -- helpers -------------------------------------------------------------
+    def _check(self, st, what):
+        if st != ISDF_OK:
+            raise IsdfError(st, "%s: %s" % (what, self.lib.isdf_last_error(self.h).decode()))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.isdf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- the path ------------------------------------------------------------
+    def fit(self):
+        self._check(self.lib.isdf_fit(self.h), "isdf_fit")
+
+    def coulomb_kernel(self, prec="fp64"):
+        self._check(self.lib.isdf_coulomb_kernel(self.h, PRECISIONS.get(prec, prec)),
+                    "isdf_coulomb_kernel")
+
+    def _get(self, fn, idx, shape):
+        out = np.empty(shape, dtype=np.complex128)
+        self._check(fn(self.h, int(idx), out.ctypes.data), fn.__name__)
+        return out
+
+    def get_metric(self, q):
+        return self._get(self.lib.isdf_get_metric, q, (self.n_ip, self.n_ip))
+
+    def get_kernel(self, q):
+        return self._get(self.lib.isdf_get_kernel, q, (self.n_ip, self.n_ip))
+
+    def get_ivs(self, k):
+        return self._get(self.lib.isdf_get_ivs, k, (self.n_ip, self.n_orb))
+
+    def get_rhs(self, q):
+        return self._get(self.lib.isdf_get_rhs, q, (self.n_ip, self.n_g))
+
+    def fragment_eri(self, coeffs, prec="fp64", out=None):
+        """ERIs of a batch of fragments in one pass.  ``coeffs``: list of
+        [N_k, n_orb, n_f] complex128 arrays (numpy = host, torch cuda tensors =
+        device).  Returns the list of [n_f]^4 outputs (same kind)."""
+        n = len(coeffs)
+        nfs = np.array([c.shape[2] for c in coeffs], dtype=np.int32)
+        dev = [(_ptr(c)[1]) for c in coeffs]
+        if any(dev) != all(dev):
+            raise ValueError("mixing host and device fragments in one call")
+        if out is None:
+            if dev[0]:
+                import torch
+                out = [torch.empty((f, f, f, f), dtype=torch.complex128, device=coeffs[0].device)
+                       for f in nfs]
+            else:
+                out = [np.empty((f, f, f, f), dtype=np.complex128) for f in nfs]
+        cptr = (ctypes.c_void_p * n)(*[_ptr(c)[0] for c in coeffs])
+        eptr = (ctypes.c_void_p * n)(*[_ptr(e)[0] for e in out])
+        flags = ISDF_FRAG_DEVICE if dev[0] else 0
+        self._check(self.lib.isdf_fragment_eri(self.h, PRECISIONS.get(prec, prec), n,
+                                               nfs.ctypes.data, cptr, eptr, flags),
+                    "isdf_fragment_eri")
+        return out
+
+    # -- serving -------------------------------------------------------------
+    def serve_start(self, max_inflight=2, max_batch=64, budget_bytes=64 << 30):
+        self._check(self.lib.isdf_serve_start(self.h, max_inflight, max_batch, budget_bytes),
+                    "isdf_serve_start")
+
+    def submit(self, coeffs, eri, prec="fp64"):
+        cp, cdev = _ptr(coeffs)
+        ep, edev = _ptr(eri)
+        if cdev != edev:
+            raise ValueError("C and eri must both be host or both device")
+        req = Request(int(coeffs.shape[2]), cp, ep, PRECISIONS.get(prec, prec),
+                      ISDF_FRAG_DEVICE if cdev else 0)
+        t = ctypes.c_uint64()
+        self._check(self.lib.isdf_submit(self.h, ctypes.byref(req), ctypes.byref(t)), "isdf_submit")
+        return t.value
+
+    def poll(self, ticket):
+        st = ctypes.c_int32()
+        lat = ctypes.c_double()
+        self._check(self.lib.isdf_poll(self.h, ctypes.c_uint64(ticket), ctypes.byref(st),
+                                       ctypes.byref(lat)), "isdf_poll")
+        return REQ_STATES[st.value], lat.value
+
+    def cancel(self, ticket):
+        self._check(self.lib.isdf_cancel(self.h, ctypes.c_uint64(ticket)), "isdf_cancel")
+
+    def serve_stop(self):
+        self._check(self.lib.isdf_serve_stop(self.h), "isdf_serve_stop")
+
+    # -- introspection ---------------------------------------------------------
+    def stats(self):
+        import json
+        buf = ctypes.create_string_buffer(1 << 16)
+        self._check(self.lib.isdf_stats(self.h, buf, len(buf)), "isdf_stats")
+        return json.loads(buf.value.decode())
+
+    def stage_ms(self, name):
+        return float(self.lib.isdf_stage_ms(self.h, name.encode()))
+
+    def last_error(self):
+        return self.lib.isdf_last_error(self.h).decode()

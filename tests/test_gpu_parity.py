@@ -1,0 +1,170 @@
+"""Parity of the gfx950 library (through the C ABI) with the FP64 oracle.
+
+Bars: integer / index work bit-exact; FP64 path within 1e-10 relative
+(max |diff| / max |oracle|) per result; mixed paths within 1e-6 Eh absolute
+on fragment ERIs.  Small cases span several 64-wide GEMM tiles with ragged
+tails (N_IP = 150, pair counts up to 196) and every mesh shape used by the
+workloads (Gamma only, even and odd axes)."""
+import numpy as np
+import pytest
+
+import isdf_inputs as inp
+from oracle import geometry as geo
+from oracle import kpoint as ko
+from oracle import supercell as sc
+
+pytestmark = pytest.mark.gpu
+
+FP64_REL = 1e-10
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def _ctx(d, **kw):
+    import paper_2601_16379_amd as pkg
+    return pkg.Isdf(d.lattice, d.cfg.grid, d.cfg.kmesh, d.orbitals, d.ip_index, **kw)
+
+
+class Case:
+    """GPU and oracle fits of one small configuration (module cache)."""
+
+    def __init__(self, name):
+        self.d = inp.make_inputs(name)
+        cfg = self.d.cfg
+        print("case", name, flush=True)
+        self.x, self.pi, self.eta, self.w = ko.fit_and_kernel(
+            self.d.orbitals, self.d.ip_index, self.d.lattice, cfg.grid, cfg.kmesh)
+        self.ctx = _ctx(self.d)
+        self.ctx.fit()
+        self.g_pi = np.stack([self.ctx.get_metric(q) for q in range(cfg.n_k)])
+        self.g_x = np.stack([self.ctx.get_ivs(k) for k in range(cfg.n_k)])
+        self.g_eta = np.stack([self.ctx.get_rhs(q) for q in range(cfg.n_k)])
+        self.ctx.coulomb_kernel("fp64")
+        self.g_w = np.stack([self.ctx.get_kernel(q) for q in range(cfg.n_k)])
+
+
+_CASES = {}
+
+
+def case(name):
+    if name not in _CASES:
+        _CASES[name] = Case(name)
+    return _CASES[name]
+
+
+SMALL = ["t_tiny_k1", "t_small_k2", "t_small_k3", "t_mid_k4"]
+
+
+@pytest.mark.parametrize("name", SMALL)
+def test_ivs_bit_exact(name):
+    c = case(name)
+    assert np.array_equal(c.g_x, c.x)
+
+
+@pytest.mark.parametrize("name", SMALL)
+def test_metric_parity(name):
+    c = case(name)
+    assert _rel(c.g_pi, c.pi) < 1e-12
+
+
+@pytest.mark.parametrize("name", SMALL)
+def test_rhs_parity(name):
+    c = case(name)
+    assert _rel(c.g_eta, c.eta) < 1e-12
+
+
+@pytest.mark.parametrize("name", SMALL)
+def test_kernel_parity(name):
+    c = case(name)
+    assert _rel(c.g_w, c.w) < FP64_REL
+    assert c.ctx.stats()["rank"] == [c.d.cfg.n_ip] * c.d.cfg.n_k
+
+
+@pytest.mark.parametrize("name", SMALL)
+def test_fragment_eri_fp64_parity(name):
+    c = case(name)
+    cfg = c.d.cfg
+    frags = inp.make_fragments(cfg)
+    out = c.ctx.fragment_eri(frags, "fp64")
+    for f, cf in enumerate(frags):
+        ref = ko.fragment_eri(c.x, cf, c.w, cfg.kmesh)
+        assert _rel(out[f], ref) < FP64_REL, (f, cf.shape)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("name", ["t_small_k3", "t_mid_k4"])
+def test_fragment_eri_mixed_within_1e6(name, prec):
+    c = case(name)
+    cfg = c.d.cfg
+    frags = inp.make_fragments(cfg)
+    out = c.ctx.fragment_eri(frags, prec)
+    for f, cf in enumerate(frags):
+        ref = ko.fragment_eri(c.x, cf, c.w, cfg.kmesh)
+        err = float(np.max(np.abs(out[f] - ref)))
+        print("%s %s frag %d n_f %d max|dV| %.3e Eh" % (name, prec, f, cf.shape[2], err))
+        assert err < 1e-6
+
+
+def test_batch_equals_alone_bitwise():
+    c = case("t_mid_k4")
+    frags = inp.make_fragments(c.d.cfg)
+    batch = c.ctx.fragment_eri(frags, "fp64")
+    for f in (0, len(frags) - 1):
+        alone = c.ctx.fragment_eri([frags[f]], "fp64")[0]
+        assert np.array_equal(alone, batch[f])
+
+
+def test_device_pointers_match_host():
+    import torch
+    c = case("t_small_k3")
+    frags = inp.make_fragments(c.d.cfg)
+    host = c.ctx.fragment_eri(frags, "fp64")
+    dev = c.ctx.fragment_eri([torch.from_numpy(f).cuda() for f in frags], "fp64")
+    torch.cuda.synchronize()
+    for h, g in zip(host, dev):
+        assert np.array_equal(h, g.cpu().numpy())
+
+
+def test_workload1_exact_eris_rank_deficient_metric():
+    """16^3 Gamma cell, 8 real orbitals, 64 points: Pi has rank 36, the
+    pivoted factorisation finds it and the ERIs equal FFT-Poisson."""
+    d = inp.make_inputs("c1_gamma_16")
+    cfg = d.cfg
+    ctx = _ctx(d)
+    ctx.fit()
+    assert ctx.stats()["rank"] == [36]
+    ctx.coulomb_kernel("fp64")
+    coeffs = inp.make_fragment(cfg, 0, 8)
+    v = ctx.fragment_eri([coeffs], "fp64")[0]
+    phi_s = sc.supercell_orbitals(d.orbitals, cfg.grid, cfg.kmesh)
+    psi = sc.fragment_orbitals(phi_s, coeffs)
+    exact = sc.exact_eri(psi, d.lattice, cfg.grid, cfg.kmesh, box="kpoint")
+    assert np.max(np.abs(v - exact)) < 1e-12
+
+
+def test_no_pivot_singular_metric_is_numeric_error():
+    import paper_2601_16379_amd as pkg
+    d = inp.make_inputs("c1_gamma_16")
+    ctx = _ctx(d, no_pivot=True)
+    with pytest.raises(pkg.IsdfError) as e:
+        ctx.fit()
+    assert e.value.status == -4
+    assert "q = 0" in str(e.value)
+
+
+def test_state_errors():
+    import paper_2601_16379_amd as pkg
+    d = inp.make_inputs("t_tiny_k1")
+    ctx = _ctx(d)
+    with pytest.raises(pkg.IsdfError) as e:
+        ctx.coulomb_kernel()
+    assert e.value.status == -3
+    ctx.fit()
+    with pytest.raises(pkg.IsdfError) as e:
+        ctx.fragment_eri([inp.make_fragment(d.cfg, 0, 2)])
+    assert e.value.status == -3
+    with pytest.raises(pkg.IsdfError) as e:
+        ctx.get_kernel(0)
+    assert e.value.status == -3
