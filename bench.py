@@ -1,0 +1,299 @@
+#!/usr/bin/env python3
+"""Benchmark of the k-point ISDF hot path on one MI355X.
+
+One step = the whole path over one batch of synthetic input: the fit
+(X^k, Pi^q and eta^q as k convolutions, FP64 pivoted Cholesky), the Coulomb
+kernel W^q (grid FFT with 4 pi/|G+q|^2, V^q GEMM, FP64 solves) and the
+fragment ERIs of every fragment of the workload, submitted at one instant to
+the serving loop and collected by polling (so each fragment has a
+submit-to-done latency).  Inputs (orbitals, interpolation points, fragment
+coefficients) are resident in HBM before timing starts.
+
+Prints one JSON line: fragment ERIs/s (sum of n_f^4 over fragments per
+second of wall time, fit included), p50/p99 latency, the speedup over the
+same step in FP64, the max |mixed - FP64| error per result, a roofline entry
+for the dominant kernel and the FP64 CPU oracle timed on this host.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Peak rates of MI355X (dense; TFLOP/s and GB/s)
+PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "hbm": 8000.0}
+PREC_PEAK = {"fp64": ("fp64", 78.6), "fp32": ("fp32", 157.3), "bf16x3": ("bf16", 2500.0)}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c3_k4_32")
+    ap.add_argument("--prec", default="bf16x3", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--no-fp64-ref", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget-s", type=float, default=25.0)
+    return ap.parse_args()
+
+
+def stage_work(stage, cfg, nfs, prec):
+    """(bound, algorithmic amount per launch, unit, peak) of a stage."""
+    nk, nip, ng, norb = cfg.n_k, cfg.n_ip, cfg.n_g, cfg.n_orb
+    s2 = sum(n * n for n in nfs)
+    dt, pk = PREC_PEAK[prec]
+    if stage == "frag_eri":   # Hermitian half of sum_q U^q R^{qH} per fragment
+        fl = sum(8.0 * nk * nip * (n * n) * (n * n + 1) / 2 for n in nfs)
+        return "mfma", fl / 1e12, "TFLOP", pk
+    if stage == "frag_u":     # U^q = W^q R^q
+        return "mfma", 8.0 * nk * nip * nip * s2 / 1e12, "TFLOP", pk
+    if stage == "v_gemm":     # Hermitian half of eta~ eta~^H
+        return "mfma", 8.0 * nk * nip * nip * ng / 2 / 1e12, "TFLOP", pk
+    if stage == "grid_fft":   # two read+write passes over eta (c128)
+        return "hbm", 4.0 * nk * nip * ng * 16 / 1e9, "GB", PEAK["hbm"]
+    if stage == "rhs":        # T^k_I(r) written + read, eta written once (c128)
+        return "hbm", 3.0 * nk * nip * ng * 16 / 1e9, "GB", PEAK["hbm"]
+    if stage == "metric_kconv":
+        return "hbm", 2.0 * nk * nip * nip * 16 / 1e9, "GB", PEAK["hbm"]
+    if stage == "frag_pair":  # write R^q once (c128)
+        return "hbm", nk * nip * s2 * 16 / 1e9, "GB", PEAK["hbm"]
+    if stage == "chol":
+        return "fp64", 8.0 * nk * nip ** 3 / 3 / 1e12, "TFLOP", PEAK["fp64"]
+    if stage == "w_solve":    # four triangular solves with N_IP right-hand sides
+        return "fp64", 4 * 8.0 * nk * nip ** 3 / 2 / 1e12, "TFLOP", PEAK["fp64"]
+    if stage == "metric_t":
+        return "mfma", 8.0 * nk * nip * nip * norb / 2 / 1e12, "TFLOP", PEAK["fp64"]
+    if stage == "frag_t":
+        return "mfma", 8.0 * nk * nip * norb * sum(nfs) / 1e12, "TFLOP", PEAK["fp64"]
+    return None
+
+
+STAGES = ["metric_t", "metric_kconv", "rhs", "chol", "grid_fft", "v_gemm", "w_solve",
+          "frag_t", "frag_pair", "frag_u", "frag_eri"]
+
+
+def cpu_baseline(d, frags, w_gpu, budget_s):
+    """The FP64 oracle on a bounded sample of the same step, extrapolated to
+    the whole step with the cost model stated in the sample string."""
+    import numpy as np
+    from oracle import kpoint as ko
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [os.cpu_count()])
+    except Exception:
+        cores = os.cpu_count()
+    cfg = d.cfg
+    rng = np.random.default_rng(0)
+    t0 = time.perf_counter()
+    x = ko.ip_values(d.orbitals, d.ip_index)
+    pi = ko.metric_k(x, cfg.kmesh)
+    t_metric = time.perf_counter() - t0
+    nr = min(512, cfg.n_g)
+    ridx = np.sort(rng.choice(cfg.n_g, nr, replace=False))
+    t0 = time.perf_counter()
+    ko.rhs(x, d.orbitals, cfg.kmesh, [0], ridx)
+    t1 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ko.rhs(x, d.orbitals, cfg.kmesh, [0, 1], ridx)
+    t2 = time.perf_counter() - t0
+    per_q = max(t2 - t1, 0.0)
+    t_rhs = (max(t1 - per_q, 0.0) + cfg.n_k * per_q) * cfg.n_g / nr
+    eta_q = (rng.standard_normal((cfg.n_ip, cfg.n_g))
+             + 1j * rng.standard_normal((cfg.n_ip, cfg.n_g)))
+    t0 = time.perf_counter()
+    ko.kernel_v_route(pi, eta_q[None], d.lattice, cfg.grid, cfg.kmesh, qs=[1])
+    t_w = (time.perf_counter() - t0) * cfg.n_k
+    # fragments: two sizes, cost model t = a n_f^2 + b n_f^4
+    nfs = [f.shape[2] for f in frags]
+    order = np.argsort(nfs)
+    pick = [int(order[0]), int(order[len(order) // 2])]
+    ts = []
+    for f in pick:
+        t0 = time.perf_counter()
+        ko.fragment_eri(x, frags[f], w_gpu, cfg.kmesh)
+        ts.append(time.perf_counter() - t0)
+        if sum(ts) > budget_s:
+            break
+    if len(ts) == 2 and nfs[pick[0]] != nfs[pick[1]]:
+        a_ = np.array([[nfs[p] ** 2, nfs[p] ** 4] for p in pick], dtype=float)
+        coef = np.linalg.lstsq(a_, np.array(ts), rcond=None)[0]
+        coef = np.maximum(coef, 0)
+        t_frag = float(sum(coef[0] * n ** 2 + coef[1] * n ** 4 for n in nfs))
+    else:
+        t_frag = ts[0] * sum(n ** 4 for n in nfs) / nfs[pick[0]] ** 4
+    t_step = t_metric + t_rhs + t_w + t_frag
+    erisum = float(sum(n ** 4 for n in nfs))
+    return {
+        "value": erisum / t_step, "unit": "ERIs/s", "cores": int(cores), "kind": "oracle",
+        "sample": ("FP64 numpy oracle (direct k and R sums) on this host: metric for all q; "
+                   "eta on %d sampled grid points for 1 and 2 q, scaled to all points and q; "
+                   "W for one q (FFT, V, pseudo-inverse) times N_q; ERIs of fragments with "
+                   "n_f = %s given the GPU FP64 W, extrapolated with t = a n_f^2 + b n_f^4 "
+                   "to all %d fragments; extrapolated step %.1f s (measured %.1f s)"
+                   % (nr, [nfs[p] for p in pick[:len(ts)]], len(nfs), t_step,
+                      t_metric + t1 + t2 + t_w / cfg.n_k + sum(ts))),
+        "seconds_per_step": t_step,
+        "stage_s": {"metric": t_metric, "rhs": t_rhs, "w": t_w, "fragments": t_frag},
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    torch.cuda.set_device(0)
+    import isdf_inputs as inp
+    import paper_2601_16379_amd as pkg
+
+    cfg = inp.get_config(args.workload)
+    t_gen = time.perf_counter()
+    d = inp.make_inputs(cfg)
+    frags = inp.make_fragments(cfg)
+    nfs = [int(f.shape[2]) for f in frags]
+    t_gen = time.perf_counter() - t_gen
+    print("inputs %s generated in %.1f s: N_k=%d grid=%s n_orb=%d n_ip=%d fragments=%d"
+          % (cfg.name, t_gen, cfg.n_k, cfg.grid, cfg.n_orb, cfg.n_ip, len(frags)),
+          file=sys.stderr, flush=True)
+
+    orb = torch.from_numpy(d.orbitals).cuda()
+    ip = torch.from_numpy(d.ip_index).cuda()
+    ctx = pkg.Isdf(d.lattice, cfg.grid, cfg.kmesh, orb, ip)
+    del orb
+    cdev = [torch.from_numpy(f).cuda() for f in frags]
+    out_mix = [torch.empty((n, n, n, n), dtype=torch.complex128, device="cuda") for n in nfs]
+    out_64 = [torch.empty((n, n, n, n), dtype=torch.complex128, device="cuda") for n in nfs]
+    torch.cuda.synchronize()
+    per_req = 16 * (cfg.n_k * cfg.n_orb * max(nfs) + cfg.n_k * cfg.n_ip * max(nfs)
+                    + 2 * cfg.n_k * cfg.n_ip * max(nfs) ** 2)
+    batch_bytes = 16 * (cfg.n_k * cfg.n_orb * sum(nfs) + cfg.n_k * cfg.n_ip * sum(nfs)
+                        + 2 * cfg.n_k * cfg.n_ip * sum(n * n for n in nfs)) + (1 << 26)
+    budget = 2 * max(batch_bytes, per_req)
+    ctx.serve_start(max_inflight=2, max_batch=len(frags), budget_bytes=budget)
+
+    def step(prec, outs):
+        ctx.fit()
+        ctx.coulomb_kernel(prec)
+        tickets = ctx.submit_n(cdev, outs, prec)
+        lat = {}
+        pending = set(tickets)
+        while pending:
+            for t in list(pending):
+                st, l = ctx.poll(t)
+                if st == "DONE":
+                    lat[t] = l
+                    pending.discard(t)
+                elif st in ("FAILED", "CANCELLED"):
+                    raise RuntimeError("request %d %s: %s" % (t, st, ctx.last_error()))
+        return [lat[t] for t in tickets]
+
+    for i in range(args.warmup):
+        step(args.prec, out_mix)
+        print("warmup step %d done" % i, file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    ctx.stage_reset()
+    lats = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        lats += step(args.prec, out_mix)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = 1e3 * wall / args.steps
+    print("timed %d steps: %.2f ms/step" % (args.steps, ms_step), file=sys.stderr, flush=True)
+    stage = {}
+    for s in STAGES:
+        tot, cnt = ctx.stage_total(s)
+        if cnt:
+            stage[s] = (tot, cnt)
+    erisum = float(sum(n ** 4 for n in nfs))
+    value = erisum * args.steps / wall
+    lat_ms = 1e3 * np.asarray(lats)
+
+    # dominant kernel and its roofline
+    dom = max(stage, key=lambda k: stage[k][0])
+    bound, amount, unit, peak = stage_work(dom, cfg, nfs, args.prec)
+    avg_ms = stage[dom][0] / stage[dom][1]
+    achieved = amount / (avg_ms / 1e3)
+    if unit == "GB":
+        roof = {"bound": "hbm", "achieved": achieved, "peak": peak, "unit": "GB/s"}
+    elif bound == "mfma":
+        roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s"}
+    roof["frac"] = achieved / peak
+    roof["traffic"] = None
+    roof["kernel"] = dom
+    roof["avg_ms"] = avg_ms
+
+    stage_rows = {}
+    for s, (tot, cnt) in stage.items():
+        w = stage_work(s, cfg, nfs, args.prec)
+        row = {"avg_ms": tot / cnt, "share": tot / sum(v[0] for v in stage.values())}
+        if w:
+            rate = w[1] / (tot / cnt / 1e3)
+            row["rate"] = rate
+            row["unit"] = "GB/s" if w[2] == "GB" else "TFLOP/s"
+            row["frac"] = rate / w[3]
+        stage_rows[s] = row
+
+    extra = {}
+    if not args.no_fp64_ref and args.prec != "fp64":
+        step("fp64", out_64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        step("fp64", out_64)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t0
+        # W is rebuilt by the last call: rebuild the mixed W for consistency of
+        # later calls (not timed)
+        errs = [float((a - b).abs().max().item()) for a, b in zip(out_mix, out_64)]
+        extra["fp64_ms_per_step"] = 1e3 * t64
+        extra["speedup_vs_fp64"] = t64 * 1e3 / ms_step
+        extra["max_err_eh"] = max(errs)
+        extra["max_err_eh_per_result"] = {"min": min(errs), "median": float(np.median(errs)),
+                                          "max": max(errs), "n": len(errs)}
+        extra["err_bound_eh"] = 1e-6
+    cpu = None
+    if not args.no_cpu_baseline:
+        w_gpu = np.stack([ctx.get_kernel(q) for q in range(cfg.n_k)])
+        cpu = cpu_baseline(d, frags, w_gpu, args.cpu_budget_s)
+    ctx.serve_stop()
+    ctx.close()
+
+    out = {
+        "metric": "fragment ERIs/s + p50/p99 latency, mixed vs FP64 at <=1e-6 Eh max error",
+        "value": value,
+        "unit": "ERIs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.prec,
+        "data": "synthetic",
+        "config": {"workload": cfg.name, "n_k": cfg.n_k, "kmesh": list(cfg.kmesh),
+                   "grid": list(cfg.grid), "n_orb": cfg.n_orb, "n_ip": cfg.n_ip,
+                   "fragments": len(nfs), "n_f_range": [min(nfs), max(nfs)],
+                   "eris_per_step": erisum, "parallelism": "1 GPU"},
+        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)),
+                       "p99": float(np.percentile(lat_ms, 99)), "n": int(lat_ms.size)},
+        "fragments_per_s": len(nfs) * args.steps / wall,
+        "roofline": roof,
+        "stages": stage_rows,
+        "cpu_baseline": cpu,
+    }
+    out.update(extra)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

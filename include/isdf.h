@@ -91,7 +91,7 @@ typedef enum {
  *   orbitals  c128 [N_k][n_orb][N_g], host or device (ISDF_INPUT_DEVICE).
  *   ip_index  int32 [n_ip] grid indices r_I (0 <= r_I < N_g, distinct), caller
  *             selected (the paper selects them by pivoted Cholesky).
- *   n_ip      number of interpolation points (1..4096).
+ *   n_ip      number of interpolation points (1..2048).
  *   hip_stream  hipStream_t every call of this context launches on (0 = null
  *               stream); the caller keeps it alive until isdf_destroy.
  * The library copies orbitals and ip_index into its own device memory; the
@@ -158,6 +158,9 @@ isdf_status isdf_fragment_eri(isdf_ctx ctx, isdf_precision prec, int32_t n_frag,
  * so requests that arrive while others run join the next batch.  C and eri
  * are caller-owned and must stay valid until poll reports DONE, FAILED or
  * CANCELLED.  latency = submit -> completion observed (host monotonic clock).
+ * isdf_fit and isdf_coulomb_kernel may run while serving only when no request
+ * is queued or running (ISDF_E_BUSY otherwise); a request admitted while no
+ * W^q exists ends FAILED.
  */
 typedef struct {
   int32_t n_f;
@@ -170,6 +173,9 @@ typedef struct {
 isdf_status isdf_serve_start(isdf_ctx ctx, int32_t max_inflight, int32_t max_batch,
                              int64_t budget_bytes);
 isdf_status isdf_submit(isdf_ctx ctx, const isdf_request* req, uint64_t* ticket);
+/* Submit n requests at one instant (same submit time; admitted together when
+ * they fit one batch).  tickets: [n] output.  All-or-nothing validation. */
+isdf_status isdf_submit_n(isdf_ctx ctx, int32_t n, const isdf_request* reqs, uint64_t* tickets);
 isdf_status isdf_poll(isdf_ctx ctx, uint64_t ticket, int32_t* state, double* latency_s);
 isdf_status isdf_cancel(isdf_ctx ctx, uint64_t ticket);
 /* Stops accepting requests, waits for everything queued, joins the thread. */
@@ -179,11 +185,15 @@ isdf_status isdf_serve_stop(isdf_ctx ctx);
  * last call of each stage, served request counts.  Truncated to cap bytes. */
 isdf_status isdf_stats(isdf_ctx ctx, char* json, int64_t cap);
 
-/* Device milliseconds of the named kernel family over the last call that ran
- * it, measured with HIP events on the context stream ("metric_kconv",
- * "rhs_kconv", "grid_fft", "v_gemm", "chol", "w_solve", "frag_t", "frag_pair",
+/* Device milliseconds of a stage over the last call that ran it, measured
+ * with HIP events on the stream the stage ran on ("metric_t", "metric_kconv",
+ * "rhs", "chol", "grid_fft", "v_gemm", "w_solve", "frag_t", "frag_pair",
  * "frag_u", "frag_eri"); -1 if unknown. */
 double isdf_stage_ms(isdf_ctx ctx, const char* name);
+/* Sum of the device milliseconds and the number of intervals of a stage since
+ * the context was created or isdf_stage_reset (served batches included). */
+isdf_status isdf_stage_total(isdf_ctx ctx, const char* name, double* ms, int64_t* count);
+isdf_status isdf_stage_reset(isdf_ctx ctx);
 
 /* Memory planner: device bytes that isdf_create/fit/coulomb_kernel would hold
  * for these sizes (no allocation), and the storage model of the paper's
@@ -193,6 +203,8 @@ int64_t isdf_plan_bytes(const int32_t grid[3], const int32_t kmesh[3], int32_t n
 int64_t isdf_storage_model_bytes(int64_t n_k, int64_t n_ip, int64_t n_ao);
 
 isdf_status isdf_destroy(isdf_ctx ctx);
+/* Message of the last failed call on ctx; with ctx == NULL, the message of the
+ * last failed isdf_create on the calling thread ("null context" if none). */
 const char* isdf_last_error(isdf_ctx ctx);
 const char* isdf_version(void);
 

@@ -16,6 +16,8 @@ LIB = os.path.join(HERE, "libisdf_gfx950.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+         # code objects loadable by the HIP runtime bundled with PyTorch
+         "-mcode-object-version=5",
          # keep hipcc from emitting packed FP32 instructions
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include")]

@@ -32,3 +32,30 @@ __device__ inline cplx cexpipi(double x) {
 }
 
 static inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+// Store one complex value in one of the operand formats of the NT GEMM:
+// 0 complex128 at element off; 1 float planes re|im; 2 bf16 planes
+// re_hi|re_lo|im_hi|im_lo (x = hi + lo), element off of each plane.
+__device__ inline unsigned short bf16_bits_of(float x) {
+  __bf16 h = (__bf16)x;
+  return __builtin_bit_cast(unsigned short, h);
+}
+__device__ inline float bf16_value(unsigned short b) { return (float)__builtin_bit_cast(__bf16, b); }
+
+__device__ inline void store_fmt(void* out, long long off, long long plane, int fmt, cplx v) {
+  if (fmt == 0) {
+    ((cplx*)out)[off] = v;
+  } else if (fmt == 1) {
+    float* o = (float*)out;
+    o[off] = (float)v.x;
+    o[plane + off] = (float)v.y;
+  } else {
+    unsigned short* o = (unsigned short*)out;
+    const float fr = (float)v.x, fi = (float)v.y;
+    const unsigned short rh = bf16_bits_of(fr), ih = bf16_bits_of(fi);
+    o[off] = rh;
+    o[plane + off] = bf16_bits_of(fr - bf16_value(rh));
+    o[2 * plane + off] = ih;
+    o[3 * plane + off] = bf16_bits_of(fi - bf16_value(ih));
+  }
+}

@@ -146,7 +146,20 @@ __global__ __launch_bounds__(256) void col_kernel(GridFftArgs a) {
     const double kz = g1 * a.recip[2] + g2 * a.recip[5] + g3 * a.recip[8];
     const double k2 = kx * kx + ky * ky + kz * kz;
     const double f = (k2 > 1e-20) ? coef / sqrt(k2) : 0.0;
-    base[(long long)i1 * n23 + col] = cscale(buf[idx], f);
+    const cplx v = cscale(buf[idx], f);
+    if (a.fmt == 0) {
+      base[(long long)i1 * n23 + col] = v;
+    } else {
+      const long long off = (long long)qi * a.split_q + (long long)I * a.split_ld + (long long)i1 * n23 + col;
+      store_fmt(a.split, off, a.split_plane, a.fmt, v);
+    }
+  }
+  // zero the row padding of the split output (grid points N_g .. ld-1)
+  if (a.fmt != 0 && cb == ncb - 1) {
+    const long long ng = (long long)a.n1 * n23;
+    for (long long g = ng + threadIdx.x; g < a.split_ld; g += blockDim.x)
+      store_fmt(a.split, (long long)qi * a.split_q + (long long)I * a.split_ld + g, a.split_plane, a.fmt,
+                cmk(0.0, 0.0));
   }
 }
 

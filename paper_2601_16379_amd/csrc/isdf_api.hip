@@ -14,6 +14,7 @@
 #include <map>
 #include <mutex>
 #include <new>
+#include <set>
 #include <string>
 #include <thread>
 #include <unordered_map>
@@ -134,6 +135,36 @@ void run_gemm(Arena& ar, int prec, int layout, std::vector<GemmDesc>& d, hipStre
   HIPCHK(gemm_launch(prec, layout, dd, (int)d.size(), total, max_gemm_blocks(), s));
 }
 
+void run_nt(Arena& ar, int prec, int conj, std::vector<NtDesc>& d, hipStream_t s) {
+  long long total = nt_plan(d.data(), (int)d.size());
+  if (total == 0) return;
+  NtDesc* dd = ar.put(d.data(), d.size(), s);
+  HIPCHK(nt_launch(prec, conj, dd, (int)d.size(), total, max_gemm_blocks(), s));
+}
+
+NtDesc mknt(const void* A, long long lda, const void* B, long long ldb, void* C, long long ldc,
+            int M, int N, int K) {
+  NtDesc d;
+  memset(&d, 0, sizeof(d));
+  d.A = A;
+  d.B = B;
+  d.C = C;
+  d.lda = lda;
+  d.ldb = ldb;
+  d.ldc = ldc;
+  d.M = M;
+  d.N = N;
+  d.Kseg = K;
+  d.Klast = K;
+  d.nseg = 1;
+  d.batch = 1;
+  return d;
+}
+
+// bytes per complex element of the GEMM operand format of a precision
+size_t fmt_bytes(int prec) { return prec == 0 ? 16 : 8; }
+size_t fmt_scalar(int prec) { return prec == 0 ? 16 : (prec == 1 ? 4 : 2); }
+
 GemmDesc mkdesc(const cplx* A, long long lda, const cplx* B, long long ldb, cplx* C, long long ldc,
                 int M, int N, int K) {
   GemmDesc d;
@@ -156,7 +187,8 @@ GemmDesc mkdesc(const cplx* A, long long lda, const cplx* B, long long ldb, cplx
 // Stage timer: HIP events on the context stream.
 struct StageTimer {
   std::map<std::string, std::pair<hipEvent_t, hipEvent_t>> ev;
-  std::map<std::string, float> ms;
+  std::map<std::string, float> ms;          // last interval
+  std::set<std::string> pending;            // recorded since the last collect
   void begin(const std::string& n, hipStream_t s) {
     auto it = ev.find(n);
     if (it == ev.end()) {
@@ -167,13 +199,27 @@ struct StageTimer {
     }
     HIPCHK(hipEventRecord(it->second.first, s));
   }
-  void end(const std::string& n, hipStream_t s) { HIPCHK(hipEventRecord(ev[n].second, s)); }
-  void collect() {
-    for (auto& kv : ev) {
+  void end(const std::string& n, hipStream_t s) {
+    HIPCHK(hipEventRecord(ev[n].second, s));
+    pending.insert(n);
+  }
+  // After the stream has drained: read the intervals recorded since the last
+  // collect, and add them to totals (ms, count) if given.
+  void collect(std::map<std::string, std::pair<double, long long>>* totals = nullptr) {
+    for (const std::string& n : pending) {
+      auto& kv = ev[n];
       float t = -1.f;
-      if (hipEventElapsedTime(&t, kv.second.first, kv.second.second) == hipSuccess) ms[kv.first] = t;
-      else (void)hipGetLastError();
+      if (hipEventElapsedTime(&t, kv.first, kv.second) == hipSuccess) {
+        ms[n] = t;
+        if (totals) {
+          (*totals)[n].first += t;
+          (*totals)[n].second += 1;
+        }
+      } else {
+        (void)hipGetLastError();
+      }
     }
+    pending.clear();
   }
   ~StageTimer() {
     for (auto& kv : ev) {
@@ -198,6 +244,7 @@ struct Workspace {
   DevBuf mem;     // C_all | Tf | M | U | eri staging
   PinnedBuf hostc;  // staging for host C
   Arena arena;
+  StageTimer timer;
   hipEvent_t done = nullptr;
   std::vector<uint64_t> tickets;
   std::vector<FragIn> frags;
@@ -227,6 +274,8 @@ struct isdf_ctx_s {
   int device = 0;
   // resident device data
   DevBuf phi, ip, xt, pi, eta, lt, w, work1, work2, perm, rank, rchunk, flag;
+  DevBuf wt64, wt32, wt16, eta_split;   // W transposed in the three GEMM formats; split eta~
+  long long ld_ip = 0, ld_g = 0;        // row pitches of split operands (multiples of 8)
   bool fitted = false, kernel_ready = false, eta_valid = false;
   std::vector<int> rank_h;
   long long rc = 0;   // r-chunk of the RHS
@@ -247,10 +296,16 @@ struct isdf_ctx_s {
   std::deque<uint64_t> queue;
   std::vector<Workspace*> ws_pool;
   long long served = 0, batches = 0;
+  int inflight_n = 0;
   std::string serve_err;
+  // accumulated device milliseconds and interval counts per stage
+  std::map<std::string, std::pair<double, long long>> totals;
 };
 
 namespace {
+
+// message of the last failed isdf_create on this thread (no context exists)
+thread_local std::string t_create_err;
 
 isdf_status fail(isdf_ctx c, isdf_status st, const std::string& msg) {
   if (c) c->err = msg;
@@ -272,6 +327,17 @@ template <class F> isdf_status guarded(isdf_ctx c, F&& f) {
     c->err = "unexpected exception";
     return ISDF_E_INVALID;
   }
+}
+
+// No request queued or on the GPU (refitting is allowed between requests).
+bool serve_idle(isdf_ctx c) {
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (!c->serving) return true;
+  for (uint64_t t : c->queue) {
+    auto it = c->reqs.find(t);
+    if (it != c->reqs.end() && it->second.state == ISDF_REQ_QUEUED) return false;
+  }
+  return c->inflight_n == 0;
 }
 
 bool good_grid(int n) {
@@ -361,7 +427,10 @@ void do_fit(isdf_ctx c) {
   c->rank_h.assign(nk, 0);
   HIPCHK(hipMemcpyAsync(c->rank_h.data(), c->rank.p, sizeof(int) * nk, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  c->timer.collect();
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->timer.collect(&c->totals);
+  }
   for (int q = 0; q < nk; ++q) {
     if (c->rank_h[q] <= 0)
       throw Fail{ISDF_E_NUMERIC, "metric Pi^q is zero or not finite at q = " + std::to_string(q)};
@@ -383,12 +452,20 @@ void do_kernel(isdf_ctx c, int prec) {
   const int nk = c->nk, nip = c->nip;
   const long long ng = c->ng;
   c->arena.reset();
-  // eta~^q_I(G) = sqrt(Omega 4pi/|G+q|^2)/N_g FFT[eta^q_I(r) exp(-iq.r)]   (eqs. (6)-(7))
+  // eta~^q_I(G) = sqrt(Omega 4pi/|G+q|^2)/N_g FFT[eta^q_I(r) exp(-iq.r)]   (eqs. (6)-(7));
+  // in place (FP64) or into the split operand format of the V GEMM (mixed)
+  const long long split_plane = (long long)nk * nip * c->ld_g;
+  if (prec != ISDF_FP64) c->eta_split.ensure((size_t)split_plane * 8);
   c->timer.begin("grid_fft", s);
   {
     GridFftArgs a;
     memset(&a, 0, sizeof(a));
     a.data = c->eta.as<cplx>();
+    a.fmt = prec;
+    a.split = c->eta_split.p;
+    a.split_ld = c->ld_g;
+    a.split_plane = split_plane;
+    a.split_q = (long long)nip * c->ld_g;
     a.n1 = c->n[0]; a.n2 = c->n[1]; a.n3 = c->n[2];
     a.m1 = c->m[0]; a.m2 = c->m[1]; a.m3 = c->m[2];
     a.q0 = 0;
@@ -401,24 +478,28 @@ void do_kernel(isdf_ctx c, int prec) {
   }
   c->timer.end("grid_fft", s);
   c->eta_valid = false;
-  // V^q = eta~ eta~^H  (Hermitian; lower tiles computed and mirrored)
+  // V^q = eta~ eta~^H  (Hermitian; lower tiles computed and mirrored); in the
+  // mixed precisions FP32 partial sums over 2048 grid points, FP64 across them
   c->timer.begin("v_gemm", s);
   {
-    std::vector<GemmDesc> d(1);
-    d[0] = mkdesc(c->eta.as<cplx>(), ng, c->eta.as<cplx>(), ng, c->work1.as<cplx>(), nip, nip, nip,
-                  (int)ng);
-    if (prec != ISDF_FP64) {
+    std::vector<NtDesc> d(1);
+    if (prec == ISDF_FP64) {
+      d[0] = mknt(c->eta.p, ng, c->eta.p, ng, c->work1.p, nip, nip, nip, (int)ng);
+      d[0].sA_bat = d[0].sB_bat = (long long)nip * ng;
+    } else {
+      d[0] = mknt(c->eta_split.p, c->ld_g, c->eta_split.p, c->ld_g, c->work1.p, nip, nip, nip, (int)ng);
+      d[0].a_plane = d[0].b_plane = split_plane;
       const int kseg = 2048;
       d[0].Kseg = (int)std::min<long long>(kseg, ng);
       d[0].nseg = (int)((ng + d[0].Kseg - 1) / d[0].Kseg);
       d[0].Klast = (int)(ng - (long long)(d[0].nseg - 1) * d[0].Kseg);
       d[0].sA_seg = d[0].sB_seg = d[0].Kseg;
+      d[0].sA_bat = d[0].sB_bat = (long long)nip * c->ld_g;
     }
     d[0].batch = nk;
-    d[0].sA_bat = d[0].sB_bat = (long long)nip * ng;
     d[0].sC_bat = nip2(c);
     d[0].herm = 1;
-    run_gemm(c->arena, prec, GEMM_B_CONJ, d, s);
+    run_nt(c->arena, prec, 2, d, s);
   }
   c->timer.end("v_gemm", s);
   // W^q = Pi^{q+} V^q Pi^{q+}   (eq. (8)), FP64 triangular solves
@@ -426,12 +507,18 @@ void do_kernel(isdf_ctx c, int prec) {
   HIPCHK(wsolve_launch(c->work1.as<cplx>(), c->work2.as<cplx>(), c->w.as<cplx>(), c->lt.as<cplx>(),
                        c->perm.as<int>(), c->rank.as<int>(), nip, nk, s));
   c->timer.end("w_solve", s);
+  // transposed copies of W in the three operand formats of the fragment GEMMs
+  HIPCHK(wt_convert_launch(c->w.as<cplx>(), c->wt64.as<cplx>(), c->wt32.as<float>(),
+                           c->wt16.as<unsigned short>(), nip, (int)c->ld_ip, nk, s));
   HIPCHK(hipMemsetAsync(c->flag.p, 0, sizeof(int), s));
   HIPCHK(nonfinite_launch(c->w.as<cplx>(), (long long)nk * nip2(c), c->flag.as<int>(), s));
   int bad = 0;
   HIPCHK(hipMemcpyAsync(&bad, c->flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  c->timer.collect();
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->timer.collect(&c->totals);
+  }
   if (bad) throw Fail{ISDF_E_NUMERIC, "non-finite entries in W^q"};
   c->kernel_ready = true;
 }
@@ -447,7 +534,13 @@ struct BatchPlan {
   size_t off_c = 0, off_tf = 0, off_m = 0, off_u = 0, off_e = 0, bytes = 0;
 };
 
-BatchPlan plan_batch(isdf_ctx c, const std::vector<FragIn>& fr) {
+// Layout of one fragment batch in its workspace:
+//   C_all [N_k][n_orb][ncol] c128          coefficients of all fragments
+//   Tf    [N_k][ncol][N_IP] c128           T^k_{Ip} = sum_mu X C, then psi(r_I + R)
+//   M     [N_q][ptot][ld_ip] (format)      R^q_{I,pq}, rows = pairs of all fragments
+//   U     [N_q][ptot][ld_ip] (format)      U^q = R^q W^q (also stages host C first)
+//   E     host-bound ERI outputs (c128)
+BatchPlan plan_batch(isdf_ctx c, const std::vector<FragIn>& fr, int prec) {
   BatchPlan p;
   long long ecount = 0;
   for (const FragIn& f : fr) {
@@ -461,23 +554,23 @@ BatchPlan plan_batch(isdf_ctx c, const std::vector<FragIn>& fr) {
     if (!(f.flags & ISDF_FRAG_DEVICE)) ecount += e4;
   }
   auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  const size_t mb = (size_t)c->nk * p.ptot * c->ld_ip * fmt_bytes(prec);
   size_t off = 0;
   p.off_c = off; off += al((size_t)c->nk * c->norb * p.ncol * sizeof(cplx));
   p.off_tf = off; off += al((size_t)c->nk * c->nip * p.ncol * sizeof(cplx));
-  p.off_m = off; off += al((size_t)c->nk * c->nip * p.ptot * sizeof(cplx));
-  // U also stages host fragment coefficients before step 13 overwrites it
+  p.off_m = off; off += al(mb);
   p.off_u = off;
-  off += al(std::max<size_t>((size_t)c->nk * c->nip * p.ptot, (size_t)c->nk * c->norb * p.ncol) * sizeof(cplx));
+  off += al(std::max<size_t>(mb, (size_t)c->nk * c->norb * p.ncol * sizeof(cplx)));
   p.off_e = off; off += al((size_t)ecount * sizeof(cplx));
   p.bytes = off;
   return p;
 }
 
-size_t request_bytes(isdf_ctx c, int nf, bool host_out) {
-  size_t b = (size_t)c->nk * c->norb * nf + (size_t)c->nk * c->nip * nf +
-             2 * (size_t)c->nk * c->nip * nf * nf;
-  if (host_out) b += (size_t)nf * nf * nf * nf;
-  return b * sizeof(cplx) + 4 * 256;
+size_t request_bytes(isdf_ctx c, int nf, bool host_out, int prec) {
+  size_t b = ((size_t)c->nk * c->norb * nf + (size_t)c->nk * c->nip * nf) * sizeof(cplx) +
+             2 * (size_t)c->nk * c->ld_ip * nf * nf * fmt_bytes(prec);
+  if (host_out) b += (size_t)nf * nf * nf * nf * sizeof(cplx);
+  return b + 5 * 256;
 }
 
 // Enqueue the whole fragment pipeline of one batch on ws.stream.
@@ -486,14 +579,15 @@ void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn
   if (!c->kernel_ready) throw Fail{ISDF_E_STATE, "isdf_coulomb_kernel must run before fragment ERIs"};
   hipStream_t s = ws.stream;
   const int nk = c->nk, norb = c->norb, nip = c->nip;
-  BatchPlan p = plan_batch(c, fr);
+  const long long ld = c->ld_ip;
+  BatchPlan p = plan_batch(c, fr, prec);
   ws.mem.ensure(p.bytes);
   ws.arena.reset();
   char* base = ws.mem.as<char>();
   cplx* Call = (cplx*)(base + p.off_c);
   cplx* Tf = (cplx*)(base + p.off_tf);
-  cplx* Mq = (cplx*)(base + p.off_m);
-  cplx* Uq = (cplx*)(base + p.off_u);
+  char* Mq = base + p.off_m;
+  char* Uq = base + p.off_u;
   cplx* Est = (cplx*)(base + p.off_e);
   // upload / gather the fragment coefficients into C_all[k][mu][col]
   size_t host_bytes = 0;
@@ -508,24 +602,24 @@ void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn
     const cplx* src = (const cplx*)f.C;
     if (!(f.flags & ISDF_FRAG_DEVICE)) {
       memcpy((char*)ws.hostc.p + hoff, f.C, fb);
-      HIPCHK(hipMemcpyAsync((char*)Uq + hoff, (char*)ws.hostc.p + hoff, fb, hipMemcpyHostToDevice, s));
-      src = (const cplx*)((char*)Uq + hoff);
+      HIPCHK(hipMemcpyAsync(Uq + hoff, (char*)ws.hostc.p + hoff, fb, hipMemcpyHostToDevice, s));
+      src = (const cplx*)(Uq + hoff);
       hoff += fb;
     }
     HIPCHK(copy_cols_launch(src, Call, nk, norb, f.nf, p.ncol, p.col[i], s));
   }
-  if (timed) c->timer.begin("frag_t", s);
-  // T^k_{Ip} = sum_mu X^k_{I mu} C^k_{mu p}   (Algorithm 2)
+  if (timed) ws.timer.begin("frag_t", s);
+  // T^k_{pI} = sum_mu C^k_{mu p} X^k_{I mu}   (Algorithm 2, stored [k][p][I])
   {
     std::vector<GemmDesc> d(1);
-    d[0] = mkdesc(c->xt.as<cplx>(), nip, Call, p.ncol, Tf, p.ncol, nip, p.ncol, norb);
+    d[0] = mkdesc(Call, p.ncol, c->xt.as<cplx>(), nip, Tf, nip, p.ncol, nip, norb);
     d[0].batch = nk;
-    d[0].sA_bat = (long long)norb * nip;
-    d[0].sB_bat = (long long)norb * p.ncol;
+    d[0].sA_bat = (long long)norb * p.ncol;
+    d[0].sB_bat = (long long)norb * nip;
     d[0].sC_bat = (long long)nip * p.ncol;
     run_gemm(ws.arena, 0, GEMM_A_KM | GEMM_B_KN, d, s);
   }
-  // psi_p(r_I + R) = N_k^{-1/2} sum_k exp(ik.R) T^k_{Ip}
+  // psi_p(r_I + R) = N_k^{-1/2} sum_k exp(ik.R) T^k_{pI}
   {
     KconvArgs a;
     memset(&a, 0, sizeof(a));
@@ -540,17 +634,21 @@ void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn
     a.scale = 1.0 / std::sqrt((double)nk);
     HIPCHK(kconv_launch(a, s));
   }
-  if (timed) c->timer.end("frag_t", s);
-  // R^q_{I,pq} = N_k^{-1/2} sum_R exp(-iq.R) conj(psi_p) psi_q   (eq. (20))
-  if (timed) c->timer.begin("frag_pair", s);
+  if (timed) ws.timer.end("frag_t", s);
+  // R^q_{I,pq} = N_k^{-1/2} sum_R exp(-iq.R) conj(psi_p) psi_q   (eq. (20)),
+  // rows (pair) x I in the GEMM operand format of the precision
+  if (timed) ws.timer.begin("frag_pair", s);
+  const long long mplane = (long long)nk * p.ptot * ld;
   {
-    int pbmax = 4096 / nk;
-    if (pbmax > 256) pbmax = 256;
-    if (pbmax < 1) pbmax = 1;
+    // tile: ti interpolation points x tp pairs, nk * tp * ti <= 4096 (64 KB)
+    int ti = 32;
+    while (ti > 1 && (long long)nk * ti > 4096) ti >>= 1;
+    int tp = (int)std::max<long long>(1, 4096 / ((long long)nk * ti));
+    if (tp > 8) tp = 8;
     std::vector<PairBlock> blocks;
     for (size_t f = 0; f < fr.size(); ++f) {
       const int np = p.nf[f] * p.nf[f];
-      for (int p0 = 0; p0 < np; p0 += pbmax) blocks.push_back(PairBlock{(int)f, p0, std::min(pbmax, np - p0)});
+      for (int p0 = 0; p0 < np; p0 += tp) blocks.push_back(PairBlock{(int)f, p0, std::min(tp, np - p0)});
     }
     PairArgs a;
     memset(&a, 0, sizeof(a));
@@ -563,45 +661,58 @@ void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn
     a.nblocks = (int)blocks.size();
     a.n_ip = nip;
     a.ncol = p.ncol;
-    a.pb_max = pbmax;
+    a.tp = tp;
+    a.ti = ti;
+    a.n_itiles = (int)((ld + ti - 1) / ti);
     a.ptot = p.ptot;
+    a.ld = ld;
+    a.plane = mplane;
+    a.fmt = prec;
     a.m1 = c->m[0]; a.m2 = c->m[1]; a.m3 = c->m[2];
     a.scale = 1.0 / std::sqrt((double)nk);
     HIPCHK(pair_launch(a, s));
   }
-  if (timed) c->timer.end("frag_pair", s);
-  // U^q_{J,P} = sum_I W^q_{IJ} R^q_{I,P}   (eq. (19), first contraction)
-  if (timed) c->timer.begin("frag_u", s);
+  if (timed) ws.timer.end("frag_pair", s);
+  // U^q_{P,J} = sum_I R^q_{P,I} W^q_{IJ}   (eq. (19), first contraction)
+  if (timed) ws.timer.begin("frag_u", s);
   {
-    std::vector<GemmDesc> d(1);
-    d[0] = mkdesc(c->w.as<cplx>(), nip, Mq, p.ptot, Uq, p.ptot, nip, (int)p.ptot, nip);
+    const void* wt = prec == 0 ? c->wt64.p : (prec == 1 ? c->wt32.p : c->wt16.p);
+    std::vector<NtDesc> d(1);
+    d[0] = mknt(Mq, ld, wt, ld, Uq, ld, (int)p.ptot, nip, nip);
     d[0].batch = nk;
-    d[0].sA_bat = nip2(c);
-    d[0].sB_bat = d[0].sC_bat = (long long)nip * p.ptot;
-    run_gemm(ws.arena, prec, GEMM_A_KM | GEMM_B_KN, d, s);
+    d[0].a_plane = mplane;
+    d[0].b_plane = (long long)nk * nip * ld;
+    d[0].c_plane = mplane;
+    d[0].sA_bat = d[0].sC_bat = p.ptot * ld;
+    d[0].sB_bat = (long long)nip * ld;
+    d[0].epi = prec == 0 ? 0 : 3;
+    run_nt(ws.arena, prec, 0, d, s);
   }
-  if (timed) c->timer.end("frag_u", s);
-  // (pq|rs) = sum_q sum_J U^q_{J,(pq)} conj(R^q_{J,(sr)})  (eq. (19), R^{-q}_{rs} = conj R^q_{sr}),
+  if (timed) ws.timer.end("frag_u", s);
+  // (pq|rs) = sum_q sum_J U^q_{(pq),J} conj(R^q_{(sr),J})  (eq. (19), R^{-q}_{rs} = conj R^q_{sr}),
   // one grouped persistent launch over all fragments, FP64 sum over q
-  if (timed) c->timer.begin("frag_eri", s);
+  if (timed) ws.timer.begin("frag_eri", s);
   {
-    std::vector<GemmDesc> d;
+    std::vector<NtDesc> d;
+    const size_t sc = fmt_scalar(prec);
     for (size_t f = 0; f < fr.size(); ++f) {
       const int nf2 = p.nf[f] * p.nf[f];
       cplx* out = (fr[f].flags & ISDF_FRAG_DEVICE) ? (cplx*)fr[f].eri : Est + p.eoff[f];
-      GemmDesc g = mkdesc(Uq + p.poff[f], p.ptot, Mq + p.poff[f], p.ptot, out, 0, nf2, nf2, nip);
+      const size_t o = (size_t)p.poff[f] * ld * sc;
+      NtDesc g = mknt(Uq + o, ld, Mq + o, ld, out, 0, nf2, nf2, nip);
+      g.a_plane = g.b_plane = mplane;
       g.nseg = nk;
-      g.sA_seg = g.sB_seg = (long long)nip * p.ptot;
+      g.sA_seg = g.sB_seg = p.ptot * ld;
       g.herm = 1;
       g.epi = 2;
       g.nf = p.nf[f];
       d.push_back(g);
     }
     // largest fragments first so the persistent launch ends balanced
-    std::stable_sort(d.begin(), d.end(), [](const GemmDesc& a, const GemmDesc& b) { return a.M > b.M; });
-    run_gemm(ws.arena, prec, GEMM_A_KM | GEMM_B_KN | GEMM_B_CONJ, d, s);
+    std::stable_sort(d.begin(), d.end(), [](const NtDesc& a, const NtDesc& b) { return a.M > b.M; });
+    run_nt(ws.arena, prec, 2, d, s);
   }
-  if (timed) c->timer.end("frag_eri", s);
+  if (timed) ws.timer.end("frag_eri", s);
   for (size_t f = 0; f < fr.size(); ++f) {
     if (fr[f].flags & ISDF_FRAG_DEVICE) continue;
     const long long e4 = (long long)p.nf[f] * p.nf[f] * p.nf[f] * p.nf[f];
@@ -622,6 +733,8 @@ void serve_loop(isdf_ctx c) {
       if (q == hipErrorNotReady) { ++i; continue; }
       const double t = now_s();
       std::lock_guard<std::mutex> lk(c->mu);
+      if (q == hipSuccess) ws->timer.collect(&c->totals);
+      --c->inflight_n;
       for (uint64_t tk : ws->tickets) {
         auto it = c->reqs.find(tk);
         if (it == c->reqs.end()) continue;
@@ -659,7 +772,7 @@ void serve_loop(isdf_ctx c) {
           }
           const isdf_request& r = it->second.req;
           if (!fr.empty() && r.prec != prec) break;
-          long long b = (long long)request_bytes(c, r.n_f, !(r.flags & ISDF_FRAG_DEVICE));
+          long long b = (long long)request_bytes(c, r.n_f, !(r.flags & ISDF_FRAG_DEVICE), r.prec);
           if (!fr.empty() && used + b > cap) break;
           if (fr.empty()) prec = r.prec;
           used += b;
@@ -679,12 +792,13 @@ void serve_loop(isdf_ctx c) {
     }
     if (ws) {
       try {
-        enqueue_batch(c, *ws, prec, fr, false);
+        enqueue_batch(c, *ws, prec, fr, true);
         HIPCHK(hipEventRecord(ws->done, ws->stream));
         ws->tickets = tks;
         inflight.push_back(ws);
         std::lock_guard<std::mutex> lk(c->mu);
         ++c->batches;
+        ++c->inflight_n;
       } catch (const Fail& e) {
         (void)hipStreamSynchronize(ws->stream);
         std::lock_guard<std::mutex> lk(c->mu);
@@ -741,14 +855,21 @@ int64_t isdf_plan_bytes(const int32_t grid[3], const int32_t kmesh[3], int32_t n
 isdf_status isdf_create(isdf_ctx* out, const double* lattice, const int32_t grid[3],
                         const int32_t kmesh[3], int32_t n_orb, const void* orbitals,
                         const int32_t* ip_index, int32_t n_ip, uint32_t flags, void* hip_stream) {
-  if (!out) return ISDF_E_INVALID;
+  t_create_err.clear();
+  if (!out) { t_create_err = "null output handle"; return ISDF_E_INVALID; }
   *out = nullptr;
-  if (!lattice || !grid || !kmesh || !orbitals || !ip_index) return ISDF_E_INVALID;
-  for (int d = 0; d < 3; ++d) {
-    if (!good_grid(grid[d])) return ISDF_E_INVALID;
-    if (kmesh[d] < 1 || kmesh[d] > 16) return ISDF_E_INVALID;
+  if (!lattice || !grid || !kmesh || !orbitals || !ip_index) {
+    t_create_err = "null argument";
+    return ISDF_E_INVALID;
   }
-  if (n_orb < 1 || n_orb > 256 || n_ip < 1 || n_ip > 2048) return ISDF_E_INVALID;
+  for (int d = 0; d < 3; ++d) {
+    if (!good_grid(grid[d])) { t_create_err = "grid size must be 2..64 with factors 2,3,5,7"; return ISDF_E_INVALID; }
+    if (kmesh[d] < 1 || kmesh[d] > 16) { t_create_err = "k mesh must be 1..16 per axis"; return ISDF_E_INVALID; }
+  }
+  if (n_orb < 1 || n_orb > 256 || n_ip < 1 || n_ip > 2048) {
+    t_create_err = "n_orb must be 1..256 and n_ip 1..2048";
+    return ISDF_E_INVALID;
+  }
   isdf_ctx c = new (std::nothrow) isdf_ctx_s();
   if (!c) return ISDF_E_NOMEM;
   isdf_status st = guarded(c, [&] {
@@ -808,6 +929,11 @@ isdf_status isdf_create(isdf_ctx* out, const double* lattice, const int32_t grid
     c->work1.alloc(m2);
     c->work2.alloc(m2);
     c->eta.alloc((size_t)nk * n_ip * ng * e);
+    c->ld_ip = (n_ip + 7) / 8 * 8;
+    c->ld_g = (ng + 7) / 8 * 8;
+    c->wt64.alloc((size_t)nk * n_ip * c->ld_ip * e);
+    c->wt32.alloc((size_t)nk * n_ip * c->ld_ip * 8);
+    c->wt16.alloc((size_t)nk * n_ip * c->ld_ip * 8);
     c->rchunk.alloc((size_t)nk * n_ip * c->rc * e);
     c->perm.alloc(sizeof(int) * nk * n_ip);
     c->rank.alloc(sizeof(int) * nk);
@@ -820,6 +946,7 @@ isdf_status isdf_create(isdf_ctx* out, const double* lattice, const int32_t grid
     HIPCHK(hipEventCreateWithFlags(&c->sync_ws.done, hipEventDisableTiming));
   });
   if (st != ISDF_OK) {
+    t_create_err = c->err;
     delete c;
     return st;
   }
@@ -829,7 +956,7 @@ isdf_status isdf_create(isdf_ctx* out, const double* lattice, const int32_t grid
 
 isdf_status isdf_fit(isdf_ctx ctx) {
   return guarded(ctx, [&] {
-    if (ctx->serving) throw Fail{ISDF_E_STATE, "stop serving before refitting"};
+    if (!serve_idle(ctx)) throw Fail{ISDF_E_BUSY, "requests are queued or running"};
     do_fit(ctx);
   });
 }
@@ -837,7 +964,7 @@ isdf_status isdf_fit(isdf_ctx ctx) {
 isdf_status isdf_coulomb_kernel(isdf_ctx ctx, isdf_precision prec) {
   return guarded(ctx, [&] {
     if (prec < ISDF_FP64 || prec > ISDF_MIXED_BF16X3) throw Fail{ISDF_E_INVALID, "bad precision"};
-    if (ctx->serving) throw Fail{ISDF_E_STATE, "stop serving before rebuilding W"};
+    if (!serve_idle(ctx)) throw Fail{ISDF_E_BUSY, "requests are queued or running"};
     do_kernel(ctx, prec);
   });
 }
@@ -901,14 +1028,15 @@ isdf_status isdf_fragment_eri(isdf_ctx ctx, isdf_precision prec, int32_t n_frag,
     }
     enqueue_batch(ctx, ctx->sync_ws, prec, fr, true);
     HIPCHK(hipStreamSynchronize(ctx->stream));
-    ctx->timer.collect();
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->sync_ws.timer.collect(&ctx->totals);
+    for (auto& kv : ctx->sync_ws.timer.ms) ctx->timer.ms[kv.first] = kv.second;
   });
 }
 
 isdf_status isdf_serve_start(isdf_ctx ctx, int32_t max_inflight, int32_t max_batch, int64_t budget_bytes) {
   return guarded(ctx, [&] {
     if (ctx->serving) throw Fail{ISDF_E_STATE, "already serving"};
-    if (!ctx->kernel_ready) throw Fail{ISDF_E_STATE, "isdf_coulomb_kernel must run before serving"};
     if (max_inflight < 1 || max_inflight > 8 || max_batch < 1 || budget_bytes <= 0)
       throw Fail{ISDF_E_INVALID, "bad serving parameters"};
     ctx->max_inflight = max_inflight;
@@ -933,23 +1061,34 @@ isdf_status isdf_serve_start(isdf_ctx ctx, int32_t max_inflight, int32_t max_bat
 }
 
 isdf_status isdf_submit(isdf_ctx ctx, const isdf_request* req, uint64_t* ticket) {
+  return isdf_submit_n(ctx, 1, req, ticket);
+}
+
+isdf_status isdf_submit_n(isdf_ctx ctx, int32_t n, const isdf_request* reqs, uint64_t* tickets) {
   if (!ctx) return ISDF_E_INVALID;
-  if (!req || !ticket || req->n_f < 1 || req->n_f > ctx->nk * ctx->norb || !req->C || !req->eri ||
-      req->prec < ISDF_FP64 || req->prec > ISDF_MIXED_BF16X3)
-    return fail(ctx, ISDF_E_INVALID, "bad request");
+  if (n < 1 || !reqs || !tickets) return fail(ctx, ISDF_E_INVALID, "bad request list");
   std::lock_guard<std::mutex> lk(ctx->mu);
   if (!ctx->serving || ctx->stop) return fail(ctx, ISDF_E_STATE, "not serving");
-  if (ctx->queue.size() >= 100000) return fail(ctx, ISDF_E_BUSY, "request queue full");
-  const bool host_out = !(req->flags & ISDF_FRAG_DEVICE);
-  if ((long long)request_bytes(ctx, req->n_f, host_out) > ctx->budget / ctx->max_inflight)
-    return fail(ctx, ISDF_E_NOMEM, "request exceeds the per-batch memory budget");
-  const uint64_t t = ctx->next_ticket++;
-  Request r;
-  r.req = *req;
-  r.t_submit = now_s();
-  ctx->reqs.emplace(t, r);
-  ctx->queue.push_back(t);
-  *ticket = t;
+  if (ctx->queue.size() + n > 100000) return fail(ctx, ISDF_E_BUSY, "request queue full");
+  for (int i = 0; i < n; ++i) {
+    const isdf_request* req = reqs + i;
+    if (req->n_f < 1 || req->n_f > ctx->nk * ctx->norb || !req->C || !req->eri ||
+        req->prec < ISDF_FP64 || req->prec > ISDF_MIXED_BF16X3)
+      return fail(ctx, ISDF_E_INVALID, "bad request " + std::to_string(i));
+    const bool host_out = !(req->flags & ISDF_FRAG_DEVICE);
+    if ((long long)request_bytes(ctx, req->n_f, host_out, req->prec) > ctx->budget / ctx->max_inflight)
+      return fail(ctx, ISDF_E_NOMEM, "request " + std::to_string(i) + " exceeds the per-batch memory budget");
+  }
+  const double t0 = now_s();
+  for (int i = 0; i < n; ++i) {
+    const uint64_t t = ctx->next_ticket++;
+    Request r;
+    r.req = reqs[i];
+    r.t_submit = t0;
+    ctx->reqs.emplace(t, r);
+    ctx->queue.push_back(t);
+    tickets[i] = t;
+  }
   ctx->cv.notify_all();
   return ISDF_OK;
 }
@@ -1019,6 +1158,23 @@ isdf_status isdf_stats(isdf_ctx ctx, char* json, int64_t cap) {
   return ISDF_OK;
 }
 
+isdf_status isdf_stage_total(isdf_ctx ctx, const char* name, double* ms, int64_t* count) {
+  if (!ctx) return ISDF_E_INVALID;
+  if (!name || !ms || !count) return fail(ctx, ISDF_E_INVALID, "null argument");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  auto it = ctx->totals.find(name);
+  *ms = it == ctx->totals.end() ? 0.0 : it->second.first;
+  *count = it == ctx->totals.end() ? 0 : it->second.second;
+  return ISDF_OK;
+}
+
+isdf_status isdf_stage_reset(isdf_ctx ctx) {
+  if (!ctx) return ISDF_E_INVALID;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->totals.clear();
+  return ISDF_OK;
+}
+
 double isdf_stage_ms(isdf_ctx ctx, const char* name) {
   if (!ctx || !name) return -1.0;
   auto it = ctx->timer.ms.find(name);
@@ -1034,7 +1190,7 @@ isdf_status isdf_destroy(isdf_ctx ctx) {
 }
 
 const char* isdf_last_error(isdf_ctx ctx) {
-  if (!ctx) return "null context";
+  if (!ctx) return t_create_err.empty() ? "null context" : t_create_err.c_str();
   return ctx->err.c_str();
 }
 

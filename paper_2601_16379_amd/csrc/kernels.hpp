@@ -39,6 +39,40 @@ hipError_t gemm_launch(int prec, int layout_flags, const GemmDesc* descs_dev, in
                        long long total_tiles, int max_blocks, hipStream_t s);
 
 // ---------------------------------------------------------------------------
+// "NT" complex GEMM (both operands k-contiguous rows) for the large
+// contractions:  C[m][n] (+)= sum_s sum_k opA(A_s[m][k]) opB(B_s[n][k]).
+// Operand formats by precision: 0 complex128 rows (ld in complex elements);
+// 1 two float planes re|im; 2 four bf16 planes re_hi|re_lo|im_hi|im_lo (ld and
+// plane strides in scalar elements; rows zero-padded to a multiple of 8).
+// epi: 0 store c128, 1 accumulate c128, 2 ERI scatter c128, 3 store in the
+// split format of the precision (plane stride c_plane), zero-filling columns
+// N..ldc-1.
+// ---------------------------------------------------------------------------
+struct NtDesc {
+  const void* A;
+  const void* B;
+  void* C;
+  long long lda, ldb, ldc;
+  long long a_plane, b_plane, c_plane;
+  long long sA_seg, sB_seg;
+  long long sA_bat, sB_bat, sC_bat;
+  int M, N, Kseg, nseg, Klast, batch;
+  int tiles_m, tiles_n, tiles_per_batch;
+  int herm, epi, nf;
+  long long tile_begin;
+};
+long long nt_plan(NtDesc* d, int n);
+// conj: bit 0 conjugates A, bit 1 conjugates B
+hipError_t nt_launch(int prec, int conj, const NtDesc* descs_dev, int ndesc, long long total,
+                     int max_blocks, hipStream_t s);
+
+// W^q (c128 [q][n][n]) -> transposed copies Wt[q][J][I] = W[q][I][J] with row
+// pitch ld in c128, two-float-plane and four-bf16-plane formats (any output
+// pointer may be null); pad columns are zero.
+hipError_t wt_convert_launch(const cplx* w, cplx* wt64, float* wt32, unsigned short* wt16, int n,
+                             int ld, int nq, hipStream_t s);
+
+// ---------------------------------------------------------------------------
 // k-mesh transforms (Algorithm 1 and 2 in the k/R domain), LDS-staged.
 // ---------------------------------------------------------------------------
 struct KconvArgs {
@@ -55,16 +89,20 @@ struct KconvArgs {
 };
 hipError_t kconv_launch(const KconvArgs& a, hipStream_t s);
 
-// Fragment pair transform: M[Q][I][pair_off_f + p*nf + q] =
-//   scale * sum_R exp(-2 pi i jQ.jR/m) conj(psi[R][I][col_f + p]) psi[R][I][col_f + q]
+// Fragment pair transform (eq. (20)):
+//   R[Q][pair_off_f + p*nf + q][I] =
+//     scale * sum_R exp(-2 pi i jQ.jR/m) conj(psi[R][col_f + p][I]) psi[R][col_f + q][I]
+// written in format fmt (0 c128, 1 float planes, 2 bf16 hi/lo planes) with
+// rows of pitch ld (>= n_ip, zero padded) and plane stride plane.
 struct PairBlock { int frag; int pair0; int npair; };
 struct PairArgs {
-  const cplx* psi;         // [N_R][n_ip][ncol]
-  cplx* out;               // [N_q][n_ip][ptot]
+  const cplx* psi;         // [N_R][ncol][n_ip]
+  void* out;               // [N_q][ptot][ld] (per plane)
   const PairBlock* blocks; // device
   const int* frag_nf; const int* frag_col; const long long* frag_pair;  // device
-  int nblocks, n_ip, ncol, pb_max;
-  long long ptot;
+  int nblocks, n_ip, ncol, tp, ti, n_itiles;
+  long long ptot, ld, plane;
+  int fmt;
   int m1, m2, m3;
   double scale;
 };
@@ -77,6 +115,9 @@ hipError_t pair_launch(const PairArgs& a, hipStream_t s);
 // ---------------------------------------------------------------------------
 struct GridFftArgs {
   cplx* data;
+  void* split;            // optional split output (fmt 1 / 2) instead of writing data back
+  int fmt;                // 0: in place c128; 1 float planes; 2 bf16 hi/lo planes
+  long long split_ld, split_plane, split_q;   // row pitch, plane stride, q stride
   int n1, n2, n3;
   int m1, m2, m3;
   int q0, nq, n_ip;

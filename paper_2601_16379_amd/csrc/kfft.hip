@@ -101,35 +101,45 @@ __global__ __launch_bounds__(256) void kconv_kernel(KconvArgs a, int etile) {
   }
 }
 
+// One workgroup: a tile of `tp` pairs of one fragment times `ti` consecutive
+// interpolation points; LDS holds [R][tp*ti] so that the output rows (pair,
+// I-range) are written as contiguous runs of I.
 __global__ __launch_bounds__(256) void pair_kernel(PairArgs a) {
   extern __shared__ cplx buf[];
   __shared__ cplx tw[3][MAXM];
   init_twiddles(tw, a.m1, a.m2, a.m3);
   const int nk = a.m1 * a.m2 * a.m3;
-  const int blk = blockIdx.x % a.nblocks;
-  const int I = blockIdx.x / a.nblocks;
+  const int it = blockIdx.x % a.n_itiles;
+  const int blk = blockIdx.x / a.n_itiles;
   const PairBlock pb = a.blocks[blk];
   const int nf = a.frag_nf[pb.frag];
   const int col = a.frag_col[pb.frag];
   const long long poff = a.frag_pair[pb.frag];
-  const int w = a.pb_max;
+  const int w = a.tp * a.ti;
+  const int I0 = it * a.ti;
   for (int idx = threadIdx.x; idx < nk * w; idx += blockDim.x) {
-    const int R = idx / w, j = idx - (idx / w) * w;
+    const int R = idx / w, e = idx - (idx / w) * w;
+    const int j = e / a.ti, i = e - (e / a.ti) * a.ti;
     cplx v = cmk(0.0, 0.0);
-    if (j < pb.npair) {
+    const int I = I0 + i;
+    if (j < pb.npair && I < a.n_ip) {
       const int P = pb.pair0 + j;
       const int p = P / nf, q = P - (P / nf) * nf;
-      const cplx* row = a.psi + ((long long)R * a.n_ip + I) * a.ncol + col;
-      v = cmulc(row[q], row[p]);   // conj(psi_p) psi_q
+      const cplx* base = a.psi + ((long long)R * a.ncol + col) * a.n_ip + I;
+      v = cmulc(base[(long long)q * a.n_ip], base[(long long)p * a.n_ip]);   // conj(psi_p) psi_q
     }
     buf[idx] = v;
   }
   __syncthreads();
   mesh_dft(buf, tw, w, a.m1, a.m2, a.m3, -1);
   for (int idx = threadIdx.x; idx < nk * w; idx += blockDim.x) {
-    const int Q = idx / w, j = idx - (idx / w) * w;
-    if (j < pb.npair)
-      a.out[((long long)Q * a.n_ip + I) * a.ptot + poff + pb.pair0 + j] = cscale(buf[idx], a.scale);
+    const int Q = idx / w, e = idx - (idx / w) * w;
+    const int j = e / a.ti, i = e - (e / a.ti) * a.ti;
+    const int I = I0 + i;
+    if (j < pb.npair && I < a.ld) {
+      const long long off = ((long long)Q * a.ptot + poff + pb.pair0 + j) * a.ld + I;
+      store_fmt(a.out, off, a.plane, a.fmt, cscale(buf[idx], a.scale));
+    }
   }
 }
 
@@ -152,9 +162,9 @@ hipError_t kconv_launch(const KconvArgs& a, hipStream_t s) {
 hipError_t pair_launch(const PairArgs& a, hipStream_t s) {
   const int nk = a.m1 * a.m2 * a.m3;
   if (a.m1 > MAXM || a.m2 > MAXM || a.m3 > MAXM) return hipErrorInvalidValue;
-  const size_t lds = (size_t)nk * a.pb_max * sizeof(cplx);
+  const size_t lds = (size_t)nk * a.tp * a.ti * sizeof(cplx);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
-  const long long blocks = (long long)a.nblocks * a.n_ip;
+  const long long blocks = (long long)a.nblocks * a.n_itiles;
   if (blocks <= 0) return hipSuccess;
   hipLaunchKernelGGL(pair_kernel, dim3((unsigned)blocks), dim3(256), lds, s, a);
   return hipGetLastError();

@@ -37,6 +37,24 @@ __global__ void nonfinite_kernel(const cplx* __restrict__ x, long long n, int* f
   if (bad) atomicOr(flag, 1);
 }
 
+// Wt[q][J][I] = W[q][I][J] in the three operand formats (row pitch ld,
+// zero padding for I >= n).
+__global__ void wt_convert_kernel(const cplx* __restrict__ w, cplx* wt64, float* wt32,
+                                  unsigned short* wt16, int n, int ld, int nq) {
+  const long long total = (long long)nq * n * ld;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const long long qJ = idx / ld;
+    const int I = (int)(idx - qJ * ld);
+    const int J = (int)(qJ % n);
+    const long long q = qJ / n;
+    const cplx v = (I < n) ? w[(q * n + I) * n + J] : cmk(0.0, 0.0);
+    if (wt64) wt64[idx] = v;
+    if (wt32) store_fmt(wt32, idx, total, 1, v);
+    if (wt16) store_fmt(wt16, idx, total, 2, v);
+  }
+}
+
 inline int grid_for(long long n) {
   long long b = (n + 255) / 256;
   return (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
@@ -60,5 +78,12 @@ hipError_t copy_cols_launch(const cplx* in, cplx* out, int nk, int norb, int nf,
 
 hipError_t nonfinite_launch(const cplx* x, long long n, int* flag, hipStream_t s) {
   hipLaunchKernelGGL(nonfinite_kernel, dim3(grid_for(n)), dim3(256), 0, s, x, n, flag);
+  return hipGetLastError();
+}
+
+hipError_t wt_convert_launch(const cplx* w, cplx* wt64, float* wt32, unsigned short* wt16, int n,
+                             int ld, int nq, hipStream_t s) {
+  hipLaunchKernelGGL(wt_convert_kernel, dim3(grid_for((long long)nq * n * ld)), dim3(256), 0, s, w,
+                     wt64, wt32, wt16, n, ld, nq);
   return hipGetLastError();
 }

@@ -27,8 +27,8 @@ REQ_STATES = {0: "QUEUED", 1: "RUNNING", 2: "DONE", 3: "FAILED", 4: "CANCELLED"}
 
 EXPORTS = ["isdf_create", "isdf_fit", "isdf_coulomb_kernel", "isdf_get_metric",
            "isdf_get_kernel", "isdf_get_ivs", "isdf_get_rhs", "isdf_fragment_eri",
-           "isdf_serve_start", "isdf_submit", "isdf_poll", "isdf_cancel", "isdf_serve_stop",
-           "isdf_stats", "isdf_stage_ms", "isdf_plan_bytes", "isdf_storage_model_bytes",
+           "isdf_serve_start", "isdf_submit", "isdf_submit_n", "isdf_poll", "isdf_cancel",
+           "isdf_serve_stop", "isdf_stats", "isdf_stage_ms", "isdf_stage_total", "isdf_stage_reset", "isdf_plan_bytes", "isdf_storage_model_bytes",
            "isdf_destroy", "isdf_last_error", "isdf_version"]
 
 
@@ -54,6 +54,13 @@ def load_library(path=LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError("libisdf_gfx950.so not found at %s; build it with "
                            "`python -m paper_2601_16379_amd.build`" % path)
+    # One HIP runtime per process: PyTorch ships its own libamdhip64.so.7;
+    # importing it first makes the library bind to that same runtime (same
+    # soname) instead of loading a second copy from /opt/rocm.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     P, I32, U32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_int64, ctypes.c_double
     sig = {
@@ -67,6 +74,9 @@ def load_library(path=LIB_PATH):
         "isdf_fragment_eri": (I32, [P, I32, I32, P, P, P, U32]),
         "isdf_serve_start": (I32, [P, I32, I32, I64]),
         "isdf_submit": (I32, [P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
+        "isdf_submit_n": (I32, [P, I32, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
+        "isdf_stage_total": (I32, [P, ctypes.c_char_p, ctypes.POINTER(D), ctypes.POINTER(I64)]),
+        "isdf_stage_reset": (I32, [P]),
         "isdf_poll": (I32, [P, ctypes.c_uint64, ctypes.POINTER(I32), ctypes.POINTER(D)]),
         "isdf_cancel": (I32, [P, ctypes.c_uint64]),
         "isdf_serve_stop": (I32, [P]),
@@ -153,7 +163,7 @@ class Isdf:
                                   self.kmesh.ctypes.data, self.n_orb, optr, iptr, self.n_ip,
                                   flags, self.stream)
         if st != ISDF_OK:
-            raise IsdfError(st, "isdf_create failed")
+            raise IsdfError(st, "isdf_create: " + self.lib.isdf_last_error(None).decode())
         self.h = h
 
     # -- helpers -------------------------------------------------------------
@@ -237,6 +247,21 @@ class Isdf:
         self._check(self.lib.isdf_submit(self.h, ctypes.byref(req), ctypes.byref(t)), "isdf_submit")
         return t.value
 
+    def submit_n(self, coeffs, eris, prec="fp64"):
+        """Submit several fragments at one instant; returns their tickets."""
+        n = len(coeffs)
+        reqs = (Request * n)()
+        for i, (c, e) in enumerate(zip(coeffs, eris)):
+            cp, cdev = _ptr(c)
+            ep, edev = _ptr(e)
+            if cdev != edev:
+                raise ValueError("C and eri must both be host or both device")
+            reqs[i] = Request(int(c.shape[2]), cp, ep, PRECISIONS.get(prec, prec),
+                              ISDF_FRAG_DEVICE if cdev else 0)
+        t = (ctypes.c_uint64 * n)()
+        self._check(self.lib.isdf_submit_n(self.h, n, reqs, t), "isdf_submit_n")
+        return list(t)
+
     def poll(self, ticket):
         st = ctypes.c_int32()
         lat = ctypes.c_double()
@@ -259,6 +284,16 @@ class Isdf:
 
     def stage_ms(self, name):
         return float(self.lib.isdf_stage_ms(self.h, name.encode()))
+
+    def stage_total(self, name):
+        ms = ctypes.c_double()
+        cnt = ctypes.c_int64()
+        self._check(self.lib.isdf_stage_total(self.h, name.encode(), ctypes.byref(ms),
+                                              ctypes.byref(cnt)), "isdf_stage_total")
+        return ms.value, cnt.value
+
+    def stage_reset(self):
+        self._check(self.lib.isdf_stage_reset(self.h), "isdf_stage_reset")
 
     def last_error(self):
         return self.lib.isdf_last_error(self.h).decode()
