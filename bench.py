@@ -55,8 +55,10 @@ def stage_work(stage, cfg, nfs, prec):
         return "mfma", 8.0 * nk * nip * nip * ng / 2 / 1e12, "TFLOP", pk
     if stage == "grid_fft":   # two read+write passes over eta (c128)
         return "hbm", 4.0 * nk * nip * ng * 16 / 1e9, "GB", PEAK["hbm"]
-    if stage == "rhs":        # T^k_I(r) written + read, eta written once (c128)
-        return "hbm", 3.0 * nk * nip * ng * 16 / 1e9, "GB", PEAK["hbm"]
+    if stage == "rhs_t":      # T^k_I(r) = X^k conj(phi^k): written once (c128)
+        return "hbm", 1.0 * nk * nip * ng * 16 / 1e9, "GB", PEAK["hbm"]
+    if stage == "rhs_kconv":  # T^k_I(r) read, eta written once (c128)
+        return "hbm", 2.0 * nk * nip * ng * 16 / 1e9, "GB", PEAK["hbm"]
     if stage == "metric_kconv":
         return "hbm", 2.0 * nk * nip * nip * 16 / 1e9, "GB", PEAK["hbm"]
     if stage == "frag_pair":  # write R^q once (c128)
@@ -72,7 +74,7 @@ def stage_work(stage, cfg, nfs, prec):
     return None
 
 
-STAGES = ["metric_t", "metric_kconv", "rhs", "chol", "grid_fft", "v_gemm", "w_solve",
+STAGES = ["metric_t", "metric_kconv", "rhs_t", "rhs_kconv", "chol", "grid_fft", "v_gemm", "w_solve",
           "frag_t", "frag_pair", "frag_u", "frag_eri"]
 
 

@@ -18,8 +18,8 @@ constexpr int CT = 1024;   // threads of the factorisation workgroup
 
 __global__ __launch_bounds__(CT) void chol_kernel(const cplx* __restrict__ pi, cplx* work, cplx* lt,
                                                   int* perm, int* rank, int n, double rtol,
-                                                  int pivot) {
-  const int q = blockIdx.x;
+                                                  int pivot, const int* qlist) {
+  const int q = qlist ? qlist[blockIdx.x] : blockIdx.x;
   const long long nn = (long long)n * n;
   const cplx* P = pi + q * nn;
   cplx* A = work + q * nn;
@@ -193,6 +193,201 @@ __global__ __launch_bounds__(256) void wsolve_kernel(const cplx* __restrict__ v,
   }
 }
 
+// Columns of Y = L^{-1} (lower triangular, the leading r x r block of the
+// factor), stored transposed: yt[c][i] = Y[i][c] (zero for i < c).  Column
+// oriented forward substitution of the identity, starting at row c.
+__global__ __launch_bounds__(256) void linv_kernel(const cplx* __restrict__ lt, const int* __restrict__ rank,
+                                                   cplx* yt, int n, int cb) {
+  extern __shared__ cplx B[];   // [r][cb]
+  const int nblk = (n + cb - 1) / cb;
+  const int q = blockIdx.x / nblk;
+  const int c0 = (blockIdx.x % nblk) * cb;
+  const int r = rank[q];
+  if (c0 >= r) return;
+  const int nc = (r - c0) < cb ? (r - c0) : cb;
+  const long long nn = (long long)n * n;
+  const cplx* L = lt + q * nn;
+  cplx* Y = yt + q * nn;
+  for (int idx = threadIdx.x; idx < r * cb; idx += blockDim.x) {
+    const int i = idx / cb, c = idx - (idx / cb) * cb;
+    B[idx] = cmk((c < nc && i == c0 + c) ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  for (int j = c0; j < r; ++j) {
+    const double djj = L[(long long)j * n + j].x;
+    if (threadIdx.x < cb) B[j * cb + threadIdx.x] = cscale(B[j * cb + threadIdx.x], 1.0 / djj);
+    __syncthreads();
+    const int rows = r - j - 1;
+    for (int idx = threadIdx.x; idx < rows * cb; idx += blockDim.x) {
+      const int i = j + 1 + idx / cb, c = idx - (idx / cb) * cb;
+      const cplx lij = L[(long long)j * n + i];
+      const cplx yj = B[j * cb + c];
+      cplx b = B[i * cb + c];
+      b.x -= lij.x * yj.x - lij.y * yj.y;
+      b.y -= lij.x * yj.y + lij.y * yj.x;
+      B[i * cb + c] = b;
+    }
+    __syncthreads();
+  }
+  for (int idx = threadIdx.x; idx < r * cb; idx += blockDim.x) {
+    const int i = idx / cb, c = idx - (idx / cb) * cb;
+    if (c < nc) Y[(long long)(c0 + c) * n + i] = B[idx];
+  }
+}
+
+// out[q][i][j] = in[q][pm[i]][pm[j]] for i, j < rank (dir 0, gather), or
+// out[q][pm[i]][pm[j]] = in[q][i][j] with zeros outside the rank (dir 1).
+__global__ void permute_kernel(const cplx* __restrict__ in, cplx* out, const int* __restrict__ perm,
+                               const int* __restrict__ rank, int n, int nq, int dir) {
+  const long long nn = (long long)n * n;
+  const long long total = nq * nn;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const int q = (int)(idx / nn);
+    const long long e = idx - q * nn;
+    const int i = (int)(e / n), j = (int)(e - (e / n) * n);
+    const int r = rank[q];
+    const int* pm = perm + (long long)q * n;
+    if (dir == 0) {
+      if (i < r && j < r) out[idx] = in[q * nn + (long long)pm[i] * n + pm[j]];
+    } else {
+      // idx enumerates destination rows/cols in permuted order
+      const cplx v = (i < r && j < r) ? in[idx] : cmk(0.0, 0.0);
+      out[q * nn + (long long)pm[i] * n + pm[j]] = v;
+    }
+  }
+}
+
+// ---- blocked, unpivoted factorisation (batched over q) ----
+__global__ void bchol_setup_kernel(const cplx* __restrict__ pi, cplx* a, int* perm, int* rank,
+                                   double* dmax, int* flag, int n, int nq) {
+  const long long nn = (long long)n * n;
+  const int q = blockIdx.y;
+  const cplx* P = pi + q * nn;
+  cplx* A = a + q * nn;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < nn;
+       idx += (long long)gridDim.x * blockDim.x)
+    A[idx] = P[idx];
+  if (blockIdx.x == 0) {
+    __shared__ double red[256];
+    double m = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      m = fmax(m, P[(long long)i * n + i].x);
+      perm[(long long)q * n + i] = i;
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+      if (threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      dmax[q] = red[0];
+      rank[q] = n;
+      flag[q] = 0;
+    }
+  }
+}
+
+// Unblocked Cholesky of the diagonal block A[jb:jb+nb, jb:jb+nb] in LDS.
+__global__ __launch_bounds__(256) void bchol_diag_kernel(cplx* a, cplx* lt, const double* dmax, int* flag,
+                                                         int n, int jb, double rtol) {
+  constexpr int NB = CHOL_NB;
+  __shared__ cplx D[NB][NB + 1];
+  __shared__ int s_bad;
+  const int q = blockIdx.x;
+  if (flag[q]) return;
+  const long long nn = (long long)n * n;
+  cplx* A = a + q * nn;
+  cplx* L = lt + q * nn;
+  const int nb = (n - jb) < NB ? (n - jb) : NB;
+  for (int idx = threadIdx.x; idx < nb * nb; idx += blockDim.x) {
+    const int i = idx / nb, j = idx - (idx / nb) * nb;
+    D[i][j] = A[(long long)(jb + i) * n + jb + j];
+  }
+  if (threadIdx.x == 0) s_bad = 0;
+  __syncthreads();
+  const double tol = rtol * dmax[q];
+  for (int j = 0; j < nb; ++j) {
+    const double djj = D[j][j].x;
+    if (!(djj > tol) || !(djj > 0.0)) {   // uniform: every thread reads the same value
+      if (threadIdx.x == 0) s_bad = 1;
+      break;
+    }
+    const double d = sqrt(djj);
+    __syncthreads();
+    for (int i = j + threadIdx.x; i < nb; i += blockDim.x) D[i][j] = (i == j) ? cmk(d, 0.0) : cscale(D[i][j], 1.0 / d);
+    __syncthreads();
+    const int w = nb - j - 1;
+    for (int idx = threadIdx.x; idx < w * w; idx += blockDim.x) {
+      const int i = j + 1 + idx / w, c = j + 1 + idx - (idx / w) * w;
+      if (c > i) continue;
+      const cplx li = D[i][j], lc = D[c][j];
+      D[i][c].x -= li.x * lc.x + li.y * lc.y;
+      D[i][c].y -= li.y * lc.x - li.x * lc.y;
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  if (s_bad) {
+    if (threadIdx.x == 0) flag[q] = 1;
+    return;
+  }
+  for (int idx = threadIdx.x; idx < nb * nb; idx += blockDim.x) {
+    const int i = idx / nb, j = idx - (idx / nb) * nb;
+    if (j > i) continue;
+    A[(long long)(jb + i) * n + jb + j] = D[i][j];
+    L[(long long)(jb + j) * n + jb + i] = D[i][j];
+  }
+}
+
+// L21 = A21 L11^{-H}: row i solves x L11^H = a, x_c = (a_c - sum_{d<c} x_d conj(L11[c][d])) / L11[c][c].
+__global__ __launch_bounds__(64) void bchol_panel_kernel(cplx* a, cplx* lt, const int* flag, int n, int jb) {
+  constexpr int NB = CHOL_NB;
+  __shared__ cplx L11[NB][NB + 1];
+  __shared__ cplx X[64][NB + 1];
+  const int q = blockIdx.y;
+  if (flag[q]) return;
+  const long long nn = (long long)n * n;
+  cplx* A = a + q * nn;
+  cplx* L = lt + q * nn;
+  const int nb = (n - jb) < NB ? (n - jb) : NB;
+  const int r0 = jb + nb + blockIdx.x * 64;
+  if (r0 >= n) return;
+  const int nr = (n - r0) < 64 ? (n - r0) : 64;
+  for (int idx = threadIdx.x; idx < nb * nb; idx += blockDim.x) {
+    const int i = idx / nb, j = idx - (idx / nb) * nb;
+    L11[i][j] = A[(long long)(jb + i) * n + jb + j];
+  }
+  for (int idx = threadIdx.x; idx < nr * nb; idx += blockDim.x) {
+    const int i = idx / nb, j = idx - (idx / nb) * nb;
+    X[i][j] = A[(long long)(r0 + i) * n + jb + j];
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < nr) {
+    for (int c = 0; c < nb; ++c) {
+      cplx acc = X[t][c];
+      for (int d = 0; d < c; ++d) {
+        const cplx x = X[t][d], l = L11[c][d];
+        // acc -= x * conj(l)
+        acc.x -= x.x * l.x + x.y * l.y;
+        acc.y -= x.y * l.x - x.x * l.y;
+      }
+      X[t][c] = cscale(acc, 1.0 / L11[c][c].x);
+    }
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < nr * nb; idx += blockDim.x) {
+    const int i = idx / nb, j = idx - (idx / nb) * nb;
+    A[(long long)(r0 + i) * n + jb + j] = X[i][j];
+  }
+  for (int idx = threadIdx.x; idx < nr * nb; idx += blockDim.x) {
+    const int j = idx / nr, i = idx - (idx / nr) * nr;   // coalesced along i for lt rows
+    L[(long long)(jb + j) * n + r0 + i] = X[i][j];
+  }
+}
+
 __global__ void zero_kernel(cplx* x, long long n) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
@@ -202,9 +397,10 @@ __global__ void zero_kernel(cplx* x, long long n) {
 }  // namespace
 
 hipError_t chol_launch(const cplx* pi, cplx* work, cplx* lt, int* perm, int* rank, int n, int nq,
-                       double rtol, int pivot, hipStream_t s) {
+                       double rtol, int pivot, hipStream_t s, const int* qlist) {
   if (nq <= 0) return hipSuccess;
-  hipLaunchKernelGGL(chol_kernel, dim3(nq), dim3(CT), 0, s, pi, work, lt, perm, rank, n, rtol, pivot);
+  hipLaunchKernelGGL(chol_kernel, dim3(nq), dim3(CT), 0, s, pi, work, lt, perm, rank, n, rtol, pivot,
+                     qlist);
   return hipGetLastError();
 }
 
@@ -222,5 +418,50 @@ hipError_t wsolve_launch(const cplx* v, cplx* z, cplx* w, const cplx* lt, const 
   const long long tot = (long long)nq * n * n;
   hipLaunchKernelGGL(zero_kernel, dim3(1024), dim3(256), 0, s, w, tot);
   hipLaunchKernelGGL(wsolve_kernel, dim3(nq * nblk), dim3(256), lds, s, v, z, w, lt, perm, rank, n, cb, 2);
+  return hipGetLastError();
+}
+
+hipError_t linv_launch(const cplx* lt, const int* rank, cplx* yt, int n, int nq, hipStream_t s) {
+  if (nq <= 0) return hipSuccess;
+  int cb = 16;
+  while (cb > 4 && (size_t)n * cb * sizeof(cplx) > 128 * 1024) cb >>= 1;
+  const size_t lds = (size_t)n * cb * sizeof(cplx);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  const int nblk = (n + cb - 1) / cb;
+  hipLaunchKernelGGL(linv_kernel, dim3(nq * nblk), dim3(256), lds, s, lt, rank, yt, n, cb);
+  return hipGetLastError();
+}
+
+hipError_t permute_launch(const cplx* in, cplx* out, const int* perm, const int* rank, int n, int nq,
+                          int dir, hipStream_t s) {
+  const long long total = (long long)nq * n * n;
+  long long b = (total + 255) / 256;
+  if (b > 8192) b = 8192;
+  if (b < 1) b = 1;
+  hipLaunchKernelGGL(permute_kernel, dim3((unsigned)b), dim3(256), 0, s, in, out, perm, rank, n, nq, dir);
+  return hipGetLastError();
+}
+
+hipError_t bchol_setup_launch(const cplx* pi, cplx* a, int* perm, int* rank, double* dmax, int* flag,
+                              int n, int nq, hipStream_t s) {
+  const long long nn = (long long)n * n;
+  long long bx = (nn + 255) / 256;
+  if (bx > 256) bx = 256;
+  hipLaunchKernelGGL(bchol_setup_kernel, dim3((unsigned)bx, nq), dim3(256), 0, s, pi, a, perm, rank, dmax,
+                     flag, n, nq);
+  return hipGetLastError();
+}
+
+hipError_t bchol_diag_launch(cplx* a, cplx* lt, const double* dmax, int* flag, int n, int nq, int jb,
+                             double rtol, hipStream_t s) {
+  hipLaunchKernelGGL(bchol_diag_kernel, dim3(nq), dim3(256), 0, s, a, lt, dmax, flag, n, jb, rtol);
+  return hipGetLastError();
+}
+
+hipError_t bchol_panel_launch(cplx* a, cplx* lt, const int* flag, int n, int nq, int jb, hipStream_t s) {
+  const int nb = (n - jb) < CHOL_NB ? (n - jb) : CHOL_NB;
+  const int rows = n - jb - nb;
+  if (rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(bchol_panel_kernel, dim3((rows + 63) / 64, nq), dim3(64), 0, s, a, lt, flag, n, jb);
   return hipGetLastError();
 }

@@ -131,7 +131,7 @@ __device__ inline void store_tile(typename NtCfg<P>::T* s, const u4 (&r)[4]) {
 }
 
 template <int P, bool A_CONJ, bool B_CONJ>
-__global__ __launch_bounds__(256) void zgemm_nt_kernel(const NtDesc* __restrict__ descs, int ndesc,
+__global__ __launch_bounds__(256, 2) void zgemm_nt_kernel(const NtDesc* __restrict__ descs, int ndesc,
                                                        long long total_tiles) {
   typedef typename NtCfg<P>::T T;
   constexpr int BK = NtCfg<P>::BK, PITCH = NtCfg<P>::PITCH, PLANES = NtCfg<P>::PLANES;
@@ -145,7 +145,15 @@ __global__ __launch_bounds__(256) void zgemm_nt_kernel(const NtDesc* __restrict_
   const int lr = lane & 15;     // row / column within a 16x16 MFMA tile
   const int lk = lane >> 4;     // k group of the lane
 
-  for (long long t = blockIdx.x; t < total_tiles; t += gridDim.x) {
+  // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs,
+  // so iteration `it` of workgroup b maps to a tile such that each XCD walks
+  // a contiguous range of the tile list (tiles that share operand rows then
+  // share that XCD's L2).  gridDim.x is a multiple of 8.
+  const long long t8 = (total_tiles + 7) / 8 * 8;
+  const long long per = t8 / 8;
+  for (long long it = blockIdx.x; it < t8; it += gridDim.x) {
+    const long long t = (it % 8) * per + it / 8;
+    if (t >= total_tiles) continue;
     int lo = 0, hi = ndesc - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
@@ -261,38 +269,34 @@ __global__ __launch_bounds__(256) void zgemm_nt_kernel(const NtDesc* __restrict_
           // one 16x16x32 MFMA per plane pair; lane k-set 8*lk .. 8*lk+7
           const unsigned short* a = (const unsigned short*)sA;
           const unsigned short* bb = (const unsigned short*)sB;
-          bf8 a_rh[2], a_rl[2], a_ih[2], a_il[2], a_nih[2], a_nil[2];
+          bf8 a_rh[2], a_rl[2], a_ih[2], a_il[2];
 #pragma unroll
           for (int i = 0; i < 2; ++i) {
             const int ra_ = wm * 32 + i * 16 + lr;
-            const u4 rh = *(const u4*)&a[(0 * 64 + ra_) * PITCH + 8 * lk];
-            const u4 rl = *(const u4*)&a[(1 * 64 + ra_) * PITCH + 8 * lk];
-            const u4 ih = *(const u4*)&a[(2 * 64 + ra_) * PITCH + 8 * lk];
-            const u4 il = *(const u4*)&a[(3 * 64 + ra_) * PITCH + 8 * lk];
-            a_rh[i] = as_bf8(rh);
-            a_rl[i] = as_bf8(rl);
-            a_ih[i] = as_bf8(ih);
-            a_il[i] = as_bf8(il);
-            a_nih[i] = as_bf8(neg_bf16x8(ih));
-            a_nil[i] = as_bf8(neg_bf16x8(il));
+            a_rh[i] = as_bf8(*(const u4*)&a[(0 * 64 + ra_) * PITCH + 8 * lk]);
+            a_rl[i] = as_bf8(*(const u4*)&a[(1 * 64 + ra_) * PITCH + 8 * lk]);
+            a_ih[i] = as_bf8(*(const u4*)&a[(2 * 64 + ra_) * PITCH + 8 * lk]);
+            a_il[i] = as_bf8(*(const u4*)&a[(3 * 64 + ra_) * PITCH + 8 * lk]);
           }
 #pragma unroll
           for (int j = 0; j < 2; ++j) {
             const int rb_ = wn * 32 + j * 16 + lr;
             const bf8 b_rh = as_bf8(*(const u4*)&bb[(0 * 64 + rb_) * PITCH + 8 * lk]);
             const bf8 b_rl = as_bf8(*(const u4*)&bb[(1 * 64 + rb_) * PITCH + 8 * lk]);
-            const bf8 b_ih = as_bf8(*(const u4*)&bb[(2 * 64 + rb_) * PITCH + 8 * lk]);
-            const bf8 b_il = as_bf8(*(const u4*)&bb[(3 * 64 + rb_) * PITCH + 8 * lk]);
+            const u4 bih = *(const u4*)&bb[(2 * 64 + rb_) * PITCH + 8 * lk];
+            const u4 bil = *(const u4*)&bb[(3 * 64 + rb_) * PITCH + 8 * lk];
+            const bf8 b_ih = as_bf8(bih), b_il = as_bf8(bil);
+            const bf8 b_nih = as_bf8(neg_bf16x8(bih)), b_nil = as_bf8(neg_bf16x8(bil));
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
               f4 cr = c_re[i][j], ci = c_im[i][j];
-              // small terms first: lo*hi and hi*lo, then hi*hi
+              // re = ar*br + ai*(-bi); small terms first (lo*hi, hi*lo), then hi*hi
               cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_rl[i], b_rh, cr, 0, 0, 0);
               cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_rh[i], b_rl, cr, 0, 0, 0);
-              cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_nil[i], b_ih, cr, 0, 0, 0);
-              cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_nih[i], b_il, cr, 0, 0, 0);
+              cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_il[i], b_nih, cr, 0, 0, 0);
+              cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_ih[i], b_nil, cr, 0, 0, 0);
               cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_rh[i], b_rh, cr, 0, 0, 0);
-              cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_nih[i], b_ih, cr, 0, 0, 0);
+              cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_ih[i], b_nih, cr, 0, 0, 0);
               ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_rl[i], b_ih, ci, 0, 0, 0);
               ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_rh[i], b_il, ci, 0, 0, 0);
               ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_il[i], b_rh, ci, 0, 0, 0);
@@ -321,7 +325,7 @@ __global__ __launch_bounds__(256) void zgemm_nt_kernel(const NtDesc* __restrict_
     }
 
     // ---- epilogue ----
-    const bool mirror = d.herm && (tm != tn);
+    const bool mirror = (d.herm == 1) && (tm != tn);
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -368,6 +372,7 @@ __global__ __launch_bounds__(256) void zgemm_nt_kernel(const NtDesc* __restrict_
           } else {
             const long long o = (long long)m * d.ldc + n;
             if (d.epi == 1) val = cadd(Cb[o], val);
+            if (d.epi == 4) val = csub(Cb[o], val);
             Cb[o] = val;
             if (mirror) {
               const long long o2 = (long long)n * d.ldc + m;
@@ -412,7 +417,9 @@ long long nt_plan(NtDesc* d, int n) {
 hipError_t nt_launch(int prec, int conj, const NtDesc* descs_dev, int ndesc, long long total,
                      int max_blocks, hipStream_t s) {
   if (total <= 0) return hipSuccess;
-  const int blocks = (int)(total < max_blocks ? total : max_blocks);
+  const long long t8 = (total + 7) / 8 * 8;
+  max_blocks = max_blocks / 8 * 8;
+  const int blocks = (int)(t8 < max_blocks ? t8 : max_blocks);
   if (prec == 0) return launch_nt<0>(conj, descs_dev, ndesc, total, blocks, s);
   if (prec == 1) return launch_nt<1>(conj, descs_dev, ndesc, total, blocks, s);
   return launch_nt<2>(conj, descs_dev, ndesc, total, blocks, s);

@@ -163,9 +163,181 @@ __global__ __launch_bounds__(256) void col_kernel(GridFftArgs a) {
   }
 }
 
+// ---- compile-time-size variants (cubic grids): every index division is by a
+// constant, and the radix loops unroll ----
+template <int N> constexpr int fac_a() {
+  int na = 1;
+  for (int f = 2; f * f <= N; ++f)
+    if (N % f == 0) na = f;
+  return na;
+}
+
+// Same transform as fft_lines with the line geometry fixed at compile time:
+// element j of line l at buf[(l / L1) * S1 + (l % L1) * S2 + j * ES].
+template <int N, int L1, int S1, int S2, int ES>
+__device__ void fft_lines_c(cplx* buf, cplx* tmp, const cplx* tw, int nlines) {
+  constexpr int NA = fac_a<N>(), NB = N / NA;
+  const int total = nlines * N;
+  for (int o = threadIdx.x; o < total; o += blockDim.x) {
+    const int l = o / N, r = o % N;
+    const int base = (l / L1) * S1 + (l % L1) * S2;
+    const int j2 = r / NA, k1 = r % NA;
+    cplx acc = cmk(0.0, 0.0);
+#pragma unroll
+    for (int j1 = 0; j1 < NA; ++j1) cfma(acc, buf[base + (NB * j1 + j2) * ES], tw[(j1 * k1 * NB) % N]);
+    tmp[base + r * ES] = cmul(acc, tw[(j2 * k1) % N]);
+  }
+  __syncthreads();
+  for (int o = threadIdx.x; o < total; o += blockDim.x) {
+    const int l = o / N, r = o % N;
+    const int base = (l / L1) * S1 + (l % L1) * S2;
+    const int k1 = r % NA, k2 = r / NA;
+    cplx acc = cmk(0.0, 0.0);
+#pragma unroll
+    for (int j2 = 0; j2 < NB; ++j2) cfma(acc, tmp[base + (j2 * NA + k1) * ES], tw[(j2 * k2 * NA) % N]);
+    buf[base + r * ES] = acc;
+  }
+  __syncthreads();
+}
+
+template <int N>
+__global__ __launch_bounds__(256) void slab_kernel_c(GridFftArgs a, int S) {
+  constexpr int N2 = N * N;
+  extern __shared__ cplx sm[];
+  cplx* buf = sm;
+  cplx* tmp = sm + S * N2;
+  cplx* tw = tmp + S * N2;
+  for (int t = threadIdx.x; t < N; t += blockDim.x) tw[t] = cexpipi(-2.0 * t / N);
+  const long long nslab = (long long)a.nq * a.n_ip * N;
+  const long long s0 = (long long)blockIdx.x * S;
+  const int ns = (int)((nslab - s0) < S ? (nslab - s0) : S);
+  for (int idx = threadIdx.x; idx < ns * N2; idx += blockDim.x) {
+    const int s = idx / N2, p = idx % N2;
+    const long long slab = s0 + s;
+    const int i1 = (int)(slab % N);
+    const long long qI = slab / N;
+    const int I = (int)(qI % a.n_ip);
+    const int qi = (int)(qI / a.n_ip);
+    double qf[3];
+    q_frac(a, a.q0 + qi, qf);
+    const int i2 = p / N, i3 = p % N;
+    const double ph = (qf[0] * i1 + qf[1] * i2 + qf[2] * i3) / N;
+    const cplx v = a.data[(long long)qi * a.q_stride + ((long long)I * N + i1) * N2 + p];
+    buf[idx] = cmul(v, cexpipi(-2.0 * ph));
+  }
+  __syncthreads();
+  fft_lines_c<N, 1, N, 0, 1>(buf, tmp, tw, ns * N);    // along i3
+  fft_lines_c<N, N, N2, 1, N>(buf, tmp, tw, ns * N);   // along i2
+  for (int idx = threadIdx.x; idx < ns * N2; idx += blockDim.x) {
+    const int s = idx / N2, p = idx % N2;
+    const long long slab = s0 + s;
+    const int i1 = (int)(slab % N);
+    const long long qI = slab / N;
+    const int I = (int)(qI % a.n_ip);
+    const int qi = (int)(qI / a.n_ip);
+    a.data[(long long)qi * a.q_stride + ((long long)I * N + i1) * N2 + p] = buf[idx];
+  }
+}
+
+template <int N>
+__global__ __launch_bounds__(256) void col_kernel_c(GridFftArgs a) {
+  constexpr int N2 = N * N;
+  constexpr int NCB = (N2 + COLS - 1) / COLS;
+  extern __shared__ cplx sm[];
+  cplx* buf = sm;
+  cplx* tmp = sm + N * COLS;
+  cplx* tw = tmp + N * COLS;
+  for (int t = threadIdx.x; t < N; t += blockDim.x) tw[t] = cexpipi(-2.0 * t / N);
+  const int cb = blockIdx.x % NCB;
+  const long long qI = blockIdx.x / NCB;
+  const int I = (int)(qI % a.n_ip);
+  const int qi = (int)(qI / a.n_ip);
+  const int c0 = cb * COLS;
+  const int nc = (N2 - c0) < COLS ? (N2 - c0) : COLS;
+  cplx* base = a.data + (long long)qi * a.q_stride + (long long)I * N * N2;
+  for (int idx = threadIdx.x; idx < N * COLS; idx += blockDim.x) {
+    const int i1 = idx / COLS, c = idx % COLS;
+    buf[idx] = (c < nc) ? base[(long long)i1 * N2 + c0 + c] : cmk(0.0, 0.0);
+  }
+  __syncthreads();
+  fft_lines_c<N, 1, 1, 0, COLS>(buf, tmp, tw, COLS);   // along i1
+  double qf[3];
+  q_frac(a, a.q0 + qi, qf);
+  const double coef = sqrt(4.0 * M_PI * a.volume) / ((double)N * N2);
+  for (int idx = threadIdx.x; idx < N * COLS; idx += blockDim.x) {
+    const int i1 = idx / COLS, c = idx % COLS;
+    if (c >= nc) continue;
+    const int col = c0 + c;
+    const double g1 = wrap_int(i1, N) + qf[0];
+    const double g2 = wrap_int(col / N, N) + qf[1];
+    const double g3 = wrap_int(col % N, N) + qf[2];
+    const double kx = g1 * a.recip[0] + g2 * a.recip[3] + g3 * a.recip[6];
+    const double ky = g1 * a.recip[1] + g2 * a.recip[4] + g3 * a.recip[7];
+    const double kz = g1 * a.recip[2] + g2 * a.recip[5] + g3 * a.recip[8];
+    const double k2 = kx * kx + ky * ky + kz * kz;
+    const double f = (k2 > 1e-20) ? coef / sqrt(k2) : 0.0;
+    const cplx v = cscale(buf[idx], f);
+    if (a.fmt == 0) {
+      base[(long long)i1 * N2 + col] = v;
+    } else {
+      const long long off = (long long)qi * a.split_q + (long long)I * a.split_ld + (long long)i1 * N2 + col;
+      store_fmt(a.split, off, a.split_plane, a.fmt, v);
+    }
+  }
+  if (a.fmt != 0 && cb == NCB - 1) {
+    const long long ng = (long long)N * N2;
+    for (long long g = ng + threadIdx.x; g < a.split_ld; g += blockDim.x)
+      store_fmt(a.split, (long long)qi * a.split_q + (long long)I * a.split_ld + g, a.split_plane, a.fmt,
+                cmk(0.0, 0.0));
+  }
+}
+
+template <int N>
+hipError_t launch_cubic(const GridFftArgs& a, hipStream_t s) {
+  constexpr int N2 = N * N;
+  int S = 2048 / N2;
+  if (S < 1) S = 1;
+  size_t ldsA = (2 * (size_t)S * N2 + N) * sizeof(cplx);
+  while (ldsA > 150 * 1024 && S > 1) {
+    --S;
+    ldsA = (2 * (size_t)S * N2 + N) * sizeof(cplx);
+  }
+  if (ldsA > 160 * 1024) return hipErrorInvalidValue;
+  const long long nslab = (long long)a.nq * a.n_ip * N;
+  if (nslab <= 0) return hipSuccess;
+  hipLaunchKernelGGL(slab_kernel_c<N>, dim3((unsigned)((nslab + S - 1) / S)), dim3(256), ldsA, s, a, S);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const size_t ldsB = (2 * (size_t)N * COLS + N) * sizeof(cplx);
+  if (ldsB > 160 * 1024) return hipErrorInvalidValue;
+  const long long ncb = (N2 + COLS - 1) / COLS;
+  hipLaunchKernelGGL(col_kernel_c<N>, dim3((unsigned)(ncb * a.nq * a.n_ip)), dim3(256), ldsB, s, a);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t gridfft_launch(const GridFftArgs& a, hipStream_t s) {
+  if (a.n1 == a.n2 && a.n2 == a.n3) {
+    switch (a.n1) {
+      case 6: return launch_cubic<6>(a, s);
+      case 8: return launch_cubic<8>(a, s);
+      case 10: return launch_cubic<10>(a, s);
+      case 12: return launch_cubic<12>(a, s);
+      case 16: return launch_cubic<16>(a, s);
+      case 18: return launch_cubic<18>(a, s);
+      case 20: return launch_cubic<20>(a, s);
+      case 24: return launch_cubic<24>(a, s);
+      case 30: return launch_cubic<30>(a, s);
+      case 32: return launch_cubic<32>(a, s);
+      case 36: return launch_cubic<36>(a, s);
+      case 40: return launch_cubic<40>(a, s);
+      case 48: return launch_cubic<48>(a, s);
+      case 60: return launch_cubic<60>(a, s);
+      case 64: return launch_cubic<64>(a, s);
+      default: break;
+    }
+  }
   const int n23 = a.n2 * a.n3;
   int S = 2048 / n23;
   if (S < 1) S = 1;

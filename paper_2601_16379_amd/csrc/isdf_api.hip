@@ -184,48 +184,57 @@ GemmDesc mkdesc(const cplx* A, long long lda, const cplx* B, long long ldb, cplx
   return d;
 }
 
-// Stage timer: HIP events on the context stream.
+// Stage timer: pairs of HIP events recorded on the stream a stage runs on; a
+// stage may be timed several times per call (e.g. once per grid tile) and the
+// intervals are summed.
 struct StageTimer {
-  std::map<std::string, std::pair<hipEvent_t, hipEvent_t>> ev;
-  std::map<std::string, float> ms;          // last interval
-  std::set<std::string> pending;            // recorded since the last collect
+  struct Slot {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    size_t used = 0;
+  };
+  std::map<std::string, Slot> slots;
+  std::map<std::string, float> ms;          // last call's sum
   void begin(const std::string& n, hipStream_t s) {
-    auto it = ev.find(n);
-    if (it == ev.end()) {
+    Slot& sl = slots[n];
+    if (sl.used == sl.ev.size()) {
       hipEvent_t a, b;
       HIPCHK(hipEventCreate(&a));
       HIPCHK(hipEventCreate(&b));
-      it = ev.emplace(n, std::make_pair(a, b)).first;
+      sl.ev.emplace_back(a, b);
     }
-    HIPCHK(hipEventRecord(it->second.first, s));
+    HIPCHK(hipEventRecord(sl.ev[sl.used].first, s));
   }
   void end(const std::string& n, hipStream_t s) {
-    HIPCHK(hipEventRecord(ev[n].second, s));
-    pending.insert(n);
+    Slot& sl = slots[n];
+    HIPCHK(hipEventRecord(sl.ev[sl.used].second, s));
+    ++sl.used;
   }
-  // After the stream has drained: read the intervals recorded since the last
+  // After the stream has drained: sum the intervals recorded since the last
   // collect, and add them to totals (ms, count) if given.
   void collect(std::map<std::string, std::pair<double, long long>>* totals = nullptr) {
-    for (const std::string& n : pending) {
-      auto& kv = ev[n];
-      float t = -1.f;
-      if (hipEventElapsedTime(&t, kv.first, kv.second) == hipSuccess) {
-        ms[n] = t;
-        if (totals) {
-          (*totals)[n].first += t;
-          (*totals)[n].second += 1;
-        }
-      } else {
-        (void)hipGetLastError();
+    for (auto& kv : slots) {
+      Slot& sl = kv.second;
+      if (sl.used == 0) continue;
+      double sum = 0;
+      for (size_t i = 0; i < sl.used; ++i) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, sl.ev[i].first, sl.ev[i].second) == hipSuccess) sum += t;
+        else (void)hipGetLastError();
       }
+      ms[kv.first] = (float)sum;
+      if (totals) {
+        (*totals)[kv.first].first += sum;
+        (*totals)[kv.first].second += 1;
+      }
+      sl.used = 0;
     }
-    pending.clear();
   }
   ~StageTimer() {
-    for (auto& kv : ev) {
-      (void)hipEventDestroy(kv.second.first);
-      (void)hipEventDestroy(kv.second.second);
-    }
+    for (auto& kv : slots)
+      for (auto& e : kv.second.ev) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+      }
   }
 };
 
@@ -271,10 +280,13 @@ struct isdf_ctx_s {
   double lattice[9], recip[9], volume = 0;
   uint32_t flags = 0;
   hipStream_t stream = nullptr;
+  hipStream_t aux = nullptr;            // second stream: the factorisation overlaps the RHS
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int device = 0;
   // resident device data
-  DevBuf phi, ip, xt, pi, eta, lt, w, work1, work2, perm, rank, rchunk, flag;
+  DevBuf phi, ip, xt, pi, eta, lt, w, work1, work2, work3, perm, rank, rchunk, flag;
   DevBuf wt64, wt32, wt16, eta_split;   // W transposed in the three GEMM formats; split eta~
+  DevBuf dmax, cflag;                   // factorisation: largest diagonal, breakdown flags
   long long ld_ip = 0, ld_g = 0;        // row pitches of split operands (multiples of 8)
   bool fitted = false, kernel_ready = false, eta_valid = false;
   std::vector<int> rank_h;
@@ -389,10 +401,14 @@ void do_fit(isdf_ctx c) {
     HIPCHK(kconv_launch(a, s));
   }
   c->timer.end("metric_kconv", s);
+  // FP64 pivoted Cholesky of every Pi^q (solve of eq. (3)) on the second
+  // stream, overlapping the RHS below (it needs only Pi)
+  HIPCHK(hipEventRecord(c->ev_fork, s));
+  HIPCHK(hipStreamWaitEvent(c->aux, c->ev_fork, 0));
   // eta^q_I(r), r-tiled: T^k_I(r) = sum_mu X^k_{I mu} conj(phi^k_mu(r)), then the
   // same k convolution (eq. (5), Algorithm 1 with Y = phi)
-  c->timer.begin("rhs", s);
   for (long long r0 = 0; r0 < ng; r0 += c->rc) {
+    c->timer.begin("rhs_t", s);
     const int rcur = (int)std::min<long long>(c->rc, ng - r0);
     std::vector<GemmDesc> d(1);
     d[0] = mkdesc(c->xt.as<cplx>(), nip, c->phi.as<cplx>() + r0, ng, c->rchunk.as<cplx>(), rcur,
@@ -402,6 +418,8 @@ void do_fit(isdf_ctx c) {
     d[0].sB_bat = (long long)norb * ng;
     d[0].sC_bat = (long long)nip * rcur;
     run_gemm(c->arena, 0, GEMM_A_KM | GEMM_B_KN | GEMM_B_CONJ, d, s);
+    c->timer.end("rhs_t", s);
+    c->timer.begin("rhs_kconv", s);
     KconvArgs a;
     memset(&a, 0, sizeof(a));
     a.in = c->rchunk.as<cplx>();
@@ -417,13 +435,50 @@ void do_fit(isdf_ctx c) {
     a.mode = 0;
     a.scale = 1.0 / nk;
     HIPCHK(kconv_launch(a, s));
+    c->timer.end("rhs_kconv", s);
   }
-  c->timer.end("rhs", s);
-  // FP64 pivoted Cholesky of every Pi^q (solve of eq. (3))
-  c->timer.begin("chol", s);
-  HIPCHK(chol_launch(c->pi.as<cplx>(), c->work2.as<cplx>(), c->lt.as<cplx>(), c->perm.as<int>(),
-                     c->rank.as<int>(), nip, nk, 1e-13, (c->flags & ISDF_NO_PIVOT) ? 0 : 1, s));
-  c->timer.end("chol", s);
+  c->timer.begin("chol", c->aux);
+  {
+    // blocked right-looking factorisation of all Pi^q at once: 64-wide
+    // diagonal blocks in LDS, panel solves, FP64 MFMA trailing updates
+    cplx* A = c->work2.as<cplx>();
+    const double rtol = 1e-13;
+    HIPCHK(bchol_setup_launch(c->pi.as<cplx>(), A, c->perm.as<int>(), c->rank.as<int>(),
+                              c->dmax.as<double>(), c->cflag.as<int>(), nip, nk, c->aux));
+    for (int jb = 0; jb < nip; jb += CHOL_NB) {
+      HIPCHK(bchol_diag_launch(A, c->lt.as<cplx>(), c->dmax.as<double>(), c->cflag.as<int>(), nip, nk,
+                               jb, rtol, c->aux));
+      HIPCHK(bchol_panel_launch(A, c->lt.as<cplx>(), c->cflag.as<int>(), nip, nk, jb, c->aux));
+      const int rest = nip - jb - CHOL_NB;
+      if (rest > 0) {
+        std::vector<NtDesc> d(1);
+        const cplx* L21 = A + (long long)(jb + CHOL_NB) * nip + jb;
+        d[0] = mknt(L21, nip, L21, nip, A + (long long)(jb + CHOL_NB) * (nip + 1), nip, rest, rest,
+                    CHOL_NB);
+        d[0].batch = nk;
+        d[0].sA_bat = d[0].sB_bat = d[0].sC_bat = nip2(c);
+        d[0].herm = 2;
+        d[0].epi = 4;
+        run_nt(c->arena, 0, 2, d, c->aux);
+      }
+    }
+    // matrices whose pivots fell below the rank tolerance (singular metrics)
+    // are refactored with diagonal pivoting
+    std::vector<int> fl(nk, 0);
+    HIPCHK(hipMemcpyAsync(fl.data(), c->cflag.p, sizeof(int) * nk, hipMemcpyDeviceToHost, c->aux));
+    HIPCHK(hipStreamSynchronize(c->aux));
+    std::vector<int> qs;
+    for (int q = 0; q < nk; ++q)
+      if (fl[q]) qs.push_back(q);
+    if (!qs.empty()) {
+      int* ql = c->arena.put(qs.data(), qs.size(), c->aux);
+      HIPCHK(chol_launch(c->pi.as<cplx>(), A, c->lt.as<cplx>(), c->perm.as<int>(), c->rank.as<int>(),
+                         nip, (int)qs.size(), rtol, (c->flags & ISDF_NO_PIVOT) ? 0 : 1, c->aux, ql));
+    }
+  }
+  c->timer.end("chol", c->aux);
+  HIPCHK(hipEventRecord(c->ev_join, c->aux));
+  HIPCHK(hipStreamWaitEvent(s, c->ev_join, 0));
   c->rank_h.assign(nk, 0);
   HIPCHK(hipMemcpyAsync(c->rank_h.data(), c->rank.p, sizeof(int) * nk, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
@@ -502,10 +557,35 @@ void do_kernel(isdf_ctx c, int prec) {
     run_nt(c->arena, prec, 2, d, s);
   }
   c->timer.end("v_gemm", s);
-  // W^q = Pi^{q+} V^q Pi^{q+}   (eq. (8)), FP64 triangular solves
+  // W^q = Pi^{q+} V^q Pi^{q+}   (eq. (8)) in FP64 through the pivoted factor
+  // P^T Pi P = L L^H of rank r:  G = L^{-H} L^{-1},  W' = G (P^T V P) G,
+  // W = P W' P^T (zero outside the rank block).  The inverse of L is a
+  // column-parallel forward substitution; the three products are FP64 MFMA.
   c->timer.begin("w_solve", s);
-  HIPCHK(wsolve_launch(c->work1.as<cplx>(), c->work2.as<cplx>(), c->w.as<cplx>(), c->lt.as<cplx>(),
-                       c->perm.as<int>(), c->rank.as<int>(), nip, nk, s));
+  {
+    const long long n2 = nip2(c);
+    HIPCHK(linv_launch(c->lt.as<cplx>(), c->rank.as<int>(), c->work2.as<cplx>(), nip, nk, s));
+    HIPCHK(permute_launch(c->work1.as<cplx>(), c->w.as<cplx>(), c->perm.as<int>(), c->rank.as<int>(),
+                          nip, nk, 0, s));
+    auto prod = [&](const cplx* A, const cplx* B, cplx* C, int conj, int herm) {
+      std::vector<NtDesc> d;
+      for (int q = 0; q < nk; ++q) {
+        const int r = c->rank_h[q];
+        NtDesc g = mknt(A + q * n2, nip, B + q * n2, nip, C + q * n2, nip, r, r, r);
+        g.herm = herm;
+        d.push_back(g);
+      }
+      run_nt(c->arena, 0, conj, d, s);
+    };
+    // G[m][n] = sum_i conj(Yt[m][i]) Yt[n][i]
+    prod(c->work2.as<cplx>(), c->work2.as<cplx>(), c->work3.as<cplx>(), 1, 1);
+    // T1 = G V'  (V' Hermitian: V'[k][n] = conj(V'[n][k]))
+    prod(c->work3.as<cplx>(), c->w.as<cplx>(), c->work1.as<cplx>(), 2, 0);
+    // W' = T1 G  (G Hermitian)
+    prod(c->work1.as<cplx>(), c->work3.as<cplx>(), c->work2.as<cplx>(), 2, 0);
+    HIPCHK(permute_launch(c->work2.as<cplx>(), c->w.as<cplx>(), c->perm.as<int>(), c->rank.as<int>(),
+                          nip, nk, 1, s));
+  }
   c->timer.end("w_solve", s);
   // transposed copies of W in the three operand formats of the fragment GEMMs
   HIPCHK(wt_convert_launch(c->w.as<cplx>(), c->wt64.as<cplx>(), c->wt32.as<float>(),
@@ -643,8 +723,8 @@ void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn
     // tile: ti interpolation points x tp pairs, nk * tp * ti <= 4096 (64 KB)
     int ti = 32;
     while (ti > 1 && (long long)nk * ti > 4096) ti >>= 1;
-    int tp = (int)std::max<long long>(1, 4096 / ((long long)nk * ti));
-    if (tp > 8) tp = 8;
+    int tp = 1;   // power of two (the LDS transform needs tp * ti to be one)
+    while (tp < 8 && (long long)nk * ti * tp * 2 <= 4096) tp *= 2;
     std::vector<PairBlock> blocks;
     for (size_t f = 0; f < fr.size(); ++f) {
       const int np = p.nf[f] * p.nf[f];
@@ -928,6 +1008,7 @@ isdf_status isdf_create(isdf_ctx* out, const double* lattice, const int32_t grid
     c->w.alloc(m2);
     c->work1.alloc(m2);
     c->work2.alloc(m2);
+    c->work3.alloc(m2);
     c->eta.alloc((size_t)nk * n_ip * ng * e);
     c->ld_ip = (n_ip + 7) / 8 * 8;
     c->ld_g = (ng + 7) / 8 * 8;
@@ -938,11 +1019,16 @@ isdf_status isdf_create(isdf_ctx* out, const double* lattice, const int32_t grid
     c->perm.alloc(sizeof(int) * nk * n_ip);
     c->rank.alloc(sizeof(int) * nk);
     c->flag.alloc(sizeof(int));
+    c->dmax.alloc(sizeof(double) * nk);
+    c->cflag.alloc(sizeof(int) * nk);
     const hipMemcpyKind kind = (flags & ISDF_INPUT_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     HIPCHK(hipMemcpyAsync(c->phi.p, orbitals, (size_t)nk * n_orb * ng * e, kind, c->stream));
     HIPCHK(hipMemcpyAsync(c->ip.p, iph.data(), sizeof(int) * n_ip, hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     c->sync_ws.stream = c->stream;
+    HIPCHK(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&c->sync_ws.done, hipEventDisableTiming));
   });
   if (st != ISDF_OK) {
@@ -1185,6 +1271,12 @@ isdf_status isdf_destroy(isdf_ctx ctx) {
   if (!ctx) return ISDF_E_INVALID;
   (void)isdf_serve_stop(ctx);
   (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->aux) {
+    (void)hipStreamSynchronize(ctx->aux);
+    (void)hipStreamDestroy(ctx->aux);
+  }
+  if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+  if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
   delete ctx;
   return ISDF_OK;
 }

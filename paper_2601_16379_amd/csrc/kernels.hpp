@@ -46,7 +46,8 @@ hipError_t gemm_launch(int prec, int layout_flags, const GemmDesc* descs_dev, in
 // plane strides in scalar elements; rows zero-padded to a multiple of 8).
 // epi: 0 store c128, 1 accumulate c128, 2 ERI scatter c128, 3 store in the
 // split format of the precision (plane stride c_plane), zero-filling columns
-// N..ldc-1.
+// N..ldc-1, 4 subtract from c128.  herm: 1 lower tiles mirrored as conj to the
+// upper triangle; 2 lower tiles only, no mirror.
 // ---------------------------------------------------------------------------
 struct NtDesc {
   const void* A;
@@ -131,11 +132,34 @@ hipError_t gridfft_launch(const GridFftArgs& a, hipStream_t s);
 // FP64 pivoted Cholesky of Pi^q (one workgroup per q) and the two-sided
 // solve W = Pi^+ V Pi^+ through the factor.
 // ---------------------------------------------------------------------------
+// qlist: device list of the nq matrices to factor (null = 0..nq-1)
 hipError_t chol_launch(const cplx* pi, cplx* work, cplx* lt, int* perm, int* rank,
-                       int n, int nq, double rtol, int pivot, hipStream_t s);
+                       int n, int nq, double rtol, int pivot, hipStream_t s,
+                       const int* qlist = nullptr);
+// Blocked (unpivoted) Cholesky pieces, batched over nq matrices A[q] (n x n,
+// lower triangle used): setup copies Pi into A, records the largest diagonal,
+// sets perm = identity, rank = n and clears the breakdown flags; diag factors
+// the NB x NB diagonal block at jb in LDS (flagging q when a pivot is not
+// above rtol * max diagonal); panel computes L21 = A21 L11^{-H}.  Both also
+// store the columns of L transposed into lt.  The trailing update is an NT
+// GEMM.
+constexpr int CHOL_NB = 64;
+hipError_t bchol_setup_launch(const cplx* pi, cplx* a, int* perm, int* rank, double* dmax, int* flag,
+                              int n, int nq, hipStream_t s);
+hipError_t bchol_diag_launch(cplx* a, cplx* lt, const double* dmax, int* flag, int n, int nq, int jb,
+                             double rtol, hipStream_t s);
+hipError_t bchol_panel_launch(cplx* a, cplx* lt, const int* flag, int n, int nq, int jb, hipStream_t s);
 // stage 1: Z = Pi~^-1 (P^T V P)   stage 2: W = P (Pi~^-1 Z^H) P^T
 hipError_t wsolve_launch(const cplx* v, cplx* z, cplx* w, const cplx* lt, const int* perm,
                          const int* rank, int n, int nq, hipStream_t s);
+
+// yt[q][c][i] = (L^{-1})[i][c] for the leading rank x rank block (transposed
+// inverse of the factor); zeros for i < c.
+hipError_t linv_launch(const cplx* lt, const int* rank, cplx* yt, int n, int nq, hipStream_t s);
+// dir 0: out[q][i][j] = in[q][perm[i]][perm[j]] (i, j < rank);
+// dir 1: out[q][perm[i]][perm[j]] = in[q][i][j], zero outside the rank block.
+hipError_t permute_launch(const cplx* in, cplx* out, const int* perm, const int* rank, int n, int nq,
+                          int dir, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // misc

@@ -24,65 +24,114 @@ __device__ void init_twiddles(cplx (*tw)[MAXM], int m1, int m2, int m3) {
   }
 }
 
+// Length-M DFT of lines p[j * estride], j < M, for the lines `line` owned by
+// this thread; M is a compile-time constant so the loops unroll and the
+// twiddle indices (j t mod M) are constants; twiddles live in registers.
+template <int M>
+__device__ void axis_dft(cplx* buf, const cplx* twa, int nlines, int eshift, int ax, int m2, int m3,
+                         int sign) {
+  cplx w[M];
+#pragma unroll
+  for (int t = 0; t < M; ++t) {
+    w[t] = twa[t];
+    if (sign < 0) w[t].y = -w[t].y;
+  }
+  const int etile = 1 << eshift;
+  for (int line = threadIdx.x; line < nlines; line += blockDim.x) {
+    const int e = line & (etile - 1);
+    const int rest = line >> eshift;
+    int base, stride;
+    if (ax == 0) { base = rest; stride = m2 * m3; }
+    else if (ax == 1) { base = (rest / m3) * m2 * m3 + (rest % m3); stride = m3; }
+    else { base = rest * M; stride = 1; }
+    const int estride = stride << eshift;
+    cplx* p = buf + (base << eshift) + e;
+    cplx x[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) x[j] = p[j * estride];
+#pragma unroll
+    for (int t = 0; t < M; ++t) {
+      cplx acc = x[0];
+#pragma unroll
+      for (int j = 1; j < M; ++j) cfma(acc, x[j], w[(j * t) % M]);
+      p[t * estride] = acc;
+    }
+  }
+}
+
+// In-place 3-D DFT over the mesh for every element column of buf[k][etile]:
+// buf[k][e] <- sum_j exp(sign * 2 pi i sum_d j_d k_d / m_d) buf[j][e].
+// etile is a power of two; tw[ax][t] = exp(2 pi i t / m_ax).
 __device__ void mesh_dft(cplx* buf, const cplx (*tw)[MAXM], int etile, int m1, int m2, int m3,
                          int sign) {
+  const int eshift = __builtin_ctz(etile);
   const int nk = m1 * m2 * m3;
   const int ms[3] = {m1, m2, m3};
   for (int ax = 0; ax < 3; ++ax) {
     const int m = ms[ax];
     if (m == 1) continue;
-    const int nlines = (nk / m) * etile;
-    for (int line = threadIdx.x; line < nlines; line += blockDim.x) {
-      const int e = line % etile;
-      const int rest = line / etile;
-      int base, stride;
-      if (ax == 0) { base = rest; stride = m2 * m3; }
-      else if (ax == 1) { base = (rest / m3) * m2 * m3 + (rest % m3); stride = m3; }
-      else { base = rest * m3; stride = 1; }
-      cplx x[MAXM];
-#pragma unroll
-      for (int j = 0; j < MAXM; ++j)
-        if (j < m) x[j] = buf[(long long)(base + j * stride) * etile + e];
-      for (int t = 0; t < m; ++t) {
-        cplx acc = cmk(0.0, 0.0);
-#pragma unroll
-        for (int j = 0; j < MAXM; ++j) {
-          if (j < m) {
-            const int jt = (j * t) % m;
-            cplx w = tw[ax][jt];
-            if (sign < 0) w.y = -w.y;
-            cfma(acc, x[j], w);
-          }
-        }
-        buf[(long long)(base + t * stride) * etile + e] = acc;
-      }
+    const int nlines = (nk / m) << eshift;
+    switch (m) {
+#define AXIS_CASE(M) \
+  case M: axis_dft<M>(buf, tw[ax], nlines, eshift, ax, m2, m3, sign); break;
+      AXIS_CASE(2) AXIS_CASE(3) AXIS_CASE(4) AXIS_CASE(5) AXIS_CASE(6) AXIS_CASE(7) AXIS_CASE(8)
+      AXIS_CASE(9) AXIS_CASE(10) AXIS_CASE(11) AXIS_CASE(12) AXIS_CASE(13) AXIS_CASE(14)
+      AXIS_CASE(15) AXIS_CASE(16)
+#undef AXIS_CASE
+      default: break;
     }
     __syncthreads();
   }
 }
 
 __global__ __launch_bounds__(256) void kconv_kernel(KconvArgs a, int etile) {
+  // blockDim.x == 256; etile a power of two
   extern __shared__ cplx buf[];
   __shared__ cplx tw[3][MAXM];
   init_twiddles(tw, a.m1, a.m2, a.m3);
+  const int eshift = __builtin_ctz(etile);
   const int nk = a.m1 * a.m2 * a.m3;
   const long long e0 = (long long)blockIdx.x * etile;
   const long long rem = a.n_elem - e0;
   const int ne = rem < etile ? (int)rem : etile;
-  for (int idx = threadIdx.x; idx < nk * etile; idx += blockDim.x) {
-    const int k = idx / etile, e = idx - (idx / etile) * etile;
-    cplx v = cmk(0.0, 0.0);
-    if (e < ne) {
-      const long long ee = e0 + e;
-      v = a.in[(long long)k * a.in_kstride + (ee / a.in_inner) * a.in_outer + ee % a.in_inner];
+  // element e0 + e maps to in/out offsets base + e when the tile does not cross
+  // a row of the (inner, outer) maps (the host guarantees it when fast != 0)
+  const bool fast = (a.in_inner % etile == 0) && (a.out_inner % etile == 0);
+  const long long in0 = (e0 / a.in_inner) * a.in_outer + e0 % a.in_inner;
+  const long long out0 = (e0 / a.out_inner) * a.out_outer + e0 % a.out_inner;
+  constexpr int UNR = 8;
+  const int total = nk << eshift;
+  for (int b0 = 0; b0 < total; b0 += UNR * 256) {
+    cplx v[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int idx = b0 + u * 256 + threadIdx.x;
+      v[u] = cmk(0.0, 0.0);
+      if (idx < total) {
+        const int k = idx >> eshift, e = idx & (etile - 1);
+        if (e < ne) {
+          long long off;
+          if (fast) {
+            off = in0 + e;
+          } else {
+            const long long ee = e0 + e;
+            off = (ee / a.in_inner) * a.in_outer + ee % a.in_inner;
+          }
+          v[u] = a.in[(long long)k * a.in_kstride + off];
+        }
+      }
     }
-    buf[idx] = v;
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int idx = b0 + u * 256 + threadIdx.x;
+      if (idx < total) buf[idx] = v[u];
+    }
   }
   __syncthreads();
   if (a.mode == 0) {
     // T^R = sum_k exp(+i k.R) T^k ;  Z^R = |T^R|^2 ;  out^q = scale * sum_R exp(+i q.R) Z^R
     mesh_dft(buf, tw, etile, a.m1, a.m2, a.m3, +1);
-    for (int idx = threadIdx.x; idx < nk * etile; idx += blockDim.x) {
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
       cplx v = buf[idx];
       buf[idx] = cmk(v.x * v.x + v.y * v.y, 0.0);
     }
@@ -91,12 +140,17 @@ __global__ __launch_bounds__(256) void kconv_kernel(KconvArgs a, int etile) {
   } else {
     mesh_dft(buf, tw, etile, a.m1, a.m2, a.m3, a.sign);
   }
-  for (int idx = threadIdx.x; idx < nk * etile; idx += blockDim.x) {
-    const int q = idx / etile, e = idx - (idx / etile) * etile;
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    const int q = idx >> eshift, e = idx & (etile - 1);
     if (e < ne) {
-      const long long ee = e0 + e;
-      a.out[(long long)q * a.out_qstride + (ee / a.out_inner) * a.out_outer + ee % a.out_inner] =
-          cscale(buf[idx], a.scale);
+      long long off;
+      if (fast) {
+        off = out0 + e;
+      } else {
+        const long long ee = e0 + e;
+        off = (ee / a.out_inner) * a.out_outer + ee % a.out_inner;
+      }
+      a.out[(long long)q * a.out_qstride + off] = cscale(buf[idx], a.scale);
     }
   }
 }
@@ -109,32 +163,55 @@ __global__ __launch_bounds__(256) void pair_kernel(PairArgs a) {
   __shared__ cplx tw[3][MAXM];
   init_twiddles(tw, a.m1, a.m2, a.m3);
   const int nk = a.m1 * a.m2 * a.m3;
-  const int it = blockIdx.x % a.n_itiles;
-  const int blk = blockIdx.x / a.n_itiles;
+  // consecutive workgroups walk the pair blocks of one interpolation-point
+  // tile, so psi rows of that tile stay in L2 while they are reused
+  const int blk = blockIdx.x % a.nblocks;
+  const int it = blockIdx.x / a.nblocks;
   const PairBlock pb = a.blocks[blk];
   const int nf = a.frag_nf[pb.frag];
   const int col = a.frag_col[pb.frag];
   const long long poff = a.frag_pair[pb.frag];
-  const int w = a.tp * a.ti;
+  const int w = a.tp * a.ti;           // power of two
+  const int wshift = __builtin_ctz(w), tshift = __builtin_ctz(a.ti);
   const int I0 = it * a.ti;
-  for (int idx = threadIdx.x; idx < nk * w; idx += blockDim.x) {
-    const int R = idx / w, e = idx - (idx / w) * w;
-    const int j = e / a.ti, i = e - (e / a.ti) * a.ti;
-    cplx v = cmk(0.0, 0.0);
-    const int I = I0 + i;
-    if (j < pb.npair && I < a.n_ip) {
-      const int P = pb.pair0 + j;
-      const int p = P / nf, q = P - (P / nf) * nf;
-      const cplx* base = a.psi + ((long long)R * a.ncol + col) * a.n_ip + I;
-      v = cmulc(base[(long long)q * a.n_ip], base[(long long)p * a.n_ip]);   // conj(psi_p) psi_q
+  __shared__ int sp[8], sq[8];          // (p, q) of the block's pairs (tp <= 8)
+  if (threadIdx.x < a.tp) {
+    const int P = pb.pair0 + threadIdx.x;
+    sp[threadIdx.x] = P / nf;
+    sq[threadIdx.x] = P - (P / nf) * nf;
+  }
+  __syncthreads();
+  constexpr int UNR = 4;
+  const int total = nk * w;
+  for (int b0 = 0; b0 < total; b0 += UNR * 256) {
+    cplx xp[UNR], xq[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int idx = b0 + u * 256 + threadIdx.x;
+      xp[u] = cmk(0.0, 0.0);
+      xq[u] = cmk(0.0, 0.0);
+      if (idx < total) {
+        const int R = idx >> wshift, e = idx & (w - 1);
+        const int j = e >> tshift, i = e & (a.ti - 1);
+        const int I = I0 + i;
+        if (j < pb.npair && I < a.n_ip) {
+          const cplx* base = a.psi + ((long long)R * a.ncol + col) * a.n_ip + I;
+          xp[u] = base[(long long)sp[j] * a.n_ip];
+          xq[u] = base[(long long)sq[j] * a.n_ip];
+        }
+      }
     }
-    buf[idx] = v;
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int idx = b0 + u * 256 + threadIdx.x;
+      if (idx < total) buf[idx] = cmulc(xq[u], xp[u]);   // conj(psi_p) psi_q
+    }
   }
   __syncthreads();
   mesh_dft(buf, tw, w, a.m1, a.m2, a.m3, -1);
   for (int idx = threadIdx.x; idx < nk * w; idx += blockDim.x) {
-    const int Q = idx / w, e = idx - (idx / w) * w;
-    const int j = e / a.ti, i = e - (e / a.ti) * a.ti;
+    const int Q = idx >> wshift, e = idx & (w - 1);
+    const int j = e >> tshift, i = e & (a.ti - 1);
     const int I = I0 + i;
     if (j < pb.npair && I < a.ld) {
       const long long off = ((long long)Q * a.ptot + poff + pb.pair0 + j) * a.ld + I;
@@ -148,9 +225,8 @@ __global__ __launch_bounds__(256) void pair_kernel(PairArgs a) {
 hipError_t kconv_launch(const KconvArgs& a, hipStream_t s) {
   const int nk = a.m1 * a.m2 * a.m3;
   if (a.m1 > MAXM || a.m2 > MAXM || a.m3 > MAXM) return hipErrorInvalidValue;
-  int etile = 4096 / nk;                // 64 KB of complex128 per block
-  if (etile > 256) etile = 256;
-  if (etile < 1) etile = 1;
+  int etile = 1;                        // largest power of two with nk*etile <= 4096 (64 KB)
+  while (etile < 256 && (long long)nk * etile * 2 <= 4096) etile *= 2;
   const long long blocks = (a.n_elem + etile - 1) / etile;
   if (blocks <= 0) return hipSuccess;
   const size_t lds = (size_t)nk * etile * sizeof(cplx);
