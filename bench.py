@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--no-fp64-ref", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=25.0)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one 1 GiB device copy first (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -71,6 +73,33 @@ def stage_work(stage, cfg, nfs, prec):
         return "mfma", 8.0 * nk * nip * nip * norb / 2 / 1e12, "TFLOP", PEAK["fp64"]
     if stage == "frag_t":
         return "mfma", 8.0 * nk * nip * norb * sum(nfs) / 1e12, "TFLOP", PEAK["fp64"]
+    return None
+
+
+KERNEL_OF_STAGE = {"frag_eri": "zgemm_nt_kernel<{p}, false, true, 3>",
+                   "frag_u": "zgemm_nt_kernel<{p}, false, false, 2>",
+                   "v_gemm": "zgemm_nt_kernel<{p}, false, true, 1>",
+                   "frag_pair": "pair_kernel(PairArgs)"}
+
+
+def counter_traffic(stage, workload, prec):
+    """HBM bytes per launch of a stage's kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE + WRITE_SIZE, scaled by a 1 GiB copy), or
+    None if there is none or a kernel source changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "%s_%s_traffic.json" % (workload, prec))
+    if stage not in KERNEL_OF_STAGE or not os.path.exists(path):
+        return None
+    prof = json.load(open(path))
+    csrc = os.path.join(ROOT, "paper_2601_16379_amd", "csrc")
+    for f, h in prof.get("sources_sha256", {}).items():
+        fp = os.path.join(csrc, f)
+        if not os.path.exists(fp) or hashlib.sha256(open(fp, "rb").read()).hexdigest() != h:
+            return None
+    key = KERNEL_OF_STAGE[stage].format(p={"fp64": 0, "fp32": 1, "bf16x3": 2}[prec])
+    for name, v in prof["kernels"].items():
+        if key in name:
+            return v["fetch_bytes"] + v["write_bytes"]
     return None
 
 
@@ -155,6 +184,13 @@ def main():
     import isdf_inputs as inp
     import paper_2601_16379_amd as pkg
 
+    if args.calib_copy:
+        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+        src.fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     cfg = inp.get_config(args.workload)
     t_gen = time.perf_counter()
     d = inp.make_inputs(cfg)
@@ -230,7 +266,7 @@ def main():
     else:
         roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s"}
     roof["frac"] = achieved / peak
-    roof["traffic"] = None
+    roof["traffic"] = counter_traffic(dom, cfg.name, args.prec)
     roof["kernel"] = dom
     roof["avg_ms"] = avg_ms
 

@@ -49,7 +49,7 @@ def ip_values(orbitals, ip_index):
 def metric_k(x, kmesh):
     """Pi^q_{IJ} = sum_k conj(T^{k+q}_{IJ}) T^k_{IJ}  (eq. (4)), direct k sum."""
     nk = x.shape[0]
-    t = np.einsum("kim,kjm->kij", x, x.conj())                    # T^k_{IJ}
+    t = np.matmul(x, np.transpose(x.conj(), (0, 2, 1)))           # T^k_{IJ}
     kq = geo.k_plus_q(kmesh)
     pi = np.empty_like(t)
     for q in range(nk):
@@ -63,11 +63,22 @@ def rhs(x, orbitals, kmesh, qs, r_index=None):
     r_index (all points if None).  Returns [len(qs), N_IP, N_r]."""
     nk = x.shape[0]
     phi = orbitals if r_index is None else orbitals[:, :, r_index]
-    t = np.einsum("kim,kmr->kir", x, phi.conj())                  # T^k_I(r)
+    t = np.matmul(x, phi.conj())                                  # T^k_I(r)
     kq = geo.k_plus_q(kmesh)
     out = np.empty((len(qs), x.shape[1], phi.shape[2]), dtype=np.complex128)
     for iq, q in enumerate(qs):
         out[iq] = np.einsum("kir,kir->ir", t[kq[:, q]].conj(), t)
+    return out
+
+
+def rhs_chunked(x, orbitals, kmesh, qs, chunk=4096):
+    """eta^q_I(r) of eq. (5) for the listed q on the whole grid, computed
+    over grid chunks so that T^k_I(r) is never held for all r at once."""
+    ng = orbitals.shape[2]
+    out = np.empty((len(qs), x.shape[1], ng), dtype=np.complex128)
+    for r0 in range(0, ng, chunk):
+        idx = np.arange(r0, min(ng, r0 + chunk))
+        out[:, :, idx] = rhs(x, orbitals, kmesh, qs, idx)
     return out
 
 

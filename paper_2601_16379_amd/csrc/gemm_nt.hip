@@ -130,7 +130,9 @@ __device__ inline void store_tile(typename NtCfg<P>::T* s, const u4 (&r)[4]) {
   }
 }
 
-template <int P, bool A_CONJ, bool B_CONJ>
+// KIND only names the call site in profiles (0 generic, 1 V^q, 2 U^q,
+// 3 fragment contraction); the code is the same.
+template <int P, bool A_CONJ, bool B_CONJ, int KIND>
 __global__ __launch_bounds__(256, 2) void zgemm_nt_kernel(const NtDesc* __restrict__ descs, int ndesc,
                                                        long long total_tiles) {
   typedef typename NtCfg<P>::T T;
@@ -385,17 +387,28 @@ __global__ __launch_bounds__(256, 2) void zgemm_nt_kernel(const NtDesc* __restri
   }
 }
 
-template <int P>
+template <int P, int KIND>
 hipError_t launch_nt(int conj, const NtDesc* descs, int ndesc, long long total, int blocks,
                      hipStream_t s) {
   dim3 g(blocks), b(256);
   switch (conj & 3) {
-    case 0: hipLaunchKernelGGL((zgemm_nt_kernel<P, false, false>), g, b, 0, s, descs, ndesc, total); break;
-    case 1: hipLaunchKernelGGL((zgemm_nt_kernel<P, true, false>), g, b, 0, s, descs, ndesc, total); break;
-    case 2: hipLaunchKernelGGL((zgemm_nt_kernel<P, false, true>), g, b, 0, s, descs, ndesc, total); break;
-    default: hipLaunchKernelGGL((zgemm_nt_kernel<P, true, true>), g, b, 0, s, descs, ndesc, total); break;
+    case 0: hipLaunchKernelGGL((zgemm_nt_kernel<P, false, false, KIND>), g, b, 0, s, descs, ndesc, total); break;
+    case 1: hipLaunchKernelGGL((zgemm_nt_kernel<P, true, false, KIND>), g, b, 0, s, descs, ndesc, total); break;
+    case 2: hipLaunchKernelGGL((zgemm_nt_kernel<P, false, true, KIND>), g, b, 0, s, descs, ndesc, total); break;
+    default: hipLaunchKernelGGL((zgemm_nt_kernel<P, true, true, KIND>), g, b, 0, s, descs, ndesc, total); break;
   }
   return hipGetLastError();
+}
+
+template <int P>
+hipError_t launch_kind(int kind, int conj, const NtDesc* descs, int ndesc, long long total, int blocks,
+                       hipStream_t s) {
+  switch (kind) {
+    case 1: return launch_nt<P, 1>(conj, descs, ndesc, total, blocks, s);
+    case 2: return launch_nt<P, 2>(conj, descs, ndesc, total, blocks, s);
+    case 3: return launch_nt<P, 3>(conj, descs, ndesc, total, blocks, s);
+    default: return launch_nt<P, 0>(conj, descs, ndesc, total, blocks, s);
+  }
 }
 
 }  // namespace
@@ -415,12 +428,12 @@ long long nt_plan(NtDesc* d, int n) {
 }
 
 hipError_t nt_launch(int prec, int conj, const NtDesc* descs_dev, int ndesc, long long total,
-                     int max_blocks, hipStream_t s) {
+                     int max_blocks, hipStream_t s, int kind) {
   if (total <= 0) return hipSuccess;
   const long long t8 = (total + 7) / 8 * 8;
   max_blocks = max_blocks / 8 * 8;
   const int blocks = (int)(t8 < max_blocks ? t8 : max_blocks);
-  if (prec == 0) return launch_nt<0>(conj, descs_dev, ndesc, total, blocks, s);
-  if (prec == 1) return launch_nt<1>(conj, descs_dev, ndesc, total, blocks, s);
-  return launch_nt<2>(conj, descs_dev, ndesc, total, blocks, s);
+  if (prec == 0) return launch_kind<0>(kind, conj, descs_dev, ndesc, total, blocks, s);
+  if (prec == 1) return launch_kind<1>(kind, conj, descs_dev, ndesc, total, blocks, s);
+  return launch_kind<2>(kind, conj, descs_dev, ndesc, total, blocks, s);
 }

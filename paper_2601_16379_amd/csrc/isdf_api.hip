@@ -135,11 +135,11 @@ void run_gemm(Arena& ar, int prec, int layout, std::vector<GemmDesc>& d, hipStre
   HIPCHK(gemm_launch(prec, layout, dd, (int)d.size(), total, max_gemm_blocks(), s));
 }
 
-void run_nt(Arena& ar, int prec, int conj, std::vector<NtDesc>& d, hipStream_t s) {
+void run_nt(Arena& ar, int prec, int conj, std::vector<NtDesc>& d, hipStream_t s, int kind = 0) {
   long long total = nt_plan(d.data(), (int)d.size());
   if (total == 0) return;
   NtDesc* dd = ar.put(d.data(), d.size(), s);
-  HIPCHK(nt_launch(prec, conj, dd, (int)d.size(), total, max_gemm_blocks(), s));
+  HIPCHK(nt_launch(prec, conj, dd, (int)d.size(), total, max_gemm_blocks(), s, kind));
 }
 
 NtDesc mknt(const void* A, long long lda, const void* B, long long ldb, void* C, long long ldc,
@@ -554,7 +554,7 @@ void do_kernel(isdf_ctx c, int prec) {
     d[0].batch = nk;
     d[0].sC_bat = nip2(c);
     d[0].herm = 1;
-    run_nt(c->arena, prec, 2, d, s);
+    run_nt(c->arena, prec, 2, d, s, 1);
   }
   c->timer.end("v_gemm", s);
   // W^q = Pi^{q+} V^q Pi^{q+}   (eq. (8)) in FP64 through the pivoted factor
@@ -766,7 +766,7 @@ void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn
     d[0].sA_bat = d[0].sC_bat = p.ptot * ld;
     d[0].sB_bat = (long long)nip * ld;
     d[0].epi = prec == 0 ? 0 : 3;
-    run_nt(ws.arena, prec, 0, d, s);
+    run_nt(ws.arena, prec, 0, d, s, 2);
   }
   if (timed) ws.timer.end("frag_u", s);
   // (pq|rs) = sum_q sum_J U^q_{(pq),J} conj(R^q_{(sr),J})  (eq. (19), R^{-q}_{rs} = conj R^q_{sr}),
@@ -790,7 +790,7 @@ void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn
     }
     // largest fragments first so the persistent launch ends balanced
     std::stable_sort(d.begin(), d.end(), [](const NtDesc& a, const NtDesc& b) { return a.M > b.M; });
-    run_nt(ws.arena, prec, 2, d, s);
+    run_nt(ws.arena, prec, 2, d, s, 3);
   }
   if (timed) ws.timer.end("frag_eri", s);
   for (size_t f = 0; f < fr.size(); ++f) {

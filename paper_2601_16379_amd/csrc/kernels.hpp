@@ -64,8 +64,9 @@ struct NtDesc {
 };
 long long nt_plan(NtDesc* d, int n);
 // conj: bit 0 conjugates A, bit 1 conjugates B
+// kind names the call site in profiles: 0 generic, 1 V^q, 2 U^q, 3 fragment contraction
 hipError_t nt_launch(int prec, int conj, const NtDesc* descs_dev, int ndesc, long long total,
-                     int max_blocks, hipStream_t s);
+                     int max_blocks, hipStream_t s, int kind = 0);
 
 // W^q (c128 [q][n][n]) -> transposed copies Wt[q][J][I] = W[q][I][J] with row
 // pitch ld in c128, two-float-plane and four-bf16-plane formats (any output

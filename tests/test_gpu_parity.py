@@ -88,7 +88,10 @@ def test_kernel_parity(name):
         ev = np.linalg.eigvalsh(c.pi[q])
         assert ranks[q] == int((ev > 1e-13 * ev.max()).sum())
     if all(r == cfg.n_ip for r in ranks):
-        assert _rel(c.g_w, c.w) < FP64_REL
+        for q in range(cfg.n_k):
+            # forward-error bound of the two-sided solve: 4 n eps cond(Pi^q)
+            tol = max(FP64_REL, 4 * cfg.n_ip * np.finfo(float).eps * np.linalg.cond(c.pi[q]))
+            assert _rel(c.g_w[q], c.w[q]) < tol
     kq = geo.k_plus_q(cfg.kmesh)
     for q in range(cfg.n_k):
         for k in range(min(cfg.n_k, 3)):
