@@ -1,0 +1,358 @@
+// Large-tile complex "NT" GEMM for the mixed precisions (FP32 and bf16x3):
+// 128x128 output tile per 512-thread workgroup, one K segment per launch.
+//
+//   C[m][n] (+)= sum_k opA(A_seg[m][k]) opB(B_seg[n][k])
+//
+// The sums over segments (q of eq. (19), blocks of grid points of eq. (7))
+// are made by launching once per segment and adding each FP32 partial into
+// an FP64 output matrix (epi 1), so every cross-segment sum is FP64 while the
+// kernel keeps only FP32 accumulators; that frees the registers for a tile
+// twice as large in each direction as the segmented kernel of gemm_nt.hip,
+// which halves the operand traffic per flop.  Operand formats and the
+// lane-local k permutation are those of gemm_nt.hip.  Eight waves in 4 x 2,
+// each 32 x 64 (2 x 4 MFMA tiles of 16x16).
+#include "kernels.hpp"
+
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+
+constexpr int BT = 128;     // tile edge
+constexpr int NT = 512;     // threads
+
+__device__ inline int isqrt_floor(long long x) {
+  long long r = (long long)sqrt((double)x);
+  while (r * r > x) --r;
+  while ((r + 1) * (r + 1) <= x) ++r;
+  return (int)r;
+}
+__device__ inline u4 neg_bf16x8(u4 v) {
+  return u4{v.x ^ 0x80008000u, v.y ^ 0x80008000u, v.z ^ 0x80008000u, v.w ^ 0x80008000u};
+}
+__device__ inline u4 neg_f32x4(u4 v) {
+  return u4{v.x ^ 0x80000000u, v.y ^ 0x80000000u, v.z ^ 0x80000000u, v.w ^ 0x80000000u};
+}
+__device__ inline bf8 as_bf8(u4 v) { return __builtin_bit_cast(bf8, v); }
+
+// BK = 64 k per stage: enough MFMA work per stage to cover the latency of
+// the next stage's global loads (one workgroup per CU).
+constexpr int BK = 64;
+template <int P> struct BigCfg;
+// per row: 64 floats (16 vectors of 4) + 4 pad / 64 bf16 (8 vectors of 8) + 8 pad
+template <> struct BigCfg<1> { static constexpr int PITCH = 68, PLANES = 2, VPR = 16, EPV = 4; typedef float T; };
+template <> struct BigCfg<2> { static constexpr int PITCH = 72, PLANES = 4, VPR = 8, EPV = 8; typedef unsigned short T; };
+constexpr int NV = 8;   // 16-byte vectors per thread per operand stage (128 x 64 x 8 B / 16 B / 512)
+
+// 128 rows x 64 k of one operand (all planes): 4096 16-byte vectors, 8 per thread
+template <int P, bool CONJ>
+__device__ inline void big_load(const void* base, long long ld, long long plane, int row0, int nrows,
+                                int k0, int kcur, u4 (&r)[NV]) {
+  typedef typename BigCfg<P>::T T;
+  constexpr int VPR = BigCfg<P>::VPR, EPV = BigCfg<P>::EPV;
+  constexpr int RSH = (VPR == 16) ? 4 : 3, PSH = RSH + 7;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const int v = threadIdx.x + NT * i;
+    const int pl = v >> PSH, row = (v >> RSH) & 127, c = v & (VPR - 1);
+    u4 x = u4{0, 0, 0, 0};
+    if (row0 + row < nrows && k0 + EPV * c < kcur) {
+      x = *(const u4*)((const T*)base + pl * plane + (long long)(row0 + row) * ld + k0 + EPV * c);
+      if constexpr (CONJ) {
+        if (P == 1 && pl == 1) x = neg_f32x4(x);
+        if (P == 2 && pl >= 2) x = neg_bf16x8(x);
+      }
+    }
+    r[i] = x;
+  }
+}
+
+template <int P>
+__device__ inline void big_store(typename BigCfg<P>::T* s, const u4 (&r)[NV]) {
+  constexpr int PITCH = BigCfg<P>::PITCH, VPR = BigCfg<P>::VPR, EPV = BigCfg<P>::EPV;
+  constexpr int RSH = (VPR == 16) ? 4 : 3, PSH = RSH + 7;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const int v = threadIdx.x + NT * i;
+    const int pl = v >> PSH, row = (v >> RSH) & 127, c = v & (VPR - 1);
+    *(u4*)(s + (pl * BT + row) * PITCH + EPV * c) = r[i];
+  }
+}
+
+template <int P, bool A_CONJ, bool B_CONJ, int KIND>
+__global__ __launch_bounds__(NT) void zgemm_big_kernel(const NtDesc* __restrict__ descs, int ndesc,
+                                                        long long total_tiles, int seg) {
+  typedef typename BigCfg<P>::T T;
+  constexpr int PITCH = BigCfg<P>::PITCH, PLANES = BigCfg<P>::PLANES;
+  __shared__ __attribute__((aligned(16))) T sA[PLANES * BT * PITCH];
+  __shared__ __attribute__((aligned(16))) T sB[PLANES * BT * PITCH];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;   // 4 x 2 waves, each 32 x 64
+  const int lr = lane & 15, lk = lane >> 4;
+
+  const long long t8 = (total_tiles + 7) / 8 * 8;
+  const long long per = t8 / 8;
+  for (long long it = blockIdx.x; it < t8; it += gridDim.x) {
+    const long long t = (it % 8) * per + it / 8;   // XCD-contiguous tile ranges
+    if (t >= total_tiles) continue;
+    int lo = 0, hi = ndesc - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (descs[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
+    }
+    const NtDesc d = descs[lo];
+    const long long local = t - d.tile_begin;
+    const int b = (int)(local / d.tiles_per_batch);
+    const int lt = (int)(local - (long long)b * d.tiles_per_batch);
+    int tm, tn;
+    if (d.herm) {
+      tm = (isqrt_floor(8LL * lt + 1) - 1) / 2;
+      tn = lt - tm * (tm + 1) / 2;
+    } else {
+      tm = lt / d.tiles_n;
+      tn = lt - tm * d.tiles_n;
+    }
+    const int m0 = tm * BT, n0 = tn * BT;
+    const size_t esz = sizeof(T);
+    const char* As = (const char*)d.A + ((long long)b * d.sA_bat + (long long)seg * d.sA_seg) * esz;
+    const char* Bs = (const char*)d.B + ((long long)b * d.sB_bat + (long long)seg * d.sB_seg) * esz;
+    const int kcur = (seg == d.nseg - 1) ? d.Klast : d.Kseg;
+
+    f4 c_re[2][4], c_im[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        c_re[i][j] = f4{0, 0, 0, 0};
+        c_im[i][j] = f4{0, 0, 0, 0};
+      }
+
+    u4 ra[NV], rb[NV];
+    big_load<P, A_CONJ>(As, d.lda, d.a_plane, m0, d.M, 0, kcur, ra);
+    big_load<P, B_CONJ>(Bs, d.ldb, d.b_plane, n0, d.N, 0, kcur, rb);
+    for (int k0 = 0; k0 < kcur; k0 += BK) {
+      __syncthreads();
+      big_store<P>(sA, ra);
+      big_store<P>(sB, rb);
+      __syncthreads();
+      if (k0 + BK < kcur) {
+        big_load<P, A_CONJ>(As, d.lda, d.a_plane, m0, d.M, k0 + BK, kcur, ra);
+        big_load<P, B_CONJ>(Bs, d.ldb, d.b_plane, n0, d.N, k0 + BK, kcur, rb);
+      }
+      if constexpr (P == 2) {
+#pragma unroll
+       for (int kh = 0; kh < BK; kh += 32) {
+        const unsigned short* a = (const unsigned short*)sA + kh;
+        const unsigned short* bb = (const unsigned short*)sB + kh;
+        bf8 a_rh[2], a_rl[2], a_ih[2], a_il[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const int ra_ = wm * 32 + i * 16 + lr;
+          a_rh[i] = as_bf8(*(const u4*)&a[(0 * BT + ra_) * PITCH + 8 * lk]);
+          a_rl[i] = as_bf8(*(const u4*)&a[(1 * BT + ra_) * PITCH + 8 * lk]);
+          a_ih[i] = as_bf8(*(const u4*)&a[(2 * BT + ra_) * PITCH + 8 * lk]);
+          a_il[i] = as_bf8(*(const u4*)&a[(3 * BT + ra_) * PITCH + 8 * lk]);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int rb_ = wn * 64 + j * 16 + lr;
+          const bf8 b_rh = as_bf8(*(const u4*)&bb[(0 * BT + rb_) * PITCH + 8 * lk]);
+          const bf8 b_rl = as_bf8(*(const u4*)&bb[(1 * BT + rb_) * PITCH + 8 * lk]);
+          const u4 bih = *(const u4*)&bb[(2 * BT + rb_) * PITCH + 8 * lk];
+          const u4 bil = *(const u4*)&bb[(3 * BT + rb_) * PITCH + 8 * lk];
+          const bf8 b_ih = as_bf8(bih), b_il = as_bf8(bil);
+          const bf8 b_nih = as_bf8(neg_bf16x8(bih)), b_nil = as_bf8(neg_bf16x8(bil));
+#pragma unroll
+          for (int i = 0; i < 2; ++i) {
+            f4 cr = c_re[i][j], ci = c_im[i][j];
+            cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_rl[i], b_rh, cr, 0, 0, 0);
+            cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_rh[i], b_rl, cr, 0, 0, 0);
+            cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_il[i], b_nih, cr, 0, 0, 0);
+            cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_ih[i], b_nil, cr, 0, 0, 0);
+            cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_rh[i], b_rh, cr, 0, 0, 0);
+            cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_ih[i], b_nih, cr, 0, 0, 0);
+            ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_rl[i], b_ih, ci, 0, 0, 0);
+            ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_rh[i], b_il, ci, 0, 0, 0);
+            ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_il[i], b_rh, ci, 0, 0, 0);
+            ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_ih[i], b_rl, ci, 0, 0, 0);
+            ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_rh[i], b_ih, ci, 0, 0, 0);
+            ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_ih[i], b_rh, ci, 0, 0, 0);
+            c_re[i][j] = cr;
+            c_im[i][j] = ci;
+          }
+        }
+       }
+      } else {
+        // FP32: lane k-set 8*lk + s, s = 0..7, per 32-k quarter
+        const float* a = (const float*)sA;
+        const float* bb = (const float*)sB;
+#pragma unroll
+        for (int half = 0; half < 2 * (BK / 32); ++half) {
+          float ar[2][4], ai[2][4];
+#pragma unroll
+          for (int i = 0; i < 2; ++i) {
+            const int ra_ = wm * 32 + i * 16 + lr;
+            const int ko = (half >> 1) * 32 + 8 * lk + 4 * (half & 1);
+            const f4 x0 = *(const f4*)&a[(0 * BT + ra_) * PITCH + ko];
+            const f4 x1 = *(const f4*)&a[(1 * BT + ra_) * PITCH + ko];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+              ar[i][s] = x0[s];
+              ai[i][s] = x1[s];
+            }
+          }
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int rb_ = wn * 64 + j * 16 + lr;
+            const int ko = (half >> 1) * 32 + 8 * lk + 4 * (half & 1);
+            const f4 y0 = *(const f4*)&bb[(0 * BT + rb_) * PITCH + ko];
+            const f4 y1 = *(const f4*)&bb[(1 * BT + rb_) * PITCH + ko];
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+              for (int i = 0; i < 2; ++i) {
+                c_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[i][s], y0[s], c_re[i][j], 0, 0, 0);
+                c_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai[i][s], y1[s], c_re[i][j], 0, 0, 0);
+                c_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[i][s], y1[s], c_im[i][j], 0, 0, 0);
+                c_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[i][s], y0[s], c_im[i][j], 0, 0, 0);
+              }
+          }
+        }
+      }
+    }
+
+    // ---- epilogue (FP32 layout: lane l, register v -> row 4*(l/16)+v, column l%16) ----
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int m = m0 + wm * 32 + i * 16 + 4 * lk + v;
+          const int n = n0 + wn * 64 + j * 16 + lr;
+          if (m >= d.M) continue;
+          const float vr = c_re[i][j][v], vi = c_im[i][j][v];
+          const long long o = (long long)b * d.sC_bat + (long long)m * d.ldc + n;
+          if (d.epi == 3) {
+            if (n >= d.ldc) continue;
+            const bool in = n < d.N;
+            store_fmt(d.C, o, d.c_plane, P, cmk(in ? vr : 0.0, in ? vi : 0.0));
+          } else {
+            if (n >= d.N) continue;
+            cplx* c = (cplx*)d.C + o;
+            cplx x = *c;                 // FP64 accumulation across launches
+            x.x += (double)vr;
+            x.y += (double)vi;
+            *c = x;
+          }
+        }
+  }
+}
+
+template <int P, int KIND>
+hipError_t launch_big(int conj, const NtDesc* descs, int ndesc, long long total, int blocks, int seg,
+                      hipStream_t s) {
+  dim3 g(blocks), b(NT);
+  switch (conj & 3) {
+    case 0: hipLaunchKernelGGL((zgemm_big_kernel<P, false, false, KIND>), g, b, 0, s, descs, ndesc, total, seg); break;
+    case 1: hipLaunchKernelGGL((zgemm_big_kernel<P, true, false, KIND>), g, b, 0, s, descs, ndesc, total, seg); break;
+    case 2: hipLaunchKernelGGL((zgemm_big_kernel<P, false, true, KIND>), g, b, 0, s, descs, ndesc, total, seg); break;
+    default: hipLaunchKernelGGL((zgemm_big_kernel<P, true, true, KIND>), g, b, 0, s, descs, ndesc, total, seg); break;
+  }
+  return hipGetLastError();
+}
+
+template <int P>
+hipError_t launch_big_kind(int kind, int conj, const NtDesc* descs, int ndesc, long long total, int blocks,
+                           int seg, hipStream_t s) {
+  switch (kind) {
+    case 1: return launch_big<P, 1>(conj, descs, ndesc, total, blocks, seg, s);
+    case 2: return launch_big<P, 2>(conj, descs, ndesc, total, blocks, seg, s);
+    case 3: return launch_big<P, 3>(conj, descs, ndesc, total, blocks, seg, s);
+    default: return launch_big<P, 0>(conj, descs, ndesc, total, blocks, seg, s);
+  }
+}
+
+// lower-tile Hermitian accumulation -> full matrix / ERI layout
+__global__ void herm_fill_kernel(cplx* c, int n, long long ld, long long bat, int nbat, int tile) {
+  const long long per = (long long)n * n;
+  const long long total = per * nbat;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const int b = (int)(idx / per);
+    const long long e = idx - (long long)b * per;
+    const int m = (int)(e / n), k = (int)(e - (e / n) * n);
+    if (m / tile < k / tile) {   // upper tile: conjugate of the computed lower entry
+      const cplx v = c[(long long)b * bat + (long long)k * ld + m];
+      c[(long long)b * bat + (long long)m * ld + k] = cmk(v.x, -v.y);
+    }
+  }
+}
+
+// E[(pq)][(sr)] (lower tiles of the computed matrix) -> eri[p][q][r][s]
+__global__ void eri_scatter_kernel(const cplx* __restrict__ e, cplx* eri, int nf, int tile) {
+  const int n = nf * nf;
+  const long long total = (long long)n * n;
+  const long long nf2 = (long long)nf * nf;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const int m = (int)(idx / n), c = (int)(idx - (idx / n) * n);
+    cplx v;
+    if (m / tile >= c / tile) {
+      v = e[idx];
+    } else {
+      const cplx u = e[(long long)c * n + m];
+      v = cmk(u.x, -u.y);
+    }
+    const int s_ = c / nf, r_ = c - s_ * nf;
+    eri[(long long)m * nf2 + (long long)r_ * nf + s_] = v;
+  }
+}
+
+inline unsigned grid_of(long long n) {
+  long long b = (n + 255) / 256;
+  return (unsigned)(b > 8192 ? 8192 : (b < 1 ? 1 : b));
+}
+
+}  // namespace
+
+long long big_plan(NtDesc* d, int n) {
+  long long acc = 0;
+  for (int i = 0; i < n; ++i) {
+    d[i].tiles_m = ceil_div(d[i].M, BT);
+    d[i].tiles_n = ceil_div(d[i].N, BT);
+    d[i].tiles_per_batch = d[i].herm ? d[i].tiles_m * (d[i].tiles_m + 1) / 2
+                                     : d[i].tiles_m * d[i].tiles_n;
+    if (d[i].Klast <= 0 || d[i].Klast > d[i].Kseg) d[i].Klast = d[i].Kseg;
+    d[i].tile_begin = acc;
+    acc += (long long)d[i].tiles_per_batch * d[i].batch;
+  }
+  return acc;
+}
+
+hipError_t big_launch(int prec, int conj, const NtDesc* descs_dev, int ndesc, long long total,
+                      int max_blocks, int seg, hipStream_t s, int kind) {
+  if (total <= 0) return hipSuccess;
+  if (prec != 1 && prec != 2) return hipErrorInvalidValue;
+  const long long t8 = (total + 7) / 8 * 8;
+  max_blocks = max_blocks / 8 * 8;
+  const int blocks = (int)(t8 < max_blocks ? t8 : max_blocks);
+  if (prec == 1) return launch_big_kind<1>(kind, conj, descs_dev, ndesc, total, blocks, seg, s);
+  return launch_big_kind<2>(kind, conj, descs_dev, ndesc, total, blocks, seg, s);
+}
+
+hipError_t herm_fill_launch(cplx* c, int n, long long ld, long long bat, int nbat, int tile, hipStream_t s) {
+  hipLaunchKernelGGL(herm_fill_kernel, dim3(grid_of((long long)n * n * nbat)), dim3(256), 0, s, c, n, ld,
+                     bat, nbat, tile);
+  return hipGetLastError();
+}
+
+hipError_t eri_scatter_launch(const cplx* e, cplx* eri, int nf, int tile, hipStream_t s) {
+  const long long n = (long long)nf * nf;
+  hipLaunchKernelGGL(eri_scatter_kernel, dim3(grid_of(n * n)), dim3(256), 0, s, e, eri, nf, tile);
+  return hipGetLastError();
+}

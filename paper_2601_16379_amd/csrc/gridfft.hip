@@ -200,6 +200,104 @@ __device__ void fft_lines_c(cplx* buf, cplx* tmp, const cplx* tw, int nlines) {
   __syncthreads();
 }
 
+// ---- two-stage radix transforms with the small DFTs in registers ----
+template <int R> struct Rot;
+// cos and sin of 2 pi t / R (closed forms where they exist), t = 0..R-1
+template <> struct Rot<2> {
+  static constexpr double c[2] = {1.0, -1.0};
+  static constexpr double s[2] = {0.0, 0.0};
+};
+template <> struct Rot<3> {
+  static constexpr double c[3] = {1.0, -0.5, -0.5};
+  static constexpr double s[3] = {0.0, 0.8660254037844386, -0.8660254037844386};
+};
+template <> struct Rot<4> {
+  static constexpr double c[4] = {1.0, 0.0, -1.0, 0.0};
+  static constexpr double s[4] = {0.0, 1.0, 0.0, -1.0};
+};
+template <> struct Rot<5> {
+  static constexpr double c[5] = {1.0, 0.30901699437494745, -0.8090169943749475, -0.8090169943749475, 0.30901699437494745};
+  static constexpr double s[5] = {0.0, 0.9510565162951535, 0.5877852522924731, -0.5877852522924731, -0.9510565162951535};
+};
+template <> struct Rot<6> {
+  static constexpr double c[6] = {1.0, 0.5, -0.5, -1.0, -0.5, 0.5};
+  static constexpr double s[6] = {0.0, 0.8660254037844386, 0.8660254037844386, 0.0, -0.8660254037844386, -0.8660254037844386};
+};
+template <> struct Rot<7> {
+  static constexpr double c[7] = {1.0, 0.6234898018587336, -0.22252093395631434, -0.900968867902419, -0.900968867902419, -0.22252093395631434, 0.6234898018587336};
+  static constexpr double s[7] = {0.0, 0.7818314824680298, 0.9749279121818236, 0.43388373911755823, -0.43388373911755823, -0.9749279121818236, -0.7818314824680298};
+};
+template <> struct Rot<8> {
+  static constexpr double c[8] = {1.0, 0.7071067811865476, 0.0, -0.7071067811865476, -1.0, -0.7071067811865476, 0.0, 0.7071067811865476};
+  static constexpr double s[8] = {0.0, 0.7071067811865476, 1.0, 0.7071067811865476, 0.0, -0.7071067811865476, -1.0, -0.7071067811865476};
+};
+
+
+// y[k] = sum_j x[j] exp(-2 pi i j k / R), compile-time R <= 8
+template <int R>
+__device__ inline void small_dft(const cplx (&x)[R], cplx (&y)[R]) {
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    double re = x[0].x, im = x[0].y;
+#pragma unroll
+    for (int j = 1; j < R; ++j) {
+      const double c = Rot<R>::c[(j * k) % R], sn = Rot<R>::s[(j * k) % R];
+      re = fma(x[j].x, c, fma(x[j].y, sn, re));
+      im = fma(x[j].y, c, fma(-x[j].x, sn, im));
+    }
+    y[k] = cmk(re, im);
+  }
+}
+
+// factor N = NA * NB with both <= 8 (NA <= NB), or 0 if impossible
+template <int N> constexpr int radix_a() {
+  int best = 0;
+  for (int a = 2; a <= 8; ++a)
+    if (N % a == 0 && N / a <= 8 && a <= N / a) best = a;
+  return best;
+}
+
+// Same transform as fft_lines_c: stage 1, one thread per (line, j2), does an
+// NA-point DFT over j1 in registers and the twiddle w^{j2 k1}; stage 2, one
+// thread per (line, k1), an NB-point DFT over j2.  Two LDS reads and two LDS
+// writes per point and axis.
+template <int N, int L1, int S1, int S2, int ES>
+__device__ void fft_lines_r(cplx* buf, cplx* tmp, const cplx* tw, int nlines) {
+  constexpr int NA = radix_a<N>(), NB = N / NA;
+  const int n1 = nlines * NB;
+  for (int it = threadIdx.x; it < n1; it += blockDim.x) {
+    const int l = it / NB, j2 = it % NB;
+    const int base = (l / L1) * S1 + (l % L1) * S2;
+    cplx x[NA], y[NA];
+#pragma unroll
+    for (int j1 = 0; j1 < NA; ++j1) x[j1] = buf[base + (NB * j1 + j2) * ES];
+    small_dft<NA>(x, y);
+    tmp[base + (j2 * NA) * ES] = y[0];
+#pragma unroll
+    for (int k1 = 1; k1 < NA; ++k1) tmp[base + (j2 * NA + k1) * ES] = cmul(y[k1], tw[(j2 * k1) % N]);
+  }
+  __syncthreads();
+  const int n2 = nlines * NA;
+  for (int it = threadIdx.x; it < n2; it += blockDim.x) {
+    const int l = it / NA, k1 = it % NA;
+    const int base = (l / L1) * S1 + (l % L1) * S2;
+    cplx x[NB], y[NB];
+#pragma unroll
+    for (int j2 = 0; j2 < NB; ++j2) x[j2] = tmp[base + (j2 * NA + k1) * ES];
+    small_dft<NB>(x, y);
+#pragma unroll
+    for (int k2 = 0; k2 < NB; ++k2) buf[base + (k1 + NA * k2) * ES] = y[k2];
+  }
+  __syncthreads();
+}
+
+// radix path when N factors into two factors <= 8, generic otherwise
+template <int N, int L1, int S1, int S2, int ES>
+__device__ inline void fft_axis(cplx* buf, cplx* tmp, const cplx* tw, int nlines) {
+  if constexpr (radix_a<N>() != 0) fft_lines_r<N, L1, S1, S2, ES>(buf, tmp, tw, nlines);
+  else fft_lines_c<N, L1, S1, S2, ES>(buf, tmp, tw, nlines);
+}
+
 template <int N>
 __global__ __launch_bounds__(256) void slab_kernel_c(GridFftArgs a, int S) {
   constexpr int N2 = N * N;
@@ -226,8 +324,8 @@ __global__ __launch_bounds__(256) void slab_kernel_c(GridFftArgs a, int S) {
     buf[idx] = cmul(v, cexpipi(-2.0 * ph));
   }
   __syncthreads();
-  fft_lines_c<N, 1, N, 0, 1>(buf, tmp, tw, ns * N);    // along i3
-  fft_lines_c<N, N, N2, 1, N>(buf, tmp, tw, ns * N);   // along i2
+  fft_axis<N, 1, N, 0, 1>(buf, tmp, tw, ns * N);    // along i3
+  fft_axis<N, N, N2, 1, N>(buf, tmp, tw, ns * N);   // along i2
   for (int idx = threadIdx.x; idx < ns * N2; idx += blockDim.x) {
     const int s = idx / N2, p = idx % N2;
     const long long slab = s0 + s;
@@ -260,7 +358,7 @@ __global__ __launch_bounds__(256) void col_kernel_c(GridFftArgs a) {
     buf[idx] = (c < nc) ? base[(long long)i1 * N2 + c0 + c] : cmk(0.0, 0.0);
   }
   __syncthreads();
-  fft_lines_c<N, 1, 1, 0, COLS>(buf, tmp, tw, COLS);   // along i1
+  fft_axis<N, 1, 1, 0, COLS>(buf, tmp, tw, COLS);   // along i1
   double qf[3];
   q_frac(a, a.q0 + qi, qf);
   const double coef = sqrt(4.0 * M_PI * a.volume) / ((double)N * N2);

@@ -142,6 +142,15 @@ void run_nt(Arena& ar, int prec, int conj, std::vector<NtDesc>& d, hipStream_t s
   HIPCHK(nt_launch(prec, conj, dd, (int)d.size(), total, max_gemm_blocks(), s, kind));
 }
 
+// Upload big-tile descriptors once and launch them for each K segment.
+void run_big(Arena& ar, int prec, int conj, std::vector<NtDesc>& d, int nseg, hipStream_t s, int kind) {
+  long long total = big_plan(d.data(), (int)d.size());
+  if (total == 0) return;
+  NtDesc* dd = ar.put(d.data(), d.size(), s);
+  for (int seg = 0; seg < nseg; ++seg)
+    HIPCHK(big_launch(prec, conj, dd, (int)d.size(), total, max_gemm_blocks(), seg, s, kind));
+}
+
 NtDesc mknt(const void* A, long long lda, const void* B, long long ldb, void* C, long long ldc,
             int M, int N, int K) {
   NtDesc d;
@@ -541,7 +550,13 @@ void do_kernel(isdf_ctx c, int prec) {
     if (prec == ISDF_FP64) {
       d[0] = mknt(c->eta.p, ng, c->eta.p, ng, c->work1.p, nip, nip, nip, (int)ng);
       d[0].sA_bat = d[0].sB_bat = (long long)nip * ng;
+      d[0].batch = nk;
+      d[0].sC_bat = nip2(c);
+      d[0].herm = 1;
+      run_nt(c->arena, prec, 2, d, s, 1);
     } else {
+      // one large-tile launch per block of 2048 grid points: FP32 inside a
+      // block, FP64 accumulation into V across blocks; lower tiles, then mirror
       d[0] = mknt(c->eta_split.p, c->ld_g, c->eta_split.p, c->ld_g, c->work1.p, nip, nip, nip, (int)ng);
       d[0].a_plane = d[0].b_plane = split_plane;
       const int kseg = 2048;
@@ -550,11 +565,14 @@ void do_kernel(isdf_ctx c, int prec) {
       d[0].Klast = (int)(ng - (long long)(d[0].nseg - 1) * d[0].Kseg);
       d[0].sA_seg = d[0].sB_seg = d[0].Kseg;
       d[0].sA_bat = d[0].sB_bat = (long long)nip * c->ld_g;
+      d[0].batch = nk;
+      d[0].sC_bat = nip2(c);
+      d[0].herm = 2;
+      d[0].epi = 1;
+      HIPCHK(zero_launch(c->work1.as<cplx>(), (long long)nk * nip2(c), s));
+      run_big(c->arena, prec, 2, d, d[0].nseg, s, 1);
+      HIPCHK(herm_fill_launch(c->work1.as<cplx>(), nip, nip, nip2(c), nk, BIG_TILE, s));
     }
-    d[0].batch = nk;
-    d[0].sC_bat = nip2(c);
-    d[0].herm = 1;
-    run_nt(c->arena, prec, 2, d, s, 1);
   }
   c->timer.end("v_gemm", s);
   // W^q = Pi^{q+} V^q Pi^{q+}   (eq. (8)) in FP64 through the pivoted factor
@@ -611,7 +629,8 @@ struct BatchPlan {
   long long ptot = 0;
   std::vector<int> col, nf;
   std::vector<long long> poff, eoff;
-  size_t off_c = 0, off_tf = 0, off_m = 0, off_u = 0, off_e = 0, bytes = 0;
+  size_t off_c = 0, off_tf = 0, off_m = 0, off_u = 0, off_e = 0, off_acc = 0, bytes = 0;
+  std::vector<long long> aoff;   // per fragment offset in the FP64 accumulation region (mixed)
 };
 
 // Layout of one fragment batch in its workspace:
@@ -642,6 +661,13 @@ BatchPlan plan_batch(isdf_ctx c, const std::vector<FragIn>& fr, int prec) {
   p.off_u = off;
   off += al(std::max<size_t>(mb, (size_t)c->nk * c->norb * p.ncol * sizeof(cplx)));
   p.off_e = off; off += al((size_t)ecount * sizeof(cplx));
+  // mixed precisions: FP64 accumulation matrices E_f[(pq)][(sr)] (one launch per q)
+  long long acount = 0;
+  for (const FragIn& f : fr) {
+    p.aoff.push_back(acount);
+    if (prec != 0) acount += (long long)f.nf * f.nf * f.nf * f.nf;
+  }
+  p.off_acc = off; off += al((size_t)acount * sizeof(cplx));
   p.bytes = off;
   return p;
 }
@@ -650,7 +676,8 @@ size_t request_bytes(isdf_ctx c, int nf, bool host_out, int prec) {
   size_t b = ((size_t)c->nk * c->norb * nf + (size_t)c->nk * c->nip * nf) * sizeof(cplx) +
              2 * (size_t)c->nk * c->ld_ip * nf * nf * fmt_bytes(prec);
   if (host_out) b += (size_t)nf * nf * nf * nf * sizeof(cplx);
-  return b + 5 * 256;
+  if (prec != 0) b += (size_t)nf * nf * nf * nf * sizeof(cplx);
+  return b + 6 * 256;
 }
 
 // Enqueue the whole fragment pipeline of one batch on ws.stream.
@@ -766,7 +793,8 @@ void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn
     d[0].sA_bat = d[0].sC_bat = p.ptot * ld;
     d[0].sB_bat = (long long)nip * ld;
     d[0].epi = prec == 0 ? 0 : 3;
-    run_nt(ws.arena, prec, 0, d, s, 2);
+    if (prec == 0) run_nt(ws.arena, prec, 0, d, s, 2);
+    else run_big(ws.arena, prec, 0, d, 1, s, 2);
   }
   if (timed) ws.timer.end("frag_u", s);
   // (pq|rs) = sum_q sum_J U^q_{(pq),J} conj(R^q_{(sr),J})  (eq. (19), R^{-q}_{rs} = conj R^q_{sr}),
@@ -775,22 +803,41 @@ void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn
   {
     std::vector<NtDesc> d;
     const size_t sc = fmt_scalar(prec);
+    cplx* acc = (cplx*)(base + p.off_acc);
     for (size_t f = 0; f < fr.size(); ++f) {
       const int nf2 = p.nf[f] * p.nf[f];
       cplx* out = (fr[f].flags & ISDF_FRAG_DEVICE) ? (cplx*)fr[f].eri : Est + p.eoff[f];
       const size_t o = (size_t)p.poff[f] * ld * sc;
-      NtDesc g = mknt(Uq + o, ld, Mq + o, ld, out, 0, nf2, nf2, nip);
+      NtDesc g = mknt(Uq + o, ld, Mq + o, ld, prec == 0 ? (void*)out : (void*)(acc + p.aoff[f]),
+                      prec == 0 ? 0 : nf2, nf2, nf2, nip);
       g.a_plane = g.b_plane = mplane;
       g.nseg = nk;
       g.sA_seg = g.sB_seg = p.ptot * ld;
-      g.herm = 1;
-      g.epi = 2;
-      g.nf = p.nf[f];
+      if (prec == 0) {
+        g.herm = 1;
+        g.epi = 2;
+        g.nf = p.nf[f];
+      } else {
+        g.herm = 2;
+        g.epi = 1;
+      }
       d.push_back(g);
     }
     // largest fragments first so the persistent launch ends balanced
     std::stable_sort(d.begin(), d.end(), [](const NtDesc& a, const NtDesc& b) { return a.M > b.M; });
-    run_nt(ws.arena, prec, 2, d, s, 3);
+    if (prec == 0) {
+      run_nt(ws.arena, prec, 2, d, s, 3);
+    } else {
+      // one launch per q: FP32 partial sums within q, FP64 sum over q in E_f
+      long long acount = 0;
+      for (size_t f = 0; f < fr.size(); ++f) acount += (long long)p.nf[f] * p.nf[f] * p.nf[f] * p.nf[f];
+      HIPCHK(zero_launch(acc, acount, s));
+      run_big(ws.arena, prec, 2, d, nk, s, 3);
+      for (size_t f = 0; f < fr.size(); ++f) {
+        cplx* out = (fr[f].flags & ISDF_FRAG_DEVICE) ? (cplx*)fr[f].eri : Est + p.eoff[f];
+        HIPCHK(eri_scatter_launch(acc + p.aoff[f], out, p.nf[f], BIG_TILE, s));
+      }
+    }
   }
   if (timed) ws.timer.end("frag_eri", s);
   for (size_t f = 0; f < fr.size(); ++f) {

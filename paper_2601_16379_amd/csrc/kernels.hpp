@@ -68,6 +68,20 @@ long long nt_plan(NtDesc* d, int n);
 hipError_t nt_launch(int prec, int conj, const NtDesc* descs_dev, int ndesc, long long total,
                      int max_blocks, hipStream_t s, int kind = 0);
 
+// Large-tile (128x128, 512 threads) NT GEMM for the mixed precisions (1, 2):
+// one K segment `seg` per launch; epi 1 adds the FP32 partial into an FP64
+// c128 output (FP64 accumulation across launches), epi 3 stores the split
+// format; herm 2 computes lower tiles only.
+long long big_plan(NtDesc* d, int n);
+hipError_t big_launch(int prec, int conj, const NtDesc* descs_dev, int ndesc, long long total,
+                      int max_blocks, int seg, hipStream_t s, int kind = 0);
+// Fill the upper tiles (tile edge `tile`) of nbat Hermitian n x n matrices
+// from their lower tiles.
+hipError_t herm_fill_launch(cplx* c, int n, long long ld, long long bat, int nbat, int tile, hipStream_t s);
+// E[(pq)][(sr)] with lower tiles computed (edge `tile`) -> eri[p][q][r][s]
+hipError_t eri_scatter_launch(const cplx* e, cplx* eri, int nf, int tile, hipStream_t s);
+constexpr int BIG_TILE = 128;
+
 // W^q (c128 [q][n][n]) -> transposed copies Wt[q][J][I] = W[q][I][J] with row
 // pitch ld in c128, two-float-plane and four-bf16-plane formats (any output
 // pointer may be null); pad columns are zero.
@@ -172,5 +186,7 @@ hipError_t gather_launch(const cplx* phi, const int* ip, cplx* xt, int nk, int n
 // into the batch matrix)
 hipError_t copy_cols_launch(const cplx* in, cplx* out, int nk, int norb, int nf,
                             int ncol, int col0, hipStream_t s);
+// x[i] = 0 for i < n (complex128)
+hipError_t zero_launch(cplx* x, long long n, hipStream_t s);
 // count non-finite entries (real or imaginary) of n complex values into *flag
 hipError_t nonfinite_launch(const cplx* x, long long n, int* flag, hipStream_t s);

@@ -55,6 +55,12 @@ __global__ void wt_convert_kernel(const cplx* __restrict__ w, cplx* wt64, float*
   }
 }
 
+__global__ void zero_c_kernel(cplx* x, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    x[i] = cmk(0.0, 0.0);
+}
+
 inline int grid_for(long long n) {
   long long b = (n + 255) / 256;
   return (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
@@ -85,5 +91,11 @@ hipError_t wt_convert_launch(const cplx* w, cplx* wt64, float* wt32, unsigned sh
                              int ld, int nq, hipStream_t s) {
   hipLaunchKernelGGL(wt_convert_kernel, dim3(grid_for((long long)nq * n * ld)), dim3(256), 0, s, w,
                      wt64, wt32, wt16, n, ld, nq);
+  return hipGetLastError();
+}
+
+hipError_t zero_launch(cplx* x, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_c_kernel, dim3(grid_for(n)), dim3(256), 0, s, x, n);
   return hipGetLastError();
 }

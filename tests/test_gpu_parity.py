@@ -186,3 +186,24 @@ def test_state_errors():
     with pytest.raises(pkg.IsdfError) as e:
         ctx.get_kernel(0)
     assert e.value.status == -3
+
+
+@pytest.mark.parametrize("name", ["t_grid10_k1", "t_grid18_k2", "t_grid20_k3", "t_grid36_k2",
+                                  "t_grid40_k1"])
+def test_grid_fft_sizes_kernel_and_eri(name):
+    """Every radix pair of the unit-cell FFT (10 = 2x5, 18 = 3x6, 20 = 4x5,
+    36 = 6x6, 40 = 5x8) through W^q and the fragment ERIs."""
+    d = inp.make_inputs(name)
+    cfg = d.cfg
+    x, pi, eta, w = ko.fit_and_kernel(d.orbitals, d.ip_index, d.lattice, cfg.grid, cfg.kmesh)
+    ctx = _ctx(d)
+    ctx.fit()
+    ctx.coulomb_kernel("fp64")
+    assert ctx.stats()["rank"] == [cfg.n_ip] * cfg.n_k
+    for q in range(cfg.n_k):
+        tol = max(FP64_REL, 4 * cfg.n_ip * np.finfo(float).eps * np.linalg.cond(pi[q]))
+        assert _rel(ctx.get_kernel(q), w[q]) < tol, q
+    frags = inp.make_fragments(cfg)
+    out = ctx.fragment_eri(frags, "fp64")
+    for f, cf in enumerate(frags):
+        assert _rel(out[f], ko.fragment_eri(x, cf, w, cfg.kmesh)) < FP64_REL
