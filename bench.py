@@ -55,8 +55,11 @@ def stage_work(stage, cfg, nfs, prec):
         return "mfma", 8.0 * nk * nip * nip * s2 / 1e12, "TFLOP", pk
     if stage == "v_gemm":     # Hermitian half of eta~ eta~^H
         return "mfma", 8.0 * nk * nip * nip * ng / 2 / 1e12, "TFLOP", pk
-    if stage == "grid_fft":   # two read+write passes over eta (c128)
-        return "hbm", 4.0 * nk * nip * ng * 16 / 1e9, "GB", PEAK["hbm"]
+    if stage == "grid_fft":
+        if prec == "fp64":    # two read+write passes over eta (c128)
+            return "hbm", 4.0 * nk * nip * ng * 16 / 1e9, "GB", PEAK["hbm"]
+        # one pass: eta read (c128), the split operand written (8 B a point)
+        return "hbm", nk * nip * ng * (16 + 8) / 1e9, "GB", PEAK["hbm"]
     if stage == "rhs_t":      # T^k_I(r) = X^k conj(phi^k): written once (c128)
         return "hbm", 1.0 * nk * nip * ng * 16 / 1e9, "GB", PEAK["hbm"]
     if stage == "rhs_kconv":  # T^k_I(r) read, eta written once (c128)
@@ -76,16 +79,19 @@ def stage_work(stage, cfg, nfs, prec):
     return None
 
 
-KERNEL_OF_STAGE = {"frag_eri": "zgemm_nt_kernel<{p}, false, true, 3>",
-                   "frag_u": "zgemm_nt_kernel<{p}, false, false, 2>",
-                   "v_gemm": "zgemm_nt_kernel<{p}, false, true, 1>",
-                   "frag_pair": "pair_kernel(PairArgs)"}
+KERNEL_OF_STAGE = {"frag_eri": ("zgemm_nt_kernel<0, false, true, 3>", "zgemm_big_kernel<{p}, false, true, 3>"),
+                   "frag_u": ("zgemm_nt_kernel<0, false, false, 2>", "zgemm_big_kernel<{p}, false, false, 2>"),
+                   "v_gemm": ("zgemm_nt_kernel<0, false, true, 1>", "zgemm_big_kernel<{p}, false, true, 1>"),
+                   "frag_pair": ("pair_kernel(PairArgs)", "pair_kernel(PairArgs)"),
+                   "rhs_kconv": ("kconv_kernel(KconvArgs, int)", "kconv_kernel(KconvArgs, int)"),
+                   "grid_fft": ("slab_kernel_c<", "fft3_reg_kernel<")}
 
 
 def counter_traffic(stage, workload, prec):
-    """HBM bytes per launch of a stage's kernel from the committed rocprofv3
-    counter summary (FETCH_SIZE + WRITE_SIZE, scaled by a 1 GiB copy), or
-    None if there is none or a kernel source changed since it was taken."""
+    """HBM bytes of one step of a stage's main kernel (all its dispatches in
+    the step) from the committed rocprofv3 counter summary (FETCH_SIZE +
+    WRITE_SIZE, scaled by a 1 GiB copy), or None if there is none or a kernel
+    source changed since it was taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "%s_%s_traffic.json" % (workload, prec))
     if stage not in KERNEL_OF_STAGE or not os.path.exists(path):
@@ -96,10 +102,10 @@ def counter_traffic(stage, workload, prec):
         fp = os.path.join(csrc, f)
         if not os.path.exists(fp) or hashlib.sha256(open(fp, "rb").read()).hexdigest() != h:
             return None
-    key = KERNEL_OF_STAGE[stage].format(p={"fp64": 0, "fp32": 1, "bf16x3": 2}[prec])
+    key = KERNEL_OF_STAGE[stage][0 if prec == "fp64" else 1].format(p={"fp32": 1, "bf16x3": 2}.get(prec, 0))
     for name, v in prof["kernels"].items():
         if key in name:
-            return v["fetch_bytes"] + v["write_bytes"]
+            return v["step_bytes"]
     return None
 
 

@@ -117,7 +117,7 @@ isdf_status isdf_fit(isdf_ctx ctx);
  * W^q for all q (eqs. (6)-(8)): grid FFT of eta^q(r) exp(-i q.r), scaled by
  * sqrt(Omega 4 pi/|G+q|^2)/N_g (FP64), V^q = eta~ eta~^H (GEMM in `prec`),
  * W^q = Pi^{q+} V^q Pi^{q+} by FP64 triangular solves with the factor of
- * isdf_fit.  Consumes eta (overwritten in place).  Synchronous.
+ * isdf_fit.  Consumes eta (isdf_get_rhs is invalid afterwards).  Synchronous.
  * Error: ISDF_E_STATE before isdf_fit.
  */
 isdf_status isdf_coulomb_kernel(isdf_ctx ctx, isdf_precision prec);
@@ -131,6 +131,15 @@ isdf_status isdf_get_ivs(isdf_ctx ctx, int32_t k, void* out);
 /* Copy eta^q (c128 [n_ip][N_g]) to host; valid between isdf_fit and
  * isdf_coulomb_kernel. */
 isdf_status isdf_get_rhs(isdf_ctx ctx, int32_t q, void* out);
+/* Test hook: copy the Coulomb-weighted transform of eq. (7),
+ *   eta~^q_I(G) = sqrt(Omega 4 pi / |G+q|^2) / N_g sum_r eta^q_I(r) exp(-i (G+q).r)
+ * (0 at G+q = 0), as it enters V^q = eta~ eta~^H: FP64 after an FP64
+ * isdf_coulomb_kernel, else the FP32 or bf16 hi+lo operand of the mixed
+ * product, converted exactly to c128.  out: host c128 [n_ip][N_g], G in the
+ * FFT order of the grid (index i_d stands for G_d = i_d wrapped to
+ * [-n_d/2, n_d/2)).  Valid after isdf_coulomb_kernel until the next isdf_fit.
+ * Error: ISDF_E_STATE before isdf_coulomb_kernel, ISDF_E_INVALID for a bad q. */
+isdf_status isdf_get_eta_tilde(isdf_ctx ctx, int32_t q, void* out);
 
 /*
  * Fragment ERIs for a batch of fragments in one pass (eqs. (19)-(20),

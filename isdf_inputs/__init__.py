@@ -102,9 +102,9 @@ CONFIGS = {
     # grid sizes of every FFT code path (radix pairs 2x5, 4x5, 3x6, 6x6, 5x8)
     "t_grid10_k1": Config("t_grid10_k1", 110, 5.0, (10, 10, 10), (1, 1, 1), 8, 30,
                           gmax=2.0, env=3.0, n_frag=1, frag_lo=4, frag_hi=4),
-    "t_grid20_k3": Config("t_grid20_k3", 111, 5.0, (20, 20, 20), (3, 1, 1), 4, 40,
+    "t_grid20_k3": Config("t_grid20_k3", 111, 5.0, (20, 20, 20), (3, 1, 1), 8, 40,
                           gmax=3.0, env=3.0, n_frag=1, frag_lo=6, frag_hi=6),
-    "t_grid18_k2": Config("t_grid18_k2", 112, 5.0, (18, 18, 18), (1, 2, 1), 6, 36,
+    "t_grid18_k2": Config("t_grid18_k2", 112, 5.0, (18, 18, 18), (1, 2, 1), 8, 36,
                           gmax=3.0, env=3.0, n_frag=1, frag_lo=5, frag_hi=5),
     "t_grid36_k2": Config("t_grid36_k2", 113, 6.0, (36, 36, 36), (2, 1, 1), 6, 40,
                           gmax=4.0, env=4.0, n_frag=1, frag_lo=6, frag_hi=6),

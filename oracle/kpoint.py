@@ -105,6 +105,23 @@ def coulomb_kernel_of(f_q, lattice, grid, kmesh, q):
     return (vol / ng ** 2) * ((fh * c[None, :]) @ fh.conj().T)
 
 
+def eta_tilde(f_q, lattice, grid, kmesh, q):
+    """The Coulomb-weighted transform whose Hermitian square is V^q (eq. (7)):
+    etatilde_I(G) = sqrt(Omega c(G+q)) / N_g * sum_r f_I(r) exp(-i (G+q).r),
+    so that (Omega/N_g^2) sum_G c(G+q) fhat_I conj(fhat_J) = etatilde etatilde^H.
+    G in the numpy FFT index order of the grid; f_q: [N_IP, N_g]."""
+    jq = geo.kmesh_indices(kmesh)[q]
+    qf = geo.q_frac_wrapped(jq, kmesh)
+    frac = geo.grid_frac(grid)
+    phase = np.exp(-2j * np.pi * (frac @ qf))
+    n1, n2, n3 = grid
+    fh = np.fft.fftn((f_q * phase[None, :]).reshape(-1, n1, n2, n3),
+                     axes=(1, 2, 3)).reshape(f_q.shape[0], -1)
+    c = geo.coulomb_g_plus_q(lattice, grid, qf)
+    vol = abs(np.linalg.det(lattice))
+    return fh * (np.sqrt(vol * c) / (n1 * n2 * n3))[None, :]
+
+
 def kernel_zeta_route(pi, eta_all, lattice, grid, kmesh, rcond=1e-13):
     """W^q for all q from xi^q = Pi^{q+} eta^q (eqs. (3), (6))."""
     out = np.empty_like(pi)

@@ -238,7 +238,7 @@ __global__ __launch_bounds__(NT) void zgemm_big_kernel(const NtDesc* __restrict_
           const float vr = c_re[i][j][v], vi = c_im[i][j][v];
           const long long o = (long long)b * d.sC_bat + (long long)m * d.ldc + n;
           if (d.epi == 3) {
-            if (n >= d.ldc) continue;
+            if (n >= (d.npad ? d.npad : d.ldc)) continue;
             const bool in = n < d.N;
             store_fmt(d.C, o, d.c_plane, P, cmk(in ? vr : 0.0, in ? vi : 0.0));
           } else {

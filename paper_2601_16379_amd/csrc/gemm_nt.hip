@@ -341,7 +341,7 @@ __global__ __launch_bounds__(256, 2) void zgemm_nt_kernel(const NtDesc* __restri
           const double vr = acc_re[i][j][v], vi = acc_im[i][j][v];
           if (d.epi == 3) {
             // split store (format of P) with zero fill of the row padding
-            if (n >= d.ldc) continue;
+            if (n >= (d.npad ? d.npad : d.ldc)) continue;
             const bool in = n < d.N;
             const long long o = (long long)b * d.sC_bat + (long long)m * d.ldc + n;
             if constexpr (P == 1) {

@@ -390,6 +390,207 @@ __global__ __launch_bounds__(256) void col_kernel_c(GridFftArgs a) {
   }
 }
 
+// ---- one-pass variant for the mixed precisions (cubic N x N x N, N*N <= 1024,
+// N = NA * NB with both factors <= 8) ----
+// One workgroup of N*N threads per (q, I).  Every thread holds one line of N
+// points in FP32 registers and transforms it there; two transposes through a
+// padded LDS plane bring the other two axes into the registers in turn:
+//   load : thread (i2, i3) holds the i1 line (lanes run along i3: the c128
+//          input rows are read as contiguous runs), phase applied, FFT i1;
+//   LDS  : thread (k1, i2) takes the i3 line, FFT i3;
+//   LDS  : thread (k1, k3) takes the i2 line, FFT i2, Coulomb factor, and the
+//          split output is written with the lanes running along k3.
+// One HBM read of the c128 input and one write of the split output per point.
+// The FP32 rounding of the transform (a few 1e-8 relative) is far below the
+// rounding of the FP32 / bf16 hi+lo operands it feeds.
+constexpr double kPiD = 3.141592653589793;
+constexpr double series_cos(double x) {
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 24; ++k) {
+    term *= -x * x / ((2.0 * k - 1.0) * (2.0 * k));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double series_sin(double x) {
+  double term = x, sum = x;
+  for (int k = 1; k < 24; ++k) {
+    term *= -x * x / ((2.0 * k) * (2.0 * k + 1.0));
+    sum += term;
+  }
+  return sum;
+}
+// cos and sin of 2 pi t / N, t = 0..N-1 (Taylor series at |x| <= pi)
+template <int N> struct TwF {
+  float c[N], s[N];
+  constexpr TwF() : c(), s() {
+    for (int t = 0; t < N; ++t) {
+      double x = 2.0 * kPiD * t / N;
+      if (x > kPiD) x -= 2.0 * kPiD;
+      c[t] = (float)series_cos(x);
+      s[t] = (float)series_sin(x);
+    }
+  }
+};
+
+// a * (c - i s) with compile-time c, s (the trivial factors fold away)
+__device__ inline float2 rot_f(float2 a, float c, float s) {
+  if (c == 1.0f && s == 0.0f) return a;
+  if (c == 0.0f && s == 1.0f) return make_float2(a.y, -a.x);
+  if (c == -1.0f && s == 0.0f) return make_float2(-a.x, -a.y);
+  if (c == 0.0f && s == -1.0f) return make_float2(-a.y, a.x);
+  return make_float2(fmaf(a.x, c, a.y * s), fmaf(a.y, c, -a.x * s));
+}
+
+template <int R>
+__device__ inline void small_dft_f(const float2 (&x)[R], float2 (&y)[R]) {
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    float2 acc = x[0];
+#pragma unroll
+    for (int j = 1; j < R; ++j) {
+      const float2 t = rot_f(x[j], (float)Rot<R>::c[(j * k) % R], (float)Rot<R>::s[(j * k) % R]);
+      acc.x += t.x;
+      acc.y += t.y;
+    }
+    y[k] = acc;
+  }
+}
+
+// forward DFT of the N values in registers: v[j] -> sum_j v[j] exp(-2 pi i jk/N)
+template <int N>
+__device__ inline void fft_reg(float2 (&v)[N]) {
+  constexpr int NA = radix_a<N>(), NB = N / NA;
+  constexpr TwF<N> tw{};
+  float2 y[NA][NB];
+#pragma unroll
+  for (int j2 = 0; j2 < NB; ++j2) {
+    float2 x[NA], z[NA];
+#pragma unroll
+    for (int j1 = 0; j1 < NA; ++j1) x[j1] = v[NB * j1 + j2];
+    small_dft_f<NA>(x, z);
+#pragma unroll
+    for (int k1 = 0; k1 < NA; ++k1) y[k1][j2] = rot_f(z[k1], tw.c[(j2 * k1) % N], tw.s[(j2 * k1) % N]);
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < NA; ++k1) {
+    float2 x[NB], z[NB];
+#pragma unroll
+    for (int j2 = 0; j2 < NB; ++j2) x[j2] = y[k1][j2];
+    small_dft_f<NB>(x, z);
+#pragma unroll
+    for (int k2 = 0; k2 < NB; ++k2) v[k1 + NA * k2] = z[k2];
+  }
+}
+
+// Redistribute the lines through one padded LDS plane: this thread's value j
+// goes to ex[wbase + j * wstride]; afterwards it holds ex[rbase + j * rstride].
+template <int N>
+__device__ inline void exchange(float* ex, float2 (&v)[N], int wbase, int wstride, int rbase,
+                                int rstride) {
+  float t[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) ex[wbase + j * wstride] = v[j].x;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < N; ++j) t[j] = ex[rbase + j * rstride];
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < N; ++j) ex[wbase + j * wstride] = v[j].y;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < N; ++j) v[j] = make_float2(t[j], ex[rbase + j * rstride]);
+  __syncthreads();
+}
+
+__device__ inline unsigned short bf16_bits_f(float x) { return bf16_bits_of(x); }
+
+template <int N>
+__global__ __launch_bounds__(N * N) void fft3_reg_kernel(GridFftArgs a) {
+  constexpr int N2 = N * N, P = N + 1;
+  extern __shared__ cplx sm[];
+  float* ex = (float*)sm;                           // [N][N][P] floats
+  float2* ph = (float2*)(ex + N * N * P);           // [3][N] Bloch phase per axis
+  const int t = threadIdx.x;
+  const int I = (int)(blockIdx.x % (unsigned)a.n_ip);
+  const int qi = (int)(blockIdx.x / (unsigned)a.n_ip);
+  double qf[3];
+  q_frac(a, a.q0 + qi, qf);
+  if (t < 3 * N) {
+    const int ax = t / N, i = t % N;
+    const cplx e = cexpipi(-2.0 * qf[ax] * i / N);
+    ph[t] = make_float2((float)e.x, (float)e.y);
+  }
+  __syncthreads();
+  // load: thread (i2, i3) = t holds the i1 line
+  const cplx* src = a.data + (long long)qi * a.q_stride + (long long)I * N * N2 + t;
+  const int i2 = t / N, i3 = t % N;
+  const float2 p2 = ph[N + i2], p3 = ph[2 * N + i3];
+  const float2 p23 = make_float2(p2.x * p3.x - p2.y * p3.y, p2.x * p3.y + p2.y * p3.x);
+  float2 v[N];
+#pragma unroll
+  for (int i1 = 0; i1 < N; ++i1) {
+    const cplx d = src[(long long)i1 * N2];
+    const float2 p1 = ph[i1];
+    const float2 pp = make_float2(p1.x * p23.x - p1.y * p23.y, p1.x * p23.y + p1.y * p23.x);
+    const float dx = (float)d.x, dy = (float)d.y;
+    v[i1] = make_float2(dx * pp.x - dy * pp.y, dx * pp.y + dy * pp.x);
+  }
+  fft_reg<N>(v);                                      // along i1
+  // (k1, i2, i3) at ex[k1*N*P + i2*P + i3]; thread (k1, i2) = t takes the i3 line
+  exchange<N>(ex, v, i2 * P + i3, N * P, (t / N) * N * P + (t % N) * P, 1);
+  fft_reg<N>(v);                                      // along i3
+  // (k1, i2, k3) at ex[k1*N*P + k3*P + i2]; thread (k1, k3) = t takes the i2 line
+  exchange<N>(ex, v, (t / N) * N * P + (t % N), P, (t / N) * N * P + (t % N) * P, 1);
+  fft_reg<N>(v);                                      // along i2
+  // Coulomb factor and split store: thread (k1, k3), register k2
+  const int k1 = t / N, k3 = t % N;
+  const double coef = sqrt(4.0 * M_PI * a.volume) / ((double)N * N2);
+  const double g1 = wrap_int(k1, N) + qf[0], g3 = wrap_int(k3, N) + qf[2];
+  const float b13x = (float)(g1 * a.recip[0] + g3 * a.recip[6]);
+  const float b13y = (float)(g1 * a.recip[1] + g3 * a.recip[7]);
+  const float b13z = (float)(g1 * a.recip[2] + g3 * a.recip[8]);
+  const float b2x = (float)a.recip[3], b2y = (float)a.recip[4], b2z = (float)a.recip[5];
+  const float fq2 = (float)qf[1], fcoef = (float)coef;
+  const bool edge13 = (k1 == 0 && k3 == 0 && qf[0] == 0.0 && qf[2] == 0.0 && qf[1] == 0.0);
+  const long long row = (long long)qi * a.split_q + (long long)I * a.split_ld + (long long)k1 * N2 + k3;
+#pragma unroll
+  for (int k2 = 0; k2 < N; ++k2) {
+    const float g2 = (float)wrap_int(k2, N) + fq2;
+    const float kx = fmaf(g2, b2x, b13x), ky = fmaf(g2, b2y, b13y), kz = fmaf(g2, b2z, b13z);
+    const float k2n = kx * kx + ky * ky + kz * kz;
+    const float f = (edge13 && k2 == 0) ? 0.0f : fcoef * rsqrtf(k2n);
+    const float re = v[k2].x * f, im = v[k2].y * f;
+    const long long off = row + (long long)k2 * N;
+    if (a.fmt == 1) {
+      float* o = (float*)a.split;
+      o[off] = re;
+      o[a.split_plane + off] = im;
+    } else {
+      unsigned short* o = (unsigned short*)a.split;
+      const unsigned short rh = bf16_bits_f(re), ih = bf16_bits_f(im);
+      o[off] = rh;
+      o[a.split_plane + off] = bf16_bits_f(re - bf16_value(rh));
+      o[2 * a.split_plane + off] = ih;
+      o[3 * a.split_plane + off] = bf16_bits_f(im - bf16_value(ih));
+    }
+  }
+  // zero the row padding of the split output (grid points N^3 .. ld-1)
+  for (long long g = (long long)N * N2 + t; g < a.split_ld; g += N2)
+    store_fmt(a.split, (long long)qi * a.split_q + (long long)I * a.split_ld + g, a.split_plane, a.fmt,
+              cmk(0.0, 0.0));
+}
+
+template <int N>
+hipError_t launch_reg(const GridFftArgs& a, hipStream_t s) {
+  static_assert(N * N <= 1024 && radix_a<N>() != 0, "one-pass FFT shape");
+  const long long items = (long long)a.nq * a.n_ip;
+  if (items <= 0) return hipSuccess;
+  const size_t lds = ((size_t)N * N * (N + 1) + 6 * N) * sizeof(float);
+  hipLaunchKernelGGL(fft3_reg_kernel<N>, dim3((unsigned)items), dim3(N * N), lds, s, a);
+  return hipGetLastError();
+}
+
 template <int N>
 hipError_t launch_cubic(const GridFftArgs& a, hipStream_t s) {
   constexpr int N2 = N * N;
@@ -416,6 +617,21 @@ hipError_t launch_cubic(const GridFftArgs& a, hipStream_t s) {
 }  // namespace
 
 hipError_t gridfft_launch(const GridFftArgs& a, hipStream_t s) {
+  if (a.fmt != 0 && a.n1 == a.n2 && a.n2 == a.n3) {
+    switch (a.n1) {
+      case 6: return launch_reg<6>(a, s);
+      case 8: return launch_reg<8>(a, s);
+      case 10: return launch_reg<10>(a, s);
+      case 12: return launch_reg<12>(a, s);
+      case 16: return launch_reg<16>(a, s);
+      case 18: return launch_reg<18>(a, s);
+      case 20: return launch_reg<20>(a, s);
+      case 24: return launch_reg<24>(a, s);
+      case 30: return launch_reg<30>(a, s);
+      case 32: return launch_reg<32>(a, s);
+      default: break;
+    }
+  }
   if (a.n1 == a.n2 && a.n2 == a.n3) {
     switch (a.n1) {
       case 6: return launch_cubic<6>(a, s);

@@ -298,6 +298,7 @@ struct isdf_ctx_s {
   DevBuf dmax, cflag;                   // factorisation: largest diagonal, breakdown flags
   long long ld_ip = 0, ld_g = 0;        // row pitches of split operands (multiples of 8)
   bool fitted = false, kernel_ready = false, eta_valid = false;
+  int kernel_prec = 0;              // precision of the last isdf_coulomb_kernel
   std::vector<int> rank_h;
   long long rc = 0;   // r-chunk of the RHS
   Arena arena;
@@ -618,6 +619,7 @@ void do_kernel(isdf_ctx c, int prec) {
     c->timer.collect(&c->totals);
   }
   if (bad) throw Fail{ISDF_E_NUMERIC, "non-finite entries in W^q"};
+  c->kernel_prec = prec;
   c->kernel_ready = true;
 }
 
@@ -743,7 +745,9 @@ void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn
   }
   if (timed) ws.timer.end("frag_t", s);
   // R^q_{I,pq} = N_k^{-1/2} sum_R exp(-iq.R) conj(psi_p) psi_q   (eq. (20)),
-  // rows (pair) x I in the GEMM operand format of the precision
+  // in the GEMM operand format of the precision, pair-major: row (pair) holds
+  // the N_k blocks of ld columns (q, I), so that the contraction over (q, J)
+  // of every fragment reads one contiguous K range per row
   if (timed) ws.timer.begin("frag_pair", s);
   const long long mplane = (long long)nk * p.ptot * ld;
   {
@@ -771,8 +775,9 @@ void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn
     a.tp = tp;
     a.ti = ti;
     a.n_itiles = (int)((ld + ti - 1) / ti);
-    a.ptot = p.ptot;
     a.ld = ld;
+    a.q_stride = ld;                     // pair-major: [pair][q][I]
+    a.p_stride = (long long)nk * ld;
     a.plane = mplane;
     a.fmt = prec;
     a.m1 = c->m[0]; a.m2 = c->m[1]; a.m3 = c->m[2];
@@ -785,34 +790,46 @@ void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn
   {
     const void* wt = prec == 0 ? c->wt64.p : (prec == 1 ? c->wt32.p : c->wt16.p);
     std::vector<NtDesc> d(1);
-    d[0] = mknt(Mq, ld, wt, ld, Uq, ld, (int)p.ptot, nip, nip);
+    d[0] = mknt(Mq, (long long)nk * ld, wt, ld, Uq, (long long)nk * ld, (int)p.ptot, nip, nip);
     d[0].batch = nk;
     d[0].a_plane = mplane;
     d[0].b_plane = (long long)nk * nip * ld;
     d[0].c_plane = mplane;
-    d[0].sA_bat = d[0].sC_bat = p.ptot * ld;
+    d[0].sA_bat = d[0].sC_bat = ld;
     d[0].sB_bat = (long long)nip * ld;
     d[0].epi = prec == 0 ? 0 : 3;
+    d[0].npad = (int)ld;
     if (prec == 0) run_nt(ws.arena, prec, 0, d, s, 2);
     else run_big(ws.arena, prec, 0, d, 1, s, 2);
   }
   if (timed) ws.timer.end("frag_u", s);
   // (pq|rs) = sum_q sum_J U^q_{(pq),J} conj(R^q_{(sr),J})  (eq. (19), R^{-q}_{rs} = conj R^q_{sr}),
-  // one grouped persistent launch over all fragments, FP64 sum over q
+  // one grouped persistent launch over all fragments; FP64 path: FP64 sum
+  // over q inside the kernel; mixed: one launch per group of ERI_QGROUP
+  // consecutive q (one contiguous K range of QGROUP * ld per row, FP32 sums),
+  // FP64 sum over the groups
   if (timed) ws.timer.begin("frag_eri", s);
   {
     std::vector<NtDesc> d;
     const size_t sc = fmt_scalar(prec);
+    const int qgroup = std::min(nk, ERI_QGROUP);
     cplx* acc = (cplx*)(base + p.off_acc);
     for (size_t f = 0; f < fr.size(); ++f) {
       const int nf2 = p.nf[f] * p.nf[f];
       cplx* out = (fr[f].flags & ISDF_FRAG_DEVICE) ? (cplx*)fr[f].eri : Est + p.eoff[f];
-      const size_t o = (size_t)p.poff[f] * ld * sc;
-      NtDesc g = mknt(Uq + o, ld, Mq + o, ld, prec == 0 ? (void*)out : (void*)(acc + p.aoff[f]),
-                      prec == 0 ? 0 : nf2, nf2, nf2, nip);
+      const size_t o = (size_t)p.poff[f] * nk * ld * sc;
+      NtDesc g = mknt(Uq + o, (long long)nk * ld, Mq + o, (long long)nk * ld,
+                      prec == 0 ? (void*)out : (void*)(acc + p.aoff[f]), prec == 0 ? 0 : nf2, nf2, nf2, nip);
       g.a_plane = g.b_plane = mplane;
-      g.nseg = nk;
-      g.sA_seg = g.sB_seg = p.ptot * ld;
+      if (prec == 0) {
+        g.nseg = nk;
+        g.sA_seg = g.sB_seg = ld;
+      } else {
+        g.Kseg = (int)(qgroup * ld);
+        g.nseg = (nk + qgroup - 1) / qgroup;
+        g.Klast = (int)((nk - (long long)(g.nseg - 1) * qgroup) * ld);
+        g.sA_seg = g.sB_seg = qgroup * ld;
+      }
       if (prec == 0) {
         g.herm = 1;
         g.epi = 2;
@@ -828,11 +845,11 @@ void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn
     if (prec == 0) {
       run_nt(ws.arena, prec, 2, d, s, 3);
     } else {
-      // one launch per q: FP32 partial sums within q, FP64 sum over q in E_f
+      // one launch per q group: FP32 partial sums inside, FP64 sum over groups in E_f
       long long acount = 0;
       for (size_t f = 0; f < fr.size(); ++f) acount += (long long)p.nf[f] * p.nf[f] * p.nf[f] * p.nf[f];
       HIPCHK(zero_launch(acc, acount, s));
-      run_big(ws.arena, prec, 2, d, nk, s, 3);
+      run_big(ws.arena, prec, 2, d, d[0].nseg, s, 3);
       for (size_t f = 0; f < fr.size(); ++f) {
         cplx* out = (fr[f].flags & ISDF_FRAG_DEVICE) ? (cplx*)fr[f].eri : Est + p.eoff[f];
         HIPCHK(eri_scatter_launch(acc + p.aoff[f], out, p.nf[f], BIG_TILE, s));
@@ -1146,6 +1163,48 @@ isdf_status isdf_get_rhs(isdf_ctx ctx, int32_t q, void* out) {
   if (q < 0 || q >= ctx->nk || !out) return fail(ctx, ISDF_E_INVALID, "bad q");
   const size_t b = (size_t)ctx->nip * ctx->ng * sizeof(cplx);
   return get_mat(ctx, ctx->eta, (long long)q * b, b, out);
+}
+
+isdf_status isdf_get_eta_tilde(isdf_ctx ctx, int32_t q, void* out) {
+  if (!ctx) return ISDF_E_INVALID;
+  if (!ctx->kernel_ready) return fail(ctx, ISDF_E_STATE, "eta~ not computed (isdf_coulomb_kernel first)");
+  if (q < 0 || q >= ctx->nk || !out) return fail(ctx, ISDF_E_INVALID, "bad q");
+  const long long nip = ctx->nip, ng = ctx->ng, ldg = ctx->ld_g;
+  if (ctx->kernel_prec == ISDF_FP64) {
+    const size_t b = (size_t)nip * ng * sizeof(cplx);
+    return get_mat(ctx, ctx->eta, (long long)q * b, b, out);
+  }
+  return guarded(ctx, [&] {
+    // the split operand of the V^q product, converted exactly to c128
+    const int planes = ctx->kernel_prec == ISDF_MIXED_FP32 ? 2 : 4;
+    const size_t sc = ctx->kernel_prec == ISDF_MIXED_FP32 ? 4 : 2;
+    const long long plane = (long long)ctx->nk * nip * ldg;
+    const size_t rows = (size_t)nip * ldg;
+    std::vector<unsigned char> h((size_t)planes * rows * sc);
+    for (int pl = 0; pl < planes; ++pl)
+      HIPCHK(hipMemcpyAsync(h.data() + pl * rows * sc,
+                            ctx->eta_split.as<char>() + ((long long)pl * plane + (long long)q * nip * ldg) * sc,
+                            rows * sc, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    auto bf = [](const unsigned short* p, size_t i) {
+      uint32_t u = (uint32_t)p[i] << 16;
+      float f;
+      memcpy(&f, &u, 4);
+      return (double)f;
+    };
+    cplx* o = (cplx*)out;
+    for (long long i = 0; i < nip; ++i)
+      for (long long g = 0; g < ng; ++g) {
+        const size_t e = (size_t)(i * ldg + g);
+        if (planes == 2) {
+          const float* f = (const float*)h.data();
+          o[i * ng + g] = cmk((double)f[e], (double)f[rows + e]);
+        } else {
+          const unsigned short* u = (const unsigned short*)h.data();
+          o[i * ng + g] = cmk(bf(u, e) + bf(u, rows + e), bf(u, 2 * rows + e) + bf(u, 3 * rows + e));
+        }
+      }
+  });
 }
 
 isdf_status isdf_fragment_eri(isdf_ctx ctx, isdf_precision prec, int32_t n_frag, const int32_t* n_f,

@@ -60,6 +60,7 @@ struct NtDesc {
   int M, N, Kseg, nseg, Klast, batch;
   int tiles_m, tiles_n, tiles_per_batch;
   int herm, epi, nf;
+  int npad;               // epi 3: columns written (zeros from N on); 0 = ldc
   long long tile_begin;
 };
 long long nt_plan(NtDesc* d, int n);
@@ -81,6 +82,9 @@ hipError_t herm_fill_launch(cplx* c, int n, long long ld, long long bat, int nba
 // E[(pq)][(sr)] with lower tiles computed (edge `tile`) -> eri[p][q][r][s]
 hipError_t eri_scatter_launch(const cplx* e, cplx* eri, int nf, int tile, hipStream_t s);
 constexpr int BIG_TILE = 128;
+// mixed-precision fragment contraction: q values summed in FP32 per launch
+// (one contiguous K range of ERI_QGROUP * ld), FP64 across launches
+constexpr int ERI_QGROUP = 8;
 
 // W^q (c128 [q][n][n]) -> transposed copies Wt[q][J][I] = W[q][I][J] with row
 // pitch ld in c128, two-float-plane and four-bf16-plane formats (any output
@@ -113,11 +117,11 @@ hipError_t kconv_launch(const KconvArgs& a, hipStream_t s);
 struct PairBlock { int frag; int pair0; int npair; };
 struct PairArgs {
   const cplx* psi;         // [N_R][ncol][n_ip]
-  void* out;               // [N_q][ptot][ld] (per plane)
+  void* out;               // element (q, pair, I) at q*q_stride + pair*p_stride + I (per plane)
   const PairBlock* blocks; // device
   const int* frag_nf; const int* frag_col; const long long* frag_pair;  // device
   int nblocks, n_ip, ncol, tp, ti, n_itiles;
-  long long ptot, ld, plane;
+  long long ld, plane, q_stride, p_stride;
   int fmt;
   int m1, m2, m3;
   double scale;

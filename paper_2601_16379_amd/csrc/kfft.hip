@@ -214,7 +214,7 @@ __global__ __launch_bounds__(256) void pair_kernel(PairArgs a) {
     const int j = e >> tshift, i = e & (a.ti - 1);
     const int I = I0 + i;
     if (j < pb.npair && I < a.ld) {
-      const long long off = ((long long)Q * a.ptot + poff + pb.pair0 + j) * a.ld + I;
+      const long long off = (long long)Q * a.q_stride + (poff + pb.pair0 + j) * a.p_stride + I;
       store_fmt(a.out, off, a.plane, a.fmt, cscale(buf[idx], a.scale));
     }
   }

@@ -26,7 +26,7 @@ ISDF_FRAG_DEVICE = 0x1
 REQ_STATES = {0: "QUEUED", 1: "RUNNING", 2: "DONE", 3: "FAILED", 4: "CANCELLED"}
 
 EXPORTS = ["isdf_create", "isdf_fit", "isdf_coulomb_kernel", "isdf_get_metric",
-           "isdf_get_kernel", "isdf_get_ivs", "isdf_get_rhs", "isdf_fragment_eri",
+           "isdf_get_kernel", "isdf_get_ivs", "isdf_get_rhs", "isdf_get_eta_tilde", "isdf_fragment_eri",
            "isdf_serve_start", "isdf_submit", "isdf_submit_n", "isdf_poll", "isdf_cancel",
            "isdf_serve_stop", "isdf_stats", "isdf_stage_ms", "isdf_stage_total", "isdf_stage_reset", "isdf_plan_bytes", "isdf_storage_model_bytes",
            "isdf_destroy", "isdf_last_error", "isdf_version"]
@@ -71,6 +71,7 @@ def load_library(path=LIB_PATH):
         "isdf_get_kernel": (I32, [P, I32, P]),
         "isdf_get_ivs": (I32, [P, I32, P]),
         "isdf_get_rhs": (I32, [P, I32, P]),
+        "isdf_get_eta_tilde": (I32, [P, I32, P]),
         "isdf_fragment_eri": (I32, [P, I32, I32, P, P, P, U32]),
         "isdf_serve_start": (I32, [P, I32, I32, I64]),
         "isdf_submit": (I32, [P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
@@ -206,6 +207,9 @@ class Isdf:
 
     def get_rhs(self, q):
         return self._get(self.lib.isdf_get_rhs, q, (self.n_ip, self.n_g))
+
+    def get_eta_tilde(self, q):
+        return self._get(self.lib.isdf_get_eta_tilde, q, (self.n_ip, self.n_g))
 
     def fragment_eri(self, coeffs, prec="fp64", out=None):
         """ERIs of a batch of fragments in one pass.  ``coeffs``: list of

@@ -207,3 +207,50 @@ def test_grid_fft_sizes_kernel_and_eri(name):
     out = ctx.fragment_eri(frags, "fp64")
     for f, cf in enumerate(frags):
         assert _rel(out[f], ko.fragment_eri(x, cf, w, cfg.kmesh)) < FP64_REL
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("name", ["t_small_k3", "t_mid_k4", "t_grid10_k1", "t_grid18_k2", "t_grid20_k3",
+                                  "t_grid36_k2"])
+def test_mixed_kernel_and_eri_within_1e6(name, prec):
+    """The mixed-precision Coulomb path (one-pass FP32 FFT on cubic grids up to
+    32^3 -- here 10, 12, 16, 18, 20 -- the two-pass FFT above that -- 36 --,
+    V^q from FP32 / bf16 hi+lo operands) through the fragment ERIs, against
+    the FP64 oracle."""
+    c = case(name)
+    cfg = c.d.cfg
+    ctx = _ctx(c.d)
+    ctx.fit()
+    ctx.coulomb_kernel(prec)
+    frags = inp.make_fragments(cfg)
+    out = ctx.fragment_eri(frags, prec)
+    worst = 0.0
+    for f, cf in enumerate(frags):
+        ref = ko.fragment_eri(c.x, cf, c.w, cfg.kmesh)
+        worst = max(worst, float(np.max(np.abs(out[f] - ref))))
+    print("%s %s kernel + ERIs max|dV| %.3e Eh" % (name, prec, worst))
+    assert worst < 1e-6
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("name", ["t_small_k2", "t_mid_k4", "t_grid10_k1", "t_grid18_k2", "t_grid20_k3",
+                                  "t_grid36_k2", "t_grid40_k1"])
+def test_eta_tilde_elementwise(name, prec):
+    """The grid-FFT stage itself (eq. (7) weighting), element by element for
+    every q: FP64 within 1e-12 of max; the mixed operands within their
+    rounding (2^-23 FP32, 2^-16 bf16 hi+lo, relative per element) plus 2e-6
+    of max for the FP32 transform of the one-pass kernel (cubic grids up to
+    32^3; 36 and 40 take the two-pass FP64 transform)."""
+    c = case(name)
+    cfg = c.d.cfg
+    ctx = _ctx(c.d)
+    ctx.fit()
+    ctx.coulomb_kernel(prec)
+    rel = {"fp64": 0.0, "fp32": 2.0 ** -23, "bf16x3": 2.0 ** -16}[prec]
+    floor = 1e-12 if prec == "fp64" else 2e-6
+    for q in range(cfg.n_k):
+        ref = ko.eta_tilde(c.eta[q], c.d.lattice, cfg.grid, cfg.kmesh, q)
+        got = ctx.get_eta_tilde(q)
+        bound = rel * np.abs(ref) + floor * np.abs(ref).max()
+        excess = float(np.max(np.abs(got - ref) - bound))
+        assert excess <= 0.0, (q, excess)

@@ -333,3 +333,26 @@ def test_covariance(small_fit):
     # sub-fragment = sub-block
     vs = ko.fragment_eri(x, c[:, :, 1:4], w, cfg.kmesh)
     assert _rel(vs, v[1:4, 1:4, 1:4, 1:4]) < 1e-12
+
+
+def test_eta_tilde_of_plane_waves_closed_form():
+    """A plane wave exp(i (G0+q).r) has the single weighted coefficient
+    sqrt(4 pi Omega)/|G0+q| at G0 (eq. (7) with c = 4 pi/|G+q|^2), and the
+    G + q = 0 term is dropped: an independent check of the phase, the FFT
+    index order, the reciprocal lattice and the weight of ``eta_tilde``."""
+    lattice = np.array([[4.0, 0.0, 0.0], [1.0, 4.5, 0.0], [0.5, 0.3, 5.0]])
+    grid, kmesh = (6, 5, 4), (2, 3, 1)
+    vol = abs(np.linalg.det(lattice))
+    frac = geo.grid_frac(grid)
+    b = geo.reciprocal(lattice)
+    g0s = np.array([(0, 0, 0), (1, -2, 1), (-3, 2, -2)])
+    for q in range(6):
+        qf = geo.q_frac_wrapped(geo.kmesh_indices(kmesh)[q], kmesh)
+        f = np.exp(2j * np.pi * (frac @ (g0s + qf).T)).T
+        et = ko.eta_tilde(f, lattice, grid, kmesh, q)
+        for i, g0 in enumerate(g0s):
+            idx = np.ravel_multi_index(tuple(np.mod(g0, grid)), grid)
+            k = np.linalg.norm((g0 + qf) @ b)
+            expect = 0.0 if k == 0.0 else np.sqrt(4.0 * np.pi * vol) / k
+            assert abs(et[i, idx] - expect) < 1e-12 * max(1.0, expect), (q, i)
+            assert np.max(np.abs(np.delete(et[i], idx))) < 1e-12, (q, i)
