@@ -26,17 +26,21 @@ __device__ void init_twiddles(cplx (*tw)[MAXM], int m1, int m2, int m3) {
 
 // Length-M DFT of lines p[j * estride], j < M, for the lines `line` owned by
 // this thread; M is a compile-time constant so the loops unroll and the
-// twiddle indices (j t mod M) are constants; twiddles live in registers.
+// twiddle indices (j t mod M) are constants; twiddles live in registers for
+// M <= 8 and are read from the LDS table (one broadcast read) above.
 template <int M>
 __device__ void axis_dft(cplx* buf, const cplx* twa, int nlines, int eshift, int ax, int m2, int m3,
                          int sign) {
-  cplx w[M];
+  constexpr int MW = M <= 8 ? M : 1;
+  cplx w[MW];
 #pragma unroll
-  for (int t = 0; t < M; ++t) {
+  for (int t = 0; t < MW; ++t) {
     w[t] = twa[t];
     if (sign < 0) w[t].y = -w[t].y;
   }
+  const double sy = sign < 0 ? -1.0 : 1.0;
   const int etile = 1 << eshift;
+#pragma unroll 1
   for (int line = threadIdx.x; line < nlines; line += blockDim.x) {
     const int e = line & (etile - 1);
     const int rest = line >> eshift;
@@ -53,7 +57,14 @@ __device__ void axis_dft(cplx* buf, const cplx* twa, int nlines, int eshift, int
     for (int t = 0; t < M; ++t) {
       cplx acc = x[0];
 #pragma unroll
-      for (int j = 1; j < M; ++j) cfma(acc, x[j], w[(j * t) % M]);
+      for (int j = 1; j < M; ++j) {
+        if constexpr (M <= 8) {
+          cfma(acc, x[j], w[(j * t) % M]);
+        } else {
+          const cplx wt = twa[(j * t) % M];
+          cfma(acc, x[j], cmk(wt.x, sy * wt.y));
+        }
+      }
       p[t * estride] = acc;
     }
   }
@@ -62,6 +73,10 @@ __device__ void axis_dft(cplx* buf, const cplx* twa, int nlines, int eshift, int
 // In-place 3-D DFT over the mesh for every element column of buf[k][etile]:
 // buf[k][e] <- sum_j exp(sign * 2 pi i sum_d j_d k_d / m_d) buf[j][e].
 // etile is a power of two; tw[ax][t] = exp(2 pi i t / m_ax).
+// MAXA: largest axis length of the mesh (4, 8 or 16): only the axis
+// transforms up to it are instantiated, which keeps the register count of
+// the kernels (and so their occupancy) set by the mesh actually used.
+template <int MAXA>
 __device__ void mesh_dft(cplx* buf, const cplx (*tw)[MAXM], int etile, int m1, int m2, int m3,
                          int sign) {
   const int eshift = __builtin_ctz(etile);
@@ -73,7 +88,7 @@ __device__ void mesh_dft(cplx* buf, const cplx (*tw)[MAXM], int etile, int m1, i
     const int nlines = (nk / m) << eshift;
     switch (m) {
 #define AXIS_CASE(M) \
-  case M: axis_dft<M>(buf, tw[ax], nlines, eshift, ax, m2, m3, sign); break;
+  case M: if constexpr (M <= MAXA) axis_dft<M>(buf, tw[ax], nlines, eshift, ax, m2, m3, sign); break;
       AXIS_CASE(2) AXIS_CASE(3) AXIS_CASE(4) AXIS_CASE(5) AXIS_CASE(6) AXIS_CASE(7) AXIS_CASE(8)
       AXIS_CASE(9) AXIS_CASE(10) AXIS_CASE(11) AXIS_CASE(12) AXIS_CASE(13) AXIS_CASE(14)
       AXIS_CASE(15) AXIS_CASE(16)
@@ -84,6 +99,7 @@ __device__ void mesh_dft(cplx* buf, const cplx (*tw)[MAXM], int etile, int m1, i
   }
 }
 
+template <int MAXA>
 __global__ __launch_bounds__(256) void kconv_kernel(KconvArgs a, int etile) {
   // blockDim.x == 256; etile a power of two
   extern __shared__ cplx buf[];
@@ -130,15 +146,15 @@ __global__ __launch_bounds__(256) void kconv_kernel(KconvArgs a, int etile) {
   __syncthreads();
   if (a.mode == 0) {
     // T^R = sum_k exp(+i k.R) T^k ;  Z^R = |T^R|^2 ;  out^q = scale * sum_R exp(+i q.R) Z^R
-    mesh_dft(buf, tw, etile, a.m1, a.m2, a.m3, +1);
+    mesh_dft<MAXA>(buf, tw, etile, a.m1, a.m2, a.m3, +1);
     for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
       cplx v = buf[idx];
       buf[idx] = cmk(v.x * v.x + v.y * v.y, 0.0);
     }
     __syncthreads();
-    mesh_dft(buf, tw, etile, a.m1, a.m2, a.m3, +1);
+    mesh_dft<MAXA>(buf, tw, etile, a.m1, a.m2, a.m3, +1);
   } else {
-    mesh_dft(buf, tw, etile, a.m1, a.m2, a.m3, a.sign);
+    mesh_dft<MAXA>(buf, tw, etile, a.m1, a.m2, a.m3, a.sign);
   }
   for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
     const int q = idx >> eshift, e = idx & (etile - 1);
@@ -158,6 +174,7 @@ __global__ __launch_bounds__(256) void kconv_kernel(KconvArgs a, int etile) {
 // One workgroup: a tile of `tp` pairs of one fragment times `ti` consecutive
 // interpolation points; LDS holds [R][tp*ti] so that the output rows (pair,
 // I-range) are written as contiguous runs of I.
+template <int MAXA>
 __global__ __launch_bounds__(256) void pair_kernel(PairArgs a) {
   extern __shared__ cplx buf[];
   __shared__ cplx tw[3][MAXM];
@@ -208,7 +225,7 @@ __global__ __launch_bounds__(256) void pair_kernel(PairArgs a) {
     }
   }
   __syncthreads();
-  mesh_dft(buf, tw, w, a.m1, a.m2, a.m3, -1);
+  mesh_dft<MAXA>(buf, tw, w, a.m1, a.m2, a.m3, -1);
   for (int idx = threadIdx.x; idx < nk * w; idx += blockDim.x) {
     const int Q = idx >> wshift, e = idx & (w - 1);
     const int j = e >> tshift, i = e & (a.ti - 1);
@@ -231,7 +248,10 @@ hipError_t kconv_launch(const KconvArgs& a, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
   const size_t lds = (size_t)nk * etile * sizeof(cplx);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(kconv_kernel, dim3((unsigned)blocks), dim3(256), lds, s, a, etile);
+  const int mx = std::max(a.m1, std::max(a.m2, a.m3));
+  if (mx <= 4) hipLaunchKernelGGL(kconv_kernel<4>, dim3((unsigned)blocks), dim3(256), lds, s, a, etile);
+  else if (mx <= 8) hipLaunchKernelGGL(kconv_kernel<8>, dim3((unsigned)blocks), dim3(256), lds, s, a, etile);
+  else hipLaunchKernelGGL(kconv_kernel<16>, dim3((unsigned)blocks), dim3(256), lds, s, a, etile);
   return hipGetLastError();
 }
 
@@ -242,6 +262,9 @@ hipError_t pair_launch(const PairArgs& a, hipStream_t s) {
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   const long long blocks = (long long)a.nblocks * a.n_itiles;
   if (blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(pair_kernel, dim3((unsigned)blocks), dim3(256), lds, s, a);
+  const int mx = std::max(a.m1, std::max(a.m2, a.m3));
+  if (mx <= 4) hipLaunchKernelGGL(pair_kernel<4>, dim3((unsigned)blocks), dim3(256), lds, s, a);
+  else if (mx <= 8) hipLaunchKernelGGL(pair_kernel<8>, dim3((unsigned)blocks), dim3(256), lds, s, a);
+  else hipLaunchKernelGGL(pair_kernel<16>, dim3((unsigned)blocks), dim3(256), lds, s, a);
   return hipGetLastError();
 }
