@@ -68,10 +68,10 @@ def stage_work(stage, cfg, nfs, prec):
         return "hbm", 2.0 * nk * nip * nip * 16 / 1e9, "GB", PEAK["hbm"]
     if stage == "frag_pair":  # write R^q once (c128)
         return "hbm", nk * nip * s2 * 16 / 1e9, "GB", PEAK["hbm"]
-    if stage == "chol":
-        return "fp64", 8.0 * nk * nip ** 3 / 3 / 1e12, "TFLOP", PEAK["fp64"]
-    if stage == "w_solve":    # four triangular solves with N_IP right-hand sides
-        return "fp64", 4 * 8.0 * nk * nip ** 3 / 2 / 1e12, "TFLOP", PEAK["fp64"]
+    if stage == "chol":       # factor (n^3/3), L^{-1} (n^3/6), G = Y^H Y lower half (n^3/2) complex MACs
+        return "fp64", 8.0 * nk * nip ** 3 / 1e12, "TFLOP", PEAK["fp64"]
+    if stage == "w_solve":    # W' = (G V') G: two full complex products
+        return "fp64", 2 * 8.0 * nk * nip ** 3 / 1e12, "TFLOP", PEAK["fp64"]
     if stage == "metric_t":
         return "mfma", 8.0 * nk * nip * nip * norb / 2 / 1e12, "TFLOP", PEAK["fp64"]
     if stage == "frag_t":

@@ -465,3 +465,87 @@ hipError_t bchol_panel_launch(cplx* a, cplx* lt, const int* flag, int n, int nq,
   hipLaunchKernelGGL(bchol_panel_kernel, dim3((rows + 63) / 64, nq), dim3(64), 0, s, a, lt, flag, n, jb);
   return hipGetLastError();
 }
+
+// ---------------------------------------------------------------------------
+// Blocked inverse of the Cholesky factor, Y = L^{-1}, for all q at once:
+// 64-row diagonal blocks inverted in LDS, the off-diagonal block rows by two
+// FP64 MFMA products each (Y_ij = -Y_ii sum_{j<=k<i} L_ik Y_kj).  Rows and
+// columns at or beyond the rank are zero throughout.
+// ---------------------------------------------------------------------------
+namespace {
+
+// lrow[q][i][j] = L[i][j] (j <= i < rank, else 0) from lt[q][j][i] = L[i][j],
+// 32 x 32 tiles transposed through LDS; yt[q] cleared.
+__global__ __launch_bounds__(256) void tri_setup_kernel(const cplx* __restrict__ lt, const int* __restrict__ rank,
+                                                        cplx* lrow, cplx* yt, int n) {
+  __shared__ cplx t[32][33];
+  const int q = blockIdx.z;
+  const int r = rank[q];
+  const int i0 = blockIdx.y * 32, j0 = blockIdx.x * 32;
+  const long long nn = (long long)n * n;
+  const cplx* L = lt + q * nn;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int k = ty; k < 32; k += 8) {
+    const int j = j0 + k, i = i0 + tx;
+    t[k][tx] = (j < n && i < n) ? L[(long long)j * n + i] : cmk(0.0, 0.0);   // L[i][j]
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int i = i0 + k, j = j0 + tx;
+    if (i < n && j < n) {
+      const long long o = q * nn + (long long)i * n + j;
+      lrow[o] = (i < r && j <= i) ? t[tx][k] : cmk(0.0, 0.0);
+      yt[o] = cmk(0.0, 0.0);
+    }
+  }
+}
+
+// Diagonal block at jb: Y_bb = L_bb^{-1} by forward substitution, one thread
+// per column, the block in LDS.  Written transposed into yt
+// (yt[jb+c][jb+i] = Y_bb[i][c]) and row-major into yd[q] (64 x 64).
+__global__ __launch_bounds__(64) void tri_inv_diag_kernel(const cplx* __restrict__ lrow,
+                                                          const int* __restrict__ rank, cplx* yt,
+                                                          cplx* yd, int n, int jb) {
+  __shared__ cplx Ls[64][65];
+  __shared__ cplx Ys[64][65];
+  const int q = blockIdx.x;
+  const long long nn = (long long)n * n;
+  const int nb = (n - jb) < 64 ? (n - jb) : 64;
+  int rb = rank[q] - jb;
+  rb = rb < 0 ? 0 : (rb > nb ? nb : rb);
+  const int c = threadIdx.x;
+  for (int i = 0; i < 64; ++i)
+    Ls[i][c] = (i < nb && c < nb) ? lrow[q * nn + (long long)(jb + i) * n + jb + c] : cmk(0.0, 0.0);
+  __syncthreads();
+  for (int i = 0; i < 64; ++i) {
+    cplx s = cmk(i == c ? 1.0 : 0.0, 0.0);
+    for (int k = c; k < i; ++k) {
+      const cplx l = Ls[i][k], y = Ys[k][c];
+      s.x -= l.x * y.x - l.y * y.y;
+      s.y -= l.x * y.y + l.y * y.x;
+    }
+    Ys[i][c] = (i < rb && c < rb && i >= c) ? cscale(s, 1.0 / Ls[i][i].x) : cmk(0.0, 0.0);
+  }
+  __syncthreads();
+  for (int i = 0; i < 64; ++i) {
+    yd[(long long)q * 4096 + i * 64 + c] = Ys[i][c];
+    if (i < nb && c < nb) yt[q * nn + (long long)(jb + c) * n + jb + i] = Ys[i][c];
+  }
+}
+
+}  // namespace
+
+hipError_t tri_setup_launch(const cplx* lt, const int* rank, cplx* lrow, cplx* yt, int n, int nq,
+                            hipStream_t s) {
+  if (nq <= 0) return hipSuccess;
+  const int nt = (n + 31) / 32;
+  hipLaunchKernelGGL(tri_setup_kernel, dim3(nt, nt, nq), dim3(256), 0, s, lt, rank, lrow, yt, n);
+  return hipGetLastError();
+}
+
+hipError_t tri_inv_diag_launch(const cplx* lrow, const int* rank, cplx* yt, cplx* yd, int n, int nq, int jb,
+                               hipStream_t s) {
+  if (nq <= 0) return hipSuccess;
+  hipLaunchKernelGGL(tri_inv_diag_kernel, dim3(nq), dim3(64), 0, s, lrow, rank, yt, yd, n, jb);
+  return hipGetLastError();
+}

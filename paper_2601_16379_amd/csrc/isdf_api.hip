@@ -485,6 +485,49 @@ void do_fit(isdf_ctx c) {
       HIPCHK(chol_launch(c->pi.as<cplx>(), A, c->lt.as<cplx>(), c->perm.as<int>(), c->rank.as<int>(),
                          nip, (int)qs.size(), rtol, (c->flags & ISDF_NO_PIVOT) ? 0 : 1, c->aux, ql));
     }
+    // the pseudo-inverse factor of eq. (8), still on the second stream:
+    // Y = L^{-1} by 64-row block rows (zero outside the rank block; stored
+    // transposed in A), G = Y^H Y, so that P^T Pi^+ P = G on the rank block.
+    // Scratch: the row-major factor in work3 (overwritten by G at the end),
+    // the block-row partials St [n][64] and diagonal inverses in work1.
+    {
+      cplx* Lrow = c->work3.as<cplx>();
+      cplx* St = c->work1.as<cplx>();
+      cplx* Yd = St + (long long)nk * nip * 64;
+      const long long nn = nip2(c);
+      HIPCHK(tri_setup_launch(c->lt.as<cplx>(), c->rank.as<int>(), Lrow, A, nip, nk, c->aux));
+      for (int jb = 0; jb < nip; jb += 64) {
+        const int nb = std::min(64, nip - jb);
+        if (jb > 0) {
+          // St[n][m] = sum_{k < jb} Yt[n][k] L[jb+m][k]
+          std::vector<NtDesc> g(1);
+          g[0] = mknt(A, nip, Lrow + (long long)jb * nip, nip, St, 64, jb, nb, jb);
+          g[0].batch = nk;
+          g[0].sA_bat = g[0].sB_bat = nn;
+          g[0].sC_bat = (long long)nip * 64;
+          run_nt(c->arena, 0, 0, g, c->aux);
+        }
+        HIPCHK(tri_inv_diag_launch(Lrow, c->rank.as<int>(), A, Yd, nip, nk, jb, c->aux));
+        if (jb > 0) {
+          // Yt[n][jb+m] = Y[jb+m][n] = -sum_k St[n][k] Y_bb[m][k]
+          std::vector<NtDesc> g(1);
+          g[0] = mknt(St, 64, Yd, 64, A + jb, nip, jb, nb, nb);
+          g[0].batch = nk;
+          g[0].sA_bat = (long long)nip * 64;
+          g[0].sB_bat = 4096;
+          g[0].sC_bat = nn;
+          g[0].epi = 4;
+          run_nt(c->arena, 0, 0, g, c->aux);
+        }
+      }
+    }
+    std::vector<NtDesc> d(1);
+    d[0] = mknt(A, nip, A, nip, c->work3.as<cplx>(), nip, nip, nip, nip);
+    d[0].batch = nk;
+    d[0].sA_bat = d[0].sB_bat = d[0].sC_bat = nip2(c);
+    d[0].herm = 1;
+    // G[m][n] = sum_i conj(Yt[m][i]) Yt[n][i]
+    run_nt(c->arena, 0, 1, d, c->aux);
   }
   c->timer.end("chol", c->aux);
   HIPCHK(hipEventRecord(c->ev_join, c->aux));
@@ -577,13 +620,12 @@ void do_kernel(isdf_ctx c, int prec) {
   }
   c->timer.end("v_gemm", s);
   // W^q = Pi^{q+} V^q Pi^{q+}   (eq. (8)) in FP64 through the pivoted factor
-  // P^T Pi P = L L^H of rank r:  G = L^{-H} L^{-1},  W' = G (P^T V P) G,
-  // W = P W' P^T (zero outside the rank block).  The inverse of L is a
-  // column-parallel forward substitution; the three products are FP64 MFMA.
+  // P^T Pi P = L L^H of rank r:  G = L^{-H} L^{-1} (formed by isdf_fit),
+  // W' = G (P^T V P) G, W = P W' P^T (zero outside the rank block); the two
+  // products are FP64 MFMA.
   c->timer.begin("w_solve", s);
   {
     const long long n2 = nip2(c);
-    HIPCHK(linv_launch(c->lt.as<cplx>(), c->rank.as<int>(), c->work2.as<cplx>(), nip, nk, s));
     HIPCHK(permute_launch(c->work1.as<cplx>(), c->w.as<cplx>(), c->perm.as<int>(), c->rank.as<int>(),
                           nip, nk, 0, s));
     auto prod = [&](const cplx* A, const cplx* B, cplx* C, int conj, int herm) {
@@ -596,8 +638,6 @@ void do_kernel(isdf_ctx c, int prec) {
       }
       run_nt(c->arena, 0, conj, d, s);
     };
-    // G[m][n] = sum_i conj(Yt[m][i]) Yt[n][i]
-    prod(c->work2.as<cplx>(), c->work2.as<cplx>(), c->work3.as<cplx>(), 1, 1);
     // T1 = G V'  (V' Hermitian: V'[k][n] = conj(V'[n][k]))
     prod(c->work3.as<cplx>(), c->w.as<cplx>(), c->work1.as<cplx>(), 2, 0);
     // W' = T1 G  (G Hermitian)
@@ -989,7 +1029,10 @@ int64_t isdf_plan_bytes(const int32_t grid[3], const int32_t kmesh[3], int32_t n
   long long b = 0;
   b += nk * n_orb * ng * e;              // orbitals
   b += nk * n_orb * n_ip * e;            // X
-  b += 5 * nk * (long long)n_ip * n_ip * e;  // Pi, L, W, two work buffers
+  b += 6 * nk * (long long)n_ip * n_ip * e;  // Pi, L, W, three work buffers
+  b += std::max(0LL, nk * ((long long)n_ip * 64 + 4096 - (long long)n_ip * n_ip) * e);  // L^{-1} scratch
+  const long long ld = (n_ip + 7) / 8 * 8;
+  b += nk * (long long)n_ip * ld * (16 + 8 + 8);  // W^T in the three operand formats
   b += nk * (long long)n_ip * ng * e;    // eta
   b += nk * (long long)n_ip * rchunk_len(ng, (int)nk, n_ip) * e;  // RHS tile
   b += n_ip * 4 + 2 * nk * (long long)n_ip * 4;
@@ -1070,7 +1113,8 @@ isdf_status isdf_create(isdf_ctx* out, const double* lattice, const int32_t grid
     c->pi.alloc(m2);
     c->lt.alloc(m2);
     c->w.alloc(m2);
-    c->work1.alloc(m2);
+    // work1 also holds the block-row scratch of the blocked L^{-1}
+    c->work1.alloc(std::max(m2, (size_t)nk * ((size_t)n_ip * 64 + 4096) * e));
     c->work2.alloc(m2);
     c->work3.alloc(m2);
     c->eta.alloc((size_t)nk * n_ip * ng * e);

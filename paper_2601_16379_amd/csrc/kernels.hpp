@@ -175,6 +175,14 @@ hipError_t wsolve_launch(const cplx* v, cplx* z, cplx* w, const cplx* lt, const 
 // yt[q][c][i] = (L^{-1})[i][c] for the leading rank x rank block (transposed
 // inverse of the factor); zeros for i < c.
 hipError_t linv_launch(const cplx* lt, const int* rank, cplx* yt, int n, int nq, hipStream_t s);
+// Blocked L^{-1} pieces: setup writes the row-major factor lrow (zero outside
+// the rank block) and clears yt; diag inverts the 64 x 64 diagonal block at
+// jb into yt (transposed) and yd[q] (row-major 64 x 64).  The off-diagonal
+// block rows are two NT GEMMs per block row.
+hipError_t tri_setup_launch(const cplx* lt, const int* rank, cplx* lrow, cplx* yt, int n, int nq,
+                            hipStream_t s);
+hipError_t tri_inv_diag_launch(const cplx* lrow, const int* rank, cplx* yt, cplx* yd, int n, int nq, int jb,
+                               hipStream_t s);
 // dir 0: out[q][i][j] = in[q][perm[i]][perm[j]] (i, j < rank);
 // dir 1: out[q][perm[i]][perm[j]] = in[q][i][j], zero outside the rank block.
 hipError_t permute_launch(const cplx* in, cplx* out, const int* perm, const int* rank, int n, int nq,
