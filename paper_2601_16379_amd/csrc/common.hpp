@@ -33,14 +33,29 @@ __device__ inline cplx cexpipi(double x) {
 
 static inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
 
-// Store one complex value in one of the operand formats of the NT GEMM:
-// 0 complex128 at element off; 1 float planes re|im; 2 bf16 planes
-// re_hi|re_lo|im_hi|im_lo (x = hi + lo), element off of each plane.
+// Store one complex value in one of the operand formats of the NT GEMMs:
+//   0  complex128 at element off;
+//   1  float planes re | im, element off of each plane (plane stride `plane`);
+//   2  bf16 hi + lo (x = hi + lo per real component), interleaved by groups
+//      of 8 elements: element off at u16 index bf16x3_index(off, p) with
+//      p = 0 re_hi, 1 re_lo, 2 im_hi, 3 im_lo, so that the 16 k of one
+//      matrix-core step of a row are 128 contiguous bytes (rows start at
+//      multiples of 8 elements; `plane` is not used).
 __device__ inline unsigned short bf16_bits_of(float x) {
   __bf16 h = (__bf16)x;
   return __builtin_bit_cast(unsigned short, h);
 }
 __device__ inline float bf16_value(unsigned short b) { return (float)__builtin_bit_cast(__bf16, b); }
+__host__ __device__ inline long long bf16x3_index(long long off, int p) { return (off >> 3) * 32 + p * 8 + (off & 7); }
+
+__device__ inline void store_bf16x3(unsigned short* o, long long off, float re, float im) {
+  const unsigned short rh = bf16_bits_of(re), ih = bf16_bits_of(im);
+  const long long b = (off >> 3) * 32 + (off & 7);
+  o[b] = rh;
+  o[b + 8] = bf16_bits_of(re - bf16_value(rh));
+  o[b + 16] = ih;
+  o[b + 24] = bf16_bits_of(im - bf16_value(ih));
+}
 
 __device__ inline void store_fmt(void* out, long long off, long long plane, int fmt, cplx v) {
   if (fmt == 0) {
@@ -50,12 +65,6 @@ __device__ inline void store_fmt(void* out, long long off, long long plane, int 
     o[off] = (float)v.x;
     o[plane + off] = (float)v.y;
   } else {
-    unsigned short* o = (unsigned short*)out;
-    const float fr = (float)v.x, fi = (float)v.y;
-    const unsigned short rh = bf16_bits_of(fr), ih = bf16_bits_of(fi);
-    o[off] = rh;
-    o[plane + off] = bf16_bits_of(fr - bf16_value(rh));
-    o[2 * plane + off] = ih;
-    o[3 * plane + off] = bf16_bits_of(fi - bf16_value(ih));
+    store_bf16x3((unsigned short*)out, off, (float)v.x, (float)v.y);
   }
 }

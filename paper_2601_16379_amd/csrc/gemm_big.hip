@@ -337,12 +337,12 @@ long long big_plan(NtDesc* d, int n) {
 hipError_t big_launch(int prec, int conj, const NtDesc* descs_dev, int ndesc, long long total,
                       int max_blocks, int seg, hipStream_t s, int kind) {
   if (total <= 0) return hipSuccess;
-  if (prec != 1 && prec != 2) return hipErrorInvalidValue;
+  // FP32 operands only; bf16 hi+lo operands go through x3_launch
+  if (prec != 1) return hipErrorInvalidValue;
   const long long t8 = (total + 7) / 8 * 8;
   max_blocks = max_blocks / 8 * 8;
   const int blocks = (int)(t8 < max_blocks ? t8 : max_blocks);
-  if (prec == 1) return launch_big_kind<1>(kind, conj, descs_dev, ndesc, total, blocks, seg, s);
-  return launch_big_kind<2>(kind, conj, descs_dev, ndesc, total, blocks, seg, s);
+  return launch_big_kind<1>(kind, conj, descs_dev, ndesc, total, blocks, seg, s);
 }
 
 hipError_t herm_fill_launch(cplx* c, int n, long long ld, long long bat, int nbat, int tile, hipStream_t s) {

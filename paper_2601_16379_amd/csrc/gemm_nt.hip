@@ -433,7 +433,8 @@ hipError_t nt_launch(int prec, int conj, const NtDesc* descs_dev, int ndesc, lon
   const long long t8 = (total + 7) / 8 * 8;
   max_blocks = max_blocks / 8 * 8;
   const int blocks = (int)(t8 < max_blocks ? t8 : max_blocks);
+  // FP64 and FP32 operands; bf16 hi+lo operands go through x3_launch
   if (prec == 0) return launch_kind<0>(kind, conj, descs_dev, ndesc, total, blocks, s);
   if (prec == 1) return launch_kind<1>(kind, conj, descs_dev, ndesc, total, blocks, s);
-  return launch_kind<2>(kind, conj, descs_dev, ndesc, total, blocks, s);
+  return hipErrorInvalidValue;
 }

@@ -1,0 +1,312 @@
+// Complex "NT" GEMM on bf16 hi+lo operands (the bf16x3 precision) with the
+// 32x32x16 bf16 matrix cores of gfx950:
+//
+//   C[m][n] (+)= sum_k opA(A_seg[m][k]) opB(B_seg[n][k])
+//
+// x = hi + lo per real component; every real product keeps hi*hi + hi*lo +
+// lo*hi (three bf16 MFMAs, FP32 accumulation), and a complex product is four
+// real ones, so one 32x32 complex block costs 12 MFMAs per 16 k.
+//
+// Workgroup: 256 threads (4 waves, 2 x 2), 128 x 128 output tile, each wave
+// 64 x 64 (2 x 2 blocks of 32 x 32).  K advances in stages of 16 (one MFMA
+// step).  In the operand format (bf16 hi/lo interleaved by 8-element groups)
+// the 16 k of one row are 128 contiguous bytes, so a stage of a 128-row
+// operand tile is 128 whole cache lines; it is copied from global memory
+// straight into LDS (global_load_lds_dwordx4, no register staging) into a
+// ring of four LDS buffers, three stages ahead of the one being multiplied,
+// one barrier per stage.  The fragments of the next stage are read from LDS
+// while the MFMAs of the current one run.  In LDS a row keeps its eight
+// 16-byte slots (2 k-groups x 4 planes) in an order XOR-permuted by the row,
+// so that the 32x32 fragment reads (lane -> row l%32, k-group l/32) hit
+// distinct banks.
+//
+// Rows beyond M / N are loaded from the last valid row (their outputs are
+// dropped); 16-byte vectors that start beyond the segment length are copied
+// from a zero block.  One K segment per launch; epilogues as in the
+// 128-tile FP32 kernel (split store, FP64 accumulation across launches).
+#include "kernels.hpp"
+
+namespace {
+
+typedef float f16v __attribute__((ext_vector_type(16)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) void lds_void;
+typedef __attribute__((address_space(1))) void glb_void;
+
+constexpr int XT = 128;               // tile edge
+constexpr int XK = 16;                // k per stage
+constexpr int NBUF = 4;               // LDS ring of stages
+constexpr int XNT = 256;              // threads
+constexpr int ROW_B = XK * 8;          // bytes of one row of one stage (128)
+constexpr int OPER_B = XT * ROW_B;     // one operand tile of a stage (16 KB)
+constexpr int STAGE_B = 2 * OPER_B;    // A and B (32 KB)
+constexpr int NCOPY = 4;               // copy instructions per wave per operand and stage
+
+// LDS position of 16-byte slot `slot` (k-group * 4 + plane) of a row
+__device__ inline int lds_slot(int row, int slot) { return slot ^ ((row ^ (row >> 3)) & 7); }
+
+__device__ inline bf8 as_bf8(u4 v) { return __builtin_bit_cast(bf8, v); }
+
+__device__ inline int isqrt_floor(long long x) {
+  long long r = (long long)sqrt((double)x);
+  while (r * r > x) --r;
+  while ((r + 1) * (r + 1) <= x) ++r;
+  return (int)r;
+}
+
+// Vectors that start at or past the end of the K segment are copied from
+// this zero block instead, so that LDS holds zeros there.
+__device__ __attribute__((aligned(16))) unsigned short kZeroVec[8];
+
+// Issue the copies of one operand's stage (128 rows x 128 bytes) into LDS at
+// `dst`: 16 wave-instructions of 8 rows, 4 per wave.  rowoff[j]: logical
+// element offset of the (clamped) row handled by this lane in the wave's
+// j-th instruction; gslot[j]: the 16-byte slot of that row this lane fetches
+// (the one whose LDS position is this lane's).
+__device__ inline void stage_copy(const unsigned short* base, const long long (&rowoff)[NCOPY],
+                                  const int (&gslot)[NCOPY], int k0, int kcur, char* dst, int wave) {
+#pragma unroll
+  for (int j = 0; j < NCOPY; ++j) {
+    const int rc = wave + 4 * j;          // rows rc*8 .. rc*8+7
+    const int kg = k0 + 8 * (gslot[j] >> 2);
+    const unsigned short* g =
+        kg < kcur ? base + 4 * (rowoff[j] + k0) + 8 * gslot[j] : kZeroVec;
+    __builtin_amdgcn_global_load_lds((glb_void*)g, (lds_void*)(dst + rc * 8 * ROW_B), 16, 0, 0);
+  }
+}
+
+// Fragments of one stage for this lane: A rows of the wave's two 32-row
+// blocks, B rows of its two 32-column blocks, four planes each (16 bytes =
+// 8 k of the lane's k-half).
+struct Frag {
+  u4 a[2][4], b[2][4];
+};
+
+__device__ inline void read_frags(const char* buf, Frag& f, int wm, int wn, int lr, int lk) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int row = wm * 64 + i * 32 + lr;
+    const char* p = buf + row * ROW_B;
+#pragma unroll
+    for (int pl = 0; pl < 4; ++pl) f.a[i][pl] = *(const u4*)(p + (lds_slot(row, 4 * lk + pl) << 4));
+  }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int row = wn * 64 + j * 32 + lr;
+    const char* p = buf + OPER_B + row * ROW_B;
+#pragma unroll
+    for (int pl = 0; pl < 4; ++pl) f.b[j][pl] = *(const u4*)(p + (lds_slot(row, 4 * lk + pl) << 4));
+  }
+}
+
+__device__ inline u4 neg_bf(u4 v) {
+  return u4{v.x ^ 0x80008000u, v.y ^ 0x80008000u, v.z ^ 0x80008000u, v.w ^ 0x80008000u};
+}
+
+// 12 MFMAs per (i, j) block pair: re += a_r b_r - a_i b_i, im += a_r b_i + a_i b_r,
+// each real product as hi*hi + hi*lo + lo*hi; conjugation flips the sign of
+// the imaginary planes of that operand.
+template <bool A_CONJ, bool B_CONJ>
+__device__ inline void mma_stage(const Frag& f, f16v (&c_re)[2][2], f16v (&c_im)[2][2]) {
+  bf8 arh[2], arl[2], aih[2], ail[2], anih[2], anil[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const u4 ih = A_CONJ ? neg_bf(f.a[i][2]) : f.a[i][2];
+    const u4 il = A_CONJ ? neg_bf(f.a[i][3]) : f.a[i][3];
+    arh[i] = as_bf8(f.a[i][0]);
+    arl[i] = as_bf8(f.a[i][1]);
+    aih[i] = as_bf8(ih);
+    ail[i] = as_bf8(il);
+    anih[i] = as_bf8(neg_bf(ih));
+    anil[i] = as_bf8(neg_bf(il));
+  }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const u4 ih = B_CONJ ? neg_bf(f.b[j][2]) : f.b[j][2];
+    const u4 il = B_CONJ ? neg_bf(f.b[j][3]) : f.b[j][3];
+    const bf8 brh = as_bf8(f.b[j][0]), brl = as_bf8(f.b[j][1]), bih = as_bf8(ih), bil = as_bf8(il);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      f16v cr = c_re[i][j], ci = c_im[i][j];
+      cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arl[i], brh, cr, 0, 0, 0);
+      ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arl[i], bih, ci, 0, 0, 0);
+      cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh[i], brl, cr, 0, 0, 0);
+      ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh[i], bil, ci, 0, 0, 0);
+      cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(anil[i], bih, cr, 0, 0, 0);
+      ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ail[i], brh, ci, 0, 0, 0);
+      cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(anih[i], bil, cr, 0, 0, 0);
+      ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih[i], brl, ci, 0, 0, 0);
+      cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh[i], brh, cr, 0, 0, 0);
+      ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh[i], bih, ci, 0, 0, 0);
+      cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(anih[i], bih, cr, 0, 0, 0);
+      ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih[i], brh, ci, 0, 0, 0);
+      c_re[i][j] = cr;
+      c_im[i][j] = ci;
+    }
+  }
+}
+
+template <bool A_CONJ, bool B_CONJ, int KIND>
+__global__ __launch_bounds__(XNT) void zgemm_x3_kernel(const NtDesc* __restrict__ descs, int ndesc,
+                                                       long long total_tiles, int seg) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];   // NBUF stages x (A, B)
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lr = lane & 31, lk = lane >> 5;
+
+  const long long t8 = (total_tiles + 7) / 8 * 8;
+  const long long per = t8 / 8;
+  for (long long it = blockIdx.x; it < t8; it += gridDim.x) {
+    const long long t = (it % 8) * per + it / 8;   // XCD-contiguous tile ranges
+    if (t >= total_tiles) continue;
+    int lo = 0, hi = ndesc - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (descs[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
+    }
+    const NtDesc d = descs[lo];
+    const long long local = t - d.tile_begin;
+    const int b = (int)(local / d.tiles_per_batch);
+    const int lt = (int)(local - (long long)b * d.tiles_per_batch);
+    int tm, tn;
+    if (d.herm) {
+      tm = (isqrt_floor(8LL * lt + 1) - 1) / 2;
+      tn = lt - tm * (tm + 1) / 2;
+    } else {
+      tm = lt / d.tiles_n;
+      tn = lt - tm * d.tiles_n;
+    }
+    const int m0 = tm * XT, n0 = tn * XT;
+    // interleaved bf16 hi/lo: logical element e at u16 4*e (e a multiple of 8)
+    const unsigned short* As = (const unsigned short*)d.A + 4 * (b * d.sA_bat + (long long)seg * d.sA_seg);
+    const unsigned short* Bs = (const unsigned short*)d.B + 4 * (b * d.sB_bat + (long long)seg * d.sB_seg);
+    const int kcur = (seg == d.nseg - 1) ? d.Klast : d.Kseg;
+
+    // this lane's rows and slots in its copy instructions
+    long long aoff[NCOPY], boff[NCOPY];
+    int gslot[NCOPY];
+#pragma unroll
+    for (int j = 0; j < NCOPY; ++j) {
+      const int row = (wave + 4 * j) * 8 + (lane >> 3);
+      gslot[j] = lds_slot(row, lane & 7);     // the slot whose LDS position is lane & 7
+      const int ra = min(m0 + row, d.M - 1), rb = min(n0 + row, d.N - 1);
+      aoff[j] = (long long)ra * d.lda;
+      boff[j] = (long long)rb * d.ldb;
+    }
+
+    f16v c_re[2][2], c_im[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          c_re[i][j][v] = 0.f;
+          c_im[i][j][v] = 0.f;
+        }
+
+    // stages of 16 k, rounded up to an even count (the extra one is all zeros)
+    const int nst = (((kcur + XK - 1) / XK) + 1) & ~1;
+    __syncthreads();                      // LDS of the previous tile no longer read
+#pragma unroll
+    for (int s = 0; s < NBUF - 1; ++s)
+      if (s < nst) {
+        stage_copy(As, aoff, gslot, s * XK, kcur, smem + s * STAGE_B, wave);
+        stage_copy(Bs, boff, gslot, s * XK, kcur, smem + s * STAGE_B + OPER_B, wave);
+      }
+    // stage 0 landed when at most the copies of stages 1 and 2 are in flight
+    if (nst > 2) asm volatile("s_waitcnt vmcnt(16)" ::: "memory");
+    else asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    Frag f0, f1;
+    read_frags(smem, f0, wm, wn, lr, lk);
+    // Stage s: make stage s+1 visible, start its copy three stages ahead and
+    // its fragment reads, then the MFMAs of stage s on the fragments read
+    // during the previous stage, so the LDS latency hides behind them.
+#define X3_STEP(S, CUR, NXT)                                                                        \
+  {                                                                                                \
+    const int s_ = (S);                                                                            \
+    /* CUR's fragment reads (issued a stage ago) are done: wait here, before   */                   \
+    /* NXT's reads are queued behind them (lgkmcnt(0), other counters free)    */                   \
+    __builtin_amdgcn_s_waitcnt(0xC07F);                                                            \
+    if (s_ + 1 < nst) {                                                                            \
+      if (s_ + 2 < nst) asm volatile("s_waitcnt vmcnt(8)" ::: "memory");                          \
+      else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");                                       \
+      __builtin_amdgcn_s_barrier();                                                                \
+      asm volatile("" ::: "memory");                                                               \
+      if (s_ + NBUF - 1 < nst) {                                                                   \
+        char* dst = smem + ((s_ + NBUF - 1) % NBUF) * STAGE_B;                                     \
+        stage_copy(As, aoff, gslot, (s_ + NBUF - 1) * XK, kcur, dst, wave);              \
+        stage_copy(Bs, boff, gslot, (s_ + NBUF - 1) * XK, kcur, dst + OPER_B, wave);     \
+      }                                                                                            \
+      read_frags(smem + ((s_ + 1) % NBUF) * STAGE_B, NXT, wm, wn, lr, lk);                         \
+    }                                                                                              \
+    mma_stage<A_CONJ, B_CONJ>(CUR, c_re, c_im);                                                    \
+  }
+    for (int s = 0; s < nst; s += 2) {
+      X3_STEP(s, f0, f1)
+      X3_STEP(s + 1, f1, f0)
+    }
+#undef X3_STEP
+
+    // ---- epilogue (32x32 layout: lane l, register v -> row 8(v/4) + 4(l/32) + v%4, column l%32) ----
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int m = m0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * lk + (v & 3);
+          const int n = n0 + wn * 64 + j * 32 + lr;
+          if (m >= d.M) continue;
+          const float vr = c_re[i][j][v], vi = c_im[i][j][v];
+          const long long o = (long long)b * d.sC_bat + (long long)m * d.ldc + n;
+          if (d.epi == 3) {
+            if (n >= (d.npad ? d.npad : d.ldc)) continue;
+            const bool in = n < d.N;
+            store_fmt(d.C, o, d.c_plane, 2, cmk(in ? vr : 0.0, in ? vi : 0.0));
+          } else {
+            if (n >= d.N) continue;
+            cplx* cp = (cplx*)d.C + o;
+            cplx x = *cp;                 // FP64 accumulation across launches
+            x.x += (double)vr;
+            x.y += (double)vi;
+            *cp = x;
+          }
+        }
+  }
+}
+
+template <int KIND>
+hipError_t launch_x3(int conj, const NtDesc* descs, int ndesc, long long total, int blocks, int seg,
+                     hipStream_t s) {
+  dim3 g(blocks), b(XNT);
+  const size_t lds = NBUF * STAGE_B;
+  switch (conj & 3) {
+    case 0: hipLaunchKernelGGL((zgemm_x3_kernel<false, false, KIND>), g, b, lds, s, descs, ndesc, total, seg); break;
+    case 1: hipLaunchKernelGGL((zgemm_x3_kernel<true, false, KIND>), g, b, lds, s, descs, ndesc, total, seg); break;
+    case 2: hipLaunchKernelGGL((zgemm_x3_kernel<false, true, KIND>), g, b, lds, s, descs, ndesc, total, seg); break;
+    default: hipLaunchKernelGGL((zgemm_x3_kernel<true, true, KIND>), g, b, lds, s, descs, ndesc, total, seg); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t x3_launch(int conj, const NtDesc* descs_dev, int ndesc, long long total, int max_blocks, int seg,
+                     hipStream_t s, int kind) {
+  if (total <= 0) return hipSuccess;
+  const long long t8 = (total + 7) / 8 * 8;
+  max_blocks = max_blocks / 8 * 8;
+  const int blocks = (int)(t8 < max_blocks ? t8 : max_blocks);
+  switch (kind) {
+    case 1: return launch_x3<1>(conj, descs_dev, ndesc, total, blocks, seg, s);
+    case 2: return launch_x3<2>(conj, descs_dev, ndesc, total, blocks, seg, s);
+    case 3: return launch_x3<3>(conj, descs_dev, ndesc, total, blocks, seg, s);
+    default: return launch_x3<0>(conj, descs_dev, ndesc, total, blocks, seg, s);
+  }
+}

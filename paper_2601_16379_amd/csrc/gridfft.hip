@@ -503,8 +503,6 @@ __device__ inline void exchange(float* ex, float2 (&v)[N], int wbase, int wstrid
   __syncthreads();
 }
 
-__device__ inline unsigned short bf16_bits_f(float x) { return bf16_bits_of(x); }
-
 template <int N>
 __global__ __launch_bounds__(N * N) void fft3_reg_kernel(GridFftArgs a) {
   constexpr int N2 = N * N, P = N + 1;
@@ -567,12 +565,7 @@ __global__ __launch_bounds__(N * N) void fft3_reg_kernel(GridFftArgs a) {
       o[off] = re;
       o[a.split_plane + off] = im;
     } else {
-      unsigned short* o = (unsigned short*)a.split;
-      const unsigned short rh = bf16_bits_f(re), ih = bf16_bits_f(im);
-      o[off] = rh;
-      o[a.split_plane + off] = bf16_bits_f(re - bf16_value(rh));
-      o[2 * a.split_plane + off] = ih;
-      o[3 * a.split_plane + off] = bf16_bits_f(im - bf16_value(ih));
+      store_bf16x3((unsigned short*)a.split, off, re, im);
     }
   }
   // zero the row padding of the split output (grid points N^3 .. ld-1)

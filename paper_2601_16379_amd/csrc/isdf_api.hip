@@ -148,7 +148,8 @@ void run_big(Arena& ar, int prec, int conj, std::vector<NtDesc>& d, int nseg, hi
   if (total == 0) return;
   NtDesc* dd = ar.put(d.data(), d.size(), s);
   for (int seg = 0; seg < nseg; ++seg)
-    HIPCHK(big_launch(prec, conj, dd, (int)d.size(), total, max_gemm_blocks(), seg, s, kind));
+    HIPCHK(prec == 2 ? x3_launch(conj, dd, (int)d.size(), total, max_gemm_blocks(), seg, s, kind)
+                     : big_launch(prec, conj, dd, (int)d.size(), total, max_gemm_blocks(), seg, s, kind));
 }
 
 NtDesc mknt(const void* A, long long lda, const void* B, long long ldb, void* C, long long ldc,
@@ -172,7 +173,9 @@ NtDesc mknt(const void* A, long long lda, const void* B, long long ldb, void* C,
 
 // bytes per complex element of the GEMM operand format of a precision
 size_t fmt_bytes(int prec) { return prec == 0 ? 16 : 8; }
-size_t fmt_scalar(int prec) { return prec == 0 ? 16 : (prec == 1 ? 4 : 2); }
+// bytes between consecutive elements of one row as addressed by pointers:
+// c128, one FP32 plane (planes separate), bf16 hi/lo interleaved (8 bytes)
+size_t fmt_scalar(int prec) { return prec == 0 ? 16 : (prec == 1 ? 4 : 8); }
 
 GemmDesc mkdesc(const cplx* A, long long lda, const cplx* B, long long ldb, cplx* C, long long ldc,
                 int M, int N, int K) {
@@ -296,7 +299,7 @@ struct isdf_ctx_s {
   DevBuf phi, ip, xt, pi, eta, lt, w, work1, work2, work3, perm, rank, rchunk, flag;
   DevBuf wt64, wt32, wt16, eta_split;   // W transposed in the three GEMM formats; split eta~
   DevBuf dmax, cflag;                   // factorisation: largest diagonal, breakdown flags
-  long long ld_ip = 0, ld_g = 0;        // row pitches of split operands (multiples of 8)
+  long long ld_ip = 0, ld_g = 0;        // row pitches of split operands (multiples of 16)
   bool fitted = false, kernel_ready = false, eta_valid = false;
   int kernel_prec = 0;              // precision of the last isdf_coulomb_kernel
   std::vector<int> rank_h;
@@ -678,8 +681,8 @@ struct BatchPlan {
 // Layout of one fragment batch in its workspace:
 //   C_all [N_k][n_orb][ncol] c128          coefficients of all fragments
 //   Tf    [N_k][ncol][N_IP] c128           T^k_{Ip} = sum_mu X C, then psi(r_I + R)
-//   M     [N_q][ptot][ld_ip] (format)      R^q_{I,pq}, rows = pairs of all fragments
-//   U     [N_q][ptot][ld_ip] (format)      U^q = R^q W^q (also stages host C first)
+//   M     [ptot][N_q][ld_ip] (format)      R^q_{I,pq}, rows = pairs of all fragments
+//   U     [ptot][N_q][ld_ip] (format)      U^q = R^q W^q (also stages host C first)
 //   E     host-bound ERI outputs (c128)
 BatchPlan plan_batch(isdf_ctx c, const std::vector<FragIn>& fr, int prec) {
   BatchPlan p;
@@ -1118,8 +1121,10 @@ isdf_status isdf_create(isdf_ctx* out, const double* lattice, const int32_t grid
     c->work2.alloc(m2);
     c->work3.alloc(m2);
     c->eta.alloc((size_t)nk * n_ip * ng * e);
-    c->ld_ip = (n_ip + 7) / 8 * 8;
-    c->ld_g = (ng + 7) / 8 * 8;
+    // row pitches of the split operands: multiples of 16 elements, so that in
+    // the bf16 hi/lo format every 16-k step of a row is one aligned 128-byte line
+    c->ld_ip = (n_ip + 15) / 16 * 16;
+    c->ld_g = (ng + 15) / 16 * 16;
     c->wt64.alloc((size_t)nk * n_ip * c->ld_ip * e);
     c->wt32.alloc((size_t)nk * n_ip * c->ld_ip * 8);
     c->wt16.alloc((size_t)nk * n_ip * c->ld_ip * 8);
@@ -1220,15 +1225,20 @@ isdf_status isdf_get_eta_tilde(isdf_ctx ctx, int32_t q, void* out) {
   }
   return guarded(ctx, [&] {
     // the split operand of the V^q product, converted exactly to c128
-    const int planes = ctx->kernel_prec == ISDF_MIXED_FP32 ? 2 : 4;
-    const size_t sc = ctx->kernel_prec == ISDF_MIXED_FP32 ? 4 : 2;
+    // (FP32: two planes; bf16x3: hi/lo interleaved by groups of 8 elements)
+    const bool f32 = ctx->kernel_prec == ISDF_MIXED_FP32;
     const long long plane = (long long)ctx->nk * nip * ldg;
     const size_t rows = (size_t)nip * ldg;
-    std::vector<unsigned char> h((size_t)planes * rows * sc);
-    for (int pl = 0; pl < planes; ++pl)
-      HIPCHK(hipMemcpyAsync(h.data() + pl * rows * sc,
-                            ctx->eta_split.as<char>() + ((long long)pl * plane + (long long)q * nip * ldg) * sc,
-                            rows * sc, hipMemcpyDeviceToHost, ctx->stream));
+    std::vector<unsigned char> h(rows * 8);
+    if (f32) {
+      for (int pl = 0; pl < 2; ++pl)
+        HIPCHK(hipMemcpyAsync(h.data() + pl * rows * 4,
+                              ctx->eta_split.as<char>() + ((long long)pl * plane + (long long)q * nip * ldg) * 4,
+                              rows * 4, hipMemcpyDeviceToHost, ctx->stream));
+    } else {
+      HIPCHK(hipMemcpyAsync(h.data(), ctx->eta_split.as<char>() + (long long)q * nip * ldg * 8, rows * 8,
+                            hipMemcpyDeviceToHost, ctx->stream));
+    }
     HIPCHK(hipStreamSynchronize(ctx->stream));
     auto bf = [](const unsigned short* p, size_t i) {
       uint32_t u = (uint32_t)p[i] << 16;
@@ -1239,13 +1249,14 @@ isdf_status isdf_get_eta_tilde(isdf_ctx ctx, int32_t q, void* out) {
     cplx* o = (cplx*)out;
     for (long long i = 0; i < nip; ++i)
       for (long long g = 0; g < ng; ++g) {
-        const size_t e = (size_t)(i * ldg + g);
-        if (planes == 2) {
+        const long long e = i * ldg + g;
+        if (f32) {
           const float* f = (const float*)h.data();
           o[i * ng + g] = cmk((double)f[e], (double)f[rows + e]);
         } else {
           const unsigned short* u = (const unsigned short*)h.data();
-          o[i * ng + g] = cmk(bf(u, e) + bf(u, rows + e), bf(u, 2 * rows + e) + bf(u, 3 * rows + e));
+          o[i * ng + g] = cmk(bf(u, bf16x3_index(e, 0)) + bf(u, bf16x3_index(e, 1)),
+                              bf(u, bf16x3_index(e, 2)) + bf(u, bf16x3_index(e, 3)));
         }
       }
   });

@@ -81,6 +81,11 @@ hipError_t big_launch(int prec, int conj, const NtDesc* descs_dev, int ndesc, lo
 hipError_t herm_fill_launch(cplx* c, int n, long long ld, long long bat, int nbat, int tile, hipStream_t s);
 // E[(pq)][(sr)] with lower tiles computed (edge `tile`) -> eri[p][q][r][s]
 hipError_t eri_scatter_launch(const cplx* e, cplx* eri, int nf, int tile, hipStream_t s);
+// bf16x3 NT GEMM on the 32x32x16 matrix cores (128 x 128 tiles, 256
+// threads, direct-to-LDS operand copies): same descriptors and epilogues as
+// big_launch for precision 2; plan with big_plan.
+hipError_t x3_launch(int conj, const NtDesc* descs_dev, int ndesc, long long total, int max_blocks, int seg,
+                     hipStream_t s, int kind);
 constexpr int BIG_TILE = 128;
 // mixed-precision fragment contraction: q values summed in FP32 per launch
 // (one contiguous K range of ERI_QGROUP * ld), FP64 across launches
