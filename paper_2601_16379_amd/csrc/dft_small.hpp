@@ -1,0 +1,111 @@
+// Small DFTs with compile-time lengths, kept in registers (unit-cell grid
+// FFT and k-mesh transforms).  Forward transforms: y[k] = sum_j x[j] exp(-2 pi i jk/R).
+#pragma once
+#include "common.hpp"
+
+namespace {
+
+template <int R> struct Rot;
+// cos and sin of 2 pi t / R (closed forms where they exist), t = 0..R-1
+template <> struct Rot<2> {
+  static constexpr double c[2] = {1.0, -1.0};
+  static constexpr double s[2] = {0.0, 0.0};
+};
+template <> struct Rot<3> {
+  static constexpr double c[3] = {1.0, -0.5, -0.5};
+  static constexpr double s[3] = {0.0, 0.8660254037844386, -0.8660254037844386};
+};
+template <> struct Rot<4> {
+  static constexpr double c[4] = {1.0, 0.0, -1.0, 0.0};
+  static constexpr double s[4] = {0.0, 1.0, 0.0, -1.0};
+};
+template <> struct Rot<5> {
+  static constexpr double c[5] = {1.0, 0.30901699437494745, -0.8090169943749475, -0.8090169943749475, 0.30901699437494745};
+  static constexpr double s[5] = {0.0, 0.9510565162951535, 0.5877852522924731, -0.5877852522924731, -0.9510565162951535};
+};
+template <> struct Rot<6> {
+  static constexpr double c[6] = {1.0, 0.5, -0.5, -1.0, -0.5, 0.5};
+  static constexpr double s[6] = {0.0, 0.8660254037844386, 0.8660254037844386, 0.0, -0.8660254037844386, -0.8660254037844386};
+};
+template <> struct Rot<7> {
+  static constexpr double c[7] = {1.0, 0.6234898018587336, -0.22252093395631434, -0.900968867902419, -0.900968867902419, -0.22252093395631434, 0.6234898018587336};
+  static constexpr double s[7] = {0.0, 0.7818314824680298, 0.9749279121818236, 0.43388373911755823, -0.43388373911755823, -0.9749279121818236, -0.7818314824680298};
+};
+template <> struct Rot<8> {
+  static constexpr double c[8] = {1.0, 0.7071067811865476, 0.0, -0.7071067811865476, -1.0, -0.7071067811865476, 0.0, 0.7071067811865476};
+  static constexpr double s[8] = {0.0, 0.7071067811865476, 1.0, 0.7071067811865476, 0.0, -0.7071067811865476, -1.0, -0.7071067811865476};
+};
+
+
+// y[k] = sum_j x[j] exp(-2 pi i j k / R), compile-time R <= 8
+template <int R>
+__device__ inline void small_dft(const cplx (&x)[R], cplx (&y)[R]) {
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    double re = x[0].x, im = x[0].y;
+#pragma unroll
+    for (int j = 1; j < R; ++j) {
+      const double c = Rot<R>::c[(j * k) % R], sn = Rot<R>::s[(j * k) % R];
+      re = fma(x[j].x, c, fma(x[j].y, sn, re));
+      im = fma(x[j].y, c, fma(-x[j].x, sn, im));
+    }
+    y[k] = cmk(re, im);
+  }
+}
+
+constexpr double kPiD = 3.141592653589793;
+constexpr double series_cos(double x) {
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 24; ++k) {
+    term *= -x * x / ((2.0 * k - 1.0) * (2.0 * k));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double series_sin(double x) {
+  double term = x, sum = x;
+  for (int k = 1; k < 24; ++k) {
+    term *= -x * x / ((2.0 * k) * (2.0 * k + 1.0));
+    sum += term;
+  }
+  return sum;
+}
+// cos and sin of 2 pi t / N, t = 0..N-1 (Taylor series at |x| <= pi)
+template <int N> struct TwF {
+  float c[N], s[N];
+  constexpr TwF() : c(), s() {
+    for (int t = 0; t < N; ++t) {
+      double x = 2.0 * kPiD * t / N;
+      if (x > kPiD) x -= 2.0 * kPiD;
+      c[t] = (float)series_cos(x);
+      s[t] = (float)series_sin(x);
+    }
+  }
+};
+
+// a * (c - i s) with compile-time c, s (the trivial factors fold away)
+__device__ inline float2 rot_f(float2 a, float c, float s) {
+  if (c == 1.0f && s == 0.0f) return a;
+  if (c == 0.0f && s == 1.0f) return make_float2(a.y, -a.x);
+  if (c == -1.0f && s == 0.0f) return make_float2(-a.x, -a.y);
+  if (c == 0.0f && s == -1.0f) return make_float2(-a.y, a.x);
+  return make_float2(fmaf(a.x, c, a.y * s), fmaf(a.y, c, -a.x * s));
+}
+
+template <int R>
+__device__ inline void small_dft_f(const float2 (&x)[R], float2 (&y)[R]) {
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    float2 acc = x[0];
+#pragma unroll
+    for (int j = 1; j < R; ++j) {
+      const float2 t = rot_f(x[j], (float)Rot<R>::c[(j * k) % R], (float)Rot<R>::s[(j * k) % R]);
+      acc.x += t.x;
+      acc.y += t.y;
+    }
+    y[k] = acc;
+  }
+}
+
+
+}  // namespace

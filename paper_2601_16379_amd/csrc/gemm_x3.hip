@@ -48,6 +48,14 @@ __device__ inline int lds_slot(int row, int slot) { return slot ^ ((row ^ (row >
 
 __device__ inline bf8 as_bf8(u4 v) { return __builtin_bit_cast(bf8, v); }
 
+// wait until at most n stages of copies (2 * NCOPY instructions each) are in flight
+__device__ inline void wait_copies(int n) {
+  if (n >= 3) asm volatile("s_waitcnt vmcnt(24)" ::: "memory");
+  else if (n == 2) asm volatile("s_waitcnt vmcnt(16)" ::: "memory");
+  else if (n == 1) asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
+  else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+
 __device__ inline int isqrt_floor(long long x) {
   long long r = (long long)sqrt((double)x);
   while (r * r > x) --r;
@@ -83,7 +91,7 @@ struct Frag {
   u4 a[2][4], b[2][4];
 };
 
-__device__ inline void read_frags(const char* buf, Frag& f, int wm, int wn, int lr, int lk) {
+__device__ inline void read_frags_a(const char* buf, Frag& f, int wm, int lr, int lk) {
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
     const int row = wm * 64 + i * 32 + lr;
@@ -91,6 +99,8 @@ __device__ inline void read_frags(const char* buf, Frag& f, int wm, int wn, int 
 #pragma unroll
     for (int pl = 0; pl < 4; ++pl) f.a[i][pl] = *(const u4*)(p + (lds_slot(row, 4 * lk + pl) << 4));
   }
+}
+__device__ inline void read_frags_b(const char* buf, Frag& f, int wn, int lr, int lk) {
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
     const int row = wn * 64 + j * 32 + lr;
@@ -98,6 +108,16 @@ __device__ inline void read_frags(const char* buf, Frag& f, int wm, int wn, int 
 #pragma unroll
     for (int pl = 0; pl < 4; ++pl) f.b[j][pl] = *(const u4*)(p + (lds_slot(row, 4 * lk + pl) << 4));
   }
+}
+
+// Pin a stage's fragments: their reads must have completed here, and later
+// uses do not depend on the loads any more (so the compiler does not place
+// its wait for them after the next stage's reads have been queued).
+__device__ inline void settle(Frag& f) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int p = 0; p < 4; ++p) asm volatile("" : "+v"(f.a[i][p]), "+v"(f.b[i][p]));
 }
 
 __device__ inline u4 neg_bf(u4 v) {
@@ -108,42 +128,31 @@ __device__ inline u4 neg_bf(u4 v) {
 // each real product as hi*hi + hi*lo + lo*hi; conjugation flips the sign of
 // the imaginary planes of that operand.
 template <bool A_CONJ, bool B_CONJ>
-__device__ inline void mma_stage(const Frag& f, f16v (&c_re)[2][2], f16v (&c_im)[2][2]) {
-  bf8 arh[2], arl[2], aih[2], ail[2], anih[2], anil[2];
+__device__ inline void mma_half(const Frag& f, int j, f16v (&c_re)[2][2], f16v (&c_im)[2][2]) {
+  const u4 bi = B_CONJ ? neg_bf(f.b[j][2]) : f.b[j][2];
+  const u4 bl = B_CONJ ? neg_bf(f.b[j][3]) : f.b[j][3];
+  const bf8 brh = as_bf8(f.b[j][0]), brl = as_bf8(f.b[j][1]), bih = as_bf8(bi), bil = as_bf8(bl);
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
     const u4 ih = A_CONJ ? neg_bf(f.a[i][2]) : f.a[i][2];
     const u4 il = A_CONJ ? neg_bf(f.a[i][3]) : f.a[i][3];
-    arh[i] = as_bf8(f.a[i][0]);
-    arl[i] = as_bf8(f.a[i][1]);
-    aih[i] = as_bf8(ih);
-    ail[i] = as_bf8(il);
-    anih[i] = as_bf8(neg_bf(ih));
-    anil[i] = as_bf8(neg_bf(il));
-  }
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const u4 ih = B_CONJ ? neg_bf(f.b[j][2]) : f.b[j][2];
-    const u4 il = B_CONJ ? neg_bf(f.b[j][3]) : f.b[j][3];
-    const bf8 brh = as_bf8(f.b[j][0]), brl = as_bf8(f.b[j][1]), bih = as_bf8(ih), bil = as_bf8(il);
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      f16v cr = c_re[i][j], ci = c_im[i][j];
-      cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arl[i], brh, cr, 0, 0, 0);
-      ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arl[i], bih, ci, 0, 0, 0);
-      cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh[i], brl, cr, 0, 0, 0);
-      ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh[i], bil, ci, 0, 0, 0);
-      cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(anil[i], bih, cr, 0, 0, 0);
-      ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ail[i], brh, ci, 0, 0, 0);
-      cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(anih[i], bil, cr, 0, 0, 0);
-      ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih[i], brl, ci, 0, 0, 0);
-      cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh[i], brh, cr, 0, 0, 0);
-      ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh[i], bih, ci, 0, 0, 0);
-      cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(anih[i], bih, cr, 0, 0, 0);
-      ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih[i], brh, ci, 0, 0, 0);
-      c_re[i][j] = cr;
-      c_im[i][j] = ci;
-    }
+    const bf8 arh = as_bf8(f.a[i][0]), arl = as_bf8(f.a[i][1]), aih = as_bf8(ih), ail = as_bf8(il);
+    const bf8 anih = as_bf8(neg_bf(ih)), anil = as_bf8(neg_bf(il));
+    f16v cr = c_re[i][j], ci = c_im[i][j];
+    cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arl, brh, cr, 0, 0, 0);
+    ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arl, bih, ci, 0, 0, 0);
+    cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, brl, cr, 0, 0, 0);
+    ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, bil, ci, 0, 0, 0);
+    cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(anil, bih, cr, 0, 0, 0);
+    ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ail, brh, ci, 0, 0, 0);
+    cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(anih, bil, cr, 0, 0, 0);
+    ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih, brl, ci, 0, 0, 0);
+    cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, brh, cr, 0, 0, 0);
+    ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, bih, ci, 0, 0, 0);
+    cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(anih, bih, cr, 0, 0, 0);
+    ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih, brh, ci, 0, 0, 0);
+    c_re[i][j] = cr;
+    c_im[i][j] = ci;
   }
 }
 
@@ -217,25 +226,26 @@ __global__ __launch_bounds__(XNT) void zgemm_x3_kernel(const NtDesc* __restrict_
         stage_copy(As, aoff, gslot, s * XK, kcur, smem + s * STAGE_B, wave);
         stage_copy(Bs, boff, gslot, s * XK, kcur, smem + s * STAGE_B + OPER_B, wave);
       }
-    // stage 0 landed when at most the copies of stages 1 and 2 are in flight
-    if (nst > 2) asm volatile("s_waitcnt vmcnt(16)" ::: "memory");
-    else asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
+    // stage 0 landed when at most the copies of the later prologue stages are in flight
+    wait_copies(min(NBUF - 2, nst - 1));
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
     Frag f0, f1;
-    read_frags(smem, f0, wm, wn, lr, lk);
-    // Stage s: make stage s+1 visible, start its copy three stages ahead and
-    // its fragment reads, then the MFMAs of stage s on the fragments read
-    // during the previous stage, so the LDS latency hides behind them.
+    read_frags_a(smem, f0, wm, lr, lk);
+    read_frags_b(smem, f0, wn, lr, lk);
+    // Stage s: make stage s+1 visible, start the copy NBUF-1 stages ahead,
+    // then the MFMAs of stage s (fragments read during the previous stage)
+    // in two halves, each behind half of the fragment reads of stage s+1, so
+    // the LDS latency hides behind them.
 #define X3_STEP(S, CUR, NXT)                                                                        \
   {                                                                                                \
     const int s_ = (S);                                                                            \
-    /* CUR's fragment reads (issued a stage ago) are done: wait here, before   */                   \
-    /* NXT's reads are queued behind them (lgkmcnt(0), other counters free)    */                   \
-    __builtin_amdgcn_s_waitcnt(0xC07F);                                                            \
+    /* CUR's fragment reads (issued a stage ago) complete here, before NXT's  */                    \
+    /* reads are queued behind them; nothing is scheduled across this point    */                   \
+    __builtin_amdgcn_sched_barrier(0);                                                             \
+    settle(CUR);                                                                                   \
     if (s_ + 1 < nst) {                                                                            \
-      if (s_ + 2 < nst) asm volatile("s_waitcnt vmcnt(8)" ::: "memory");                          \
-      else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");                                       \
+      wait_copies(min(NBUF - 3, nst - s_ - 2));  /* stage s+1 landed */                           \
       __builtin_amdgcn_s_barrier();                                                                \
       asm volatile("" ::: "memory");                                                               \
       if (s_ + NBUF - 1 < nst) {                                                                   \
@@ -243,9 +253,11 @@ __global__ __launch_bounds__(XNT) void zgemm_x3_kernel(const NtDesc* __restrict_
         stage_copy(As, aoff, gslot, (s_ + NBUF - 1) * XK, kcur, dst, wave);              \
         stage_copy(Bs, boff, gslot, (s_ + NBUF - 1) * XK, kcur, dst + OPER_B, wave);     \
       }                                                                                            \
-      read_frags(smem + ((s_ + 1) % NBUF) * STAGE_B, NXT, wm, wn, lr, lk);                         \
+      read_frags_a(smem + ((s_ + 1) % NBUF) * STAGE_B, NXT, wm, lr, lk);                           \
     }                                                                                              \
-    mma_stage<A_CONJ, B_CONJ>(CUR, c_re, c_im);                                                    \
+    mma_half<A_CONJ, B_CONJ>(CUR, 0, c_re, c_im);                                                  \
+    if (s_ + 1 < nst) read_frags_b(smem + ((s_ + 1) % NBUF) * STAGE_B, NXT, wn, lr, lk);           \
+    mma_half<A_CONJ, B_CONJ>(CUR, 1, c_re, c_im);                                                  \
   }
     for (int s = 0; s < nst; s += 2) {
       X3_STEP(s, f0, f1)
@@ -254,30 +266,56 @@ __global__ __launch_bounds__(XNT) void zgemm_x3_kernel(const NtDesc* __restrict_
 #undef X3_STEP
 
     // ---- epilogue (32x32 layout: lane l, register v -> row 8(v/4) + 4(l/32) + v%4, column l%32) ----
+    if (d.epi == 3) {
+      // split store: each wave assembles its 64 x 64 block in LDS in the
+      // operand format (a row of 64 is 512 contiguous bytes) and writes it
+      // with 16-byte stores, two rows per instruction
+      __syncthreads();                    // every wave is past its last stage reads
+      unsigned short* st = (unsigned short*)(smem + wave * 32768);
+      const int npad = d.npad ? d.npad : (int)d.ldc;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < 2; ++j)
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          const int m = m0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * lk + (v & 3);
-          const int n = n0 + wn * 64 + j * 32 + lr;
-          if (m >= d.M) continue;
-          const float vr = c_re[i][j][v], vi = c_im[i][j][v];
-          const long long o = (long long)b * d.sC_bat + (long long)m * d.ldc + n;
-          if (d.epi == 3) {
-            if (n >= (d.npad ? d.npad : d.ldc)) continue;
-            const bool in = n < d.N;
-            store_fmt(d.C, o, d.c_plane, 2, cmk(in ? vr : 0.0, in ? vi : 0.0));
-          } else {
-            if (n >= d.N) continue;
-            cplx* cp = (cplx*)d.C + o;
+          for (int v = 0; v < 16; ++v) {
+            const int ml = i * 32 + 8 * (v >> 2) + 4 * lk + (v & 3);
+            const int nl = j * 32 + lr;
+            const bool in = n0 + wn * 64 + nl < d.N;
+            const float re = in ? c_re[i][j][v] : 0.f, im = in ? c_im[i][j][v] : 0.f;
+            const unsigned short rh = bf16_bits_of(re), ih = bf16_bits_of(im);
+            unsigned short* e = st + ml * 256 + (nl >> 3) * 32 + (nl & 7);
+            e[0] = rh;
+            e[8] = bf16_bits_of(re - bf16_value(rh));
+            e[16] = ih;
+            e[24] = bf16_bits_of(im - bf16_value(ih));
+          }
+      __builtin_amdgcn_wave_barrier();
+      unsigned short* C = (unsigned short*)d.C + 4 * ((long long)b * d.sC_bat + n0 + wn * 64);
+#pragma unroll 4
+      for (int h = 0; h < 32; ++h) {
+        const int ml = 2 * h + lk, part = lane & 31;
+        const int m = m0 + wm * 64 + ml;
+        if (m < d.M && n0 + wn * 64 + (part >> 2) * 8 < npad)
+          *(u4*)(C + 4 * (long long)m * d.ldc + part * 8) = *(const u4*)(st + ml * 256 + part * 8);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            const int m = m0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * lk + (v & 3);
+            const int n = n0 + wn * 64 + j * 32 + lr;
+            if (m >= d.M || n >= d.N) continue;
+            cplx* cp = (cplx*)d.C + (long long)b * d.sC_bat + (long long)m * d.ldc + n;
             cplx x = *cp;                 // FP64 accumulation across launches
-            x.x += (double)vr;
-            x.y += (double)vi;
+            x.x += (double)c_re[i][j][v];
+            x.y += (double)c_im[i][j][v];
             *cp = x;
           }
-        }
+    }
   }
 }
 

@@ -825,6 +825,15 @@ void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn
     a.fmt = prec;
     a.m1 = c->m[0]; a.m2 = c->m[1]; a.m3 = c->m[2];
     a.scale = 1.0 / std::sqrt((double)nk);
+    if (pair_reg_supported(prec, a.m1, a.m2, a.m3)) {
+      // register path: items (fragment, 64-point I chunk, pair)
+      const long long nchunk = (ld + 63) / 64;
+      std::vector<long long> ioff(fr.size() + 1, 0);
+      for (size_t f = 0; f < fr.size(); ++f) ioff[f + 1] = ioff[f] + nchunk * p.nf[f] * p.nf[f];
+      a.item_off = ws.arena.put(ioff.data(), ioff.size(), s);
+      a.nfrag = (int)fr.size();
+      a.nitems = ioff.back();
+    }
     HIPCHK(pair_launch(a, s));
   }
   if (timed) ws.timer.end("frag_pair", s);

@@ -128,10 +128,18 @@ struct PairArgs {
   int nblocks, n_ip, ncol, tp, ti, n_itiles;
   long long ld, plane, q_stride, p_stride;
   int fmt;
+  // register path (mixed precisions, mesh axes <= 4): one wave per (pair,
+  // 64 interpolation points); items ordered (fragment, I chunk, pair),
+  // item_off[f] = first item of fragment f (nfrag + 1 entries, device)
+  const long long* item_off;
+  int nfrag;
+  long long nitems;
   int m1, m2, m3;
   double scale;
 };
 hipError_t pair_launch(const PairArgs& a, hipStream_t s);
+// true when pair_launch takes the register path (needs item_off / nitems)
+bool pair_reg_supported(int fmt, int m1, int m2, int m3);
 
 // ---------------------------------------------------------------------------
 // Unit-cell grid FFT of f_{q,I}(r) exp(-i q.r) with the Coulomb factor

@@ -8,6 +8,7 @@
 // the pointwise step, transforms back and stores: one HBM read and one HBM
 // write per element, however many mesh axes there are.
 #include "kernels.hpp"
+#include "dft_small.hpp"
 
 namespace {
 
@@ -237,6 +238,166 @@ __global__ __launch_bounds__(256) void pair_kernel(PairArgs a) {
   }
 }
 
+// ---- register path of the pair transform (mixed precisions) ----
+// 3-D forward DFT over an M1 x M2 x M3 mesh held in registers,
+// x[(j1 * M2 + j2) * M3 + j3], one axis at a time.
+template <int M1, int M2, int M3>
+__device__ inline void mesh_dft_reg(float2 (&x)[M1 * M2 * M3]) {
+  if constexpr (M3 > 1) {
+#pragma unroll
+    for (int a = 0; a < M1 * M2; ++a) {
+      float2 t[M3], y[M3];
+#pragma unroll
+      for (int j = 0; j < M3; ++j) t[j] = x[a * M3 + j];
+      small_dft_f<M3>(t, y);
+#pragma unroll
+      for (int j = 0; j < M3; ++j) x[a * M3 + j] = y[j];
+    }
+  }
+  if constexpr (M2 > 1) {
+#pragma unroll
+    for (int j1 = 0; j1 < M1; ++j1)
+#pragma unroll
+      for (int j3 = 0; j3 < M3; ++j3) {
+        float2 t[M2], y[M2];
+#pragma unroll
+        for (int j = 0; j < M2; ++j) t[j] = x[(j1 * M2 + j) * M3 + j3];
+        small_dft_f<M2>(t, y);
+#pragma unroll
+        for (int j = 0; j < M2; ++j) x[(j1 * M2 + j) * M3 + j3] = y[j];
+      }
+  }
+  if constexpr (M1 > 1) {
+#pragma unroll
+    for (int b = 0; b < M2 * M3; ++b) {
+      float2 t[M1], y[M1];
+#pragma unroll
+      for (int j = 0; j < M1; ++j) t[j] = x[j * M2 * M3 + b];
+      small_dft_f<M1>(t, y);
+#pragma unroll
+      for (int j = 0; j < M1; ++j) x[j * M2 * M3 + b] = y[j];
+    }
+  }
+}
+
+// One wave per (pair (p, q) of a fragment, 64 consecutive interpolation
+// points): lane I loads psi_p(r_I + R) and psi_q(r_I + R) for every R (each
+// load instruction reads 64 consecutive I), forms conj(psi_p) psi_q (FP64
+// product, rounded once to FP32), transforms R -> q in registers and writes
+// the N_k outputs of its I (each store instruction covers 64 consecutive I
+// of one row).  Workgroups are mapped XCD-contiguously so the psi rows of
+// one fragment and I chunk stay in one L2 while all its pairs use them.
+template <int M1, int M2, int M3>
+__global__ __launch_bounds__(256, 2) void pair_reg_kernel(PairArgs a, int nblocks) {
+  constexpr int NK = M1 * M2 * M3;
+  // output staging: per wave 8 rows (q) of 64 points in the operand format
+  __shared__ __attribute__((aligned(16))) unsigned short stage[4][8][256];
+  const int g8 = gridDim.x >> 3;
+  const int blk = (int)(blockIdx.x & 7) * g8 + (int)(blockIdx.x >> 3);
+  if (blk >= nblocks) return;
+  const long long item = (long long)blk * 4 + (threadIdx.x >> 6);
+  if (item >= a.nitems) return;                      // whole wave
+  const int lane = threadIdx.x & 63;
+  int lo = 0, hi = a.nfrag - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.item_off[mid] <= item) lo = mid; else hi = mid - 1;
+  }
+  const int f = lo;
+  const int nf = a.frag_nf[f];
+  const int nf2 = nf * nf;
+  const long long local = item - a.item_off[f];
+  const int chunk = (int)(local / nf2);
+  const int pp = (int)(local - (long long)chunk * nf2);
+  const int p = pp / nf, q = pp - (pp / nf) * nf;
+  const int I = chunk * 64 + lane;
+  const bool in = I < a.n_ip;
+  const int col = a.frag_col[f];
+  const cplx* bp = a.psi + (long long)(col + p) * a.n_ip + (in ? I : 0);
+  const cplx* bq = a.psi + (long long)(col + q) * a.n_ip + (in ? I : 0);
+  const long long rstride = (long long)a.ncol * a.n_ip;
+  float2 x[NK];
+#pragma unroll
+  for (int R = 0; R < NK; ++R) {
+    const cplx u = bp[R * rstride], v = bq[R * rstride];
+    // conj(u) v
+    const double re = u.x * v.x + u.y * v.y, im = u.x * v.y - u.y * v.x;
+    x[R] = in ? make_float2((float)re, (float)im) : make_float2(0.f, 0.f);
+  }
+  mesh_dft_reg<M1, M2, M3>(x);
+  const float sc = (float)a.scale;
+  const long long base = (a.frag_pair[f] + pp) * a.p_stride + chunk * 64;   // row start of this chunk
+  const int nI = (a.ld - chunk * 64) < 64 ? (int)(a.ld - chunk * 64) : 64;  // a multiple of 16
+  if (a.fmt == 1) {
+    if (I >= a.ld) return;
+    float* o = (float*)a.out;
+#pragma unroll
+    for (int Q = 0; Q < NK; ++Q) {
+      const long long off = base + lane + Q * a.q_stride;
+      o[off] = x[Q].x * sc;
+      o[a.plane + off] = x[Q].y * sc;
+    }
+    return;
+  }
+  // bf16 hi/lo: each row (q) of the chunk is 64 points x 8 bytes = 512
+  // contiguous bytes; rows are assembled in LDS, 8 at a time, and written
+  // with 16-byte stores (two rows per wave instruction)
+  unsigned short (*st)[256] = stage[threadIdx.x >> 6];
+  const int e = (lane >> 3) * 32 + (lane & 7);
+#pragma unroll
+  for (int Q0 = 0; Q0 < NK; Q0 += 8) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (Q0 + u >= NK) break;
+      const float re = x[Q0 + u].x * sc, im = x[Q0 + u].y * sc;
+      const unsigned short rh = bf16_bits_of(re), ih = bf16_bits_of(im);
+      st[u][e] = rh;
+      st[u][e + 8] = bf16_bits_of(re - bf16_value(rh));
+      st[u][e + 16] = ih;
+      st[u][e + 24] = bf16_bits_of(im - bf16_value(ih));
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int u = 2 * h + (lane >> 5), part = lane & 31;   // row u, 16-byte part
+      if (Q0 + u < NK && part * 2 < nI) {
+        const uint4 v = *(const uint4*)&st[u][part * 8];
+        *(uint4*)((unsigned short*)a.out + 4 * (base + (long long)(Q0 + u) * a.q_stride) + part * 8) = v;
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+template <int M1, int M2, int M3>
+hipError_t launch_pair_reg(const PairArgs& a, hipStream_t s) {
+  const long long nb = (a.nitems + 3) / 4;
+  if (nb <= 0) return hipSuccess;
+  if (nb > (1LL << 30)) return hipErrorInvalidValue;
+  const long long g = (nb + 7) / 8 * 8;
+  hipLaunchKernelGGL((pair_reg_kernel<M1, M2, M3>), dim3((unsigned)g), dim3(256), 0, s, a, (int)nb);
+  return hipGetLastError();
+}
+
+template <int M1, int M2>
+hipError_t pair_reg_m3(const PairArgs& a, hipStream_t s) {
+  switch (a.m3) {
+    case 1: return launch_pair_reg<M1, M2, 1>(a, s);
+    case 2: return launch_pair_reg<M1, M2, 2>(a, s);
+    case 3: return launch_pair_reg<M1, M2, 3>(a, s);
+    default: return launch_pair_reg<M1, M2, 4>(a, s);
+  }
+}
+template <int M1>
+hipError_t pair_reg_m2(const PairArgs& a, hipStream_t s) {
+  switch (a.m2) {
+    case 1: return pair_reg_m3<M1, 1>(a, s);
+    case 2: return pair_reg_m3<M1, 2>(a, s);
+    case 3: return pair_reg_m3<M1, 3>(a, s);
+    default: return pair_reg_m3<M1, 4>(a, s);
+  }
+}
+
 }  // namespace
 
 hipError_t kconv_launch(const KconvArgs& a, hipStream_t s) {
@@ -255,7 +416,19 @@ hipError_t kconv_launch(const KconvArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+bool pair_reg_supported(int fmt, int m1, int m2, int m3) {
+  return fmt != 0 && m1 <= 4 && m2 <= 4 && m3 <= 4;
+}
+
 hipError_t pair_launch(const PairArgs& a, hipStream_t s) {
+  if (pair_reg_supported(a.fmt, a.m1, a.m2, a.m3)) {
+    switch (a.m1) {
+      case 1: return pair_reg_m2<1>(a, s);
+      case 2: return pair_reg_m2<2>(a, s);
+      case 3: return pair_reg_m2<3>(a, s);
+      default: return pair_reg_m2<4>(a, s);
+    }
+  }
   const int nk = a.m1 * a.m2 * a.m3;
   if (a.m1 > MAXM || a.m2 > MAXM || a.m3 > MAXM) return hipErrorInvalidValue;
   const size_t lds = (size_t)nk * a.tp * a.ti * sizeof(cplx);
