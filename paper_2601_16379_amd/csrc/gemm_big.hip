@@ -313,6 +313,30 @@ __global__ void eri_scatter_kernel(const cplx* __restrict__ e, cplx* eri, int nf
   }
 }
 
+__global__ void eri_scatter_batch_kernel(const cplx* __restrict__ e, const long long* __restrict__ eoff,
+                                         cplx* const* __restrict__ eri, const int* __restrict__ nfa, int tile) {
+  const int f = blockIdx.y;
+  const int nf = nfa[f];
+  const cplx* ef = e + eoff[f];
+  cplx* out = eri[f];
+  const int n = nf * nf;
+  const long long total = (long long)n * n;
+  const long long nf2 = (long long)nf * nf;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const int m = (int)(idx / n), c = (int)(idx - (idx / n) * n);
+    cplx v;
+    if (m / tile >= c / tile) {
+      v = ef[idx];
+    } else {
+      const cplx u = ef[(long long)c * n + m];
+      v = cmk(u.x, -u.y);
+    }
+    const int s_ = c / nf, r_ = c - s_ * nf;
+    out[(long long)m * nf2 + (long long)r_ * nf + s_] = v;
+  }
+}
+
 inline unsigned grid_of(long long n) {
   long long b = (n + 255) / 256;
   return (unsigned)(b > 8192 ? 8192 : (b < 1 ? 1 : b));
@@ -354,5 +378,15 @@ hipError_t herm_fill_launch(cplx* c, int n, long long ld, long long bat, int nba
 hipError_t eri_scatter_launch(const cplx* e, cplx* eri, int nf, int tile, hipStream_t s) {
   const long long n = (long long)nf * nf;
   hipLaunchKernelGGL(eri_scatter_kernel, dim3(grid_of(n * n)), dim3(256), 0, s, e, eri, nf, tile);
+  return hipGetLastError();
+}
+
+hipError_t eri_scatter_batch_launch(const cplx* e, const long long* eoff, cplx* const* eri, const int* nf,
+                                    int n, int maxnf, int tile, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const long long m = (long long)maxnf * maxnf;
+  long long bx = (m * m + 255) / 256;
+  if (bx > 1024) bx = 1024;
+  hipLaunchKernelGGL(eri_scatter_batch_kernel, dim3((unsigned)bx, n), dim3(256), 0, s, e, eoff, eri, nf, tile);
   return hipGetLastError();
 }

@@ -50,8 +50,7 @@ __device__ inline bf8 as_bf8(u4 v) { return __builtin_bit_cast(bf8, v); }
 
 // wait until at most n stages of copies (2 * NCOPY instructions each) are in flight
 __device__ inline void wait_copies(int n) {
-  if (n >= 3) asm volatile("s_waitcnt vmcnt(24)" ::: "memory");
-  else if (n == 2) asm volatile("s_waitcnt vmcnt(16)" ::: "memory");
+  if (n >= 2) asm volatile("s_waitcnt vmcnt(16)" ::: "memory");
   else if (n == 1) asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
   else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
@@ -124,37 +123,54 @@ __device__ inline u4 neg_bf(u4 v) {
   return u4{v.x ^ 0x80008000u, v.y ^ 0x80008000u, v.z ^ 0x80008000u, v.w ^ 0x80008000u};
 }
 
-// 12 MFMAs per (i, j) block pair: re += a_r b_r - a_i b_i, im += a_r b_i + a_i b_r,
+// The 12 MFMAs of one 32x32 block pair (i, j) and one 16-k step, as six
+// (re, im) term pairs: re += a_r b_r - a_i b_i, im += a_r b_i + a_i b_r,
 // each real product as hi*hi + hi*lo + lo*hi; conjugation flips the sign of
 // the imaginary planes of that operand.
+struct BFr {
+  bf8 rh, rl, ih, il, nih, nil;
+};
+template <bool CONJ>
+__device__ inline BFr split_a(const u4 (&a)[4]) {
+  const u4 ih = CONJ ? neg_bf(a[2]) : a[2];
+  const u4 il = CONJ ? neg_bf(a[3]) : a[3];
+  return BFr{as_bf8(a[0]), as_bf8(a[1]), as_bf8(ih), as_bf8(il), as_bf8(neg_bf(ih)), as_bf8(neg_bf(il))};
+}
+#define X3_TERMS(A, BRH, BRL, BIH, BIL, CR, CI, T)                          \
+  if ((T) == 0) { CR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A.rl, BRH, CR, 0, 0, 0);  \
+                  CI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A.rl, BIH, CI, 0, 0, 0); }\
+  if ((T) == 1) { CR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A.rh, BRL, CR, 0, 0, 0);  \
+                  CI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A.rh, BIL, CI, 0, 0, 0); }\
+  if ((T) == 2) { CR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A.nil, BIH, CR, 0, 0, 0); \
+                  CI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A.il, BRH, CI, 0, 0, 0); }\
+  if ((T) == 3) { CR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A.nih, BIL, CR, 0, 0, 0); \
+                  CI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A.ih, BRL, CI, 0, 0, 0); }\
+  if ((T) == 4) { CR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A.rh, BRH, CR, 0, 0, 0);  \
+                  CI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A.rh, BIH, CI, 0, 0, 0); }\
+  if ((T) == 5) { CR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A.nih, BIH, CR, 0, 0, 0); \
+                  CI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A.ih, BRH, CI, 0, 0, 0); }
+
+// MFMAs of one stage for the wave's column block j: the four accumulator
+// chains of the two row blocks are interleaved, so a chain is used every
+// fourth MFMA.
 template <bool A_CONJ, bool B_CONJ>
 __device__ inline void mma_half(const Frag& f, int j, f16v (&c_re)[2][2], f16v (&c_im)[2][2]) {
   const u4 bi = B_CONJ ? neg_bf(f.b[j][2]) : f.b[j][2];
   const u4 bl = B_CONJ ? neg_bf(f.b[j][3]) : f.b[j][3];
   const bf8 brh = as_bf8(f.b[j][0]), brl = as_bf8(f.b[j][1]), bih = as_bf8(bi), bil = as_bf8(bl);
+  const BFr x0 = split_a<A_CONJ>(f.a[0]), x1 = split_a<A_CONJ>(f.a[1]);
+  f16v cr0 = c_re[0][j], ci0 = c_im[0][j], cr1 = c_re[1][j], ci1 = c_im[1][j];
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const u4 ih = A_CONJ ? neg_bf(f.a[i][2]) : f.a[i][2];
-    const u4 il = A_CONJ ? neg_bf(f.a[i][3]) : f.a[i][3];
-    const bf8 arh = as_bf8(f.a[i][0]), arl = as_bf8(f.a[i][1]), aih = as_bf8(ih), ail = as_bf8(il);
-    const bf8 anih = as_bf8(neg_bf(ih)), anil = as_bf8(neg_bf(il));
-    f16v cr = c_re[i][j], ci = c_im[i][j];
-    cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arl, brh, cr, 0, 0, 0);
-    ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arl, bih, ci, 0, 0, 0);
-    cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, brl, cr, 0, 0, 0);
-    ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, bil, ci, 0, 0, 0);
-    cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(anil, bih, cr, 0, 0, 0);
-    ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ail, brh, ci, 0, 0, 0);
-    cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(anih, bil, cr, 0, 0, 0);
-    ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih, brl, ci, 0, 0, 0);
-    cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, brh, cr, 0, 0, 0);
-    ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, bih, ci, 0, 0, 0);
-    cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(anih, bih, cr, 0, 0, 0);
-    ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih, brh, ci, 0, 0, 0);
-    c_re[i][j] = cr;
-    c_im[i][j] = ci;
+  for (int t = 0; t < 6; ++t) {
+    X3_TERMS(x0, brh, brl, bih, bil, cr0, ci0, t)
+    X3_TERMS(x1, brh, brl, bih, bil, cr1, ci1, t)
   }
+  c_re[0][j] = cr0;
+  c_im[0][j] = ci0;
+  c_re[1][j] = cr1;
+  c_im[1][j] = ci1;
 }
+#undef X3_TERMS
 
 template <bool A_CONJ, bool B_CONJ, int KIND>
 __global__ __launch_bounds__(XNT) void zgemm_x3_kernel(const NtDesc* __restrict__ descs, int ndesc,
@@ -162,7 +178,7 @@ __global__ __launch_bounds__(XNT) void zgemm_x3_kernel(const NtDesc* __restrict_
   extern __shared__ __attribute__((aligned(16))) char smem[];   // NBUF stages x (A, B)
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave >> 1, wn = wave & 1;
   const int lr = lane & 31, lk = lane >> 5;
 
@@ -246,12 +262,13 @@ __global__ __launch_bounds__(XNT) void zgemm_x3_kernel(const NtDesc* __restrict_
     settle(CUR);                                                                                   \
     if (s_ + 1 < nst) {                                                                            \
       wait_copies(min(NBUF - 3, nst - s_ - 2));  /* stage s+1 landed */                           \
+      /* bare s_barrier: __syncthreads() would also wait for the copies in flight */                \
       __builtin_amdgcn_s_barrier();                                                                \
       asm volatile("" ::: "memory");                                                               \
       if (s_ + NBUF - 1 < nst) {                                                                   \
         char* dst = smem + ((s_ + NBUF - 1) % NBUF) * STAGE_B;                                     \
-        stage_copy(As, aoff, gslot, (s_ + NBUF - 1) * XK, kcur, dst, wave);              \
-        stage_copy(Bs, boff, gslot, (s_ + NBUF - 1) * XK, kcur, dst + OPER_B, wave);     \
+        stage_copy(As, aoff, gslot, (s_ + NBUF - 1) * XK, kcur, dst, wave);                        \
+        stage_copy(Bs, boff, gslot, (s_ + NBUF - 1) * XK, kcur, dst + OPER_B, wave);               \
       }                                                                                            \
       read_frags_a(smem + ((s_ + 1) % NBUF) * STAGE_B, NXT, wm, lr, lk);                           \
     }                                                                                              \

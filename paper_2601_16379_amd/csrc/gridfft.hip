@@ -457,7 +457,49 @@ __global__ __launch_bounds__(N * N) void fft3_reg_kernel(GridFftArgs a) {
     const float kx = fmaf(g2, b2x, b13x), ky = fmaf(g2, b2y, b13y), kz = fmaf(g2, b2z, b13z);
     const float k2n = kx * kx + ky * ky + kz * kz;
     const float f = (edge13 && k2 == 0) ? 0.0f : fcoef * rsqrtf(k2n);
-    const float re = v[k2].x * f, im = v[k2].y * f;
+    v[k2] = make_float2(v[k2].x * f, v[k2].y * f);
+  }
+  if constexpr (N % 8 == 0 && 64 % N == 0) {
+    if (a.fmt == 2) {
+      // bf16 hi/lo: a wave holds 64/N whole rows (k1) of N points for every
+      // k2; rows of 8 k2 at a time are assembled in LDS (N * 8 contiguous
+      // bytes each) and written with 16-byte stores
+      constexpr int RW = 64 / N, CK = 8;
+      const int lane = t & 63, wv = t >> 6;
+      unsigned short* st = (unsigned short*)ex + wv * (CK * RW * N * 4);
+      const int kl = lane / N;
+      const int eo = (k3 >> 3) * 32 + (k3 & 7);
+      const long long base = (long long)qi * a.split_q + (long long)I * a.split_ld;
+#pragma unroll
+      for (int c0 = 0; c0 < N; c0 += CK) {
+#pragma unroll
+        for (int u = 0; u < CK; ++u) {
+          const float re = v[c0 + u].x, im = v[c0 + u].y;
+          const unsigned short rh = bf16_bits_of(re), ih = bf16_bits_of(im);
+          unsigned short* e = st + (u * RW + kl) * (N * 4) + eo;
+          e[0] = rh;
+          e[8] = bf16_bits_of(re - bf16_value(rh));
+          e[16] = ih;
+          e[24] = bf16_bits_of(im - bf16_value(ih));
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int h = 0; h < CK * RW * (N / 2) / 64; ++h) {
+          const int c = h * 64 + lane, r = c / (N / 2), part = c % (N / 2);
+          const int u = r / RW, k1r = wv * RW + r % RW;
+          *(uint4*)((unsigned short*)a.split + 4 * (base + (long long)k1r * N2 + (long long)(c0 + u) * N) +
+                    part * 8) = *(const uint4*)(st + r * (N * 4) + part * 8);
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+      for (long long g = (long long)N * N2 + t; g < a.split_ld; g += N2)
+        store_fmt(a.split, base + g, a.split_plane, a.fmt, cmk(0.0, 0.0));
+      return;
+    }
+  }
+#pragma unroll
+  for (int k2 = 0; k2 < N; ++k2) {
+    const float re = v[k2].x, im = v[k2].y;
     const long long off = row + (long long)k2 * N;
     if (a.fmt == 1) {
       float* o = (float*)a.split;
@@ -478,7 +520,9 @@ hipError_t launch_reg(const GridFftArgs& a, hipStream_t s) {
   static_assert(N * N <= 1024 && radix_a<N>() != 0, "one-pass FFT shape");
   const long long items = (long long)a.nq * a.n_ip;
   if (items <= 0) return hipSuccess;
-  const size_t lds = ((size_t)N * N * (N + 1) + 6 * N) * sizeof(float);
+  // transposes (N x N x (N+1) floats) + phase tables; the staged output
+  // rows of the bf16 path reuse it (N * N * 64 bytes)
+  const size_t lds = std::max(((size_t)N * N * (N + 1) + 6 * N) * sizeof(float), (size_t)N * N * 64);
   hipLaunchKernelGGL(fft3_reg_kernel<N>, dim3((unsigned)items), dim3(N * N), lds, s, a);
   return hipGetLastError();
 }

@@ -748,18 +748,23 @@ void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn
   if (host_bytes) ws.hostc.ensure(host_bytes);
   // the staged host copies land in the U region first (free until step 13)
   size_t hoff = 0;
+  std::vector<const cplx*> srcs(fr.size());
+  int maxnf = 0;
   for (size_t i = 0; i < fr.size(); ++i) {
     const FragIn& f = fr[i];
     const size_t fb = (size_t)nk * norb * f.nf * sizeof(cplx);
-    const cplx* src = (const cplx*)f.C;
+    srcs[i] = (const cplx*)f.C;
     if (!(f.flags & ISDF_FRAG_DEVICE)) {
       memcpy((char*)ws.hostc.p + hoff, f.C, fb);
       HIPCHK(hipMemcpyAsync(Uq + hoff, (char*)ws.hostc.p + hoff, fb, hipMemcpyHostToDevice, s));
-      src = (const cplx*)(Uq + hoff);
+      srcs[i] = (const cplx*)(Uq + hoff);
       hoff += fb;
     }
-    HIPCHK(copy_cols_launch(src, Call, nk, norb, f.nf, p.ncol, p.col[i], s));
+    maxnf = std::max(maxnf, f.nf);
   }
+  HIPCHK(copy_cols_batch_launch(ws.arena.put(srcs.data(), srcs.size(), s), Call, nk, norb,
+                                ws.arena.put(p.nf.data(), p.nf.size(), s),
+                                ws.arena.put(p.col.data(), p.col.size(), s), (int)fr.size(), maxnf, p.ncol, s));
   if (timed) ws.timer.begin("frag_t", s);
   // T^k_{pI} = sum_mu C^k_{mu p} X^k_{I mu}   (Algorithm 2, stored [k][p][I])
   {
@@ -902,10 +907,16 @@ void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn
       for (size_t f = 0; f < fr.size(); ++f) acount += (long long)p.nf[f] * p.nf[f] * p.nf[f] * p.nf[f];
       HIPCHK(zero_launch(acc, acount, s));
       run_big(ws.arena, prec, 2, d, d[0].nseg, s, 3);
+      std::vector<cplx*> outs(fr.size());
+      int maxnf = 0;
       for (size_t f = 0; f < fr.size(); ++f) {
-        cplx* out = (fr[f].flags & ISDF_FRAG_DEVICE) ? (cplx*)fr[f].eri : Est + p.eoff[f];
-        HIPCHK(eri_scatter_launch(acc + p.aoff[f], out, p.nf[f], BIG_TILE, s));
+        outs[f] = (fr[f].flags & ISDF_FRAG_DEVICE) ? (cplx*)fr[f].eri : Est + p.eoff[f];
+        maxnf = std::max(maxnf, p.nf[f]);
       }
+      HIPCHK(eri_scatter_batch_launch(acc, ws.arena.put(p.aoff.data(), p.aoff.size(), s),
+                                      ws.arena.put(outs.data(), outs.size(), s),
+                                      ws.arena.put(p.nf.data(), p.nf.size(), s), (int)fr.size(), maxnf, BIG_TILE,
+                                      s));
     }
   }
   if (timed) ws.timer.end("frag_eri", s);

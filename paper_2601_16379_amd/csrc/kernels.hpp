@@ -81,6 +81,10 @@ hipError_t big_launch(int prec, int conj, const NtDesc* descs_dev, int ndesc, lo
 hipError_t herm_fill_launch(cplx* c, int n, long long ld, long long bat, int nbat, int tile, hipStream_t s);
 // E[(pq)][(sr)] with lower tiles computed (edge `tile`) -> eri[p][q][r][s]
 hipError_t eri_scatter_launch(const cplx* e, cplx* eri, int nf, int tile, hipStream_t s);
+// the same for n fragments in one launch: fragment f reads e + eoff[f] and
+// writes eri[f]; nf, eoff, eri are device arrays
+hipError_t eri_scatter_batch_launch(const cplx* e, const long long* eoff, cplx* const* eri, const int* nf,
+                                    int n, int maxnf, int tile, hipStream_t s);
 // bf16x3 NT GEMM on the 32x32x16 matrix cores (128 x 128 tiles, 256
 // threads, direct-to-LDS operand copies): same descriptors and epilogues as
 // big_launch for precision 2; plan with big_plan.
@@ -209,6 +213,9 @@ hipError_t gather_launch(const cplx* phi, const int* ip, cplx* xt, int nk, int n
                          long long ng, int nip, hipStream_t s);
 // out[k][mu][col0 + p] = in[k][mu][p] for a fragment's coefficients (device copy
 // into the batch matrix)
+// fragment f: in[f] [nk][norb][nf[f]] -> out[k][mu][col[f] + p], one launch
+hipError_t copy_cols_batch_launch(const cplx* const* in, cplx* out, int nk, int norb, const int* nf,
+                                  const int* col, int n, int maxnf, int ncol, hipStream_t s);
 hipError_t copy_cols_launch(const cplx* in, cplx* out, int nk, int norb, int nf,
                             int ncol, int col0, hipStream_t s);
 // x[i] = 0 for i < n (complex128)

@@ -27,6 +27,20 @@ __global__ void copy_cols_kernel(const cplx* __restrict__ in, cplx* out, int nk,
   }
 }
 
+__global__ void copy_cols_batch_kernel(const cplx* const* __restrict__ in, cplx* out, int nk, int norb,
+                                       const int* __restrict__ nfa, const int* __restrict__ cola, int ncol) {
+  const int f = blockIdx.y;
+  const int nf = nfa[f], col0 = cola[f];
+  const cplx* src = in[f];
+  const long long total = (long long)nk * norb * nf;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const long long km = idx / nf;
+    const int p = (int)(idx - km * nf);
+    out[km * ncol + col0 + p] = src[idx];
+  }
+}
+
 __global__ void nonfinite_kernel(const cplx* __restrict__ x, long long n, int* flag) {
   int bad = 0;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
@@ -72,6 +86,17 @@ hipError_t gather_launch(const cplx* phi, const int* ip, cplx* xt, int nk, int n
                          int nip, hipStream_t s) {
   hipLaunchKernelGGL(gather_kernel, dim3(grid_for((long long)nk * norb * nip)), dim3(256), 0, s,
                      phi, ip, xt, nk, norb, ng, nip);
+  return hipGetLastError();
+}
+
+hipError_t copy_cols_batch_launch(const cplx* const* in, cplx* out, int nk, int norb, const int* nf,
+                                  const int* col, int n, int maxnf, int ncol, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const long long per = (long long)nk * norb * maxnf;
+  long long bx = (per + 255) / 256;
+  if (bx > 1024) bx = 1024;
+  hipLaunchKernelGGL(copy_cols_batch_kernel, dim3((unsigned)bx, n), dim3(256), 0, s, in, out, nk, norb, nf, col,
+                     ncol);
   return hipGetLastError();
 }
 

@@ -233,8 +233,8 @@ def test_mixed_kernel_and_eri_within_1e6(name, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
-@pytest.mark.parametrize("name", ["t_small_k2", "t_mid_k4", "t_grid10_k1", "t_grid18_k2", "t_grid20_k3",
-                                  "t_grid36_k2", "t_grid40_k1"])
+@pytest.mark.parametrize("name", ["t_tiny_k2", "t_small_k2", "t_mid_k4", "t_grid10_k1", "t_grid18_k2",
+                                  "t_grid20_k3", "t_grid36_k2", "t_grid40_k1"])
 def test_eta_tilde_elementwise(name, prec):
     """The grid-FFT stage itself (eq. (7) weighting), element by element for
     every q: FP64 within 1e-12 of max; the mixed operands within their
