@@ -68,8 +68,10 @@ def stage_work(stage, cfg, nfs, prec):
         return "hbm", 2.0 * nk * nip * nip * 16 / 1e9, "GB", PEAK["hbm"]
     if stage == "frag_pair":  # write R^q once (c128)
         return "hbm", nk * nip * s2 * 16 / 1e9, "GB", PEAK["hbm"]
-    if stage == "chol":       # factor (n^3/3), L^{-1} (n^3/6), G = Y^H Y lower half (n^3/2) complex MACs
-        return "fp64", 8.0 * nk * nip ** 3 / 1e12, "TFLOP", PEAK["fp64"]
+    if stage == "chol":       # blocked factor: n^3/3 complex MACs
+        return "fp64", 8.0 * nk * nip ** 3 / 3 / 1e12, "TFLOP", PEAK["fp64"]
+    if stage == "pinv":       # L^{-1} (n^3/6) and G = Y^H Y lower half (n^3/2) complex MACs
+        return "fp64", 8.0 * nk * nip ** 3 * (1 / 6 + 1 / 2) / 1e12, "TFLOP", PEAK["fp64"]
     if stage == "w_solve":    # W' = (G V') G: two full complex products
         return "fp64", 2 * 8.0 * nk * nip ** 3 / 1e12, "TFLOP", PEAK["fp64"]
     if stage == "metric_t":
@@ -109,7 +111,7 @@ def counter_traffic(stage, workload, prec):
     return None
 
 
-STAGES = ["metric_t", "metric_kconv", "rhs_t", "rhs_kconv", "chol", "grid_fft", "v_gemm", "w_solve",
+STAGES = ["metric_t", "metric_kconv", "rhs_t", "rhs_kconv", "chol", "pinv", "grid_fft", "v_gemm", "w_solve",
           "frag_t", "frag_pair", "frag_u", "frag_eri"]
 
 

@@ -293,10 +293,10 @@ struct isdf_ctx_s {
   uint32_t flags = 0;
   hipStream_t stream = nullptr;
   hipStream_t aux = nullptr;            // second stream: the factorisation overlaps the RHS
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_pinv = nullptr;
   int device = 0;
   // resident device data
-  DevBuf phi, ip, xt, pi, eta, lt, w, work1, work2, work3, perm, rank, rchunk, flag;
+  DevBuf phi, ip, xt, pi, eta, lt, w, work1, work2, work3, pinv_ws, perm, rank, rchunk, flag;
   DevBuf wt64, wt32, wt16, eta_split;   // W transposed in the three GEMM formats; split eta~
   DevBuf dmax, cflag;                   // factorisation: largest diagonal, breakdown flags
   long long ld_ip = 0, ld_g = 0;        // row pitches of split operands (multiples of 16)
@@ -305,6 +305,7 @@ struct isdf_ctx_s {
   std::vector<int> rank_h;
   long long rc = 0;   // r-chunk of the RHS
   Arena arena;
+  Arena arena_aux;                      // descriptors of the second stream (chol, pinv)
   StageTimer timer;
   std::string err;
   // fragment workspace of the synchronous call
@@ -383,6 +384,9 @@ void do_fit(isdf_ctx c) {
   const int nk = c->nk, norb = c->norb, nip = c->nip;
   const long long ng = c->ng;
   c->arena.reset();
+  // the second stream may still be forming the previous fit's pseudo-inverse
+  HIPCHK(hipStreamSynchronize(c->aux));
+  c->arena_aux.reset();
   // X^k (IV gather)
   HIPCHK(gather_launch(c->phi.as<cplx>(), c->ip.as<int>(), c->xt.as<cplx>(), nk, norb, ng, nip, s));
   // T^k_IJ = sum_mu X^k_{I mu} conj(X^k_{J mu})  (Algorithm 1, Y = X)
@@ -423,14 +427,7 @@ void do_fit(isdf_ctx c) {
   for (long long r0 = 0; r0 < ng; r0 += c->rc) {
     c->timer.begin("rhs_t", s);
     const int rcur = (int)std::min<long long>(c->rc, ng - r0);
-    std::vector<GemmDesc> d(1);
-    d[0] = mkdesc(c->xt.as<cplx>(), nip, c->phi.as<cplx>() + r0, ng, c->rchunk.as<cplx>(), rcur,
-                  nip, rcur, norb);
-    d[0].batch = nk;
-    d[0].sA_bat = (long long)norb * nip;
-    d[0].sB_bat = (long long)norb * ng;
-    d[0].sC_bat = (long long)nip * rcur;
-    run_gemm(c->arena, 0, GEMM_A_KM | GEMM_B_KN | GEMM_B_CONJ, d, s);
+    HIPCHK(rhs_t_launch(c->xt.as<cplx>(), c->phi.as<cplx>(), c->rchunk.as<cplx>(), nk, norb, nip, ng, r0, rcur, s));
     c->timer.end("rhs_t", s);
     c->timer.begin("rhs_kconv", s);
     KconvArgs a;
@@ -472,7 +469,7 @@ void do_fit(isdf_ctx c) {
         d[0].sA_bat = d[0].sB_bat = d[0].sC_bat = nip2(c);
         d[0].herm = 2;
         d[0].epi = 4;
-        run_nt(c->arena, 0, 2, d, c->aux);
+        run_nt(c->arena_aux, 0, 2, d, c->aux);
       }
     }
     // matrices whose pivots fell below the rank tolerance (singular metrics)
@@ -484,53 +481,10 @@ void do_fit(isdf_ctx c) {
     for (int q = 0; q < nk; ++q)
       if (fl[q]) qs.push_back(q);
     if (!qs.empty()) {
-      int* ql = c->arena.put(qs.data(), qs.size(), c->aux);
+      int* ql = c->arena_aux.put(qs.data(), qs.size(), c->aux);
       HIPCHK(chol_launch(c->pi.as<cplx>(), A, c->lt.as<cplx>(), c->perm.as<int>(), c->rank.as<int>(),
                          nip, (int)qs.size(), rtol, (c->flags & ISDF_NO_PIVOT) ? 0 : 1, c->aux, ql));
     }
-    // the pseudo-inverse factor of eq. (8), still on the second stream:
-    // Y = L^{-1} by 64-row block rows (zero outside the rank block; stored
-    // transposed in A), G = Y^H Y, so that P^T Pi^+ P = G on the rank block.
-    // Scratch: the row-major factor in work3 (overwritten by G at the end),
-    // the block-row partials St [n][64] and diagonal inverses in work1.
-    {
-      cplx* Lrow = c->work3.as<cplx>();
-      cplx* St = c->work1.as<cplx>();
-      cplx* Yd = St + (long long)nk * nip * 64;
-      const long long nn = nip2(c);
-      HIPCHK(tri_setup_launch(c->lt.as<cplx>(), c->rank.as<int>(), Lrow, A, nip, nk, c->aux));
-      for (int jb = 0; jb < nip; jb += 64) {
-        const int nb = std::min(64, nip - jb);
-        if (jb > 0) {
-          // St[n][m] = sum_{k < jb} Yt[n][k] L[jb+m][k]
-          std::vector<NtDesc> g(1);
-          g[0] = mknt(A, nip, Lrow + (long long)jb * nip, nip, St, 64, jb, nb, jb);
-          g[0].batch = nk;
-          g[0].sA_bat = g[0].sB_bat = nn;
-          g[0].sC_bat = (long long)nip * 64;
-          run_nt(c->arena, 0, 0, g, c->aux);
-        }
-        HIPCHK(tri_inv_diag_launch(Lrow, c->rank.as<int>(), A, Yd, nip, nk, jb, c->aux));
-        if (jb > 0) {
-          // Yt[n][jb+m] = Y[jb+m][n] = -sum_k St[n][k] Y_bb[m][k]
-          std::vector<NtDesc> g(1);
-          g[0] = mknt(St, 64, Yd, 64, A + jb, nip, jb, nb, nb);
-          g[0].batch = nk;
-          g[0].sA_bat = (long long)nip * 64;
-          g[0].sB_bat = 4096;
-          g[0].sC_bat = nn;
-          g[0].epi = 4;
-          run_nt(c->arena, 0, 0, g, c->aux);
-        }
-      }
-    }
-    std::vector<NtDesc> d(1);
-    d[0] = mknt(A, nip, A, nip, c->work3.as<cplx>(), nip, nip, nip, nip);
-    d[0].batch = nk;
-    d[0].sA_bat = d[0].sB_bat = d[0].sC_bat = nip2(c);
-    d[0].herm = 1;
-    // G[m][n] = sum_i conj(Yt[m][i]) Yt[n][i]
-    run_nt(c->arena, 0, 1, d, c->aux);
   }
   c->timer.end("chol", c->aux);
   HIPCHK(hipEventRecord(c->ev_join, c->aux));
@@ -549,6 +503,58 @@ void do_fit(isdf_ctx c) {
       throw Fail{ISDF_E_NUMERIC, "Cholesky breakdown of Pi^q (singular metric) at q = " +
                                      std::to_string(q) + ", column " + std::to_string(c->rank_h[q])};
   }
+  // The pseudo-inverse factor of eq. (8) on the second stream: it overlaps
+  // the grid FFT and the V^q product of isdf_coulomb_kernel, which waits for
+  // it (ev_pinv) before W^q = G V' G.
+  c->timer.begin("pinv", c->aux);
+  {
+    cplx* A = c->work2.as<cplx>();
+    // Y = L^{-1} by 64-row block rows (zero outside the rank block; stored
+    // transposed in A = work2), G = Y^H Y (into work3), so that
+    // P^T Pi^+ P = G on the rank block.  Scratch: the row-major factor in
+    // work3 (overwritten by G at the end), the block-row partials St [n][64]
+    // and the diagonal inverses in pinv_ws.
+    {
+      cplx* Lrow = c->work3.as<cplx>();
+      cplx* St = c->pinv_ws.as<cplx>();
+      cplx* Yd = St + (long long)nk * nip * 64;
+      const long long nn = nip2(c);
+      HIPCHK(tri_setup_launch(c->lt.as<cplx>(), c->rank.as<int>(), Lrow, A, nip, nk, c->aux));
+      for (int jb = 0; jb < nip; jb += 64) {
+        const int nb = std::min(64, nip - jb);
+        if (jb > 0) {
+          // St[n][m] = sum_{k < jb} Yt[n][k] L[jb+m][k]
+          std::vector<NtDesc> g(1);
+          g[0] = mknt(A, nip, Lrow + (long long)jb * nip, nip, St, 64, jb, nb, jb);
+          g[0].batch = nk;
+          g[0].sA_bat = g[0].sB_bat = nn;
+          g[0].sC_bat = (long long)nip * 64;
+          run_nt(c->arena_aux, 0, 0, g, c->aux);
+        }
+        HIPCHK(tri_inv_diag_launch(Lrow, c->rank.as<int>(), A, Yd, nip, nk, jb, c->aux));
+        if (jb > 0) {
+          // Yt[n][jb+m] = Y[jb+m][n] = -sum_k St[n][k] Y_bb[m][k]
+          std::vector<NtDesc> g(1);
+          g[0] = mknt(St, 64, Yd, 64, A + jb, nip, jb, nb, nb);
+          g[0].batch = nk;
+          g[0].sA_bat = (long long)nip * 64;
+          g[0].sB_bat = 4096;
+          g[0].sC_bat = nn;
+          g[0].epi = 4;
+          run_nt(c->arena_aux, 0, 0, g, c->aux);
+        }
+      }
+    }
+    std::vector<NtDesc> d(1);
+    d[0] = mknt(A, nip, A, nip, c->work3.as<cplx>(), nip, nip, nip, nip);
+    d[0].batch = nk;
+    d[0].sA_bat = d[0].sB_bat = d[0].sC_bat = nip2(c);
+    d[0].herm = 1;
+    // G[m][n] = sum_i conj(Yt[m][i]) Yt[n][i]
+    run_nt(c->arena_aux, 0, 1, d, c->aux);
+  }
+  c->timer.end("pinv", c->aux);
+  HIPCHK(hipEventRecord(c->ev_pinv, c->aux));
   c->fitted = true;
   c->eta_valid = true;
   c->kernel_ready = false;
@@ -626,6 +632,7 @@ void do_kernel(isdf_ctx c, int prec) {
   // P^T Pi P = L L^H of rank r:  G = L^{-H} L^{-1} (formed by isdf_fit),
   // W' = G (P^T V P) G, W = P W' P^T (zero outside the rank block); the two
   // products are FP64 MFMA.
+  HIPCHK(hipStreamWaitEvent(s, c->ev_pinv, 0));   // G from isdf_fit's second stream
   c->timer.begin("w_solve", s);
   {
     const long long n2 = nip2(c);
@@ -1053,7 +1060,7 @@ int64_t isdf_plan_bytes(const int32_t grid[3], const int32_t kmesh[3], int32_t n
   b += nk * n_orb * ng * e;              // orbitals
   b += nk * n_orb * n_ip * e;            // X
   b += 6 * nk * (long long)n_ip * n_ip * e;  // Pi, L, W, three work buffers
-  b += std::max(0LL, nk * ((long long)n_ip * 64 + 4096 - (long long)n_ip * n_ip) * e);  // L^{-1} scratch
+  b += nk * ((long long)n_ip * 64 + 4096) * e;  // L^{-1} scratch
   const long long ld = (n_ip + 7) / 8 * 8;
   b += nk * (long long)n_ip * ld * (16 + 8 + 8);  // W^T in the three operand formats
   b += nk * (long long)n_ip * ng * e;    // eta
@@ -1136,8 +1143,8 @@ isdf_status isdf_create(isdf_ctx* out, const double* lattice, const int32_t grid
     c->pi.alloc(m2);
     c->lt.alloc(m2);
     c->w.alloc(m2);
-    // work1 also holds the block-row scratch of the blocked L^{-1}
-    c->work1.alloc(std::max(m2, (size_t)nk * ((size_t)n_ip * 64 + 4096) * e));
+    c->work1.alloc(m2);
+    c->pinv_ws.alloc((size_t)nk * ((size_t)n_ip * 64 + 4096) * e);   // blocked L^{-1} scratch
     c->work2.alloc(m2);
     c->work3.alloc(m2);
     c->eta.alloc((size_t)nk * n_ip * ng * e);
@@ -1162,6 +1169,7 @@ isdf_status isdf_create(isdf_ctx* out, const double* lattice, const int32_t grid
     HIPCHK(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&c->ev_pinv, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&c->sync_ws.done, hipEventDisableTiming));
   });
   if (st != ISDF_OK) {
@@ -1458,6 +1466,7 @@ isdf_status isdf_destroy(isdf_ctx ctx) {
   }
   if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
   if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+  if (ctx->ev_pinv) (void)hipEventDestroy(ctx->ev_pinv);
   delete ctx;
   return ISDF_OK;
 }

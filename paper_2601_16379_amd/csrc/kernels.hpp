@@ -142,6 +142,12 @@ struct PairArgs {
   double scale;
 };
 hipError_t pair_launch(const PairArgs& a, hipStream_t s);
+
+// out[k][I][r] = sum_mu xt[k][mu][I] conj(phi[k][mu][r0 + r]), r < rcur
+// (the right-hand side's T^k_I(r) on one tile of grid points); FP64 vector
+// units, n_orb <= 256
+hipError_t rhs_t_launch(const cplx* xt, const cplx* phi, cplx* out, int nk, int norb, int nip, long long ng,
+                        long long r0, int rcur, hipStream_t s);
 // true when pair_launch takes the register path (needs item_off / nitems)
 bool pair_reg_supported(int fmt, int m1, int m2, int m3);
 
