@@ -78,7 +78,7 @@ __device__ inline void stage_copy(const unsigned short* base, const long long (&
     const int rc = wave + 4 * j;          // rows rc*8 .. rc*8+7
     const int kg = k0 + 8 * (gslot[j] >> 2);
     const unsigned short* g =
-        kg < kcur ? base + 4 * (rowoff[j] + k0) + 8 * gslot[j] : kZeroVec;
+        (kg < kcur && rowoff[j] >= 0) ? base + 4 * (rowoff[j] + k0) + 8 * gslot[j] : kZeroVec;
     __builtin_amdgcn_global_load_lds((glb_void*)g, (lds_void*)(dst + rc * 8 * ROW_B), 16, 0, 0);
   }
 }
@@ -86,23 +86,29 @@ __device__ inline void stage_copy(const unsigned short* base, const long long (&
 // Fragments of one stage for this lane: A rows of the wave's two 32-row
 // blocks, B rows of its two 32-column blocks, four planes each (16 bytes =
 // 8 k of the lane's k-half).
+// Fragments of one stage for this lane: NI 32-row blocks of A (rows rb0 +
+// i * 32) and NJ 32-row blocks of B (rows cb0 + j * 32), four planes each
+// (16 bytes = 8 k of the lane's k-group l/32).
+template <int NI, int NJ>
 struct Frag {
-  u4 a[2][4], b[2][4];
+  u4 a[NI][4], b[NJ][4];
 };
 
-__device__ inline void read_frags_a(const char* buf, Frag& f, int wm, int lr, int lk) {
+template <int NI, int NJ>
+__device__ inline void read_frags_a(const char* buf, Frag<NI, NJ>& f, int rb0, int lr, int lk) {
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const int row = wm * 64 + i * 32 + lr;
+  for (int i = 0; i < NI; ++i) {
+    const int row = rb0 + i * 32 + lr;
     const char* p = buf + row * ROW_B;
 #pragma unroll
     for (int pl = 0; pl < 4; ++pl) f.a[i][pl] = *(const u4*)(p + (lds_slot(row, 4 * lk + pl) << 4));
   }
 }
-__device__ inline void read_frags_b(const char* buf, Frag& f, int wn, int lr, int lk) {
+template <int NI, int NJ>
+__device__ inline void read_frags_b(const char* buf, Frag<NI, NJ>& f, int cb0, int lr, int lk) {
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int row = wn * 64 + j * 32 + lr;
+  for (int j = 0; j < NJ; ++j) {
+    const int row = cb0 + j * 32 + lr;
     const char* p = buf + OPER_B + row * ROW_B;
 #pragma unroll
     for (int pl = 0; pl < 4; ++pl) f.b[j][pl] = *(const u4*)(p + (lds_slot(row, 4 * lk + pl) << 4));
@@ -112,11 +118,16 @@ __device__ inline void read_frags_b(const char* buf, Frag& f, int wn, int lr, in
 // Pin a stage's fragments: their reads must have completed here, and later
 // uses do not depend on the loads any more (so the compiler does not place
 // its wait for them after the next stage's reads have been queued).
-__device__ inline void settle(Frag& f) {
+template <int NI, int NJ>
+__device__ inline void settle(Frag<NI, NJ>& f) {
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < NI; ++i)
 #pragma unroll
-    for (int p = 0; p < 4; ++p) asm volatile("" : "+v"(f.a[i][p]), "+v"(f.b[i][p]));
+    for (int p = 0; p < 4; ++p) asm volatile("" : "+v"(f.a[i][p]));
+#pragma unroll
+  for (int j = 0; j < NJ; ++j)
+#pragma unroll
+    for (int p = 0; p < 4; ++p) asm volatile("" : "+v"(f.b[j][p]));
 }
 
 __device__ inline u4 neg_bf(u4 v) {
@@ -150,27 +161,161 @@ __device__ inline BFr split_a(const u4 (&a)[4]) {
   if ((T) == 5) { CR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A.nih, BIH, CR, 0, 0, 0); \
                   CI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A.ih, BRH, CI, 0, 0, 0); }
 
-// MFMAs of one stage for the wave's column block j: the four accumulator
-// chains of the two row blocks are interleaved, so a chain is used every
-// fourth MFMA.
-template <bool A_CONJ, bool B_CONJ>
-__device__ inline void mma_half(const Frag& f, int j, f16v (&c_re)[2][2], f16v (&c_im)[2][2]) {
+// MFMAs of one stage for the wave's column block j; with two row blocks
+// their four accumulator chains are interleaved (a chain every fourth MFMA).
+template <int NI, int NJ, bool A_CONJ, bool B_CONJ>
+__device__ inline void mma_half(const Frag<NI, NJ>& f, int j, f16v (&c_re)[NI][NJ], f16v (&c_im)[NI][NJ]) {
   const u4 bi = B_CONJ ? neg_bf(f.b[j][2]) : f.b[j][2];
   const u4 bl = B_CONJ ? neg_bf(f.b[j][3]) : f.b[j][3];
   const bf8 brh = as_bf8(f.b[j][0]), brl = as_bf8(f.b[j][1]), bih = as_bf8(bi), bil = as_bf8(bl);
-  const BFr x0 = split_a<A_CONJ>(f.a[0]), x1 = split_a<A_CONJ>(f.a[1]);
-  f16v cr0 = c_re[0][j], ci0 = c_im[0][j], cr1 = c_re[1][j], ci1 = c_im[1][j];
+  if constexpr (NI == 2) {
+    const BFr x0 = split_a<A_CONJ>(f.a[0]), x1 = split_a<A_CONJ>(f.a[1]);
+    f16v cr0 = c_re[0][j], ci0 = c_im[0][j], cr1 = c_re[1][j], ci1 = c_im[1][j];
 #pragma unroll
-  for (int t = 0; t < 6; ++t) {
-    X3_TERMS(x0, brh, brl, bih, bil, cr0, ci0, t)
-    X3_TERMS(x1, brh, brl, bih, bil, cr1, ci1, t)
+    for (int t = 0; t < 6; ++t) {
+      X3_TERMS(x0, brh, brl, bih, bil, cr0, ci0, t)
+      X3_TERMS(x1, brh, brl, bih, bil, cr1, ci1, t)
+    }
+    c_re[0][j] = cr0;
+    c_im[0][j] = ci0;
+    c_re[1][j] = cr1;
+    c_im[1][j] = ci1;
+  } else {
+    const BFr x0 = split_a<A_CONJ>(f.a[0]);
+    f16v cr0 = c_re[0][j], ci0 = c_im[0][j];
+#pragma unroll
+    for (int t = 0; t < 6; ++t) { X3_TERMS(x0, brh, brl, bih, bil, cr0, ci0, t) }
+    c_re[0][j] = cr0;
+    c_im[0][j] = ci0;
   }
-  c_re[0][j] = cr0;
-  c_im[0][j] = ci0;
-  c_re[1][j] = cr1;
-  c_im[1][j] = ci1;
 }
 #undef X3_TERMS
+
+// K loop and epilogue of one tile.  The wave owns the (NI*32) x (NJ*32)
+// block at rows rb0, columns cb0 of the tile: 64 x 64 in full tiles (2 x 2
+// waves); in tiles with at most 32 valid rows (columns) each wave takes a
+// 32 x 32 block of the one 32-row (32-column) strip, so edge tiles cost a
+// quarter of the matrix-core work.
+template <int NI, int NJ, bool A_CONJ, bool B_CONJ>
+__device__ inline void tile_body(const NtDesc& d, int b, int m0, int n0, const unsigned short* As,
+                                 const unsigned short* Bs, int kcur, const long long (&aoff)[NCOPY],
+                                 const long long (&boff)[NCOPY], const int (&gslot)[NCOPY], int rb0, int cb0,
+                                 char* smem, int wave, int lane) {
+  const int lr = lane & 31, lk = lane >> 5;
+  f16v c_re[NI][NJ], c_im[NI][NJ];
+#pragma unroll
+  for (int i = 0; i < NI; ++i)
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        c_re[i][j][v] = 0.f;
+        c_im[i][j][v] = 0.f;
+      }
+
+    // stages of 16 k, rounded up to an even count (the extra one is all zeros)
+    const int nst = (((kcur + XK - 1) / XK) + 1) & ~1;
+    __syncthreads();                      // LDS of the previous tile no longer read
+#pragma unroll
+    for (int s = 0; s < NBUF - 1; ++s)
+      if (s < nst) {
+        stage_copy(As, aoff, gslot, s * XK, kcur, smem + s * STAGE_B, wave);
+        stage_copy(Bs, boff, gslot, s * XK, kcur, smem + s * STAGE_B + OPER_B, wave);
+      }
+    // stage 0 landed when at most the copies of the later prologue stages are in flight
+    wait_copies(min(NBUF - 2, nst - 1));
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    Frag<NI, NJ> f0, f1;
+    read_frags_a(smem, f0, rb0, lr, lk);
+    read_frags_b(smem, f0, cb0, lr, lk);
+    // Stage s: make stage s+1 visible, start the copy NBUF-1 stages ahead,
+    // then the MFMAs of stage s (fragments read during the previous stage)
+    // in two halves, each behind half of the fragment reads of stage s+1, so
+    // the LDS latency hides behind them.
+#define X3_STEP(S, CUR, NXT)                                                                        \
+  {                                                                                                \
+    const int s_ = (S);                                                                            \
+    /* CUR's fragment reads (issued a stage ago) complete here, before NXT's  */                    \
+    /* reads are queued behind them; nothing is scheduled across this point    */                   \
+    __builtin_amdgcn_sched_barrier(0);                                                             \
+    settle(CUR);                                                                                   \
+    if (s_ + 1 < nst) {                                                                            \
+      wait_copies(min(NBUF - 3, nst - s_ - 2));  /* stage s+1 landed */                           \
+      /* bare s_barrier: __syncthreads() would also wait for the copies in flight */                \
+      __builtin_amdgcn_s_barrier();                                                                \
+      asm volatile("" ::: "memory");                                                               \
+      if (s_ + NBUF - 1 < nst) {                                                                   \
+        char* dst = smem + ((s_ + NBUF - 1) % NBUF) * STAGE_B;                                     \
+        stage_copy(As, aoff, gslot, (s_ + NBUF - 1) * XK, kcur, dst, wave);                        \
+        stage_copy(Bs, boff, gslot, (s_ + NBUF - 1) * XK, kcur, dst + OPER_B, wave);               \
+      }                                                                                            \
+      read_frags_a(smem + ((s_ + 1) % NBUF) * STAGE_B, NXT, rb0, lr, lk);                          \
+    }                                                                                              \
+    mma_half<NI, NJ, A_CONJ, B_CONJ>(CUR, 0, c_re, c_im);                                          \
+    if (s_ + 1 < nst) read_frags_b(smem + ((s_ + 1) % NBUF) * STAGE_B, NXT, cb0, lr, lk);          \
+    if (NJ == 2) mma_half<NI, NJ, A_CONJ, B_CONJ>(CUR, NJ - 1, c_re, c_im);                        \
+  }
+    for (int s = 0; s < nst; s += 2) {
+      X3_STEP(s, f0, f1)
+      X3_STEP(s + 1, f1, f0)
+    }
+#undef X3_STEP
+
+    // ---- epilogue (32x32 layout: lane l, register v -> row 8(v/4) + 4(l/32) + v%4, column l%32) ----
+  if (d.epi == 3) {
+    // split store: each wave assembles its block in LDS in the operand
+    // format (a row of NJ*32 points is NJ*256 contiguous bytes) and writes it
+    // with 16-byte stores
+    __syncthreads();                      // every wave is past its last stage reads
+    unsigned short* st = (unsigned short*)(smem + wave * 32768);
+    const int npad = d.npad ? d.npad : (int)d.ldc;
+    constexpr int RU = NJ * 128;          // u16 per staged row
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+#pragma unroll
+      for (int j = 0; j < NJ; ++j)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int ml = i * 32 + 8 * (v >> 2) + 4 * lk + (v & 3);
+          const int nl = j * 32 + lr;
+          const bool in = n0 + cb0 + nl < d.N;
+          const float re = in ? c_re[i][j][v] : 0.f, im = in ? c_im[i][j][v] : 0.f;
+          const unsigned short rh = bf16_bits_of(re), ih = bf16_bits_of(im);
+          unsigned short* e = st + ml * RU + (nl >> 3) * 32 + (nl & 7);
+          e[0] = rh;
+          e[8] = bf16_bits_of(re - bf16_value(rh));
+          e[16] = ih;
+          e[24] = bf16_bits_of(im - bf16_value(ih));
+        }
+    __builtin_amdgcn_wave_barrier();
+    unsigned short* C = (unsigned short*)d.C + 4 * ((long long)b * d.sC_bat + n0 + cb0);
+    constexpr int PPR = NJ * 16;          // 16-byte parts per row
+#pragma unroll 4
+    for (int h = 0; h < NI * NJ * 8; ++h) {
+      const int c = h * 64 + lane, ml = c / PPR, part = c % PPR;
+      const int m = m0 + rb0 + ml;
+      if (m < d.M && n0 + cb0 + (part >> 2) * 8 < npad)
+        *(u4*)(C + 4 * (long long)m * d.ldc + part * 8) = *(const u4*)(st + ml * RU + part * 8);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+#pragma unroll
+      for (int j = 0; j < NJ; ++j)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int m = m0 + rb0 + i * 32 + 8 * (v >> 2) + 4 * lk + (v & 3);
+          const int n = n0 + cb0 + j * 32 + lr;
+          if (m >= d.M || n >= d.N) continue;
+          cplx* cp = (cplx*)d.C + (long long)b * d.sC_bat + (long long)m * d.ldc + n;
+          cplx x = *cp;                 // FP64 accumulation across launches
+          x.x += (double)c_re[i][j][v];
+          x.y += (double)c_im[i][j][v];
+          *cp = x;
+        }
+  }
+}
 
 template <bool A_CONJ, bool B_CONJ, int KIND>
 __global__ __launch_bounds__(XNT) void zgemm_x3_kernel(const NtDesc* __restrict__ descs, int ndesc,
@@ -180,7 +325,6 @@ __global__ __launch_bounds__(XNT) void zgemm_x3_kernel(const NtDesc* __restrict_
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave >> 1, wn = wave & 1;
-  const int lr = lane & 31, lk = lane >> 5;
 
   const long long t8 = (total_tiles + 7) / 8 * 8;
   const long long per = t8 / 8;
@@ -210,129 +354,24 @@ __global__ __launch_bounds__(XNT) void zgemm_x3_kernel(const NtDesc* __restrict_
     const unsigned short* Bs = (const unsigned short*)d.B + 4 * (b * d.sB_bat + (long long)seg * d.sB_seg);
     const int kcur = (seg == d.nseg - 1) ? d.Klast : d.Kseg;
 
-    // this lane's rows and slots in its copy instructions
+    // this lane's rows and slots in its copy instructions; rows past M / N
+    // are copied from the zero block (offset -1)
     long long aoff[NCOPY], boff[NCOPY];
     int gslot[NCOPY];
 #pragma unroll
     for (int j = 0; j < NCOPY; ++j) {
       const int row = (wave + 4 * j) * 8 + (lane >> 3);
       gslot[j] = lds_slot(row, lane & 7);     // the slot whose LDS position is lane & 7
-      const int ra = min(m0 + row, d.M - 1), rb = min(n0 + row, d.N - 1);
-      aoff[j] = (long long)ra * d.lda;
-      boff[j] = (long long)rb * d.ldb;
+      aoff[j] = m0 + row < d.M ? (long long)(m0 + row) * d.lda : -1;
+      boff[j] = n0 + row < d.N ? (long long)(n0 + row) * d.ldb : -1;
     }
-
-    f16v c_re[2][2], c_im[2][2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          c_re[i][j][v] = 0.f;
-          c_im[i][j][v] = 0.f;
-        }
-
-    // stages of 16 k, rounded up to an even count (the extra one is all zeros)
-    const int nst = (((kcur + XK - 1) / XK) + 1) & ~1;
-    __syncthreads();                      // LDS of the previous tile no longer read
-#pragma unroll
-    for (int s = 0; s < NBUF - 1; ++s)
-      if (s < nst) {
-        stage_copy(As, aoff, gslot, s * XK, kcur, smem + s * STAGE_B, wave);
-        stage_copy(Bs, boff, gslot, s * XK, kcur, smem + s * STAGE_B + OPER_B, wave);
-      }
-    // stage 0 landed when at most the copies of the later prologue stages are in flight
-    wait_copies(min(NBUF - 2, nst - 1));
-    __builtin_amdgcn_s_barrier();
-    asm volatile("" ::: "memory");
-    Frag f0, f1;
-    read_frags_a(smem, f0, wm, lr, lk);
-    read_frags_b(smem, f0, wn, lr, lk);
-    // Stage s: make stage s+1 visible, start the copy NBUF-1 stages ahead,
-    // then the MFMAs of stage s (fragments read during the previous stage)
-    // in two halves, each behind half of the fragment reads of stage s+1, so
-    // the LDS latency hides behind them.
-#define X3_STEP(S, CUR, NXT)                                                                        \
-  {                                                                                                \
-    const int s_ = (S);                                                                            \
-    /* CUR's fragment reads (issued a stage ago) complete here, before NXT's  */                    \
-    /* reads are queued behind them; nothing is scheduled across this point    */                   \
-    __builtin_amdgcn_sched_barrier(0);                                                             \
-    settle(CUR);                                                                                   \
-    if (s_ + 1 < nst) {                                                                            \
-      wait_copies(min(NBUF - 3, nst - s_ - 2));  /* stage s+1 landed */                           \
-      /* bare s_barrier: __syncthreads() would also wait for the copies in flight */                \
-      __builtin_amdgcn_s_barrier();                                                                \
-      asm volatile("" ::: "memory");                                                               \
-      if (s_ + NBUF - 1 < nst) {                                                                   \
-        char* dst = smem + ((s_ + NBUF - 1) % NBUF) * STAGE_B;                                     \
-        stage_copy(As, aoff, gslot, (s_ + NBUF - 1) * XK, kcur, dst, wave);                        \
-        stage_copy(Bs, boff, gslot, (s_ + NBUF - 1) * XK, kcur, dst + OPER_B, wave);               \
-      }                                                                                            \
-      read_frags_a(smem + ((s_ + 1) % NBUF) * STAGE_B, NXT, wm, lr, lk);                           \
-    }                                                                                              \
-    mma_half<A_CONJ, B_CONJ>(CUR, 0, c_re, c_im);                                                  \
-    if (s_ + 1 < nst) read_frags_b(smem + ((s_ + 1) % NBUF) * STAGE_B, NXT, wn, lr, lk);           \
-    mma_half<A_CONJ, B_CONJ>(CUR, 1, c_re, c_im);                                                  \
-  }
-    for (int s = 0; s < nst; s += 2) {
-      X3_STEP(s, f0, f1)
-      X3_STEP(s + 1, f1, f0)
-    }
-#undef X3_STEP
-
-    // ---- epilogue (32x32 layout: lane l, register v -> row 8(v/4) + 4(l/32) + v%4, column l%32) ----
-    if (d.epi == 3) {
-      // split store: each wave assembles its 64 x 64 block in LDS in the
-      // operand format (a row of 64 is 512 contiguous bytes) and writes it
-      // with 16-byte stores, two rows per instruction
-      __syncthreads();                    // every wave is past its last stage reads
-      unsigned short* st = (unsigned short*)(smem + wave * 32768);
-      const int npad = d.npad ? d.npad : (int)d.ldc;
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-          for (int v = 0; v < 16; ++v) {
-            const int ml = i * 32 + 8 * (v >> 2) + 4 * lk + (v & 3);
-            const int nl = j * 32 + lr;
-            const bool in = n0 + wn * 64 + nl < d.N;
-            const float re = in ? c_re[i][j][v] : 0.f, im = in ? c_im[i][j][v] : 0.f;
-            const unsigned short rh = bf16_bits_of(re), ih = bf16_bits_of(im);
-            unsigned short* e = st + ml * 256 + (nl >> 3) * 32 + (nl & 7);
-            e[0] = rh;
-            e[8] = bf16_bits_of(re - bf16_value(rh));
-            e[16] = ih;
-            e[24] = bf16_bits_of(im - bf16_value(ih));
-          }
-      __builtin_amdgcn_wave_barrier();
-      unsigned short* C = (unsigned short*)d.C + 4 * ((long long)b * d.sC_bat + n0 + wn * 64);
-#pragma unroll 4
-      for (int h = 0; h < 32; ++h) {
-        const int ml = 2 * h + lk, part = lane & 31;
-        const int m = m0 + wm * 64 + ml;
-        if (m < d.M && n0 + wn * 64 + (part >> 2) * 8 < npad)
-          *(u4*)(C + 4 * (long long)m * d.ldc + part * 8) = *(const u4*)(st + ml * 256 + part * 8);
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-          for (int v = 0; v < 16; ++v) {
-            const int m = m0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * lk + (v & 3);
-            const int n = n0 + wn * 64 + j * 32 + lr;
-            if (m >= d.M || n >= d.N) continue;
-            cplx* cp = (cplx*)d.C + (long long)b * d.sC_bat + (long long)m * d.ldc + n;
-            cplx x = *cp;                 // FP64 accumulation across launches
-            x.x += (double)c_re[i][j][v];
-            x.y += (double)c_im[i][j][v];
-            *cp = x;
-          }
-    }
+    if (d.M - m0 <= 32)
+      tile_body<1, 1, A_CONJ, B_CONJ>(d, b, m0, n0, As, Bs, kcur, aoff, boff, gslot, 0, wave * 32, smem, wave, lane);
+    else if (d.N - n0 <= 32)
+      tile_body<1, 1, A_CONJ, B_CONJ>(d, b, m0, n0, As, Bs, kcur, aoff, boff, gslot, wave * 32, 0, smem, wave, lane);
+    else
+      tile_body<2, 2, A_CONJ, B_CONJ>(d, b, m0, n0, As, Bs, kcur, aoff, boff, gslot, wm * 64, wn * 64, smem, wave,
+                                      lane);
   }
 }
 
