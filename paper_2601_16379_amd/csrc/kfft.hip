@@ -238,6 +238,159 @@ __global__ __launch_bounds__(256) void pair_kernel(PairArgs a) {
   }
 }
 
+// ---- register path of the k convolution (mode 0), mesh M1 x M2 x M3 with
+// M1 in {1, 2, 4} and M2, M3 <= 4 ----
+// M1 lanes per element (lane l: element l / M1, k1 = l % M1): the M2 x M3
+// values of a k1 plane sit in the lane's registers (FP64), the k1 axis is a
+// radix-2 transform across the lanes of a quad (DPP, no LDS).  Both
+// transforms have the sign +1: T^R = sum_k exp(+ik.R) T^k, then
+// out^q = scale * sum_R exp(+iq.R) |T^R|^2.
+template <int R>
+__device__ inline void dft_pos(cplx (&x)[R]) {
+  if constexpr (R > 1) {
+    cplx y[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      double re = x[0].x, im = x[0].y;
+#pragma unroll
+      for (int j = 1; j < R; ++j) {
+        const double c = Rot<R>::c[(j * k) % R], sn = Rot<R>::s[(j * k) % R];
+        re = fma(x[j].x, c, fma(-x[j].y, sn, re));
+        im = fma(x[j].y, c, fma(x[j].x, sn, im));
+      }
+      y[k] = cmk(re, im);
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) x[k] = y[k];
+  }
+}
+
+template <int M2, int M3>
+__device__ inline void dft23_pos(cplx (&x)[M2 * M3]) {
+#pragma unroll
+  for (int a = 0; a < M2; ++a) {
+    cplx t[M3];
+#pragma unroll
+    for (int j = 0; j < M3; ++j) t[j] = x[a * M3 + j];
+    dft_pos<M3>(t);
+#pragma unroll
+    for (int j = 0; j < M3; ++j) x[a * M3 + j] = t[j];
+  }
+#pragma unroll
+  for (int b = 0; b < M3; ++b) {
+    cplx t[M2];
+#pragma unroll
+    for (int j = 0; j < M2; ++j) t[j] = x[j * M3 + b];
+    dft_pos<M2>(t);
+#pragma unroll
+    for (int j = 0; j < M2; ++j) x[j * M3 + b] = t[j];
+  }
+}
+
+// value of the lane (l ^ 1) or (l ^ 2) of the quad
+template <int CTRL>
+__device__ inline double dpp_d(double v) {
+  const int2 u = __builtin_bit_cast(int2, v);
+  int2 r;
+  r.x = __builtin_amdgcn_update_dpp(0, u.x, CTRL, 0xF, 0xF, false);
+  r.y = __builtin_amdgcn_update_dpp(0, u.y, CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, r);
+}
+constexpr int DPP_XOR1 = 0xB1;   // quad_perm [1, 0, 3, 2]
+constexpr int DPP_XOR2 = 0x4E;   // quad_perm [2, 3, 0, 1]
+template <int CTRL>
+__device__ inline cplx dpp_c(cplx v) { return cmk(dpp_d<CTRL>(v.x), dpp_d<CTRL>(v.y)); }
+
+// radix-2 step across lanes l, l ^ X: even lanes v + p, odd lanes p - v
+// (or, with twist, the odd lanes of the second half p - i v and v + i p)
+template <int CTRL>
+__device__ inline cplx bfly(cplx v, bool hi) {
+  const cplx p = dpp_c<CTRL>(v);
+  return hi ? csub(p, v) : cadd(v, p);
+}
+
+template <int M1, int M2, int M3>
+__global__ __launch_bounds__(256) void kconv_reg_kernel(KconvArgs a) {
+  constexpr int NV = M2 * M3, EPW = 64 / M1;
+  const int lane = threadIdx.x & 63;
+  const int k1 = lane % M1;
+  const long long e = ((long long)blockIdx.x * 4 + (threadIdx.x >> 6)) * EPW + lane / M1;
+  const bool in = e < a.n_elem;
+  const long long ie = in ? (e / a.in_inner) * a.in_outer + e % a.in_inner : 0;
+  cplx x[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+    x[v] = in ? a.in[(long long)(k1 * NV + v) * a.in_kstride + ie] : cmk(0.0, 0.0);
+  dft23_pos<M2, M3>(x);
+  // k1 axis across the quad; M1 = 4 leaves the lanes in bit-reversed order
+  if constexpr (M1 == 2) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) x[v] = bfly<DPP_XOR1>(x[v], k1 & 1);
+  } else if constexpr (M1 == 4) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const cplx s = bfly<DPP_XOR2>(x[v], k1 >= 2);      // x_j +- x_{j^2}
+      const cplx p = dpp_c<DPP_XOR1>(s);
+      // lanes 0..3 -> y0 = s0 + s1, y2 = s0 - s1, y1 = d0 + i d1, y3 = d0 - i d1
+      if (k1 == 0) x[v] = cadd(s, p);
+      else if (k1 == 1) x[v] = csub(p, s);
+      else if (k1 == 2) x[v] = cmk(s.x - p.y, s.y + p.x);
+      else x[v] = cmk(p.x + s.y, p.y - s.x);
+    }
+  }
+  // |T^R|^2
+#pragma unroll
+  for (int v = 0; v < NV; ++v) x[v] = cmk(x[v].x * x[v].x + x[v].y * x[v].y, 0.0);
+  // R1 axis: input lanes hold R1 = bitrev(k1) for M1 = 4; output in natural order
+  if constexpr (M1 == 2) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) x[v] = bfly<DPP_XOR1>(x[v], k1 & 1);
+  } else if constexpr (M1 == 4) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const cplx s = bfly<DPP_XOR1>(x[v], k1 & 1);       // a, b (lanes 0, 1), c, d (lanes 2, 3)
+      const cplx p = dpp_c<DPP_XOR2>(s);
+      // y0 = a + c, y1 = b + i d, y2 = a - c, y3 = b - i d
+      if (k1 == 0) x[v] = cadd(s, p);
+      else if (k1 == 2) x[v] = csub(p, s);
+      else if (k1 == 1) x[v] = cmk(s.x - p.y, s.y + p.x);
+      else x[v] = cmk(p.x + s.y, p.y - s.x);
+    }
+  }
+  dft23_pos<M2, M3>(x);
+  if (!in) return;
+  const long long oe = (e / a.out_inner) * a.out_outer + e % a.out_inner;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) a.out[(long long)(k1 * NV + v) * a.out_qstride + oe] = cscale(x[v], a.scale);
+}
+
+template <int M1, int M2, int M3>
+hipError_t launch_kconv_reg(const KconvArgs& a, hipStream_t s) {
+  constexpr int EPB = 4 * (64 / M1);
+  const long long blocks = (a.n_elem + EPB - 1) / EPB;
+  if (blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL((kconv_reg_kernel<M1, M2, M3>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+template <int M1, int M2>
+hipError_t kconv_reg_m3(const KconvArgs& a, hipStream_t s) {
+  switch (a.m3) {
+    case 1: return launch_kconv_reg<M1, M2, 1>(a, s);
+    case 2: return launch_kconv_reg<M1, M2, 2>(a, s);
+    case 3: return launch_kconv_reg<M1, M2, 3>(a, s);
+    default: return launch_kconv_reg<M1, M2, 4>(a, s);
+  }
+}
+template <int M1>
+hipError_t kconv_reg_m2(const KconvArgs& a, hipStream_t s) {
+  switch (a.m2) {
+    case 1: return kconv_reg_m3<M1, 1>(a, s);
+    case 2: return kconv_reg_m3<M1, 2>(a, s);
+    case 3: return kconv_reg_m3<M1, 3>(a, s);
+    default: return kconv_reg_m3<M1, 4>(a, s);
+  }
+}
+
 // ---- register path of the pair transform (mixed precisions) ----
 // 3-D forward DFT over an M1 x M2 x M3 mesh held in registers,
 // x[(j1 * M2 + j2) * M3 + j3], one axis at a time.
@@ -401,6 +554,11 @@ hipError_t pair_reg_m2(const PairArgs& a, hipStream_t s) {
 }  // namespace
 
 hipError_t kconv_launch(const KconvArgs& a, hipStream_t s) {
+  if (a.mode == 0 && (a.m1 == 1 || a.m1 == 2 || a.m1 == 4) && a.m2 <= 4 && a.m3 <= 4) {
+    if (a.m1 == 1) return kconv_reg_m2<1>(a, s);
+    if (a.m1 == 2) return kconv_reg_m2<2>(a, s);
+    return kconv_reg_m2<4>(a, s);
+  }
   const int nk = a.m1 * a.m2 * a.m3;
   if (a.m1 > MAXM || a.m2 > MAXM || a.m3 > MAXM) return hipErrorInvalidValue;
   int etile = 1;                        // largest power of two with nk*etile <= 4096 (64 KB)
