@@ -596,7 +596,7 @@ void do_kernel(isdf_ctx c, int prec) {
   c->timer.end("grid_fft", s);
   c->eta_valid = false;
   // V^q = eta~ eta~^H  (Hermitian; lower tiles computed and mirrored); in the
-  // mixed precisions FP32 partial sums over 2048 grid points, FP64 across them
+  // mixed precisions FP32 partial sums over 8192 grid points, FP64 across them
   c->timer.begin("v_gemm", s);
   {
     std::vector<NtDesc> d(1);
@@ -608,11 +608,11 @@ void do_kernel(isdf_ctx c, int prec) {
       d[0].herm = 1;
       run_nt(c->arena, prec, 2, d, s, 1);
     } else {
-      // one large-tile launch per block of 2048 grid points: FP32 inside a
+      // one large-tile launch per block of 8192 grid points: FP32 inside a
       // block, FP64 accumulation into V across blocks; lower tiles, then mirror
       d[0] = mknt(c->eta_split.p, c->ld_g, c->eta_split.p, c->ld_g, c->work1.p, nip, nip, nip, (int)ng);
       d[0].a_plane = d[0].b_plane = split_plane;
-      const int kseg = 2048;
+      const int kseg = 8192;
       d[0].Kseg = (int)std::min<long long>(kseg, ng);
       d[0].nseg = (int)((ng + d[0].Kseg - 1) / d[0].Kseg);
       d[0].Klast = (int)(ng - (long long)(d[0].nseg - 1) * d[0].Kseg);
