@@ -66,8 +66,8 @@ def stage_work(stage, cfg, nfs, prec):
         return "hbm", 2.0 * nk * nip * ng * 16 / 1e9, "GB", PEAK["hbm"]
     if stage == "metric_kconv":
         return "hbm", 2.0 * nk * nip * nip * 16 / 1e9, "GB", PEAK["hbm"]
-    if stage == "frag_pair":  # write R^q once (c128)
-        return "hbm", nk * nip * s2 * 16 / 1e9, "GB", PEAK["hbm"]
+    if stage == "frag_pair":  # write R^q once (c128 in FP64, 8 B a point in the mixed formats)
+        return "hbm", nk * nip * s2 * (16 if prec == "fp64" else 8) / 1e9, "GB", PEAK["hbm"]
     if stage == "chol":       # blocked factor: n^3/3 complex MACs
         return "fp64", 8.0 * nk * nip ** 3 / 3 / 1e12, "TFLOP", PEAK["fp64"]
     if stage == "pinv":       # L^{-1} (n^3/6) and G = Y^H Y lower half (n^3/2) complex MACs
@@ -81,12 +81,22 @@ def stage_work(stage, cfg, nfs, prec):
     return None
 
 
-KERNEL_OF_STAGE = {"frag_eri": ("zgemm_nt_kernel<0, false, true, 3>", "zgemm_big_kernel<{p}, false, true, 3>"),
-                   "frag_u": ("zgemm_nt_kernel<0, false, false, 2>", "zgemm_big_kernel<{p}, false, false, 2>"),
-                   "v_gemm": ("zgemm_nt_kernel<0, false, true, 1>", "zgemm_big_kernel<{p}, false, true, 1>"),
-                   "frag_pair": ("pair_kernel(PairArgs)", "pair_kernel(PairArgs)"),
-                   "rhs_kconv": ("kconv_kernel(KconvArgs, int)", "kconv_kernel(KconvArgs, int)"),
+KERNEL_OF_STAGE = {"frag_eri": ("zgemm_nt_kernel<0, false, true, 3>", "{x}false, true, 3>"),
+                   "frag_u": ("zgemm_nt_kernel<0, false, false, 2>", "{x}false, false, 2>"),
+                   "v_gemm": ("zgemm_nt_kernel<0, false, true, 1>", "{x}false, true, 1>"),
+                   "frag_pair": ("pair_kernel(PairArgs)", "pair_reg_kernel<"),
+                   "rhs_t": ("rhs_t_kernel<", "rhs_t_kernel<"),
+                   "rhs_kconv": ("kconv_reg_kernel<", "kconv_reg_kernel<"),
                    "grid_fft": ("slab_kernel_c<", "fft3_reg_kernel<")}
+
+
+def kernel_name(stage, prec):
+    """Name (prefix) of a stage's main kernel as the profiler lists it: the
+    FP32 path runs the two-plane big-tile kernel, bf16x3 its own MFMA kernel."""
+    if stage not in KERNEL_OF_STAGE:
+        return stage
+    x = {"fp32": "zgemm_big_kernel<1, ", "bf16x3": "zgemm_x3_kernel<"}.get(prec, "")
+    return KERNEL_OF_STAGE[stage][0 if prec == "fp64" else 1].format(x=x)
 
 
 def counter_traffic(stage, workload, prec):
@@ -104,7 +114,7 @@ def counter_traffic(stage, workload, prec):
         fp = os.path.join(csrc, f)
         if not os.path.exists(fp) or hashlib.sha256(open(fp, "rb").read()).hexdigest() != h:
             return None
-    key = KERNEL_OF_STAGE[stage][0 if prec == "fp64" else 1].format(p={"fp32": 1, "bf16x3": 2}.get(prec, 0))
+    key = kernel_name(stage, prec)
     for name, v in prof["kernels"].items():
         if key in name:
             return v["step_bytes"]
@@ -253,20 +263,25 @@ def main():
     wall = time.perf_counter() - t0
     ms_step = 1e3 * wall / args.steps
     print("timed %d steps: %.2f ms/step" % (args.steps, ms_step), file=sys.stderr, flush=True)
+    # device time of each stage per step (HIP events on the stream it runs on)
+    # and the number of timed intervals (kernel launches for "*_kernel")
     stage = {}
-    for s in STAGES:
+    for s in STAGES + [s + "_kernel" for s in KERNEL_OF_STAGE]:
         tot, cnt = ctx.stage_total(s)
         if cnt:
-            stage[s] = (tot, cnt)
+            stage[s] = (tot / args.steps, cnt / args.steps)
     erisum = float(sum(n ** 4 for n in nfs))
     value = erisum * args.steps / wall
     lat_ms = 1e3 * np.asarray(lats)
 
-    # dominant kernel and its roofline
-    dom = max(stage, key=lambda k: stage[k][0])
+    # dominant stage and the roofline of its main kernel: algorithmic work of
+    # one launch over the average launch duration; where the stage also runs
+    # small helper kernels its GEMM launches are timed alone ("<stage>_kernel")
+    dom = max((s for s in STAGES if s in stage), key=lambda k: stage[k][0])
     bound, amount, unit, peak = stage_work(dom, cfg, nfs, args.prec)
-    avg_ms = stage[dom][0] / stage[dom][1]
-    achieved = amount / (avg_ms / 1e3)
+    kt, kn = stage.get(dom + "_kernel", stage[dom])
+    avg_ms = kt / kn
+    achieved = (amount / kn) / (avg_ms / 1e3)
     if unit == "GB":
         roof = {"bound": "hbm", "achieved": achieved, "peak": peak, "unit": "GB/s"}
     elif bound == "mfma":
@@ -274,16 +289,24 @@ def main():
     else:
         roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s"}
     roof["frac"] = achieved / peak
-    roof["traffic"] = counter_traffic(dom, cfg.name, args.prec)
-    roof["kernel"] = dom
-    roof["avg_ms"] = avg_ms
+    tr = counter_traffic(dom, cfg.name, args.prec)
+    roof["traffic"] = None if tr is None else tr / kn
+    roof["stage"] = dom
+    roof["kernel"] = kernel_name(dom, args.prec)
+    roof["avg_launch_ms"] = avg_ms
+    roof["launches_per_step"] = kn
+    roof["algorithmic_per_launch"] = amount / kn * (1e9 if unit == "GB" else 1e12)
 
     stage_rows = {}
-    for s, (tot, cnt) in stage.items():
+    for s in STAGES:
+        if s not in stage:
+            continue
+        tot, cnt = stage[s]
         w = stage_work(s, cfg, nfs, args.prec)
-        row = {"avg_ms": tot / cnt, "share": tot / sum(v[0] for v in stage.values())}
+        row = {"ms_per_step": tot, "intervals_per_step": cnt,
+               "share": tot / sum(stage[k][0] for k in STAGES if k in stage)}
         if w:
-            rate = w[1] / (tot / cnt / 1e3)
+            rate = w[1] / (tot / 1e3)
             row["rate"] = rate
             row["unit"] = "GB/s" if w[2] == "GB" else "TFLOP/s"
             row["frac"] = rate / w[3]

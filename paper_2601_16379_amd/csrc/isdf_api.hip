@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <deque>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <new>
@@ -135,21 +136,31 @@ void run_gemm(Arena& ar, int prec, int layout, std::vector<GemmDesc>& d, hipStre
   HIPCHK(gemm_launch(prec, layout, dd, (int)d.size(), total, max_gemm_blocks(), s));
 }
 
-void run_nt(Arena& ar, int prec, int conj, std::vector<NtDesc>& d, hipStream_t s, int kind = 0) {
+// mark(true) / mark(false) bracket each kernel launch when given (kernel timing)
+typedef std::function<void(bool)> LaunchMark;
+
+void run_nt(Arena& ar, int prec, int conj, std::vector<NtDesc>& d, hipStream_t s, int kind = 0,
+            const LaunchMark& mark = nullptr) {
   long long total = nt_plan(d.data(), (int)d.size());
   if (total == 0) return;
   NtDesc* dd = ar.put(d.data(), d.size(), s);
+  if (mark) mark(true);
   HIPCHK(nt_launch(prec, conj, dd, (int)d.size(), total, max_gemm_blocks(), s, kind));
+  if (mark) mark(false);
 }
 
 // Upload big-tile descriptors once and launch them for each K segment.
-void run_big(Arena& ar, int prec, int conj, std::vector<NtDesc>& d, int nseg, hipStream_t s, int kind) {
+void run_big(Arena& ar, int prec, int conj, std::vector<NtDesc>& d, int nseg, hipStream_t s, int kind,
+             const LaunchMark& mark = nullptr) {
   long long total = big_plan(d.data(), (int)d.size());
   if (total == 0) return;
   NtDesc* dd = ar.put(d.data(), d.size(), s);
-  for (int seg = 0; seg < nseg; ++seg)
+  for (int seg = 0; seg < nseg; ++seg) {
+    if (mark) mark(true);
     HIPCHK(prec == 2 ? x3_launch(conj, dd, (int)d.size(), total, max_gemm_blocks(), seg, s, kind)
                      : big_launch(prec, conj, dd, (int)d.size(), total, max_gemm_blocks(), seg, s, kind));
+    if (mark) mark(false);
+  }
 }
 
 NtDesc mknt(const void* A, long long lda, const void* B, long long ldb, void* C, long long ldc,
@@ -236,7 +247,7 @@ struct StageTimer {
       ms[kv.first] = (float)sum;
       if (totals) {
         (*totals)[kv.first].first += sum;
-        (*totals)[kv.first].second += 1;
+        (*totals)[kv.first].second += (long long)sl.used;
       }
       sl.used = 0;
     }
@@ -906,14 +917,21 @@ void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn
     }
     // largest fragments first so the persistent launch ends balanced
     std::stable_sort(d.begin(), d.end(), [](const NtDesc& a, const NtDesc& b) { return a.M > b.M; });
+    // the GEMM launches alone, timed as "frag_eri_kernel" (one interval per launch)
+    LaunchMark mark = nullptr;
+    if (timed)
+      mark = [&](bool on) {
+        if (on) ws.timer.begin("frag_eri_kernel", s);
+        else ws.timer.end("frag_eri_kernel", s);
+      };
     if (prec == 0) {
-      run_nt(ws.arena, prec, 2, d, s, 3);
+      run_nt(ws.arena, prec, 2, d, s, 3, mark);
     } else {
       // one launch per q group: FP32 partial sums inside, FP64 sum over groups in E_f
       long long acount = 0;
       for (size_t f = 0; f < fr.size(); ++f) acount += (long long)p.nf[f] * p.nf[f] * p.nf[f] * p.nf[f];
       HIPCHK(zero_launch(acc, acount, s));
-      run_big(ws.arena, prec, 2, d, d[0].nseg, s, 3);
+      run_big(ws.arena, prec, 2, d, d[0].nseg, s, 3, mark);
       std::vector<cplx*> outs(fr.size());
       int maxnf = 0;
       for (size_t f = 0; f < fr.size(); ++f) {
