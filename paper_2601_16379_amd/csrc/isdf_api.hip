@@ -1062,9 +1062,13 @@ int64_t isdf_storage_model_bytes(int64_t n_k, int64_t n_ip, int64_t n_ao) {
   return (n_k * n_ip * n_ip + n_k * n_ip * n_ao) * 16;
 }
 
+#ifndef ISDF_RHS_TILE_BYTES
+#define ISDF_RHS_TILE_BYTES (2LL << 30)
+#endif
+
 static long long rchunk_len(long long ng, int nk, int nip) {
-  // r tile of the right-hand side: T^k_I(r) for all k of one tile <= 2 GiB
-  long long rc = (2LL << 30) / ((long long)nk * nip * (long long)sizeof(cplx));
+  // r tile of the right-hand side: T^k_I(r) for all k of one tile
+  long long rc = (long long)(ISDF_RHS_TILE_BYTES) / ((long long)nk * nip * (long long)sizeof(cplx));
   rc = std::max<long long>(64, std::min<long long>(rc, ng));
   return rc;
 }
@@ -1156,7 +1160,8 @@ isdf_status isdf_create(isdf_ctx* out, const double* lattice, const int32_t grid
     c->rc = rchunk_len(ng, nk, n_ip);
     c->phi.alloc((size_t)nk * n_orb * ng * e);
     c->ip.alloc(sizeof(int) * n_ip);
-    c->xt.alloc((size_t)nk * n_orb * n_ip * e);
+    // + RHS_X_PAD elements: rhs_t_launch reads whole blocks of points
+    c->xt.alloc(((size_t)nk * n_orb * n_ip + RHS_X_PAD) * e);
     const size_t m2 = (size_t)nk * n_ip * n_ip * e;
     c->pi.alloc(m2);
     c->lt.alloc(m2);

@@ -145,7 +145,9 @@ hipError_t pair_launch(const PairArgs& a, hipStream_t s);
 
 // out[k][I][r] = sum_mu xt[k][mu][I] conj(phi[k][mu][r0 + r]), r < rcur
 // (the right-hand side's T^k_I(r) on one tile of grid points); FP64 vector
-// units, n_orb <= 256
+// units.  xt must stay readable for RHS_X_PAD elements past its end (blocks
+// of points read whole rows; the extra outputs are not stored).
+constexpr int RHS_X_PAD = 16;
 hipError_t rhs_t_launch(const cplx* xt, const cplx* phi, cplx* out, int nk, int norb, int nip, long long ng,
                         long long r0, int rcur, hipStream_t s);
 // true when pair_launch takes the register path (needs item_off / nitems)

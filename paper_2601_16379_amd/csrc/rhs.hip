@@ -4,9 +4,10 @@
 // vector units with every output written once in 4 KB rows.
 //
 // Workgroup (256 threads): RT = 256 consecutive r x IT interpolation points
-// of one k.  The X^k rows of the IT points sit in LDS (read as broadcasts);
-// each thread streams phi^k_mu(r) for its r over mu and accumulates its IT
-// outputs in registers.
+// of one k.  The X^k values of the IT points are the same for every lane and
+// are read through the scalar cache into SGPRs (the FMAs take them as their
+// scalar operand, so no LDS traffic); each thread streams phi^k_mu(r) for its
+// r over mu and accumulates its IT outputs in registers.
 #include "kernels.hpp"
 
 namespace {
@@ -17,25 +18,24 @@ template <int IT>
 __global__ __launch_bounds__(256) void rhs_t_kernel(const cplx* __restrict__ xt, const cplx* __restrict__ phi,
                                                     cplx* __restrict__ out, int norb, int nip, long long ng,
                                                     long long r0, int rcur) {
-  extern __shared__ cplx xs[];                    // [norb][IT]
   const int k = blockIdx.z;
   const int I0 = blockIdx.y * IT;
   const int r = blockIdx.x * RT + threadIdx.x;
   const int ni = (nip - I0) < IT ? (nip - I0) : IT;
-  const cplx* X = xt + (long long)k * norb * nip;   // [mu][I]
-  for (int idx = threadIdx.x; idx < norb * IT; idx += blockDim.x) {
-    const int mu = idx / IT, i = idx - (idx / IT) * IT;
-    xs[idx] = (i < ni) ? X[(long long)mu * nip + I0 + i] : cmk(0.0, 0.0);
-  }
-  __syncthreads();
   if (r >= rcur) return;
+  // X^k_{I mu} rows of this block's points: the same for every lane, read
+  // through the scalar cache into SGPRs
+  const cplx* X = xt + (long long)k * norb * nip + I0;   // [mu][I]
   const cplx* P = phi + (long long)k * norb * ng + r0 + r;
   double ar[IT], ai[IT];
 #pragma unroll
   for (int i = 0; i < IT; ++i) ar[i] = ai[i] = 0.0;
+  // one phi row per step: loading several orbitals ahead measured slower
   for (int mu = 0; mu < norb; ++mu) {
     const cplx f = P[(long long)mu * ng];
-    const cplx* x = xs + mu * IT;
+    // rows past N_IP (last block) read the padding after X or the next row;
+    // their outputs are not stored
+    const cplx* x = X + (long long)mu * nip;
 #pragma unroll
     for (int i = 0; i < IT; ++i) {
       // x * conj(f)
@@ -56,9 +56,8 @@ hipError_t rhs_t_launch(const cplx* xt, const cplx* phi, cplx* out, int nk, int 
                         long long r0, int rcur, hipStream_t s) {
   if (nk <= 0 || rcur <= 0) return hipSuccess;
   constexpr int IT = 16;
-  const size_t lds = (size_t)norb * IT * sizeof(cplx);
-  if (lds > 64 * 1024) return hipErrorInvalidValue;
+  static_assert(IT <= RHS_X_PAD, "X padding covers one block of points");
   dim3 g((rcur + RT - 1) / RT, (nip + IT - 1) / IT, nk);
-  hipLaunchKernelGGL(rhs_t_kernel<IT>, g, dim3(RT), lds, s, xt, phi, out, norb, nip, ng, r0, rcur);
+  hipLaunchKernelGGL(rhs_t_kernel<IT>, g, dim3(RT), 0, s, xt, phi, out, norb, nip, ng, r0, rcur);
   return hipGetLastError();
 }
