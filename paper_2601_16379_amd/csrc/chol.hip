@@ -113,128 +113,6 @@ __global__ __launch_bounds__(CT) void chol_kernel(const cplx* __restrict__ pi, c
   if (threadIdx.x == 0) rank[q] = r;
 }
 
-// Triangular solves with the factor for a block of `cb` right-hand-side
-// columns held in LDS.  stage 1: B = (P^T V P)[:, cols], Z = L^-H L^-1 B.
-// stage 2: B = Z^H[:, cols], W[perm][perm] = L^-H L^-1 B.
-__global__ __launch_bounds__(256) void wsolve_kernel(const cplx* __restrict__ v, cplx* z, cplx* w,
-                                                     const cplx* __restrict__ lt,
-                                                     const int* __restrict__ perm,
-                                                     const int* __restrict__ rank, int n, int cb,
-                                                     int stage) {
-  extern __shared__ cplx B[];   // [r][cb]
-  const int nblk = (n + cb - 1) / cb;
-  const int q = blockIdx.x / nblk;
-  const int c0 = (blockIdx.x % nblk) * cb;
-  const int r = rank[q];
-  if (c0 >= r) return;
-  const int nc = (r - c0) < cb ? (r - c0) : cb;
-  const long long nn = (long long)n * n;
-  const cplx* L = lt + q * nn;
-  const int* pm = perm + (long long)q * n;
-  const cplx* V = v + q * nn;
-  cplx* Z = z + q * nn;
-  cplx* W = w + q * nn;
-
-  for (int idx = threadIdx.x; idx < r * cb; idx += blockDim.x) {
-    const int i = idx / cb, c = idx - (idx / cb) * cb;
-    cplx x = cmk(0.0, 0.0);
-    if (c < nc) {
-      if (stage == 1) x = V[(long long)pm[i] * n + pm[c0 + c]];
-      else x = cconj(Z[(long long)(c0 + c) * n + i]);
-    }
-    B[idx] = x;
-  }
-  __syncthreads();
-  // forward: L y = b, column oriented (L_ij = lt[j][i])
-  for (int j = 0; j < r; ++j) {
-    const double djj = L[(long long)j * n + j].x;
-    if (threadIdx.x < cb) B[j * cb + threadIdx.x] = cscale(B[j * cb + threadIdx.x], 1.0 / djj);
-    __syncthreads();
-    const int rows = r - j - 1;
-    for (int idx = threadIdx.x; idx < rows * cb; idx += blockDim.x) {
-      const int i = j + 1 + idx / cb, c = idx - (idx / cb) * cb;
-      const cplx lij = L[(long long)j * n + i];
-      const cplx yj = B[j * cb + c];
-      cplx b = B[i * cb + c];
-      b.x -= lij.x * yj.x - lij.y * yj.y;
-      b.y -= lij.x * yj.y + lij.y * yj.x;
-      B[i * cb + c] = b;
-    }
-    __syncthreads();
-  }
-  // backward: L^H z = y, row oriented: z_i = (y_i - sum_{j>i} conj(L_ji) z_j) / L_ii
-  const int tpc = blockDim.x / cb;           // threads per column (power of two, <= 64)
-  const int c = threadIdx.x / tpc, sub = threadIdx.x % tpc;
-  for (int i = r - 1; i >= 0; --i) {
-    cplx acc = cmk(0.0, 0.0);
-    if (c < cb) {
-      for (int j = i + 1 + sub; j < r; j += tpc) {
-        const cplx lji = L[(long long)i * n + j];   // L_ji
-        const cplx zj = B[j * cb + c];
-        acc.x += lji.x * zj.x + lji.y * zj.y;       // conj(L_ji) * z_j
-        acc.y += lji.x * zj.y - lji.y * zj.x;
-      }
-    }
-    for (int off = tpc >> 1; off > 0; off >>= 1) {
-      acc.x += __shfl_xor(acc.x, off);
-      acc.y += __shfl_xor(acc.y, off);
-    }
-    if (c < cb && sub == 0) {
-      const double dii = L[(long long)i * n + i].x;
-      B[i * cb + c] = cscale(csub(B[i * cb + c], acc), 1.0 / dii);
-    }
-    __syncthreads();
-  }
-  for (int idx = threadIdx.x; idx < r * cb; idx += blockDim.x) {
-    const int i = idx / cb, cc = idx - (idx / cb) * cb;
-    if (cc >= nc) continue;
-    if (stage == 1) Z[(long long)i * n + c0 + cc] = B[idx];
-    else W[(long long)pm[i] * n + pm[c0 + cc]] = B[idx];
-  }
-}
-
-// Columns of Y = L^{-1} (lower triangular, the leading r x r block of the
-// factor), stored transposed: yt[c][i] = Y[i][c] (zero for i < c).  Column
-// oriented forward substitution of the identity, starting at row c.
-__global__ __launch_bounds__(256) void linv_kernel(const cplx* __restrict__ lt, const int* __restrict__ rank,
-                                                   cplx* yt, int n, int cb) {
-  extern __shared__ cplx B[];   // [r][cb]
-  const int nblk = (n + cb - 1) / cb;
-  const int q = blockIdx.x / nblk;
-  const int c0 = (blockIdx.x % nblk) * cb;
-  const int r = rank[q];
-  if (c0 >= r) return;
-  const int nc = (r - c0) < cb ? (r - c0) : cb;
-  const long long nn = (long long)n * n;
-  const cplx* L = lt + q * nn;
-  cplx* Y = yt + q * nn;
-  for (int idx = threadIdx.x; idx < r * cb; idx += blockDim.x) {
-    const int i = idx / cb, c = idx - (idx / cb) * cb;
-    B[idx] = cmk((c < nc && i == c0 + c) ? 1.0 : 0.0, 0.0);
-  }
-  __syncthreads();
-  for (int j = c0; j < r; ++j) {
-    const double djj = L[(long long)j * n + j].x;
-    if (threadIdx.x < cb) B[j * cb + threadIdx.x] = cscale(B[j * cb + threadIdx.x], 1.0 / djj);
-    __syncthreads();
-    const int rows = r - j - 1;
-    for (int idx = threadIdx.x; idx < rows * cb; idx += blockDim.x) {
-      const int i = j + 1 + idx / cb, c = idx - (idx / cb) * cb;
-      const cplx lij = L[(long long)j * n + i];
-      const cplx yj = B[j * cb + c];
-      cplx b = B[i * cb + c];
-      b.x -= lij.x * yj.x - lij.y * yj.y;
-      b.y -= lij.x * yj.y + lij.y * yj.x;
-      B[i * cb + c] = b;
-    }
-    __syncthreads();
-  }
-  for (int idx = threadIdx.x; idx < r * cb; idx += blockDim.x) {
-    const int i = idx / cb, c = idx - (idx / cb) * cb;
-    if (c < nc) Y[(long long)(c0 + c) * n + i] = B[idx];
-  }
-}
-
 // out[q][i][j] = in[q][pm[i]][pm[j]] for i, j < rank (dir 0, gather), or
 // out[q][pm[i]][pm[j]] = in[q][i][j] with zeros outside the rank (dir 1).
 __global__ void permute_kernel(const cplx* __restrict__ in, cplx* out, const int* __restrict__ perm,
@@ -401,34 +279,6 @@ hipError_t chol_launch(const cplx* pi, cplx* work, cplx* lt, int* perm, int* ran
   if (nq <= 0) return hipSuccess;
   hipLaunchKernelGGL(chol_kernel, dim3(nq), dim3(CT), 0, s, pi, work, lt, perm, rank, n, rtol, pivot,
                      qlist);
-  return hipGetLastError();
-}
-
-hipError_t wsolve_launch(const cplx* v, cplx* z, cplx* w, const cplx* lt, const int* perm,
-                         const int* rank, int n, int nq, hipStream_t s) {
-  if (nq <= 0) return hipSuccess;
-  int cb = 16;
-  while (cb > 4 && (size_t)n * cb * sizeof(cplx) > 128 * 1024) cb >>= 1;
-  const size_t lds = (size_t)n * cb * sizeof(cplx);
-  if (lds > 160 * 1024) return hipErrorInvalidValue;
-  const int nblk = (n + cb - 1) / cb;
-  hipLaunchKernelGGL(wsolve_kernel, dim3(nq * nblk), dim3(256), lds, s, v, z, w, lt, perm, rank, n, cb, 1);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const long long tot = (long long)nq * n * n;
-  hipLaunchKernelGGL(zero_kernel, dim3(1024), dim3(256), 0, s, w, tot);
-  hipLaunchKernelGGL(wsolve_kernel, dim3(nq * nblk), dim3(256), lds, s, v, z, w, lt, perm, rank, n, cb, 2);
-  return hipGetLastError();
-}
-
-hipError_t linv_launch(const cplx* lt, const int* rank, cplx* yt, int n, int nq, hipStream_t s) {
-  if (nq <= 0) return hipSuccess;
-  int cb = 16;
-  while (cb > 4 && (size_t)n * cb * sizeof(cplx) > 128 * 1024) cb >>= 1;
-  const size_t lds = (size_t)n * cb * sizeof(cplx);
-  if (lds > 160 * 1024) return hipErrorInvalidValue;
-  const int nblk = (n + cb - 1) / cb;
-  hipLaunchKernelGGL(linv_kernel, dim3(nq * nblk), dim3(256), lds, s, lt, rank, yt, n, cb);
   return hipGetLastError();
 }
 

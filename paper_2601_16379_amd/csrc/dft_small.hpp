@@ -94,6 +94,23 @@ __device__ inline float2 rot_f(float2 a, float c, float s) {
 
 template <int R>
 __device__ inline void small_dft_f(const float2 (&x)[R], float2 (&y)[R]) {
+  if constexpr (R == 2) {
+    y[0] = make_float2(x[0].x + x[1].x, x[0].y + x[1].y);
+    y[1] = make_float2(x[0].x - x[1].x, x[0].y - x[1].y);
+    return;
+  } else if constexpr (R == 4) {
+    // a = x0 + x2, b = x0 - x2, c = x1 + x3, d = x1 - x3:
+    // y0 = a + c, y2 = a - c, y1 = b - i d, y3 = b + i d
+    const float2 a = make_float2(x[0].x + x[2].x, x[0].y + x[2].y);
+    const float2 b = make_float2(x[0].x - x[2].x, x[0].y - x[2].y);
+    const float2 c = make_float2(x[1].x + x[3].x, x[1].y + x[3].y);
+    const float2 d = make_float2(x[1].x - x[3].x, x[1].y - x[3].y);
+    y[0] = make_float2(a.x + c.x, a.y + c.y);
+    y[2] = make_float2(a.x - c.x, a.y - c.y);
+    y[1] = make_float2(b.x + d.y, b.y - d.x);
+    y[3] = make_float2(b.x - d.y, b.y + d.x);
+    return;
+  }
 #pragma unroll
   for (int k = 0; k < R; ++k) {
     float2 acc = x[0];

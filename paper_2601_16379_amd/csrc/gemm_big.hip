@@ -1,5 +1,6 @@
-// Large-tile complex "NT" GEMM for the mixed precisions (FP32 and bf16x3):
-// 128x128 output tile per 512-thread workgroup, one K segment per launch.
+// Large-tile complex "NT" GEMM for the FP32 mixed precision: 128x128 output
+// tile per 512-thread workgroup, one K segment per launch (the bf16x3
+// operands have their own kernel in gemm_x3.hip).
 //
 //   C[m][n] (+)= sum_k opA(A_seg[m][k]) opB(B_seg[n][k])
 //
@@ -10,13 +11,13 @@
 // twice as large in each direction as the segmented kernel of gemm_nt.hip,
 // which halves the operand traffic per flop.  Operand formats and the
 // lane-local k permutation are those of gemm_nt.hip.  Eight waves in 4 x 2,
-// each 32 x 64 (2 x 4 MFMA tiles of 16x16).
+// each 32 x 64 (2 x 4 MFMA tiles of 16x16).  The template parameter P is the
+// operand format (1 = two FP32 planes, the only one instantiated).
 #include "kernels.hpp"
 
 namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 
 constexpr int BT = 128;     // tile edge
@@ -28,21 +29,16 @@ __device__ inline int isqrt_floor(long long x) {
   while ((r + 1) * (r + 1) <= x) ++r;
   return (int)r;
 }
-__device__ inline u4 neg_bf16x8(u4 v) {
-  return u4{v.x ^ 0x80008000u, v.y ^ 0x80008000u, v.z ^ 0x80008000u, v.w ^ 0x80008000u};
-}
 __device__ inline u4 neg_f32x4(u4 v) {
   return u4{v.x ^ 0x80000000u, v.y ^ 0x80000000u, v.z ^ 0x80000000u, v.w ^ 0x80000000u};
 }
-__device__ inline bf8 as_bf8(u4 v) { return __builtin_bit_cast(bf8, v); }
 
 // BK = 64 k per stage: enough MFMA work per stage to cover the latency of
 // the next stage's global loads (one workgroup per CU).
 constexpr int BK = 64;
 template <int P> struct BigCfg;
-// per row: 64 floats (16 vectors of 4) + 4 pad / 64 bf16 (8 vectors of 8) + 8 pad
+// per row: 64 floats (16 vectors of 4) + 4 pad
 template <> struct BigCfg<1> { static constexpr int PITCH = 68, PLANES = 2, VPR = 16, EPV = 4; typedef float T; };
-template <> struct BigCfg<2> { static constexpr int PITCH = 72, PLANES = 4, VPR = 8, EPV = 8; typedef unsigned short T; };
 constexpr int NV = 8;   // 16-byte vectors per thread per operand stage (128 x 64 x 8 B / 16 B / 512)
 
 // 128 rows x 64 k of one operand (all planes): 4096 16-byte vectors, 8 per thread
@@ -60,8 +56,7 @@ __device__ inline void big_load(const void* base, long long ld, long long plane,
     if (row0 + row < nrows && k0 + EPV * c < kcur) {
       x = *(const u4*)((const T*)base + pl * plane + (long long)(row0 + row) * ld + k0 + EPV * c);
       if constexpr (CONJ) {
-        if (P == 1 && pl == 1) x = neg_f32x4(x);
-        if (P == 2 && pl >= 2) x = neg_bf16x8(x);
+        if (pl == 1) x = neg_f32x4(x);
       }
     }
     r[i] = x;
@@ -143,50 +138,7 @@ __global__ __launch_bounds__(NT) void zgemm_big_kernel(const NtDesc* __restrict_
         big_load<P, A_CONJ>(As, d.lda, d.a_plane, m0, d.M, k0 + BK, kcur, ra);
         big_load<P, B_CONJ>(Bs, d.ldb, d.b_plane, n0, d.N, k0 + BK, kcur, rb);
       }
-      if constexpr (P == 2) {
-#pragma unroll
-       for (int kh = 0; kh < BK; kh += 32) {
-        const unsigned short* a = (const unsigned short*)sA + kh;
-        const unsigned short* bb = (const unsigned short*)sB + kh;
-        bf8 a_rh[2], a_rl[2], a_ih[2], a_il[2];
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-          const int ra_ = wm * 32 + i * 16 + lr;
-          a_rh[i] = as_bf8(*(const u4*)&a[(0 * BT + ra_) * PITCH + 8 * lk]);
-          a_rl[i] = as_bf8(*(const u4*)&a[(1 * BT + ra_) * PITCH + 8 * lk]);
-          a_ih[i] = as_bf8(*(const u4*)&a[(2 * BT + ra_) * PITCH + 8 * lk]);
-          a_il[i] = as_bf8(*(const u4*)&a[(3 * BT + ra_) * PITCH + 8 * lk]);
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int rb_ = wn * 64 + j * 16 + lr;
-          const bf8 b_rh = as_bf8(*(const u4*)&bb[(0 * BT + rb_) * PITCH + 8 * lk]);
-          const bf8 b_rl = as_bf8(*(const u4*)&bb[(1 * BT + rb_) * PITCH + 8 * lk]);
-          const u4 bih = *(const u4*)&bb[(2 * BT + rb_) * PITCH + 8 * lk];
-          const u4 bil = *(const u4*)&bb[(3 * BT + rb_) * PITCH + 8 * lk];
-          const bf8 b_ih = as_bf8(bih), b_il = as_bf8(bil);
-          const bf8 b_nih = as_bf8(neg_bf16x8(bih)), b_nil = as_bf8(neg_bf16x8(bil));
-#pragma unroll
-          for (int i = 0; i < 2; ++i) {
-            f4 cr = c_re[i][j], ci = c_im[i][j];
-            cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_rl[i], b_rh, cr, 0, 0, 0);
-            cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_rh[i], b_rl, cr, 0, 0, 0);
-            cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_il[i], b_nih, cr, 0, 0, 0);
-            cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_ih[i], b_nil, cr, 0, 0, 0);
-            cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_rh[i], b_rh, cr, 0, 0, 0);
-            cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_ih[i], b_nih, cr, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_rl[i], b_ih, ci, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_rh[i], b_il, ci, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_il[i], b_rh, ci, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_ih[i], b_rl, ci, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_rh[i], b_ih, ci, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_ih[i], b_rh, ci, 0, 0, 0);
-            c_re[i][j] = cr;
-            c_im[i][j] = ci;
-          }
-        }
-       }
-      } else {
+      {
         // FP32: lane k-set 8*lk + s, s = 0..7, per 32-k quarter
         const float* a = (const float*)sA;
         const float* bb = (const float*)sB;

@@ -8,14 +8,11 @@
 // format of the precision:
 //   FP64    complex128 interleaved rows; v_mfma_f64_16x16x4;
 //   FP32    two float planes (re, im), rows zero-padded to a multiple of 8;
-//           v_mfma_f32_16x16x4;
-//   BF16x3  four bf16 planes (re_hi, re_lo, im_hi, im_lo) with
-//           x = hi + lo, rows zero-padded to a multiple of 8;
-//           v_mfma_f32_16x16x32_bf16, products hi*hi + hi*lo + lo*hi.
-// A lane-local permutation of k (lane l of an MFMA step s takes
-// k = K_l + s with K_l = (l/16) * steps) lets every lane read its operand
-// fragment with 16-byte LDS loads for all three types; A and B use the same
-// permutation, so the sum over k is unchanged.  In FP32 and BF16x3 each K
+//           v_mfma_f32_16x16x4.
+// (bf16x3 operands use the kernel of gemm_x3.hip.)  A lane-local permutation
+// of k (lane l of an MFMA step s takes k = K_l + s with K_l = (l/16) * steps)
+// lets every lane read its operand fragment with 16-byte LDS loads; A and B
+// use the same permutation, so the sum over k is unchanged.  In FP32 each K
 // segment (one q, or one block of grid points) accumulates in FP32 and is
 // added into FP64 registers, so sums over q are FP64.
 //
@@ -28,7 +25,6 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 
 constexpr int TM = 64, TN = 64;
@@ -45,21 +41,6 @@ template <int P> struct NtCfg;
 template <> struct NtCfg<0> { static constexpr int BK = 16, PITCH = 18, PLANES = 2; typedef double T; };
 // FP32: BK = 32, planes re/im of floats, pitch 36
 template <> struct NtCfg<1> { static constexpr int BK = 32, PITCH = 36, PLANES = 2; typedef float T; };
-// BF16x3: BK = 32, planes re_hi/re_lo/im_hi/im_lo of bf16, pitch 40
-template <> struct NtCfg<2> { static constexpr int BK = 32, PITCH = 40, PLANES = 4; typedef unsigned short T; };
-
-__device__ inline u4 neg_bf16x8(u4 v) {
-  return u4{v.x ^ 0x80008000u, v.y ^ 0x80008000u, v.z ^ 0x80008000u, v.w ^ 0x80008000u};
-}
-__device__ inline bf8 as_bf8(u4 v) { return __builtin_bit_cast(bf8, v); }
-
-__device__ inline unsigned short bf16_bits(float x) {
-  __bf16 h = (__bf16)x;
-  return __builtin_bit_cast(unsigned short, h);
-}
-__device__ inline float bf16_val(unsigned short b) {
-  return (float)__builtin_bit_cast(__bf16, b);
-}
 
 // Stage one operand tile (64 rows x BK) from global memory into registers.
 // Returns per-thread vectors; rows >= nrows or k >= kcur read as zero.
@@ -84,22 +65,13 @@ __device__ inline void load_tile(const void* base, long long ld, long long plane
           x.w = (unsigned int)(b >> 32);
         }
       }
-    } else if constexpr (P == 1) {
+    } else {
       // 2 planes x 64 rows x 8 chunks of 4 floats: v -> plane v/512, row, chunk
       const int pl = v >> 9, row = (v >> 3) & 63, c = v & 7;
       if (row0 + row < nrows && k0 + 4 * c < kcur) {
         const float* p = (const float*)base + pl * plane + (long long)(row0 + row) * ld + k0 + 4 * c;
         x = *(const u4*)p;
         if (CONJ && pl == 1) x = u4{x.x ^ 0x80000000u, x.y ^ 0x80000000u, x.z ^ 0x80000000u, x.w ^ 0x80000000u};
-      }
-    } else {
-      // 4 planes x 64 rows x 4 chunks of 8 bf16: v -> plane v/256, row, chunk
-      const int pl = v >> 8, row = (v >> 2) & 63, c = v & 3;
-      if (row0 + row < nrows && k0 + 8 * c < kcur) {
-        const unsigned short* p =
-            (const unsigned short*)base + pl * plane + (long long)(row0 + row) * ld + k0 + 8 * c;
-        x = *(const u4*)p;
-        if (CONJ && pl >= 2) x = neg_bf16x8(x);
       }
     }
     r[i] = x;
@@ -120,12 +92,9 @@ __device__ inline void store_tile(typename NtCfg<P>::T* s, const u4 (&r)[4]) {
           __builtin_bit_cast(double, (unsigned long long)r[i].x | ((unsigned long long)r[i].y << 32));
       sd[(1 * 64 + row) * PITCH + k] =
           __builtin_bit_cast(double, (unsigned long long)r[i].z | ((unsigned long long)r[i].w << 32));
-    } else if constexpr (P == 1) {
+    } else {
       const int pl = v >> 9, row = (v >> 3) & 63, c = v & 7;
       *(u4*)((float*)s + (pl * 64 + row) * PITCH + 4 * c) = r[i];
-    } else {
-      const int pl = v >> 8, row = (v >> 2) & 63, c = v & 3;
-      *(u4*)((unsigned short*)s + (pl * 64 + row) * PITCH + 8 * c) = r[i];
     }
   }
 }
@@ -174,7 +143,7 @@ __global__ __launch_bounds__(256, 2) void zgemm_nt_kernel(const NtDesc* __restri
       tn = lt - tm * d.tiles_n;
     }
     const int m0 = tm * TM, n0 = tn * TN;
-    const size_t esz = (P == 0) ? sizeof(cplx) : (P == 1 ? sizeof(float) : sizeof(unsigned short));
+    const size_t esz = (P == 0) ? sizeof(cplx) : sizeof(float);
     const char* Ab = (const char*)d.A + (long long)b * d.sA_bat * esz;
     const char* Bb = (const char*)d.B + (long long)b * d.sB_bat * esz;
 
@@ -233,7 +202,7 @@ __global__ __launch_bounds__(256, 2) void zgemm_nt_kernel(const NtDesc* __restri
                 acc_im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i][s], bi[j][s], acc_im[i][j], 0, 0, 0);
                 acc_im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i][s], br[j][s], acc_im[i][j], 0, 0, 0);
               }
-        } else if constexpr (P == 1) {
+        } else {
           // lane k-set: 8*lk + s, s = 0..7
           const float* a = (const float*)sA;
           const float* bb = (const float*)sB;
@@ -266,48 +235,6 @@ __global__ __launch_bounds__(256, 2) void zgemm_nt_kernel(const NtDesc* __restri
                   c_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[i][s], bi[j][s], c_im[i][j], 0, 0, 0);
                   c_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[i][s], br[j][s], c_im[i][j], 0, 0, 0);
                 }
-          }
-        } else {
-          // one 16x16x32 MFMA per plane pair; lane k-set 8*lk .. 8*lk+7
-          const unsigned short* a = (const unsigned short*)sA;
-          const unsigned short* bb = (const unsigned short*)sB;
-          bf8 a_rh[2], a_rl[2], a_ih[2], a_il[2];
-#pragma unroll
-          for (int i = 0; i < 2; ++i) {
-            const int ra_ = wm * 32 + i * 16 + lr;
-            a_rh[i] = as_bf8(*(const u4*)&a[(0 * 64 + ra_) * PITCH + 8 * lk]);
-            a_rl[i] = as_bf8(*(const u4*)&a[(1 * 64 + ra_) * PITCH + 8 * lk]);
-            a_ih[i] = as_bf8(*(const u4*)&a[(2 * 64 + ra_) * PITCH + 8 * lk]);
-            a_il[i] = as_bf8(*(const u4*)&a[(3 * 64 + ra_) * PITCH + 8 * lk]);
-          }
-#pragma unroll
-          for (int j = 0; j < 2; ++j) {
-            const int rb_ = wn * 32 + j * 16 + lr;
-            const bf8 b_rh = as_bf8(*(const u4*)&bb[(0 * 64 + rb_) * PITCH + 8 * lk]);
-            const bf8 b_rl = as_bf8(*(const u4*)&bb[(1 * 64 + rb_) * PITCH + 8 * lk]);
-            const u4 bih = *(const u4*)&bb[(2 * 64 + rb_) * PITCH + 8 * lk];
-            const u4 bil = *(const u4*)&bb[(3 * 64 + rb_) * PITCH + 8 * lk];
-            const bf8 b_ih = as_bf8(bih), b_il = as_bf8(bil);
-            const bf8 b_nih = as_bf8(neg_bf16x8(bih)), b_nil = as_bf8(neg_bf16x8(bil));
-#pragma unroll
-            for (int i = 0; i < 2; ++i) {
-              f4 cr = c_re[i][j], ci = c_im[i][j];
-              // re = ar*br + ai*(-bi); small terms first (lo*hi, hi*lo), then hi*hi
-              cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_rl[i], b_rh, cr, 0, 0, 0);
-              cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_rh[i], b_rl, cr, 0, 0, 0);
-              cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_il[i], b_nih, cr, 0, 0, 0);
-              cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_ih[i], b_nil, cr, 0, 0, 0);
-              cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_rh[i], b_rh, cr, 0, 0, 0);
-              cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_ih[i], b_nih, cr, 0, 0, 0);
-              ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_rl[i], b_ih, ci, 0, 0, 0);
-              ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_rh[i], b_il, ci, 0, 0, 0);
-              ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_il[i], b_rh, ci, 0, 0, 0);
-              ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_ih[i], b_rl, ci, 0, 0, 0);
-              ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_rh[i], b_ih, ci, 0, 0, 0);
-              ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_ih[i], b_rh, ci, 0, 0, 0);
-              c_re[i][j] = cr;
-              c_im[i][j] = ci;
-            }
           }
         }
       }
@@ -348,14 +275,6 @@ __global__ __launch_bounds__(256, 2) void zgemm_nt_kernel(const NtDesc* __restri
               float* c = (float*)d.C;
               c[o] = in ? (float)vr : 0.f;
               c[d.c_plane + o] = in ? (float)vi : 0.f;
-            } else if constexpr (P == 2) {
-              unsigned short* c = (unsigned short*)d.C;
-              const float fr = in ? (float)vr : 0.f, fi = in ? (float)vi : 0.f;
-              const unsigned short rh = bf16_bits(fr), ih = bf16_bits(fi);
-              c[o] = rh;
-              c[d.c_plane + o] = bf16_bits(fr - bf16_val(rh));
-              c[2 * d.c_plane + o] = ih;
-              c[3 * d.c_plane + o] = bf16_bits(fi - bf16_val(ih));
             }
             continue;
           }

@@ -193,13 +193,6 @@ hipError_t bchol_setup_launch(const cplx* pi, cplx* a, int* perm, int* rank, dou
 hipError_t bchol_diag_launch(cplx* a, cplx* lt, const double* dmax, int* flag, int n, int nq, int jb,
                              double rtol, hipStream_t s);
 hipError_t bchol_panel_launch(cplx* a, cplx* lt, const int* flag, int n, int nq, int jb, hipStream_t s);
-// stage 1: Z = Pi~^-1 (P^T V P)   stage 2: W = P (Pi~^-1 Z^H) P^T
-hipError_t wsolve_launch(const cplx* v, cplx* z, cplx* w, const cplx* lt, const int* perm,
-                         const int* rank, int n, int nq, hipStream_t s);
-
-// yt[q][c][i] = (L^{-1})[i][c] for the leading rank x rank block (transposed
-// inverse of the factor); zeros for i < c.
-hipError_t linv_launch(const cplx* lt, const int* rank, cplx* yt, int n, int nq, hipStream_t s);
 // Blocked L^{-1} pieces: setup writes the row-major factor lrow (zero outside
 // the rank block) and clears yt; diag inverts the 64 x 64 diagonal block at
 // jb into yt (transposed) and yd[q] (row-major 64 x 64).  The off-diagonal

@@ -245,23 +245,32 @@ __global__ __launch_bounds__(256) void pair_kernel(PairArgs a) {
 // radix-2 transform across the lanes of a quad (DPP, no LDS).  Both
 // transforms have the sign +1: T^R = sum_k exp(+ik.R) T^k, then
 // out^q = scale * sum_R exp(+iq.R) |T^R|^2.
+// y_k = sum_j x_j exp(+2 pi i jk / R) for R <= 4: butterflies (no
+// multiplications except the two of radix 3)
 template <int R>
 __device__ inline void dft_pos(cplx (&x)[R]) {
-  if constexpr (R > 1) {
-    cplx y[R];
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-      double re = x[0].x, im = x[0].y;
-#pragma unroll
-      for (int j = 1; j < R; ++j) {
-        const double c = Rot<R>::c[(j * k) % R], sn = Rot<R>::s[(j * k) % R];
-        re = fma(x[j].x, c, fma(-x[j].y, sn, re));
-        im = fma(x[j].y, c, fma(x[j].x, sn, im));
-      }
-      y[k] = cmk(re, im);
-    }
-#pragma unroll
-    for (int k = 0; k < R; ++k) x[k] = y[k];
+  static_assert(R >= 1 && R <= 4, "register k transforms take mesh axes of length <= 4");
+  if constexpr (R == 2) {
+    const cplx a = x[0], b = x[1];
+    x[0] = cadd(a, b);
+    x[1] = csub(a, b);
+  } else if constexpr (R == 3) {
+    // y0 = x0 + s, y1,2 = (x0 - s/2) +- i (sqrt(3)/2) d, s = x1 + x2, d = x1 - x2
+    constexpr double h = 0.8660254037844386;
+    const cplx s_ = cadd(x[1], x[2]), d = csub(x[1], x[2]);
+    const cplx t = cmk(fma(-0.5, s_.x, x[0].x), fma(-0.5, s_.y, x[0].y));
+    x[0] = cadd(x[0], s_);
+    x[1] = cmk(fma(-h, d.y, t.x), fma(h, d.x, t.y));
+    x[2] = cmk(fma(h, d.y, t.x), fma(-h, d.x, t.y));
+  } else if constexpr (R == 4) {
+    // a = x0 + x2, b = x0 - x2, c = x1 + x3, d = x1 - x3:
+    // y0 = a + c, y2 = a - c, y1 = b + i d, y3 = b - i d
+    const cplx a = cadd(x[0], x[2]), b = csub(x[0], x[2]);
+    const cplx c = cadd(x[1], x[3]), d = csub(x[1], x[3]);
+    x[0] = cadd(a, c);
+    x[2] = csub(a, c);
+    x[1] = cmk(b.x - d.y, b.y + d.x);
+    x[3] = cmk(b.x + d.y, b.y - d.x);
   }
 }
 
@@ -306,7 +315,22 @@ __device__ inline cplx dpp_c(cplx v) { return cmk(dpp_d<CTRL>(v.x), dpp_d<CTRL>(
 template <int CTRL>
 __device__ inline cplx bfly(cplx v, bool hi) {
   const cplx p = dpp_c<CTRL>(v);
-  return hi ? csub(p, v) : cadd(v, p);
+  // selects, not branches: hi ? p - v : p + v
+  const double sg = hi ? -1.0 : 1.0;
+  return cmk(fma(sg, v.x, p.x), fma(sg, v.y, p.y));
+}
+
+// Last radix-2 step of a 4-point transform across a quad, from the lane's
+// value s and its partner's p: role 0 -> s + p, 1 -> p - s, 2 -> s + i p,
+// 3 -> p - i s.  Written as u + rho w with (u, w) = (s, p) or (p, s) and
+// rho in {1, -1, i, -i}, all by selects.
+__device__ inline cplx quad_out(cplx s, cplx p, int role) {
+  const bool odd = role & 1, rot = role & 2;
+  const cplx u = odd ? p : s, w = odd ? s : p;
+  // rho w: 1 -> w, -1 -> -w, i -> (-w.y, w.x), -i -> (w.y, -w.x)
+  const double wx = rot ? -w.y : w.x, wy = rot ? w.x : w.y;
+  const double sg = odd ? -1.0 : 1.0;
+  return cmk(fma(sg, wx, u.x), fma(sg, wy, u.y));
 }
 
 template <int M1, int M2, int M3>
@@ -329,13 +353,10 @@ __global__ __launch_bounds__(256) void kconv_reg_kernel(KconvArgs a) {
   } else if constexpr (M1 == 4) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const cplx s = bfly<DPP_XOR2>(x[v], k1 >= 2);      // x_j +- x_{j^2}
-      const cplx p = dpp_c<DPP_XOR1>(s);
+      const cplx s_ = bfly<DPP_XOR2>(x[v], k1 >= 2);     // x_j +- x_{j^2}
+      const cplx p = dpp_c<DPP_XOR1>(s_);
       // lanes 0..3 -> y0 = s0 + s1, y2 = s0 - s1, y1 = d0 + i d1, y3 = d0 - i d1
-      if (k1 == 0) x[v] = cadd(s, p);
-      else if (k1 == 1) x[v] = csub(p, s);
-      else if (k1 == 2) x[v] = cmk(s.x - p.y, s.y + p.x);
-      else x[v] = cmk(p.x + s.y, p.y - s.x);
+      x[v] = quad_out(s_, p, k1);
     }
   }
   // |T^R|^2
@@ -348,13 +369,10 @@ __global__ __launch_bounds__(256) void kconv_reg_kernel(KconvArgs a) {
   } else if constexpr (M1 == 4) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const cplx s = bfly<DPP_XOR1>(x[v], k1 & 1);       // a, b (lanes 0, 1), c, d (lanes 2, 3)
-      const cplx p = dpp_c<DPP_XOR2>(s);
+      const cplx s_ = bfly<DPP_XOR1>(x[v], k1 & 1);      // a, b (lanes 0, 1), c, d (lanes 2, 3)
+      const cplx p = dpp_c<DPP_XOR2>(s_);
       // y0 = a + c, y1 = b + i d, y2 = a - c, y3 = b - i d
-      if (k1 == 0) x[v] = cadd(s, p);
-      else if (k1 == 2) x[v] = csub(p, s);
-      else if (k1 == 1) x[v] = cmk(s.x - p.y, s.y + p.x);
-      else x[v] = cmk(p.x + s.y, p.y - s.x);
+      x[v] = quad_out(s_, p, ((k1 & 1) << 1) | (k1 >> 1));
     }
   }
   dft23_pos<M2, M3>(x);
@@ -470,12 +488,28 @@ __global__ __launch_bounds__(256, 2) void pair_reg_kernel(PairArgs a, int nblock
   const cplx* bq = a.psi + (long long)(col + q) * a.n_ip + (in ? I : 0);
   const long long rstride = (long long)a.ncol * a.n_ip;
   float2 x[NK];
+  // loads in batches of RB lattice vectors, all issued before the first use
+  // (left to itself the compiler waits for every pair of loads in turn)
+  constexpr int RB = NK < 8 ? NK : 8;
 #pragma unroll
-  for (int R = 0; R < NK; ++R) {
-    const cplx u = bp[R * rstride], v = bq[R * rstride];
-    // conj(u) v
-    const double re = u.x * v.x + u.y * v.y, im = u.x * v.y - u.y * v.x;
-    x[R] = in ? make_float2((float)re, (float)im) : make_float2(0.f, 0.f);
+  for (int R0 = 0; R0 < NK; R0 += RB) {
+    cplx u[RB], v[RB];
+#pragma unroll
+    for (int j = 0; j < RB; ++j) {
+      if (R0 + j < NK) {
+        u[j] = bp[(R0 + j) * rstride];
+        v[j] = bq[(R0 + j) * rstride];
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < RB; ++j) {
+      if (R0 + j < NK) {
+        // conj(u) v
+        const double re = u[j].x * v[j].x + u[j].y * v[j].y, im = u[j].x * v[j].y - u[j].y * v[j].x;
+        x[R0 + j] = in ? make_float2((float)re, (float)im) : make_float2(0.f, 0.f);
+      }
+    }
   }
   mesh_dft_reg<M1, M2, M3>(x);
   const float sc = (float)a.scale;
