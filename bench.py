@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--no-fp64-ref", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=25.0)
+    ap.add_argument("--max-batch", type=int, default=0,
+                    help="fragments per serving batch (0: all of a step in one batch)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device copy first (reference for HBM byte counters)")
     return ap.parse_args()
@@ -81,9 +83,9 @@ def stage_work(stage, cfg, nfs, prec):
     return None
 
 
-KERNEL_OF_STAGE = {"frag_eri": ("zgemm_nt_kernel<0, false, true, 3>", "{x}false, true, 3>"),
-                   "frag_u": ("zgemm_nt_kernel<0, false, false, 2>", "{x}false, false, 2>"),
-                   "v_gemm": ("zgemm_nt_kernel<0, false, true, 1>", "{x}false, true, 1>"),
+KERNEL_OF_STAGE = {"frag_eri": ("zgemm_nt_kernel<0, false, true, 3>", "{x}false, true, 3"),
+                   "frag_u": ("zgemm_nt_kernel<0, false, false, 2>", "{x}false, false, 2"),
+                   "v_gemm": ("zgemm_nt_kernel<0, false, true, 1>", "{x}false, true, 1"),
                    "frag_pair": ("pair_kernel(PairArgs)", "pair_reg_kernel<"),
                    "rhs_t": ("rhs_t_kernel<", "rhs_t_kernel<"),
                    "rhs_kconv": ("kconv_reg_kernel<", "kconv_reg_kernel<"),
@@ -232,7 +234,7 @@ def main():
     batch_bytes = 16 * (cfg.n_k * cfg.n_orb * sum(nfs) + cfg.n_k * cfg.n_ip * sum(nfs)
                         + 2 * cfg.n_k * cfg.n_ip * sum(n * n for n in nfs)) + (1 << 26)
     budget = 2 * max(batch_bytes, per_req)
-    ctx.serve_start(max_inflight=2, max_batch=len(frags), budget_bytes=budget)
+    ctx.serve_start(max_inflight=2, max_batch=args.max_batch or len(frags), budget_bytes=budget)
 
     def step(prec, outs):
         ctx.fit()

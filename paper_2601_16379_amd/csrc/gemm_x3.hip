@@ -22,7 +22,7 @@
 //
 // Rows beyond M / N are loaded from the last valid row (their outputs are
 // dropped); 16-byte vectors that start beyond the segment length are copied
-// from a zero block.  One K segment per launch; epilogues as in the
+// from a zero block.  Each lane's copy sources are computed once per tile.  One K segment per launch; epilogues as in the
 // 128-tile FP32 kernel (split store, FP64 accumulation across launches).
 #include "kernels.hpp"
 
@@ -67,18 +67,19 @@ __device__ inline int isqrt_floor(long long x) {
 __device__ __attribute__((aligned(16))) unsigned short kZeroVec[8];
 
 // Issue the copies of one operand's stage (128 rows x 128 bytes) into LDS at
-// `dst`: 16 wave-instructions of 8 rows, 4 per wave.  rowoff[j]: logical
-// element offset of the (clamped) row handled by this lane in the wave's
-// j-th instruction; gslot[j]: the 16-byte slot of that row this lane fetches
-// (the one whose LDS position is this lane's).
-__device__ inline void stage_copy(const unsigned short* base, const long long (&rowoff)[NCOPY],
-                                  const int (&gslot)[NCOPY], int k0, int kcur, char* dst, int wave) {
+// `dst`: 16 wave-instructions of 8 rows, 4 per wave.  src[j]: this lane's
+// 16-byte source of the wave's j-th instruction at k = 0 (row base plus the
+// slot gslot[j] whose LDS position is this lane's); the address advances by
+// 4 u16 an element of k.  In the last stage of a segment, vectors that start
+// at or past its end are copied from the zero block.
+__device__ inline void stage_copy(const unsigned short* const (&src)[NCOPY], const int (&gslot)[NCOPY], int k0,
+                                  int kcur, char* dst, int wave) {
+  const bool tail = k0 + XK > kcur;       // the same for the whole workgroup
 #pragma unroll
   for (int j = 0; j < NCOPY; ++j) {
     const int rc = wave + 4 * j;          // rows rc*8 .. rc*8+7
-    const int kg = k0 + 8 * (gslot[j] >> 2);
-    const unsigned short* g =
-        (kg < kcur && rowoff[j] >= 0) ? base + 4 * (rowoff[j] + k0) + 8 * gslot[j] : kZeroVec;
+    const unsigned short* g = src[j] + 4 * k0;
+    if (tail && k0 + 8 * (gslot[j] >> 2) >= kcur) g = kZeroVec;
     __builtin_amdgcn_global_load_lds((glb_void*)g, (lds_void*)(dst + rc * 8 * ROW_B), 16, 0, 0);
   }
 }
@@ -197,10 +198,9 @@ __device__ inline void mma_half(const Frag<NI, NJ>& f, int j, f16v (&c_re)[NI][N
 // 32 x 32 block of the one 32-row (32-column) strip, so edge tiles cost a
 // quarter of the matrix-core work.
 template <int NI, int NJ, bool A_CONJ, bool B_CONJ>
-__device__ inline void tile_body(const NtDesc& d, int b, int m0, int n0, const unsigned short* As,
-                                 const unsigned short* Bs, int kcur, const long long (&aoff)[NCOPY],
-                                 const long long (&boff)[NCOPY], const int (&gslot)[NCOPY], int rb0, int cb0,
-                                 char* smem, int wave, int lane) {
+__device__ inline void tile_body(const NtDesc& d, int b, int m0, int n0, int kcur,
+                                 const unsigned short* const (&asrc)[NCOPY], const unsigned short* const (&bsrc)[NCOPY],
+                                 const int (&gslot)[NCOPY], int rb0, int cb0, char* smem, int wave, int lane) {
   const int lr = lane & 31, lk = lane >> 5;
   f16v c_re[NI][NJ], c_im[NI][NJ];
 #pragma unroll
@@ -219,8 +219,8 @@ __device__ inline void tile_body(const NtDesc& d, int b, int m0, int n0, const u
 #pragma unroll
     for (int s = 0; s < NBUF - 1; ++s)
       if (s < nst) {
-        stage_copy(As, aoff, gslot, s * XK, kcur, smem + s * STAGE_B, wave);
-        stage_copy(Bs, boff, gslot, s * XK, kcur, smem + s * STAGE_B + OPER_B, wave);
+        stage_copy(asrc, gslot, s * XK, kcur, smem + s * STAGE_B, wave);
+        stage_copy(bsrc, gslot, s * XK, kcur, smem + s * STAGE_B + OPER_B, wave);
       }
     // stage 0 landed when at most the copies of the later prologue stages are in flight
     wait_copies(min(NBUF - 2, nst - 1));
@@ -247,8 +247,8 @@ __device__ inline void tile_body(const NtDesc& d, int b, int m0, int n0, const u
       asm volatile("" ::: "memory");                                                               \
       if (s_ + NBUF - 1 < nst) {                                                                   \
         char* dst = smem + ((s_ + NBUF - 1) % NBUF) * STAGE_B;                                     \
-        stage_copy(As, aoff, gslot, (s_ + NBUF - 1) * XK, kcur, dst, wave);                        \
-        stage_copy(Bs, boff, gslot, (s_ + NBUF - 1) * XK, kcur, dst + OPER_B, wave);               \
+        stage_copy(asrc, gslot, (s_ + NBUF - 1) * XK, kcur, dst, wave);                            \
+        stage_copy(bsrc, gslot, (s_ + NBUF - 1) * XK, kcur, dst + OPER_B, wave);                   \
       }                                                                                            \
       read_frags_a(smem + ((s_ + 1) % NBUF) * STAGE_B, NXT, rb0, lr, lk);                          \
     }                                                                                              \
@@ -354,24 +354,25 @@ __global__ __launch_bounds__(XNT) void zgemm_x3_kernel(const NtDesc* __restrict_
     const unsigned short* Bs = (const unsigned short*)d.B + 4 * (b * d.sB_bat + (long long)seg * d.sB_seg);
     const int kcur = (seg == d.nseg - 1) ? d.Klast : d.Kseg;
 
-    // this lane's rows and slots in its copy instructions; rows past M / N
-    // are copied from the zero block (offset -1)
-    long long aoff[NCOPY], boff[NCOPY];
+    // this lane's sources and slots in its copy instructions; rows past M / N
+    // read the last valid row (their outputs are not stored)
+    const unsigned short* asrc[NCOPY];
+    const unsigned short* bsrc[NCOPY];
     int gslot[NCOPY];
 #pragma unroll
     for (int j = 0; j < NCOPY; ++j) {
       const int row = (wave + 4 * j) * 8 + (lane >> 3);
       gslot[j] = lds_slot(row, lane & 7);     // the slot whose LDS position is lane & 7
-      aoff[j] = m0 + row < d.M ? (long long)(m0 + row) * d.lda : -1;
-      boff[j] = n0 + row < d.N ? (long long)(n0 + row) * d.ldb : -1;
+      const int ra = min(m0 + row, d.M - 1), rb = min(n0 + row, d.N - 1);
+      asrc[j] = As + 4 * ((long long)ra * d.lda) + 8 * gslot[j];
+      bsrc[j] = Bs + 4 * ((long long)rb * d.ldb) + 8 * gslot[j];
     }
     if (d.M - m0 <= 32)
-      tile_body<1, 1, A_CONJ, B_CONJ>(d, b, m0, n0, As, Bs, kcur, aoff, boff, gslot, 0, wave * 32, smem, wave, lane);
+      tile_body<1, 1, A_CONJ, B_CONJ>(d, b, m0, n0, kcur, asrc, bsrc, gslot, 0, wave * 32, smem, wave, lane);
     else if (d.N - n0 <= 32)
-      tile_body<1, 1, A_CONJ, B_CONJ>(d, b, m0, n0, As, Bs, kcur, aoff, boff, gslot, wave * 32, 0, smem, wave, lane);
+      tile_body<1, 1, A_CONJ, B_CONJ>(d, b, m0, n0, kcur, asrc, bsrc, gslot, wave * 32, 0, smem, wave, lane);
     else
-      tile_body<2, 2, A_CONJ, B_CONJ>(d, b, m0, n0, As, Bs, kcur, aoff, boff, gslot, wm * 64, wn * 64, smem, wave,
-                                      lane);
+      tile_body<2, 2, A_CONJ, B_CONJ>(d, b, m0, n0, kcur, asrc, bsrc, gslot, wm * 64, wn * 64, smem, wave, lane);
   }
 }
 
