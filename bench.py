@@ -74,8 +74,8 @@ def stage_work(stage, cfg, nfs, prec):
         return "fp64", 8.0 * nk * nip ** 3 / 3 / 1e12, "TFLOP", PEAK["fp64"]
     if stage == "pinv":       # L^{-1} (n^3/6) and G = Y^H Y lower half (n^3/2) complex MACs
         return "fp64", 8.0 * nk * nip ** 3 * (1 / 6 + 1 / 2) / 1e12, "TFLOP", PEAK["fp64"]
-    if stage == "w_solve":    # W' = (G V') G: two full complex products
-        return "fp64", 2 * 8.0 * nk * nip ** 3 / 1e12, "TFLOP", PEAK["fp64"]
+    if stage == "w_solve":    # W' = (G V') G: one full product, one Hermitian (lower half)
+        return "fp64", 1.5 * 8.0 * nk * nip ** 3 / 1e12, "TFLOP", PEAK["fp64"]
     if stage == "metric_t":
         return "mfma", 8.0 * nk * nip * nip * norb / 2 / 1e12, "TFLOP", PEAK["fp64"]
     if stage == "frag_t":

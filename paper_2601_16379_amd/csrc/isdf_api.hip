@@ -661,8 +661,8 @@ void do_kernel(isdf_ctx c, int prec) {
     };
     // T1 = G V'  (V' Hermitian: V'[k][n] = conj(V'[n][k]))
     prod(c->work3.as<cplx>(), c->w.as<cplx>(), c->work1.as<cplx>(), 2, 0);
-    // W' = T1 G  (G Hermitian)
-    prod(c->work1.as<cplx>(), c->work3.as<cplx>(), c->work2.as<cplx>(), 2, 0);
+    // W' = T1 G  (G Hermitian); W' = G V' G is Hermitian: lower tiles, mirrored
+    prod(c->work1.as<cplx>(), c->work3.as<cplx>(), c->work2.as<cplx>(), 2, 1);
     HIPCHK(permute_launch(c->work2.as<cplx>(), c->w.as<cplx>(), c->perm.as<int>(), c->rank.as<int>(),
                           nip, nk, 1, s));
   }

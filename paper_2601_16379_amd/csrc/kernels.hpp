@@ -93,7 +93,10 @@ hipError_t x3_launch(int conj, const NtDesc* descs_dev, int ndesc, long long tot
 constexpr int BIG_TILE = 128;
 // mixed-precision fragment contraction: q values summed in FP32 per launch
 // (one contiguous K range of ERI_QGROUP * ld), FP64 across launches
-constexpr int ERI_QGROUP = 8;
+// (32: the max ERI error at the benchmark workload was 2.426e-7 Eh with 8,
+// 2.428e-7 with 16 and 2.429e-7 with 32 q per launch, set by the V^q
+// rounding; the contraction took 22.8, 22.1 and 21.7 ms)
+constexpr int ERI_QGROUP = 32;
 
 // W^q (c128 [q][n][n]) -> transposed copies Wt[q][J][I] = W[q][I][J] with row
 // pitch ld in c128, two-float-plane and four-bf16-plane formats (any output
