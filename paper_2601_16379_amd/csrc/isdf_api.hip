@@ -783,6 +783,7 @@ void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn
   HIPCHK(copy_cols_batch_launch(ws.arena.put(srcs.data(), srcs.size(), s), Call, nk, norb,
                                 ws.arena.put(p.nf.data(), p.nf.size(), s),
                                 ws.arena.put(p.col.data(), p.col.size(), s), (int)fr.size(), maxnf, p.ncol, s));
+  const bool psi32 = prec != 0 && pair_reg_supported(prec, c->m[0], c->m[1], c->m[2]);
   if (timed) ws.timer.begin("frag_t", s);
   // T^k_{pI} = sum_mu C^k_{mu p} X^k_{I mu}   (Algorithm 2, stored [k][p][I])
   {
@@ -807,6 +808,9 @@ void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn
     a.mode = 1;
     a.sign = +1;
     a.scale = 1.0 / std::sqrt((double)nk);
+    // the register pair transform of the mixed precisions reads psi as
+    // complex FP32, staged in the U region (free until U^q is formed)
+    if (psi32) a.out32 = (float2*)Uq;
     HIPCHK(kconv_launch(a, s));
   }
   if (timed) ws.timer.end("frag_t", s);
@@ -830,6 +834,7 @@ void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn
     PairArgs a;
     memset(&a, 0, sizeof(a));
     a.psi = Tf;
+    a.psi32 = psi32 ? (const float2*)Uq : nullptr;
     a.out = Mq;
     a.blocks = ws.arena.put(blocks.data(), blocks.size(), s);
     a.frag_nf = ws.arena.put(p.nf.data(), p.nf.size(), s);

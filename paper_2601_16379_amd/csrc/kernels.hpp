@@ -118,6 +118,7 @@ struct KconvArgs {
   int mode;        // 0: out = scale * DFT_{+}( |DFT_{+}(in)|^2 ) ; 1: out = scale * DFT_{sign}(in)
   int sign;        // +1 / -1 for mode 1
   double scale;
+  float2* out32;   // mode 1: when set, the result goes here as complex FP32 (same offsets), not to out
 };
 hipError_t kconv_launch(const KconvArgs& a, hipStream_t s);
 
@@ -129,6 +130,7 @@ hipError_t kconv_launch(const KconvArgs& a, hipStream_t s);
 struct PairBlock { int frag; int pair0; int npair; };
 struct PairArgs {
   const cplx* psi;         // [N_R][ncol][n_ip]
+  const float2* psi32;     // register path: when set, psi as complex FP32 (same layout) is read instead
   void* out;               // element (q, pair, I) at q*q_stride + pair*p_stride + I (per plane)
   const PairBlock* blocks; // device
   const int* frag_nf; const int* frag_col; const long long* frag_pair;  // device
