@@ -130,7 +130,7 @@ hipError_t kconv_launch(const KconvArgs& a, hipStream_t s);
 struct PairBlock { int frag; int pair0; int npair; };
 struct PairArgs {
   const cplx* psi;         // [N_R][ncol][n_ip]
-  const float2* psi32;     // register path: when set, psi as complex FP32 (same layout) is read instead
+  const float2* psi32;     // register path (required there): psi as complex FP32, same layout
   void* out;               // element (q, pair, I) at q*q_stride + pair*p_stride + I (per plane)
   const PairBlock* blocks; // device
   const int* frag_nf; const int* frag_col; const long long* frag_pair;  // device

@@ -454,13 +454,15 @@ __device__ inline void mesh_dft_reg(float2 (&x)[M1 * M2 * M3]) {
 }
 
 // One wave per (pair (p, q) of a fragment, 64 consecutive interpolation
-// points): lane I loads psi_p(r_I + R) and psi_q(r_I + R) for every R (each
-// load instruction reads 64 consecutive I), forms conj(psi_p) psi_q (from
-// complex FP32 psi when psi32 is given, else an FP64 product rounded once to
-// FP32), transforms R -> q in registers and writes
+// points): lane I loads psi_p(r_I + R) and psi_q(r_I + R) for every R from the
+// complex FP32 copy of psi (each load instruction reads 64 consecutive I),
+// forms conj(psi_p) psi_q in FP32, transforms R -> q in registers and writes
 // the N_k outputs of its I (each store instruction covers 64 consecutive I
 // of one row).  Workgroups are mapped XCD-contiguously so the psi rows of
 // one fragment and I chunk stay in one L2 while all its pairs use them.
+#ifndef PAIR_RB
+#define PAIR_RB 8
+#endif
 template <int M1, int M2, int M3>
 __global__ __launch_bounds__(256, 2) void pair_reg_kernel(PairArgs a, int nblocks) {
   constexpr int NK = M1 * M2 * M3;
@@ -487,56 +489,31 @@ __global__ __launch_bounds__(256, 2) void pair_reg_kernel(PairArgs a, int nblock
   const int I = chunk * 64 + lane;
   const bool in = I < a.n_ip;
   const int col = a.frag_col[f];
-  const cplx* bp = a.psi + (long long)(col + p) * a.n_ip + (in ? I : 0);
-  const cplx* bq = a.psi + (long long)(col + q) * a.n_ip + (in ? I : 0);
   const long long rstride = (long long)a.ncol * a.n_ip;
   float2 x[NK];
   // loads in batches of RB lattice vectors, all issued before the first use
   // (left to itself the compiler waits for every pair of loads in turn)
-  if (a.psi32) {
-    // complex FP32 psi (the product is rounded to FP32 either way)
-    const float2* fp = a.psi32 + (long long)(col + p) * a.n_ip + (in ? I : 0);
-    const float2* fq = a.psi32 + (long long)(col + q) * a.n_ip + (in ? I : 0);
-    constexpr int RB = NK < 16 ? NK : 16;
+  // complex FP32 psi (the register path serves the mixed precisions only)
+  const float2* fp = a.psi32 + (long long)(col + p) * a.n_ip + (in ? I : 0);
+  const float2* fq = a.psi32 + (long long)(col + q) * a.n_ip + (in ? I : 0);
+  constexpr int RB = NK < PAIR_RB ? NK : PAIR_RB;
 #pragma unroll
-    for (int R0 = 0; R0 < NK; R0 += RB) {
-      float2 u[RB], v[RB];
+  for (int R0 = 0; R0 < NK; R0 += RB) {
+    float2 u[RB], v[RB];
 #pragma unroll
-      for (int j = 0; j < RB; ++j) {
-        if (R0 + j < NK) {
-          u[j] = fp[(R0 + j) * rstride];
-          v[j] = fq[(R0 + j) * rstride];
-        }
-      }
-      __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int j = 0; j < RB; ++j) {
-        if (R0 + j < NK) {
-          const float re = fmaf(u[j].x, v[j].x, u[j].y * v[j].y), im = fmaf(u[j].x, v[j].y, -(u[j].y * v[j].x));
-          x[R0 + j] = in ? make_float2(re, im) : make_float2(0.f, 0.f);
-        }
+    for (int j = 0; j < RB; ++j) {
+      if (R0 + j < NK) {
+        u[j] = fp[(R0 + j) * rstride];
+        v[j] = fq[(R0 + j) * rstride];
       }
     }
-  } else {
-    constexpr int RB = NK < 8 ? NK : 8;
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int R0 = 0; R0 < NK; R0 += RB) {
-      cplx u[RB], v[RB];
-#pragma unroll
-      for (int j = 0; j < RB; ++j) {
-        if (R0 + j < NK) {
-          u[j] = bp[(R0 + j) * rstride];
-          v[j] = bq[(R0 + j) * rstride];
-        }
-      }
-      __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int j = 0; j < RB; ++j) {
-        if (R0 + j < NK) {
-          // conj(u) v
-          const double re = u[j].x * v[j].x + u[j].y * v[j].y, im = u[j].x * v[j].y - u[j].y * v[j].x;
-          x[R0 + j] = in ? make_float2((float)re, (float)im) : make_float2(0.f, 0.f);
-        }
+    for (int j = 0; j < RB; ++j) {
+      if (R0 + j < NK) {
+        // conj(u) v
+        const float re = fmaf(u[j].x, v[j].x, u[j].y * v[j].y), im = fmaf(u[j].x, v[j].y, -(u[j].y * v[j].x));
+        x[R0 + j] = in ? make_float2(re, im) : make_float2(0.f, 0.f);
       }
     }
   }
@@ -643,6 +620,7 @@ bool pair_reg_supported(int fmt, int m1, int m2, int m3) {
 
 hipError_t pair_launch(const PairArgs& a, hipStream_t s) {
   if (pair_reg_supported(a.fmt, a.m1, a.m2, a.m3)) {
+    if (!a.psi32 || !a.item_off) return hipErrorInvalidValue;
     switch (a.m1) {
       case 1: return pair_reg_m2<1>(a, s);
       case 2: return pair_reg_m2<2>(a, s);
