@@ -8,22 +8,26 @@
 // real ones, so one 32x32 complex block costs 12 MFMAs per 16 k.
 //
 // Workgroup: 256 threads (4 waves, 2 x 2), 128 x 128 output tile, each wave
-// 64 x 64 (2 x 2 blocks of 32 x 32).  K advances in stages of 16 (one MFMA
-// step).  In the operand format (bf16 hi/lo interleaved by 8-element groups)
-// the 16 k of one row are 128 contiguous bytes, so a stage of a 128-row
-// operand tile is 128 whole cache lines; it is copied from global memory
-// straight into LDS (global_load_lds_dwordx4, no register staging) into a
-// ring of four LDS buffers, three stages ahead of the one being multiplied,
-// one barrier per stage.  The fragments of the next stage are read from LDS
-// while the MFMAs of the current one run.  In LDS a row keeps its eight
-// 16-byte slots (2 k-groups x 4 planes) in an order XOR-permuted by the row,
-// so that the 32x32 fragment reads (lane -> row l%32, k-group l/32) hit
-// distinct banks.
+// 64 x 64 (2 x 2 blocks of 32 x 32); two workgroups per CU.  K advances in
+// stages of 16 (one MFMA step).  In the operand format (bf16 hi/lo
+// interleaved by 8-element groups) the 16 k of one row are 128 contiguous
+// bytes, so a stage of a 128-row operand tile is 128 whole cache lines; it is
+// copied from global memory straight into LDS (global_load_lds_dwordx4, no
+// register staging) into one of two LDS stage buffers, two stages ahead of
+// the one being multiplied.  Each stage: wait for its copies, barrier, read
+// the fragments, barrier (the buffer then takes the copy two stages ahead),
+// MFMAs.  The stalls of one workgroup's waves are filled by the other
+// workgroup's MFMAs (with one workgroup per CU and the next stage's
+// fragments prefetched instead, the matrix cores were busy about half the
+// time).  In LDS a row keeps its eight 16-byte slots (2 k-groups x 4 planes)
+// in an order XOR-permuted by the row, so that the 32x32 fragment reads
+// (lane -> row l%32, k-group l/32) hit distinct banks.
 //
 // Rows beyond M / N are loaded from the last valid row (their outputs are
 // dropped); 16-byte vectors that start beyond the segment length are copied
-// from a zero block.  Each lane's copy sources are computed once per tile.  One K segment per launch; epilogues as in the
-// 128-tile FP32 kernel (split store, FP64 accumulation across launches).
+// from a zero block.  Each lane's copy sources are computed once per tile.
+// One K segment per launch; epilogues as in the 128-tile FP32 kernel (split
+// store, FP64 accumulation across launches).
 #include "kernels.hpp"
 
 namespace {
@@ -36,7 +40,7 @@ typedef __attribute__((address_space(1))) void glb_void;
 
 constexpr int XT = 128;               // tile edge
 constexpr int XK = 16;                // k per stage
-constexpr int NBUF = 4;               // LDS ring of stages
+constexpr int NBUF = 2;               // LDS stages (two workgroups per CU)
 constexpr int XNT = 256;              // threads
 constexpr int ROW_B = XK * 8;          // bytes of one row of one stage (128)
 constexpr int OPER_B = XT * ROW_B;     // one operand tile of a stage (16 KB)
@@ -50,8 +54,8 @@ __device__ inline bf8 as_bf8(u4 v) { return __builtin_bit_cast(bf8, v); }
 
 // wait until at most n stages of copies (2 * NCOPY instructions each) are in flight
 __device__ inline void wait_copies(int n) {
-  if (n >= 2) asm volatile("s_waitcnt vmcnt(16)" ::: "memory");
-  else if (n == 1) asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
+  static_assert(2 * NCOPY == 8, "vmcnt below counts 8 copies a stage");
+  if (n >= 1) asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
   else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
 
@@ -116,9 +120,8 @@ __device__ inline void read_frags_b(const char* buf, Frag<NI, NJ>& f, int cb0, i
   }
 }
 
-// Pin a stage's fragments: their reads must have completed here, and later
-// uses do not depend on the loads any more (so the compiler does not place
-// its wait for them after the next stage's reads have been queued).
+// Pin a stage's fragments: their reads have completed here, and later uses
+// do not depend on the loads any more.
 template <int NI, int NJ>
 __device__ inline void settle(Frag<NI, NJ>& f) {
 #pragma unroll
@@ -192,92 +195,30 @@ __device__ inline void mma_half(const Frag<NI, NJ>& f, int j, f16v (&c_re)[NI][N
 }
 #undef X3_TERMS
 
-// K loop and epilogue of one tile.  The wave owns the (NI*32) x (NJ*32)
-// block at rows rb0, columns cb0 of the tile: 64 x 64 in full tiles (2 x 2
-// waves); in tiles with at most 32 valid rows (columns) each wave takes a
-// 32 x 32 block of the one 32-row (32-column) strip, so edge tiles cost a
-// quarter of the matrix-core work.
-template <int NI, int NJ, bool A_CONJ, bool B_CONJ>
-__device__ inline void tile_body(const NtDesc& d, int b, int m0, int n0, int kcur,
-                                 const unsigned short* const (&asrc)[NCOPY], const unsigned short* const (&bsrc)[NCOPY],
-                                 const int (&gslot)[NCOPY], int rb0, int cb0, char* smem, int wave, int lane) {
+// Epilogue of one tile (32x32 layout: lane l, register v -> row
+// 8(v/4) + 4(l/32) + v%4, column l%32).  epi 3: each wave assembles its
+// block 32 rows at a time in LDS (16 KB a wave) in the operand format (a row
+// of NJ*32 points is NJ*256 contiguous bytes) and writes it with 16-byte
+// stores; otherwise FP64 read-modify-write accumulation.
+template <int NI, int NJ>
+__device__ inline void tile_epilogue(const NtDesc& d, int b, int m0, int n0, int rb0, int cb0,
+                                     const f16v (&c_re)[NI][NJ], const f16v (&c_im)[NI][NJ], char* smem, int wave,
+                                     int lane) {
   const int lr = lane & 31, lk = lane >> 5;
-  f16v c_re[NI][NJ], c_im[NI][NJ];
-#pragma unroll
-  for (int i = 0; i < NI; ++i)
-#pragma unroll
-    for (int j = 0; j < NJ; ++j)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        c_re[i][j][v] = 0.f;
-        c_im[i][j][v] = 0.f;
-      }
-
-    // stages of 16 k, rounded up to an even count (the extra one is all zeros)
-    const int nst = (((kcur + XK - 1) / XK) + 1) & ~1;
-    __syncthreads();                      // LDS of the previous tile no longer read
-#pragma unroll
-    for (int s = 0; s < NBUF - 1; ++s)
-      if (s < nst) {
-        stage_copy(asrc, gslot, s * XK, kcur, smem + s * STAGE_B, wave);
-        stage_copy(bsrc, gslot, s * XK, kcur, smem + s * STAGE_B + OPER_B, wave);
-      }
-    // stage 0 landed when at most the copies of the later prologue stages are in flight
-    wait_copies(min(NBUF - 2, nst - 1));
-    __builtin_amdgcn_s_barrier();
-    asm volatile("" ::: "memory");
-    Frag<NI, NJ> f0, f1;
-    read_frags_a(smem, f0, rb0, lr, lk);
-    read_frags_b(smem, f0, cb0, lr, lk);
-    // Stage s: make stage s+1 visible, start the copy NBUF-1 stages ahead,
-    // then the MFMAs of stage s (fragments read during the previous stage)
-    // in two halves, each behind half of the fragment reads of stage s+1, so
-    // the LDS latency hides behind them.
-#define X3_STEP(S, CUR, NXT)                                                                        \
-  {                                                                                                \
-    const int s_ = (S);                                                                            \
-    /* CUR's fragment reads (issued a stage ago) complete here, before NXT's  */                    \
-    /* reads are queued behind them; nothing is scheduled across this point    */                   \
-    __builtin_amdgcn_sched_barrier(0);                                                             \
-    settle(CUR);                                                                                   \
-    if (s_ + 1 < nst) {                                                                            \
-      wait_copies(min(NBUF - 3, nst - s_ - 2));  /* stage s+1 landed */                           \
-      /* bare s_barrier: __syncthreads() would also wait for the copies in flight */                \
-      __builtin_amdgcn_s_barrier();                                                                \
-      asm volatile("" ::: "memory");                                                               \
-      if (s_ + NBUF - 1 < nst) {                                                                   \
-        char* dst = smem + ((s_ + NBUF - 1) % NBUF) * STAGE_B;                                     \
-        stage_copy(asrc, gslot, (s_ + NBUF - 1) * XK, kcur, dst, wave);                            \
-        stage_copy(bsrc, gslot, (s_ + NBUF - 1) * XK, kcur, dst + OPER_B, wave);                   \
-      }                                                                                            \
-      read_frags_a(smem + ((s_ + 1) % NBUF) * STAGE_B, NXT, rb0, lr, lk);                          \
-    }                                                                                              \
-    mma_half<NI, NJ, A_CONJ, B_CONJ>(CUR, 0, c_re, c_im);                                          \
-    if (s_ + 1 < nst) read_frags_b(smem + ((s_ + 1) % NBUF) * STAGE_B, NXT, cb0, lr, lk);          \
-    if (NJ == 2) mma_half<NI, NJ, A_CONJ, B_CONJ>(CUR, NJ - 1, c_re, c_im);                        \
-  }
-    for (int s = 0; s < nst; s += 2) {
-      X3_STEP(s, f0, f1)
-      X3_STEP(s + 1, f1, f0)
-    }
-#undef X3_STEP
-
-    // ---- epilogue (32x32 layout: lane l, register v -> row 8(v/4) + 4(l/32) + v%4, column l%32) ----
   if (d.epi == 3) {
-    // split store: each wave assembles its block in LDS in the operand
-    // format (a row of NJ*32 points is NJ*256 contiguous bytes) and writes it
-    // with 16-byte stores
     __syncthreads();                      // every wave is past its last stage reads
-    unsigned short* st = (unsigned short*)(smem + wave * 32768);
+    unsigned short* st = (unsigned short*)(smem + wave * 16384);
     const int npad = d.npad ? d.npad : (int)d.ldc;
     constexpr int RU = NJ * 128;          // u16 per staged row
+    constexpr int PPR = NJ * 16;          // 16-byte parts per row
+    unsigned short* C = (unsigned short*)d.C + 4 * ((long long)b * d.sC_bat + n0 + cb0);
 #pragma unroll
-    for (int i = 0; i < NI; ++i)
+    for (int i = 0; i < NI; ++i) {
 #pragma unroll
       for (int j = 0; j < NJ; ++j)
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
-          const int ml = i * 32 + 8 * (v >> 2) + 4 * lk + (v & 3);
+          const int ml = 8 * (v >> 2) + 4 * lk + (v & 3);
           const int nl = j * 32 + lr;
           const bool in = n0 + cb0 + nl < d.N;
           const float re = in ? c_re[i][j][v] : 0.f, im = in ? c_im[i][j][v] : 0.f;
@@ -288,15 +229,15 @@ __device__ inline void tile_body(const NtDesc& d, int b, int m0, int n0, int kcu
           e[16] = ih;
           e[24] = bf16_bits_of(im - bf16_value(ih));
         }
-    __builtin_amdgcn_wave_barrier();
-    unsigned short* C = (unsigned short*)d.C + 4 * ((long long)b * d.sC_bat + n0 + cb0);
-    constexpr int PPR = NJ * 16;          // 16-byte parts per row
+      __builtin_amdgcn_wave_barrier();
 #pragma unroll 4
-    for (int h = 0; h < NI * NJ * 8; ++h) {
-      const int c = h * 64 + lane, ml = c / PPR, part = c % PPR;
-      const int m = m0 + rb0 + ml;
-      if (m < d.M && n0 + cb0 + (part >> 2) * 8 < npad)
-        *(u4*)(C + 4 * (long long)m * d.ldc + part * 8) = *(const u4*)(st + ml * RU + part * 8);
+      for (int h = 0; h < NJ * 8; ++h) {
+        const int c = h * 64 + lane, ml = c / PPR, part = c % PPR;
+        const int m = m0 + rb0 + i * 32 + ml;
+        if (m < d.M && n0 + cb0 + (part >> 2) * 8 < npad)
+          *(u4*)(C + 4 * (long long)m * d.ldc + part * 8) = *(const u4*)(st + ml * RU + part * 8);
+      }
+      __builtin_amdgcn_wave_barrier();
     }
   } else {
 #pragma unroll
@@ -317,9 +258,64 @@ __device__ inline void tile_body(const NtDesc& d, int b, int m0, int n0, int kcu
   }
 }
 
+// K loop and epilogue of one tile.  The wave owns the (NI*32) x (NJ*32)
+// block at rows rb0, columns cb0 of the tile: 64 x 64 in full tiles (2 x 2
+// waves); in tiles with at most 32 valid rows (columns) each wave takes a
+// 32 x 32 block of the one 32-row (32-column) strip, so edge tiles cost a
+// quarter of the matrix-core work.  Two workgroups share a CU (64 KB of LDS
+// each): two LDS stages, each stage's fragments read from LDS at its start
+// (the waves of the other workgroup keep the matrix cores busy meanwhile),
+// copies two stages ahead.
+template <int NI, int NJ, bool A_CONJ, bool B_CONJ>
+__device__ inline void tile_body(const NtDesc& d, int b, int m0, int n0, int kcur,
+                                  const unsigned short* const (&asrc)[NCOPY], const unsigned short* const (&bsrc)[NCOPY],
+                                  const int (&gslot)[NCOPY], int rb0, int cb0, char* smem, int wave, int lane) {
+  const int lr = lane & 31, lk = lane >> 5;
+  f16v c_re[NI][NJ], c_im[NI][NJ];
+#pragma unroll
+  for (int i = 0; i < NI; ++i)
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        c_re[i][j][v] = 0.f;
+        c_im[i][j][v] = 0.f;
+      }
+  const int nst = (kcur + XK - 1) / XK;
+  __syncthreads();                        // LDS of the previous tile no longer read
+#pragma unroll
+  for (int s = 0; s < NBUF; ++s)
+    if (s < nst) {
+      stage_copy(asrc, gslot, s * XK, kcur, smem + s * STAGE_B, wave);
+      stage_copy(bsrc, gslot, s * XK, kcur, smem + s * STAGE_B + OPER_B, wave);
+    }
+  for (int s = 0; s < nst; ++s) {
+    char* buf = smem + (s & 1) * STAGE_B;
+    // stage s landed: at most the copies of stage s+1 still in flight
+    wait_copies(s + 1 < nst ? 1 : 0);
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    Frag<NI, NJ> f;
+    read_frags_a(buf, f, rb0, lr, lk);
+    read_frags_b(buf, f, cb0, lr, lk);
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    settle(f);
+    // every wave holds its fragments of stage s: its buffer takes stage s+2
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    if (s + NBUF < nst) {
+      stage_copy(asrc, gslot, (s + NBUF) * XK, kcur, buf, wave);
+      stage_copy(bsrc, gslot, (s + NBUF) * XK, kcur, buf + OPER_B, wave);
+    }
+    mma_half<NI, NJ, A_CONJ, B_CONJ>(f, 0, c_re, c_im);
+    if (NJ == 2) mma_half<NI, NJ, A_CONJ, B_CONJ>(f, NJ - 1, c_re, c_im);
+  }
+  tile_epilogue<NI, NJ>(d, b, m0, n0, rb0, cb0, c_re, c_im, smem, wave, lane);
+}
+
 template <bool A_CONJ, bool B_CONJ, int KIND>
-__global__ __launch_bounds__(XNT) void zgemm_x3_kernel(const NtDesc* __restrict__ descs, int ndesc,
-                                                       long long total_tiles, int seg) {
+__global__ __launch_bounds__(XNT, 2) void zgemm_x3_kernel(const NtDesc* __restrict__ descs, int ndesc,
+                                                          long long total_tiles, int seg) {
   extern __shared__ __attribute__((aligned(16))) char smem[];   // NBUF stages x (A, B)
   const int tid = threadIdx.x;
   const int lane = tid & 63;
