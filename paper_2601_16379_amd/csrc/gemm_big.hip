@@ -229,8 +229,11 @@ hipError_t launch_big_kind(int kind, int conj, const NtDesc* descs, int ndesc, l
   }
 }
 
-// lower-tile Hermitian accumulation -> full matrix / ERI layout
-__global__ void herm_fill_kernel(cplx* c, int n, long long ld, long long bat, int nbat, int tile) {
+// Hermitian matrices of which the lower triangle (diagonal included) was
+// computed -> full matrix: every upper element is the conjugate of its
+// lower mirror (the GEMMs compute lower tiles; in diagonal tiles the blocks
+// strictly above the diagonal may be skipped)
+__global__ void herm_fill_kernel(cplx* c, int n, long long ld, long long bat, int nbat) {
   const long long per = (long long)n * n;
   const long long total = per * nbat;
   for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
@@ -238,35 +241,17 @@ __global__ void herm_fill_kernel(cplx* c, int n, long long ld, long long bat, in
     const int b = (int)(idx / per);
     const long long e = idx - (long long)b * per;
     const int m = (int)(e / n), k = (int)(e - (e / n) * n);
-    if (m / tile < k / tile) {   // upper tile: conjugate of the computed lower entry
+    if (m < k) {
       const cplx v = c[(long long)b * bat + (long long)k * ld + m];
       c[(long long)b * bat + (long long)m * ld + k] = cmk(v.x, -v.y);
     }
   }
 }
 
-// E[(pq)][(sr)] (lower tiles of the computed matrix) -> eri[p][q][r][s]
-__global__ void eri_scatter_kernel(const cplx* __restrict__ e, cplx* eri, int nf, int tile) {
-  const int n = nf * nf;
-  const long long total = (long long)n * n;
-  const long long nf2 = (long long)nf * nf;
-  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
-       idx += (long long)gridDim.x * blockDim.x) {
-    const int m = (int)(idx / n), c = (int)(idx - (idx / n) * n);
-    cplx v;
-    if (m / tile >= c / tile) {
-      v = e[idx];
-    } else {
-      const cplx u = e[(long long)c * n + m];
-      v = cmk(u.x, -u.y);
-    }
-    const int s_ = c / nf, r_ = c - s_ * nf;
-    eri[(long long)m * nf2 + (long long)r_ * nf + s_] = v;
-  }
-}
-
+// E[(pq)][(sr)] (lower triangle computed) -> eri[p][q][r][s], fragment f
+// reading e + eoff[f] and writing eri[f]
 __global__ void eri_scatter_batch_kernel(const cplx* __restrict__ e, const long long* __restrict__ eoff,
-                                         cplx* const* __restrict__ eri, const int* __restrict__ nfa, int tile) {
+                                         cplx* const* __restrict__ eri, const int* __restrict__ nfa) {
   const int f = blockIdx.y;
   const int nf = nfa[f];
   const cplx* ef = e + eoff[f];
@@ -278,7 +263,7 @@ __global__ void eri_scatter_batch_kernel(const cplx* __restrict__ e, const long 
        idx += (long long)gridDim.x * blockDim.x) {
     const int m = (int)(idx / n), c = (int)(idx - (idx / n) * n);
     cplx v;
-    if (m / tile >= c / tile) {
+    if (m >= c) {
       v = ef[idx];
     } else {
       const cplx u = ef[(long long)c * n + m];
@@ -321,24 +306,18 @@ hipError_t big_launch(int prec, int conj, const NtDesc* descs_dev, int ndesc, lo
   return launch_big_kind<1>(kind, conj, descs_dev, ndesc, total, blocks, seg, s);
 }
 
-hipError_t herm_fill_launch(cplx* c, int n, long long ld, long long bat, int nbat, int tile, hipStream_t s) {
+hipError_t herm_fill_launch(cplx* c, int n, long long ld, long long bat, int nbat, hipStream_t s) {
   hipLaunchKernelGGL(herm_fill_kernel, dim3(grid_of((long long)n * n * nbat)), dim3(256), 0, s, c, n, ld,
-                     bat, nbat, tile);
-  return hipGetLastError();
-}
-
-hipError_t eri_scatter_launch(const cplx* e, cplx* eri, int nf, int tile, hipStream_t s) {
-  const long long n = (long long)nf * nf;
-  hipLaunchKernelGGL(eri_scatter_kernel, dim3(grid_of(n * n)), dim3(256), 0, s, e, eri, nf, tile);
+                     bat, nbat);
   return hipGetLastError();
 }
 
 hipError_t eri_scatter_batch_launch(const cplx* e, const long long* eoff, cplx* const* eri, const int* nf,
-                                    int n, int maxnf, int tile, hipStream_t s) {
+                                    int n, int maxnf, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const long long m = (long long)maxnf * maxnf;
   long long bx = (m * m + 255) / 256;
   if (bx > 1024) bx = 1024;
-  hipLaunchKernelGGL(eri_scatter_batch_kernel, dim3((unsigned)bx, n), dim3(256), 0, s, e, eoff, eri, nf, tile);
+  hipLaunchKernelGGL(eri_scatter_batch_kernel, dim3((unsigned)bx, n), dim3(256), 0, s, e, eoff, eri, nf);
   return hipGetLastError();
 }

@@ -268,8 +268,9 @@ __device__ inline void tile_epilogue(const NtDesc& d, int b, int m0, int n0, int
 // copies two stages ahead.
 template <int NI, int NJ, bool A_CONJ, bool B_CONJ>
 __device__ inline void tile_body(const NtDesc& d, int b, int m0, int n0, int kcur,
-                                  const unsigned short* const (&asrc)[NCOPY], const unsigned short* const (&bsrc)[NCOPY],
-                                  const int (&gslot)[NCOPY], int rb0, int cb0, char* smem, int wave, int lane) {
+                                 const unsigned short* const (&asrc)[NCOPY], const unsigned short* const (&bsrc)[NCOPY],
+                                 const int (&gslot)[NCOPY], int rb0, int cb0, char* smem, int wave, int lane,
+                                 bool idle) {
   const int lr = lane & 31, lk = lane >> 5;
   f16v c_re[NI][NJ], c_im[NI][NJ];
 #pragma unroll
@@ -307,10 +308,12 @@ __device__ inline void tile_body(const NtDesc& d, int b, int m0, int n0, int kcu
       stage_copy(asrc, gslot, (s + NBUF) * XK, kcur, buf, wave);
       stage_copy(bsrc, gslot, (s + NBUF) * XK, kcur, buf + OPER_B, wave);
     }
-    mma_half<NI, NJ, A_CONJ, B_CONJ>(f, 0, c_re, c_im);
-    if (NJ == 2) mma_half<NI, NJ, A_CONJ, B_CONJ>(f, NJ - 1, c_re, c_im);
+    if (!idle) {
+      mma_half<NI, NJ, A_CONJ, B_CONJ>(f, 0, c_re, c_im);
+      if (NJ == 2) mma_half<NI, NJ, A_CONJ, B_CONJ>(f, NJ - 1, c_re, c_im);
+    }
   }
-  tile_epilogue<NI, NJ>(d, b, m0, n0, rb0, cb0, c_re, c_im, smem, wave, lane);
+  if (!idle) tile_epilogue<NI, NJ>(d, b, m0, n0, rb0, cb0, c_re, c_im, smem, wave, lane);
 }
 
 template <bool A_CONJ, bool B_CONJ, int KIND>
@@ -363,12 +366,18 @@ __global__ __launch_bounds__(XNT, 2) void zgemm_x3_kernel(const NtDesc* __restri
       asrc[j] = As + 4 * ((long long)ra * d.lda) + 8 * gslot[j];
       bsrc[j] = Bs + 4 * ((long long)rb * d.ldb) + 8 * gslot[j];
     }
+    // Hermitian outputs (lower tiles; the upper triangle is mirrored later):
+    // in a diagonal tile, a wave whose block lies strictly above the
+    // diagonal only helps with the copies (accumulating epilogues only)
+    const bool diag = d.herm && tm == tn && d.epi != 3;
     if (d.M - m0 <= 32)
-      tile_body<1, 1, A_CONJ, B_CONJ>(d, b, m0, n0, kcur, asrc, bsrc, gslot, 0, wave * 32, smem, wave, lane);
+      tile_body<1, 1, A_CONJ, B_CONJ>(d, b, m0, n0, kcur, asrc, bsrc, gslot, 0, wave * 32, smem, wave, lane,
+                                      diag && wave > 0);
     else if (d.N - n0 <= 32)
-      tile_body<1, 1, A_CONJ, B_CONJ>(d, b, m0, n0, kcur, asrc, bsrc, gslot, wave * 32, 0, smem, wave, lane);
+      tile_body<1, 1, A_CONJ, B_CONJ>(d, b, m0, n0, kcur, asrc, bsrc, gslot, wave * 32, 0, smem, wave, lane, false);
     else
-      tile_body<2, 2, A_CONJ, B_CONJ>(d, b, m0, n0, kcur, asrc, bsrc, gslot, wm * 64, wn * 64, smem, wave, lane);
+      tile_body<2, 2, A_CONJ, B_CONJ>(d, b, m0, n0, kcur, asrc, bsrc, gslot, wm * 64, wn * 64, smem, wave, lane,
+                                      diag && wm < wn);
   }
 }
 

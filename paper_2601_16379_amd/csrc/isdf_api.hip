@@ -635,7 +635,7 @@ void do_kernel(isdf_ctx c, int prec) {
       d[0].epi = 1;
       HIPCHK(zero_launch(c->work1.as<cplx>(), (long long)nk * nip2(c), s));
       run_big(c->arena, prec, 2, d, d[0].nseg, s, 1);
-      HIPCHK(herm_fill_launch(c->work1.as<cplx>(), nip, nip, nip2(c), nk, BIG_TILE, s));
+      HIPCHK(herm_fill_launch(c->work1.as<cplx>(), nip, nip, nip2(c), nk, s));
     }
   }
   c->timer.end("v_gemm", s);
@@ -945,8 +945,7 @@ void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn
       }
       HIPCHK(eri_scatter_batch_launch(acc, ws.arena.put(p.aoff.data(), p.aoff.size(), s),
                                       ws.arena.put(outs.data(), outs.size(), s),
-                                      ws.arena.put(p.nf.data(), p.nf.size(), s), (int)fr.size(), maxnf, BIG_TILE,
-                                      s));
+                                      ws.arena.put(p.nf.data(), p.nf.size(), s), (int)fr.size(), maxnf, s));
     }
   }
   if (timed) ws.timer.end("frag_eri", s);

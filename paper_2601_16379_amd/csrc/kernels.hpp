@@ -76,21 +76,19 @@ hipError_t nt_launch(int prec, int conj, const NtDesc* descs_dev, int ndesc, lon
 long long big_plan(NtDesc* d, int n);
 hipError_t big_launch(int prec, int conj, const NtDesc* descs_dev, int ndesc, long long total,
                       int max_blocks, int seg, hipStream_t s, int kind = 0);
-// Fill the upper tiles (tile edge `tile`) of nbat Hermitian n x n matrices
-// from their lower tiles.
-hipError_t herm_fill_launch(cplx* c, int n, long long ld, long long bat, int nbat, int tile, hipStream_t s);
-// E[(pq)][(sr)] with lower tiles computed (edge `tile`) -> eri[p][q][r][s]
-hipError_t eri_scatter_launch(const cplx* e, cplx* eri, int nf, int tile, hipStream_t s);
-// the same for n fragments in one launch: fragment f reads e + eoff[f] and
-// writes eri[f]; nf, eoff, eri are device arrays
+// Fill the upper triangles of nbat Hermitian n x n matrices (pitch ld,
+// batch stride bat) from their computed lower triangles.
+hipError_t herm_fill_launch(cplx* c, int n, long long ld, long long bat, int nbat, hipStream_t s);
+// E[(pq)][(sr)] with the lower triangle computed -> eri[p][q][r][s] for n
+// fragments in one launch: fragment f reads e + eoff[f] and writes eri[f];
+// nf, eoff, eri are device arrays
 hipError_t eri_scatter_batch_launch(const cplx* e, const long long* eoff, cplx* const* eri, const int* nf,
-                                    int n, int maxnf, int tile, hipStream_t s);
+                                    int n, int maxnf, hipStream_t s);
 // bf16x3 NT GEMM on the 32x32x16 matrix cores (128 x 128 tiles, 256
 // threads, direct-to-LDS operand copies): same descriptors and epilogues as
 // big_launch for precision 2; plan with big_plan.
 hipError_t x3_launch(int conj, const NtDesc* descs_dev, int ndesc, long long total, int max_blocks, int seg,
                      hipStream_t s, int kind);
-constexpr int BIG_TILE = 128;
 // mixed-precision fragment contraction: q values summed in FP32 per launch
 // (one contiguous K range of ERI_QGROUP * ld), FP64 across launches
 // (32: the max ERI error at the benchmark workload was 2.426e-7 Eh with 8,
