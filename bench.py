@@ -45,9 +45,11 @@ def parse():
     return ap.parse_args()
 
 
-def stage_work(stage, cfg, nfs, prec):
-    """(bound, algorithmic amount per launch, unit, peak) of a stage."""
+def stage_work(stage, cfg, nfs, prec, eta32=False):
+    """(bound, algorithmic amount per launch, unit, peak) of a stage; eta32:
+    the fit stored T and eta as complex FP32 (8 B a value, else 16)."""
     nk, nip, ng, norb = cfg.n_k, cfg.n_ip, cfg.n_g, cfg.n_orb
+    eb = 8 if eta32 else 16
     s2 = sum(n * n for n in nfs)
     dt, pk = PREC_PEAK[prec]
     if stage == "frag_eri":   # Hermitian half of sum_q U^q R^{qH} per fragment
@@ -60,12 +62,12 @@ def stage_work(stage, cfg, nfs, prec):
     if stage == "grid_fft":
         if prec == "fp64":    # two read+write passes over eta (c128)
             return "hbm", 4.0 * nk * nip * ng * 16 / 1e9, "GB", PEAK["hbm"]
-        # one pass: eta read (c128), the split operand written (8 B a point)
-        return "hbm", nk * nip * ng * (16 + 8) / 1e9, "GB", PEAK["hbm"]
-    if stage == "rhs_t":      # T^k_I(r) = X^k conj(phi^k): written once (c128)
-        return "hbm", 1.0 * nk * nip * ng * 16 / 1e9, "GB", PEAK["hbm"]
-    if stage == "rhs_kconv":  # T^k_I(r) read, eta written once (c128)
-        return "hbm", 2.0 * nk * nip * ng * 16 / 1e9, "GB", PEAK["hbm"]
+        # one pass: eta read, the split operand written (8 B a point)
+        return "hbm", nk * nip * ng * (eb + 8) / 1e9, "GB", PEAK["hbm"]
+    if stage == "rhs_t":      # T^k_I(r) = X^k conj(phi^k): written once
+        return "hbm", 1.0 * nk * nip * ng * eb / 1e9, "GB", PEAK["hbm"]
+    if stage == "rhs_kconv":  # T^k_I(r) read, eta written once
+        return "hbm", 2.0 * nk * nip * ng * eb / 1e9, "GB", PEAK["hbm"]
     if stage == "metric_kconv":
         return "hbm", 2.0 * nk * nip * nip * 16 / 1e9, "GB", PEAK["hbm"]
     if stage == "frag_pair":  # write R^q once (c128 in FP64, 8 B a point in the mixed formats)
@@ -237,7 +239,7 @@ def main():
     ctx.serve_start(max_inflight=2, max_batch=args.max_batch or len(frags), budget_bytes=budget)
 
     def step(prec, outs):
-        ctx.fit()
+        ctx.fit(prec)
         ctx.coulomb_kernel(prec)
         tickets = ctx.submit_n(cdev, outs, prec)
         lat = {}
@@ -276,11 +278,13 @@ def main():
     value = erisum * args.steps / wall
     lat_ms = 1e3 * np.asarray(lats)
 
+    # a mixed-precision fit stores T and eta as complex FP32 on the one-pass FFT grids
+    eta32 = args.prec != "fp64" and pkg.isdf_fit_eta_fp32(cfg.grid)
     # dominant stage and the roofline of its main kernel: algorithmic work of
     # one launch over the average launch duration; where the stage also runs
     # small helper kernels its GEMM launches are timed alone ("<stage>_kernel")
     dom = max((s for s in STAGES if s in stage), key=lambda k: stage[k][0])
-    bound, amount, unit, peak = stage_work(dom, cfg, nfs, args.prec)
+    bound, amount, unit, peak = stage_work(dom, cfg, nfs, args.prec, eta32)
     kt, kn = stage.get(dom + "_kernel", stage[dom])
     avg_ms = kt / kn
     achieved = (amount / kn) / (avg_ms / 1e3)
@@ -304,7 +308,7 @@ def main():
         if s not in stage:
             continue
         tot, cnt = stage[s]
-        w = stage_work(s, cfg, nfs, args.prec)
+        w = stage_work(s, cfg, nfs, args.prec, eta32)
         row = {"ms_per_step": tot, "intervals_per_step": cnt,
                "share": tot / sum(stage[k][0] for k in STAGES if k in stage)}
         if w:

@@ -109,16 +109,28 @@ isdf_status isdf_create(isdf_ctx* out, const double* lattice, const int32_t grid
  * convolution of T^k_I(r) = sum_mu X^k_{I mu} conj(phi^k_mu(r)), r-tiled; then
  * the FP64 Cholesky factor of every Pi^q with diagonal pivoting (relative
  * tolerance 1e-13; the rank is reported by isdf_stats).  Synchronous.
- * Error: ISDF_E_NUMERIC when ISDF_NO_PIVOT is set and a Pi^q is singular.
+ * `prec` is the precision of the kernel that will consume eta (eqs. (5)-(7)):
+ * with ISDF_FP64 eta is kept in FP64; with a mixed precision, on the grids
+ * whose mixed grid FFT reads it directly (cubic, 6..32 points a side: see
+ * isdf_fit_eta_fp32), T^k_I(r) and eta are stored as complex FP32 (FP64
+ * arithmetic, one rounding per stored value), halving the HBM traffic of
+ * the RHS and of the grid FFT.  X, Pi^q and its factor are FP64 always.
+ * Error: ISDF_E_INVALID for an unknown precision; ISDF_E_NUMERIC when
+ * ISDF_NO_PIVOT is set and a Pi^q is singular.
  */
-isdf_status isdf_fit(isdf_ctx ctx);
+isdf_status isdf_fit(isdf_ctx ctx, isdf_precision prec);
+
+/* 1 if isdf_fit with a mixed precision stores eta as complex FP32 on this
+ * grid, 0 if it keeps FP64 there. */
+int32_t isdf_fit_eta_fp32(const int32_t grid[3]);
 
 /*
  * W^q for all q (eqs. (6)-(8)): grid FFT of eta^q(r) exp(-i q.r), scaled by
  * sqrt(Omega 4 pi/|G+q|^2)/N_g (FP64), V^q = eta~ eta~^H (GEMM in `prec`),
  * W^q = Pi^{q+} V^q Pi^{q+} by FP64 triangular solves with the factor of
  * isdf_fit.  Consumes eta (isdf_get_rhs is invalid afterwards).  Synchronous.
- * Error: ISDF_E_STATE before isdf_fit.
+ * Error: ISDF_E_STATE before isdf_fit, or with prec = ISDF_FP64 after a
+ * mixed-precision fit that stored eta in FP32.
  */
 isdf_status isdf_coulomb_kernel(isdf_ctx ctx, isdf_precision prec);
 
@@ -129,7 +141,8 @@ isdf_status isdf_get_metric(isdf_ctx ctx, int32_t q, void* out);
 isdf_status isdf_get_kernel(isdf_ctx ctx, int32_t q, void* out);
 isdf_status isdf_get_ivs(isdf_ctx ctx, int32_t k, void* out);
 /* Copy eta^q (c128 [n_ip][N_g]) to host; valid between isdf_fit and
- * isdf_coulomb_kernel. */
+ * isdf_coulomb_kernel.  After a fit that stored eta in FP32 the values are
+ * those FP32 numbers, widened exactly. */
 isdf_status isdf_get_rhs(isdf_ctx ctx, int32_t q, void* out);
 /* Test hook: copy the Coulomb-weighted transform of eq. (7),
  *   eta~^q_I(G) = sqrt(Omega 4 pi / |G+q|^2) / N_g sum_r eta^q_I(r) exp(-i (G+q).r)

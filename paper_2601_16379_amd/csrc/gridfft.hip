@@ -402,7 +402,8 @@ __device__ inline void exchange(float* ex, float2 (&v)[N], int wbase, int wstrid
   __syncthreads();
 }
 
-template <int N>
+// IN32: eta read as complex FP32 from data32 instead of c128 from data
+template <int N, bool IN32>
 __global__ __launch_bounds__(N * N) void fft3_reg_kernel(GridFftArgs a) {
   constexpr int N2 = N * N, P = N + 1;
   extern __shared__ cplx sm[];
@@ -420,17 +421,25 @@ __global__ __launch_bounds__(N * N) void fft3_reg_kernel(GridFftArgs a) {
   }
   __syncthreads();
   // load: thread (i2, i3) = t holds the i1 line
-  const cplx* src = a.data + (long long)qi * a.q_stride + (long long)I * N * N2 + t;
+  const long long src0 = (long long)qi * a.q_stride + (long long)I * N * N2 + t;
   const int i2 = t / N, i3 = t % N;
   const float2 p2 = ph[N + i2], p3 = ph[2 * N + i3];
   const float2 p23 = make_float2(p2.x * p3.x - p2.y * p3.y, p2.x * p3.y + p2.y * p3.x);
   float2 v[N];
 #pragma unroll
   for (int i1 = 0; i1 < N; ++i1) {
-    const cplx d = src[(long long)i1 * N2];
+    float dx, dy;
+    if (IN32) {
+      const float2 d = a.data32[src0 + (long long)i1 * N2];
+      dx = d.x;
+      dy = d.y;
+    } else {
+      const cplx d = a.data[src0 + (long long)i1 * N2];
+      dx = (float)d.x;
+      dy = (float)d.y;
+    }
     const float2 p1 = ph[i1];
     const float2 pp = make_float2(p1.x * p23.x - p1.y * p23.y, p1.x * p23.y + p1.y * p23.x);
-    const float dx = (float)d.x, dy = (float)d.y;
     v[i1] = make_float2(dx * pp.x - dy * pp.y, dx * pp.y + dy * pp.x);
   }
   fft_reg<N>(v);                                      // along i1
@@ -523,7 +532,8 @@ hipError_t launch_reg(const GridFftArgs& a, hipStream_t s) {
   // transposes (N x N x (N+1) floats) + phase tables; the staged output
   // rows of the bf16 path reuse it (N * N * 64 bytes)
   const size_t lds = std::max(((size_t)N * N * (N + 1) + 6 * N) * sizeof(float), (size_t)N * N * 64);
-  hipLaunchKernelGGL(fft3_reg_kernel<N>, dim3((unsigned)items), dim3(N * N), lds, s, a);
+  if (a.data32) hipLaunchKernelGGL((fft3_reg_kernel<N, true>), dim3((unsigned)items), dim3(N * N), lds, s, a);
+  else hipLaunchKernelGGL((fft3_reg_kernel<N, false>), dim3((unsigned)items), dim3(N * N), lds, s, a);
   return hipGetLastError();
 }
 
@@ -552,7 +562,17 @@ hipError_t launch_cubic(const GridFftArgs& a, hipStream_t s) {
 
 }  // namespace
 
+bool gridfft_reg_grid(int n1, int n2, int n3) {
+  if (n1 != n2 || n2 != n3) return false;
+  switch (n1) {
+    case 6: case 8: case 10: case 12: case 16: case 18: case 20: case 24: case 30: case 32: return true;
+    default: return false;
+  }
+}
+
 hipError_t gridfft_launch(const GridFftArgs& a, hipStream_t s) {
+  // FP32 input exists only for the register kernel of the mixed formats
+  if (a.data32 && (a.fmt == 0 || !gridfft_reg_grid(a.n1, a.n2, a.n3))) return hipErrorInvalidValue;
   if (a.fmt != 0 && a.n1 == a.n2 && a.n2 == a.n3) {
     switch (a.n1) {
       case 6: return launch_reg<6>(a, s);

@@ -312,6 +312,7 @@ struct isdf_ctx_s {
   DevBuf dmax, cflag;                   // factorisation: largest diagonal, breakdown flags
   long long ld_ip = 0, ld_g = 0;        // row pitches of split operands (multiples of 16)
   bool fitted = false, kernel_ready = false, eta_valid = false;
+  bool eta32 = false;               // eta (and the RHS tile) held as complex FP32
   int kernel_prec = 0;              // precision of the last isdf_coulomb_kernel
   std::vector<int> rank_h;
   long long rc = 0;   // r-chunk of the RHS
@@ -390,7 +391,7 @@ long long nip2(const isdf_ctx c) { return (long long)c->nip * c->nip; }
 // --------------------------------------------------------------------------
 // fit
 // --------------------------------------------------------------------------
-void do_fit(isdf_ctx c) {
+void do_fit(isdf_ctx c, int prec) {
   hipStream_t s = c->stream;
   const int nk = c->nk, norb = c->norb, nip = c->nip;
   const long long ng = c->ng;
@@ -434,17 +435,26 @@ void do_fit(isdf_ctx c) {
   HIPCHK(hipEventRecord(c->ev_fork, s));
   HIPCHK(hipStreamWaitEvent(c->aux, c->ev_fork, 0));
   // eta^q_I(r), r-tiled: T^k_I(r) = sum_mu X^k_{I mu} conj(phi^k_mu(r)), then the
-  // same k convolution (eq. (5), Algorithm 1 with Y = phi)
+  // same k convolution (eq. (5), Algorithm 1 with Y = phi).  For a mixed
+  // precision kernel whose grid FFT reads FP32, T and eta are stored as
+  // complex FP32 (FP64 arithmetic, one rounding per stored value).
+  c->eta32 = prec != ISDF_FP64 && gridfft_reg_grid(c->n[0], c->n[1], c->n[2]);
+  float2* const t32 = c->eta32 ? c->rchunk.as<float2>() : nullptr;
   for (long long r0 = 0; r0 < ng; r0 += c->rc) {
     c->timer.begin("rhs_t", s);
     const int rcur = (int)std::min<long long>(c->rc, ng - r0);
-    HIPCHK(rhs_t_launch(c->xt.as<cplx>(), c->phi.as<cplx>(), c->rchunk.as<cplx>(), nk, norb, nip, ng, r0, rcur, s));
+    HIPCHK(rhs_t_launch(c->xt.as<cplx>(), c->phi.as<cplx>(), c->rchunk.as<cplx>(), t32, nk, norb, nip, ng, r0,
+                        rcur, s));
     c->timer.end("rhs_t", s);
     c->timer.begin("rhs_kconv", s);
     KconvArgs a;
     memset(&a, 0, sizeof(a));
     a.in = c->rchunk.as<cplx>();
     a.out = c->eta.as<cplx>() + r0;
+    if (c->eta32) {
+      a.in32 = t32;
+      a.out32 = c->eta.as<float2>() + r0;
+    }
     a.in_kstride = (long long)nip * rcur;
     a.out_qstride = (long long)nip * ng;
     a.n_elem = (long long)nip * rcur;
@@ -576,6 +586,8 @@ void do_fit(isdf_ctx c) {
 // --------------------------------------------------------------------------
 void do_kernel(isdf_ctx c, int prec) {
   if (!c->fitted || !c->eta_valid) throw Fail{ISDF_E_STATE, "isdf_fit must run before isdf_coulomb_kernel"};
+  if (c->eta32 && prec == ISDF_FP64)
+    throw Fail{ISDF_E_STATE, "eta was stored in FP32 by a mixed-precision fit; fit with ISDF_FP64 first"};
   hipStream_t s = c->stream;
   const int nk = c->nk, nip = c->nip;
   const long long ng = c->ng;
@@ -589,6 +601,7 @@ void do_kernel(isdf_ctx c, int prec) {
     GridFftArgs a;
     memset(&a, 0, sizeof(a));
     a.data = c->eta.as<cplx>();
+    a.data32 = c->eta32 ? c->eta.as<float2>() : nullptr;
     a.fmt = prec;
     a.split = c->eta_split.p;
     a.split_ld = c->ld_g;
@@ -1087,7 +1100,7 @@ int64_t isdf_plan_bytes(const int32_t grid[3], const int32_t kmesh[3], int32_t n
   b += nk * n_orb * n_ip * e;            // X
   b += 6 * nk * (long long)n_ip * n_ip * e;  // Pi, L, W, three work buffers
   b += nk * ((long long)n_ip * 64 + 4096) * e;  // L^{-1} scratch
-  const long long ld = (n_ip + 7) / 8 * 8;
+  const long long ld = (n_ip + 15) / 16 * 16;
   b += nk * (long long)n_ip * ld * (16 + 8 + 8);  // W^T in the three operand formats
   b += nk * (long long)n_ip * ng * e;    // eta
   b += nk * (long long)n_ip * rchunk_len(ng, (int)nk, n_ip) * e;  // RHS tile
@@ -1208,11 +1221,17 @@ isdf_status isdf_create(isdf_ctx* out, const double* lattice, const int32_t grid
   return ISDF_OK;
 }
 
-isdf_status isdf_fit(isdf_ctx ctx) {
+isdf_status isdf_fit(isdf_ctx ctx, isdf_precision prec) {
   return guarded(ctx, [&] {
+    if (prec < ISDF_FP64 || prec > ISDF_MIXED_BF16X3) throw Fail{ISDF_E_INVALID, "bad precision"};
     if (!serve_idle(ctx)) throw Fail{ISDF_E_BUSY, "requests are queued or running"};
-    do_fit(ctx);
+    do_fit(ctx, prec);
   });
+}
+
+int32_t isdf_fit_eta_fp32(const int32_t grid[3]) {
+  if (!grid) return 0;
+  return gridfft_reg_grid(grid[0], grid[1], grid[2]) ? 1 : 0;
 }
 
 isdf_status isdf_coulomb_kernel(isdf_ctx ctx, isdf_precision prec) {
@@ -1265,8 +1284,16 @@ isdf_status isdf_get_rhs(isdf_ctx ctx, int32_t q, void* out) {
   if (!ctx) return ISDF_E_INVALID;
   if (!ctx->eta_valid) return fail(ctx, ISDF_E_STATE, "eta not available (fit first; consumed by the kernel)");
   if (q < 0 || q >= ctx->nk || !out) return fail(ctx, ISDF_E_INVALID, "bad q");
-  const size_t b = (size_t)ctx->nip * ctx->ng * sizeof(cplx);
-  return get_mat(ctx, ctx->eta, (long long)q * b, b, out);
+  const size_t n = (size_t)ctx->nip * ctx->ng;
+  if (!ctx->eta32) return get_mat(ctx, ctx->eta, (long long)q * n * sizeof(cplx), n * sizeof(cplx), out);
+  return guarded(ctx, [&] {
+    std::vector<float2> h(n);
+    HIPCHK(hipMemcpyAsync(h.data(), ctx->eta.as<float2>() + (long long)q * n, n * sizeof(float2),
+                          hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    cplx* o = (cplx*)out;
+    for (size_t i = 0; i < n; ++i) o[i] = cmk((double)h[i].x, (double)h[i].y);
+  });
 }
 
 isdf_status isdf_get_eta_tilde(isdf_ctx ctx, int32_t q, void* out) {

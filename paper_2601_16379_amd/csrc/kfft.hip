@@ -134,7 +134,12 @@ __global__ __launch_bounds__(256) void kconv_kernel(KconvArgs a, int etile) {
             const long long ee = e0 + e;
             off = (ee / a.in_inner) * a.in_outer + ee % a.in_inner;
           }
-          v[u] = a.in[(long long)k * a.in_kstride + off];
+          if (a.in32) {
+            const float2 f = a.in32[(long long)k * a.in_kstride + off];
+            v[u] = cmk((double)f.x, (double)f.y);
+          } else {
+            v[u] = a.in[(long long)k * a.in_kstride + off];
+          }
         }
       }
     }
@@ -335,7 +340,8 @@ __device__ inline cplx quad_out(cplx s, cplx p, int role) {
   return cmk(fma(sg, wx, u.x), fma(sg, wy, u.y));
 }
 
-template <int M1, int M2, int M3>
+// F32: input from in32 and output to out32 (complex FP32, FP64 arithmetic)
+template <int M1, int M2, int M3, bool F32>
 __global__ __launch_bounds__(256) void kconv_reg_kernel(KconvArgs a) {
   constexpr int NV = M2 * M3, EPW = 64 / M1;
   const int lane = threadIdx.x & 63;
@@ -345,8 +351,18 @@ __global__ __launch_bounds__(256) void kconv_reg_kernel(KconvArgs a) {
   const long long ie = in ? (e / a.in_inner) * a.in_outer + e % a.in_inner : 0;
   cplx x[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v)
-    x[v] = in ? a.in[(long long)(k1 * NV + v) * a.in_kstride + ie] : cmk(0.0, 0.0);
+  for (int v = 0; v < NV; ++v) {
+    // every lane loads (ie = 0 is in bounds for lanes past the end, whose
+    // quads only exchange among themselves and store nothing): a load under
+    // a branch is waited for inside it, one round trip per value
+    const long long off = (long long)(k1 * NV + v) * a.in_kstride + ie;
+    if (F32) {
+      const float2 f = a.in32[off];
+      x[v] = cmk((double)f.x, (double)f.y);
+    } else {
+      x[v] = a.in[off];
+    }
+  }
   dft23_pos<M2, M3>(x);
   // k1 axis across the quad; M1 = 4 leaves the lanes in bit-reversed order
   if constexpr (M1 == 2) {
@@ -381,7 +397,12 @@ __global__ __launch_bounds__(256) void kconv_reg_kernel(KconvArgs a) {
   if (!in) return;
   const long long oe = (e / a.out_inner) * a.out_outer + e % a.out_inner;
 #pragma unroll
-  for (int v = 0; v < NV; ++v) a.out[(long long)(k1 * NV + v) * a.out_qstride + oe] = cscale(x[v], a.scale);
+  for (int v = 0; v < NV; ++v) {
+    const long long off = (long long)(k1 * NV + v) * a.out_qstride + oe;
+    const cplx r = cscale(x[v], a.scale);
+    if (F32) a.out32[off] = make_float2((float)r.x, (float)r.y);
+    else a.out[off] = r;
+  }
 }
 
 template <int M1, int M2, int M3>
@@ -389,7 +410,8 @@ hipError_t launch_kconv_reg(const KconvArgs& a, hipStream_t s) {
   constexpr int EPB = 4 * (64 / M1);
   const long long blocks = (a.n_elem + EPB - 1) / EPB;
   if (blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL((kconv_reg_kernel<M1, M2, M3>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+  if (a.in32) hipLaunchKernelGGL((kconv_reg_kernel<M1, M2, M3, true>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL((kconv_reg_kernel<M1, M2, M3, false>), dim3((unsigned)blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 template <int M1, int M2>
@@ -594,7 +616,9 @@ hipError_t pair_reg_m2(const PairArgs& a, hipStream_t s) {
 }  // namespace
 
 hipError_t kconv_launch(const KconvArgs& a, hipStream_t s) {
-  if (a.mode == 0 && (a.m1 == 1 || a.m1 == 2 || a.m1 == 4) && a.m2 <= 4 && a.m3 <= 4) {
+  // the register path converts both ends or neither
+  const bool io_same = (a.in32 != nullptr) == (a.out32 != nullptr);
+  if (a.mode == 0 && io_same && (a.m1 == 1 || a.m1 == 2 || a.m1 == 4) && a.m2 <= 4 && a.m3 <= 4) {
     if (a.m1 == 1) return kconv_reg_m2<1>(a, s);
     if (a.m1 == 2) return kconv_reg_m2<2>(a, s);
     return kconv_reg_m2<4>(a, s);

@@ -7,17 +7,19 @@
 // of one k.  The X^k values of the IT points are the same for every lane and
 // are read through the scalar cache into SGPRs (the FMAs take them as their
 // scalar operand, so no LDS traffic); each thread streams phi^k_mu(r) for its
-// r over mu and accumulates its IT outputs in registers.
+// r over mu and accumulates its IT outputs in registers.  The sums are stored
+// in FP64, or rounded once to complex FP32 when the mixed-precision kernel
+// consumes them.
 #include "kernels.hpp"
 
 namespace {
 
 constexpr int RT = 256;
 
-template <int IT>
+template <int IT, bool F32>
 __global__ __launch_bounds__(256) void rhs_t_kernel(const cplx* __restrict__ xt, const cplx* __restrict__ phi,
-                                                    cplx* __restrict__ out, int norb, int nip, long long ng,
-                                                    long long r0, int rcur) {
+                                                    cplx* __restrict__ out, float2* __restrict__ out32, int norb,
+                                                    int nip, long long ng, long long r0, int rcur) {
   const int k = blockIdx.z;
   const int I0 = blockIdx.y * IT;
   const int r = blockIdx.x * RT + threadIdx.x;
@@ -44,20 +46,26 @@ __global__ __launch_bounds__(256) void rhs_t_kernel(const cplx* __restrict__ xt,
       ai[i] = fma(xv.y, f.x, fma(-xv.x, f.y, ai[i]));
     }
   }
-  cplx* o = out + ((long long)k * nip + I0) * rcur + r;
+  const long long o = ((long long)k * nip + I0) * rcur + r;
 #pragma unroll
   for (int i = 0; i < IT; ++i)
-    if (i < ni) o[(long long)i * rcur] = cmk(ar[i], ai[i]);
+    if (i < ni) {
+      if (F32) out32[o + (long long)i * rcur] = make_float2((float)ar[i], (float)ai[i]);
+      else out[o + (long long)i * rcur] = cmk(ar[i], ai[i]);
+    }
 }
 
 }  // namespace
 
-hipError_t rhs_t_launch(const cplx* xt, const cplx* phi, cplx* out, int nk, int norb, int nip, long long ng,
-                        long long r0, int rcur, hipStream_t s) {
+hipError_t rhs_t_launch(const cplx* xt, const cplx* phi, cplx* out, float2* out32, int nk, int norb, int nip,
+                        long long ng, long long r0, int rcur, hipStream_t s) {
   if (nk <= 0 || rcur <= 0) return hipSuccess;
   constexpr int IT = 16;
   static_assert(IT <= RHS_X_PAD, "X padding covers one block of points");
   dim3 g((rcur + RT - 1) / RT, (nip + IT - 1) / IT, nk);
-  hipLaunchKernelGGL(rhs_t_kernel<IT>, g, dim3(RT), 0, s, xt, phi, out, norb, nip, ng, r0, rcur);
+  if (out32)
+    hipLaunchKernelGGL((rhs_t_kernel<IT, true>), g, dim3(RT), 0, s, xt, phi, out, out32, norb, nip, ng, r0, rcur);
+  else
+    hipLaunchKernelGGL((rhs_t_kernel<IT, false>), g, dim3(RT), 0, s, xt, phi, out, out32, norb, nip, ng, r0, rcur);
   return hipGetLastError();
 }

@@ -25,7 +25,7 @@ ISDF_NO_PIVOT = 0x2
 ISDF_FRAG_DEVICE = 0x1
 REQ_STATES = {0: "QUEUED", 1: "RUNNING", 2: "DONE", 3: "FAILED", 4: "CANCELLED"}
 
-EXPORTS = ["isdf_create", "isdf_fit", "isdf_coulomb_kernel", "isdf_get_metric",
+EXPORTS = ["isdf_create", "isdf_fit", "isdf_fit_eta_fp32", "isdf_coulomb_kernel", "isdf_get_metric",
            "isdf_get_kernel", "isdf_get_ivs", "isdf_get_rhs", "isdf_get_eta_tilde", "isdf_fragment_eri",
            "isdf_serve_start", "isdf_submit", "isdf_submit_n", "isdf_poll", "isdf_cancel",
            "isdf_serve_stop", "isdf_stats", "isdf_stage_ms", "isdf_stage_total", "isdf_stage_reset", "isdf_plan_bytes", "isdf_storage_model_bytes",
@@ -65,7 +65,8 @@ def load_library(path=LIB_PATH):
     P, I32, U32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_int64, ctypes.c_double
     sig = {
         "isdf_create": (I32, [ctypes.POINTER(P), P, P, P, I32, P, P, I32, U32, P]),
-        "isdf_fit": (I32, [P]),
+        "isdf_fit": (I32, [P, I32]),
+        "isdf_fit_eta_fp32": (I32, [P]),
         "isdf_coulomb_kernel": (I32, [P, I32]),
         "isdf_get_metric": (I32, [P, I32, P]),
         "isdf_get_kernel": (I32, [P, I32, P]),
@@ -127,6 +128,12 @@ def isdf_plan_bytes(grid, kmesh, n_orb, n_ip):
     return int(lib.isdf_plan_bytes(g.ctypes.data, k.ctypes.data, int(n_orb), int(n_ip)))
 
 
+def isdf_fit_eta_fp32(grid):
+    """True if a mixed-precision fit stores eta as complex FP32 on this grid."""
+    g = np.ascontiguousarray(np.asarray(grid, dtype=np.int32))
+    return bool(load_library().isdf_fit_eta_fp32(g.ctypes.data))
+
+
 def isdf_storage_model_bytes(n_k, n_ip, n_ao):
     return int(load_library().isdf_storage_model_bytes(int(n_k), int(n_ip), int(n_ao)))
 
@@ -184,8 +191,10 @@ class Isdf:
             pass
 
     # -- the path ------------------------------------------------------------
-    def fit(self):
-        self._check(self.lib.isdf_fit(self.h), "isdf_fit")
+    def fit(self, prec="fp64"):
+        """``prec``: precision of the kernel that will consume eta; a mixed
+        precision stores eta as complex FP32 where the grid allows it."""
+        self._check(self.lib.isdf_fit(self.h, PRECISIONS.get(prec, prec)), "isdf_fit")
 
     def coulomb_kernel(self, prec="fp64"):
         self._check(self.lib.isdf_coulomb_kernel(self.h, PRECISIONS.get(prec, prec)),

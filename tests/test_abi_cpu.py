@@ -49,6 +49,15 @@ def test_plan_bytes_at_most_linear_in_nk():
     assert b5 > 53e9
 
 
+def test_fp32_eta_only_on_register_fft_grids():
+    # the mixed grid FFT reads FP32 eta only in its one-pass register kernel
+    for n in (6, 8, 10, 12, 16, 18, 20, 24, 30, 32):
+        assert pkg.isdf_fit_eta_fp32((n, n, n))
+    for g in ((36, 36, 36), (40, 40, 40), (16, 16, 24), (64, 64, 64)):
+        assert not pkg.isdf_fit_eta_fp32(g)
+    assert pkg.load_library().isdf_fit_eta_fp32(None) == 0
+
+
 def test_create_rejects_invalid_arguments_without_device():
     lib = pkg.load_library()
     h = ctypes.c_void_p()
@@ -80,7 +89,8 @@ def test_create_rejects_invalid_arguments_without_device():
 
 def test_calls_on_null_context_fail_cleanly():
     lib = pkg.load_library()
-    assert lib.isdf_fit(None) == -1
+    assert lib.isdf_fit(None, 0) == -1
+    assert lib.isdf_fit(None, 2) == -1
     assert lib.isdf_coulomb_kernel(None, 0) == -1
     assert lib.isdf_destroy(None) == -1
     assert isinstance(lib.isdf_last_error(None), bytes)

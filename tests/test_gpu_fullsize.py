@@ -57,7 +57,7 @@ def test_workload2_full_oracle():
     for o, r in zip(out, ref):
         assert _rel(o, r) < 1e-10
     for prec in ("fp32", "bf16x3"):
-        ctx.fit()
+        ctx.fit(prec)
         ctx.coulomb_kernel(prec)
         out = ctx.fragment_eri(frags, prec)
         for o, r in zip(out, ref):
@@ -122,8 +122,8 @@ def test_workload3_kernel_and_fragments(w3):
     for f in pick:
         assert _rel(out[f], ref[f]) < 1e-10, f
     # mixed precision (the benchmarked path): W^q and every fragment GEMM in
-    # bf16x3, against the FP64 results of the same batch
-    ctx.fit()
+    # bf16x3 (FP32 eta), against the FP64 results of the same batch
+    ctx.fit("bf16x3")
     ctx.coulomb_kernel("bf16x3")
     mixed = ctx.fragment_eri(frags, "bf16x3")
     errs = [float(np.max(np.abs(m - o))) for m, o in zip(mixed, out)]

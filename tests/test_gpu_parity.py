@@ -220,7 +220,7 @@ def test_mixed_kernel_and_eri_within_1e6(name, prec):
     c = case(name)
     cfg = c.d.cfg
     ctx = _ctx(c.d)
-    ctx.fit()
+    ctx.fit(prec)
     ctx.coulomb_kernel(prec)
     frags = inp.make_fragments(cfg)
     out = ctx.fragment_eri(frags, prec)
@@ -240,11 +240,13 @@ def test_eta_tilde_elementwise(name, prec):
     every q: FP64 within 1e-12 of max; the mixed operands within their
     rounding (2^-23 FP32, 2^-16 bf16 hi+lo, relative per element) plus 2e-6
     of max for the FP32 transform of the one-pass kernel (cubic grids up to
-    32^3; 36 and 40 take the two-pass FP64 transform)."""
+    32^3; 36 and 40 take the two-pass FP64 transform).  The fit runs in the
+    same precision, so on the one-pass grids the transform reads the FP32
+    eta (its rounding, 2^-24 relative, is well inside the floor)."""
     c = case(name)
     cfg = c.d.cfg
     ctx = _ctx(c.d)
-    ctx.fit()
+    ctx.fit(prec)
     ctx.coulomb_kernel(prec)
     rel = {"fp64": 0.0, "fp32": 2.0 ** -23, "bf16x3": 2.0 ** -16}[prec]
     floor = 1e-12 if prec == "fp64" else 2e-6
@@ -254,3 +256,53 @@ def test_eta_tilde_elementwise(name, prec):
         bound = rel * np.abs(ref) + floor * np.abs(ref).max()
         excess = float(np.max(np.abs(got - ref) - bound))
         assert excess <= 0.0, (q, excess)
+
+
+@pytest.mark.parametrize("name", SMALL + ["t_grid10_k1", "t_grid20_k3"])
+def test_mixed_fit_eta_fp32_bound(name):
+    """A mixed-precision fit stores T^k_I(r) and eta^q_I(r) as complex FP32
+    (FP64 arithmetic).  Rounding T (|dT| <= 2^-24 |T|) perturbs
+    T_R = sum_k exp(ik.R) T^k by at most 2^-24 A with A = sum_k |T^k|, so
+    |d eta^q| <= 2^-23 A^2 + 2^-24 |eta^q| (the final rounding), and
+    A^2 <= N_k sum_k |T^k|^2 = N_k eta^{q=0} (Cauchy-Schwarz, Parseval of
+    eq. (5)).  Element by element against the oracle; X and Pi stay FP64
+    and bit-for-bit / 1e-12 as in the FP64 fit; an FP64 kernel after such a
+    fit is a state error."""
+    import paper_2601_16379_amd as pkg
+    c = case(name)
+    cfg = c.d.cfg
+    assert pkg.isdf_fit_eta_fp32(cfg.grid)
+    ctx = _ctx(c.d)
+    ctx.fit("bf16x3")
+    assert np.array_equal(np.stack([ctx.get_ivs(k) for k in range(cfg.n_k)]), c.x)
+    assert _rel(np.stack([ctx.get_metric(q) for q in range(cfg.n_k)]), c.pi) < 1e-12
+    eta0 = np.abs(c.eta[0])
+    worst = 0.0
+    for q in range(cfg.n_k):
+        got = ctx.get_rhs(q)
+        # the stored values are FP32 numbers
+        assert np.array_equal(got.real.astype(np.float32).astype(np.float64), got.real)
+        assert np.array_equal(got.imag.astype(np.float32).astype(np.float64), got.imag)
+        ref = c.eta[q]
+        bound = 2.0 ** -23 * cfg.n_k * eta0 + 2.0 ** -24 * np.abs(ref) + 1e-12 * np.abs(ref).max()
+        excess = float(np.max(np.abs(got - ref) - bound))
+        worst = max(worst, _rel(got, ref))
+        assert excess <= 0.0, (q, excess)
+    print("%s FP32 eta: max|d eta| / max|eta| = %.2e" % (name, worst))
+    with pytest.raises(pkg.IsdfError) as e:
+        ctx.coulomb_kernel("fp64")
+    assert e.value.status == -3
+
+
+def test_fp64_fit_then_mixed_kernel_within_1e6():
+    """The FP64 eta also feeds the mixed kernel (the grid FFT converts it)."""
+    c = case("t_mid_k4")
+    cfg = c.d.cfg
+    ctx = _ctx(c.d)
+    ctx.fit("fp64")
+    ctx.coulomb_kernel("bf16x3")
+    frags = inp.make_fragments(cfg)
+    out = ctx.fragment_eri(frags, "bf16x3")
+    for f, cf in enumerate(frags):
+        ref = ko.fragment_eri(c.x, cf, c.w, cfg.kmesh)
+        assert float(np.max(np.abs(out[f] - ref))) < 1e-6
