@@ -9,7 +9,15 @@ integrals"; eq. (1) for the Bloch sums):
   a momentum difference q is the mesh difference modulo m (eq. (2): q is the
   pair momentum shifted into the first Brillouin zone);
 * the Coulomb kernel is 4 pi / |K|^2 with the K = 0 term dropped
-  (neutralising background), K = G + q.
+  (neutralising background), K = G + q.  On the DFT grid K is known only
+  modulo n b per axis; each index takes the representative of its class
+  nearest zero per axis, |K_d| <= n_d / 2 (fractional units), and where two
+  representatives tie (K_d = +-n_d/2: the Nyquist plane of an even grid, or
+  a zone-boundary q on an odd one) the kernel is their average.  That
+  reading is symmetric under K -> -K, so the kernels at q and -q are
+  reflections of each other and Pi^{-q}, V^{-q}, W^{-q} are the complex
+  conjugates of those at q; it is the same kernel for the k-point form and
+  for the Gamma-point supercell form.
 """
 import numpy as np
 
@@ -65,23 +73,41 @@ def q_frac_wrapped(jq, kmesh):
     return wrap(np.asarray(jq), m) / m
 
 
+def coulomb_nearest(frac, period, brows):
+    """4 pi/|K|^2 for fractional vectors frac [N, 3] (units of the rows of
+    brows) taken modulo period[d] per axis: the representative with
+    |K_d| <= period_d / 2 per axis, averaged over the two where K_d sits at
+    +-period_d/2 (2, 4 or 8 vectors); 0 where K = 0."""
+    frac = np.asarray(frac, dtype=np.float64)
+    per = np.asarray(period, dtype=np.float64)
+    x = np.mod(frac + per / 2, per) - per / 2          # in [-p/2, p/2)
+    tie = np.abs(x + per / 2) < 1e-9                    # K_d = -p/2 = +p/2 (mod p)
+    acc = np.zeros(frac.shape[0])
+    cnt = np.zeros(frac.shape[0])
+    for s in range(8):
+        sh = np.array([(s >> d) & 1 for d in range(3)], dtype=np.float64)
+        ok = np.all(tie | (sh == 0), axis=1)            # shift only tied axes
+        kv = (x + sh * per) @ brows
+        k2 = np.einsum("ij,ij->i", kv, kv)
+        nz = ok & (k2 > 1e-24)
+        acc[nz] += 4.0 * np.pi / k2[nz]
+        cnt[ok] += 1
+    return acc / cnt
+
+
 def coulomb_g_plus_q(lattice, grid, qfrac):
     """c(G+q) = 4 pi/|G+q|^2 on the DFT index set of the unit-cell grid.
 
-    G = B g with g in [-n/2, n/2) per axis (numpy FFT index order, C order
-    over the grid), q = B qfrac; the term with G+q = 0 is 0.  Returns the
-    kernel as a float64 array of shape [N_g]."""
+    Index s_d of axis d stands for the class G_d = s_d (mod n_d); K = G + q
+    with q = B qfrac takes the representative nearest zero per axis (ties
+    averaged, see the module notes); the term with K = 0 is 0.  Returns the
+    kernel as a float64 array of shape [N_g] (numpy FFT index order, C
+    order over the grid)."""
     b = reciprocal(lattice)
     n1, n2, n3 = grid
-    g = np.stack(np.meshgrid(wrap(np.arange(n1), n1), wrap(np.arange(n2), n2),
-                             wrap(np.arange(n3), n3), indexing="ij"), -1).reshape(-1, 3)
-    kf = g + np.asarray(qfrac)[None, :]
-    kv = kf @ b
-    k2 = np.einsum("ij,ij->i", kv, kv)
-    out = np.zeros_like(k2)
-    nz = k2 > 1e-24
-    out[nz] = 4.0 * np.pi / k2[nz]
-    return out
+    g = np.stack(np.meshgrid(np.arange(n1), np.arange(n2), np.arange(n3),
+                             indexing="ij"), -1).reshape(-1, 3)
+    return coulomb_nearest(g + np.asarray(qfrac)[None, :], grid, b)
 
 
 def supercell_lattice(lattice, kmesh):
@@ -89,39 +115,12 @@ def supercell_lattice(lattice, kmesh):
     return np.asarray(lattice) * np.asarray(kmesh)[:, None]
 
 
-def supercell_box(grid, kmesh, mode):
-    """Integer representative (units of the supercell reciprocal vectors) of
-    every DFT index s of the supercell grid, per axis, M_d = m_d n_d.
-
-    mode "supercell": s -> wrap(s, M)  (the plain supercell FFT box);
-    mode "kpoint":    s -> m wrap((s - jw)/m, n) + jw with jw = wrap(s mod m, m),
-                      i.e. K = G + q with G in the unit-cell box and q wrapped,
-                      the box the k-point Coulomb kernel sums over.
-    Returns three integer arrays (one per axis)."""
-    out = []
-    for d in range(3):
-        n, m = grid[d], kmesh[d]
-        big = n * m
-        s = np.arange(big)
-        if mode == "supercell":
-            out.append(wrap(s, big))
-        elif mode == "kpoint":
-            jw = wrap(s % m, m)
-            g = ((s - jw) // m) % n
-            out.append(m * wrap(g, n) + jw)
-        else:
-            raise ValueError(mode)
-    return out
-
-
-def coulomb_supercell(lattice, grid, kmesh, mode):
-    """4 pi/|K|^2 on the supercell DFT index set (C order), K = 0 dropped."""
+def coulomb_supercell(lattice, grid, kmesh):
+    """4 pi/|K|^2 on the supercell DFT index set (C order), K = 0 dropped,
+    with the same nearest-representative reading: supercell index s_d is
+    the class K_d = s_d (mod m_d n_d) in units of the supercell reciprocal
+    rows, i.e. K = G + q of the k-point form with the same representative."""
     bs = reciprocal(supercell_lattice(lattice, kmesh))
-    r1, r2, r3 = supercell_box(grid, kmesh, mode)
-    g = np.stack(np.meshgrid(r1, r2, r3, indexing="ij"), -1).reshape(-1, 3)
-    kv = g @ bs
-    k2 = np.einsum("ij,ij->i", kv, kv)
-    out = np.zeros_like(k2)
-    nz = k2 > 1e-24
-    out[nz] = 4.0 * np.pi / k2[nz]
-    return out
+    shape = [grid[d] * kmesh[d] for d in range(3)]
+    s = np.stack(np.meshgrid(*[np.arange(n) for n in shape], indexing="ij"), -1).reshape(-1, 3)
+    return coulomb_nearest(s, shape, bs)

@@ -61,18 +61,17 @@ def fragment_orbitals(phi_s, coeffs):
     return np.einsum("kmp,kmx->px", coeffs, phi_s) / np.sqrt(nk)
 
 
-def exact_eri(psi, lattice, grid, kmesh, box="kpoint"):
+def exact_eri(psi, lattice, grid, kmesh):
     """FFT-Poisson ERIs of fragment orbitals psi [n_f, N_S] on the supercell.
 
     (pq|rs) = (Omega_S/N_S^2) sum_{K != 0} (4 pi/|K|^2) rhohat_pq(K) rhohat_rs(-K)
-    with rho_pq = conj(psi_p) psi_q.  The box representative K of each DFT
-    index is attached to the first density (the k-point kernel attaches G+q
-    to the density that carries momentum q); for a box symmetric under
-    K -> -K the two placements agree.  Returns [n_f]^4 complex128."""
+    with rho_pq = conj(psi_p) psi_q and the nearest-representative kernel of
+    ``geometry`` (symmetric under K -> -K, so it does not matter which of the
+    two densities carries K).  Returns [n_f]^4 complex128."""
     nf, ns = psi.shape
     shape = tuple(grid[d] * kmesh[d] for d in range(3))
     vol_s = abs(np.linalg.det(geo.supercell_lattice(lattice, kmesh)))
-    kern = geo.coulomb_supercell(lattice, grid, kmesh, box)
+    kern = geo.coulomb_supercell(lattice, grid, kmesh)
     rho = (psi.conj()[:, None, :] * psi[None, :, :]).reshape(nf * nf, *shape)
     rhat = np.fft.fftn(rho, axes=(1, 2, 3)).reshape(nf * nf, -1)
     refl = poisson.reflect_index(shape)
@@ -90,7 +89,7 @@ def pinv_hermitian(mat, rcond):
     return (v[:, keep] / w[keep]) @ v[:, keep].conj().T, int(keep.sum())
 
 
-def gamma_isdf(orbitals, ip_index, lattice, grid, kmesh, box="kpoint", rcond=1e-13):
+def gamma_isdf(orbitals, ip_index, lattice, grid, kmesh, rcond=1e-13):
     """Gamma-point supercell ISDF: returns (xs, zeta, Wcal, rank).
 
     xs      supercell indices of the interpolation points (a = (t, I));
@@ -115,20 +114,20 @@ def gamma_isdf(orbitals, ip_index, lattice, grid, kmesh, box="kpoint", rcond=1e-
     shape = tuple(grid[d] * kmesh[d] for d in range(3))
     ns = psi_c.shape[1]
     vol_s = abs(np.linalg.det(geo.supercell_lattice(lattice, kmesh)))
-    kern = geo.coulomb_supercell(lattice, grid, kmesh, box)
+    kern = geo.coulomb_supercell(lattice, grid, kmesh)
     zhat = np.fft.fftn(zeta.reshape(-1, *shape), axes=(1, 2, 3)).reshape(zeta.shape[0], -1)
     refl = poisson.reflect_index(shape)
-    # (zeta_a|zeta_b), box attached to zeta_a as in exact_eri
+    # (zeta_a|zeta_b)
     wcal = (vol_s / ns ** 2) * ((zhat * kern[None, :]) @ zhat[:, refl].T)
     return xs, zeta, wcal, rank
 
 
 def gamma_isdf_eri(orbitals, ip_index, coeffs, lattice, grid, kmesh,
-                   box="kpoint", rcond=1e-13, isdf=None):
+                   rcond=1e-13, isdf=None):
     """(pq|rs) = sum_ab P_{a,pq} Wcal_ab P_{b,rs} on the supercell (eq. (9)
     specialised to one k point and transformed with eq. (17))."""
     if isdf is None:
-        isdf = gamma_isdf(orbitals, ip_index, lattice, grid, kmesh, box, rcond)
+        isdf = gamma_isdf(orbitals, ip_index, lattice, grid, kmesh, rcond)
     xs, _, wcal, _ = isdf
     phi_s = supercell_orbitals(orbitals, grid, kmesh)
     psi = fragment_orbitals(phi_s, coeffs)                        # [n_f, N_S]

@@ -60,13 +60,54 @@ __device__ inline double wrap_frac(int j, int m) {
   return (double)w / (double)m;
 }
 
-__device__ inline int wrap_int(int g, int n) { return ((g + n / 2) % n) - n / 2; }
-
 __device__ inline void q_frac(const GridFftArgs& a, int q, double qf[3]) {
   const int j1 = q / (a.m2 * a.m3), j2 = (q / a.m3) % a.m2, j3 = q % a.m3;
   qf[0] = wrap_frac(j1, a.m1);
   qf[1] = wrap_frac(j2, a.m2);
   qf[2] = wrap_frac(j3, a.m3);
+}
+
+__device__ inline int wrap_int(int g, int n) { return ((g + n / 2) % n) - n / 2; }
+
+// Wrapped mesh integers of q (the Bloch phase uses jw/m).
+__device__ inline void q_wrapped(const GridFftArgs& a, int q, int jw[3]) {
+  const int j[3] = {q / (a.m2 * a.m3), (q / a.m3) % a.m2, q % a.m3};
+  const int m[3] = {a.m1, a.m2, a.m3};
+  for (int d = 0; d < 3; ++d) jw[d] = ((j[d] + m[d] / 2) % m[d]) - m[d] / 2;
+}
+
+// Axis d of K = G + q for DFT index i (frequency i after the Bloch phase
+// exp(-i q.r), q = jw/m): the representative of the class i + jw/m (mod n)
+// nearest zero, in units of b_d.  It is unique except at +-n/2 (the Nyquist
+// plane of an even grid, or a zone-boundary q on an odd one): there `tie`
+// is set and the returned -n/2 stands with +n/2.  Integer arithmetic in
+// units of 1/m, so ties are found exactly.
+__device__ inline double k_axis(int i, int jw, int n, int m, bool& tie) {
+  const int P = n * m;
+  int r = (i * m + jw) % P;
+  if (r < 0) r += P;
+  if (2 * r >= P) r -= P;
+  tie = (2 * r == -P);
+  return (double)r / (double)m;
+}
+
+// 4 pi/|K|^2 factor of eq. (7) up to the constant: the mean of 1/|K|^2 over
+// the representatives of K (each tied axis doubles them, with the opposite
+// sign), 0 at K = 0.  b: reciprocal rows b1 b2 b3.
+__device__ inline double inv_k2_mean(const double x[3], const bool t[3], const double* b) {
+  double acc = 0.0;
+  int cnt = 0;
+  for (int s = 0; s < 8; ++s) {
+    if (((s & 1) && !t[0]) || ((s & 2) && !t[1]) || ((s & 4) && !t[2])) continue;
+    const double y0 = (s & 1) ? -x[0] : x[0], y1 = (s & 2) ? -x[1] : x[1], y2 = (s & 4) ? -x[2] : x[2];
+    const double kx = y0 * b[0] + y1 * b[3] + y2 * b[6];
+    const double ky = y0 * b[1] + y1 * b[4] + y2 * b[7];
+    const double kz = y0 * b[2] + y1 * b[5] + y2 * b[8];
+    const double k2 = kx * kx + ky * ky + kz * kz;
+    if (k2 > 1e-20) acc += 1.0 / k2;
+    ++cnt;
+  }
+  return acc / cnt;
 }
 
 __global__ __launch_bounds__(256) void slab_kernel(GridFftArgs a, int S) {
@@ -132,21 +173,19 @@ __global__ __launch_bounds__(256) void col_kernel(GridFftArgs a) {
   }
   __syncthreads();
   fft_lines(buf, tmp, tw1, a.n1, COLS, 1, 1, 0, COLS);                 // along i1
-  double qf[3];
-  q_frac(a, a.q0 + qi, qf);
+  int jw[3];
+  q_wrapped(a, a.q0 + qi, jw);
   const double coef = sqrt(4.0 * M_PI * a.volume) / ((double)a.n1 * n23);
   for (int idx = threadIdx.x; idx < a.n1 * COLS; idx += blockDim.x) {
     const int i1 = idx / COLS, c = idx - (idx / COLS) * COLS;
     if (c >= nc) continue;
     const int col = c0 + c;
-    const double g1 = wrap_int(i1, a.n1) + qf[0];
-    const double g2 = wrap_int(col / a.n3, a.n2) + qf[1];
-    const double g3 = wrap_int(col % a.n3, a.n3) + qf[2];
-    const double kx = g1 * a.recip[0] + g2 * a.recip[3] + g3 * a.recip[6];
-    const double ky = g1 * a.recip[1] + g2 * a.recip[4] + g3 * a.recip[7];
-    const double kz = g1 * a.recip[2] + g2 * a.recip[5] + g3 * a.recip[8];
-    const double k2 = kx * kx + ky * ky + kz * kz;
-    const double f = (k2 > 1e-20) ? coef / sqrt(k2) : 0.0;
+    double x[3];
+    bool t[3];
+    x[0] = k_axis(i1, jw[0], a.n1, a.m1, t[0]);
+    x[1] = k_axis(col / a.n3, jw[1], a.n2, a.m2, t[1]);
+    x[2] = k_axis(col % a.n3, jw[2], a.n3, a.m3, t[2]);
+    const double f = coef * sqrt(inv_k2_mean(x, t, a.recip));
     const cplx v = cscale(buf[idx], f);
     if (a.fmt == 0) {
       base[(long long)i1 * n23 + col] = v;
@@ -312,21 +351,19 @@ __global__ __launch_bounds__(256) void col_kernel_c(GridFftArgs a) {
   }
   __syncthreads();
   fft_axis<N, 1, 1, 0, COLS>(buf, tmp, tw, COLS);   // along i1
-  double qf[3];
-  q_frac(a, a.q0 + qi, qf);
+  int jw[3];
+  q_wrapped(a, a.q0 + qi, jw);
   const double coef = sqrt(4.0 * M_PI * a.volume) / ((double)N * N2);
   for (int idx = threadIdx.x; idx < N * COLS; idx += blockDim.x) {
     const int i1 = idx / COLS, c = idx % COLS;
     if (c >= nc) continue;
     const int col = c0 + c;
-    const double g1 = wrap_int(i1, N) + qf[0];
-    const double g2 = wrap_int(col / N, N) + qf[1];
-    const double g3 = wrap_int(col % N, N) + qf[2];
-    const double kx = g1 * a.recip[0] + g2 * a.recip[3] + g3 * a.recip[6];
-    const double ky = g1 * a.recip[1] + g2 * a.recip[4] + g3 * a.recip[7];
-    const double kz = g1 * a.recip[2] + g2 * a.recip[5] + g3 * a.recip[8];
-    const double k2 = kx * kx + ky * ky + kz * kz;
-    const double f = (k2 > 1e-20) ? coef / sqrt(k2) : 0.0;
+    double x[3];
+    bool t[3];
+    x[0] = k_axis(i1, jw[0], N, a.m1, t[0]);
+    x[1] = k_axis(col / N, jw[1], N, a.m2, t[1]);
+    x[2] = k_axis(col % N, jw[2], N, a.m3, t[2]);
+    const double f = coef * sqrt(inv_k2_mean(x, t, a.recip));
     const cplx v = cscale(buf[idx], f);
     if (a.fmt == 0) {
       base[(long long)i1 * N2 + col] = v;
@@ -450,24 +487,16 @@ __global__ __launch_bounds__(N * N) void fft3_reg_kernel(GridFftArgs a) {
   exchange<N>(ex, v, (t / N) * N * P + (t % N), P, (t / N) * N * P + (t % N) * P, 1);
   fft_reg<N>(v);                                      // along i2
   // Coulomb factor and split store: thread (k1, k3), register k2
+  // Coulomb factor of eq. (7) from the per-q table (it depends on q and the
+  // grid index only): thread (k1, k3), register k2
   const int k1 = t / N, k3 = t % N;
-  const double coef = sqrt(4.0 * M_PI * a.volume) / ((double)N * N2);
-  const double g1 = wrap_int(k1, N) + qf[0], g3 = wrap_int(k3, N) + qf[2];
-  const float b13x = (float)(g1 * a.recip[0] + g3 * a.recip[6]);
-  const float b13y = (float)(g1 * a.recip[1] + g3 * a.recip[7]);
-  const float b13z = (float)(g1 * a.recip[2] + g3 * a.recip[8]);
-  const float b2x = (float)a.recip[3], b2y = (float)a.recip[4], b2z = (float)a.recip[5];
-  const float fq2 = (float)qf[1], fcoef = (float)coef;
-  const bool edge13 = (k1 == 0 && k3 == 0 && qf[0] == 0.0 && qf[2] == 0.0 && qf[1] == 0.0);
-  const long long row = (long long)qi * a.split_q + (long long)I * a.split_ld + (long long)k1 * N2 + k3;
+  const float* fq = a.fac + (long long)qi * N * N2 + k1 * N2 + k3;
 #pragma unroll
   for (int k2 = 0; k2 < N; ++k2) {
-    const float g2 = (float)wrap_int(k2, N) + fq2;
-    const float kx = fmaf(g2, b2x, b13x), ky = fmaf(g2, b2y, b13y), kz = fmaf(g2, b2z, b13z);
-    const float k2n = kx * kx + ky * ky + kz * kz;
-    const float f = (edge13 && k2 == 0) ? 0.0f : fcoef * rsqrtf(k2n);
+    const float f = fq[k2 * N];
     v[k2] = make_float2(v[k2].x * f, v[k2].y * f);
   }
+  const long long row = (long long)qi * a.split_q + (long long)I * a.split_ld + (long long)k1 * N2 + k3;
   if constexpr (N % 8 == 0 && 64 % N == 0) {
     if (a.fmt == 2) {
       // bf16 hi/lo: a wave holds 64/N whole rows (k1) of N points for every
@@ -524,6 +553,26 @@ __global__ __launch_bounds__(N * N) void fft3_reg_kernel(GridFftArgs a) {
               cmk(0.0, 0.0));
 }
 
+// fac[qi][g] = sqrt(Omega 4 pi mean(1/|K|^2)) / N_g for q = q0 + qi and grid
+// index g (C order): the weight of eq. (7) on the nearest representative(s)
+// of K = G + q, in FP64 and rounded once.
+__global__ __launch_bounds__(256) void coulomb_table_kernel(GridFftArgs a) {
+  const long long ng = (long long)a.n1 * a.n2 * a.n3;
+  const int qi = blockIdx.y;
+  int jw[3];
+  q_wrapped(a, a.q0 + qi, jw);
+  const double coef = sqrt(4.0 * M_PI * a.volume) / (double)ng;
+  for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < ng; g += (long long)gridDim.x * blockDim.x) {
+    const int i1 = (int)(g / ((long long)a.n2 * a.n3)), i2 = (int)((g / a.n3) % a.n2), i3 = (int)(g % a.n3);
+    double x[3];
+    bool t[3];
+    x[0] = k_axis(i1, jw[0], a.n1, a.m1, t[0]);
+    x[1] = k_axis(i2, jw[1], a.n2, a.m2, t[1]);
+    x[2] = k_axis(i3, jw[2], a.n3, a.m3, t[2]);
+    a.fac[(long long)qi * ng + g] = (float)(coef * sqrt(inv_k2_mean(x, t, a.recip)));
+  }
+}
+
 template <int N>
 hipError_t launch_reg(const GridFftArgs& a, hipStream_t s) {
   static_assert(N * N <= 1024 && radix_a<N>() != 0, "one-pass FFT shape");
@@ -532,6 +581,8 @@ hipError_t launch_reg(const GridFftArgs& a, hipStream_t s) {
   // transposes (N x N x (N+1) floats) + phase tables; the staged output
   // rows of the bf16 path reuse it (N * N * 64 bytes)
   const size_t lds = std::max(((size_t)N * N * (N + 1) + 6 * N) * sizeof(float), (size_t)N * N * 64);
+  if (!a.fac) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(coulomb_table_kernel, dim3((N * N * N + 255) / 256, a.nq), dim3(256), 0, s, a);
   if (a.data32) hipLaunchKernelGGL((fft3_reg_kernel<N, true>), dim3((unsigned)items), dim3(N * N), lds, s, a);
   else hipLaunchKernelGGL((fft3_reg_kernel<N, false>), dim3((unsigned)items), dim3(N * N), lds, s, a);
   return hipGetLastError();

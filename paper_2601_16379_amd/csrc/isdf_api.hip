@@ -310,6 +310,7 @@ struct isdf_ctx_s {
   DevBuf phi, ip, xt, pi, eta, lt, w, work1, work2, work3, pinv_ws, perm, rank, rchunk, flag;
   DevBuf wt64, wt32, wt16, eta_split;   // W transposed in the three GEMM formats; split eta~
   DevBuf dmax, cflag;                   // factorisation: largest diagonal, breakdown flags
+  DevBuf fac;                           // per-q Coulomb factors of the mixed grid FFT (FP32, N_q x N_g)
   long long ld_ip = 0, ld_g = 0;        // row pitches of split operands (multiples of 16)
   bool fitted = false, kernel_ready = false, eta_valid = false;
   bool eta32 = false;               // eta (and the RHS tile) held as complex FP32
@@ -602,6 +603,11 @@ void do_kernel(isdf_ctx c, int prec) {
     memset(&a, 0, sizeof(a));
     a.data = c->eta.as<cplx>();
     a.data32 = c->eta32 ? c->eta.as<float2>() : nullptr;
+    // per-q Coulomb factors of the one-pass (register) FFT
+    if (prec != ISDF_FP64 && gridfft_reg_grid(c->n[0], c->n[1], c->n[2])) {
+      c->fac.ensure((size_t)nk * ng * sizeof(float));
+      a.fac = c->fac.as<float>();
+    }
     a.fmt = prec;
     a.split = c->eta_split.p;
     a.split_ld = c->ld_g;
@@ -1105,6 +1111,7 @@ int64_t isdf_plan_bytes(const int32_t grid[3], const int32_t kmesh[3], int32_t n
   b += nk * (long long)n_ip * ng * e;    // eta
   b += nk * (long long)n_ip * rchunk_len(ng, (int)nk, n_ip) * e;  // RHS tile
   b += n_ip * 4 + 2 * nk * (long long)n_ip * 4;
+  b += nk * ng * 4;                      // Coulomb factors of the mixed grid FFT
   return b;
 }
 

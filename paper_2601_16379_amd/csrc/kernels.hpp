@@ -149,10 +149,10 @@ hipError_t pair_launch(const PairArgs& a, hipStream_t s);
 
 // out[k][I][r] = sum_mu xt[k][mu][I] conj(phi[k][mu][r0 + r]), r < rcur
 // (the right-hand side's T^k_I(r) on one tile of grid points); FP64 vector
-// units.  With out32 set the sums are stored there as complex FP32 (same
-// offsets) instead of in out.  xt must stay readable for RHS_X_PAD elements
-// past its end (blocks of points read whole rows; the extra outputs are not
-// stored).
+// units.  With out32 set the sums are computed on the FP32 matrix cores and
+// stored there as complex FP32 (same offsets) instead of in out.  xt must
+// stay readable for RHS_X_PAD elements past its end (blocks of points read
+// whole rows; the extra outputs are not stored).
 constexpr int RHS_X_PAD = 16;
 hipError_t rhs_t_launch(const cplx* xt, const cplx* phi, cplx* out, float2* out32, int nk, int norb, int nip,
                         long long ng, long long r0, int rcur, hipStream_t s);
@@ -167,6 +167,7 @@ bool pair_reg_supported(int fmt, int m1, int m2, int m3);
 struct GridFftArgs {
   cplx* data;
   const float2* data32;   // mixed formats on the register grids: complex FP32 input (same offsets) instead of data
+  float* fac;             // mixed formats on the register grids: scratch of nq * N_g floats for the Coulomb factors
   void* split;            // optional split output (fmt 1 / 2) instead of writing data back
   int fmt;                // 0: in place c128; 1 float planes; 2 bf16 hi/lo planes
   long long split_ld, split_plane, split_q;   // row pitch, plane stride, q stride

@@ -60,7 +60,7 @@ def test_gaussian_self_energy_closed_form():
                 rho += norm * np.exp(-np.einsum("ij,ij->i", d, d) / (2 * sigma ** 2))
     shape = (n, n, n)
     rhat = np.fft.fftn(rho.reshape(shape)).reshape(-1)
-    kern = geo.coulomb_supercell(lattice, shape, (1, 1, 1), "supercell")
+    kern = geo.coulomb_supercell(lattice, shape, (1, 1, 1))
     refl = poisson.reflect_index(shape)
     val = poisson.coulomb_pair_sum(rhat[refl], rhat, kern, length ** 3, n ** 3).real
     ref = poisson.gaussian_self_energy_closed_form(
@@ -71,6 +71,22 @@ def test_gaussian_self_energy_closed_form():
 # --------------------------------------------------------------------------
 # DFT conventions / box: explicit sums on a tiny cell
 # --------------------------------------------------------------------------
+def _symmetric_box(n, qf):
+    """(g, weight) of every G_d = g with |g + qf| <= n/2: the box of K_d
+    values symmetric about zero, with weight 1/2 on its two faces
+    |g + qf| = n/2 (each face point and its opposite are the same DFT
+    index).  Enumerated over a range wider than the box, no modular
+    arithmetic."""
+    out = []
+    for g in range(-n, n + 1):
+        x = g + qf
+        if abs(x) < n / 2 - 1e-9:
+            out.append((g, 1.0))
+        elif abs(abs(x) - n / 2) < 1e-9:
+            out.append((g, 0.5))
+    return out
+
+
 def _explicit_kpoint_box_eri(d, coeffs):
     """(pq|rs) with the G+q box summed explicitly (no FFT, no index tables)."""
     cfg = d.cfg
@@ -89,9 +105,9 @@ def _explicit_kpoint_box_eri(d, coeffs):
     for jq in geo.kmesh_indices(cfg.kmesh):
         qf = np.array([((jq[a] + cfg.kmesh[a] // 2) % cfg.kmesh[a] - cfg.kmesh[a] // 2)
                        / cfg.kmesh[a] for a in range(3)])
-        for g1 in range(-(cfg.grid[0] // 2), cfg.grid[0] - cfg.grid[0] // 2):
-            for g2 in range(-(cfg.grid[1] // 2), cfg.grid[1] - cfg.grid[1] // 2):
-                for g3 in range(-(cfg.grid[2] // 2), cfg.grid[2] - cfg.grid[2] // 2):
+        for g1, w1 in _symmetric_box(cfg.grid[0], qf[0]):
+            for g2, w2 in _symmetric_box(cfg.grid[1], qf[1]):
+                for g3, w3 in _symmetric_box(cfg.grid[2], qf[2]):
                     kv = (np.array([g1, g2, g3]) + qf) @ b
                     k2 = kv @ kv
                     if k2 < 1e-14:
@@ -99,7 +115,7 @@ def _explicit_kpoint_box_eri(d, coeffs):
                     e = np.exp(-1j * (x_cart @ kv))
                     fk = rho @ e                       # rhohat(K)
                     fmk = rho @ e.conj()               # rhohat(-K)
-                    eri += (4 * np.pi / k2) * np.outer(fk, fmk)
+                    eri += (w1 * w2 * w3 * 4 * np.pi / k2) * np.outer(fk, fmk)
     return (vol_s / ns ** 2) * eri.reshape(nf, nf, nf, nf)
 
 
@@ -108,7 +124,7 @@ def test_exact_eri_matches_explicit_sums_tiny():
     coeffs = inp.make_fragment(d.cfg, 0, 3)
     phi_s = sc.supercell_orbitals(d.orbitals, d.cfg.grid, d.cfg.kmesh)
     psi = sc.fragment_orbitals(phi_s, coeffs)
-    fft_eri = sc.exact_eri(psi, d.lattice, d.cfg.grid, d.cfg.kmesh, box="kpoint")
+    fft_eri = sc.exact_eri(psi, d.lattice, d.cfg.grid, d.cfg.kmesh)
     brute = _explicit_kpoint_box_eri(d, coeffs)
     assert _rel(fft_eri, brute) < 1e-13
 
@@ -126,16 +142,15 @@ def test_coulomb_kernel_matches_explicit_dft_tiny():
         qf = np.array([((jq[a] + cfg.kmesh[a] // 2) % cfg.kmesh[a] - cfg.kmesh[a] // 2)
                        / cfg.kmesh[a] for a in range(3)])
         ref = np.zeros((5, 5), dtype=np.complex128)
-        h = cfg.grid[0] // 2
-        for g1 in range(-h, h):
-            for g2 in range(-h, h):
-                for g3 in range(-h, h):
+        for g1, w1 in _symmetric_box(cfg.grid[0], qf[0]):
+            for g2, w2 in _symmetric_box(cfg.grid[1], qf[1]):
+                for g3, w3 in _symmetric_box(cfg.grid[2], qf[2]):
                     kv = (np.array([g1, g2, g3]) + qf) @ b
                     k2 = kv @ kv
                     if k2 < 1e-14:
                         continue
                     fh = f @ np.exp(-1j * (r_cart @ kv))
-                    ref += (4 * np.pi / k2) * np.outer(fh, fh.conj())
+                    ref += (w1 * w2 * w3 * 4 * np.pi / k2) * np.outer(fh, fh.conj())
         ref *= cfg.volume / cfg.n_g ** 2
         assert _rel(w, ref) < 1e-13
 
@@ -153,13 +168,12 @@ def test_full_grid_ips_reproduce_exact_eri(name):
     isdf = ko.fragment_eri(x, coeffs, w, d.cfg.kmesh)
     phi_s = sc.supercell_orbitals(d.orbitals, d.cfg.grid, d.cfg.kmesh)
     psi = sc.fragment_orbitals(phi_s, coeffs)
-    exact = sc.exact_eri(psi, d.lattice, d.cfg.grid, d.cfg.kmesh, box="kpoint")
+    exact = sc.exact_eri(psi, d.lattice, d.cfg.grid, d.cfg.kmesh)
     assert _rel(isdf, exact) < 1e-12
-    # The Gamma-point supercell form with the plain supercell box is exact too.
-    ex_s = sc.exact_eri(psi, d.lattice, d.cfg.grid, d.cfg.kmesh, box="supercell")
+    # The Gamma-point supercell form is exact too.
     g_s = sc.gamma_isdf_eri(d.orbitals, d.ip_index, coeffs, d.lattice, d.cfg.grid,
-                            d.cfg.kmesh, box="supercell")
-    assert _rel(g_s, ex_s) < 1e-12
+                            d.cfg.kmesh)
+    assert _rel(g_s, exact) < 1e-12
 
 
 def test_c1_ips_span_pair_space_exact():
@@ -174,7 +188,7 @@ def test_c1_ips_span_pair_space_exact():
     isdf = ko.fragment_eri(x, coeffs, w, d.cfg.kmesh)
     phi_s = sc.supercell_orbitals(d.orbitals, d.cfg.grid, d.cfg.kmesh)
     psi = sc.fragment_orbitals(phi_s, coeffs)
-    exact = sc.exact_eri(psi, d.lattice, d.cfg.grid, d.cfg.kmesh, box="kpoint")
+    exact = sc.exact_eri(psi, d.lattice, d.cfg.grid, d.cfg.kmesh)
     assert np.max(np.abs(isdf - exact)) < 1e-12
     # real orbitals: 8-fold symmetry and a real tensor
     assert np.max(np.abs(isdf.imag)) < 1e-14
@@ -194,7 +208,7 @@ def test_kpoint_equals_supercell_isdf(name):
     x, pi, eta, w = ko.fit_and_kernel(d.orbitals, d.ip_index, d.lattice, cfg.grid, cfg.kmesh)
     kp = ko.fragment_eri(x, coeffs, w, cfg.kmesh)
     gs = sc.gamma_isdf_eri(d.orbitals, d.ip_index, coeffs, d.lattice, cfg.grid,
-                           cfg.kmesh, box="kpoint")
+                           cfg.kmesh)
     assert _rel(kp, gs) < 1e-11
 
 
@@ -264,9 +278,8 @@ def test_minus_q_conjugation(small_fit):
     for q in range(cfg.n_k):
         assert _rel(pi[mq[q]], pi[q].conj()) < 1e-13
         assert _rel(eta[mq[q]], eta[q].conj()) < 1e-13
-        on_boundary = np.any((m % 2 == 0) & (jq[q] == m // 2))
-        if not on_boundary:
-            assert _rel(w[mq[q]], w[q].conj()) < 1e-11
+        # the kernel is symmetric under K -> -K, zone-boundary q included
+        assert _rel(w[mq[q]], w[q].conj()) < 1e-11
 
 
 def test_eri_symmetries_and_psd(small_fit):
@@ -337,9 +350,11 @@ def test_covariance(small_fit):
 
 def test_eta_tilde_of_plane_waves_closed_form():
     """A plane wave exp(i (G0+q).r) has the single weighted coefficient
-    sqrt(4 pi Omega)/|G0+q| at G0 (eq. (7) with c = 4 pi/|G+q|^2), and the
-    G + q = 0 term is dropped: an independent check of the phase, the FFT
-    index order, the reciprocal lattice and the weight of ``eta_tilde``."""
+    sqrt(Omega c) at G0 (eq. (7)), c = 4 pi/|K|^2 for the representative K
+    of G0 + q nearest zero (faces averaged: G0 = (-3, ., -2) sits on the
+    faces of the 6 x 5 x 4 grid), and the K = 0 term is dropped: an
+    independent check of the phase, the FFT index order, the reciprocal
+    lattice and the weight of ``eta_tilde``."""
     lattice = np.array([[4.0, 0.0, 0.0], [1.0, 4.5, 0.0], [0.5, 0.3, 5.0]])
     grid, kmesh = (6, 5, 4), (2, 3, 1)
     vol = abs(np.linalg.det(lattice))
@@ -352,7 +367,16 @@ def test_eta_tilde_of_plane_waves_closed_form():
         et = ko.eta_tilde(f, lattice, grid, kmesh, q)
         for i, g0 in enumerate(g0s):
             idx = np.ravel_multi_index(tuple(np.mod(g0, grid)), grid)
-            k = np.linalg.norm((g0 + qf) @ b)
-            expect = 0.0 if k == 0.0 else np.sqrt(4.0 * np.pi * vol) / k
+            # the kernel of K = G0 + q is carried by the representatives of
+            # its DFT index in the symmetric box (half weight on a face)
+            c = 0.0
+            reps = [[(g, w) for g, w in _symmetric_box(grid[a], qf[a]) if (g - g0[a]) % grid[a] == 0]
+                    for a in range(3)]
+            for g1, w1 in reps[0]:
+                for g2, w2 in reps[1]:
+                    for g3, w3 in reps[2]:
+                        k2 = float(np.sum(((np.array([g1, g2, g3]) + qf) @ b) ** 2))
+                        c += 0.0 if k2 < 1e-14 else w1 * w2 * w3 * 4.0 * np.pi / k2
+            expect = np.sqrt(vol * c)
             assert abs(et[i, idx] - expect) < 1e-12 * max(1.0, expect), (q, i)
             assert np.max(np.abs(np.delete(et[i], idx))) < 1e-12, (q, i)
