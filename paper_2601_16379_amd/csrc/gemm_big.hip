@@ -6,7 +6,8 @@
 //
 // The sums over segments (q of eq. (19), blocks of grid points of eq. (7))
 // are made by launching once per segment and adding each FP32 partial into
-// an FP64 output matrix (epi 1), so every cross-segment sum is FP64 while the
+// an FP64 output matrix (epi 1: the first segment stores, the later ones
+// add), so every cross-segment sum is FP64 while the
 // kernel keeps only FP32 accumulators; that frees the registers for a tile
 // twice as large in each direction as the segmented kernel of gemm_nt.hip,
 // which halves the operand traffic per flop.  Operand formats and the
@@ -196,7 +197,7 @@ __global__ __launch_bounds__(NT) void zgemm_big_kernel(const NtDesc* __restrict_
           } else {
             if (n >= d.N) continue;
             cplx* c = (cplx*)d.C + o;
-            cplx x = *c;                 // FP64 accumulation across launches
+            cplx x = seg > 0 ? *c : cmk(0.0, 0.0);   // FP64 accumulation across launches
             x.x += (double)vr;
             x.y += (double)vi;
             *c = x;
@@ -261,16 +262,14 @@ __global__ void eri_scatter_batch_kernel(const cplx* __restrict__ e, const long 
   const long long nf2 = (long long)nf * nf;
   for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
        idx += (long long)gridDim.x * blockDim.x) {
+    // m = (pq) = p nf + q, c = (sr) = s nf + r
     const int m = (int)(idx / n), c = (int)(idx - (idx / n) * n);
-    cplx v;
-    if (m >= c) {
-      v = ef[idx];
-    } else {
-      const cplx u = ef[(long long)c * n + m];
-      v = cmk(u.x, -u.y);
-    }
-    const int s_ = c / nf, r_ = c - s_ * nf;
-    out[(long long)m * nf2 + (long long)r_ * nf + s_] = v;
+    const int p_ = m / nf, q_ = m - p_ * nf, s_ = c / nf, r_ = c - s_ * nf;
+    // G over the classes {q, -q}: (pq|rs) = G[(pq)][(sr)] + conj(G[(qp)][(rs)])
+    const int m2 = q_ * nf + p_, c2 = r_ * nf + s_;
+    const cplx a = m >= c ? ef[idx] : cconj(ef[(long long)c * n + m]);
+    const cplx b = m2 >= c2 ? ef[(long long)m2 * n + c2] : cconj(ef[(long long)c2 * n + m2]);
+    out[(long long)m * nf2 + (long long)r_ * nf + s_] = cmk(a.x + b.x, a.y - b.y);
   }
 }
 

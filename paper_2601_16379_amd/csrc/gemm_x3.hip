@@ -199,11 +199,12 @@ __device__ inline void mma_half(const Frag<NI, NJ>& f, int j, f16v (&c_re)[NI][N
 // 8(v/4) + 4(l/32) + v%4, column l%32).  epi 3: each wave assembles its
 // block 32 rows at a time in LDS (16 KB a wave) in the operand format (a row
 // of NJ*32 points is NJ*256 contiguous bytes) and writes it with 16-byte
-// stores; otherwise FP64 read-modify-write accumulation.
+// stores; otherwise FP64 accumulation across launches (the first K segment,
+// `first`, stores).
 template <int NI, int NJ>
 __device__ inline void tile_epilogue(const NtDesc& d, int b, int m0, int n0, int rb0, int cb0,
                                      const f16v (&c_re)[NI][NJ], const f16v (&c_im)[NI][NJ], char* smem, int wave,
-                                     int lane) {
+                                     int lane, bool first) {
   const int lr = lane & 31, lk = lane >> 5;
   if (d.epi == 3) {
     __syncthreads();                      // every wave is past its last stage reads
@@ -250,7 +251,7 @@ __device__ inline void tile_epilogue(const NtDesc& d, int b, int m0, int n0, int
           const int n = n0 + cb0 + j * 32 + lr;
           if (m >= d.M || n >= d.N) continue;
           cplx* cp = (cplx*)d.C + (long long)b * d.sC_bat + (long long)m * d.ldc + n;
-          cplx x = *cp;                 // FP64 accumulation across launches
+          cplx x = first ? cmk(0.0, 0.0) : *cp;   // FP64 accumulation across launches
           x.x += (double)c_re[i][j][v];
           x.y += (double)c_im[i][j][v];
           *cp = x;
@@ -270,7 +271,7 @@ template <int NI, int NJ, bool A_CONJ, bool B_CONJ>
 __device__ inline void tile_body(const NtDesc& d, int b, int m0, int n0, int kcur,
                                  const unsigned short* const (&asrc)[NCOPY], const unsigned short* const (&bsrc)[NCOPY],
                                  const int (&gslot)[NCOPY], int rb0, int cb0, char* smem, int wave, int lane,
-                                 bool idle) {
+                                 bool idle, bool first) {
   const int lr = lane & 31, lk = lane >> 5;
   f16v c_re[NI][NJ], c_im[NI][NJ];
 #pragma unroll
@@ -313,7 +314,7 @@ __device__ inline void tile_body(const NtDesc& d, int b, int m0, int n0, int kcu
       if (NJ == 2) mma_half<NI, NJ, A_CONJ, B_CONJ>(f, NJ - 1, c_re, c_im);
     }
   }
-  if (!idle) tile_epilogue<NI, NJ>(d, b, m0, n0, rb0, cb0, c_re, c_im, smem, wave, lane);
+  if (!idle) tile_epilogue<NI, NJ>(d, b, m0, n0, rb0, cb0, c_re, c_im, smem, wave, lane, first);
 }
 
 template <bool A_CONJ, bool B_CONJ, int KIND>
@@ -368,16 +369,19 @@ __global__ __launch_bounds__(XNT, 2) void zgemm_x3_kernel(const NtDesc* __restri
     }
     // Hermitian outputs (lower tiles; the upper triangle is mirrored later):
     // in a diagonal tile, a wave whose block lies strictly above the
-    // diagonal only helps with the copies (accumulating epilogues only)
+    // diagonal only helps with the copies (FP64 epilogues only; the entries it
+    // skips lie above the diagonal, which the consumers never read)
     const bool diag = d.herm && tm == tn && d.epi != 3;
+    const bool first = seg == 0;
     if (d.M - m0 <= 32)
       tile_body<1, 1, A_CONJ, B_CONJ>(d, b, m0, n0, kcur, asrc, bsrc, gslot, 0, wave * 32, smem, wave, lane,
-                                      diag && wave > 0);
+                                      diag && wave > 0, first);
     else if (d.N - n0 <= 32)
-      tile_body<1, 1, A_CONJ, B_CONJ>(d, b, m0, n0, kcur, asrc, bsrc, gslot, wave * 32, 0, smem, wave, lane, false);
+      tile_body<1, 1, A_CONJ, B_CONJ>(d, b, m0, n0, kcur, asrc, bsrc, gslot, wave * 32, 0, smem, wave, lane, false,
+                                      first);
     else
       tile_body<2, 2, A_CONJ, B_CONJ>(d, b, m0, n0, kcur, asrc, bsrc, gslot, wm * 64, wn * 64, smem, wave, lane,
-                                      diag && wm < wn);
+                                      diag && wm < wn, first);
   }
 }
 

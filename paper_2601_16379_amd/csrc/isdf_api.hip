@@ -316,6 +316,13 @@ struct isdf_ctx_s {
   bool eta32 = false;               // eta (and the RHS tile) held as complex FP32
   int kernel_prec = 0;              // precision of the last isdf_coulomb_kernel
   std::vector<int> rank_h;
+  // q <-> -q: Pi^{-q}, W^{-q} and R^{-q}_{pq} are conjugates of those at q,
+  // so the fragment contraction runs over the classes {q, -q}: hq[h] is the
+  // smaller index of class h (nh classes), qslot[q] its class where q == hq,
+  // else -1; hself[h] = 1 if q == -q.  Device copy qmap = [qslot | hq | hself].
+  int nh = 0;
+  std::vector<int> qslot_h, hq_h, hself_h;
+  DevBuf qmap;
   long long rc = 0;   // r-chunk of the RHS
   Arena arena;
   Arena arena_aux;                      // descriptors of the second stream (chol, pinv)
@@ -652,7 +659,6 @@ void do_kernel(isdf_ctx c, int prec) {
       d[0].sC_bat = nip2(c);
       d[0].herm = 2;
       d[0].epi = 1;
-      HIPCHK(zero_launch(c->work1.as<cplx>(), (long long)nk * nip2(c), s));
       run_big(c->arena, prec, 2, d, d[0].nseg, s, 1);
       HIPCHK(herm_fill_launch(c->work1.as<cplx>(), nip, nip, nip2(c), nk, s));
     }
@@ -687,8 +693,11 @@ void do_kernel(isdf_ctx c, int prec) {
   }
   c->timer.end("w_solve", s);
   // transposed copies of W in the three operand formats of the fragment GEMMs
+  // (one per class {q, -q}, weight 1/2 where q = -q: the fragment contraction
+  // adds the conjugate term of -q itself)
   HIPCHK(wt_convert_launch(c->w.as<cplx>(), c->wt64.as<cplx>(), c->wt32.as<float>(),
-                           c->wt16.as<unsigned short>(), nip, (int)c->ld_ip, nk, s));
+                           c->wt16.as<unsigned short>(), nip, (int)c->ld_ip, c->nh, c->qmap.as<int>() + nk,
+                           c->qmap.as<int>() + nk + c->nh, s));
   HIPCHK(hipMemsetAsync(c->flag.p, 0, sizeof(int), s));
   HIPCHK(nonfinite_launch(c->w.as<cplx>(), (long long)nk * nip2(c), c->flag.as<int>(), s));
   int bad = 0;
@@ -718,9 +727,11 @@ struct BatchPlan {
 // Layout of one fragment batch in its workspace:
 //   C_all [N_k][n_orb][ncol] c128          coefficients of all fragments
 //   Tf    [N_k][ncol][N_IP] c128           T^k_{Ip} = sum_mu X C, then psi(r_I + R)
-//   M     [ptot][N_q][ld_ip] (format)      R^q_{I,pq}, rows = pairs of all fragments
-//   U     [ptot][N_q][ld_ip] (format)      U^q = R^q W^q (also stages host C first)
+//   M     [ptot][nh][ld_ip] (format)       R^q_{I,pq} for one q of each class {q, -q},
+//                                          rows = pairs of all fragments
+//   U     [ptot][nh][ld_ip] (format)       U^q = R^q W^q (also stages host C first)
 //   E     host-bound ERI outputs (c128)
+//   acc   FP64 G_f[(pq)][(sr)] of every fragment
 BatchPlan plan_batch(isdf_ctx c, const std::vector<FragIn>& fr, int prec) {
   BatchPlan p;
   long long ecount = 0;
@@ -735,7 +746,7 @@ BatchPlan plan_batch(isdf_ctx c, const std::vector<FragIn>& fr, int prec) {
     if (!(f.flags & ISDF_FRAG_DEVICE)) ecount += e4;
   }
   auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-  const size_t mb = (size_t)c->nk * p.ptot * c->ld_ip * fmt_bytes(prec);
+  const size_t mb = (size_t)c->nh * p.ptot * c->ld_ip * fmt_bytes(prec);
   size_t off = 0;
   p.off_c = off; off += al((size_t)c->nk * c->norb * p.ncol * sizeof(cplx));
   p.off_tf = off; off += al((size_t)c->nk * c->nip * p.ncol * sizeof(cplx));
@@ -743,11 +754,12 @@ BatchPlan plan_batch(isdf_ctx c, const std::vector<FragIn>& fr, int prec) {
   p.off_u = off;
   off += al(std::max<size_t>(mb, (size_t)c->nk * c->norb * p.ncol * sizeof(cplx)));
   p.off_e = off; off += al((size_t)ecount * sizeof(cplx));
-  // mixed precisions: FP64 accumulation matrices E_f[(pq)][(sr)] (one launch per q)
+  // FP64 matrices G_f[(pq)][(sr)] (the mixed precisions accumulate them over
+  // q groups), turned into the ERIs by the scatter
   long long acount = 0;
   for (const FragIn& f : fr) {
     p.aoff.push_back(acount);
-    if (prec != 0) acount += (long long)f.nf * f.nf * f.nf * f.nf;
+    acount += (long long)f.nf * f.nf * f.nf * f.nf;
   }
   p.off_acc = off; off += al((size_t)acount * sizeof(cplx));
   p.bytes = off;
@@ -756,9 +768,9 @@ BatchPlan plan_batch(isdf_ctx c, const std::vector<FragIn>& fr, int prec) {
 
 size_t request_bytes(isdf_ctx c, int nf, bool host_out, int prec) {
   size_t b = ((size_t)c->nk * c->norb * nf + (size_t)c->nk * c->nip * nf) * sizeof(cplx) +
-             2 * (size_t)c->nk * c->ld_ip * nf * nf * fmt_bytes(prec);
+             2 * (size_t)c->nh * c->ld_ip * nf * nf * fmt_bytes(prec);
   if (host_out) b += (size_t)nf * nf * nf * nf * sizeof(cplx);
-  if (prec != 0) b += (size_t)nf * nf * nf * nf * sizeof(cplx);
+  b += (size_t)nf * nf * nf * nf * sizeof(cplx);
   return b + 6 * 256;
 }
 
@@ -835,10 +847,12 @@ void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn
   if (timed) ws.timer.end("frag_t", s);
   // R^q_{I,pq} = N_k^{-1/2} sum_R exp(-iq.R) conj(psi_p) psi_q   (eq. (20)),
   // in the GEMM operand format of the precision, pair-major: row (pair) holds
-  // the N_k blocks of ld columns (q, I), so that the contraction over (q, J)
-  // of every fragment reads one contiguous K range per row
+  // the nh blocks of ld columns (class of q, I), so that the contraction over
+  // (q, J) of every fragment reads one contiguous K range per row.  Only one
+  // q of each class {q, -q} is kept: R^{-q}_{pq} = conj(R^q_{qp}).
   if (timed) ws.timer.begin("frag_pair", s);
-  const long long mplane = (long long)nk * p.ptot * ld;
+  const int nh = c->nh;
+  const long long mplane = (long long)nh * p.ptot * ld;
   {
     // tile: ti interpolation points x tp pairs, nk * tp * ti <= 4096 (64 KB)
     int ti = 32;
@@ -866,8 +880,9 @@ void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn
     a.ti = ti;
     a.n_itiles = (int)((ld + ti - 1) / ti);
     a.ld = ld;
-    a.q_stride = ld;                     // pair-major: [pair][q][I]
-    a.p_stride = (long long)nk * ld;
+    a.q_stride = ld;                     // pair-major: [pair][class][I]
+    a.p_stride = (long long)nh * ld;
+    a.qslot = c->qmap.as<int>();
     a.plane = mplane;
     a.fmt = prec;
     a.m1 = c->m[0]; a.m2 = c->m[1]; a.m3 = c->m[2];
@@ -889,10 +904,10 @@ void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn
   {
     const void* wt = prec == 0 ? c->wt64.p : (prec == 1 ? c->wt32.p : c->wt16.p);
     std::vector<NtDesc> d(1);
-    d[0] = mknt(Mq, (long long)nk * ld, wt, ld, Uq, (long long)nk * ld, (int)p.ptot, nip, nip);
-    d[0].batch = nk;
+    d[0] = mknt(Mq, (long long)nh * ld, wt, ld, Uq, (long long)nh * ld, (int)p.ptot, nip, nip);
+    d[0].batch = nh;
     d[0].a_plane = mplane;
-    d[0].b_plane = (long long)nk * nip * ld;
+    d[0].b_plane = (long long)nh * nip * ld;
     d[0].c_plane = mplane;
     d[0].sA_bat = d[0].sC_bat = ld;
     d[0].sB_bat = (long long)nip * ld;
@@ -902,39 +917,38 @@ void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn
     else run_big(ws.arena, prec, 0, d, 1, s, 2);
   }
   if (timed) ws.timer.end("frag_u", s);
-  // (pq|rs) = sum_q sum_J U^q_{(pq),J} conj(R^q_{(sr),J})  (eq. (19), R^{-q}_{rs} = conj R^q_{sr}),
-  // one grouped persistent launch over all fragments; FP64 path: FP64 sum
-  // over q inside the kernel; mixed: one launch per group of ERI_QGROUP
-  // consecutive q (one contiguous K range of QGROUP * ld per row, FP32 sums),
-  // FP64 sum over the groups
+  // (pq|rs) = sum_q sum_J U^q_{(pq),J} conj(R^q_{(sr),J})  (eq. (19), R^{-q}_{rs} = conj R^q_{sr}).
+  // The term of -q is the conjugate of that of q with (pq) -> (qp) and
+  // (sr) -> (rs) (R^{-q}_{pq} = conj R^q_{qp}, W^{-q} = conj W^q), so the
+  // contraction runs over one q per class {q, -q} (weight 1/2 where q = -q,
+  // folded into W):  G_f[(pq)][(sr)] = sum_{h, J} U^h_{(pq),J} conj(R^h_{(sr),J})
+  // in FP64 (lower tiles; one grouped persistent launch over all fragments),
+  // then (pq|rs) = G[(pq)][(sr)] + conj(G[(qp)][(rs)]) by the scatter.  FP64
+  // path: FP64 sum over the classes inside the kernel; mixed: one launch per
+  // group of classes (one contiguous K range per row, FP32 sums inside),
+  // FP64 sum over the groups.
   if (timed) ws.timer.begin("frag_eri", s);
   {
     std::vector<NtDesc> d;
     const size_t sc = fmt_scalar(prec);
-    const int qgroup = std::min(nk, ERI_QGROUP);
+    const int ngroup = (nh + ERI_QGROUP - 1) / ERI_QGROUP;
+    const int qgroup = (nh + ngroup - 1) / ngroup;       // balanced groups
     cplx* acc = (cplx*)(base + p.off_acc);
     for (size_t f = 0; f < fr.size(); ++f) {
       const int nf2 = p.nf[f] * p.nf[f];
-      cplx* out = (fr[f].flags & ISDF_FRAG_DEVICE) ? (cplx*)fr[f].eri : Est + p.eoff[f];
-      const size_t o = (size_t)p.poff[f] * nk * ld * sc;
-      NtDesc g = mknt(Uq + o, (long long)nk * ld, Mq + o, (long long)nk * ld,
-                      prec == 0 ? (void*)out : (void*)(acc + p.aoff[f]), prec == 0 ? 0 : nf2, nf2, nf2, nip);
+      const size_t o = (size_t)p.poff[f] * nh * ld * sc;
+      NtDesc g = mknt(Uq + o, (long long)nh * ld, Mq + o, (long long)nh * ld, acc + p.aoff[f], nf2, nf2, nf2, nip);
       g.a_plane = g.b_plane = mplane;
+      g.herm = 2;
       if (prec == 0) {
-        g.nseg = nk;
+        g.nseg = nh;
         g.sA_seg = g.sB_seg = ld;
+        g.epi = 0;
       } else {
         g.Kseg = (int)(qgroup * ld);
-        g.nseg = (nk + qgroup - 1) / qgroup;
-        g.Klast = (int)((nk - (long long)(g.nseg - 1) * qgroup) * ld);
+        g.nseg = (nh + qgroup - 1) / qgroup;
+        g.Klast = (int)((nh - (long long)(g.nseg - 1) * qgroup) * ld);
         g.sA_seg = g.sB_seg = qgroup * ld;
-      }
-      if (prec == 0) {
-        g.herm = 1;
-        g.epi = 2;
-        g.nf = p.nf[f];
-      } else {
-        g.herm = 2;
         g.epi = 1;
       }
       d.push_back(g);
@@ -948,24 +962,17 @@ void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn
         if (on) ws.timer.begin("frag_eri_kernel", s);
         else ws.timer.end("frag_eri_kernel", s);
       };
-    if (prec == 0) {
-      run_nt(ws.arena, prec, 2, d, s, 3, mark);
-    } else {
-      // one launch per q group: FP32 partial sums inside, FP64 sum over groups in E_f
-      long long acount = 0;
-      for (size_t f = 0; f < fr.size(); ++f) acount += (long long)p.nf[f] * p.nf[f] * p.nf[f] * p.nf[f];
-      HIPCHK(zero_launch(acc, acount, s));
-      run_big(ws.arena, prec, 2, d, d[0].nseg, s, 3, mark);
-      std::vector<cplx*> outs(fr.size());
-      int maxnf = 0;
-      for (size_t f = 0; f < fr.size(); ++f) {
-        outs[f] = (fr[f].flags & ISDF_FRAG_DEVICE) ? (cplx*)fr[f].eri : Est + p.eoff[f];
-        maxnf = std::max(maxnf, p.nf[f]);
-      }
-      HIPCHK(eri_scatter_batch_launch(acc, ws.arena.put(p.aoff.data(), p.aoff.size(), s),
-                                      ws.arena.put(outs.data(), outs.size(), s),
-                                      ws.arena.put(p.nf.data(), p.nf.size(), s), (int)fr.size(), maxnf, s));
+    if (prec == 0) run_nt(ws.arena, prec, 2, d, s, 3, mark);
+    else run_big(ws.arena, prec, 2, d, d[0].nseg, s, 3, mark);
+    std::vector<cplx*> outs(fr.size());
+    int maxnf = 0;
+    for (size_t f = 0; f < fr.size(); ++f) {
+      outs[f] = (fr[f].flags & ISDF_FRAG_DEVICE) ? (cplx*)fr[f].eri : Est + p.eoff[f];
+      maxnf = std::max(maxnf, p.nf[f]);
     }
+    HIPCHK(eri_scatter_batch_launch(acc, ws.arena.put(p.aoff.data(), p.aoff.size(), s),
+                                    ws.arena.put(outs.data(), outs.size(), s),
+                                    ws.arena.put(p.nf.data(), p.nf.size(), s), (int)fr.size(), maxnf, s));
   }
   if (timed) ws.timer.end("frag_eri", s);
   for (size_t f = 0; f < fr.size(); ++f) {
@@ -1181,6 +1188,17 @@ isdf_status isdf_create(isdf_ctx* out, const double* lattice, const int32_t grid
     const int nk = c->nk;
     const long long ng = c->ng;
     const size_t e = sizeof(cplx);
+    c->qslot_h.assign(nk, -1);
+    for (int q = 0; q < nk; ++q) {
+      const int j1 = q / (c->m[1] * c->m[2]), j2 = (q / c->m[2]) % c->m[1], j3 = q % c->m[2];
+      const int mq = (((c->m[0] - j1) % c->m[0]) * c->m[1] + (c->m[1] - j2) % c->m[1]) * c->m[2] +
+                     (c->m[2] - j3) % c->m[2];
+      if (mq < q) continue;
+      c->qslot_h[q] = (int)c->hq_h.size();
+      c->hq_h.push_back(q);
+      c->hself_h.push_back(mq == q ? 1 : 0);
+    }
+    c->nh = (int)c->hq_h.size();
     c->rc = rchunk_len(ng, nk, n_ip);
     c->phi.alloc((size_t)nk * n_orb * ng * e);
     c->ip.alloc(sizeof(int) * n_ip);
@@ -1208,6 +1226,14 @@ isdf_status isdf_create(isdf_ctx* out, const double* lattice, const int32_t grid
     c->flag.alloc(sizeof(int));
     c->dmax.alloc(sizeof(double) * nk);
     c->cflag.alloc(sizeof(int) * nk);
+    c->qmap.alloc(sizeof(int) * (nk + 2 * c->nh));
+    {
+      std::vector<int> qm(c->qslot_h);
+      qm.insert(qm.end(), c->hq_h.begin(), c->hq_h.end());
+      qm.insert(qm.end(), c->hself_h.begin(), c->hself_h.end());
+      HIPCHK(hipStreamSynchronize(c->stream));
+      HIPCHK(hipMemcpy(c->qmap.p, qm.data(), sizeof(int) * qm.size(), hipMemcpyHostToDevice));
+    }
     const hipMemcpyKind kind = (flags & ISDF_INPUT_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     HIPCHK(hipMemcpyAsync(c->phi.p, orbitals, (size_t)nk * n_orb * ng * e, kind, c->stream));
     HIPCHK(hipMemcpyAsync(c->ip.p, iph.data(), sizeof(int) * n_ip, hipMemcpyHostToDevice, c->stream));

@@ -70,18 +70,20 @@ hipError_t nt_launch(int prec, int conj, const NtDesc* descs_dev, int ndesc, lon
                      int max_blocks, hipStream_t s, int kind = 0);
 
 // Large-tile (128x128, 512 threads) NT GEMM for the mixed precisions (1, 2):
-// one K segment `seg` per launch; epi 1 adds the FP32 partial into an FP64
-// c128 output (FP64 accumulation across launches), epi 3 stores the split
-// format; herm 2 computes lower tiles only.
+// one K segment `seg` per launch; epi 1 accumulates the FP32 partials in an
+// FP64 c128 output (segment 0 stores, later segments add), epi 3 stores the
+// split format; herm 2 computes lower tiles only (entries above the diagonal
+// inside diagonal tiles are left unwritten).
 long long big_plan(NtDesc* d, int n);
 hipError_t big_launch(int prec, int conj, const NtDesc* descs_dev, int ndesc, long long total,
                       int max_blocks, int seg, hipStream_t s, int kind = 0);
 // Fill the upper triangles of nbat Hermitian n x n matrices (pitch ld,
 // batch stride bat) from their computed lower triangles.
 hipError_t herm_fill_launch(cplx* c, int n, long long ld, long long bat, int nbat, hipStream_t s);
-// E[(pq)][(sr)] with the lower triangle computed -> eri[p][q][r][s] for n
-// fragments in one launch: fragment f reads e + eoff[f] and writes eri[f];
-// nf, eoff, eri are device arrays
+// G[(pq)][(sr)] (Hermitian, lower triangle computed; the contraction over the
+// classes {q, -q}) -> eri[p][q][r][s] = G[(pq)][(sr)] + conj(G[(qp)][(rs)])
+// for n fragments in one launch: fragment f reads e + eoff[f] and writes
+// eri[f]; nf, eoff, eri are device arrays
 hipError_t eri_scatter_batch_launch(const cplx* e, const long long* eoff, cplx* const* eri, const int* nf,
                                     int n, int maxnf, hipStream_t s);
 // bf16x3 NT GEMM on the 32x32x16 matrix cores (128 x 128 tiles, 256
@@ -89,18 +91,20 @@ hipError_t eri_scatter_batch_launch(const cplx* e, const long long* eoff, cplx* 
 // big_launch for precision 2; plan with big_plan.
 hipError_t x3_launch(int conj, const NtDesc* descs_dev, int ndesc, long long total, int max_blocks, int seg,
                      hipStream_t s, int kind);
-// mixed-precision fragment contraction: q values summed in FP32 per launch
-// (one contiguous K range of ERI_QGROUP * ld), FP64 across launches
-// (32: the max ERI error at the benchmark workload was 2.426e-7 Eh with 8,
-// 2.428e-7 with 16 and 2.429e-7 with 32 q per launch, set by the V^q
-// rounding; the contraction took 22.8, 22.1 and 21.7 ms)
-constexpr int ERI_QGROUP = 32;
+// mixed-precision fragment contraction: classes {q, -q} summed in FP32 per
+// launch (one contiguous K range of at most ERI_QGROUP * ld, the classes
+// split into balanced groups), FP64 across launches (the max ERI error at
+// the benchmark workload was 2.426e-7 Eh with 8, 2.428e-7 with 16 and
+// 2.429e-7 with 32 q per launch, set by the V^q rounding; the 36 classes
+// of a 4x4x4 mesh take one launch)
+constexpr int ERI_QGROUP = 40;
 
-// W^q (c128 [q][n][n]) -> transposed copies Wt[q][J][I] = W[q][I][J] with row
-// pitch ld in c128, two-float-plane and four-bf16-plane formats (any output
-// pointer may be null); pad columns are zero.
+// W^q (c128 [q][n][n]) -> transposed copies Wt[h][J][I] = w_h W[hq[h]][I][J]
+// for the nh classes {q, -q} (hq, hself: device), w_h = 1/2 where q = -q,
+// with row pitch ld in c128, two-float-plane and four-bf16-plane formats
+// (any output pointer may be null); pad columns are zero.
 hipError_t wt_convert_launch(const cplx* w, cplx* wt64, float* wt32, unsigned short* wt16, int n,
-                             int ld, int nq, hipStream_t s);
+                             int ld, int nh, const int* hq, const int* hself, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // k-mesh transforms (Algorithm 1 and 2 in the k/R domain), LDS-staged.
@@ -130,12 +134,13 @@ struct PairBlock { int frag; int pair0; int npair; };
 struct PairArgs {
   const cplx* psi;         // [N_R][ncol][n_ip]
   const float2* psi32;     // register path (required there): psi as complex FP32, same layout
-  void* out;               // element (q, pair, I) at q*q_stride + pair*p_stride + I (per plane)
+  void* out;               // element (q, pair, I) at qslot[q]*q_stride + pair*p_stride + I (per plane)
   const PairBlock* blocks; // device
   const int* frag_nf; const int* frag_col; const long long* frag_pair;  // device
   int nblocks, n_ip, ncol, tp, ti, n_itiles;
   long long ld, plane, q_stride, p_stride;
   int fmt;
+  const int* qslot;        // device: output block of each q (rows q with qslot < 0 are not written)
   // register path (mixed precisions, mesh axes <= 4): one wave per (pair,
   // 64 interpolation points); items ordered (fragment, I chunk, pair),
   // item_off[f] = first item of fragment f (nfrag + 1 entries, device)

@@ -238,8 +238,9 @@ __global__ __launch_bounds__(256) void pair_kernel(PairArgs a) {
     const int Q = idx >> wshift, e = idx & (w - 1);
     const int j = e >> tshift, i = e & (a.ti - 1);
     const int I = I0 + i;
-    if (j < pb.npair && I < a.ld) {
-      const long long off = (long long)Q * a.q_stride + (poff + pb.pair0 + j) * a.p_stride + I;
+    const int slot = a.qslot[Q];
+    if (slot >= 0 && j < pb.npair && I < a.ld) {
+      const long long off = (long long)slot * a.q_stride + (poff + pb.pair0 + j) * a.p_stride + I;
       store_fmt(a.out, off, a.plane, a.fmt, cscale(buf[idx], a.scale));
     }
   }
@@ -548,7 +549,9 @@ __global__ __launch_bounds__(256, 2) void pair_reg_kernel(PairArgs a, int nblock
     float* o = (float*)a.out;
 #pragma unroll
     for (int Q = 0; Q < NK; ++Q) {
-      const long long off = base + lane + Q * a.q_stride;
+      const int slot = a.qslot[Q];
+      if (slot < 0) continue;
+      const long long off = base + lane + slot * a.q_stride;
       o[off] = x[Q].x * sc;
       o[a.plane + off] = x[Q].y * sc;
     }
@@ -575,9 +578,13 @@ __global__ __launch_bounds__(256, 2) void pair_reg_kernel(PairArgs a, int nblock
 #pragma unroll
     for (int h = 0; h < 4; ++h) {
       const int u = 2 * h + (lane >> 5), part = lane & 31;   // row u, 16-byte part
-      if (Q0 + u < NK && part * 2 < nI) {
+      // output block of row u (uniform loads, one per half wave)
+      const int s0 = Q0 + 2 * h < NK ? a.qslot[Q0 + 2 * h] : -1;
+      const int s1 = Q0 + 2 * h + 1 < NK ? a.qslot[Q0 + 2 * h + 1] : -1;
+      const int slot = (lane >> 5) ? s1 : s0;
+      if (slot >= 0 && part * 2 < nI) {
         const uint4 v = *(const uint4*)&st[u][part * 8];
-        *(uint4*)((unsigned short*)a.out + 4 * (base + (long long)(Q0 + u) * a.q_stride) + part * 8) = v;
+        *(uint4*)((unsigned short*)a.out + 4 * (base + (long long)slot * a.q_stride) + part * 8) = v;
       }
     }
     __builtin_amdgcn_wave_barrier();
@@ -643,6 +650,7 @@ bool pair_reg_supported(int fmt, int m1, int m2, int m3) {
 }
 
 hipError_t pair_launch(const PairArgs& a, hipStream_t s) {
+  if (!a.qslot) return hipErrorInvalidValue;
   if (pair_reg_supported(a.fmt, a.m1, a.m2, a.m3)) {
     if (!a.psi32 || !a.item_off) return hipErrorInvalidValue;
     switch (a.m1) {

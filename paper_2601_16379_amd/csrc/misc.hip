@@ -51,18 +51,21 @@ __global__ void nonfinite_kernel(const cplx* __restrict__ x, long long n, int* f
   if (bad) atomicOr(flag, 1);
 }
 
-// Wt[q][J][I] = W[q][I][J] in the three operand formats (row pitch ld,
-// zero padding for I >= n).
-__global__ void wt_convert_kernel(const cplx* __restrict__ w, cplx* wt64, float* wt32,
-                                  unsigned short* wt16, int n, int ld, int nq) {
-  const long long total = (long long)nq * n * ld;
+// Wt[h][J][I] = w_h W[hq[h]][I][J] in the three operand formats (row pitch
+// ld, zero padding for I >= n), w_h = 1/2 where q = -q (hself[h]).
+__global__ void wt_convert_kernel(const cplx* __restrict__ w, cplx* wt64, float* wt32, unsigned short* wt16,
+                                  int n, int ld, int nh, const int* __restrict__ hq,
+                                  const int* __restrict__ hself) {
+  const long long total = (long long)nh * n * ld;
   for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
        idx += (long long)gridDim.x * blockDim.x) {
-    const long long qJ = idx / ld;
-    const int I = (int)(idx - qJ * ld);
-    const int J = (int)(qJ % n);
-    const long long q = qJ / n;
-    const cplx v = (I < n) ? w[(q * n + I) * n + J] : cmk(0.0, 0.0);
+    const long long hJ = idx / ld;
+    const int I = (int)(idx - hJ * ld);
+    const int J = (int)(hJ % n);
+    const int h = (int)(hJ / n);
+    const long long q = hq[h];
+    const double wgt = hself[h] ? 0.5 : 1.0;
+    const cplx v = (I < n) ? cscale(w[(q * n + I) * n + J], wgt) : cmk(0.0, 0.0);
     if (wt64) wt64[idx] = v;
     if (wt32) store_fmt(wt32, idx, total, 1, v);
     if (wt16) store_fmt(wt16, idx, total, 2, v);
@@ -113,9 +116,9 @@ hipError_t nonfinite_launch(const cplx* x, long long n, int* flag, hipStream_t s
 }
 
 hipError_t wt_convert_launch(const cplx* w, cplx* wt64, float* wt32, unsigned short* wt16, int n,
-                             int ld, int nq, hipStream_t s) {
-  hipLaunchKernelGGL(wt_convert_kernel, dim3(grid_for((long long)nq * n * ld)), dim3(256), 0, s, w,
-                     wt64, wt32, wt16, n, ld, nq);
+                             int ld, int nh, const int* hq, const int* hself, hipStream_t s) {
+  hipLaunchKernelGGL(wt_convert_kernel, dim3(grid_for((long long)nh * n * ld)), dim3(256), 0, s, w,
+                     wt64, wt32, wt16, n, ld, nh, hq, hself);
   return hipGetLastError();
 }
 
