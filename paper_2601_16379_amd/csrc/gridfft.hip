@@ -60,6 +60,8 @@ __device__ inline double wrap_frac(int j, int m) {
   return (double)w / (double)m;
 }
 
+__device__ inline int q_of(const GridFftArgs& a, int qi) { return a.qlist ? a.qlist[qi] : a.q0 + qi; }
+
 __device__ inline void q_frac(const GridFftArgs& a, int q, double qf[3]) {
   const int j1 = q / (a.m2 * a.m3), j2 = (q / a.m3) % a.m2, j3 = q % a.m3;
   qf[0] = wrap_frac(j1, a.m1);
@@ -130,7 +132,7 @@ __global__ __launch_bounds__(256) void slab_kernel(GridFftArgs a, int S) {
     const int I = (int)(qI % a.n_ip);
     const int qi = (int)(qI / a.n_ip);
     double qf[3];
-    q_frac(a, a.q0 + qi, qf);
+    q_frac(a, q_of(a, qi), qf);
     const int i2 = p / a.n3, i3 = p - (p / a.n3) * a.n3;
     const double ph = qf[0] * i1 / a.n1 + qf[1] * i2 / a.n2 + qf[2] * i3 / a.n3;
     const cplx v = a.data[(long long)qi * a.q_stride + ((long long)I * a.n1 + i1) * n23 + p];
@@ -174,7 +176,7 @@ __global__ __launch_bounds__(256) void col_kernel(GridFftArgs a) {
   __syncthreads();
   fft_lines(buf, tmp, tw1, a.n1, COLS, 1, 1, 0, COLS);                 // along i1
   int jw[3];
-  q_wrapped(a, a.q0 + qi, jw);
+  q_wrapped(a, q_of(a, qi), jw);
   const double coef = sqrt(4.0 * M_PI * a.volume) / ((double)a.n1 * n23);
   for (int idx = threadIdx.x; idx < a.n1 * COLS; idx += blockDim.x) {
     const int i1 = idx / COLS, c = idx - (idx / COLS) * COLS;
@@ -309,7 +311,7 @@ __global__ __launch_bounds__(256) void slab_kernel_c(GridFftArgs a, int S) {
     const int I = (int)(qI % a.n_ip);
     const int qi = (int)(qI / a.n_ip);
     double qf[3];
-    q_frac(a, a.q0 + qi, qf);
+    q_frac(a, q_of(a, qi), qf);
     const int i2 = p / N, i3 = p % N;
     const double ph = (qf[0] * i1 + qf[1] * i2 + qf[2] * i3) / N;
     const cplx v = a.data[(long long)qi * a.q_stride + ((long long)I * N + i1) * N2 + p];
@@ -352,7 +354,7 @@ __global__ __launch_bounds__(256) void col_kernel_c(GridFftArgs a) {
   __syncthreads();
   fft_axis<N, 1, 1, 0, COLS>(buf, tmp, tw, COLS);   // along i1
   int jw[3];
-  q_wrapped(a, a.q0 + qi, jw);
+  q_wrapped(a, q_of(a, qi), jw);
   const double coef = sqrt(4.0 * M_PI * a.volume) / ((double)N * N2);
   for (int idx = threadIdx.x; idx < N * COLS; idx += blockDim.x) {
     const int i1 = idx / COLS, c = idx % COLS;
@@ -450,7 +452,7 @@ __global__ __launch_bounds__(N * N) void fft3_reg_kernel(GridFftArgs a) {
   const int I = (int)(blockIdx.x % (unsigned)a.n_ip);
   const int qi = (int)(blockIdx.x / (unsigned)a.n_ip);
   double qf[3];
-  q_frac(a, a.q0 + qi, qf);
+  q_frac(a, q_of(a, qi), qf);
   if (t < 3 * N) {
     const int ax = t / N, i = t % N;
     const cplx e = cexpipi(-2.0 * qf[ax] * i / N);
@@ -560,7 +562,7 @@ __global__ __launch_bounds__(256) void coulomb_table_kernel(GridFftArgs a) {
   const long long ng = (long long)a.n1 * a.n2 * a.n3;
   const int qi = blockIdx.y;
   int jw[3];
-  q_wrapped(a, a.q0 + qi, jw);
+  q_wrapped(a, q_of(a, qi), jw);
   const double coef = sqrt(4.0 * M_PI * a.volume) / (double)ng;
   for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < ng; g += (long long)gridDim.x * blockDim.x) {
     const int i1 = (int)(g / ((long long)a.n2 * a.n3)), i2 = (int)((g / a.n3) % a.n2), i3 = (int)(g % a.n3);

@@ -402,6 +402,7 @@ long long nip2(const isdf_ctx c) { return (long long)c->nip * c->nip; }
 void do_fit(isdf_ctx c, int prec) {
   hipStream_t s = c->stream;
   const int nk = c->nk, norb = c->norb, nip = c->nip;
+  const int nh = c->nh;                 // classes {q, -q}: Pi, eta, W are kept for one q of each
   const long long ng = c->ng;
   c->arena.reset();
   // the second stream may still be forming the previous fit's pseudo-inverse
@@ -421,7 +422,8 @@ void do_fit(isdf_ctx c, int prec) {
     run_gemm(c->arena, 0, GEMM_A_KM | GEMM_B_KN | GEMM_B_CONJ, d, s);
   }
   c->timer.end("metric_t", s);
-  // Pi^q = N_k^-1 sum_R exp(iq.R) |sum_k exp(ik.R) T^k|^2   (eq. (4), Algorithm 1)
+  // Pi^q = N_k^-1 sum_R exp(iq.R) |sum_k exp(ik.R) T^k|^2   (eq. (4), Algorithm 1),
+  // kept for one q per class (Pi^{-q} = conj Pi^q), in class order
   c->timer.begin("metric_kconv", s);
   {
     KconvArgs a;
@@ -435,6 +437,7 @@ void do_fit(isdf_ctx c, int prec) {
     a.m1 = c->m[0]; a.m2 = c->m[1]; a.m3 = c->m[2];
     a.mode = 0;
     a.scale = 1.0 / nk;
+    a.qslot = c->qmap.as<int>();
     HIPCHK(kconv_launch(a, s));
   }
   c->timer.end("metric_kconv", s);
@@ -473,6 +476,7 @@ void do_fit(isdf_ctx c, int prec) {
     a.m1 = c->m[0]; a.m2 = c->m[1]; a.m3 = c->m[2];
     a.mode = 0;
     a.scale = 1.0 / nk;
+    a.qslot = c->qmap.as<int>();         // eta^{-q} = conj eta^q: one q per class
     HIPCHK(kconv_launch(a, s));
     c->timer.end("rhs_kconv", s);
   }
@@ -483,18 +487,18 @@ void do_fit(isdf_ctx c, int prec) {
     cplx* A = c->work2.as<cplx>();
     const double rtol = 1e-13;
     HIPCHK(bchol_setup_launch(c->pi.as<cplx>(), A, c->perm.as<int>(), c->rank.as<int>(),
-                              c->dmax.as<double>(), c->cflag.as<int>(), nip, nk, c->aux));
+                              c->dmax.as<double>(), c->cflag.as<int>(), nip, nh, c->aux));
     for (int jb = 0; jb < nip; jb += CHOL_NB) {
-      HIPCHK(bchol_diag_launch(A, c->lt.as<cplx>(), c->dmax.as<double>(), c->cflag.as<int>(), nip, nk,
+      HIPCHK(bchol_diag_launch(A, c->lt.as<cplx>(), c->dmax.as<double>(), c->cflag.as<int>(), nip, nh,
                                jb, rtol, c->aux));
-      HIPCHK(bchol_panel_launch(A, c->lt.as<cplx>(), c->cflag.as<int>(), nip, nk, jb, c->aux));
+      HIPCHK(bchol_panel_launch(A, c->lt.as<cplx>(), c->cflag.as<int>(), nip, nh, jb, c->aux));
       const int rest = nip - jb - CHOL_NB;
       if (rest > 0) {
         std::vector<NtDesc> d(1);
         const cplx* L21 = A + (long long)(jb + CHOL_NB) * nip + jb;
         d[0] = mknt(L21, nip, L21, nip, A + (long long)(jb + CHOL_NB) * (nip + 1), nip, rest, rest,
                     CHOL_NB);
-        d[0].batch = nk;
+        d[0].batch = nh;
         d[0].sA_bat = d[0].sB_bat = d[0].sC_bat = nip2(c);
         d[0].herm = 2;
         d[0].epi = 4;
@@ -503,12 +507,12 @@ void do_fit(isdf_ctx c, int prec) {
     }
     // matrices whose pivots fell below the rank tolerance (singular metrics)
     // are refactored with diagonal pivoting
-    std::vector<int> fl(nk, 0);
-    HIPCHK(hipMemcpyAsync(fl.data(), c->cflag.p, sizeof(int) * nk, hipMemcpyDeviceToHost, c->aux));
+    std::vector<int> fl(nh, 0);
+    HIPCHK(hipMemcpyAsync(fl.data(), c->cflag.p, sizeof(int) * nh, hipMemcpyDeviceToHost, c->aux));
     HIPCHK(hipStreamSynchronize(c->aux));
     std::vector<int> qs;
-    for (int q = 0; q < nk; ++q)
-      if (fl[q]) qs.push_back(q);
+    for (int h = 0; h < nh; ++h)
+      if (fl[h]) qs.push_back(h);
     if (!qs.empty()) {
       int* ql = c->arena_aux.put(qs.data(), qs.size(), c->aux);
       HIPCHK(chol_launch(c->pi.as<cplx>(), A, c->lt.as<cplx>(), c->perm.as<int>(), c->rank.as<int>(),
@@ -518,19 +522,20 @@ void do_fit(isdf_ctx c, int prec) {
   c->timer.end("chol", c->aux);
   HIPCHK(hipEventRecord(c->ev_join, c->aux));
   HIPCHK(hipStreamWaitEvent(s, c->ev_join, 0));
-  c->rank_h.assign(nk, 0);
-  HIPCHK(hipMemcpyAsync(c->rank_h.data(), c->rank.p, sizeof(int) * nk, hipMemcpyDeviceToHost, s));
+  c->rank_h.assign(nh, 0);
+  HIPCHK(hipMemcpyAsync(c->rank_h.data(), c->rank.p, sizeof(int) * nh, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   {
     std::lock_guard<std::mutex> lk(c->mu);
     c->timer.collect(&c->totals);
   }
-  for (int q = 0; q < nk; ++q) {
-    if (c->rank_h[q] <= 0)
+  for (int h = 0; h < nh; ++h) {
+    const int q = c->hq_h[h];
+    if (c->rank_h[h] <= 0)
       throw Fail{ISDF_E_NUMERIC, "metric Pi^q is zero or not finite at q = " + std::to_string(q)};
-    if ((c->flags & ISDF_NO_PIVOT) && c->rank_h[q] < nip)
-      throw Fail{ISDF_E_NUMERIC, "Cholesky breakdown of Pi^q (singular metric) at q = " +
-                                     std::to_string(q) + ", column " + std::to_string(c->rank_h[q])};
+    if ((c->flags & ISDF_NO_PIVOT) && c->rank_h[h] < nip)
+      throw Fail{ISDF_E_NUMERIC, "Cholesky breakdown of Pi^q (singular metric) at q = " + std::to_string(q) +
+                                     ", column " + std::to_string(c->rank_h[h])};
   }
   // The pseudo-inverse factor of eq. (8) on the second stream: it overlaps
   // the grid FFT and the V^q product of isdf_coulomb_kernel, which waits for
@@ -546,26 +551,26 @@ void do_fit(isdf_ctx c, int prec) {
     {
       cplx* Lrow = c->work3.as<cplx>();
       cplx* St = c->pinv_ws.as<cplx>();
-      cplx* Yd = St + (long long)nk * nip * 64;
+      cplx* Yd = St + (long long)nh * nip * 64;
       const long long nn = nip2(c);
-      HIPCHK(tri_setup_launch(c->lt.as<cplx>(), c->rank.as<int>(), Lrow, A, nip, nk, c->aux));
+      HIPCHK(tri_setup_launch(c->lt.as<cplx>(), c->rank.as<int>(), Lrow, A, nip, nh, c->aux));
       for (int jb = 0; jb < nip; jb += 64) {
         const int nb = std::min(64, nip - jb);
         if (jb > 0) {
           // St[n][m] = sum_{k < jb} Yt[n][k] L[jb+m][k]
           std::vector<NtDesc> g(1);
           g[0] = mknt(A, nip, Lrow + (long long)jb * nip, nip, St, 64, jb, nb, jb);
-          g[0].batch = nk;
+          g[0].batch = nh;
           g[0].sA_bat = g[0].sB_bat = nn;
           g[0].sC_bat = (long long)nip * 64;
           run_nt(c->arena_aux, 0, 0, g, c->aux);
         }
-        HIPCHK(tri_inv_diag_launch(Lrow, c->rank.as<int>(), A, Yd, nip, nk, jb, c->aux));
+        HIPCHK(tri_inv_diag_launch(Lrow, c->rank.as<int>(), A, Yd, nip, nh, jb, c->aux));
         if (jb > 0) {
           // Yt[n][jb+m] = Y[jb+m][n] = -sum_k St[n][k] Y_bb[m][k]
           std::vector<NtDesc> g(1);
           g[0] = mknt(St, 64, Yd, 64, A + jb, nip, jb, nb, nb);
-          g[0].batch = nk;
+          g[0].batch = nh;
           g[0].sA_bat = (long long)nip * 64;
           g[0].sB_bat = 4096;
           g[0].sC_bat = nn;
@@ -576,7 +581,7 @@ void do_fit(isdf_ctx c, int prec) {
     }
     std::vector<NtDesc> d(1);
     d[0] = mknt(A, nip, A, nip, c->work3.as<cplx>(), nip, nip, nip, nip);
-    d[0].batch = nk;
+    d[0].batch = nh;
     d[0].sA_bat = d[0].sB_bat = d[0].sC_bat = nip2(c);
     d[0].herm = 1;
     // G[m][n] = sum_i conj(Yt[m][i]) Yt[n][i]
@@ -598,11 +603,12 @@ void do_kernel(isdf_ctx c, int prec) {
     throw Fail{ISDF_E_STATE, "eta was stored in FP32 by a mixed-precision fit; fit with ISDF_FP64 first"};
   hipStream_t s = c->stream;
   const int nk = c->nk, nip = c->nip;
+  const int nh = c->nh;                 // one q per class {q, -q}: W^{-q} = conj W^q
   const long long ng = c->ng;
   c->arena.reset();
   // eta~^q_I(G) = sqrt(Omega 4pi/|G+q|^2)/N_g FFT[eta^q_I(r) exp(-iq.r)]   (eqs. (6)-(7));
   // in place (FP64) or into the split operand format of the V GEMM (mixed)
-  const long long split_plane = (long long)nk * nip * c->ld_g;
+  const long long split_plane = (long long)nh * nip * c->ld_g;
   if (prec != ISDF_FP64) c->eta_split.ensure((size_t)split_plane * 8);
   c->timer.begin("grid_fft", s);
   {
@@ -612,7 +618,7 @@ void do_kernel(isdf_ctx c, int prec) {
     a.data32 = c->eta32 ? c->eta.as<float2>() : nullptr;
     // per-q Coulomb factors of the one-pass (register) FFT
     if (prec != ISDF_FP64 && gridfft_reg_grid(c->n[0], c->n[1], c->n[2])) {
-      c->fac.ensure((size_t)nk * ng * sizeof(float));
+      c->fac.ensure((size_t)nh * ng * sizeof(float));
       a.fac = c->fac.as<float>();
     }
     a.fmt = prec;
@@ -623,7 +629,8 @@ void do_kernel(isdf_ctx c, int prec) {
     a.n1 = c->n[0]; a.n2 = c->n[1]; a.n3 = c->n[2];
     a.m1 = c->m[0]; a.m2 = c->m[1]; a.m3 = c->m[2];
     a.q0 = 0;
-    a.nq = nk;
+    a.nq = nh;
+    a.qlist = c->qmap.as<int>() + nk;
     a.n_ip = nip;
     a.q_stride = (long long)nip * ng;
     memcpy(a.recip, c->recip, sizeof(a.recip));
@@ -640,7 +647,7 @@ void do_kernel(isdf_ctx c, int prec) {
     if (prec == ISDF_FP64) {
       d[0] = mknt(c->eta.p, ng, c->eta.p, ng, c->work1.p, nip, nip, nip, (int)ng);
       d[0].sA_bat = d[0].sB_bat = (long long)nip * ng;
-      d[0].batch = nk;
+      d[0].batch = nh;
       d[0].sC_bat = nip2(c);
       d[0].herm = 1;
       run_nt(c->arena, prec, 2, d, s, 1);
@@ -655,12 +662,12 @@ void do_kernel(isdf_ctx c, int prec) {
       d[0].Klast = (int)(ng - (long long)(d[0].nseg - 1) * d[0].Kseg);
       d[0].sA_seg = d[0].sB_seg = d[0].Kseg;
       d[0].sA_bat = d[0].sB_bat = (long long)nip * c->ld_g;
-      d[0].batch = nk;
+      d[0].batch = nh;
       d[0].sC_bat = nip2(c);
       d[0].herm = 2;
       d[0].epi = 1;
       run_big(c->arena, prec, 2, d, d[0].nseg, s, 1);
-      HIPCHK(herm_fill_launch(c->work1.as<cplx>(), nip, nip, nip2(c), nk, s));
+      HIPCHK(herm_fill_launch(c->work1.as<cplx>(), nip, nip, nip2(c), nh, s));
     }
   }
   c->timer.end("v_gemm", s);
@@ -673,12 +680,12 @@ void do_kernel(isdf_ctx c, int prec) {
   {
     const long long n2 = nip2(c);
     HIPCHK(permute_launch(c->work1.as<cplx>(), c->w.as<cplx>(), c->perm.as<int>(), c->rank.as<int>(),
-                          nip, nk, 0, s));
+                          nip, nh, 0, s));
     auto prod = [&](const cplx* A, const cplx* B, cplx* C, int conj, int herm) {
       std::vector<NtDesc> d;
-      for (int q = 0; q < nk; ++q) {
-        const int r = c->rank_h[q];
-        NtDesc g = mknt(A + q * n2, nip, B + q * n2, nip, C + q * n2, nip, r, r, r);
+      for (int h = 0; h < nh; ++h) {
+        const int r = c->rank_h[h];
+        NtDesc g = mknt(A + h * n2, nip, B + h * n2, nip, C + h * n2, nip, r, r, r);
         g.herm = herm;
         d.push_back(g);
       }
@@ -689,17 +696,16 @@ void do_kernel(isdf_ctx c, int prec) {
     // W' = T1 G  (G Hermitian); W' = G V' G is Hermitian: lower tiles, mirrored
     prod(c->work1.as<cplx>(), c->work3.as<cplx>(), c->work2.as<cplx>(), 2, 1);
     HIPCHK(permute_launch(c->work2.as<cplx>(), c->w.as<cplx>(), c->perm.as<int>(), c->rank.as<int>(),
-                          nip, nk, 1, s));
+                          nip, nh, 1, s));
   }
   c->timer.end("w_solve", s);
   // transposed copies of W in the three operand formats of the fragment GEMMs
   // (one per class {q, -q}, weight 1/2 where q = -q: the fragment contraction
   // adds the conjugate term of -q itself)
   HIPCHK(wt_convert_launch(c->w.as<cplx>(), c->wt64.as<cplx>(), c->wt32.as<float>(),
-                           c->wt16.as<unsigned short>(), nip, (int)c->ld_ip, c->nh, c->qmap.as<int>() + nk,
-                           c->qmap.as<int>() + nk + c->nh, s));
+                           c->wt16.as<unsigned short>(), nip, (int)c->ld_ip, nh, c->qmap.as<int>() + nk + nh, s));
   HIPCHK(hipMemsetAsync(c->flag.p, 0, sizeof(int), s));
-  HIPCHK(nonfinite_launch(c->w.as<cplx>(), (long long)nk * nip2(c), c->flag.as<int>(), s));
+  HIPCHK(nonfinite_launch(c->w.as<cplx>(), (long long)nh * nip2(c), c->flag.as<int>(), s));
   int bad = 0;
   HIPCHK(hipMemcpyAsync(&bad, c->flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
@@ -1282,20 +1288,43 @@ static isdf_status get_mat(isdf_ctx ctx, const DevBuf& b, long long off, size_t 
   });
 }
 
+// Index of -q on the k mesh, and for a q of no stored class its partner:
+// the stored class slot of q or of -q, and whether the value is conjugated.
+static int minus_q_index(isdf_ctx c, int q) {
+  const int j1 = q / (c->m[1] * c->m[2]), j2 = (q / c->m[2]) % c->m[1], j3 = q % c->m[2];
+  return (((c->m[0] - j1) % c->m[0]) * c->m[1] + (c->m[1] - j2) % c->m[1]) * c->m[2] + (c->m[2] - j3) % c->m[2];
+}
+static int class_slot(isdf_ctx c, int q, bool* conj) {
+  const int h = c->qslot_h[q];
+  *conj = h < 0;
+  return h >= 0 ? h : c->qslot_h[minus_q_index(c, q)];
+}
+
+// Copy slot h of a [class][n][n] matrix set to host, conjugated for -q.
+static isdf_status get_class_mat(isdf_ctx ctx, const DevBuf& b, int q, void* out) {
+  bool cj;
+  const int h = class_slot(ctx, q, &cj);
+  const size_t bytes = (size_t)ctx->nip * ctx->nip * sizeof(cplx);
+  isdf_status st = get_mat(ctx, b, (long long)h * bytes, bytes, out);
+  if (st == ISDF_OK && cj) {
+    cplx* o = (cplx*)out;
+    for (size_t i = 0; i < (size_t)ctx->nip * ctx->nip; ++i) o[i].y = -o[i].y;
+  }
+  return st;
+}
+
 isdf_status isdf_get_metric(isdf_ctx ctx, int32_t q, void* out) {
   if (!ctx) return ISDF_E_INVALID;
   if (!ctx->fitted) return fail(ctx, ISDF_E_STATE, "metric not computed");
   if (q < 0 || q >= ctx->nk || !out) return fail(ctx, ISDF_E_INVALID, "bad q");
-  const size_t b = (size_t)ctx->nip * ctx->nip * sizeof(cplx);
-  return get_mat(ctx, ctx->pi, (long long)q * b, b, out);
+  return get_class_mat(ctx, ctx->pi, q, out);              // Pi^{-q} = conj Pi^q
 }
 
 isdf_status isdf_get_kernel(isdf_ctx ctx, int32_t q, void* out) {
   if (!ctx) return ISDF_E_INVALID;
   if (!ctx->kernel_ready) return fail(ctx, ISDF_E_STATE, "Coulomb kernel not computed");
   if (q < 0 || q >= ctx->nk || !out) return fail(ctx, ISDF_E_INVALID, "bad q");
-  const size_t b = (size_t)ctx->nip * ctx->nip * sizeof(cplx);
-  return get_mat(ctx, ctx->w, (long long)q * b, b, out);
+  return get_class_mat(ctx, ctx->w, q, out);               // W^{-q} = conj W^q
 }
 
 isdf_status isdf_get_ivs(isdf_ctx ctx, int32_t k, void* out) {
@@ -1318,14 +1347,23 @@ isdf_status isdf_get_rhs(isdf_ctx ctx, int32_t q, void* out) {
   if (!ctx->eta_valid) return fail(ctx, ISDF_E_STATE, "eta not available (fit first; consumed by the kernel)");
   if (q < 0 || q >= ctx->nk || !out) return fail(ctx, ISDF_E_INVALID, "bad q");
   const size_t n = (size_t)ctx->nip * ctx->ng;
-  if (!ctx->eta32) return get_mat(ctx, ctx->eta, (long long)q * n * sizeof(cplx), n * sizeof(cplx), out);
+  bool cj;                                                   // eta^{-q} = conj eta^q
+  const int hs = class_slot(ctx, q, &cj);
   return guarded(ctx, [&] {
-    std::vector<float2> h(n);
-    HIPCHK(hipMemcpyAsync(h.data(), ctx->eta.as<float2>() + (long long)q * n, n * sizeof(float2),
-                          hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(hipStreamSynchronize(ctx->stream));
     cplx* o = (cplx*)out;
-    for (size_t i = 0; i < n; ++i) o[i] = cmk((double)h[i].x, (double)h[i].y);
+    if (!ctx->eta32) {
+      HIPCHK(hipMemcpyAsync(o, ctx->eta.as<cplx>() + (long long)hs * n, n * sizeof(cplx), hipMemcpyDeviceToHost,
+                            ctx->stream));
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+    } else {
+      std::vector<float2> h(n);
+      HIPCHK(hipMemcpyAsync(h.data(), ctx->eta.as<float2>() + (long long)hs * n, n * sizeof(float2),
+                            hipMemcpyDeviceToHost, ctx->stream));
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+      for (size_t i = 0; i < n; ++i) o[i] = cmk((double)h[i].x, (double)h[i].y);
+    }
+    if (cj)
+      for (size_t i = 0; i < n; ++i) o[i].y = -o[i].y;
   });
 }
 
@@ -1334,24 +1372,51 @@ isdf_status isdf_get_eta_tilde(isdf_ctx ctx, int32_t q, void* out) {
   if (!ctx->kernel_ready) return fail(ctx, ISDF_E_STATE, "eta~ not computed (isdf_coulomb_kernel first)");
   if (q < 0 || q >= ctx->nk || !out) return fail(ctx, ISDF_E_INVALID, "bad q");
   const long long nip = ctx->nip, ng = ctx->ng, ldg = ctx->ld_g;
+  // a q of no stored class: eta~^q(G) = conj(eta~^{-q}(G')) with G' the
+  // index of -(G + q) - (-q) (per axis -s, or 1 - s where q sits on the
+  // zone boundary of an even mesh), which the symmetric kernel weighs alike
+  bool cj;
+  const int hs = class_slot(ctx, q, &cj);
+  auto reflect = [&](cplx* o) {
+    if (!cj) return;
+    const int j[3] = {q / (ctx->m[1] * ctx->m[2]), (q / ctx->m[2]) % ctx->m[1], q % ctx->m[2]};
+    int dl[3];
+    for (int d = 0; d < 3; ++d) dl[d] = (ctx->m[d] % 2 == 0 && 2 * j[d] == ctx->m[d]) ? 1 : 0;
+    std::vector<cplx> row(ng);
+    for (long long i = 0; i < nip; ++i) {
+      cplx* r = o + i * ng;
+      for (long long g = 0; g < ng; ++g) {
+        const int s1 = (int)(g / ((long long)ctx->n[1] * ctx->n[2])), s2 = (int)((g / ctx->n[2]) % ctx->n[1]),
+                  s3 = (int)(g % ctx->n[2]);
+        const int t1 = ((dl[0] - s1) % ctx->n[0] + ctx->n[0]) % ctx->n[0];
+        const int t2 = ((dl[1] - s2) % ctx->n[1] + ctx->n[1]) % ctx->n[1];
+        const int t3 = ((dl[2] - s3) % ctx->n[2] + ctx->n[2]) % ctx->n[2];
+        const cplx v = r[((long long)t1 * ctx->n[1] + t2) * ctx->n[2] + t3];
+        row[g] = cmk(v.x, -v.y);
+      }
+      memcpy(r, row.data(), ng * sizeof(cplx));
+    }
+  };
   if (ctx->kernel_prec == ISDF_FP64) {
     const size_t b = (size_t)nip * ng * sizeof(cplx);
-    return get_mat(ctx, ctx->eta, (long long)q * b, b, out);
+    isdf_status st = get_mat(ctx, ctx->eta, (long long)hs * b, b, out);
+    if (st == ISDF_OK) reflect((cplx*)out);
+    return st;
   }
   return guarded(ctx, [&] {
     // the split operand of the V^q product, converted exactly to c128
     // (FP32: two planes; bf16x3: hi/lo interleaved by groups of 8 elements)
     const bool f32 = ctx->kernel_prec == ISDF_MIXED_FP32;
-    const long long plane = (long long)ctx->nk * nip * ldg;
+    const long long plane = (long long)ctx->nh * nip * ldg;
     const size_t rows = (size_t)nip * ldg;
     std::vector<unsigned char> h(rows * 8);
     if (f32) {
       for (int pl = 0; pl < 2; ++pl)
         HIPCHK(hipMemcpyAsync(h.data() + pl * rows * 4,
-                              ctx->eta_split.as<char>() + ((long long)pl * plane + (long long)q * nip * ldg) * 4,
+                              ctx->eta_split.as<char>() + ((long long)pl * plane + (long long)hs * nip * ldg) * 4,
                               rows * 4, hipMemcpyDeviceToHost, ctx->stream));
     } else {
-      HIPCHK(hipMemcpyAsync(h.data(), ctx->eta_split.as<char>() + (long long)q * nip * ldg * 8, rows * 8,
+      HIPCHK(hipMemcpyAsync(h.data(), ctx->eta_split.as<char>() + (long long)hs * nip * ldg * 8, rows * 8,
                             hipMemcpyDeviceToHost, ctx->stream));
     }
     HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -1374,6 +1439,7 @@ isdf_status isdf_get_eta_tilde(isdf_ctx ctx, int32_t q, void* out) {
                               bf(u, bf16x3_index(e, 2)) + bf(u, bf16x3_index(e, 3)));
         }
       }
+    reflect(o);
   });
 }
 
@@ -1502,7 +1568,12 @@ isdf_status isdf_stats(isdf_ctx ctx, char* json, int64_t cap) {
   std::string s = "{\"n_k\":" + std::to_string(ctx->nk) + ",\"n_g\":" + std::to_string(ctx->ng) +
                   ",\"n_orb\":" + std::to_string(ctx->norb) + ",\"n_ip\":" + std::to_string(ctx->nip) +
                   ",\"r_tile\":" + std::to_string(ctx->rc) + ",\"rank\":[";
-  for (size_t i = 0; i < ctx->rank_h.size(); ++i) s += (i ? "," : "") + std::to_string(ctx->rank_h[i]);
+  // per q (the class of q or of -q; the factor of conj Pi has the same rank)
+  if (!ctx->rank_h.empty())
+    for (int q = 0; q < ctx->nk; ++q) {
+      bool cj;
+      s += (q ? "," : "") + std::to_string(ctx->rank_h[class_slot(ctx, q, &cj)]);
+    }
   s += "],\"stage_ms\":{";
   bool first = true;
   for (auto& kv : ctx->timer.ms) {

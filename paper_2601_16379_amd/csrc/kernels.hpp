@@ -99,12 +99,12 @@ hipError_t x3_launch(int conj, const NtDesc* descs_dev, int ndesc, long long tot
 // of a 4x4x4 mesh take one launch)
 constexpr int ERI_QGROUP = 40;
 
-// W^q (c128 [q][n][n]) -> transposed copies Wt[h][J][I] = w_h W[hq[h]][I][J]
-// for the nh classes {q, -q} (hq, hself: device), w_h = 1/2 where q = -q,
-// with row pitch ld in c128, two-float-plane and four-bf16-plane formats
-// (any output pointer may be null); pad columns are zero.
+// W (c128 [h][n][n], one q per class {q, -q}) -> transposed copies
+// Wt[h][J][I] = w_h W[h][I][J], w_h = 1/2 where q = -q (hself: device), with
+// row pitch ld in c128, two-float-plane and four-bf16-plane formats (any
+// output pointer may be null); pad columns are zero.
 hipError_t wt_convert_launch(const cplx* w, cplx* wt64, float* wt32, unsigned short* wt16, int n,
-                             int ld, int nh, const int* hq, const int* hself, hipStream_t s);
+                             int ld, int nh, const int* hself, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // k-mesh transforms (Algorithm 1 and 2 in the k/R domain), LDS-staged.
@@ -122,6 +122,7 @@ struct KconvArgs {
   double scale;
   float2* out32;        // when set, the result goes here as complex FP32 (same offsets), not to out
   const float2* in32;   // when set, the input is read from here as complex FP32 (same offsets), not from in
+  const int* qslot;     // mode 0, device, optional: output q goes to block qslot[q] (skipped if < 0)
 };
 hipError_t kconv_launch(const KconvArgs& a, hipStream_t s);
 
@@ -173,6 +174,7 @@ struct GridFftArgs {
   cplx* data;
   const float2* data32;   // mixed formats on the register grids: complex FP32 input (same offsets) instead of data
   float* fac;             // mixed formats on the register grids: scratch of nq * N_g floats for the Coulomb factors
+  const int* qlist;       // device, optional: item qi is momentum qlist[qi] (else q0 + qi)
   void* split;            // optional split output (fmt 1 / 2) instead of writing data back
   int fmt;                // 0: in place c128; 1 float planes; 2 bf16 hi/lo planes
   long long split_ld, split_plane, split_q;   // row pitch, plane stride, q stride

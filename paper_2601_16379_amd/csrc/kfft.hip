@@ -163,8 +163,9 @@ __global__ __launch_bounds__(256) void kconv_kernel(KconvArgs a, int etile) {
     mesh_dft<MAXA>(buf, tw, etile, a.m1, a.m2, a.m3, a.sign);
   }
   for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-    const int q = idx >> eshift, e = idx & (etile - 1);
-    if (e < ne) {
+    const int q0 = idx >> eshift, e = idx & (etile - 1);
+    const int q = (a.mode == 0 && a.qslot) ? a.qslot[q0] : q0;
+    if (q >= 0 && e < ne) {
       long long off;
       if (fast) {
         off = out0 + e;
@@ -399,7 +400,9 @@ __global__ __launch_bounds__(256) void kconv_reg_kernel(KconvArgs a) {
   const long long oe = (e / a.out_inner) * a.out_outer + e % a.out_inner;
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
-    const long long off = (long long)(k1 * NV + v) * a.out_qstride + oe;
+    const int slot = a.qslot ? a.qslot[k1 * NV + v] : k1 * NV + v;
+    if (slot < 0) continue;
+    const long long off = (long long)slot * a.out_qstride + oe;
     const cplx r = cscale(x[v], a.scale);
     if (F32) a.out32[off] = make_float2((float)r.x, (float)r.y);
     else a.out[off] = r;

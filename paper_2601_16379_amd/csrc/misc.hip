@@ -51,11 +51,10 @@ __global__ void nonfinite_kernel(const cplx* __restrict__ x, long long n, int* f
   if (bad) atomicOr(flag, 1);
 }
 
-// Wt[h][J][I] = w_h W[hq[h]][I][J] in the three operand formats (row pitch
-// ld, zero padding for I >= n), w_h = 1/2 where q = -q (hself[h]).
+// Wt[h][J][I] = w_h W[h][I][J] in the three operand formats (row pitch ld,
+// zero padding for I >= n), w_h = 1/2 where q = -q (hself[h]).
 __global__ void wt_convert_kernel(const cplx* __restrict__ w, cplx* wt64, float* wt32, unsigned short* wt16,
-                                  int n, int ld, int nh, const int* __restrict__ hq,
-                                  const int* __restrict__ hself) {
+                                  int n, int ld, int nh, const int* __restrict__ hself) {
   const long long total = (long long)nh * n * ld;
   for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
        idx += (long long)gridDim.x * blockDim.x) {
@@ -63,7 +62,7 @@ __global__ void wt_convert_kernel(const cplx* __restrict__ w, cplx* wt64, float*
     const int I = (int)(idx - hJ * ld);
     const int J = (int)(hJ % n);
     const int h = (int)(hJ / n);
-    const long long q = hq[h];
+    const long long q = h;
     const double wgt = hself[h] ? 0.5 : 1.0;
     const cplx v = (I < n) ? cscale(w[(q * n + I) * n + J], wgt) : cmk(0.0, 0.0);
     if (wt64) wt64[idx] = v;
@@ -116,9 +115,9 @@ hipError_t nonfinite_launch(const cplx* x, long long n, int* flag, hipStream_t s
 }
 
 hipError_t wt_convert_launch(const cplx* w, cplx* wt64, float* wt32, unsigned short* wt16, int n,
-                             int ld, int nh, const int* hq, const int* hself, hipStream_t s) {
+                             int ld, int nh, const int* hself, hipStream_t s) {
   hipLaunchKernelGGL(wt_convert_kernel, dim3(grid_for((long long)nh * n * ld)), dim3(256), 0, s, w,
-                     wt64, wt32, wt16, n, ld, nh, hq, hself);
+                     wt64, wt32, wt16, n, ld, nh, hself);
   return hipGetLastError();
 }
 
