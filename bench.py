@@ -45,39 +45,56 @@ def parse():
     return ap.parse_args()
 
 
+def n_classes(kmesh):
+    """Number of classes {q, -q} of the k mesh: the stages from the metric on
+    run over one q of each (the others are complex conjugates)."""
+    m1, m2, m3 = kmesh
+    n = 0
+    for j1 in range(m1):
+        for j2 in range(m2):
+            for j3 in range(m3):
+                q = (j1 * m2 + j2) * m3 + j3
+                mq = (((m1 - j1) % m1) * m2 + (m2 - j2) % m2) * m3 + (m3 - j3) % m3
+                n += mq >= q
+    return n
+
+
 def stage_work(stage, cfg, nfs, prec, eta32=False):
     """(bound, algorithmic amount per launch, unit, peak) of a stage; eta32:
-    the fit stored T and eta as complex FP32 (8 B a value, else 16)."""
+    the fit stored T and eta as complex FP32 (8 B a value, else 16).  The
+    k-space stages (T^k, k convolutions' inputs) count all N_k; everything
+    indexed by q counts the nh classes {q, -q} it runs over."""
     nk, nip, ng, norb = cfg.n_k, cfg.n_ip, cfg.n_g, cfg.n_orb
+    nh = n_classes(cfg.kmesh)
     eb = 8 if eta32 else 16
     s2 = sum(n * n for n in nfs)
     dt, pk = PREC_PEAK[prec]
     if stage == "frag_eri":   # Hermitian half of sum_q U^q R^{qH} per fragment
-        fl = sum(8.0 * nk * nip * (n * n) * (n * n + 1) / 2 for n in nfs)
+        fl = sum(8.0 * nh * nip * (n * n) * (n * n + 1) / 2 for n in nfs)
         return "mfma", fl / 1e12, "TFLOP", pk
     if stage == "frag_u":     # U^q = W^q R^q
-        return "mfma", 8.0 * nk * nip * nip * s2 / 1e12, "TFLOP", pk
+        return "mfma", 8.0 * nh * nip * nip * s2 / 1e12, "TFLOP", pk
     if stage == "v_gemm":     # Hermitian half of eta~ eta~^H
-        return "mfma", 8.0 * nk * nip * nip * ng / 2 / 1e12, "TFLOP", pk
+        return "mfma", 8.0 * nh * nip * nip * ng / 2 / 1e12, "TFLOP", pk
     if stage == "grid_fft":
         if prec == "fp64":    # two read+write passes over eta (c128)
-            return "hbm", 4.0 * nk * nip * ng * 16 / 1e9, "GB", PEAK["hbm"]
+            return "hbm", 4.0 * nh * nip * ng * 16 / 1e9, "GB", PEAK["hbm"]
         # one pass: eta read, the split operand written (8 B a point)
-        return "hbm", nk * nip * ng * (eb + 8) / 1e9, "GB", PEAK["hbm"]
+        return "hbm", nh * nip * ng * (eb + 8) / 1e9, "GB", PEAK["hbm"]
     if stage == "rhs_t":      # T^k_I(r) = X^k conj(phi^k): written once
         return "hbm", 1.0 * nk * nip * ng * eb / 1e9, "GB", PEAK["hbm"]
-    if stage == "rhs_kconv":  # T^k_I(r) read, eta written once
-        return "hbm", 2.0 * nk * nip * ng * eb / 1e9, "GB", PEAK["hbm"]
+    if stage == "rhs_kconv":  # T^k_I(r) read (all k), eta written once (nh classes)
+        return "hbm", (nk + nh) * nip * ng * eb / 1e9, "GB", PEAK["hbm"]
     if stage == "metric_kconv":
-        return "hbm", 2.0 * nk * nip * nip * 16 / 1e9, "GB", PEAK["hbm"]
+        return "hbm", (nk + nh) * nip * nip * 16 / 1e9, "GB", PEAK["hbm"]
     if stage == "frag_pair":  # write R^q once (c128 in FP64, 8 B a point in the mixed formats)
-        return "hbm", nk * nip * s2 * (16 if prec == "fp64" else 8) / 1e9, "GB", PEAK["hbm"]
+        return "hbm", nh * nip * s2 * (16 if prec == "fp64" else 8) / 1e9, "GB", PEAK["hbm"]
     if stage == "chol":       # blocked factor: n^3/3 complex MACs
-        return "fp64", 8.0 * nk * nip ** 3 / 3 / 1e12, "TFLOP", PEAK["fp64"]
+        return "fp64", 8.0 * nh * nip ** 3 / 3 / 1e12, "TFLOP", PEAK["fp64"]
     if stage == "pinv":       # L^{-1} (n^3/6) and G = Y^H Y lower half (n^3/2) complex MACs
-        return "fp64", 8.0 * nk * nip ** 3 * (1 / 6 + 1 / 2) / 1e12, "TFLOP", PEAK["fp64"]
+        return "fp64", 8.0 * nh * nip ** 3 * (1 / 6 + 1 / 2) / 1e12, "TFLOP", PEAK["fp64"]
     if stage == "w_solve":    # W' = (G V') G: one full product, one Hermitian (lower half)
-        return "fp64", 1.5 * 8.0 * nk * nip ** 3 / 1e12, "TFLOP", PEAK["fp64"]
+        return "fp64", 1.5 * 8.0 * nh * nip ** 3 / 1e12, "TFLOP", PEAK["fp64"]
     if stage == "metric_t":
         return "mfma", 8.0 * nk * nip * nip * norb / 2 / 1e12, "TFLOP", PEAK["fp64"]
     if stage == "frag_t":
