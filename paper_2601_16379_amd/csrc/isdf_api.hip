@@ -305,6 +305,10 @@ struct isdf_ctx_s {
   hipStream_t stream = nullptr;
   hipStream_t aux = nullptr;            // second stream: the factorisation overlaps the RHS
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_pinv = nullptr;
+  // third stream: the RHS k convolution of one r tile beside the pre-product
+  // of the next (two FP32 tiles in the tile buffer)
+  hipStream_t aux2 = nullptr;
+  hipEvent_t ev_rt[2] = {nullptr, nullptr}, ev_kc[2] = {nullptr, nullptr};
   int device = 0;
   // resident device data
   DevBuf phi, ip, xt, pi, eta, lt, w, work1, work2, work3, pinv_ws, perm, rank, rchunk, flag;
@@ -451,19 +455,30 @@ void do_fit(isdf_ctx c, int prec) {
   // complex FP32 (FP64 arithmetic, one rounding per stored value).
   c->eta32 = prec != ISDF_FP64 && gridfft_reg_grid(c->n[0], c->n[1], c->n[2]);
   float2* const t32 = c->eta32 ? c->rchunk.as<float2>() : nullptr;
-  for (long long r0 = 0; r0 < ng; r0 += c->rc) {
+  // complex FP32 tiles take half the buffer: two of them alternate, so the
+  // k convolution of tile i (third stream) runs beside the pre-product of
+  // tile i + 1; the FP64 tile fills the buffer and the two alternate with it
+  const int nbuf = c->eta32 ? 2 : 1;
+  HIPCHK(hipStreamWaitEvent(c->aux2, c->ev_fork, 0));
+  int it = 0;
+  for (long long r0 = 0; r0 < ng; r0 += c->rc, ++it) {
+    const int b = it % nbuf;
+    const long long toff = (long long)b * nk * nip * c->rc;       // elements of the tile's own type
+    if (it >= nbuf) HIPCHK(hipStreamWaitEvent(s, c->ev_kc[b], 0));   // tile b read by its convolution
     c->timer.begin("rhs_t", s);
     const int rcur = (int)std::min<long long>(c->rc, ng - r0);
-    HIPCHK(rhs_t_launch(c->xt.as<cplx>(), c->phi.as<cplx>(), c->rchunk.as<cplx>(), t32, nk, norb, nip, ng, r0,
-                        rcur, s));
+    HIPCHK(rhs_t_launch(c->xt.as<cplx>(), c->phi.as<cplx>(), c->rchunk.as<cplx>() + toff,
+                        t32 ? t32 + toff : nullptr, nk, norb, nip, ng, r0, rcur, s));
     c->timer.end("rhs_t", s);
-    c->timer.begin("rhs_kconv", s);
+    HIPCHK(hipEventRecord(c->ev_rt[b], s));
+    HIPCHK(hipStreamWaitEvent(c->aux2, c->ev_rt[b], 0));
+    c->timer.begin("rhs_kconv", c->aux2);
     KconvArgs a;
     memset(&a, 0, sizeof(a));
-    a.in = c->rchunk.as<cplx>();
+    a.in = c->rchunk.as<cplx>() + toff;
     a.out = c->eta.as<cplx>() + r0;
     if (c->eta32) {
-      a.in32 = t32;
+      a.in32 = t32 + toff;
       a.out32 = c->eta.as<float2>() + r0;
     }
     a.in_kstride = (long long)nip * rcur;
@@ -477,9 +492,12 @@ void do_fit(isdf_ctx c, int prec) {
     a.mode = 0;
     a.scale = 1.0 / nk;
     a.qslot = c->qmap.as<int>();         // eta^{-q} = conj eta^q: one q per class
-    HIPCHK(kconv_launch(a, s));
-    c->timer.end("rhs_kconv", s);
+    HIPCHK(kconv_launch(a, c->aux2));
+    c->timer.end("rhs_kconv", c->aux2);
+    HIPCHK(hipEventRecord(c->ev_kc[b], c->aux2));
   }
+  // eta complete: the main stream continues after the last convolution
+  HIPCHK(hipStreamWaitEvent(s, c->ev_kc[(it - 1) % nbuf], 0));
   c->timer.begin("chol", c->aux);
   {
     // blocked right-looking factorisation of all Pi^q at once: 64-wide
@@ -1246,6 +1264,11 @@ isdf_status isdf_create(isdf_ctx* out, const double* lattice, const int32_t grid
     HIPCHK(hipStreamSynchronize(c->stream));
     c->sync_ws.stream = c->stream;
     HIPCHK(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+    HIPCHK(hipStreamCreateWithFlags(&c->aux2, hipStreamNonBlocking));
+    for (int b = 0; b < 2; ++b) {
+      HIPCHK(hipEventCreateWithFlags(&c->ev_rt[b], hipEventDisableTiming));
+      HIPCHK(hipEventCreateWithFlags(&c->ev_kc[b], hipEventDisableTiming));
+    }
     HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&c->ev_pinv, hipEventDisableTiming));
@@ -1621,6 +1644,14 @@ isdf_status isdf_destroy(isdf_ctx ctx) {
   if (ctx->aux) {
     (void)hipStreamSynchronize(ctx->aux);
     (void)hipStreamDestroy(ctx->aux);
+  }
+  if (ctx->aux2) {
+    (void)hipStreamSynchronize(ctx->aux2);
+    (void)hipStreamDestroy(ctx->aux2);
+  }
+  for (int b = 0; b < 2; ++b) {
+    if (ctx->ev_rt[b]) (void)hipEventDestroy(ctx->ev_rt[b]);
+    if (ctx->ev_kc[b]) (void)hipEventDestroy(ctx->ev_kc[b]);
   }
   if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
   if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
