@@ -257,19 +257,27 @@ __global__ void eri_scatter_batch_kernel(const cplx* __restrict__ e, const long 
   const int nf = nfa[f];
   const cplx* ef = e + eoff[f];
   cplx* out = eri[f];
-  const int n = nf * nf;
-  const long long total = (long long)n * n;
-  const long long nf2 = (long long)nf * nf;
-  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
-       idx += (long long)gridDim.x * blockDim.x) {
-    // m = (pq) = p nf + q, c = (sr) = s nf + r
-    const int m = (int)(idx / n), c = (int)(idx - (idx / n) * n);
-    const int p_ = m / nf, q_ = m - p_ * nf, s_ = c / nf, r_ = c - s_ * nf;
-    // G over the classes {q, -q}: (pq|rs) = G[(pq)][(sr)] + conj(G[(qp)][(rs)])
-    const int m2 = q_ * nf + p_, c2 = r_ * nf + s_;
-    const cplx a = m >= c ? ef[idx] : cconj(ef[(long long)c * n + m]);
-    const cplx b = m2 >= c2 ? ef[(long long)m2 * n + c2] : cconj(ef[(long long)c2 * n + m2]);
-    out[(long long)m * nf2 + (long long)r_ * nf + s_] = cmk(a.x + b.x, a.y - b.y);
+  const long long n = (long long)nf * nf;
+  const long long total = n * n;
+  // G[a][b] from the computed lower triangle (G is Hermitian)
+  auto g = [&](long long a, long long b) { return a >= b ? ef[a * n + b] : cconj(ef[b * n + a]); };
+  // (pq|rs) = G[(pq)][(sr)] + conj(G[(qp)][(rs)]) = v; (qp|sr) = conj(v),
+  // (rs|pq) = v, (sr|qp) = conj(v): one thread per orbit {o1, o2, o3, o4}
+  // (the smallest of the four output indices) reads G twice and writes all
+  for (long long o = blockIdx.x * (long long)blockDim.x + threadIdx.x; o < total;
+       o += (long long)gridDim.x * blockDim.x) {
+    const long long pq = o / n, rs = o - pq * n;
+    const int p_ = (int)(pq / nf), q_ = (int)(pq - (long long)p_ * nf);
+    const int r_ = (int)(rs / nf), s_ = (int)(rs - (long long)r_ * nf);
+    const long long qp = (long long)q_ * nf + p_, sr = (long long)s_ * nf + r_;
+    const long long o2 = qp * n + sr, o3 = rs * n + pq, o4 = sr * n + qp;
+    if (o2 < o || o3 < o || o4 < o) continue;
+    const cplx a = g(pq, sr), b = g(qp, rs);
+    const cplx v = cmk(a.x + b.x, a.y - b.y), vc = cmk(v.x, -v.y);
+    out[o] = v;
+    out[o2] = vc;
+    out[o3] = v;
+    out[o4] = vc;
   }
 }
 
