@@ -70,6 +70,9 @@ typedef enum {
 /* flags for isdf_create */
 #define ISDF_INPUT_DEVICE 0x1u   /* orbitals / ip_index are device pointers      */
 #define ISDF_NO_PIVOT 0x2u       /* plain Cholesky: a singular Pi^q is an error  */
+/* at most n classes {q, -q} of eta per q batch (bits 16-31; 0 = as many as
+ * fit, see isdf_fit) */
+#define ISDF_Q_BATCH(n) ((((uint32_t)(n)) & 0xFFFFu) << 16)
 
 /* request states reported by isdf_poll */
 #define ISDF_REQ_QUEUED 0
@@ -109,6 +112,11 @@ isdf_status isdf_create(isdf_ctx* out, const double* lattice, const int32_t grid
  * convolution of T^k_I(r) = sum_mu X^k_{I mu} conj(phi^k_mu(r)), r-tiled; then
  * the FP64 Cholesky factor of every Pi^q with diagonal pivoting (relative
  * tolerance 1e-13; the rank is reported by isdf_stats).  Synchronous.
+ * Pi^{-q}, eta^{-q} and W^{-q} are the complex conjugates of those at q, so
+ * one q of each class {q, -q} is computed and stored.  eta of every class
+ * is formed here when it fits (60 % of the device memory left after
+ * isdf_create's buffers, capped by ISDF_Q_BATCH); otherwise
+ * isdf_coulomb_kernel forms it per q batch and isdf_get_rhs is unavailable.
  * `prec` is the precision of the kernel that will consume eta (eqs. (5)-(7)):
  * with ISDF_FP64 eta is kept in FP64; with a mixed precision, on the grids
  * whose mixed grid FFT reads it directly (cubic, 6..32 points a side: see
@@ -126,9 +134,12 @@ int32_t isdf_fit_eta_fp32(const int32_t grid[3]);
 
 /*
  * W^q for all q (eqs. (6)-(8)): grid FFT of eta^q(r) exp(-i q.r), scaled by
- * sqrt(Omega 4 pi/|G+q|^2)/N_g (FP64), V^q = eta~ eta~^H (GEMM in `prec`),
- * W^q = Pi^{q+} V^q Pi^{q+} by FP64 triangular solves with the factor of
- * isdf_fit.  Consumes eta (isdf_get_rhs is invalid afterwards).  Synchronous.
+ * sqrt(Omega 4 pi/|K|^2)/N_g (FP64; K the representative of G+q nearest
+ * zero per axis, the kernel averaged over the two at a tie +-n/2),
+ * V^q = eta~ eta~^H (GEMM in `prec`), W^q = Pi^{q+} V^q Pi^{q+} by FP64
+ * triangular solves with the factor of isdf_fit; one q per class {q, -q},
+ * in q batches (eta formed per batch) when isdf_fit did not form eta.
+ * Consumes eta (isdf_get_rhs is invalid afterwards).  Synchronous.
  * Error: ISDF_E_STATE before isdf_fit, or with prec = ISDF_FP64 after a
  * mixed-precision fit that stored eta in FP32.
  */
@@ -145,13 +156,14 @@ isdf_status isdf_get_ivs(isdf_ctx ctx, int32_t k, void* out);
  * those FP32 numbers, widened exactly. */
 isdf_status isdf_get_rhs(isdf_ctx ctx, int32_t q, void* out);
 /* Test hook: copy the Coulomb-weighted transform of eq. (7),
- *   eta~^q_I(G) = sqrt(Omega 4 pi / |G+q|^2) / N_g sum_r eta^q_I(r) exp(-i (G+q).r)
- * (0 at G+q = 0), as it enters V^q = eta~ eta~^H: FP64 after an FP64
+ *   eta~^q_I(G) = sqrt(Omega 4 pi / |K|^2) / N_g sum_r eta^q_I(r) exp(-i (G+q).r)
+ * (K as in isdf_coulomb_kernel; 0 at K = 0), as it enters V^q = eta~ eta~^H: FP64 after an FP64
  * isdf_coulomb_kernel, else the FP32 or bf16 hi+lo operand of the mixed
  * product, converted exactly to c128.  out: host c128 [n_ip][N_g], G in the
  * FFT order of the grid (index i_d stands for G_d = i_d wrapped to
  * [-n_d/2, n_d/2)).  Valid after isdf_coulomb_kernel until the next isdf_fit.
- * Error: ISDF_E_STATE before isdf_coulomb_kernel, ISDF_E_INVALID for a bad q. */
+ * Error: ISDF_E_STATE before isdf_coulomb_kernel or after one that ran in q
+ * batches, ISDF_E_INVALID for a bad q. */
 isdf_status isdf_get_eta_tilde(isdf_ctx ctx, int32_t q, void* out);
 
 /*
@@ -218,8 +230,9 @@ isdf_status isdf_stage_total(isdf_ctx ctx, const char* name, double* ms, int64_t
 isdf_status isdf_stage_reset(isdf_ctx ctx);
 
 /* Memory planner: device bytes that isdf_create/fit/coulomb_kernel would hold
- * for these sizes (no allocation), and the storage model of the paper's
- * section on diamond, N_k N_IP^2 + N_k N_IP N_AO complex128 elements. */
+ * for these sizes with eta of every class resident (no allocation; q
+ * batches need less), and the storage model of the paper's section on
+ * diamond, N_k N_IP^2 + N_k N_IP N_AO complex128 elements. */
 int64_t isdf_plan_bytes(const int32_t grid[3], const int32_t kmesh[3], int32_t n_orb,
                         int32_t n_ip);
 int64_t isdf_storage_model_bytes(int64_t n_k, int64_t n_ip, int64_t n_ao);

@@ -317,6 +317,8 @@ struct isdf_ctx_s {
   DevBuf fac;                           // per-q Coulomb factors of the mixed grid FFT (FP32, N_q x N_g)
   long long ld_ip = 0, ld_g = 0;        // row pitches of split operands (multiples of 16)
   bool fitted = false, kernel_ready = false, eta_valid = false;
+  bool kernel_pending = false;          // a fit whose eta (resident or per batch) the kernel has not consumed
+  bool etat_valid = false;              // eta~ of every class still held after the kernel (no q batches)
   bool eta32 = false;               // eta (and the RHS tile) held as complex FP32
   int kernel_prec = 0;              // precision of the last isdf_coulomb_kernel
   std::vector<int> rank_h;
@@ -327,6 +329,11 @@ struct isdf_ctx_s {
   int nh = 0;
   std::vector<int> qslot_h, hq_h, hself_h;
   DevBuf qmap;
+  // q batches: eta (and the split eta~, the factor table) hold qb classes at
+  // a time; with qb < nh the RHS is formed per batch inside
+  // isdf_coulomb_kernel instead of in isdf_fit (eta_batched)
+  int qb = 0;
+  bool eta_batched = false;
   long long rc = 0;   // r-chunk of the RHS
   Arena arena;
   Arena arena_aux;                      // descriptors of the second stream (chol, pinv)
@@ -403,6 +410,62 @@ long long nip2(const isdf_ctx c) { return (long long)c->nip * c->nip; }
 // --------------------------------------------------------------------------
 // fit
 // --------------------------------------------------------------------------
+// eta^q_I(r) of the classes that qslot (device map q -> eta slot, or -1)
+// selects, r-tiled: T^k_I(r) = sum_mu X^k_{I mu} conj(phi^k_mu(r)), then the
+// k convolution of eq. (5) (Algorithm 1 with Y = phi); T and eta as complex
+// FP32 when c->eta32 (FP32 matrix cores for T, FP64 convolution).  The main
+// stream continues after the last convolution; the third stream starts
+// after `start` (recorded on the main stream).
+void rhs_eta(isdf_ctx c, const int* qslot, hipEvent_t start) {
+  hipStream_t s = c->stream;
+  const int nk = c->nk, norb = c->norb, nip = c->nip;
+  const long long ng = c->ng;
+  float2* const t32 = c->eta32 ? c->rchunk.as<float2>() : nullptr;
+  // complex FP32 tiles take half the buffer: two of them alternate, so the
+  // k convolution of tile i (third stream) runs beside the pre-product of
+  // tile i + 1; the FP64 tile fills the buffer and the two alternate with it
+  const int nbuf = c->eta32 ? 2 : 1;
+  HIPCHK(hipStreamWaitEvent(c->aux2, start, 0));
+  int it = 0;
+  for (long long r0 = 0; r0 < ng; r0 += c->rc, ++it) {
+    const int b = it % nbuf;
+    const long long toff = (long long)b * nk * nip * c->rc;       // elements of the tile's own type
+    if (it >= nbuf) HIPCHK(hipStreamWaitEvent(s, c->ev_kc[b], 0));   // tile b read by its convolution
+    c->timer.begin("rhs_t", s);
+    const int rcur = (int)std::min<long long>(c->rc, ng - r0);
+    HIPCHK(rhs_t_launch(c->xt.as<cplx>(), c->phi.as<cplx>(), c->rchunk.as<cplx>() + toff,
+                        t32 ? t32 + toff : nullptr, nk, norb, nip, ng, r0, rcur, s));
+    c->timer.end("rhs_t", s);
+    HIPCHK(hipEventRecord(c->ev_rt[b], s));
+    HIPCHK(hipStreamWaitEvent(c->aux2, c->ev_rt[b], 0));
+    c->timer.begin("rhs_kconv", c->aux2);
+    KconvArgs a;
+    memset(&a, 0, sizeof(a));
+    a.in = c->rchunk.as<cplx>() + toff;
+    a.out = c->eta.as<cplx>() + r0;
+    if (c->eta32) {
+      a.in32 = t32 + toff;
+      a.out32 = c->eta.as<float2>() + r0;
+    }
+    a.in_kstride = (long long)nip * rcur;
+    a.out_qstride = (long long)nip * ng;
+    a.n_elem = (long long)nip * rcur;
+    a.in_inner = a.n_elem;
+    a.in_outer = 0;
+    a.out_inner = rcur;
+    a.out_outer = ng;
+    a.m1 = c->m[0]; a.m2 = c->m[1]; a.m3 = c->m[2];
+    a.mode = 0;
+    a.scale = 1.0 / nk;
+    a.qslot = qslot;                     // eta^{-q} = conj eta^q: one q per class
+    HIPCHK(kconv_launch(a, c->aux2));
+    c->timer.end("rhs_kconv", c->aux2);
+    HIPCHK(hipEventRecord(c->ev_kc[b], c->aux2));
+  }
+  // eta complete: the main stream continues after the last convolution
+  HIPCHK(hipStreamWaitEvent(s, c->ev_kc[(it - 1) % nbuf], 0));
+}
+
 void do_fit(isdf_ctx c, int prec) {
   hipStream_t s = c->stream;
   const int nk = c->nk, norb = c->norb, nip = c->nip;
@@ -449,55 +512,12 @@ void do_fit(isdf_ctx c, int prec) {
   // stream, overlapping the RHS below (it needs only Pi)
   HIPCHK(hipEventRecord(c->ev_fork, s));
   HIPCHK(hipStreamWaitEvent(c->aux, c->ev_fork, 0));
-  // eta^q_I(r), r-tiled: T^k_I(r) = sum_mu X^k_{I mu} conj(phi^k_mu(r)), then the
-  // same k convolution (eq. (5), Algorithm 1 with Y = phi).  For a mixed
-  // precision kernel whose grid FFT reads FP32, T and eta are stored as
-  // complex FP32 (FP64 arithmetic, one rounding per stored value).
+  // eta^q_I(r) for every class now when they all fit (else per q batch in
+  // isdf_coulomb_kernel).  For a mixed precision kernel whose grid FFT reads
+  // FP32, T and eta are stored as complex FP32.
   c->eta32 = prec != ISDF_FP64 && gridfft_reg_grid(c->n[0], c->n[1], c->n[2]);
-  float2* const t32 = c->eta32 ? c->rchunk.as<float2>() : nullptr;
-  // complex FP32 tiles take half the buffer: two of them alternate, so the
-  // k convolution of tile i (third stream) runs beside the pre-product of
-  // tile i + 1; the FP64 tile fills the buffer and the two alternate with it
-  const int nbuf = c->eta32 ? 2 : 1;
-  HIPCHK(hipStreamWaitEvent(c->aux2, c->ev_fork, 0));
-  int it = 0;
-  for (long long r0 = 0; r0 < ng; r0 += c->rc, ++it) {
-    const int b = it % nbuf;
-    const long long toff = (long long)b * nk * nip * c->rc;       // elements of the tile's own type
-    if (it >= nbuf) HIPCHK(hipStreamWaitEvent(s, c->ev_kc[b], 0));   // tile b read by its convolution
-    c->timer.begin("rhs_t", s);
-    const int rcur = (int)std::min<long long>(c->rc, ng - r0);
-    HIPCHK(rhs_t_launch(c->xt.as<cplx>(), c->phi.as<cplx>(), c->rchunk.as<cplx>() + toff,
-                        t32 ? t32 + toff : nullptr, nk, norb, nip, ng, r0, rcur, s));
-    c->timer.end("rhs_t", s);
-    HIPCHK(hipEventRecord(c->ev_rt[b], s));
-    HIPCHK(hipStreamWaitEvent(c->aux2, c->ev_rt[b], 0));
-    c->timer.begin("rhs_kconv", c->aux2);
-    KconvArgs a;
-    memset(&a, 0, sizeof(a));
-    a.in = c->rchunk.as<cplx>() + toff;
-    a.out = c->eta.as<cplx>() + r0;
-    if (c->eta32) {
-      a.in32 = t32 + toff;
-      a.out32 = c->eta.as<float2>() + r0;
-    }
-    a.in_kstride = (long long)nip * rcur;
-    a.out_qstride = (long long)nip * ng;
-    a.n_elem = (long long)nip * rcur;
-    a.in_inner = a.n_elem;
-    a.in_outer = 0;
-    a.out_inner = rcur;
-    a.out_outer = ng;
-    a.m1 = c->m[0]; a.m2 = c->m[1]; a.m3 = c->m[2];
-    a.mode = 0;
-    a.scale = 1.0 / nk;
-    a.qslot = c->qmap.as<int>();         // eta^{-q} = conj eta^q: one q per class
-    HIPCHK(kconv_launch(a, c->aux2));
-    c->timer.end("rhs_kconv", c->aux2);
-    HIPCHK(hipEventRecord(c->ev_kc[b], c->aux2));
-  }
-  // eta complete: the main stream continues after the last convolution
-  HIPCHK(hipStreamWaitEvent(s, c->ev_kc[(it - 1) % nbuf], 0));
+  c->eta_batched = c->qb < nh;
+  if (!c->eta_batched) rhs_eta(c, c->qmap.as<int>(), c->ev_fork);
   c->timer.begin("chol", c->aux);
   {
     // blocked right-looking factorisation of all Pi^q at once: 64-wide
@@ -608,7 +628,8 @@ void do_fit(isdf_ctx c, int prec) {
   c->timer.end("pinv", c->aux);
   HIPCHK(hipEventRecord(c->ev_pinv, c->aux));
   c->fitted = true;
-  c->eta_valid = true;
+  c->eta_valid = !c->eta_batched;
+  c->kernel_pending = true;
   c->kernel_ready = false;
 }
 
@@ -616,7 +637,7 @@ void do_fit(isdf_ctx c, int prec) {
 // Coulomb kernel
 // --------------------------------------------------------------------------
 void do_kernel(isdf_ctx c, int prec) {
-  if (!c->fitted || !c->eta_valid) throw Fail{ISDF_E_STATE, "isdf_fit must run before isdf_coulomb_kernel"};
+  if (!c->fitted || !c->kernel_pending) throw Fail{ISDF_E_STATE, "isdf_fit must run before isdf_coulomb_kernel"};
   if (c->eta32 && prec == ISDF_FP64)
     throw Fail{ISDF_E_STATE, "eta was stored in FP32 by a mixed-precision fit; fit with ISDF_FP64 first"};
   hipStream_t s = c->stream;
@@ -624,71 +645,89 @@ void do_kernel(isdf_ctx c, int prec) {
   const int nh = c->nh;                 // one q per class {q, -q}: W^{-q} = conj W^q
   const long long ng = c->ng;
   c->arena.reset();
-  // eta~^q_I(G) = sqrt(Omega 4pi/|G+q|^2)/N_g FFT[eta^q_I(r) exp(-iq.r)]   (eqs. (6)-(7));
-  // in place (FP64) or into the split operand format of the V GEMM (mixed)
-  const long long split_plane = (long long)nh * nip * c->ld_g;
+  // q batches of qb classes (one batch, eta formed by the fit, when they all
+  // fit); per batch: eta (when batched), the grid FFT, V^q
+  const int qb = c->eta_batched ? c->qb : nh;
+  const long long split_plane = (long long)qb * nip * c->ld_g;
   if (prec != ISDF_FP64) c->eta_split.ensure((size_t)split_plane * 8);
-  c->timer.begin("grid_fft", s);
-  {
-    GridFftArgs a;
-    memset(&a, 0, sizeof(a));
-    a.data = c->eta.as<cplx>();
-    a.data32 = c->eta32 ? c->eta.as<float2>() : nullptr;
-    // per-q Coulomb factors of the one-pass (register) FFT
-    if (prec != ISDF_FP64 && gridfft_reg_grid(c->n[0], c->n[1], c->n[2])) {
-      c->fac.ensure((size_t)nh * ng * sizeof(float));
-      a.fac = c->fac.as<float>();
+  const bool reg = prec != ISDF_FP64 && gridfft_reg_grid(c->n[0], c->n[1], c->n[2]);
+  if (reg) c->fac.ensure((size_t)qb * ng * sizeof(float));
+  std::vector<int> bslot(nk);
+  for (int h0 = 0; h0 < nh; h0 += qb) {
+    const int nb = std::min(qb, nh - h0);
+    if (c->eta_batched) {
+      // eta of classes h0 .. h0 + nb - 1 into slots 0 .. nb - 1 (eq. (5))
+      for (int q = 0; q < nk; ++q) {
+        const int h = c->qslot_h[q];
+        bslot[q] = (h >= h0 && h < h0 + nb) ? h - h0 : -1;
+      }
+      const int* bs = c->arena.put(bslot.data(), bslot.size(), s);
+      HIPCHK(hipEventRecord(c->ev_fork, s));   // the previous batch's FFT has read eta
+      rhs_eta(c, bs, c->ev_fork);
     }
-    a.fmt = prec;
-    a.split = c->eta_split.p;
-    a.split_ld = c->ld_g;
-    a.split_plane = split_plane;
-    a.split_q = (long long)nip * c->ld_g;
-    a.n1 = c->n[0]; a.n2 = c->n[1]; a.n3 = c->n[2];
-    a.m1 = c->m[0]; a.m2 = c->m[1]; a.m3 = c->m[2];
-    a.q0 = 0;
-    a.nq = nh;
-    a.qlist = c->qmap.as<int>() + nk;
-    a.n_ip = nip;
-    a.q_stride = (long long)nip * ng;
-    memcpy(a.recip, c->recip, sizeof(a.recip));
-    a.volume = c->volume;
-    HIPCHK(gridfft_launch(a, s));
+    // eta~^q_I(G) = sqrt(Omega 4pi/|K|^2)/N_g FFT[eta^q_I(r) exp(-iq.r)]   (eqs. (6)-(7));
+    // in place (FP64) or into the split operand format of the V GEMM (mixed)
+    c->timer.begin("grid_fft", s);
+    {
+      GridFftArgs a;
+      memset(&a, 0, sizeof(a));
+      a.data = c->eta.as<cplx>();
+      a.data32 = c->eta32 ? c->eta.as<float2>() : nullptr;
+      if (reg) a.fac = c->fac.as<float>();   // per-q Coulomb factors of the one-pass FFT
+      a.fmt = prec;
+      a.split = c->eta_split.p;
+      a.split_ld = c->ld_g;
+      a.split_plane = split_plane;
+      a.split_q = (long long)nip * c->ld_g;
+      a.n1 = c->n[0]; a.n2 = c->n[1]; a.n3 = c->n[2];
+      a.m1 = c->m[0]; a.m2 = c->m[1]; a.m3 = c->m[2];
+      a.q0 = 0;
+      a.nq = nb;
+      a.qlist = c->qmap.as<int>() + nk + h0;
+      a.n_ip = nip;
+      a.q_stride = (long long)nip * ng;
+      memcpy(a.recip, c->recip, sizeof(a.recip));
+      a.volume = c->volume;
+      HIPCHK(gridfft_launch(a, s));
+    }
+    c->timer.end("grid_fft", s);
+    // V^q = eta~ eta~^H  (Hermitian; lower tiles computed and mirrored); in the
+    // mixed precisions FP32 partial sums over 8192 grid points, FP64 across them
+    c->timer.begin("v_gemm", s);
+    {
+      cplx* vout = c->work1.as<cplx>() + (long long)h0 * nip2(c);
+      std::vector<NtDesc> d(1);
+      if (prec == ISDF_FP64) {
+        d[0] = mknt(c->eta.p, ng, c->eta.p, ng, vout, nip, nip, nip, (int)ng);
+        d[0].sA_bat = d[0].sB_bat = (long long)nip * ng;
+        d[0].batch = nb;
+        d[0].sC_bat = nip2(c);
+        d[0].herm = 1;
+        run_nt(c->arena, prec, 2, d, s, 1);
+      } else {
+        // one large-tile launch per block of 8192 grid points: FP32 inside a
+        // block, FP64 accumulation into V across blocks; lower tiles, then mirror
+        d[0] = mknt(c->eta_split.p, c->ld_g, c->eta_split.p, c->ld_g, vout, nip, nip, nip, (int)ng);
+        d[0].a_plane = d[0].b_plane = split_plane;
+        const int kseg = 8192;
+        d[0].Kseg = (int)std::min<long long>(kseg, ng);
+        d[0].nseg = (int)((ng + d[0].Kseg - 1) / d[0].Kseg);
+        d[0].Klast = (int)(ng - (long long)(d[0].nseg - 1) * d[0].Kseg);
+        d[0].sA_seg = d[0].sB_seg = d[0].Kseg;
+        d[0].sA_bat = d[0].sB_bat = (long long)nip * c->ld_g;
+        d[0].batch = nb;
+        d[0].sC_bat = nip2(c);
+        d[0].herm = 2;
+        d[0].epi = 1;
+        run_big(c->arena, prec, 2, d, d[0].nseg, s, 1);
+        HIPCHK(herm_fill_launch(vout, nip, nip, nip2(c), nb, s));
+      }
+    }
+    c->timer.end("v_gemm", s);
   }
-  c->timer.end("grid_fft", s);
   c->eta_valid = false;
-  // V^q = eta~ eta~^H  (Hermitian; lower tiles computed and mirrored); in the
-  // mixed precisions FP32 partial sums over 8192 grid points, FP64 across them
-  c->timer.begin("v_gemm", s);
-  {
-    std::vector<NtDesc> d(1);
-    if (prec == ISDF_FP64) {
-      d[0] = mknt(c->eta.p, ng, c->eta.p, ng, c->work1.p, nip, nip, nip, (int)ng);
-      d[0].sA_bat = d[0].sB_bat = (long long)nip * ng;
-      d[0].batch = nh;
-      d[0].sC_bat = nip2(c);
-      d[0].herm = 1;
-      run_nt(c->arena, prec, 2, d, s, 1);
-    } else {
-      // one large-tile launch per block of 8192 grid points: FP32 inside a
-      // block, FP64 accumulation into V across blocks; lower tiles, then mirror
-      d[0] = mknt(c->eta_split.p, c->ld_g, c->eta_split.p, c->ld_g, c->work1.p, nip, nip, nip, (int)ng);
-      d[0].a_plane = d[0].b_plane = split_plane;
-      const int kseg = 8192;
-      d[0].Kseg = (int)std::min<long long>(kseg, ng);
-      d[0].nseg = (int)((ng + d[0].Kseg - 1) / d[0].Kseg);
-      d[0].Klast = (int)(ng - (long long)(d[0].nseg - 1) * d[0].Kseg);
-      d[0].sA_seg = d[0].sB_seg = d[0].Kseg;
-      d[0].sA_bat = d[0].sB_bat = (long long)nip * c->ld_g;
-      d[0].batch = nh;
-      d[0].sC_bat = nip2(c);
-      d[0].herm = 2;
-      d[0].epi = 1;
-      run_big(c->arena, prec, 2, d, d[0].nseg, s, 1);
-      HIPCHK(herm_fill_launch(c->work1.as<cplx>(), nip, nip, nip2(c), nh, s));
-    }
-  }
-  c->timer.end("v_gemm", s);
+  c->kernel_pending = false;
+  c->etat_valid = !c->eta_batched;
   // W^q = Pi^{q+} V^q Pi^{q+}   (eq. (8)) in FP64 through the pivoted factor
   // P^T Pi P = L L^H of rank r:  G = L^{-H} L^{-1} (formed by isdf_fit),
   // W' = G (P^T V P) G, W = P W' P^T (zero outside the rank block); the two
@@ -1131,18 +1170,24 @@ int64_t isdf_plan_bytes(const int32_t grid[3], const int32_t kmesh[3], int32_t n
   if (!grid || !kmesh) return -1;
   const long long ng = (long long)grid[0] * grid[1] * grid[2];
   const long long nk = (long long)kmesh[0] * kmesh[1] * kmesh[2];
+  // classes {q, -q}: (N_k + number of q = -q) / 2, q = -q where every axis is 0 or m/2
+  long long nself = 1;
+  for (int d = 0; d < 3; ++d) nself *= (kmesh[d] % 2 == 0) ? 2 : 1;
+  const long long nh = (nk + nself) / 2;
   const long long e = sizeof(cplx);
+  const long long ld = (n_ip + 15) / 16 * 16, ldg = (ng + 15) / 16 * 16;
   long long b = 0;
   b += nk * n_orb * ng * e;              // orbitals
   b += nk * n_orb * n_ip * e;            // X
-  b += 6 * nk * (long long)n_ip * n_ip * e;  // Pi, L, W, three work buffers
-  b += nk * ((long long)n_ip * 64 + 4096) * e;  // L^{-1} scratch
-  const long long ld = (n_ip + 15) / 16 * 16;
-  b += nk * (long long)n_ip * ld * (16 + 8 + 8);  // W^T in the three operand formats
-  b += nk * (long long)n_ip * ng * e;    // eta
+  b += nk * (long long)n_ip * n_ip * e;  // T^k of the metric, then V
+  b += 5 * nh * (long long)n_ip * n_ip * e;  // Pi, L, W, two work buffers (per class)
+  b += nh * ((long long)n_ip * 64 + 4096) * e;  // L^{-1} scratch
+  b += nh * (long long)n_ip * ld * (16 + 8 + 8);  // W^T in the three operand formats
+  b += nh * (long long)n_ip * ng * e;    // eta of every class (FP64 size; q batches need less)
+  b += nh * (long long)n_ip * ldg * 8;   // split eta~ (mixed precisions)
   b += nk * (long long)n_ip * rchunk_len(ng, (int)nk, n_ip) * e;  // RHS tile
-  b += n_ip * 4 + 2 * nk * (long long)n_ip * 4;
-  b += nk * ng * 4;                      // Coulomb factors of the mixed grid FFT
+  b += n_ip * 4 + 2 * nh * (long long)n_ip * 4;
+  b += nh * ng * 4;                      // Coulomb factors of the mixed grid FFT
   return b;
 }
 
@@ -1228,28 +1273,43 @@ isdf_status isdf_create(isdf_ctx* out, const double* lattice, const int32_t grid
     c->ip.alloc(sizeof(int) * n_ip);
     // + RHS_X_PAD elements: rhs_t_launch reads whole blocks of points
     c->xt.alloc(((size_t)nk * n_orb * n_ip + RHS_X_PAD) * e);
-    const size_t m2 = (size_t)nk * n_ip * n_ip * e;
+    const int nh = c->nh;
+    const size_t m2 = (size_t)nh * n_ip * n_ip * e;   // one matrix per class {q, -q}
     c->pi.alloc(m2);
     c->lt.alloc(m2);
     c->w.alloc(m2);
-    c->work1.alloc(m2);
-    c->pinv_ws.alloc((size_t)nk * ((size_t)n_ip * 64 + 4096) * e);   // blocked L^{-1} scratch
-    c->work2.alloc(m2);
-    c->work3.alloc(m2);
-    c->eta.alloc((size_t)nk * n_ip * ng * e);
+    c->work1.alloc((size_t)nk * n_ip * n_ip * e);      // T^k of the metric, then V per class
+    c->pinv_ws.alloc((size_t)nh * ((size_t)n_ip * 64 + 4096) * e);   // blocked L^{-1} scratch
     // row pitches of the split operands: multiples of 16 elements, so that in
     // the bf16 hi/lo format every 16-k step of a row is one aligned 128-byte line
     c->ld_ip = (n_ip + 15) / 16 * 16;
     c->ld_g = (ng + 15) / 16 * 16;
-    c->wt64.alloc((size_t)nk * n_ip * c->ld_ip * e);
-    c->wt32.alloc((size_t)nk * n_ip * c->ld_ip * 8);
-    c->wt16.alloc((size_t)nk * n_ip * c->ld_ip * 8);
+    c->work2.alloc(m2);
+    c->work3.alloc(m2);
+    c->wt64.alloc((size_t)nh * n_ip * c->ld_ip * e);
+    c->wt32.alloc((size_t)nh * n_ip * c->ld_ip * 8);
+    c->wt16.alloc((size_t)nh * n_ip * c->ld_ip * 8);
     c->rchunk.alloc((size_t)nk * n_ip * c->rc * e);
-    c->perm.alloc(sizeof(int) * nk * n_ip);
-    c->rank.alloc(sizeof(int) * nk);
+    c->perm.alloc(sizeof(int) * nh * n_ip);
+    c->rank.alloc(sizeof(int) * nh);
     c->flag.alloc(sizeof(int));
-    c->dmax.alloc(sizeof(double) * nk);
-    c->cflag.alloc(sizeof(int) * nk);
+    c->dmax.alloc(sizeof(double) * nh);
+    c->cflag.alloc(sizeof(int) * nh);
+    // classes per q batch of eta (FP64 size), the split eta~ and the factor
+    // table: all of them when that fits in 60 % of the memory left, else the
+    // largest batch that does (ISDF_Q_BATCH(n) caps it); the rest of the
+    // memory is for fragment workspaces
+    {
+      const size_t per_class = (size_t)n_ip * ng * e + (size_t)n_ip * c->ld_g * 8 + (size_t)ng * 4;
+      size_t fr = 0, tot = 0;
+      HIPCHK(hipMemGetInfo(&fr, &tot));
+      long long qb = (long long)(0.6 * (double)fr / (double)per_class);
+      const int cap = (int)((flags >> 16) & 0xFFFFu);
+      if (cap > 0) qb = std::min<long long>(qb, cap);
+      if (qb < 1) throw Fail{ISDF_E_NOMEM, "no room for the eta of one q class"};
+      c->qb = (int)std::min<long long>(qb, nh);
+    }
+    c->eta.alloc((size_t)c->qb * n_ip * ng * e);
     c->qmap.alloc(sizeof(int) * (nk + 2 * c->nh));
     {
       std::vector<int> qm(c->qslot_h);
@@ -1367,7 +1427,9 @@ isdf_status isdf_get_ivs(isdf_ctx ctx, int32_t k, void* out) {
 
 isdf_status isdf_get_rhs(isdf_ctx ctx, int32_t q, void* out) {
   if (!ctx) return ISDF_E_INVALID;
-  if (!ctx->eta_valid) return fail(ctx, ISDF_E_STATE, "eta not available (fit first; consumed by the kernel)");
+  if (!ctx->eta_valid)
+    return fail(ctx, ISDF_E_STATE,
+                "eta not available (fit first; consumed by the kernel; formed inside the kernel when q-batched)");
   if (q < 0 || q >= ctx->nk || !out) return fail(ctx, ISDF_E_INVALID, "bad q");
   const size_t n = (size_t)ctx->nip * ctx->ng;
   bool cj;                                                   // eta^{-q} = conj eta^q
@@ -1393,6 +1455,7 @@ isdf_status isdf_get_rhs(isdf_ctx ctx, int32_t q, void* out) {
 isdf_status isdf_get_eta_tilde(isdf_ctx ctx, int32_t q, void* out) {
   if (!ctx) return ISDF_E_INVALID;
   if (!ctx->kernel_ready) return fail(ctx, ISDF_E_STATE, "eta~ not computed (isdf_coulomb_kernel first)");
+  if (!ctx->etat_valid) return fail(ctx, ISDF_E_STATE, "eta~ is not kept when the kernel runs in q batches");
   if (q < 0 || q >= ctx->nk || !out) return fail(ctx, ISDF_E_INVALID, "bad q");
   const long long nip = ctx->nip, ng = ctx->ng, ldg = ctx->ld_g;
   // a q of no stored class: eta~^q(G) = conj(eta~^{-q}(G')) with G' the

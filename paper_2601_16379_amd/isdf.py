@@ -146,7 +146,7 @@ class Isdf:
     """One library context: ``isdf_create`` at construction, the other calls
     as methods with the C names (``fit``, ``coulomb_kernel``, ...)."""
 
-    def __init__(self, lattice, grid, kmesh, orbitals, ip_index, no_pivot=False, stream=None):
+    def __init__(self, lattice, grid, kmesh, orbitals, ip_index, no_pivot=False, stream=None, q_batch=0):
         self.lib = load_library()
         lat = np.ascontiguousarray(np.asarray(lattice, dtype=np.float64))
         self.grid = np.ascontiguousarray(np.asarray(grid, dtype=np.int32))
@@ -164,7 +164,8 @@ class Isdf:
             raise ValueError("orbitals must be [N_k, n_orb, N_g]")
         self.n_orb = int(shape[1])
         self.n_ip = int(ip_index.shape[0])
-        flags = (ISDF_INPUT_DEVICE if odev else 0) | (ISDF_NO_PIVOT if no_pivot else 0)
+        flags = (ISDF_INPUT_DEVICE if odev else 0) | (ISDF_NO_PIVOT if no_pivot else 0) \
+            | ((int(q_batch) & 0xFFFF) << 16)
         self.stream = current_stream() if stream is None else stream
         h = ctypes.c_void_p()
         st = self.lib.isdf_create(ctypes.byref(h), lat.ctypes.data, self.grid.ctypes.data,

@@ -40,13 +40,16 @@ def test_storage_model_matches_paper_number():
 
 
 def test_plan_bytes_at_most_linear_in_nk():
-    # resident data is linear in N_k; the r-tile scratch is capped at 2 GiB
+    # resident data is at most linear in N_k (q-indexed data grows with the
+    # classes {q, -q}: 8 of the 2x2x2 mesh, 12 of the 4x2x2 mesh); the r-tile
+    # scratch is capped at 2 GiB
     b1 = pkg.isdf_plan_bytes((32, 32, 32), (2, 2, 2), 26, 520)
     b2 = pkg.isdf_plan_bytes((32, 32, 32), (4, 2, 2), 26, 520)
-    assert 1.5 < b2 / b1 <= 2.0
-    # workload 5 shapes: the orbitals alone are ~53 GB
+    assert 1.2 < b2 / b1 <= 2.0
+    # workload 5 shapes: the orbitals alone are ~53 GB, and eta of all 504
+    # classes (FP64, 537 GB) exceeds one GPU, hence the q batches
     b5 = pkg.isdf_plan_bytes((40, 40, 40), (10, 10, 10), 52, 1040)
-    assert b5 > 53e9
+    assert b5 > 53e9 + 504 * 1040 * 64000 * 16
 
 
 def test_fp32_eta_only_on_register_fft_grids():

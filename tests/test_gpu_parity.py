@@ -311,3 +311,35 @@ def test_fp64_fit_then_mixed_kernel_within_1e6():
     for f, cf in enumerate(frags):
         ref = ko.fragment_eri(c.x, cf, c.w, cfg.kmesh)
         assert float(np.max(np.abs(out[f] - ref))) < 1e-6
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+@pytest.mark.parametrize("name,qb", [("t_mid_k4", 5), ("t_small_k3", 4)])
+def test_q_batches_equal_resident_bitwise(name, qb, prec):
+    """With eta formed per batch of qb classes inside the kernel (ISDF_Q_BATCH)
+    every element goes through the same instructions as with eta resident:
+    W^q for every q and the ERIs are bitwise equal; eta is then unavailable
+    after the fit and eta~ after the kernel."""
+    import paper_2601_16379_amd as pkg
+    c = case(name)
+    cfg = c.d.cfg
+    frags = inp.make_fragments(cfg)
+    res = []
+    for q_batch in (0, qb):
+        ctx = _ctx(c.d, q_batch=q_batch)
+        ctx.fit(prec)
+        if q_batch:
+            with pytest.raises(pkg.IsdfError) as e:
+                ctx.get_rhs(0)
+            assert e.value.status == -3
+        ctx.coulomb_kernel(prec)
+        if q_batch:
+            with pytest.raises(pkg.IsdfError) as e:
+                ctx.get_eta_tilde(0)
+            assert e.value.status == -3
+        w = np.stack([ctx.get_kernel(q) for q in range(cfg.n_k)])
+        res.append((w, ctx.fragment_eri(frags, prec)))
+        ctx.close()
+    assert np.array_equal(res[0][0], res[1][0])
+    for a, b in zip(res[0][1], res[1][1]):
+        assert np.array_equal(a, b)
