@@ -162,7 +162,7 @@ def cpu_baseline(d, frags, w_gpu, budget_s):
     x = ko.ip_values(d.orbitals, d.ip_index)
     pi = ko.metric_k(x, cfg.kmesh)
     t_metric = time.perf_counter() - t0
-    nr = min(512, cfg.n_g)
+    nr = min(2048, cfg.n_g)
     ridx = np.sort(rng.choice(cfg.n_g, nr, replace=False))
     t0 = time.perf_counter()
     ko.rhs(x, d.orbitals, cfg.kmesh, [0], ridx)
@@ -177,10 +177,10 @@ def cpu_baseline(d, frags, w_gpu, budget_s):
     t0 = time.perf_counter()
     ko.kernel_v_route(pi, eta_q[None], d.lattice, cfg.grid, cfg.kmesh, qs=[1])
     t_w = (time.perf_counter() - t0) * cfg.n_k
-    # fragments: two sizes, cost model t = a n_f^2 + b n_f^4
+    # fragments: three sizes, cost model t = a n_f^2 + b n_f^4
     nfs = [f.shape[2] for f in frags]
     order = np.argsort(nfs)
-    pick = [int(order[0]), int(order[len(order) // 2])]
+    pick = [int(order[0]), int(order[len(order) // 2]), int(order[(3 * len(order)) // 4])]
     ts = []
     for f in pick:
         t0 = time.perf_counter()
@@ -188,8 +188,9 @@ def cpu_baseline(d, frags, w_gpu, budget_s):
         ts.append(time.perf_counter() - t0)
         if sum(ts) > budget_s:
             break
-    if len(ts) == 2 and nfs[pick[0]] != nfs[pick[1]]:
-        a_ = np.array([[nfs[p] ** 2, nfs[p] ** 4] for p in pick], dtype=float)
+    done = pick[:len(ts)]
+    if len(ts) >= 2 and len(set(nfs[p] for p in done)) >= 2:
+        a_ = np.array([[nfs[p] ** 2, nfs[p] ** 4] for p in done], dtype=float)
         coef = np.linalg.lstsq(a_, np.array(ts), rcond=None)[0]
         coef = np.maximum(coef, 0)
         t_frag = float(sum(coef[0] * n ** 2 + coef[1] * n ** 4 for n in nfs))
@@ -214,7 +215,7 @@ def cpu_baseline(d, frags, w_gpu, budget_s):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import numpy as np

@@ -110,6 +110,10 @@ CONFIGS = {
                           gmax=4.0, env=4.0, n_frag=1, frag_lo=6, frag_hi=6),
     "t_grid40_k1": Config("t_grid40_k1", 114, 6.0, (40, 40, 40), (1, 1, 1), 8, 36,
                           gmax=4.0, env=4.0, n_frag=1, frag_lo=4, frag_hi=4),
+    # first mesh axis of length 4 (four lanes per element in the register k
+    # convolution and pair transform) with axes of 2, odd n_orb, ragged tiles
+    "t_m4_k16": Config("t_m4_k16", 115, 5.0, (10, 10, 10), (4, 2, 2), 7, 90,
+                       gmax=2.0, env=3.0, n_frag=3, frag_lo=4, frag_hi=9),
 }
 
 

@@ -310,8 +310,8 @@ template <int CTRL>
 __device__ inline double dpp_d(double v) {
   const int2 u = __builtin_bit_cast(int2, v);
   int2 r;
-  r.x = __builtin_amdgcn_update_dpp(0, u.x, CTRL, 0xF, 0xF, false);
-  r.y = __builtin_amdgcn_update_dpp(0, u.y, CTRL, 0xF, 0xF, false);
+  r.x = __builtin_amdgcn_mov_dpp(u.x, CTRL, 0xF, 0xF, true);
+  r.y = __builtin_amdgcn_mov_dpp(u.y, CTRL, 0xF, 0xF, true);
   return __builtin_bit_cast(double, r);
 }
 constexpr int DPP_XOR1 = 0xB1;   // quad_perm [1, 0, 3, 2]
@@ -327,19 +327,6 @@ __device__ inline cplx bfly(cplx v, bool hi) {
   // selects, not branches: hi ? p - v : p + v
   const double sg = hi ? -1.0 : 1.0;
   return cmk(fma(sg, v.x, p.x), fma(sg, v.y, p.y));
-}
-
-// Last radix-2 step of a 4-point transform across a quad, from the lane's
-// value s and its partner's p: role 0 -> s + p, 1 -> p - s, 2 -> s + i p,
-// 3 -> p - i s.  Written as u + rho w with (u, w) = (s, p) or (p, s) and
-// rho in {1, -1, i, -i}, all by selects.
-__device__ inline cplx quad_out(cplx s, cplx p, int role) {
-  const bool odd = role & 1, rot = role & 2;
-  const cplx u = odd ? p : s, w = odd ? s : p;
-  // rho w: 1 -> w, -1 -> -w, i -> (-w.y, w.x), -i -> (w.y, -w.x)
-  const double wx = rot ? -w.y : w.x, wy = rot ? w.x : w.y;
-  const double sg = odd ? -1.0 : 1.0;
-  return cmk(fma(sg, wx, u.x), fma(sg, wy, u.y));
 }
 
 // F32: input from in32 and output to out32 (complex FP32, FP64 arithmetic)
@@ -371,28 +358,44 @@ __global__ __launch_bounds__(256) void kconv_reg_kernel(KconvArgs a) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) x[v] = bfly<DPP_XOR1>(x[v], k1 & 1);
   } else if constexpr (M1 == 4) {
+    // lanes 0..3 -> y0 = s0 + s1, y2 = s0 - s1, y1 = d0 + i d1, y3 = d0 - i d1;
+    // lane k1 forms z = s + rho p with rho = 1, -1, i, i (y = gamma z with
+    // gamma = 1, -1, 1, -i): only |y|^2 = |z|^2 is used, so gamma is dropped
+    // and the step is two FMAs a component, no selects
+    const double rr = k1 == 0 ? 1.0 : (k1 == 1 ? -1.0 : 0.0), ri = k1 >= 2 ? 1.0 : 0.0;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       const cplx s_ = bfly<DPP_XOR2>(x[v], k1 >= 2);     // x_j +- x_{j^2}
       const cplx p = dpp_c<DPP_XOR1>(s_);
-      // lanes 0..3 -> y0 = s0 + s1, y2 = s0 - s1, y1 = d0 + i d1, y3 = d0 - i d1
-      x[v] = quad_out(s_, p, k1);
+      const double zr = fma(rr, p.x, fma(-ri, p.y, s_.x));
+      const double zi = fma(rr, p.y, fma(ri, p.x, s_.y));
+      x[v] = cmk(zr * zr + zi * zi, 0.0);
     }
   }
   // |T^R|^2
+  if constexpr (M1 != 4) {
 #pragma unroll
-  for (int v = 0; v < NV; ++v) x[v] = cmk(x[v].x * x[v].x + x[v].y * x[v].y, 0.0);
+    for (int v = 0; v < NV; ++v) x[v] = cmk(x[v].x * x[v].x + x[v].y * x[v].y, 0.0);
+  }
   // R1 axis: input lanes hold R1 = bitrev(k1) for M1 = 4; output in natural order
   if constexpr (M1 == 2) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) x[v] = bfly<DPP_XOR1>(x[v], k1 & 1);
   } else if constexpr (M1 == 4) {
+    // real inputs: s = p1 +- x across lanes (l, l ^ 1), then with p the value
+    // of lane l ^ 2: y0 = s + p, y1 = p - s (real), y2 = s + i p, y3 = p - i s,
+    // as lane-constant coefficients of s and p
+    const int role = ((k1 & 1) << 1) | (k1 >> 1);
+    const double sg = (k1 & 1) ? -1.0 : 1.0;
+    const double ar = role == 0 || role == 2 ? 1.0 : (role == 1 ? -1.0 : 0.0);
+    const double br = role <= 1 || role == 3 ? 1.0 : 0.0;
+    const double ai = role == 3 ? -1.0 : 0.0, bi = role == 2 ? 1.0 : 0.0;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const cplx s_ = bfly<DPP_XOR1>(x[v], k1 & 1);      // a, b (lanes 0, 1), c, d (lanes 2, 3)
-      const cplx p = dpp_c<DPP_XOR2>(s_);
+      const double s_ = fma(sg, x[v].x, dpp_d<DPP_XOR1>(x[v].x));   // a, b (lanes 0, 1), c, d (lanes 2, 3)
+      const double p = dpp_d<DPP_XOR2>(s_);
       // y0 = a + c, y1 = b + i d, y2 = a - c, y3 = b - i d
-      x[v] = quad_out(s_, p, ((k1 & 1) << 1) | (k1 >> 1));
+      x[v] = cmk(fma(ar, s_, br * p), fma(ai, s_, bi * p));
     }
   }
   dft23_pos<M2, M3>(x);

@@ -211,7 +211,7 @@ def test_grid_fft_sizes_kernel_and_eri(name):
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 @pytest.mark.parametrize("name", ["t_small_k3", "t_mid_k4", "t_grid10_k1", "t_grid18_k2", "t_grid20_k3",
-                                  "t_grid36_k2"])
+                                  "t_grid36_k2", "t_m4_k16"])
 def test_mixed_kernel_and_eri_within_1e6(name, prec):
     """The mixed-precision Coulomb path (one-pass FP32 FFT on cubic grids up to
     32^3 -- here 10, 12, 16, 18, 20 -- the two-pass FFT above that -- 36 --,
@@ -258,7 +258,7 @@ def test_eta_tilde_elementwise(name, prec):
         assert excess <= 0.0, (q, excess)
 
 
-@pytest.mark.parametrize("name", SMALL + ["t_grid10_k1", "t_grid20_k3"])
+@pytest.mark.parametrize("name", SMALL + ["t_grid10_k1", "t_grid20_k3", "t_m4_k16"])
 def test_mixed_fit_eta_fp32_bound(name):
     """A mixed-precision fit computes T^k_I(r) = sum_mu X^k_{I mu} conj(phi^k_mu(r))
     on the FP32 matrix cores (inputs rounded to FP32, K = 2 n_orb real terms
@@ -314,7 +314,7 @@ def test_fp64_fit_then_mixed_kernel_within_1e6():
 
 
 @pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
-@pytest.mark.parametrize("name,qb", [("t_mid_k4", 5), ("t_small_k3", 4)])
+@pytest.mark.parametrize("name,qb", [("t_mid_k4", 5), ("t_small_k3", 4), ("t_m4_k16", 5)])
 def test_q_batches_equal_resident_bitwise(name, qb, prec):
     """With eta formed per batch of qb classes inside the kernel (ISDF_Q_BATCH)
     every element goes through the same instructions as with eta resident:
