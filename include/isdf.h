@@ -185,6 +185,28 @@ isdf_status isdf_fragment_eri(isdf_ctx ctx, isdf_precision prec, int32_t n_frag,
                               uint32_t flags);
 
 /*
+ * A fragment batch captured as a HIP graph (the batched persistent launch of
+ * Algorithm 2 replayed without host-side launch work, for callers that run the
+ * same batch shape repeatedly).  isdf_graph_create runs the batch once on a
+ * private stream and workspace (sizing every buffer, checking the result
+ * paths), then captures the same launches and instantiates them.  Only device
+ * pointers: C[f] and eri[f] as in isdf_fragment_eri with ISDF_FRAG_DEVICE.
+ * Every replay reads C[f], X^k and W^q as they are at that time and writes
+ * eri[f]: coefficients may be updated in place between replays, and a new
+ * isdf_coulomb_kernel is seen by the next replay.  isdf_graph_launch replays
+ * the graph after the work already queued on the context's stream and waits
+ * for it.  Error: ISDF_E_STATE when no Coulomb kernel is current (create and
+ * launch), ISDF_E_INVALID for bad arguments or host pointers.  The graph owns
+ * its workspace until isdf_graph_destroy, which must come before the
+ * context's isdf_destroy.
+ */
+typedef struct isdf_graph_s* isdf_graph;
+isdf_status isdf_graph_create(isdf_ctx ctx, isdf_precision prec, int32_t n_frag, const int32_t* n_f,
+                              const void* const* C, void* const* eri, isdf_graph* out);
+isdf_status isdf_graph_launch(isdf_graph g);
+isdf_status isdf_graph_destroy(isdf_graph g);
+
+/*
  * Served requests (continuous batching).  isdf_serve_start launches the
  * serving thread; isdf_submit queues one fragment (non-blocking) and returns
  * a ticket; the thread admits queued requests into batches while their HBM

@@ -13,6 +13,7 @@
 #include <deque>
 #include <functional>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <set>
@@ -1546,6 +1547,82 @@ isdf_status isdf_fragment_eri(isdf_ctx ctx, isdf_precision prec, int32_t n_frag,
     ctx->sync_ws.timer.collect(&ctx->totals);
     for (auto& kv : ctx->sync_ws.timer.ms) ctx->timer.ms[kv.first] = kv.second;
   });
+}
+
+struct isdf_graph_s {
+  isdf_ctx ctx = nullptr;
+  Workspace ws;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t after = nullptr;     // work queued on the context's stream before a replay
+  ~isdf_graph_s() {
+    if (ws.stream) (void)hipStreamSynchronize(ws.stream);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (after) (void)hipEventDestroy(after);
+  }
+};
+
+isdf_status isdf_graph_create(isdf_ctx ctx, isdf_precision prec, int32_t n_frag, const int32_t* n_f,
+                              const void* const* C, void* const* eri, isdf_graph* out) {
+  return guarded(ctx, [&] {
+    if (!out || n_frag < 1 || !n_f || !C || !eri) throw Fail{ISDF_E_INVALID, "bad graph arguments"};
+    *out = nullptr;
+    if (prec < ISDF_FP64 || prec > ISDF_MIXED_BF16X3) throw Fail{ISDF_E_INVALID, "bad precision"};
+    if (!ctx->kernel_ready) throw Fail{ISDF_E_STATE, "isdf_coulomb_kernel must run before fragment ERIs"};
+    std::vector<FragIn> fr;
+    for (int f = 0; f < n_frag; ++f) {
+      if (n_f[f] < 1 || n_f[f] > ctx->nk * ctx->norb || !C[f] || !eri[f])
+        throw Fail{ISDF_E_INVALID, "bad fragment " + std::to_string(f)};
+      hipPointerAttribute_t a1, a2;
+      if (hipPointerGetAttributes(&a1, C[f]) != hipSuccess || hipPointerGetAttributes(&a2, eri[f]) != hipSuccess ||
+          a1.type != hipMemoryTypeDevice || a2.type != hipMemoryTypeDevice) {
+        (void)hipGetLastError();
+        throw Fail{ISDF_E_INVALID, "graph fragments need device pointers (fragment " + std::to_string(f) + ")"};
+      }
+      fr.push_back(FragIn{n_f[f], C[f], eri[f], ISDF_FRAG_DEVICE});
+    }
+    std::unique_ptr<isdf_graph_s> g(new isdf_graph_s());
+    g->ctx = ctx;
+    HIPCHK(hipStreamCreateWithFlags(&g->ws.stream, hipStreamNonBlocking));
+    g->ws.own_stream = true;
+    HIPCHK(hipEventCreateWithFlags(&g->after, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(g->after, ctx->stream));
+    HIPCHK(hipStreamWaitEvent(g->ws.stream, g->after, 0));
+    // eager pass: sizes the workspace and descriptor arena (no allocation may
+    // happen under capture) and runs every launch once
+    enqueue_batch(ctx, g->ws, prec, fr, false);
+    HIPCHK(hipStreamSynchronize(g->ws.stream));
+    HIPCHK(hipStreamBeginCapture(g->ws.stream, hipStreamCaptureModeThreadLocal));
+    try {
+      enqueue_batch(ctx, g->ws, prec, fr, false);
+    } catch (...) {
+      hipGraph_t part = nullptr;
+      (void)hipStreamEndCapture(g->ws.stream, &part);
+      if (part) (void)hipGraphDestroy(part);
+      throw;
+    }
+    HIPCHK(hipStreamEndCapture(g->ws.stream, &g->graph));
+    HIPCHK(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+    *out = g.release();
+  });
+}
+
+isdf_status isdf_graph_launch(isdf_graph g) {
+  if (!g) return ISDF_E_INVALID;
+  return guarded(g->ctx, [&] {
+    if (!g->ctx->kernel_ready) throw Fail{ISDF_E_STATE, "isdf_coulomb_kernel must run before fragment ERIs"};
+    HIPCHK(hipEventRecord(g->after, g->ctx->stream));
+    HIPCHK(hipStreamWaitEvent(g->ws.stream, g->after, 0));
+    HIPCHK(hipGraphLaunch(g->exec, g->ws.stream));
+    HIPCHK(hipStreamSynchronize(g->ws.stream));
+  });
+}
+
+isdf_status isdf_graph_destroy(isdf_graph g) {
+  if (!g) return ISDF_E_INVALID;
+  delete g;
+  return ISDF_OK;
 }
 
 isdf_status isdf_serve_start(isdf_ctx ctx, int32_t max_inflight, int32_t max_batch, int64_t budget_bytes) {

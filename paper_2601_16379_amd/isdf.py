@@ -29,6 +29,7 @@ EXPORTS = ["isdf_create", "isdf_fit", "isdf_fit_eta_fp32", "isdf_coulomb_kernel"
            "isdf_get_kernel", "isdf_get_ivs", "isdf_get_rhs", "isdf_get_eta_tilde", "isdf_fragment_eri",
            "isdf_serve_start", "isdf_submit", "isdf_submit_n", "isdf_poll", "isdf_cancel",
            "isdf_serve_stop", "isdf_stats", "isdf_stage_ms", "isdf_stage_total", "isdf_stage_reset", "isdf_plan_bytes", "isdf_storage_model_bytes",
+           "isdf_graph_create", "isdf_graph_launch", "isdf_graph_destroy",
            "isdf_destroy", "isdf_last_error", "isdf_version"]
 
 
@@ -86,6 +87,9 @@ def load_library(path=LIB_PATH):
         "isdf_stage_ms": (D, [P, ctypes.c_char_p]),
         "isdf_plan_bytes": (I64, [P, P, I32, I32]),
         "isdf_storage_model_bytes": (I64, [I64, I64, I64]),
+        "isdf_graph_create": (I32, [P, I32, I32, P, P, P, ctypes.POINTER(P)]),
+        "isdf_graph_launch": (I32, [P]),
+        "isdf_graph_destroy": (I32, [P]),
         "isdf_destroy": (I32, [P]),
         "isdf_last_error": (ctypes.c_char_p, [P]),
         "isdf_version": (ctypes.c_char_p, []),
@@ -181,6 +185,8 @@ class Isdf:
             raise IsdfError(st, "%s: %s" % (what, self.lib.isdf_last_error(self.h).decode()))
 
     def close(self):
+        for g in getattr(self, "_graphs", []):
+            g.close()                      # graphs go before their context
         if getattr(self, "h", None):
             self.lib.isdf_destroy(self.h)
             self.h = None
@@ -244,6 +250,26 @@ class Isdf:
                                                nfs.ctypes.data, cptr, eptr, flags),
                     "isdf_fragment_eri")
         return out
+
+    def graph(self, coeffs, out, prec="bf16x3"):
+        """The fragment pipeline of this batch (device tensors ``coeffs``, ERIs
+        into ``out``) captured as a HIP graph; ``.launch()`` replays it."""
+        n = len(coeffs)
+        if len(out) != n:
+            raise ValueError("one output per fragment")
+        if not all(_ptr(c)[1] for c in coeffs) or not all(_ptr(e)[1] for e in out):
+            raise ValueError("graph fragments must be device tensors")
+        nfs = np.array([c.shape[2] for c in coeffs], dtype=np.int32)
+        cptr = (ctypes.c_void_p * n)(*[_ptr(c)[0] for c in coeffs])
+        eptr = (ctypes.c_void_p * n)(*[_ptr(e)[0] for e in out])
+        h = ctypes.c_void_p()
+        self._check(self.lib.isdf_graph_create(self.h, PRECISIONS.get(prec, prec), n, nfs.ctypes.data,
+                                               cptr, eptr, ctypes.byref(h)), "isdf_graph_create")
+        g = FragmentGraph(self, h, list(coeffs), list(out))
+        if not hasattr(self, "_graphs"):
+            self._graphs = []
+        self._graphs.append(g)
+        return g
 
     # -- serving -------------------------------------------------------------
     def serve_start(self, max_inflight=2, max_batch=64, budget_bytes=64 << 30):
@@ -311,3 +337,25 @@ class Isdf:
 
     def last_error(self):
         return self.lib.isdf_last_error(self.h).decode()
+
+
+class FragmentGraph:
+    """A captured fragment batch (isdf_graph_*); keeps its tensors alive."""
+
+    def __init__(self, ctx, h, coeffs, out):
+        self.ctx, self.h, self.coeffs, self.out = ctx, h, coeffs, out
+
+    def launch(self):
+        self.ctx._check(self.ctx.lib.isdf_graph_launch(self.h), "isdf_graph_launch")
+        return self.out
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.isdf_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
