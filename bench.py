@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--workload", default="c3_k4_32")
     ap.add_argument("--prec", default="bf16x3", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--no-fp64-ref", action="store_true")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="skip the fragment-batch comparison (eager / HIP graph / tuned tiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=25.0)
     ap.add_argument("--max-batch", type=int, default=0,
@@ -357,6 +359,30 @@ def main():
     if not args.no_cpu_baseline:
         w_gpu = np.stack([ctx.get_kernel(q) for q in range(cfg.n_k)])
         cpu = cpu_baseline(d, frags, w_gpu, args.cpu_budget_s)
+    if not args.no_graph and args.prec != "fp64":
+        # the fragment batch alone (after the timed steps): eager
+        # isdf_fragment_eri, its captured HIP graph, and the eager batch again
+        # with the launch tiling isdf_autotune picks on it
+        ctx.fit(args.prec)
+        ctx.coulomb_kernel(args.prec)
+
+        def per_call(fn, n=5):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(n):
+                fn()
+            torch.cuda.synchronize()
+            return 1e3 * (time.perf_counter() - t0) / n
+
+        eager_ms = per_call(lambda: ctx.fragment_eri(cdev, args.prec, out=out_mix))
+        g = ctx.graph(cdev, out_mix, args.prec)
+        graph_ms = per_call(g.launch)
+        g.close()
+        rep = ctx.autotune(cdev, out_mix, args.prec)
+        tuned_ms = per_call(lambda: ctx.fragment_eri(cdev, args.prec, out=out_mix))
+        extra["fragment_batch"] = {"eager_ms": eager_ms, "graph_ms": graph_ms, "tuned_eager_ms": tuned_ms,
+                                   "autotune": rep}
     ctx.serve_stop()
     ctx.close()
 

@@ -207,6 +207,34 @@ isdf_status isdf_graph_launch(isdf_graph g);
 isdf_status isdf_graph_destroy(isdf_graph g);
 
 /*
+ * Launch tiling of the fragment contraction, measured on the caller's batch.
+ * Two runtime choices shape the GEMM launches of Algorithm 2: the number of
+ * classes {q, -q} whose K ranges one ERI launch covers (the FP32 partial sums
+ * then go into the FP64 accumulation once per launch) and the workgroups per
+ * CU of the persistent tile loops.  isdf_autotune runs the batch (device
+ * pointers, as isdf_graph_create) under each candidate -- the N_h classes in
+ * one, two or three launches and the default (at most 40 classes a launch),
+ * times {2, 4, 8} workgroups per CU --, twice each after a warm-up, keeps the fastest
+ * for this context and, when `report` is not NULL, fills it.  The eri[f] hold
+ * the last candidate's results afterwards.  isdf_set_tiling sets the two
+ * values directly (wg_per_cu 0 = default of 8).  Results of every tiling
+ * meet the same error bounds; the FP32 partial sums change with the classes
+ * per launch, so mixed results are bitwise reproducible for a fixed tiling
+ * only.  Error: ISDF_E_STATE without a Coulomb kernel, ISDF_E_BUSY while
+ * served requests are queued or running, ISDF_E_INVALID for bad arguments.
+ */
+typedef struct {
+  int32_t eri_qgroup;   /* classes per ERI launch chosen */
+  int32_t wg_per_cu;    /* workgroups per CU chosen */
+  double ms;            /* batch time with the chosen tiling (best of two) */
+  double ms_default;    /* batch time with the default tiling (<= 40 classes a launch, 8 per CU) */
+  int32_t n_tried;      /* candidates timed */
+} isdf_tune_report;
+isdf_status isdf_autotune(isdf_ctx ctx, isdf_precision prec, int32_t n_frag, const int32_t* n_f,
+                          const void* const* C, void* const* eri, isdf_tune_report* report);
+isdf_status isdf_set_tiling(isdf_ctx ctx, int32_t eri_qgroup, int32_t wg_per_cu);
+
+/*
  * Served requests (continuous batching).  isdf_serve_start launches the
  * serving thread; isdf_submit queues one fragment (non-blocking) and returns
  * a ticket; the thread admits queued requests into batches while their HBM

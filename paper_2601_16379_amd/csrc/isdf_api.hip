@@ -130,11 +130,25 @@ int max_gemm_blocks() {
   return g_max_blocks;
 }
 
+// Workgroups per CU of the persistent GEMM launches issued by this thread (0:
+// the default of max_gemm_blocks); the fragment pipeline sets it from its
+// context's tuned value for the duration of a batch.
+thread_local int t_wg_per_cu = 0;
+int gemm_blocks() {
+  if (t_wg_per_cu <= 0) return max_gemm_blocks();
+  return max_gemm_blocks() / 8 * t_wg_per_cu;
+}
+struct WgScope {
+  int old;
+  explicit WgScope(int v) : old(t_wg_per_cu) { t_wg_per_cu = v; }
+  ~WgScope() { t_wg_per_cu = old; }
+};
+
 void run_gemm(Arena& ar, int prec, int layout, std::vector<GemmDesc>& d, hipStream_t s) {
   long long total = gemm_plan(d.data(), (int)d.size());
   if (total == 0) return;
   GemmDesc* dd = ar.put(d.data(), d.size(), s);
-  HIPCHK(gemm_launch(prec, layout, dd, (int)d.size(), total, max_gemm_blocks(), s));
+  HIPCHK(gemm_launch(prec, layout, dd, (int)d.size(), total, gemm_blocks(), s));
 }
 
 // mark(true) / mark(false) bracket each kernel launch when given (kernel timing)
@@ -146,7 +160,7 @@ void run_nt(Arena& ar, int prec, int conj, std::vector<NtDesc>& d, hipStream_t s
   if (total == 0) return;
   NtDesc* dd = ar.put(d.data(), d.size(), s);
   if (mark) mark(true);
-  HIPCHK(nt_launch(prec, conj, dd, (int)d.size(), total, max_gemm_blocks(), s, kind));
+  HIPCHK(nt_launch(prec, conj, dd, (int)d.size(), total, gemm_blocks(), s, kind));
   if (mark) mark(false);
 }
 
@@ -158,8 +172,8 @@ void run_big(Arena& ar, int prec, int conj, std::vector<NtDesc>& d, int nseg, hi
   NtDesc* dd = ar.put(d.data(), d.size(), s);
   for (int seg = 0; seg < nseg; ++seg) {
     if (mark) mark(true);
-    HIPCHK(prec == 2 ? x3_launch(conj, dd, (int)d.size(), total, max_gemm_blocks(), seg, s, kind)
-                     : big_launch(prec, conj, dd, (int)d.size(), total, max_gemm_blocks(), seg, s, kind));
+    HIPCHK(prec == 2 ? x3_launch(conj, dd, (int)d.size(), total, gemm_blocks(), seg, s, kind)
+                     : big_launch(prec, conj, dd, (int)d.size(), total, gemm_blocks(), seg, s, kind));
     if (mark) mark(false);
   }
 }
@@ -322,6 +336,10 @@ struct isdf_ctx_s {
   bool etat_valid = false;              // eta~ of every class still held after the kernel (no q batches)
   bool eta32 = false;               // eta (and the RHS tile) held as complex FP32
   int kernel_prec = 0;              // precision of the last isdf_coulomb_kernel
+  // launch tiling of the fragment contraction (isdf_autotune / isdf_set_tiling):
+  // classes per ERI launch (the K extent of one launch) and workgroups per CU
+  // of its persistent GEMM launches (0: default)
+  int eri_qgroup = ERI_QGROUP, frag_wg_per_cu = 0;
   std::vector<int> rank_h;
   // q <-> -q: Pi^{-q}, W^{-q} and R^{-q}_{pq} are conjugates of those at q,
   // so the fragment contraction runs over the classes {q, -q}: hq[h] is the
@@ -843,6 +861,7 @@ void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn
                    bool timed) {
   if (!c->kernel_ready) throw Fail{ISDF_E_STATE, "isdf_coulomb_kernel must run before fragment ERIs"};
   hipStream_t s = ws.stream;
+  WgScope wg(c->frag_wg_per_cu);
   const int nk = c->nk, norb = c->norb, nip = c->nip;
   const long long ld = c->ld_ip;
   BatchPlan p = plan_batch(c, fr, prec);
@@ -995,7 +1014,7 @@ void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn
   {
     std::vector<NtDesc> d;
     const size_t sc = fmt_scalar(prec);
-    const int ngroup = (nh + ERI_QGROUP - 1) / ERI_QGROUP;
+    const int ngroup = (nh + c->eri_qgroup - 1) / c->eri_qgroup;
     const int qgroup = (nh + ngroup - 1) / ngroup;       // balanced groups
     cplx* acc = (cplx*)(base + p.off_acc);
     for (size_t f = 0; f < fr.size(); ++f) {
@@ -1623,6 +1642,84 @@ isdf_status isdf_graph_destroy(isdf_graph g) {
   if (!g) return ISDF_E_INVALID;
   delete g;
   return ISDF_OK;
+}
+
+isdf_status isdf_set_tiling(isdf_ctx ctx, int32_t eri_qgroup, int32_t wg_per_cu) {
+  return guarded(ctx, [&] {
+    if (eri_qgroup < 1 || wg_per_cu < 0 || wg_per_cu > 8) throw Fail{ISDF_E_INVALID, "bad tiling"};
+    if (!serve_idle(ctx)) throw Fail{ISDF_E_BUSY, "requests are queued or running"};
+    ctx->eri_qgroup = eri_qgroup;
+    ctx->frag_wg_per_cu = wg_per_cu;
+  });
+}
+
+isdf_status isdf_autotune(isdf_ctx ctx, isdf_precision prec, int32_t n_frag, const int32_t* n_f,
+                          const void* const* C, void* const* eri, isdf_tune_report* report) {
+  return guarded(ctx, [&] {
+    if (n_frag < 1 || !n_f || !C || !eri) throw Fail{ISDF_E_INVALID, "bad fragment arguments"};
+    if (prec < ISDF_FP64 || prec > ISDF_MIXED_BF16X3) throw Fail{ISDF_E_INVALID, "bad precision"};
+    if (!ctx->kernel_ready) throw Fail{ISDF_E_STATE, "isdf_coulomb_kernel must run before fragment ERIs"};
+    if (!serve_idle(ctx)) throw Fail{ISDF_E_BUSY, "requests are queued or running"};
+    std::vector<FragIn> fr;
+    for (int f = 0; f < n_frag; ++f) {
+      if (n_f[f] < 1 || n_f[f] > ctx->nk * ctx->norb || !C[f] || !eri[f])
+        throw Fail{ISDF_E_INVALID, "bad fragment " + std::to_string(f)};
+      fr.push_back(FragIn{n_f[f], C[f], eri[f], ISDF_FRAG_DEVICE});
+    }
+    const int nh = ctx->nh;
+    // classes per launch for one, two and three launches over the classes,
+    // and the default (at most ERI_QGROUP per launch)
+    const int def_g = (nh + ((nh + ERI_QGROUP - 1) / ERI_QGROUP) - 1) / ((nh + ERI_QGROUP - 1) / ERI_QGROUP);
+    std::vector<int> groups = {def_g};
+    for (int nl = 1; nl <= 3 && nl <= nh; ++nl) groups.push_back((nh + nl - 1) / nl);
+    std::sort(groups.begin(), groups.end());
+    groups.erase(std::unique(groups.begin(), groups.end()), groups.end());
+    const int wgs[] = {2, 4, 8};
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    const int old_g = ctx->eri_qgroup, old_w = ctx->frag_wg_per_cu;
+    double best = 1e300, def_ms = 0;
+    int best_g = old_g, best_w = old_w;
+    try {
+      for (int g : groups) {
+        for (int w : wgs) {
+          ctx->eri_qgroup = g;
+          ctx->frag_wg_per_cu = w;
+          enqueue_batch(ctx, ctx->sync_ws, prec, fr, false);     // warm-up (sizes the workspace)
+          double ms = 1e300;
+          for (int rep = 0; rep < 2; ++rep) {
+            HIPCHK(hipEventRecord(e0, ctx->stream));
+            enqueue_batch(ctx, ctx->sync_ws, prec, fr, false);
+            HIPCHK(hipEventRecord(e1, ctx->stream));
+            HIPCHK(hipEventSynchronize(e1));
+            float t = 0.f;
+            HIPCHK(hipEventElapsedTime(&t, e0, e1));
+            ms = std::min(ms, (double)t);
+          }
+          if (g == def_g && w == 8) def_ms = ms;
+          if (ms < best) { best = ms; best_g = g; best_w = w; }
+        }
+      }
+    } catch (...) {
+      ctx->eri_qgroup = old_g;
+      ctx->frag_wg_per_cu = old_w;
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->eri_qgroup = best_g;
+    ctx->frag_wg_per_cu = best_w;
+    if (report) {
+      report->eri_qgroup = best_g;
+      report->wg_per_cu = best_w;
+      report->ms = best;
+      report->ms_default = def_ms;
+      report->n_tried = (int32_t)(groups.size() * 3);
+    }
+  });
 }
 
 isdf_status isdf_serve_start(isdf_ctx ctx, int32_t max_inflight, int32_t max_batch, int64_t budget_bytes) {

@@ -29,7 +29,7 @@ EXPORTS = ["isdf_create", "isdf_fit", "isdf_fit_eta_fp32", "isdf_coulomb_kernel"
            "isdf_get_kernel", "isdf_get_ivs", "isdf_get_rhs", "isdf_get_eta_tilde", "isdf_fragment_eri",
            "isdf_serve_start", "isdf_submit", "isdf_submit_n", "isdf_poll", "isdf_cancel",
            "isdf_serve_stop", "isdf_stats", "isdf_stage_ms", "isdf_stage_total", "isdf_stage_reset", "isdf_plan_bytes", "isdf_storage_model_bytes",
-           "isdf_graph_create", "isdf_graph_launch", "isdf_graph_destroy",
+           "isdf_graph_create", "isdf_graph_launch", "isdf_graph_destroy", "isdf_autotune", "isdf_set_tiling",
            "isdf_destroy", "isdf_last_error", "isdf_version"]
 
 
@@ -42,6 +42,11 @@ class IsdfError(RuntimeError):
 class Request(ctypes.Structure):
     _fields_ = [("n_f", ctypes.c_int32), ("C", ctypes.c_void_p), ("eri", ctypes.c_void_p),
                 ("prec", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class TuneReport(ctypes.Structure):
+    _fields_ = [("eri_qgroup", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32), ("ms", ctypes.c_double),
+                ("ms_default", ctypes.c_double), ("n_tried", ctypes.c_int32)]
 
 
 _lib = None
@@ -89,6 +94,8 @@ def load_library(path=LIB_PATH):
         "isdf_storage_model_bytes": (I64, [I64, I64, I64]),
         "isdf_graph_create": (I32, [P, I32, I32, P, P, P, ctypes.POINTER(P)]),
         "isdf_graph_launch": (I32, [P]),
+        "isdf_autotune": (I32, [P, I32, I32, P, P, P, ctypes.POINTER(TuneReport)]),
+        "isdf_set_tiling": (I32, [P, I32, I32]),
         "isdf_graph_destroy": (I32, [P]),
         "isdf_destroy": (I32, [P]),
         "isdf_last_error": (ctypes.c_char_p, [P]),
@@ -270,6 +277,23 @@ class Isdf:
             self._graphs = []
         self._graphs.append(g)
         return g
+
+    def autotune(self, coeffs, out, prec="bf16x3"):
+        """isdf_autotune on this batch (device tensors); returns the report."""
+        n = len(coeffs)
+        if not all(_ptr(c)[1] for c in coeffs) or not all(_ptr(e)[1] for e in out):
+            raise ValueError("autotune fragments must be device tensors")
+        nfs = np.array([c.shape[2] for c in coeffs], dtype=np.int32)
+        cptr = (ctypes.c_void_p * n)(*[_ptr(c)[0] for c in coeffs])
+        eptr = (ctypes.c_void_p * n)(*[_ptr(e)[0] for e in out])
+        r = TuneReport()
+        self._check(self.lib.isdf_autotune(self.h, PRECISIONS.get(prec, prec), n, nfs.ctypes.data, cptr, eptr,
+                                           ctypes.byref(r)), "isdf_autotune")
+        return {"eri_qgroup": r.eri_qgroup, "wg_per_cu": r.wg_per_cu, "ms": r.ms,
+                "ms_default": r.ms_default, "n_tried": r.n_tried}
+
+    def set_tiling(self, eri_qgroup, wg_per_cu=0):
+        self._check(self.lib.isdf_set_tiling(self.h, int(eri_qgroup), int(wg_per_cu)), "isdf_set_tiling")
 
     # -- serving -------------------------------------------------------------
     def serve_start(self, max_inflight=2, max_batch=64, budget_bytes=64 << 30):
