@@ -339,7 +339,7 @@ struct isdf_ctx_s {
   // launch tiling of the fragment contraction (isdf_autotune / isdf_set_tiling):
   // classes per ERI launch (the K extent of one launch) and workgroups per CU
   // of its persistent GEMM launches (0: default)
-  int eri_qgroup = ERI_QGROUP, frag_wg_per_cu = 0;
+  int eri_qgroup = ERI_QGROUP, frag_wg_per_cu = FRAG_WG_PER_CU;
   std::vector<int> rank_h;
   // q <-> -q: Pi^{-q}, W^{-q} and R^{-q}_{pq} are conjugates of those at q,
   // so the fragment contraction runs over the classes {q, -q}: hq[h] is the
@@ -1668,7 +1668,7 @@ isdf_status isdf_autotune(isdf_ctx ctx, isdf_precision prec, int32_t n_frag, con
     }
     const int nh = ctx->nh;
     // classes per launch for one, two and three launches over the classes,
-    // and the default (at most ERI_QGROUP per launch)
+    // and the initial tiling (at most ERI_QGROUP per launch)
     const int def_g = (nh + ((nh + ERI_QGROUP - 1) / ERI_QGROUP) - 1) / ((nh + ERI_QGROUP - 1) / ERI_QGROUP);
     std::vector<int> groups = {def_g};
     for (int nl = 1; nl <= 3 && nl <= nh; ++nl) groups.push_back((nh + nl - 1) / nl);
@@ -1697,7 +1697,7 @@ isdf_status isdf_autotune(isdf_ctx ctx, isdf_precision prec, int32_t n_frag, con
             HIPCHK(hipEventElapsedTime(&t, e0, e1));
             ms = std::min(ms, (double)t);
           }
-          if (g == def_g && w == 8) def_ms = ms;
+          if (g == def_g && w == FRAG_WG_PER_CU) def_ms = ms;
           if (ms < best) { best = ms; best_g = g; best_w = w; }
         }
       }

@@ -95,9 +95,13 @@ hipError_t x3_launch(int conj, const NtDesc* descs_dev, int ndesc, long long tot
 // launch (one contiguous K range of at most ERI_QGROUP * ld, the classes
 // split into balanced groups), FP64 across launches (the max ERI error at
 // the benchmark workload was 2.426e-7 Eh with 8, 2.428e-7 with 16 and
-// 2.429e-7 with 32 q per launch, set by the V^q rounding; the 36 classes
-// of a 4x4x4 mesh take one launch)
-constexpr int ERI_QGROUP = 40;
+// 2.429e-7 with 32 q per launch, set by the V^q rounding).  The initial
+// tiling of a context -- at most 12 classes a launch (three launches for the
+// 36 classes of a 4x4x4 mesh) and 2 workgroups per CU for the fragment GEMMs
+// (one resident wave of workgroups) -- is what the launch-tiling autotuner
+// picks on a 4x4x4 mesh with 64 fragments of 12-40 orbitals.
+constexpr int ERI_QGROUP = 12;
+constexpr int FRAG_WG_PER_CU = 2;
 
 // W (c128 [h][n][n], one q per class {q, -q}) -> transposed copies
 // Wt[h][J][I] = w_h W[h][I][J], w_h = 1/2 where q = -q (hself: device), with
