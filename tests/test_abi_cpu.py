@@ -100,3 +100,12 @@ def test_calls_on_null_context_fail_cleanly():
     st = ctypes.c_int32()
     assert lib.isdf_poll(None, ctypes.c_uint64(1), ctypes.byref(st), None) == -1
     assert lib.isdf_stage_ms(None, b"chol") == -1.0
+    # batch graphs and launch tiling
+    h = ctypes.c_void_p()
+    nf = (ctypes.c_int32 * 1)(4)
+    ptrs = (ctypes.c_void_p * 1)(None)
+    assert lib.isdf_graph_create(None, 2, 1, nf, ptrs, ptrs, ctypes.byref(h)) == -1 and not h.value
+    assert lib.isdf_graph_launch(None) == -1
+    assert lib.isdf_graph_destroy(None) == -1
+    assert lib.isdf_autotune(None, 2, 1, nf, ptrs, ptrs, None) == -1
+    assert lib.isdf_set_tiling(None, 12, 2) == -1
