@@ -15,7 +15,10 @@
  *                        (eqs. (6)-(8)), grid FFTs with the 4 pi/|G+q|^2 kernel;
  *   isdf_fragment_eri    fragment ERIs from W^q and fragment coefficients
  *                        C^k_{mu p} (eqs. (17), (19)-(20), Algorithm 2);
- *   isdf_submit/poll     the same as served requests (continuous batching).
+ *   isdf_submit/poll     the same as served requests (continuous batching);
+ *   isdf_graph_*         one fragment batch captured as a HIP graph and replayed;
+ *   isdf_autotune        launch tiling of the fragment contraction timed on a
+ *                        caller's batch (isdf_set_tiling sets it directly).
  *
  * Conventions (the paper leaves them implicit; they are fixed here):
  *   - complex numbers are interleaved (re, im) float64 pairs ("c128");
