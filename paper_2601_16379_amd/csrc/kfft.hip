@@ -489,9 +489,7 @@ __device__ inline void mesh_dft_reg(float2 (&x)[M1 * M2 * M3]) {
 // the N_k outputs of its I (each store instruction covers 64 consecutive I
 // of one row).  Workgroups are mapped XCD-contiguously so the psi rows of
 // one fragment and I chunk stay in one L2 while all its pairs use them.
-#ifndef PAIR_RB
-#define PAIR_RB 8
-#endif
+constexpr int PAIR_RB = 8;   // lattice vectors whose loads are issued together
 template <int M1, int M2, int M3>
 __global__ __launch_bounds__(256, 2) void pair_reg_kernel(PairArgs a, int nblocks) {
   constexpr int NK = M1 * M2 * M3;
