@@ -36,6 +36,9 @@ def parse():
     ap.add_argument("--workload", default="c3_k4_32")
     ap.add_argument("--prec", default="bf16x3", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--no-fp64-ref", action="store_true")
+    ap.add_argument("--poisson-rates", default="200,1000,4000",
+                    help="request rates (1/s) of the open-arrival serving sweep after the timed steps; '' skips it")
+    ap.add_argument("--poisson-n", type=int, default=256, help="requests per rate of the sweep")
     ap.add_argument("--no-graph", action="store_true",
                     help="skip the fragment-batch comparison (eager / HIP graph / tuned tiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -214,6 +217,43 @@ def cpu_baseline(d, frags, w_gpu, budget_s):
     }
 
 
+def poisson_sweep(ctx, inp, cfg, cdev, outs, prec, rates, n):
+    """Open arrivals: requests for the step's fragments (reused cyclically)
+    submitted one at a time at Poisson arrival times (seeded), while earlier
+    ones run; per rate the offered and served rates and the p50 / p99 latency
+    (the library's clock: submit -> completion observed)."""
+    import numpy as np
+    rows = []
+    for rate in rates:
+        arr = inp.make_arrivals(cfg, n, rate)
+        tickets, pending, lat = [], set(), {}
+        i = 0
+        t0 = time.perf_counter()
+        while i < n or pending:
+            now = time.perf_counter() - t0
+            while i < n and arr[i] <= now:
+                f = i % len(cdev)
+                t = ctx.submit_n([cdev[f]], [outs[f]], prec)[0]
+                tickets.append(t)
+                pending.add(t)
+                i += 1
+            for t in list(pending):
+                st, l = ctx.poll(t)
+                if st == "DONE":
+                    lat[t] = l
+                    pending.discard(t)
+                elif st in ("FAILED", "CANCELLED"):
+                    raise RuntimeError("request %d %s: %s" % (t, st, ctx.last_error()))
+        wall = time.perf_counter() - t0
+        lm = 1e3 * np.array([lat[t] for t in tickets])
+        rows.append({"rate_per_s": rate, "requests": n, "offered_per_s": n / float(arr[-1]),
+                     "served_per_s": n / wall, "p50_ms": float(np.percentile(lm, 50)),
+                     "p99_ms": float(np.percentile(lm, 99))})
+        print("poisson %g/s: p50 %.2f ms, p99 %.2f ms" % (rate, rows[-1]["p50_ms"], rows[-1]["p99_ms"]),
+              file=sys.stderr, flush=True)
+    return rows
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -339,6 +379,9 @@ def main():
         stage_rows[s] = row
 
     extra = {}
+    rates = [float(r) for r in args.poisson_rates.split(",") if r.strip()]
+    if rates:
+        extra["poisson"] = poisson_sweep(ctx, inp, cfg, cdev, out_mix, args.prec, rates, args.poisson_n)
     if not args.no_fp64_ref and args.prec != "fp64":
         step("fp64", out_64)
         torch.cuda.synchronize()
