@@ -6,8 +6,10 @@ Readings of the paper fixed here (each pinned by ``tests/test_oracle_pins.py``):
   quantity at k (eq. (2) writes phi(r)^* = phi^{-k}(r)); the orbital at mesh
   point -k is never looked up;
 * q is the mesh difference of the pair momenta, q = k_mu - k_nu (eq. (2));
-  in the Coulomb kernel q is wrapped to [-1/2, 1/2) per axis, and G runs over
-  the unit-cell DFT box [-n/2, n/2);
+  in the Coulomb kernel q is wrapped to [-1/2, 1/2) per axis, and each DFT
+  index of the unit-cell grid stands for K = G + q taken at its
+  representative nearest zero per axis (the kernel averaged over the two
+  representatives where K_d = +-n_d/2), see ``oracle.geometry``;
 * the element-wise product of Algorithm 1 is T^R conj(T^R) = |T^R|^2 (what
   the least-squares normal equations of eq. (2) require);
 * the normal equations of eq. (3) are solved in the minimum-norm
@@ -55,6 +57,21 @@ def metric_k(x, kmesh):
     for q in range(nk):
         pi[q] = np.einsum("kij,kij->ij", t[kq[:, q]].conj(), t)
     return pi
+
+
+def metric_rows(x, kmesh, rows, qs=None):
+    """Rows I in ``rows`` of Pi^q_{IJ} = sum_k conj(T^{k+q}_{IJ}) T^k_{IJ}
+    (eq. (4)) for the listed q (all if None), from the rows of T^k alone:
+    the same direct k sum as ``metric_k`` at a cost linear in the number of
+    rows.  Returns [len(qs), len(rows), N_IP]."""
+    nk = x.shape[0]
+    qs = list(range(nk)) if qs is None else list(qs)
+    t = np.matmul(x[:, rows, :], np.transpose(x.conj(), (0, 2, 1)))   # T^k_{IJ}, I in rows
+    kq = geo.k_plus_q(kmesh)
+    out = np.empty((len(qs),) + t.shape[1:], dtype=np.complex128)
+    for iq, q in enumerate(qs):
+        out[iq] = np.einsum("kij,kij->ij", t[kq[:, q]].conj(), t)
+    return out
 
 
 def rhs(x, orbitals, kmesh, qs, r_index=None):

@@ -380,3 +380,76 @@ def test_eta_tilde_of_plane_waves_closed_form():
             expect = np.sqrt(vol * c)
             assert abs(et[i, idx] - expect) < 1e-12 * max(1.0, expect), (q, i)
             assert np.max(np.abs(np.delete(et[i], idx))) < 1e-12, (q, i)
+
+
+# --------------------------------------------------------------------------
+# Lattice duality and the reduced forms the sampled GPU references use
+# --------------------------------------------------------------------------
+def test_reciprocal_duality_non_orthogonal():
+    """a_i . b_j = 2 pi delta_ij on a triclinic lattice (explicit dot
+    products), and the textbook reciprocal of a hexagonal lattice
+    a1 = (a, 0, 0), a2 = (a/2, a sqrt(3)/2, 0), a3 = (0, 0, c):
+    b1 = 2 pi/a (1, -1/sqrt(3), 0), b2 = 2 pi/a (0, 2/sqrt(3), 0),
+    b3 = 2 pi/c (0, 0, 1).  The hexagonal lattice matrix is not symmetric,
+    so a transposed inverse fails it."""
+    tri = np.array([[4.0, 0.0, 0.0], [1.0, 4.5, 0.0], [0.5, 0.3, 5.0]])
+    b = geo.reciprocal(tri)
+    for i in range(3):
+        for j in range(3):
+            dot = sum(tri[i][c] * b[j][c] for c in range(3))
+            assert abs(dot - (2 * np.pi if i == j else 0.0)) < 1e-13
+    a, c = 4.7, 7.3
+    hexa = np.array([[a, 0.0, 0.0], [a / 2, a * math.sqrt(3) / 2, 0.0], [0.0, 0.0, c]])
+    expect = np.array([[2 * np.pi / a, -2 * np.pi / (a * math.sqrt(3)), 0.0],
+                       [0.0, 4 * np.pi / (a * math.sqrt(3)), 0.0],
+                       [0.0, 0.0, 2 * np.pi / c]])
+    assert np.max(np.abs(geo.reciprocal(hexa) - expect)) < 1e-13
+
+
+def test_rhs_reduced_forms_equal_full_form():
+    """rhs on a subset of grid points and of q (in any order) returns the
+    matching entries of the full call, and rhs_chunked with a chunk that does
+    not divide N_g equals the full call: the forms the sampled GPU
+    references rely on."""
+    d = _case("t_small_k3")
+    cfg = d.cfg
+    x = ko.ip_values(d.orbitals, d.ip_index)
+    full = ko.rhs(x, d.orbitals, cfg.kmesh, list(range(cfg.n_k)))
+    rng = np.random.default_rng(5)
+    ridx = np.sort(rng.choice(cfg.n_g, 97, replace=False))
+    qs = [7, 0, 13]
+    sub = ko.rhs(x, d.orbitals, cfg.kmesh, qs, ridx)
+    assert _rel(sub, full[qs][:, :, ridx]) < 1e-15
+    assert cfg.n_g % 500 != 0
+    ch = ko.rhs_chunked(x, d.orbitals, cfg.kmesh, qs, chunk=500)
+    assert _rel(ch, full[qs]) < 1e-15
+    # subsets of interpolation points (rows) are rows of the full result
+    rows = [3, 40, 11]
+    sub_rows = ko.rhs(x[:, rows], d.orbitals, cfg.kmesh, qs, ridx)
+    assert _rel(sub_rows, full[qs][:, rows][:, :, ridx]) < 1e-15
+
+
+def test_kernel_v_route_q_subset_equals_full_call():
+    """kernel_v_route with qs = [q2, q0] returns the rows q2, q0 of the full
+    call (eta given in the order of qs)."""
+    d = _case("t_small_k3")
+    cfg = d.cfg
+    x = ko.ip_values(d.orbitals, d.ip_index)
+    pi = ko.metric_k(x, cfg.kmesh)
+    eta = ko.rhs(x, d.orbitals, cfg.kmesh, list(range(cfg.n_k)))
+    full = ko.kernel_v_route(pi, eta, d.lattice, cfg.grid, cfg.kmesh)
+    qs = [9, 0, 4]
+    sub = ko.kernel_v_route(pi, eta[qs], d.lattice, cfg.grid, cfg.kmesh, qs=qs)
+    assert _rel(sub, full[qs]) < 1e-15
+
+
+def test_metric_rows_equal_full_metric():
+    """Rows of Pi^q from the rows of X alone (the reduced form used at the
+    largest workloads) equal rows of the full metric for every q."""
+    d = _case("t_small_k3")
+    cfg = d.cfg
+    x = ko.ip_values(d.orbitals, d.ip_index)
+    pi = ko.metric_k(x, cfg.kmesh)
+    rows = [5, 0, 77]
+    pr = ko.metric_rows(x, cfg.kmesh, rows)
+    assert _rel(pr, pi[:, rows, :]) < 1e-15
