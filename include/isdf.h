@@ -26,8 +26,11 @@
  *     the point (i1/n1) a1 + (i2/n2) a2 + (i3/n3) a3;
  *   - the k mesh is Gamma-centred, k index = (j1*m2 + j2)*m3 + j3 is the point
  *     sum_d (j_d/m_d) b_d; q is the mesh difference of pair momenta (mod m),
- *     wrapped to [-1/2, 1/2) per axis inside the Coulomb kernel, G runs over
- *     the unit-cell DFT box [-n/2, n/2) and the G+q = 0 term is dropped;
+ *     wrapped to [-1/2, 1/2) per axis inside the Coulomb kernel; each DFT
+ *     index of the grid stands for K = G + q at its representative nearest
+ *     zero per axis (|K_d| <= n_d/2 in units of b_d, the kernel averaged over
+ *     the two representatives at a tie K_d = +-n_d/2), and the K = 0 term is
+ *     dropped;
  *   - a superscript -k in the paper is read as the complex conjugate at k;
  *   - ERIs are in Hartree, chemists' notation with the conjugate on p and r:
  *       (pq|rs) = int int conj(psi_p) psi_q (x) conj(psi_r) psi_s (y) / |x-y|,
@@ -258,6 +261,8 @@ typedef struct {
   void* eri;            /* c128 [n_f]^4           */
   int32_t prec;         /* isdf_precision         */
   uint32_t flags;       /* ISDF_FRAG_DEVICE       */
+  int32_t priority;     /* admission order: higher first, submission order
+                           among equal priorities (0 = default)           */
 } isdf_request;
 
 isdf_status isdf_serve_start(isdf_ctx ctx, int32_t max_inflight, int32_t max_batch,

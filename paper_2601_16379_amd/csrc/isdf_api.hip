@@ -95,11 +95,26 @@ struct PinnedBuf {
 // Descriptor arena: GEMM descriptors and small tables are written to pinned
 // host memory and copied to device memory on the launching stream.  Reset
 // only after the stream has drained.
+// The host copy is pinned, so a queued copy reads it when it executes: reset
+// waits for the stream (the previous user of the arena may still have copies
+// queued), and reserve sizes the arena for a whole pass before its first put
+// (earlier device pointers must stay valid while the pass is enqueued).
 struct Arena {
   PinnedBuf host;
   DevBuf dev;
   size_t used = 0;
-  void reset() { used = 0; }
+  void reset(hipStream_t s) {
+    HIPCHK(hipStreamSynchronize(s));
+    used = 0;
+  }
+  // Capacity for `bytes` of puts (each put adds at most 255 bytes of
+  // alignment); the stream has drained (reset) and nothing was put yet.
+  void reserve(size_t bytes) {
+    if (used != 0) throw Fail{ISDF_E_INVALID, "descriptor arena reserved after a put"};
+    const size_t cap = std::max<size_t>(1 << 20, bytes);
+    if (host.bytes < cap) host.ensure(cap);
+    if (dev.bytes < cap) dev.ensure(cap);
+  }
   template <class T> T* put(const T* src, size_t n, hipStream_t s) {
     size_t bytes = n * sizeof(T);
     size_t off = (used + 255) & ~size_t(255);
@@ -365,6 +380,7 @@ struct isdf_ctx_s {
   std::condition_variable cv;
   std::thread worker;
   bool serving = false, stop = false;
+  bool exclusive = false;               // a synchronous call holds the context (see Exclusive)
   int max_inflight = 2, max_batch = 64;
   long long budget = 0;
   uint64_t next_ticket = 1;
@@ -405,16 +421,34 @@ template <class F> isdf_status guarded(isdf_ctx c, F&& f) {
   }
 }
 
-// No request queued or on the GPU (refitting is allowed between requests).
-bool serve_idle(isdf_ctx c) {
-  std::lock_guard<std::mutex> lk(c->mu);
-  if (!c->serving) return true;
-  for (uint64_t t : c->queue) {
-    auto it = c->reqs.find(t);
-    if (it != c->reqs.end() && it->second.state == ISDF_REQ_QUEUED) return false;
+// Exclusive use of the context by a synchronous call that rewrites or times
+// its GPU state (isdf_fit, isdf_coulomb_kernel, isdf_autotune,
+// isdf_set_tiling): refused with ISDF_E_BUSY while served requests are queued
+// or in flight (a batch counts from the moment its requests leave the queue);
+// while it is held the serving thread admits nothing.  clear_kernel: W^q is
+// invalid from the start of the call (a request admitted afterwards without
+// a new kernel fails).
+struct Exclusive {
+  isdf_ctx c;
+  Exclusive(isdf_ctx c_, bool clear_kernel) : c(c_) {
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (c->serving) {
+      for (uint64_t t : c->queue) {
+        auto it = c->reqs.find(t);
+        if (it != c->reqs.end() && it->second.state == ISDF_REQ_QUEUED)
+          throw Fail{ISDF_E_BUSY, "requests are queued or running"};
+      }
+      if (c->inflight_n != 0) throw Fail{ISDF_E_BUSY, "requests are queued or running"};
+    }
+    c->exclusive = true;
+    if (clear_kernel) c->kernel_ready = false;
   }
-  return c->inflight_n == 0;
-}
+  ~Exclusive() {
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->exclusive = false;
+    c->cv.notify_all();
+  }
+};
 
 bool good_grid(int n) {
   if (n < 2 || n > 64) return false;
@@ -490,10 +524,11 @@ void do_fit(isdf_ctx c, int prec) {
   const int nk = c->nk, norb = c->norb, nip = c->nip;
   const int nh = c->nh;                 // classes {q, -q}: Pi, eta, W are kept for one q of each
   const long long ng = c->ng;
-  c->arena.reset();
+  c->arena.reset(s);
+  c->arena.reserve(((size_t)1 << 20) + (size_t)c->nh * 1024);
   // the second stream may still be forming the previous fit's pseudo-inverse
-  HIPCHK(hipStreamSynchronize(c->aux));
-  c->arena_aux.reset();
+  c->arena_aux.reset(c->aux);
+  c->arena_aux.reserve(((size_t)1 << 20) + (size_t)c->nh * 1024);
   // X^k (IV gather)
   HIPCHK(gather_launch(c->phi.as<cplx>(), c->ip.as<int>(), c->xt.as<cplx>(), nk, norb, ng, nip, s));
   // T^k_IJ = sum_mu X^k_{I mu} conj(X^k_{J mu})  (Algorithm 1, Y = X)
@@ -663,7 +698,11 @@ void do_kernel(isdf_ctx c, int prec) {
   const int nk = c->nk, nip = c->nip;
   const int nh = c->nh;                 // one q per class {q, -q}: W^{-q} = conj W^q
   const long long ng = c->ng;
-  c->arena.reset();
+  c->arena.reset(s);
+  // per q batch: the slot map and a few descriptors; the W solve: one
+  // descriptor per class for each of its two products
+  c->arena.reserve(((size_t)1 << 20) + (size_t)nh * 2 * (sizeof(NtDesc) + 256) +
+                   (size_t)((nh + std::max(c->qb, 1) - 1) / std::max(c->qb, 1)) * (nk * sizeof(int) + 4096));
   // q batches of qb classes (one batch, eta formed by the fit, when they all
   // fit); per batch: eta (when batched), the grid FFT, V^q
   const int qb = c->eta_batched ? c->qb : nh;
@@ -802,77 +841,144 @@ struct BatchPlan {
   long long ptot = 0;
   std::vector<int> col, nf;
   std::vector<long long> poff, eoff;
-  size_t off_c = 0, off_tf = 0, off_m = 0, off_u = 0, off_e = 0, off_acc = 0, bytes = 0;
-  std::vector<long long> aoff;   // per fragment offset in the FP64 accumulation region (mixed)
+  std::vector<long long> aoff;   // per fragment offset in the FP64 accumulation region
+  // (pq)-blocking of the single fragment of a blocked batch: its nf^2 pairs
+  // in nb blocks of at most pb pairs; R^q of two blocks (row block i and
+  // column block j) and U^q of block i are held at a time
+  int nb = 1;
+  long long pb = 0;
+  bool psi32 = false;            // the register pair transform reads psi as complex FP32
+  size_t off_c = 0, off_tf = 0, off_psi = 0, off_m = 0, off_m2 = 0, off_u = 0, off_e = 0, off_acc = 0,
+         bytes = 0;
+  size_t arena_bytes = 0;        // descriptor bytes of the whole pass (upper bound)
 };
+
+constexpr int MAX_PAIR_BLOCKS = 32;
+
+size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Layout of one fragment batch in its workspace:
 //   C_all [N_k][n_orb][ncol] c128          coefficients of all fragments
 //   Tf    [N_k][ncol][N_IP] c128           T^k_{Ip} = sum_mu X C, then psi(r_I + R)
-//   M     [ptot][nh][ld_ip] (format)       R^q_{I,pq} for one q of each class {q, -q},
-//                                          rows = pairs of all fragments
-//   U     [ptot][nh][ld_ip] (format)       U^q = R^q W^q (also stages host C first)
+//   psi32 [N_k][ncol][N_IP] complex FP32   psi for the register pair transform
+//                                          (blocked batches; otherwise staged in U)
+//   M     [rows][nh][ld_ip] (format)       R^q_{I,pq} for one q of each class {q, -q},
+//                                          rows = pairs of all fragments (or of block i)
+//   M2    [pb][nh][ld_ip] (format)         R^q of column block j (blocked batches)
+//   U     [rows][nh][ld_ip] (format)       U^q = R^q W^q (also stages host C first)
 //   E     host-bound ERI outputs (c128)
 //   acc   FP64 G_f[(pq)][(sr)] of every fragment
-BatchPlan plan_batch(isdf_ctx c, const std::vector<FragIn>& fr, int prec) {
+// nb == 1: every fragment unblocked; nb > 1: one fragment, pairs in nb blocks.
+BatchPlan plan_batch(isdf_ctx c, const std::vector<FragIn>& fr, int prec, int nb) {
   BatchPlan p;
-  long long ecount = 0;
+  long long ecount = 0, acount = 0;
   for (const FragIn& f : fr) {
     p.col.push_back(p.ncol);
     p.nf.push_back(f.nf);
     p.poff.push_back(p.ptot);
     p.ncol += f.nf;
     p.ptot += (long long)f.nf * f.nf;
-    long long e4 = (long long)f.nf * f.nf * f.nf * f.nf;
+    const long long e4 = (long long)f.nf * f.nf * f.nf * f.nf;
     p.eoff.push_back((f.flags & ISDF_FRAG_DEVICE) ? -1 : ecount);
     if (!(f.flags & ISDF_FRAG_DEVICE)) ecount += e4;
-  }
-  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-  const size_t mb = (size_t)c->nh * p.ptot * c->ld_ip * fmt_bytes(prec);
-  size_t off = 0;
-  p.off_c = off; off += al((size_t)c->nk * c->norb * p.ncol * sizeof(cplx));
-  p.off_tf = off; off += al((size_t)c->nk * c->nip * p.ncol * sizeof(cplx));
-  p.off_m = off; off += al(mb);
-  p.off_u = off;
-  off += al(std::max<size_t>(mb, (size_t)c->nk * c->norb * p.ncol * sizeof(cplx)));
-  p.off_e = off; off += al((size_t)ecount * sizeof(cplx));
-  // FP64 matrices G_f[(pq)][(sr)] (the mixed precisions accumulate them over
-  // q groups), turned into the ERIs by the scatter
-  long long acount = 0;
-  for (const FragIn& f : fr) {
     p.aoff.push_back(acount);
-    acount += (long long)f.nf * f.nf * f.nf * f.nf;
+    acount += e4;
   }
-  p.off_acc = off; off += al((size_t)acount * sizeof(cplx));
+  p.nb = std::max(1, nb);
+  p.pb = (p.ptot + p.nb - 1) / p.nb;
+  p.psi32 = prec != 0 && pair_reg_supported(prec, c->m[0], c->m[1], c->m[2]);
+  const size_t row = (size_t)c->nh * c->ld_ip * fmt_bytes(prec);   // one pair row of R^q / U^q
+  const size_t rows = p.nb == 1 ? (size_t)p.ptot : (size_t)p.pb;
+  const size_t cstage = (size_t)c->nk * c->norb * p.ncol * sizeof(cplx);
+  const size_t psi32b = (size_t)c->nk * p.ncol * c->nip * sizeof(float2);
+  size_t off = 0;
+  p.off_c = off; off += al256(cstage);
+  p.off_tf = off; off += al256((size_t)c->nk * c->nip * p.ncol * sizeof(cplx));
+  if (p.nb > 1 && p.psi32) { p.off_psi = off; off += al256(psi32b); }
+  p.off_m = off; off += al256(rows * row);
+  if (p.nb > 1) { p.off_m2 = off; off += al256(rows * row); }
+  p.off_u = off;
+  if (p.nb == 1 || !p.psi32) p.off_psi = off;   // psi32 staged in U until U^q is formed
+  off += al256(std::max(rows * row, std::max(cstage, p.psi32 && p.nb == 1 ? psi32b : (size_t)0)));
+  p.off_e = off; off += al256((size_t)ecount * sizeof(cplx));
+  p.off_acc = off; off += al256((size_t)acount * sizeof(cplx));
   p.bytes = off;
+  // descriptor arena: per-fragment tables, the pair blocks of every pair
+  // transform table set (one per pair block), the GEMM descriptors (one per
+  // fragment, or one per block pair), 256 bytes of alignment per put
+  const size_t nfr = fr.size();
+  const size_t ntab = (size_t)p.nb;
+  const size_t nblk_pairs = (size_t)p.ptot + ntab * nfr;          // PairBlocks at tp = 1 (upper bound)
+  p.arena_bytes = 256 * (size_t)(64 + 16 * ntab) + nblk_pairs * sizeof(PairBlock) +
+                  ntab * (nfr * 48 + 64) + (nfr + 8) * 64 +
+                  ((size_t)p.nb * (p.nb + 1) / 2 + nfr + 8) * (sizeof(NtDesc) + 256) + 4 * sizeof(GemmDesc);
   return p;
 }
 
-size_t request_bytes(isdf_ctx c, int nf, bool host_out, int prec) {
-  size_t b = ((size_t)c->nk * c->norb * nf + (size_t)c->nk * c->nip * nf) * sizeof(cplx) +
-             2 * (size_t)c->nh * c->ld_ip * nf * nf * fmt_bytes(prec);
-  if (host_out) b += (size_t)nf * nf * nf * nf * sizeof(cplx);
-  b += (size_t)nf * nf * nf * nf * sizeof(cplx);
-  return b + 6 * 256;
+// Device bytes of one fragment batch's workspace (no allocation).
+size_t batch_bytes(isdf_ctx c, const std::vector<FragIn>& fr, int prec, int nb) {
+  return plan_batch(c, fr, prec, nb).bytes;
 }
 
-// Enqueue the whole fragment pipeline of one batch on ws.stream.
-void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn>& fr,
-                   bool timed) {
+// Smallest pair-block count (1 = unblocked) whose workspace for the single
+// fragment `f` fits `cap` bytes, or 0 if none up to MAX_PAIR_BLOCKS does.
+int blocks_for(isdf_ctx c, const FragIn& f, int prec, size_t cap) {
+  std::vector<FragIn> one(1, f);
+  const long long np = (long long)f.nf * f.nf;
+  for (int nb = 1; nb <= MAX_PAIR_BLOCKS && nb <= np; ++nb)
+    if (batch_bytes(c, one, prec, nb) <= cap) return nb;
+  return 0;
+}
+
+// Workspace bytes a request needs at least (at the largest pair blocking).
+size_t request_bytes(isdf_ctx c, int nf, bool host_out, int prec) {
+  FragIn f{nf, nullptr, nullptr, host_out ? 0u : (uint32_t)ISDF_FRAG_DEVICE};
+  std::vector<FragIn> one(1, f);
+  const long long np = (long long)nf * nf;
+  return batch_bytes(c, one, prec, (int)std::min<long long>(MAX_PAIR_BLOCKS, np));
+}
+
+// Device tables of one pair transform over pair range [p0, p0 + np) of each
+// fragment of the batch (np = all pairs when the batch is unblocked).
+struct PairTables {
+  const PairBlock* blocks = nullptr;
+  const long long* item_off = nullptr;
+  const long long* frag_pair = nullptr;
+  const int* frag_p0 = nullptr;
+  const int* frag_np = nullptr;
+  int nblocks = 0;
+  long long nitems = 0;
+};
+
+// Enqueue the whole fragment pipeline of one batch on ws.stream.  capture:
+// the stream is being captured into a graph (no synchronisation; the
+// workspace and arena were sized by an eager pass).
+void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn>& fr, bool timed,
+                   int nb = 1, bool capture = false) {
   if (!c->kernel_ready) throw Fail{ISDF_E_STATE, "isdf_coulomb_kernel must run before fragment ERIs"};
+  if (nb > 1 && fr.size() != 1) throw Fail{ISDF_E_INVALID, "pair blocking applies to one fragment"};
   hipStream_t s = ws.stream;
   WgScope wg(c->frag_wg_per_cu);
   const int nk = c->nk, norb = c->norb, nip = c->nip;
   const long long ld = c->ld_ip;
-  BatchPlan p = plan_batch(c, fr, prec);
-  ws.mem.ensure(p.bytes);
-  ws.arena.reset();
+  BatchPlan p = plan_batch(c, fr, prec, nb);
+  if (!capture) {
+    ws.arena.reset(s);
+    ws.arena.reserve(p.arena_bytes);
+    ws.mem.ensure(p.bytes);
+  } else {
+    if (p.bytes > ws.mem.bytes) throw Fail{ISDF_E_INVALID, "captured batch larger than its workspace"};
+    ws.arena.used = 0;
+  }
   char* base = ws.mem.as<char>();
   cplx* Call = (cplx*)(base + p.off_c);
   cplx* Tf = (cplx*)(base + p.off_tf);
   char* Mq = base + p.off_m;
+  char* Mq2 = base + p.off_m2;
   char* Uq = base + p.off_u;
+  float2* psi32 = (float2*)(base + p.off_psi);
   cplx* Est = (cplx*)(base + p.off_e);
+  cplx* acc = (cplx*)(base + p.off_acc);
   // upload / gather the fragment coefficients into C_all[k][mu][col]
   size_t host_bytes = 0;
   for (const FragIn& f : fr)
@@ -897,7 +1003,6 @@ void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn
   HIPCHK(copy_cols_batch_launch(ws.arena.put(srcs.data(), srcs.size(), s), Call, nk, norb,
                                 ws.arena.put(p.nf.data(), p.nf.size(), s),
                                 ws.arena.put(p.col.data(), p.col.size(), s), (int)fr.size(), maxnf, p.ncol, s));
-  const bool psi32 = prec != 0 && pair_reg_supported(prec, c->m[0], c->m[1], c->m[2]);
   if (timed) ws.timer.begin("frag_t", s);
   // T^k_{pI} = sum_mu C^k_{mu p} X^k_{I mu}   (Algorithm 2, stored [k][p][I])
   {
@@ -923,40 +1028,69 @@ void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn
     a.sign = +1;
     a.scale = 1.0 / std::sqrt((double)nk);
     // the register pair transform of the mixed precisions reads psi as
-    // complex FP32, staged in the U region (free until U^q is formed)
-    if (psi32) a.out32 = (float2*)Uq;
+    // complex FP32 (in the U region while it is free, or its own region)
+    if (p.psi32) a.out32 = psi32;
     HIPCHK(kconv_launch(a, s));
   }
   if (timed) ws.timer.end("frag_t", s);
+  const int nh = c->nh;
+  const long long rows = p.nb == 1 ? p.ptot : p.pb;            // pair rows of the M / U regions
+  const long long mplane = (long long)nh * rows * ld;
+  // pair-transform tile: ti interpolation points x tp pairs, nk * tp * ti <= 4096 (64 KB)
+  int ti = 32;
+  while (ti > 1 && (long long)nk * ti > 4096) ti >>= 1;
+  int tp = 1;   // power of two (the LDS transform needs tp * ti to be one)
+  while (tp < 8 && (long long)nk * ti * tp * 2 <= 4096) tp *= 2;
+  const bool reg = pair_reg_supported(prec, c->m[0], c->m[1], c->m[2]);
+  const long long nchunk = (ld + 63) / 64;
+  // tables of the pair transform over pairs [pbeg, pbeg + pcnt) of every
+  // fragment (unblocked: all pairs, output rows at the fragment's pair offset;
+  // blocked: the block's pairs, output rows from 0)
+  auto make_tables = [&](long long pbeg, long long pcnt) {
+    PairTables t;
+    std::vector<PairBlock> blocks;
+    std::vector<long long> fpair(fr.size());
+    std::vector<int> fp0(fr.size()), fnp(fr.size());
+    std::vector<long long> ioff(fr.size() + 1, 0);
+    for (size_t f = 0; f < fr.size(); ++f) {
+      const long long np = p.nb == 1 ? (long long)p.nf[f] * p.nf[f] : pcnt;
+      const long long b0 = p.nb == 1 ? 0 : pbeg;
+      fp0[f] = (int)b0;
+      fnp[f] = (int)np;
+      fpair[f] = p.nb == 1 ? p.poff[f] : -b0;
+      for (long long q0 = 0; q0 < np; q0 += tp)
+        blocks.push_back(PairBlock{(int)f, (int)(b0 + q0), (int)std::min<long long>(tp, np - q0)});
+      ioff[f + 1] = ioff[f] + nchunk * np;
+    }
+    t.nblocks = (int)blocks.size();
+    t.blocks = ws.arena.put(blocks.data(), blocks.size(), s);
+    t.frag_pair = ws.arena.put(fpair.data(), fpair.size(), s);
+    t.frag_p0 = ws.arena.put(fp0.data(), fp0.size(), s);
+    t.frag_np = ws.arena.put(fnp.data(), fnp.size(), s);
+    t.item_off = ws.arena.put(ioff.data(), ioff.size(), s);
+    t.nitems = ioff.back();
+    return t;
+  };
+  const int* d_nf = ws.arena.put(p.nf.data(), p.nf.size(), s);
+  const int* d_col = ws.arena.put(p.col.data(), p.col.size(), s);
   // R^q_{I,pq} = N_k^{-1/2} sum_R exp(-iq.R) conj(psi_p) psi_q   (eq. (20)),
   // in the GEMM operand format of the precision, pair-major: row (pair) holds
   // the nh blocks of ld columns (class of q, I), so that the contraction over
   // (q, J) of every fragment reads one contiguous K range per row.  Only one
   // q of each class {q, -q} is kept: R^{-q}_{pq} = conj(R^q_{qp}).
-  if (timed) ws.timer.begin("frag_pair", s);
-  const int nh = c->nh;
-  const long long mplane = (long long)nh * p.ptot * ld;
-  {
-    // tile: ti interpolation points x tp pairs, nk * tp * ti <= 4096 (64 KB)
-    int ti = 32;
-    while (ti > 1 && (long long)nk * ti > 4096) ti >>= 1;
-    int tp = 1;   // power of two (the LDS transform needs tp * ti to be one)
-    while (tp < 8 && (long long)nk * ti * tp * 2 <= 4096) tp *= 2;
-    std::vector<PairBlock> blocks;
-    for (size_t f = 0; f < fr.size(); ++f) {
-      const int np = p.nf[f] * p.nf[f];
-      for (int p0 = 0; p0 < np; p0 += tp) blocks.push_back(PairBlock{(int)f, p0, std::min(tp, np - p0)});
-    }
+  auto pair_transform = [&](const PairTables& t, char* out) {
     PairArgs a;
     memset(&a, 0, sizeof(a));
     a.psi = Tf;
-    a.psi32 = psi32 ? (const float2*)Uq : nullptr;
-    a.out = Mq;
-    a.blocks = ws.arena.put(blocks.data(), blocks.size(), s);
-    a.frag_nf = ws.arena.put(p.nf.data(), p.nf.size(), s);
-    a.frag_col = ws.arena.put(p.col.data(), p.col.size(), s);
-    a.frag_pair = ws.arena.put(p.poff.data(), p.poff.size(), s);
-    a.nblocks = (int)blocks.size();
+    a.psi32 = p.psi32 ? psi32 : nullptr;
+    a.out = out;
+    a.blocks = t.blocks;
+    a.frag_nf = d_nf;
+    a.frag_col = d_col;
+    a.frag_pair = t.frag_pair;
+    a.frag_p0 = t.frag_p0;
+    a.frag_np = t.frag_np;
+    a.nblocks = t.nblocks;
     a.n_ip = nip;
     a.ncol = p.ncol;
     a.tp = tp;
@@ -970,24 +1104,18 @@ void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn
     a.fmt = prec;
     a.m1 = c->m[0]; a.m2 = c->m[1]; a.m3 = c->m[2];
     a.scale = 1.0 / std::sqrt((double)nk);
-    if (pair_reg_supported(prec, a.m1, a.m2, a.m3)) {
-      // register path: items (fragment, 64-point I chunk, pair)
-      const long long nchunk = (ld + 63) / 64;
-      std::vector<long long> ioff(fr.size() + 1, 0);
-      for (size_t f = 0; f < fr.size(); ++f) ioff[f + 1] = ioff[f] + nchunk * p.nf[f] * p.nf[f];
-      a.item_off = ws.arena.put(ioff.data(), ioff.size(), s);
+    if (reg) {
+      a.item_off = t.item_off;
       a.nfrag = (int)fr.size();
-      a.nitems = ioff.back();
+      a.nitems = t.nitems;
     }
     HIPCHK(pair_launch(a, s));
-  }
-  if (timed) ws.timer.end("frag_pair", s);
+  };
   // U^q_{P,J} = sum_I R^q_{P,I} W^q_{IJ}   (eq. (19), first contraction)
-  if (timed) ws.timer.begin("frag_u", s);
-  {
+  auto u_gemm = [&](const char* m, long long nrows) {
     const void* wt = prec == 0 ? c->wt64.p : (prec == 1 ? c->wt32.p : c->wt16.p);
     std::vector<NtDesc> d(1);
-    d[0] = mknt(Mq, (long long)nh * ld, wt, ld, Uq, (long long)nh * ld, (int)p.ptot, nip, nip);
+    d[0] = mknt(m, (long long)nh * ld, wt, ld, Uq, (long long)nh * ld, (int)nrows, nip, nip);
     d[0].batch = nh;
     d[0].a_plane = mplane;
     d[0].b_plane = (long long)nh * nip * ld;
@@ -998,64 +1126,107 @@ void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn
     d[0].npad = (int)ld;
     if (prec == 0) run_nt(ws.arena, prec, 0, d, s, 2);
     else run_big(ws.arena, prec, 0, d, 1, s, 2);
-  }
-  if (timed) ws.timer.end("frag_u", s);
+  };
   // (pq|rs) = sum_q sum_J U^q_{(pq),J} conj(R^q_{(sr),J})  (eq. (19), R^{-q}_{rs} = conj R^q_{sr}).
   // The term of -q is the conjugate of that of q with (pq) -> (qp) and
   // (sr) -> (rs) (R^{-q}_{pq} = conj R^q_{qp}, W^{-q} = conj W^q), so the
   // contraction runs over one q per class {q, -q} (weight 1/2 where q = -q,
   // folded into W):  G_f[(pq)][(sr)] = sum_{h, J} U^h_{(pq),J} conj(R^h_{(sr),J})
-  // in FP64 (lower tiles; one grouped persistent launch over all fragments),
-  // then (pq|rs) = G[(pq)][(sr)] + conj(G[(qp)][(rs)]) by the scatter.  FP64
-  // path: FP64 sum over the classes inside the kernel; mixed: one launch per
-  // group of classes (one contiguous K range per row, FP32 sums inside),
-  // FP64 sum over the groups.
-  if (timed) ws.timer.begin("frag_eri", s);
-  {
+  // in FP64 (lower triangle; one grouped persistent launch over all
+  // fragments, or one per block pair), then (pq|rs) = G[(pq)][(sr)] +
+  // conj(G[(qp)][(rs)]) by the scatter.  FP64 path: FP64 sum over the
+  // classes inside the kernel; mixed: one launch per group of classes (one
+  // contiguous K range per row, FP32 sums inside), FP64 sum over the groups.
+  const size_t sc = fmt_scalar(prec);
+  const int ngroup = (nh + c->eri_qgroup - 1) / c->eri_qgroup;
+  const int qgroup = (nh + ngroup - 1) / ngroup;       // balanced groups
+  auto eri_desc = [&](const void* A, const void* B, cplx* C, long long ldc, int M, int N, int herm) {
+    NtDesc g = mknt(A, (long long)nh * ld, B, (long long)nh * ld, C, ldc, M, N, nip);
+    g.a_plane = g.b_plane = mplane;
+    g.herm = herm;
+    if (prec == 0) {
+      g.nseg = nh;
+      g.sA_seg = g.sB_seg = ld;
+      g.epi = 0;
+    } else {
+      g.Kseg = (int)(qgroup * ld);
+      g.nseg = (nh + qgroup - 1) / qgroup;
+      g.Klast = (int)((nh - (long long)(g.nseg - 1) * qgroup) * ld);
+      g.sA_seg = g.sB_seg = qgroup * ld;
+      g.epi = 1;
+    }
+    return g;
+  };
+  // the GEMM launches alone, timed as "frag_eri_kernel" (one interval per launch)
+  LaunchMark mark = nullptr;
+  if (timed)
+    mark = [&](bool on) {
+      if (on) ws.timer.begin("frag_eri_kernel", s);
+      else ws.timer.end("frag_eri_kernel", s);
+    };
+  auto eri_gemm = [&](std::vector<NtDesc>& d) {
+    if (prec == 0) run_nt(ws.arena, prec, 2, d, s, 3, mark);
+    else run_big(ws.arena, prec, 2, d, d[0].nseg, s, 3, mark);
+  };
+  if (p.nb == 1) {
+    if (timed) ws.timer.begin("frag_pair", s);
+    pair_transform(make_tables(0, 0), Mq);
+    if (timed) ws.timer.end("frag_pair", s);
+    if (timed) ws.timer.begin("frag_u", s);
+    u_gemm(Mq, p.ptot);
+    if (timed) ws.timer.end("frag_u", s);
+    if (timed) ws.timer.begin("frag_eri", s);
     std::vector<NtDesc> d;
-    const size_t sc = fmt_scalar(prec);
-    const int ngroup = (nh + c->eri_qgroup - 1) / c->eri_qgroup;
-    const int qgroup = (nh + ngroup - 1) / ngroup;       // balanced groups
-    cplx* acc = (cplx*)(base + p.off_acc);
     for (size_t f = 0; f < fr.size(); ++f) {
       const int nf2 = p.nf[f] * p.nf[f];
       const size_t o = (size_t)p.poff[f] * nh * ld * sc;
-      NtDesc g = mknt(Uq + o, (long long)nh * ld, Mq + o, (long long)nh * ld, acc + p.aoff[f], nf2, nf2, nf2, nip);
-      g.a_plane = g.b_plane = mplane;
-      g.herm = 2;
-      if (prec == 0) {
-        g.nseg = nh;
-        g.sA_seg = g.sB_seg = ld;
-        g.epi = 0;
-      } else {
-        g.Kseg = (int)(qgroup * ld);
-        g.nseg = (nh + qgroup - 1) / qgroup;
-        g.Klast = (int)((nh - (long long)(g.nseg - 1) * qgroup) * ld);
-        g.sA_seg = g.sB_seg = qgroup * ld;
-        g.epi = 1;
-      }
-      d.push_back(g);
+      d.push_back(eri_desc(Uq + o, Mq + o, acc + p.aoff[f], nf2, nf2, nf2, 2));
     }
     // largest fragments first so the persistent launch ends balanced
     std::stable_sort(d.begin(), d.end(), [](const NtDesc& a, const NtDesc& b) { return a.M > b.M; });
-    // the GEMM launches alone, timed as "frag_eri_kernel" (one interval per launch)
-    LaunchMark mark = nullptr;
-    if (timed)
-      mark = [&](bool on) {
-        if (on) ws.timer.begin("frag_eri_kernel", s);
-        else ws.timer.end("frag_eri_kernel", s);
-      };
-    if (prec == 0) run_nt(ws.arena, prec, 2, d, s, 3, mark);
-    else run_big(ws.arena, prec, 2, d, d[0].nseg, s, 3, mark);
-    std::vector<cplx*> outs(fr.size());
-    int maxnf = 0;
-    for (size_t f = 0; f < fr.size(); ++f) {
-      outs[f] = (fr[f].flags & ISDF_FRAG_DEVICE) ? (cplx*)fr[f].eri : Est + p.eoff[f];
-      maxnf = std::max(maxnf, p.nf[f]);
+    eri_gemm(d);
+  } else {
+    // (pq)-blocked fragment (eqs. (19)-(20) over pair blocks): for row block
+    // i, R^q_i and U^q_i = R^q_i W^q; for every column block j <= i, R^q_j
+    // (recomputed into the second R region unless j == i) and the block
+    // G[B_i][B_j] = U_i R_j^H (the lower tiles where j == i)
+    const long long nf2 = (long long)p.nf[0] * p.nf[0];
+    std::vector<PairTables> tabs(p.nb);
+    for (int b = 0; b < p.nb; ++b) {
+      const long long b0 = (long long)b * p.pb;
+      tabs[b] = make_tables(b0, std::min<long long>(p.pb, nf2 - b0));
     }
+    for (int i = 0; i < p.nb; ++i) {
+      const long long i0 = (long long)i * p.pb, ni = std::min<long long>(p.pb, nf2 - i0);
+      if (timed) ws.timer.begin("frag_pair", s);
+      pair_transform(tabs[i], Mq);
+      if (timed) ws.timer.end("frag_pair", s);
+      if (timed) ws.timer.begin("frag_u", s);
+      u_gemm(Mq, ni);
+      if (timed) ws.timer.end("frag_u", s);
+      for (int j = 0; j <= i; ++j) {
+        const long long j0 = (long long)j * p.pb, nj = std::min<long long>(p.pb, nf2 - j0);
+        const char* rj = Mq;
+        if (j != i) {
+          if (timed) ws.timer.begin("frag_pair", s);
+          pair_transform(tabs[j], Mq2);
+          if (timed) ws.timer.end("frag_pair", s);
+          rj = Mq2;
+        }
+        if (timed) ws.timer.begin("frag_eri", s);
+        std::vector<NtDesc> d(1, eri_desc(Uq, rj, acc + i0 * nf2 + j0, nf2, (int)ni, (int)nj, j == i ? 2 : 0));
+        eri_gemm(d);
+        if (timed) ws.timer.end("frag_eri", s);
+      }
+    }
+    if (timed) ws.timer.begin("frag_eri", s);
+  }
+  {
+    std::vector<cplx*> outs(fr.size());
+    for (size_t f = 0; f < fr.size(); ++f)
+      outs[f] = (fr[f].flags & ISDF_FRAG_DEVICE) ? (cplx*)fr[f].eri : Est + p.eoff[f];
     HIPCHK(eri_scatter_batch_launch(acc, ws.arena.put(p.aoff.data(), p.aoff.size(), s),
-                                    ws.arena.put(outs.data(), outs.size(), s),
-                                    ws.arena.put(p.nf.data(), p.nf.size(), s), (int)fr.size(), maxnf, s));
+                                    ws.arena.put(outs.data(), outs.size(), s), d_nf, (int)fr.size(), maxnf, s));
   }
   if (timed) ws.timer.end("frag_eri", s);
   for (size_t f = 0; f < fr.size(); ++f) {
@@ -1065,9 +1236,67 @@ void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn
   }
 }
 
+// Memory a synchronous fragment call may use: what is free on the device
+// plus what the workspace already holds, less a margin.
+size_t sync_cap(const Workspace& ws) {
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+    (void)hipGetLastError();
+    return ws.mem.bytes;
+  }
+  const size_t avail = fr + ws.mem.bytes;
+  const size_t margin = std::max<size_t>((size_t)1 << 28, avail / 16);
+  return avail > margin ? avail - margin : 0;
+}
+
+// Run a list of fragments on ws within `cap` bytes of workspace: greedy
+// sub-batches of consecutive fragments whose unblocked workspace fits, and a
+// fragment that does not fit alone runs (pq)-blocked.  Sub-batches after the
+// first wait for the previous one (the workspace is reused).
+void enqueue_fragments(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn>& fr, bool timed,
+                       size_t cap) {
+  size_t i = 0;
+  while (i < fr.size()) {
+    std::vector<FragIn> sub(1, fr[i]);
+    const int nb = blocks_for(c, fr[i], prec, cap);
+    if (nb == 0)
+      throw Fail{ISDF_E_NOMEM, "fragment of " + std::to_string(fr[i].nf) + " orbitals does not fit the " +
+                                   std::to_string(cap >> 20) + " MiB workspace even in " +
+                                   std::to_string(MAX_PAIR_BLOCKS) + " pair blocks"};
+    size_t j = i + 1;
+    if (nb == 1)
+      while (j < fr.size()) {
+        sub.push_back(fr[j]);
+        if (batch_bytes(c, sub, prec, 1) > cap) {
+          sub.pop_back();
+          break;
+        }
+        ++j;
+      }
+    enqueue_batch(c, ws, prec, sub, timed, nb);
+    i = j;
+  }
+}
+
+// Checks that every C[f] and eri[f] is device memory (callers that hand the
+// pointers to kernels without staging).
+void require_device(const void* const* C, void* const* eri, int n) {
+  for (int f = 0; f < n; ++f) {
+    hipPointerAttribute_t a1, a2;
+    if (hipPointerGetAttributes(&a1, C[f]) != hipSuccess || hipPointerGetAttributes(&a2, eri[f]) != hipSuccess ||
+        a1.type != hipMemoryTypeDevice || a2.type != hipMemoryTypeDevice) {
+      (void)hipGetLastError();
+      throw Fail{ISDF_E_INVALID, "fragment " + std::to_string(f) + " needs device pointers for C and eri"};
+    }
+  }
+}
+
 // --------------------------------------------------------------------------
 // serving thread
 // --------------------------------------------------------------------------
+// Workspace bytes of one served batch.
+long long serve_cap(isdf_ctx c) { return c->budget / c->max_inflight; }
+
 void serve_loop(isdf_ctx c) {
   std::vector<Workspace*> inflight;
   while (true) {
@@ -1105,8 +1334,12 @@ void serve_loop(isdf_ctx c) {
     {
       std::unique_lock<std::mutex> lk(c->mu);
       if (c->stop && c->queue.empty() && inflight.empty()) break;
-      if (!c->ws_pool.empty() && !c->queue.empty()) {
-        const long long cap = c->budget / c->max_inflight;
+      // nothing is admitted while a synchronous call holds the context
+      // (isdf_fit, isdf_coulomb_kernel, isdf_autotune, isdf_set_tiling)
+      if (!c->exclusive && !c->ws_pool.empty() && !c->queue.empty()) {
+        // a batch's fragments fit the per-batch budget unblocked together
+        // (the sum of their single-fragment workspaces bounds the batch's);
+        // a request that fits only (pq)-blocked runs alone
         long long used = 0;
         while (!c->queue.empty() && (int)fr.size() < c->max_batch) {
           uint64_t tk = c->queue.front();
@@ -1117,18 +1350,21 @@ void serve_loop(isdf_ctx c) {
           }
           const isdf_request& r = it->second.req;
           if (!fr.empty() && r.prec != prec) break;
-          long long b = (long long)request_bytes(c, r.n_f, !(r.flags & ISDF_FRAG_DEVICE), r.prec);
-          if (!fr.empty() && used + b > cap) break;
+          const FragIn fi{r.n_f, r.C, r.eri, r.flags};
+          const long long b = (long long)batch_bytes(c, std::vector<FragIn>(1, fi), r.prec, 1);
+          if (!fr.empty() && used + b > serve_cap(c)) break;
           if (fr.empty()) prec = r.prec;
           used += b;
-          fr.push_back(FragIn{r.n_f, r.C, r.eri, r.flags});
+          fr.push_back(fi);
           tks.push_back(tk);
           it->second.state = ISDF_REQ_RUNNING;
           c->queue.pop_front();
+          if (b > serve_cap(c)) break;          // blocked: alone in its batch
         }
         if (!fr.empty()) {
           ws = c->ws_pool.back();
           c->ws_pool.pop_back();
+          ++c->inflight_n;                      // in flight from the moment its requests left the queue
         }
       } else if (inflight.empty()) {
         c->cv.wait_for(lk, std::chrono::microseconds(200));
@@ -1137,16 +1373,17 @@ void serve_loop(isdf_ctx c) {
     }
     if (ws) {
       try {
-        enqueue_batch(c, *ws, prec, fr, true);
+        enqueue_fragments(c, *ws, prec, fr, true, (size_t)serve_cap(c));
         HIPCHK(hipEventRecord(ws->done, ws->stream));
         ws->tickets = tks;
         inflight.push_back(ws);
         std::lock_guard<std::mutex> lk(c->mu);
         ++c->batches;
-        ++c->inflight_n;
       } catch (const Fail& e) {
         (void)hipStreamSynchronize(ws->stream);
         std::lock_guard<std::mutex> lk(c->mu);
+        --c->inflight_n;
+        c->cv.notify_all();
         for (uint64_t tk : tks) {
           auto& r = c->reqs[tk];
           r.state = ISDF_REQ_FAILED;
@@ -1366,7 +1603,7 @@ isdf_status isdf_create(isdf_ctx* out, const double* lattice, const int32_t grid
 isdf_status isdf_fit(isdf_ctx ctx, isdf_precision prec) {
   return guarded(ctx, [&] {
     if (prec < ISDF_FP64 || prec > ISDF_MIXED_BF16X3) throw Fail{ISDF_E_INVALID, "bad precision"};
-    if (!serve_idle(ctx)) throw Fail{ISDF_E_BUSY, "requests are queued or running"};
+    Exclusive ex(ctx, true);
     do_fit(ctx, prec);
   });
 }
@@ -1379,7 +1616,9 @@ int32_t isdf_fit_eta_fp32(const int32_t grid[3]) {
 isdf_status isdf_coulomb_kernel(isdf_ctx ctx, isdf_precision prec) {
   return guarded(ctx, [&] {
     if (prec < ISDF_FP64 || prec > ISDF_MIXED_BF16X3) throw Fail{ISDF_E_INVALID, "bad precision"};
-    if (!serve_idle(ctx)) throw Fail{ISDF_E_BUSY, "requests are queued or running"};
+    if (!ctx->fitted || !ctx->kernel_pending)
+      throw Fail{ISDF_E_STATE, "isdf_fit must run before isdf_coulomb_kernel"};
+    Exclusive ex(ctx, true);
     do_kernel(ctx, prec);
   });
 }
@@ -1560,7 +1799,7 @@ isdf_status isdf_fragment_eri(isdf_ctx ctx, isdf_precision prec, int32_t n_frag,
         throw Fail{ISDF_E_INVALID, "bad fragment " + std::to_string(f)};
       fr.push_back(FragIn{n_f[f], C[f], eri[f], flags});
     }
-    enqueue_batch(ctx, ctx->sync_ws, prec, fr, true);
+    enqueue_fragments(ctx, ctx->sync_ws, prec, fr, true, sync_cap(ctx->sync_ws));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     std::lock_guard<std::mutex> lk(ctx->mu);
     ctx->sync_ws.timer.collect(&ctx->totals);
@@ -1593,14 +1832,9 @@ isdf_status isdf_graph_create(isdf_ctx ctx, isdf_precision prec, int32_t n_frag,
     for (int f = 0; f < n_frag; ++f) {
       if (n_f[f] < 1 || n_f[f] > ctx->nk * ctx->norb || !C[f] || !eri[f])
         throw Fail{ISDF_E_INVALID, "bad fragment " + std::to_string(f)};
-      hipPointerAttribute_t a1, a2;
-      if (hipPointerGetAttributes(&a1, C[f]) != hipSuccess || hipPointerGetAttributes(&a2, eri[f]) != hipSuccess ||
-          a1.type != hipMemoryTypeDevice || a2.type != hipMemoryTypeDevice) {
-        (void)hipGetLastError();
-        throw Fail{ISDF_E_INVALID, "graph fragments need device pointers (fragment " + std::to_string(f) + ")"};
-      }
       fr.push_back(FragIn{n_f[f], C[f], eri[f], ISDF_FRAG_DEVICE});
     }
+    require_device(C, eri, n_frag);
     std::unique_ptr<isdf_graph_s> g(new isdf_graph_s());
     g->ctx = ctx;
     HIPCHK(hipStreamCreateWithFlags(&g->ws.stream, hipStreamNonBlocking));
@@ -1614,7 +1848,7 @@ isdf_status isdf_graph_create(isdf_ctx ctx, isdf_precision prec, int32_t n_frag,
     HIPCHK(hipStreamSynchronize(g->ws.stream));
     HIPCHK(hipStreamBeginCapture(g->ws.stream, hipStreamCaptureModeThreadLocal));
     try {
-      enqueue_batch(ctx, g->ws, prec, fr, false);
+      enqueue_batch(ctx, g->ws, prec, fr, false, 1, true);
     } catch (...) {
       hipGraph_t part = nullptr;
       (void)hipStreamEndCapture(g->ws.stream, &part);
@@ -1647,7 +1881,7 @@ isdf_status isdf_graph_destroy(isdf_graph g) {
 isdf_status isdf_set_tiling(isdf_ctx ctx, int32_t eri_qgroup, int32_t wg_per_cu) {
   return guarded(ctx, [&] {
     if (eri_qgroup < 1 || wg_per_cu < 0 || wg_per_cu > 8) throw Fail{ISDF_E_INVALID, "bad tiling"};
-    if (!serve_idle(ctx)) throw Fail{ISDF_E_BUSY, "requests are queued or running"};
+    Exclusive ex(ctx, false);
     ctx->eri_qgroup = eri_qgroup;
     ctx->frag_wg_per_cu = wg_per_cu;
   });
@@ -1659,13 +1893,15 @@ isdf_status isdf_autotune(isdf_ctx ctx, isdf_precision prec, int32_t n_frag, con
     if (n_frag < 1 || !n_f || !C || !eri) throw Fail{ISDF_E_INVALID, "bad fragment arguments"};
     if (prec < ISDF_FP64 || prec > ISDF_MIXED_BF16X3) throw Fail{ISDF_E_INVALID, "bad precision"};
     if (!ctx->kernel_ready) throw Fail{ISDF_E_STATE, "isdf_coulomb_kernel must run before fragment ERIs"};
-    if (!serve_idle(ctx)) throw Fail{ISDF_E_BUSY, "requests are queued or running"};
     std::vector<FragIn> fr;
     for (int f = 0; f < n_frag; ++f) {
       if (n_f[f] < 1 || n_f[f] > ctx->nk * ctx->norb || !C[f] || !eri[f])
         throw Fail{ISDF_E_INVALID, "bad fragment " + std::to_string(f)};
       fr.push_back(FragIn{n_f[f], C[f], eri[f], ISDF_FRAG_DEVICE});
     }
+    // the candidates run on device pointers without staging
+    require_device(C, eri, n_frag);
+    Exclusive ex(ctx, false);
     const int nh = ctx->nh;
     // classes per launch for one, two and three launches over the classes,
     // and the initial tiling (at most ERI_QGROUP per launch)
@@ -1774,7 +2010,16 @@ isdf_status isdf_submit_n(isdf_ctx ctx, int32_t n, const isdf_request* reqs, uin
     r.req = reqs[i];
     r.t_submit = t0;
     ctx->reqs.emplace(t, r);
-    ctx->queue.push_back(t);
+    // admission order: after every queued request of the same or a higher
+    // priority (FIFO among equals)
+    auto pos = ctx->queue.end();
+    while (pos != ctx->queue.begin()) {
+      auto prev = std::prev(pos);
+      auto it = ctx->reqs.find(*prev);
+      if (it != ctx->reqs.end() && it->second.req.priority >= reqs[i].priority) break;
+      pos = prev;
+    }
+    ctx->queue.insert(pos, t);
     tickets[i] = t;
   }
   ctx->cv.notify_all();

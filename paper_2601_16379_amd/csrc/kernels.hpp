@@ -148,8 +148,13 @@ struct PairArgs {
   const int* qslot;        // device: output block of each q (rows q with qslot < 0 are not written)
   // register path (mixed precisions, mesh axes <= 4): one wave per (pair,
   // 64 interpolation points); items ordered (fragment, I chunk, pair),
-  // item_off[f] = first item of fragment f (nfrag + 1 entries, device)
+  // item_off[f] = first item of fragment f (nfrag + 1 entries, device).
+  // A fragment's pairs may be a range: pairs frag_p0[f] .. frag_p0[f] +
+  // frag_np[f] - 1 (device arrays; null = all nf^2 pairs from 0); the output
+  // row of pair P is frag_pair[f] + P in both paths.
   const long long* item_off;
+  const int* frag_p0;
+  const int* frag_np;
   int nfrag;
   long long nitems;
   int m1, m2, m3;

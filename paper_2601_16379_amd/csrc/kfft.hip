@@ -508,10 +508,11 @@ __global__ __launch_bounds__(256, 2) void pair_reg_kernel(PairArgs a, int nblock
   }
   const int f = lo;
   const int nf = a.frag_nf[f];
-  const int nf2 = nf * nf;
+  const int np = a.frag_np ? a.frag_np[f] : nf * nf;     // pairs of this fragment in the launch
+  const int pbeg = a.frag_p0 ? a.frag_p0[f] : 0;
   const long long local = item - a.item_off[f];
-  const int chunk = (int)(local / nf2);
-  const int pp = (int)(local - (long long)chunk * nf2);
+  const int chunk = (int)(local / np);
+  const int pp = pbeg + (int)(local - (long long)chunk * np);
   const int p = pp / nf, q = pp - (pp / nf) * nf;
   const int I = chunk * 64 + lane;
   const bool in = I < a.n_ip;

@@ -41,7 +41,7 @@ class IsdfError(RuntimeError):
 
 class Request(ctypes.Structure):
     _fields_ = [("n_f", ctypes.c_int32), ("C", ctypes.c_void_p), ("eri", ctypes.c_void_p),
-                ("prec", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+                ("prec", ctypes.c_int32), ("flags", ctypes.c_uint32), ("priority", ctypes.c_int32)]
 
 
 class TuneReport(ctypes.Structure):
@@ -300,18 +300,18 @@ class Isdf:
         self._check(self.lib.isdf_serve_start(self.h, max_inflight, max_batch, budget_bytes),
                     "isdf_serve_start")
 
-    def submit(self, coeffs, eri, prec="fp64"):
+    def submit(self, coeffs, eri, prec="fp64", priority=0):
         cp, cdev = _ptr(coeffs)
         ep, edev = _ptr(eri)
         if cdev != edev:
             raise ValueError("C and eri must both be host or both device")
         req = Request(int(coeffs.shape[2]), cp, ep, PRECISIONS.get(prec, prec),
-                      ISDF_FRAG_DEVICE if cdev else 0)
+                      ISDF_FRAG_DEVICE if cdev else 0, int(priority))
         t = ctypes.c_uint64()
         self._check(self.lib.isdf_submit(self.h, ctypes.byref(req), ctypes.byref(t)), "isdf_submit")
         return t.value
 
-    def submit_n(self, coeffs, eris, prec="fp64"):
+    def submit_n(self, coeffs, eris, prec="fp64", priority=0):
         """Submit several fragments at one instant; returns their tickets."""
         n = len(coeffs)
         reqs = (Request * n)()
@@ -321,7 +321,7 @@ class Isdf:
             if cdev != edev:
                 raise ValueError("C and eri must both be host or both device")
             reqs[i] = Request(int(c.shape[2]), cp, ep, PRECISIONS.get(prec, prec),
-                              ISDF_FRAG_DEVICE if cdev else 0)
+                              ISDF_FRAG_DEVICE if cdev else 0, int(priority))
         t = (ctypes.c_uint64 * n)()
         self._check(self.lib.isdf_submit_n(self.h, n, reqs, t), "isdf_submit_n")
         return list(t)
