@@ -1,18 +1,29 @@
 #!/usr/bin/env python3
 """Benchmark of the k-point ISDF hot path on one MI355X.
 
-One step = the whole path over one batch of synthetic input: the fit
-(X^k, Pi^q and eta^q as k convolutions, FP64 pivoted Cholesky), the Coulomb
-kernel W^q (grid FFT with 4 pi/|G+q|^2, V^q GEMM, FP64 solves) and the
-fragment ERIs of every fragment of the workload, submitted at one instant to
-the serving loop and collected by polling (so each fragment has a
-submit-to-done latency).  Inputs (orbitals, interpolation points, fragment
-coefficients) are resident in HBM before timing starts.
+Two kinds of workload:
 
-Prints one JSON line: fragment ERIs/s (sum of n_f^4 over fragments per
-second of wall time, fit included), p50/p99 latency, the speedup over the
-same step in FP64, the max |mixed - FP64| error per result, a roofline entry
-for the dominant kernel and the FP64 CPU oracle timed on this host.
+* the N_k = 1000 cell (10x10x10 mesh, 40^3 grid, 52 orbitals, 1040
+  interpolation points, a stream of 500 fragments of 20-120 orbitals; the
+  default) and the N_k = 216 cell: the fit and the Coulomb kernel (X^k, Pi^q
+  and eta^q as k convolutions, the FP64 pivoted Cholesky, the grid FFT with
+  4 pi/|G+q|^2, V^q and W^q) run once and are timed once; every timed step is
+  then a fixed slice of the fragment stream (consecutive fragments of the
+  seeded stream, cycling), submitted at one instant to the serving loop with
+  W^q resident and polled to completion.  After the timed steps the same
+  cell is fitted in FP64 and one slice is run in FP64: the speedup of the
+  mixed precision over the plain FP64 GPU path and the max |mixed - FP64| of
+  every result of that slice.  The N_k = 216 cell can instead be served to
+  open Poisson arrivals (--arrivals).
+* the small cells (N_k <= 64): one step is the whole path, fit + kernel + all
+  fragments of the cell.
+
+Inputs (orbitals, interpolation points, fragment coefficients) are resident
+in HBM before timing starts.  Prints one JSON line: fragment ERIs/s (sum of
+n_f^4 over the step's fragments per second of wall time), p50/p99 request
+latency, the speedup over FP64, the max error per result, a roofline entry for
+the dominant kernel and the FP64 CPU oracle timed on this host on a bounded
+sample.
 """
 import argparse
 import json
@@ -26,21 +37,26 @@ sys.path.insert(0, ROOT)
 # Peak rates of MI355X (dense; TFLOP/s and GB/s)
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "hbm": 8000.0}
 PREC_PEAK = {"fp64": ("fp64", 78.6), "fp32": ("fp32", 157.3), "bf16x3": ("bf16", 2500.0)}
+STREAM_MIN_NK = 216
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c3_k4_32")
+    ap.add_argument("--workload", default="c5_k10_40")
     ap.add_argument("--prec", default="bf16x3", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--slice", type=int, default=4,
+                    help="fragments per timed step of the large cells (a fixed slice of the stream)")
     ap.add_argument("--no-fp64-ref", action="store_true")
-    ap.add_argument("--poisson-rates", default="200,1000,4000",
-                    help="request rates (1/s) of the open-arrival serving sweep after the timed steps; '' skips it")
+    ap.add_argument("--arrivals", type=int, default=0,
+                    help="large cells: serve this many requests at the cell's Poisson rate instead of slices")
+    ap.add_argument("--poisson-rates", default=None,
+                    help="small cells: rates (1/s) of the open-arrival sweep after the timed steps; '' skips it")
     ap.add_argument("--poisson-n", type=int, default=256, help="requests per rate of the sweep")
     ap.add_argument("--no-graph", action="store_true",
-                    help="skip the fragment-batch comparison (eager / HIP graph / tuned tiling)")
+                    help="small cells: skip the fragment-batch comparison (eager / HIP graph / tuned tiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=25.0)
     ap.add_argument("--max-batch", type=int, default=0,
@@ -48,6 +64,10 @@ def parse():
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device copy first (reference for HBM byte counters)")
     return ap.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
 
 
 def n_classes(kmesh):
@@ -64,14 +84,22 @@ def n_classes(kmesh):
     return n
 
 
-def stage_work(stage, cfg, nfs, prec, eta32=False):
-    """(bound, algorithmic amount per launch, unit, peak) of a stage; eta32:
-    the fit stored T and eta as complex FP32 (8 B a value, else 16).  The
-    k-space stages (T^k, k convolutions' inputs) count all N_k; everything
-    indexed by q counts the nh classes {q, -q} it runs over."""
+def frag_flops(cfg, n):
+    """Algorithmic flops of one fragment's GEMMs: U^q = R^q W^q
+    (8 nh N_IP^2 n^2) and the Hermitian half of the contraction
+    (8 nh N_IP n^2 (n^2 + 1) / 2)."""
+    nh, nip = n_classes(cfg.kmesh), cfg.n_ip
+    return 8.0 * nh * nip * nip * n * n + 8.0 * nh * nip * (n * n) * (n * n + 1) / 2
+
+
+def stage_work(stage, cfg, nfs, prec):
+    """(bound, algorithmic amount, unit, peak) of a stage over the fragments
+    nfs (fragment stages) or one fit + kernel.  The k-space stages (T^k, the
+    k convolutions' inputs) count all N_k; everything indexed by q counts the
+    nh classes {q, -q} it runs over.  The fit and the kernel are FP64 in
+    every precision (16 bytes a value)."""
     nk, nip, ng, norb = cfg.n_k, cfg.n_ip, cfg.n_g, cfg.n_orb
     nh = n_classes(cfg.kmesh)
-    eb = 8 if eta32 else 16
     s2 = sum(n * n for n in nfs)
     dt, pk = PREC_PEAK[prec]
     if stage == "frag_eri":   # Hermitian half of sum_q U^q R^{qH} per fragment
@@ -79,21 +107,20 @@ def stage_work(stage, cfg, nfs, prec, eta32=False):
         return "mfma", fl / 1e12, "TFLOP", pk
     if stage == "frag_u":     # U^q = W^q R^q
         return "mfma", 8.0 * nh * nip * nip * s2 / 1e12, "TFLOP", pk
-    if stage == "v_gemm":     # Hermitian half of eta~ eta~^H
-        return "mfma", 8.0 * nh * nip * nip * ng / 2 / 1e12, "TFLOP", pk
-    if stage == "grid_fft":
-        if prec == "fp64":    # two read+write passes over eta (c128)
-            return "hbm", 4.0 * nh * nip * ng * 16 / 1e9, "GB", PEAK["hbm"]
-        # one pass: eta read, the split operand written (8 B a point)
-        return "hbm", nh * nip * ng * (eb + 8) / 1e9, "GB", PEAK["hbm"]
-    if stage == "rhs_t":      # T^k_I(r) = X^k conj(phi^k): written once
-        return "hbm", 1.0 * nk * nip * ng * eb / 1e9, "GB", PEAK["hbm"]
-    if stage == "rhs_kconv":  # T^k_I(r) read (all k), eta written once (nh classes)
-        return "hbm", (nk + nh) * nip * ng * eb / 1e9, "GB", PEAK["hbm"]
-    if stage == "metric_kconv":
-        return "hbm", (nk + nh) * nip * nip * 16 / 1e9, "GB", PEAK["hbm"]
     if stage == "frag_pair":  # write R^q once (c128 in FP64, 8 B a point in the mixed formats)
         return "hbm", nh * nip * s2 * (16 if prec == "fp64" else 8) / 1e9, "GB", PEAK["hbm"]
+    if stage == "frag_t":
+        return "mfma", 8.0 * nk * nip * norb * sum(nfs) / 1e12, "TFLOP", PEAK["fp64"]
+    if stage == "v_gemm":     # Hermitian half of eta~ eta~^H, FP64 MFMA
+        return "mfma", 8.0 * nh * nip * nip * ng / 2 / 1e12, "TFLOP", PEAK["fp64"]
+    if stage == "grid_fft":   # two read+write passes over eta (c128)
+        return "hbm", 4.0 * nh * nip * ng * 16 / 1e9, "GB", PEAK["hbm"]
+    if stage == "rhs_t":      # T^k_I(r) = X^k conj(phi^k): written once per q batch pass
+        return "hbm", 1.0 * nk * nip * ng * 16 / 1e9, "GB", PEAK["hbm"]
+    if stage == "rhs_kconv":  # T^k_I(r) read (all k), eta written once (nh classes)
+        return "hbm", (nk + nh) * nip * ng * 16 / 1e9, "GB", PEAK["hbm"]
+    if stage == "metric_kconv":
+        return "hbm", (nk + nh) * nip * nip * 16 / 1e9, "GB", PEAK["hbm"]
     if stage == "chol":       # blocked factor: n^3/3 complex MACs
         return "fp64", 8.0 * nh * nip ** 3 / 3 / 1e12, "TFLOP", PEAK["fp64"]
     if stage == "pinv":       # L^{-1} (n^3/6) and G = Y^H Y lower half (n^3/2) complex MACs
@@ -102,18 +129,16 @@ def stage_work(stage, cfg, nfs, prec, eta32=False):
         return "fp64", 1.5 * 8.0 * nh * nip ** 3 / 1e12, "TFLOP", PEAK["fp64"]
     if stage == "metric_t":
         return "mfma", 8.0 * nk * nip * nip * norb / 2 / 1e12, "TFLOP", PEAK["fp64"]
-    if stage == "frag_t":
-        return "mfma", 8.0 * nk * nip * norb * sum(nfs) / 1e12, "TFLOP", PEAK["fp64"]
     return None
 
 
 KERNEL_OF_STAGE = {"frag_eri": ("zgemm_nt_kernel<0, false, true, 3>", "{x}false, true, 3"),
                    "frag_u": ("zgemm_nt_kernel<0, false, false, 2>", "{x}false, false, 2"),
-                   "v_gemm": ("zgemm_nt_kernel<0, false, true, 1>", "{x}false, true, 1"),
-                   "frag_pair": ("pair_kernel(PairArgs)", "pair_reg_kernel<"),
+                   "frag_pair": ("pair_kernel", "pair_kernel"),
+                   "v_gemm": ("zgemm_nt_kernel<0, false, true, 1>", "zgemm_nt_kernel<0, false, true, 1>"),
                    "rhs_t": ("rhs_t_kernel<", "rhs_t_kernel<"),
-                   "rhs_kconv": ("kconv_reg_kernel<", "kconv_reg_kernel<"),
-                   "grid_fft": ("slab_kernel_c<", "fft3_reg_kernel<")}
+                   "rhs_kconv": ("kconv_", "kconv_"),
+                   "grid_fft": ("slab_kernel_c<", "slab_kernel_c<")}
 
 
 def kernel_name(stage, prec):
@@ -126,10 +151,10 @@ def kernel_name(stage, prec):
 
 
 def counter_traffic(stage, workload, prec):
-    """HBM bytes of one step of a stage's main kernel (all its dispatches in
-    the step) from the committed rocprofv3 counter summary (FETCH_SIZE +
-    WRITE_SIZE, scaled by a 1 GiB copy), or None if there is none or a kernel
-    source changed since it was taken."""
+    """HBM bytes per launch of a stage's main kernel from the committed
+    rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, scaled by a 1 GiB
+    copy), or None if there is none or a kernel source changed since it was
+    taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "%s_%s_traffic.json" % (workload, prec))
     if stage not in KERNEL_OF_STAGE or not os.path.exists(path):
@@ -143,90 +168,382 @@ def counter_traffic(stage, workload, prec):
     key = kernel_name(stage, prec)
     for name, v in prof["kernels"].items():
         if key in name:
-            return v["step_bytes"]
+            return v.get("launch_bytes")
     return None
 
 
-STAGES = ["metric_t", "metric_kconv", "rhs_t", "rhs_kconv", "chol", "pinv", "grid_fft", "v_gemm", "w_solve",
-          "frag_t", "frag_pair", "frag_u", "frag_eri"]
+FIT_STAGES = ["metric_t", "metric_kconv", "rhs_t", "rhs_kconv", "chol", "pinv", "grid_fft", "v_gemm", "w_solve"]
+FRAG_STAGES = ["frag_t", "frag_pair", "frag_u", "frag_eri"]
+STAGES = FIT_STAGES + FRAG_STAGES
 
 
-def cpu_baseline(d, frags, w_gpu, budget_s):
-    """The FP64 oracle on a bounded sample of the same step, extrapolated to
-    the whole step with the cost model stated in the sample string."""
-    import numpy as np
-    from oracle import kpoint as ko
+def blas_threads():
     try:
         from threadpoolctl import threadpool_info
-        cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [os.cpu_count()])
+        return max([p.get("num_threads", 1) for p in threadpool_info()] or [os.cpu_count()])
     except Exception:
-        cores = os.cpu_count()
+        return os.cpu_count()
+
+
+class FixedW:
+    """W^q stand-in for timing the oracle's fragment step: the same matrix
+    for every q (the oracle's cost does not depend on the values)."""
+
+    def __init__(self, n, seed=0):
+        import numpy as np
+        rng = np.random.default_rng(seed)
+        a = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+        self.w = a @ a.conj().T / n
+        self.shape = (1, n, n)
+
+    def __getitem__(self, q):
+        return self.w
+
+
+def cpu_baseline(d, nfs_step, budget_s):
+    """The FP64 oracle on bounded samples of the same workload, extrapolated
+    with the cost model stated in the sample string.  The rate is the
+    oracle's fragment ERIs/s with W^q given (the step's work on the GPU);
+    the whole-job seconds (fit + kernel + every fragment of the cell) are
+    reported beside it."""
+    import numpy as np
+    from oracle import kpoint as ko
     cfg = d.cfg
+    nk, nip, ng = cfg.n_k, cfg.n_ip, cfg.n_g
     rng = np.random.default_rng(0)
-    t0 = time.perf_counter()
+    t_all = time.perf_counter()
     x = ko.ip_values(d.orbitals, d.ip_index)
-    pi = ko.metric_k(x, cfg.kmesh)
-    t_metric = time.perf_counter() - t0
-    nr = min(2048, cfg.n_g)
-    ridx = np.sort(rng.choice(cfg.n_g, nr, replace=False))
+    # metric: rows of Pi^q for one and two q (direct k sums), scaled to all
+    # rows and all N_k q of the plain form
+    rows = list(range(min(8, nip)))
     t0 = time.perf_counter()
-    ko.rhs(x, d.orbitals, cfg.kmesh, [0], ridx)
+    ko.metric_rows(x, cfg.kmesh, rows, [0])
     t1 = time.perf_counter() - t0
     t0 = time.perf_counter()
-    ko.rhs(x, d.orbitals, cfg.kmesh, [0, 1], ridx)
+    ko.metric_rows(x, cfg.kmesh, rows, [0, 1])
     t2 = time.perf_counter() - t0
     per_q = max(t2 - t1, 0.0)
-    t_rhs = (max(t1 - per_q, 0.0) + cfg.n_k * per_q) * cfg.n_g / nr
-    eta_q = (rng.standard_normal((cfg.n_ip, cfg.n_g))
-             + 1j * rng.standard_normal((cfg.n_ip, cfg.n_g)))
+    t_metric = (max(t1 - per_q, 0.0) + nk * per_q) * nip / len(rows)
+    # RHS: eta on sampled grid points for one and two q, scaled to all
+    # points and N_k q
+    nr = min(256, ng)
+    ridx = np.sort(rng.choice(ng, nr, replace=False))
     t0 = time.perf_counter()
-    ko.kernel_v_route(pi, eta_q[None], d.lattice, cfg.grid, cfg.kmesh, qs=[1])
-    t_w = (time.perf_counter() - t0) * cfg.n_k
-    # fragments: three sizes, cost model t = a n_f^2 + b n_f^4
-    nfs = [f.shape[2] for f in frags]
-    order = np.argsort(nfs)
-    pick = [int(order[0]), int(order[len(order) // 2]), int(order[(3 * len(order)) // 4])]
+    ko.rhs(x, d.orbitals, cfg.kmesh, [0], ridx)
+    r1 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ko.rhs(x, d.orbitals, cfg.kmesh, [0, 1], ridx)
+    r2 = time.perf_counter() - t0
+    per_q = max(r2 - r1, 0.0)
+    t_rhs = (max(r1 - per_q, 0.0) + nk * per_q) * ng / nr
+    # W for one q (FFT, V, pseudo-inverse) on a stand-in eta, times N_k
+    eta_q = rng.standard_normal((nip, ng)) + 1j * rng.standard_normal((nip, ng))
+    pi_fix = FixedW(nip, 3)        # a Hermitian positive definite stand-in for Pi^q
+    t0 = time.perf_counter()
+    ko.kernel_v_route(pi_fix, eta_q[None], d.lattice, cfg.grid, cfg.kmesh, qs=[1])
+    t_w = (time.perf_counter() - t0) * nk
+    del eta_q
+    # fragments: two small sizes given a stand-in W, cost t = a n^2 + b n^4
+    w_fix = FixedW(nip)
+    sizes = [4, 8] if nk >= STREAM_MIN_NK else sorted(set([min(nfs_step), int(np.median(nfs_step))]))
     ts = []
-    for f in pick:
+    for n in sizes:
+        c = inp_fragment(cfg, n)
         t0 = time.perf_counter()
-        ko.fragment_eri(x, frags[f], w_gpu, cfg.kmesh)
+        ko.fragment_eri(x, c, w_fix, cfg.kmesh)
         ts.append(time.perf_counter() - t0)
-        if sum(ts) > budget_s:
-            break
-    done = pick[:len(ts)]
-    if len(ts) >= 2 and len(set(nfs[p] for p in done)) >= 2:
-        a_ = np.array([[nfs[p] ** 2, nfs[p] ** 4] for p in done], dtype=float)
-        coef = np.linalg.lstsq(a_, np.array(ts), rcond=None)[0]
-        coef = np.maximum(coef, 0)
-        t_frag = float(sum(coef[0] * n ** 2 + coef[1] * n ** 4 for n in nfs))
-    else:
-        t_frag = ts[0] * sum(n ** 4 for n in nfs) / nfs[pick[0]] ** 4
-    t_step = t_metric + t_rhs + t_w + t_frag
-    erisum = float(sum(n ** 4 for n in nfs))
+    a_ = np.array([[n ** 2, n ** 4] for n in sizes], dtype=float)
+    coef = np.maximum(np.linalg.lstsq(a_, np.array(ts), rcond=None)[0], 0)
+    t_frag = lambda ns: float(sum(coef[0] * n ** 2 + coef[1] * n ** 4 for n in ns))
+    step_s = t_frag(nfs_step)
+    import isdf_inputs as inp
+    all_nfs = [int(n) for n in inp.fragment_sizes(cfg)]
+    whole = t_metric + t_rhs + t_w + t_frag(all_nfs)
     return {
-        "value": erisum / t_step, "unit": "ERIs/s", "cores": int(cores), "kind": "oracle",
-        "sample": ("FP64 numpy oracle (direct k and R sums) on this host: metric for all q; "
-                   "eta on %d sampled grid points for 1 and 2 q, scaled to all points and q; "
-                   "W for one q (FFT, V, pseudo-inverse) times N_q; ERIs of fragments with "
-                   "n_f = %s given the GPU FP64 W, extrapolated with t = a n_f^2 + b n_f^4 "
-                   "to all %d fragments; extrapolated step %.1f s (measured %.1f s)"
-                   % (nr, [nfs[p] for p in pick[:len(ts)]], len(nfs), t_step,
-                      t_metric + t1 + t2 + t_w / cfg.n_k + sum(ts))),
-        "seconds_per_step": t_step,
-        "stage_s": {"metric": t_metric, "rhs": t_rhs, "w": t_w, "fragments": t_frag},
+        "value": float(sum(n ** 4 for n in nfs_step)) / step_s, "unit": "ERIs/s", "cores": int(blas_threads()),
+        "kind": "oracle",
+        "sample": ("FP64 numpy oracle (direct k and R sums) on this host: fragment ERIs of n_f = %s given W^q, "
+                   "extrapolated with t = a n_f^2 + b n_f^4 to the step's fragments (n_f %s); whole cell: "
+                   "Pi^q rows for 1 and 2 q scaled to all rows and %d q, eta on %d grid points for 1 and 2 q "
+                   "scaled to the grid and %d q, W for one q times %d, all %d fragments; measured %.1f s"
+                   % (sizes, list(nfs_step), nk, nr, nk, nk, len(all_nfs), time.perf_counter() - t_all)),
+        "seconds_per_step": step_s,
+        "whole_cell_s": whole,
+        "stage_s": {"metric": t_metric, "rhs": t_rhs, "w": t_w, "fragments_all": t_frag(all_nfs)},
     }
 
 
+def inp_fragment(cfg, n):
+    import isdf_inputs as inp
+    return inp.make_fragment(cfg, 10_000 + n, n)
+
+
+def roofline_entry(ctx, stage_tot, cfg, nfs, prec, steps):
+    """Roofline of the dominant fragment stage's main kernel: algorithmic
+    work of one launch over its average launch duration (HIP events around
+    each launch on the stream it runs on)."""
+    dom = max((s for s in FRAG_STAGES if s in stage_tot), key=lambda k: stage_tot[k][0])
+    bound, amount, unit, peak = stage_work(dom, cfg, nfs, prec)
+    kt, kn = stage_tot.get(dom + "_kernel", stage_tot[dom])
+    avg_ms = kt / kn
+    achieved = (amount / kn) / (avg_ms / 1e3)
+    roof = {"bound": "hbm" if unit == "GB" else "mfma", "achieved": achieved, "peak": peak,
+            "unit": "GB/s" if unit == "GB" else "TFLOP/s"}
+    roof["frac"] = achieved / peak
+    roof["traffic"] = counter_traffic(dom, cfg.name, prec)
+    roof["stage"] = dom
+    roof["kernel"] = kernel_name(dom, prec)
+    roof["avg_launch_ms"] = avg_ms
+    roof["launches_per_step"] = kn / steps
+    roof["algorithmic_per_launch"] = amount / kn * (1e9 if unit == "GB" else 1e12)
+    if prec == "bf16x3" and unit != "GB":
+        # three bf16 MFMA products per algorithmic real product
+        roof["frac_of_x3_ceiling"] = achieved / (peak / 3)
+    return roof
+
+
+def stage_rows(stage_tot, cfg, nfs, prec, per):
+    rows = {}
+    tot_ms = sum(stage_tot[k][0] for k in STAGES if k in stage_tot)
+    for s in STAGES:
+        if s not in stage_tot:
+            continue
+        tot, cnt = stage_tot[s]
+        w = stage_work(s, cfg, nfs if s in FRAG_STAGES else [], prec)
+        row = {"ms": tot / per, "intervals": cnt / per, "share": tot / tot_ms if tot_ms else 0.0}
+        if w and tot > 0:
+            amount = w[1] * (1 if s in FRAG_STAGES else per)
+            rate = amount / (tot / 1e3)
+            row["rate"] = rate
+            row["unit"] = "GB/s" if w[2] == "GB" else "TFLOP/s"
+            row["frac"] = rate / w[3]
+        rows[s] = row
+    return rows
+
+
+def collect_stages(ctx, names):
+    out = {}
+    for s in names:
+        tot, cnt = ctx.stage_total(s)
+        if cnt:
+            out[s] = (tot, cnt)
+    return out
+
+
+def poll_all(ctx, tickets, t_sched=None):
+    """Poll tickets to completion; latency from submission (or from the
+    scheduled arrival time when t_sched gives one per ticket)."""
+    lat = {}
+    pending = set(tickets)
+    while pending:
+        for t in list(pending):
+            st, l = ctx.poll(t)
+            if st == "DONE":
+                lat[t] = l
+                pending.discard(t)
+            elif st in ("FAILED", "CANCELLED"):
+                raise RuntimeError("request %d %s: %s" % (t, st, ctx.last_error()))
+    return [lat[t] for t in tickets]
+
+
+# --------------------------------------------------------------------------
+# large cells: fit + kernel once, then slices of the fragment stream
+# --------------------------------------------------------------------------
+def run_stream(args, cfg, pkg, inp, np, torch):
+    t_gen = time.perf_counter()
+    d = inp.make_inputs(cfg)
+    t_gen = time.perf_counter() - t_gen
+    log("inputs %s generated in %.1f s: N_k=%d grid=%s n_orb=%d n_ip=%d"
+        % (cfg.name, t_gen, cfg.n_k, cfg.grid, cfg.n_orb, cfg.n_ip))
+    t0 = time.perf_counter()
+    ctx = pkg.Isdf(d.lattice, cfg.grid, cfg.kmesh, d.orbitals, d.ip_index)
+    torch.cuda.synchronize()
+    log("context created in %.1f s (orbitals copied to HBM)" % (time.perf_counter() - t0))
+    nfs_all = [int(n) for n in inp.fragment_sizes(cfg)]
+    S = max(1, args.slice)
+    nsl = args.warmup + args.steps
+    slices = [[(i * S + j) % len(nfs_all) for j in range(S)] for i in range(nsl)]
+    need = sorted(set(f for sl in slices for f in sl))
+    coeffs = {f: torch.from_numpy(inp.make_fragment(cfg, f, nfs_all[f])).cuda() for f in need}
+    out_elems = max(sum(nfs_all[f] ** 4 for f in sl) for sl in slices)
+    out_buf = torch.empty(out_elems, dtype=torch.complex128, device="cuda")
+
+    def outs_of(sl, buf):
+        o, off = [], 0
+        for f in sl:
+            n = nfs_all[f]
+            o.append(buf[off:off + n ** 4].view(n, n, n, n))
+            off += n ** 4
+        return o
+
+    # fit + Coulomb kernel (once per cell), timed
+    ctx.stage_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.fit(args.prec)
+    t_fit = time.perf_counter() - t0
+    ctx.coulomb_kernel(args.prec)
+    t_kernel = time.perf_counter() - t0 - t_fit
+    fit_stages = collect_stages(ctx, FIT_STAGES)
+    log("fit %.2f s, Coulomb kernel %.2f s" % (t_fit, t_kernel))
+    free, total = torch.cuda.mem_get_info()
+    budget = int(0.9 * free)
+    ctx.serve_start(max_inflight=1, max_batch=args.max_batch or S, budget_bytes=budget)
+
+    def step(sl, prec, buf):
+        return poll_all(ctx, ctx.submit_n([coeffs[f] for f in sl], outs_of(sl, buf), prec))
+
+    for i in range(args.warmup):
+        step(slices[i], args.prec, out_buf)
+        log("warmup slice %d done" % i)
+    torch.cuda.synchronize()
+    ctx.stage_reset()
+    lats, step_s = [], []
+    keep = None
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ts = time.perf_counter()
+        sl = slices[args.warmup + i]
+        lats += step(sl, args.prec, out_buf)
+        step_s.append(time.perf_counter() - ts)
+        if i == 0:
+            keep = out_buf[:sum(nfs_all[f] ** 4 for f in sl)].clone()
+        log("slice %d (n_f %s): %.3f s" % (i, [nfs_all[f] for f in sl], step_s[-1]))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    timed_nfs = [nfs_all[f] for i in range(args.steps) for f in slices[args.warmup + i]]
+    frag_tot = collect_stages(ctx, FRAG_STAGES + [s + "_kernel" for s in FRAG_STAGES])
+    erisum = float(sum(n ** 4 for n in timed_nfs))
+    value = erisum / wall
+    lat_ms = 1e3 * np.asarray(lats)
+    flops_timed = sum(frag_flops(cfg, n) for n in timed_nfs)
+    # whole cell (fit + kernel + every fragment of the stream) at the measured
+    # fragment rate: an estimate, stated as one
+    est_stream_s = sum(frag_flops(cfg, n) for n in nfs_all) / (flops_timed / wall)
+    extra = {"fit_s": t_fit, "kernel_s": t_kernel,
+             "fit_kernel_stages": stage_rows(fit_stages, cfg, [], args.prec, 1),
+             "step_s": {"min": min(step_s), "median": float(np.median(step_s)), "max": max(step_s)},
+             "fragment_tflops_per_s": flops_timed / wall / 1e12,
+             "whole_cell_estimate": {"fragments": len(nfs_all), "stream_s": est_stream_s,
+                                     "total_s": t_fit + t_kernel + est_stream_s,
+                                     "eris_per_s": float(sum(n ** 4 for n in nfs_all))
+                                     / (t_fit + t_kernel + est_stream_s),
+                                     "basis": "fit + kernel measured once; the 500-fragment stream at the "
+                                              "measured fragment flop rate of the timed slices"}}
+    ctx.serve_stop()
+    roof = roofline_entry(ctx, frag_tot, cfg, timed_nfs, args.prec, args.steps)
+    stages = stage_rows(frag_tot, cfg, timed_nfs, args.prec, args.steps)
+    if not args.no_fp64_ref and args.prec != "fp64":
+        # the plain FP64 GPU path on the same cell: fit + kernel, and the
+        # first timed slice; speedup on that slice and max error per result
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.fit("fp64")
+        t64_fit = time.perf_counter() - t0
+        ctx.coulomb_kernel("fp64")
+        t64_kernel = time.perf_counter() - t0 - t64_fit
+        log("FP64 fit %.2f s, kernel %.2f s" % (t64_fit, t64_kernel))
+        sl = slices[args.warmup]
+        ctx.serve_start(max_inflight=1, max_batch=args.max_batch or S, budget_bytes=budget)
+        t0 = time.perf_counter()
+        lat64 = poll_all(ctx, ctx.submit_n([coeffs[f] for f in sl], outs_of(sl, out_buf), "fp64"))
+        t64 = time.perf_counter() - t0
+        ctx.serve_stop()
+        mixed = outs_of(sl, keep)
+        ref64 = outs_of(sl, out_buf)
+        errs = [float((a - b).abs().max().item()) for a, b in zip(mixed, ref64)]
+        vmax = [float(b.abs().max().item()) for b in ref64]
+        extra.update({
+            "fp64_fit_s": t64_fit, "fp64_kernel_s": t64_kernel,
+            "fp64_slice_s": t64, "mixed_slice_s": step_s[0],
+            "speedup_vs_fp64": t64 / step_s[0],
+            "speedup_vs_fp64_whole_cell": (t64_fit + t64_kernel + est_stream_s * t64 / step_s[0])
+            / (t_fit + t_kernel + est_stream_s),
+            "fp64_latency_ms": {"p50": float(np.percentile(1e3 * np.asarray(lat64), 50)),
+                                "p99": float(np.percentile(1e3 * np.asarray(lat64), 99))},
+            "max_err_eh": max(errs),
+            "max_err_eh_per_result": [{"n_f": nfs_all[f], "err": e, "max_abs_v": v}
+                                      for f, e, v in zip(sl, errs, vmax)],
+            "err_bound_eh": 1e-6, "err_reference": "GPU FP64 path, same slice"})
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(d, [nfs_all[f] for f in slices[args.warmup]], args.cpu_budget_s)
+    ctx.close()
+    nh = n_classes(cfg.kmesh)
+    cfgd = {"workload": cfg.name, "n_k": cfg.n_k, "kmesh": list(cfg.kmesh), "grid": list(cfg.grid),
+            "n_orb": cfg.n_orb, "n_ip": cfg.n_ip, "classes": nh, "stream_fragments": len(nfs_all),
+            "n_f_range": [cfg.frag_lo, cfg.frag_hi], "fragments_per_step": S,
+            "eris_per_step": erisum / args.steps, "parallelism": "1 GPU",
+            "step": "one fixed slice of the fragment stream, W^q resident (fit + kernel once, reported apart)"}
+    return value, wall, erisum, lat_ms, roof, stages, cpu, extra, cfgd, len(timed_nfs)
+
+
+# --------------------------------------------------------------------------
+# large cells served to open arrivals
+# --------------------------------------------------------------------------
+def run_arrivals(args, cfg, pkg, inp, np, torch):
+    d = inp.make_inputs(cfg)
+    ctx = pkg.Isdf(d.lattice, cfg.grid, cfg.kmesh, d.orbitals, d.ip_index)
+    t0 = time.perf_counter()
+    ctx.fit(args.prec)
+    ctx.coulomb_kernel(args.prec)
+    t_fk = time.perf_counter() - t0
+    n = args.arrivals
+    nfs_all = [int(x) for x in inp.fragment_sizes(cfg, n)]
+    coeffs = [torch.from_numpy(inp.make_fragment(cfg, f, nfs_all[f])).cuda() for f in range(n)]
+    # outputs: a ring large enough for every request that can be queued at once
+    outs = [torch.empty((m, m, m, m), dtype=torch.complex128, device="cuda") for m in nfs_all]
+    arr = inp.make_arrivals(cfg, n)
+    free, _ = torch.cuda.mem_get_info()
+    ctx.serve_start(max_inflight=2, max_batch=args.max_batch or 16, budget_bytes=int(0.8 * free))
+    tickets, sched = [], []
+    i = 0
+    lat = {}
+    pending = set()
+    t0 = time.perf_counter()
+    while i < n or pending:
+        now = time.perf_counter() - t0
+        while i < n and arr[i] <= now:
+            t = ctx.submit(coeffs[i], outs[i], args.prec)
+            tickets.append(t)
+            sched.append(arr[i])
+            pending.add(t)
+            i += 1
+        for t in list(pending):
+            st, _ = ctx.poll(t)
+            if st == "DONE":
+                lat[t] = time.perf_counter() - t0
+                pending.discard(t)
+            elif st in ("FAILED", "CANCELLED"):
+                raise RuntimeError("request %d %s: %s" % (t, st, ctx.last_error()))
+    wall = time.perf_counter() - t0
+    ctx.serve_stop()
+    ctx.close()
+    # latency from the scheduled arrival to the observed completion
+    lm = np.array([1e3 * (lat[t] - s) for t, s in zip(tickets, sched)])
+    erisum = float(sum(m ** 4 for m in nfs_all))
+    extra = {"arrivals": {"rate_per_s": cfg.arrival_rate, "requests": n, "offered_per_s": n / float(arr[-1]),
+                          "served_per_s": n / wall, "fit_kernel_s": t_fk,
+                          "latency_from": "scheduled arrival"}}
+    cfgd = {"workload": cfg.name, "n_k": cfg.n_k, "kmesh": list(cfg.kmesh), "grid": list(cfg.grid),
+            "n_orb": cfg.n_orb, "n_ip": cfg.n_ip, "requests": n, "n_f_range": [cfg.frag_lo, cfg.frag_hi],
+            "parallelism": "1 GPU", "step": "one request of the open-arrival run"}
+    return erisum / wall, wall, erisum, lm, None, {}, None, extra, cfgd, n
+
+
+# --------------------------------------------------------------------------
+# small cells: one step = fit + kernel + every fragment
+# --------------------------------------------------------------------------
 def poisson_sweep(ctx, inp, cfg, cdev, outs, prec, rates, n):
     """Open arrivals: requests for the step's fragments (reused cyclically)
-    submitted one at a time at Poisson arrival times (seeded), while earlier
-    ones run; per rate the offered and served rates and the p50 / p99 latency
-    (the library's clock: submit -> completion observed)."""
+    submitted one at a time at seeded Poisson arrival times while earlier
+    ones run; per rate the offered and served rates and the p50 / p99
+    latency from the scheduled arrival to the observed completion."""
     import numpy as np
     rows = []
     for rate in rates:
         arr = inp.make_arrivals(cfg, n, rate)
-        tickets, pending, lat = [], set(), {}
+        tickets, sched, pending, done = [], [], set(), {}
         i = 0
         t0 = time.perf_counter()
         while i < n or pending:
@@ -235,23 +552,115 @@ def poisson_sweep(ctx, inp, cfg, cdev, outs, prec, rates, n):
                 f = i % len(cdev)
                 t = ctx.submit_n([cdev[f]], [outs[f]], prec)[0]
                 tickets.append(t)
+                sched.append(arr[i])
                 pending.add(t)
                 i += 1
             for t in list(pending):
-                st, l = ctx.poll(t)
+                st, _ = ctx.poll(t)
                 if st == "DONE":
-                    lat[t] = l
+                    done[t] = time.perf_counter() - t0
                     pending.discard(t)
                 elif st in ("FAILED", "CANCELLED"):
                     raise RuntimeError("request %d %s: %s" % (t, st, ctx.last_error()))
         wall = time.perf_counter() - t0
-        lm = 1e3 * np.array([lat[t] for t in tickets])
+        lm = 1e3 * np.array([done[t] - s for t, s in zip(tickets, sched)])
         rows.append({"rate_per_s": rate, "requests": n, "offered_per_s": n / float(arr[-1]),
                      "served_per_s": n / wall, "p50_ms": float(np.percentile(lm, 50)),
-                     "p99_ms": float(np.percentile(lm, 99))})
-        print("poisson %g/s: p50 %.2f ms, p99 %.2f ms" % (rate, rows[-1]["p50_ms"], rows[-1]["p99_ms"]),
-              file=sys.stderr, flush=True)
+                     "p99_ms": float(np.percentile(lm, 99)), "latency_from": "scheduled arrival"})
+        log("poisson %g/s: p50 %.2f ms, p99 %.2f ms" % (rate, rows[-1]["p50_ms"], rows[-1]["p99_ms"]))
     return rows
+
+
+def run_whole(args, cfg, pkg, inp, np, torch):
+    d = inp.make_inputs(cfg)
+    frags = inp.make_fragments(cfg)
+    nfs = [int(f.shape[2]) for f in frags]
+    log("inputs %s: N_k=%d grid=%s n_orb=%d n_ip=%d fragments=%d"
+        % (cfg.name, cfg.n_k, cfg.grid, cfg.n_orb, cfg.n_ip, len(frags)))
+    ctx = pkg.Isdf(d.lattice, cfg.grid, cfg.kmesh, d.orbitals, d.ip_index)
+    cdev = [torch.from_numpy(f).cuda() for f in frags]
+    out_mix = [torch.empty((n, n, n, n), dtype=torch.complex128, device="cuda") for n in nfs]
+    out_64 = [torch.empty((n, n, n, n), dtype=torch.complex128, device="cuda") for n in nfs]
+    torch.cuda.synchronize()
+    free, _ = torch.cuda.mem_get_info()
+    ctx.serve_start(max_inflight=2, max_batch=args.max_batch or len(frags), budget_bytes=int(0.8 * free))
+
+    def step(prec, outs):
+        ctx.fit(prec)
+        ctx.coulomb_kernel(prec)
+        return poll_all(ctx, ctx.submit_n(cdev, outs, prec))
+
+    for i in range(args.warmup):
+        step(args.prec, out_mix)
+        log("warmup step %d done" % i)
+    torch.cuda.synchronize()
+    ctx.stage_reset()
+    lats = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        lats += step(args.prec, out_mix)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    log("timed %d steps: %.2f ms/step" % (args.steps, 1e3 * wall / args.steps))
+    tot = collect_stages(ctx, STAGES + [s + "_kernel" for s in FRAG_STAGES])
+    erisum = float(sum(n ** 4 for n in nfs)) * args.steps
+    roof = roofline_entry(ctx, tot, cfg, nfs * args.steps, args.prec, args.steps)
+    stages = stage_rows(tot, cfg, nfs * args.steps, args.prec, args.steps)
+    extra = {}
+    rates = [float(r) for r in (args.poisson_rates if args.poisson_rates is not None else "200,1000,4000").split(",")
+             if r.strip()]
+    if rates:
+        extra["poisson"] = poisson_sweep(ctx, inp, cfg, cdev, out_mix, args.prec, rates, args.poisson_n)
+    if not args.no_fp64_ref and args.prec != "fp64":
+        step("fp64", out_64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nfp = 3
+        for _ in range(nfp):
+            step("fp64", out_64)
+        torch.cuda.synchronize()
+        t64 = (time.perf_counter() - t0) / nfp
+        errs = [float((a - b).abs().max().item()) for a, b in zip(out_mix, out_64)]
+        extra["fp64_ms_per_step"] = 1e3 * t64
+        extra["speedup_vs_fp64"] = t64 / (wall / args.steps)
+        extra["max_err_eh"] = max(errs)
+        extra["max_err_eh_per_result"] = {"min": min(errs), "median": float(np.median(errs)),
+                                          "max": max(errs), "n": len(errs)}
+        extra["err_bound_eh"] = 1e-6
+        extra["err_reference"] = "GPU FP64 path, same fragments"
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(d, nfs, args.cpu_budget_s)
+    if not args.no_graph and args.prec != "fp64":
+        ctx.serve_stop()
+        ctx.fit(args.prec)
+        ctx.coulomb_kernel(args.prec)
+
+        def per_call(fn, n=5):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(n):
+                fn()
+            torch.cuda.synchronize()
+            return 1e3 * (time.perf_counter() - t0) / n
+
+        eager_ms = per_call(lambda: ctx.fragment_eri(cdev, args.prec, out=out_mix))
+        g = ctx.graph(cdev, out_mix, args.prec)
+        graph_ms = per_call(g.launch)
+        g.close()
+        rep = ctx.autotune(cdev, out_mix, args.prec)
+        tuned_ms = per_call(lambda: ctx.fragment_eri(cdev, args.prec, out=out_mix))
+        extra["fragment_batch"] = {"eager_ms": eager_ms, "graph_ms": graph_ms, "tuned_eager_ms": tuned_ms,
+                                   "autotune": rep}
+    else:
+        ctx.serve_stop()
+    ctx.close()
+    cfgd = {"workload": cfg.name, "n_k": cfg.n_k, "kmesh": list(cfg.kmesh), "grid": list(cfg.grid),
+            "n_orb": cfg.n_orb, "n_ip": cfg.n_ip, "fragments": len(nfs), "n_f_range": [min(nfs), max(nfs)],
+            "eris_per_step": erisum / args.steps, "parallelism": "1 GPU",
+            "step": "fit + Coulomb kernel + every fragment of the cell"}
+    return erisum / wall, wall, erisum, 1e3 * np.asarray(lats), roof, stages, cpu, extra, cfgd, len(nfs) * args.steps
 
 
 def main():
@@ -274,183 +683,33 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     cfg = inp.get_config(args.workload)
-    t_gen = time.perf_counter()
-    d = inp.make_inputs(cfg)
-    frags = inp.make_fragments(cfg)
-    nfs = [int(f.shape[2]) for f in frags]
-    t_gen = time.perf_counter() - t_gen
-    print("inputs %s generated in %.1f s: N_k=%d grid=%s n_orb=%d n_ip=%d fragments=%d"
-          % (cfg.name, t_gen, cfg.n_k, cfg.grid, cfg.n_orb, cfg.n_ip, len(frags)),
-          file=sys.stderr, flush=True)
-
-    orb = torch.from_numpy(d.orbitals).cuda()
-    ip = torch.from_numpy(d.ip_index).cuda()
-    ctx = pkg.Isdf(d.lattice, cfg.grid, cfg.kmesh, orb, ip)
-    del orb
-    cdev = [torch.from_numpy(f).cuda() for f in frags]
-    out_mix = [torch.empty((n, n, n, n), dtype=torch.complex128, device="cuda") for n in nfs]
-    out_64 = [torch.empty((n, n, n, n), dtype=torch.complex128, device="cuda") for n in nfs]
-    torch.cuda.synchronize()
-    per_req = 16 * (cfg.n_k * cfg.n_orb * max(nfs) + cfg.n_k * cfg.n_ip * max(nfs)
-                    + 2 * cfg.n_k * cfg.n_ip * max(nfs) ** 2)
-    batch_bytes = 16 * (cfg.n_k * cfg.n_orb * sum(nfs) + cfg.n_k * cfg.n_ip * sum(nfs)
-                        + 2 * cfg.n_k * cfg.n_ip * sum(n * n for n in nfs)) + (1 << 26)
-    budget = 2 * max(batch_bytes, per_req)
-    ctx.serve_start(max_inflight=2, max_batch=args.max_batch or len(frags), budget_bytes=budget)
-
-    def step(prec, outs):
-        ctx.fit(prec)
-        ctx.coulomb_kernel(prec)
-        tickets = ctx.submit_n(cdev, outs, prec)
-        lat = {}
-        pending = set(tickets)
-        while pending:
-            for t in list(pending):
-                st, l = ctx.poll(t)
-                if st == "DONE":
-                    lat[t] = l
-                    pending.discard(t)
-                elif st in ("FAILED", "CANCELLED"):
-                    raise RuntimeError("request %d %s: %s" % (t, st, ctx.last_error()))
-        return [lat[t] for t in tickets]
-
-    for i in range(args.warmup):
-        step(args.prec, out_mix)
-        print("warmup step %d done" % i, file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    ctx.stage_reset()
-    lats = []
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        lats += step(args.prec, out_mix)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_step = 1e3 * wall / args.steps
-    print("timed %d steps: %.2f ms/step" % (args.steps, ms_step), file=sys.stderr, flush=True)
-    # device time of each stage per step (HIP events on the stream it runs on)
-    # and the number of timed intervals (kernel launches for "*_kernel")
-    stage = {}
-    for s in STAGES + [s + "_kernel" for s in KERNEL_OF_STAGE]:
-        tot, cnt = ctx.stage_total(s)
-        if cnt:
-            stage[s] = (tot / args.steps, cnt / args.steps)
-    erisum = float(sum(n ** 4 for n in nfs))
-    value = erisum * args.steps / wall
-    lat_ms = 1e3 * np.asarray(lats)
-
-    # a mixed-precision fit stores T and eta as complex FP32 on the one-pass FFT grids
-    eta32 = args.prec != "fp64" and pkg.isdf_fit_eta_fp32(cfg.grid)
-    # dominant stage and the roofline of its main kernel: algorithmic work of
-    # one launch over the average launch duration; where the stage also runs
-    # small helper kernels its GEMM launches are timed alone ("<stage>_kernel")
-    dom = max((s for s in STAGES if s in stage), key=lambda k: stage[k][0])
-    bound, amount, unit, peak = stage_work(dom, cfg, nfs, args.prec, eta32)
-    kt, kn = stage.get(dom + "_kernel", stage[dom])
-    avg_ms = kt / kn
-    achieved = (amount / kn) / (avg_ms / 1e3)
-    if unit == "GB":
-        roof = {"bound": "hbm", "achieved": achieved, "peak": peak, "unit": "GB/s"}
-    elif bound == "mfma":
-        roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s"}
+    if cfg.n_k >= STREAM_MIN_NK and args.arrivals > 0:
+        res = run_arrivals(args, cfg, pkg, inp, np, torch)
+    elif cfg.n_k >= STREAM_MIN_NK:
+        res = run_stream(args, cfg, pkg, inp, np, torch)
     else:
-        roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s"}
-    roof["frac"] = achieved / peak
-    tr = counter_traffic(dom, cfg.name, args.prec)
-    roof["traffic"] = None if tr is None else tr / kn
-    roof["stage"] = dom
-    roof["kernel"] = kernel_name(dom, args.prec)
-    roof["avg_launch_ms"] = avg_ms
-    roof["launches_per_step"] = kn
-    roof["algorithmic_per_launch"] = amount / kn * (1e9 if unit == "GB" else 1e12)
-
-    stage_rows = {}
-    for s in STAGES:
-        if s not in stage:
-            continue
-        tot, cnt = stage[s]
-        w = stage_work(s, cfg, nfs, args.prec, eta32)
-        row = {"ms_per_step": tot, "intervals_per_step": cnt,
-               "share": tot / sum(stage[k][0] for k in STAGES if k in stage)}
-        if w:
-            rate = w[1] / (tot / 1e3)
-            row["rate"] = rate
-            row["unit"] = "GB/s" if w[2] == "GB" else "TFLOP/s"
-            row["frac"] = rate / w[3]
-        stage_rows[s] = row
-
-    extra = {}
-    rates = [float(r) for r in args.poisson_rates.split(",") if r.strip()]
-    if rates:
-        extra["poisson"] = poisson_sweep(ctx, inp, cfg, cdev, out_mix, args.prec, rates, args.poisson_n)
-    if not args.no_fp64_ref and args.prec != "fp64":
-        step("fp64", out_64)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        step("fp64", out_64)
-        torch.cuda.synchronize()
-        t64 = time.perf_counter() - t0
-        # W is rebuilt by the last call: rebuild the mixed W for consistency of
-        # later calls (not timed)
-        errs = [float((a - b).abs().max().item()) for a, b in zip(out_mix, out_64)]
-        extra["fp64_ms_per_step"] = 1e3 * t64
-        extra["speedup_vs_fp64"] = t64 * 1e3 / ms_step
-        extra["max_err_eh"] = max(errs)
-        extra["max_err_eh_per_result"] = {"min": min(errs), "median": float(np.median(errs)),
-                                          "max": max(errs), "n": len(errs)}
-        extra["err_bound_eh"] = 1e-6
-    cpu = None
-    if not args.no_cpu_baseline:
-        w_gpu = np.stack([ctx.get_kernel(q) for q in range(cfg.n_k)])
-        cpu = cpu_baseline(d, frags, w_gpu, args.cpu_budget_s)
-    if not args.no_graph and args.prec != "fp64":
-        # the fragment batch alone (after the timed steps): eager
-        # isdf_fragment_eri, its captured HIP graph, and the eager batch again
-        # with the launch tiling isdf_autotune picks on it
-        ctx.fit(args.prec)
-        ctx.coulomb_kernel(args.prec)
-
-        def per_call(fn, n=5):
-            fn()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(n):
-                fn()
-            torch.cuda.synchronize()
-            return 1e3 * (time.perf_counter() - t0) / n
-
-        eager_ms = per_call(lambda: ctx.fragment_eri(cdev, args.prec, out=out_mix))
-        g = ctx.graph(cdev, out_mix, args.prec)
-        graph_ms = per_call(g.launch)
-        g.close()
-        rep = ctx.autotune(cdev, out_mix, args.prec)
-        tuned_ms = per_call(lambda: ctx.fragment_eri(cdev, args.prec, out=out_mix))
-        extra["fragment_batch"] = {"eager_ms": eager_ms, "graph_ms": graph_ms, "tuned_eager_ms": tuned_ms,
-                                   "autotune": rep}
-    ctx.serve_stop()
-    ctx.close()
-
+        res = run_whole(args, cfg, pkg, inp, np, torch)
+    value, wall, erisum, lat_ms, roof, stages, cpu, extra, cfgd, nreq = res
+    steps = args.steps if not (cfg.n_k >= STREAM_MIN_NK and args.arrivals > 0) else nreq
     out = {
         "metric": "fragment ERIs/s + p50/p99 latency, mixed vs FP64 at <=1e-6 Eh max error",
         "value": value,
         "unit": "ERIs/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": 1e3 * wall / steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": args.prec,
         "data": "synthetic",
-        "config": {"workload": cfg.name, "n_k": cfg.n_k, "kmesh": list(cfg.kmesh),
-                   "grid": list(cfg.grid), "n_orb": cfg.n_orb, "n_ip": cfg.n_ip,
-                   "fragments": len(nfs), "n_f_range": [min(nfs), max(nfs)],
-                   "eris_per_step": erisum, "parallelism": "1 GPU"},
-        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)),
-                       "p99": float(np.percentile(lat_ms, 99)), "n": int(lat_ms.size)},
-        "fragments_per_s": len(nfs) * args.steps / wall,
+        "config": cfgd,
+        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
+                       "n": int(lat_ms.size)},
+        "fragments_per_s": nreq / wall,
         "roofline": roof,
-        "stages": stage_rows,
+        "stages": stages,
         "cpu_baseline": cpu,
     }
     out.update(extra)

@@ -66,11 +66,13 @@ typedef enum {
 } isdf_status;
 
 typedef enum {
-  ISDF_FP64 = 0,        /* all GEMMs in FP64 MFMA                                  */
-  ISDF_MIXED_FP32 = 1,  /* W^q and fragment GEMMs in FP32 MFMA, FP32 accumulation
-                           within one q (or one K segment), FP64 across them     */
-  ISDF_MIXED_BF16X3 = 2 /* same GEMMs with operands split hi+lo in bf16 and three
-                           bf16 MFMA products (hi*hi + hi*lo + lo*hi)           */
+  ISDF_FP64 = 0,        /* every GEMM in FP64 MFMA                                 */
+  ISDF_MIXED_FP32 = 1,  /* the fragment GEMMs (U^q = R^q W^q and the contraction)
+                           in FP32 MFMA, FP32 accumulation within one class of q
+                           (or one K segment), FP64 across them; the fit and the
+                           Coulomb kernel stay FP64                              */
+  ISDF_MIXED_BF16X3 = 2 /* the same GEMMs with operands split hi+lo in bf16 and
+                           three bf16 MFMA products (hi*hi + hi*lo + lo*hi)     */
 } isdf_precision;
 
 /* flags for isdf_create */
@@ -90,6 +92,10 @@ typedef enum {
 /* fragment buffers: C and eri are device pointers when this bit is set in
  * isdf_fragment_eri's flags / isdf_request.flags, host pointers otherwise */
 #define ISDF_FRAG_DEVICE 0x1u
+/* isdf_fragment_eri flags bits 8-15: run every fragment alone with its n_f^2
+ * pairs in n blocks (at most n_f^2; 0 or 1 = blocks only where memory
+ * requires them) */
+#define ISDF_FRAG_BLOCKS(n) ((((uint32_t)(n)) & 0xFFu) << 8)
 
 /*
  * Create a context (eq. (1)-(2) inputs).
@@ -120,34 +126,33 @@ isdf_status isdf_create(isdf_ctx* out, const double* lattice, const int32_t grid
  * tolerance 1e-13; the rank is reported by isdf_stats).  Synchronous.
  * Pi^{-q}, eta^{-q} and W^{-q} are the complex conjugates of those at q, so
  * one q of each class {q, -q} is computed and stored.  eta of every class
- * is formed here when it fits (60 % of the device memory left after
- * isdf_create's buffers, capped by ISDF_Q_BATCH); otherwise
- * isdf_coulomb_kernel forms it per q batch and isdf_get_rhs is unavailable.
- * `prec` is the precision of the kernel that will consume eta (eqs. (5)-(7)):
- * with ISDF_FP64 eta is kept in FP64; with a mixed precision, on the grids
- * whose mixed grid FFT reads it directly (cubic, 6..32 points a side: see
- * isdf_fit_eta_fp32), T^k_I(r) and eta are stored as complex FP32 (FP64
- * arithmetic, one rounding per stored value), halving the HBM traffic of
- * the RHS and of the grid FFT.  X, Pi^q and its factor are FP64 always.
- * Error: ISDF_E_INVALID for an unknown precision; ISDF_E_NUMERIC when
- * ISDF_NO_PIVOT is set and a Pi^q is singular.
+ * is formed here when it fits in 60 % of the device memory left after the
+ * context's other buffers (capped by ISDF_Q_BATCH); otherwise
+ * isdf_coulomb_kernel forms it per q batch, isdf_get_rhs is unavailable, and
+ * the kernel hands the fit's transient buffers (eta, the RHS tiles, T^k of
+ * the metric, the factorisation scratch) back to the fragment workspaces
+ * when it ends (the next fit allocates them again).  Everything here is
+ * FP64 in every precision; `prec` is accepted for symmetry with
+ * isdf_coulomb_kernel.  Error: ISDF_E_INVALID for an unknown precision;
+ * ISDF_E_NUMERIC when ISDF_NO_PIVOT is set and a Pi^q is singular.
  */
 isdf_status isdf_fit(isdf_ctx ctx, isdf_precision prec);
-
-/* 1 if isdf_fit with a mixed precision stores eta as complex FP32 on this
- * grid, 0 if it keeps FP64 there. */
-int32_t isdf_fit_eta_fp32(const int32_t grid[3]);
 
 /*
  * W^q for all q (eqs. (6)-(8)): grid FFT of eta^q(r) exp(-i q.r), scaled by
  * sqrt(Omega 4 pi/|K|^2)/N_g (FP64; K the representative of G+q nearest
  * zero per axis, the kernel averaged over the two at a tie +-n/2),
- * V^q = eta~ eta~^H (GEMM in `prec`), W^q = Pi^{q+} V^q Pi^{q+} by FP64
+ * V^q = eta~ eta~^H (FP64 MFMA), W^q = Pi^{q+} V^q Pi^{q+} by FP64
  * triangular solves with the factor of isdf_fit; one q per class {q, -q},
  * in q batches (eta formed per batch) when isdf_fit did not form eta.
+ * The kernel is FP64 in every precision: W^q amplifies the rounding of eta
+ * and V^q by up to cond(Pi^q) on each side, and at the conditioning of the
+ * workloads (cond(Pi^q) 1e4-5e5) an FP32 or bf16 hi+lo V^q moves the ERIs by
+ * 3e-6 to 2e-5 Eh; the mixed precisions apply to the fragment GEMMs, where
+ * the error with an FP64 W^q stays within the 1e-6 Eh bound.  `prec` is
+ * accepted for symmetry with isdf_fragment_eri.
  * Consumes eta (isdf_get_rhs is invalid afterwards).  Synchronous.
- * Error: ISDF_E_STATE before isdf_fit, or with prec = ISDF_FP64 after a
- * mixed-precision fit that stored eta in FP32.
+ * Error: ISDF_E_STATE before isdf_fit.
  */
 isdf_status isdf_coulomb_kernel(isdf_ctx ctx, isdf_precision prec);
 
@@ -158,14 +163,12 @@ isdf_status isdf_get_metric(isdf_ctx ctx, int32_t q, void* out);
 isdf_status isdf_get_kernel(isdf_ctx ctx, int32_t q, void* out);
 isdf_status isdf_get_ivs(isdf_ctx ctx, int32_t k, void* out);
 /* Copy eta^q (c128 [n_ip][N_g]) to host; valid between isdf_fit and
- * isdf_coulomb_kernel.  After a fit that stored eta in FP32 the values are
- * those FP32 numbers, widened exactly. */
+ * isdf_coulomb_kernel (and only when the fit formed eta of every class). */
 isdf_status isdf_get_rhs(isdf_ctx ctx, int32_t q, void* out);
 /* Test hook: copy the Coulomb-weighted transform of eq. (7),
  *   eta~^q_I(G) = sqrt(Omega 4 pi / |K|^2) / N_g sum_r eta^q_I(r) exp(-i (G+q).r)
- * (K as in isdf_coulomb_kernel; 0 at K = 0), as it enters V^q = eta~ eta~^H: FP64 after an FP64
- * isdf_coulomb_kernel, else the FP32 or bf16 hi+lo operand of the mixed
- * product, converted exactly to c128.  out: host c128 [n_ip][N_g], G in the
+ * (K as in isdf_coulomb_kernel; 0 at K = 0), as it enters V^q = eta~ eta~^H
+ * (FP64).  out: host c128 [n_ip][N_g], G in the
  * FFT order of the grid (index i_d stands for G_d = i_d wrapped to
  * [-n_d/2, n_d/2)).  Valid after isdf_coulomb_kernel until the next isdf_fit.
  * Error: ISDF_E_STATE before isdf_coulomb_kernel or after one that ran in q
@@ -182,9 +185,17 @@ isdf_status isdf_get_eta_tilde(isdf_ctx ctx, int32_t q, void* out);
  *   n_f       [n_frag] orbitals per fragment (>= 1), host memory.
  *   C         [n_frag] pointers, fragment f: c128 [N_k][n_orb][n_f[f]].
  *   eri       [n_frag] pointers, fragment f: c128 [n_f]^4 output.
- *   flags     ISDF_FRAG_DEVICE if C[f] / eri[f] are device pointers.
+ *   flags     ISDF_FRAG_DEVICE if C[f] / eri[f] are device pointers;
+ *             ISDF_FRAG_BLOCKS(n) to force n pair blocks per fragment.
+ * Memory: the batch runs in sub-batches of consecutive fragments whose
+ * workspace fits the free device memory; a fragment that does not fit alone
+ * runs with its pairs (pq) in blocks (eqs. (19)-(20) over pair blocks: R^q of
+ * a row block and of a column block and U^q of the row block are held at a
+ * time, and the Hermitian contraction runs over block pairs), up to 32
+ * blocks.  Results do not depend on the blocking (each output element is
+ * summed in the same order).
  * Synchronous.  Error: ISDF_E_STATE before isdf_coulomb_kernel,
- * ISDF_E_NOMEM if the batch exceeds the memory budget (split it).
+ * ISDF_E_NOMEM if a fragment does not fit even in 32 pair blocks.
  */
 isdf_status isdf_fragment_eri(isdf_ctx ctx, isdf_precision prec, int32_t n_frag,
                               const int32_t* n_f, const void* const* C, void* const* eri,

@@ -29,8 +29,10 @@ Every stream is seeded from ``numpy.random.SeedSequence([cfg_id, stream, ...])``
 """
 from __future__ import annotations
 
+import concurrent.futures as cf
 import dataclasses
 import hashlib
+import os
 from typing import Optional
 
 import numpy as np
@@ -102,9 +104,9 @@ CONFIGS = {
     # grid sizes of every FFT code path (radix pairs 2x5, 4x5, 3x6, 6x6, 5x8)
     "t_grid10_k1": Config("t_grid10_k1", 110, 5.0, (10, 10, 10), (1, 1, 1), 8, 30,
                           gmax=2.0, env=3.0, n_frag=1, frag_lo=4, frag_hi=4),
-    "t_grid20_k3": Config("t_grid20_k3", 111, 5.0, (20, 20, 20), (3, 1, 1), 8, 40,
+    "t_grid20_k3": Config("t_grid20_k3", 111, 5.0, (20, 20, 20), (3, 1, 1), 4, 40,
                           gmax=3.0, env=3.0, n_frag=1, frag_lo=6, frag_hi=6),
-    "t_grid18_k2": Config("t_grid18_k2", 112, 5.0, (18, 18, 18), (1, 2, 1), 8, 36,
+    "t_grid18_k2": Config("t_grid18_k2", 112, 5.0, (18, 18, 18), (1, 2, 1), 6, 36,
                           gmax=3.0, env=3.0, n_frag=1, frag_lo=5, frag_hi=5),
     "t_grid36_k2": Config("t_grid36_k2", 113, 6.0, (36, 36, 36), (2, 1, 1), 6, 40,
                           gmax=4.0, env=4.0, n_frag=1, frag_lo=6, frag_hi=6),
@@ -114,6 +116,21 @@ CONFIGS = {
     # convolution and pair transform) with axes of 2, odd n_orb, ragged tiles
     "t_m4_k16": Config("t_m4_k16", 115, 5.0, (10, 10, 10), (4, 2, 2), 7, 90,
                        gmax=2.0, env=3.0, n_frag=3, frag_lo=4, frag_hi=9),
+    # mesh axes of 6 and 10 (the k-mesh shapes of workloads 4 and 5): the LDS
+    # k transforms with axis lengths up to 8 and up to 16
+    "t_k6_line": Config("t_k6_line", 116, 5.0, (10, 10, 10), (6, 1, 1), 5, 60,
+                        gmax=2.0, env=3.0, n_frag=2, frag_lo=4, frag_hi=9),
+    "t_k10_line": Config("t_k10_line", 117, 5.0, (8, 8, 8), (1, 10, 1), 4, 48,
+                         gmax=1.5, env=2.0, n_frag=2, frag_lo=3, frag_hi=7),
+    "t_k6_cube": Config("t_k6_cube", 118, 4.0, (6, 6, 6), (6, 6, 6), 2, 16,
+                        gmax=1.5, env=2.0, n_frag=2, frag_lo=3, frag_hi=6),
+    "t_k10_cube": Config("t_k10_cube", 119, 4.0, (4, 4, 4), (10, 10, 10), 2, 10,
+                         gmax=1.0, env=2.0, n_frag=2, frag_lo=2, frag_hi=4),
+    # ill-conditioned metrics like the large workloads (cond(Pi^q) 4e4-5e5,
+    # workloads 3 and 4 measure 1e4-2e5): 33 interpolation points per
+    # orbital on smooth orbitals
+    "t_cond_k8": Config("t_cond_k8", 120, 6.0, (16, 16, 16), (2, 2, 2), 6, 200,
+                        gmax=4.0, env=2.0, n_frag=2, frag_lo=6, frag_hi=10),
 }
 
 
@@ -186,19 +203,64 @@ def _orbitals_at_k(cfg: Config, kidx: int, jk: np.ndarray, g, envelope) -> np.nd
     return (s_inv_half.T @ phi)
 
 
-def make_orbitals(cfg: Config, k_subset: Optional[np.ndarray] = None) -> np.ndarray:
-    """Bloch orbitals ``[len(k_subset) or N_k, N_orb, N_g]`` (complex128)."""
+def _workers(cfg: Config, nk: int) -> int:
+    """Threads for the per-k generation: one for small cells, up to 16 for
+    large ones (each k point is independent; BLAS runs single-threaded inside
+    a worker, which gives the same numbers as a serial run)."""
+    if nk * cfg.n_orb * cfg.n_g < (1 << 24):
+        return 1
+    return max(1, min(16, os.cpu_count() or 1, nk))
+
+
+def make_orbitals(cfg: Config, k_subset: Optional[np.ndarray] = None,
+                  out: Optional[np.ndarray] = None) -> np.ndarray:
+    """Bloch orbitals ``[len(k_subset) or N_k, N_orb, N_g]`` (complex128),
+    written into ``out`` when given."""
     g, envelope = _plane_wave_set(cfg)
     jks = kmesh_indices(cfg.kmesh)
     ks = np.arange(cfg.n_k) if k_subset is None else np.asarray(k_subset)
-    out = np.empty((len(ks), cfg.n_orb, cfg.n_g), dtype=np.complex128)
-    for i, k in enumerate(ks):
-        out[i] = _orbitals_at_k(cfg, int(k), jks[k], g, envelope)
+    if out is None:
+        out = np.empty((len(ks), cfg.n_orb, cfg.n_g), dtype=np.complex128)
+
+    def one(i):
+        out[i] = _orbitals_at_k(cfg, int(ks[i]), jks[ks[i]], g, envelope)
+
+    nw = _workers(cfg, len(ks))
+    if nw == 1:
+        for i in range(len(ks)):
+            one(i)
+    else:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(1), cf.ThreadPoolExecutor(nw) as ex:
+            list(ex.map(one, range(len(ks))))
     return out
 
 
+def density(cfg: Config, orbitals: np.ndarray) -> np.ndarray:
+    """rho(r) = sum_k sum_mu |phi^k_mu(r)|^2, summed per k and then over k in
+    k order (threads over k for large cells)."""
+    nk = orbitals.shape[0]
+    part = np.empty((nk, orbitals.shape[2]))
+
+    def one(k):
+        o = orbitals[k]
+        part[k] = (o.real * o.real + o.imag * o.imag).sum(axis=0)
+
+    nw = _workers(cfg, nk)
+    if nw == 1:
+        for k in range(nk):
+            one(k)
+    else:
+        with cf.ThreadPoolExecutor(nw) as ex:
+            list(ex.map(one, range(nk)))
+    rho = np.zeros(orbitals.shape[2])
+    for k in range(nk):
+        rho += part[k]
+    return rho
+
+
 def make_ip_index(cfg: Config, orbitals: np.ndarray) -> np.ndarray:
-    rho = np.einsum("kmr,kmr->r", orbitals.conj(), orbitals).real
+    rho = density(cfg, orbitals)
     p = rho / rho.sum()
     rng = _seed(cfg, STREAM_IPS)
     idx = rng.choice(cfg.n_g, size=cfg.n_ip, replace=False, p=p)

@@ -177,11 +177,13 @@ def fragment_psi_at_ips(x, coeffs, kmesh):
     (eq. (17) at the interpolation points; Algorithm 2 first two steps),
     direct sum over k.  Returns [N_R, N_IP, n_f] with R in mesh C order."""
     nk = x.shape[0]
-    t = np.einsum("kim,kmp->kip", x, coeffs)                      # T^k_{Ip}
+    t = np.matmul(x, coeffs)                                      # T^k_{Ip} = sum_mu X C
     j = geo.kmesh_indices(kmesh)
     m = np.asarray(kmesh, dtype=np.float64)
     phase = np.exp(2j * np.pi * ((j[:, None, :] * j[None, :, :]) / m).sum(-1))  # [R, k]
-    return np.einsum("rk,kip->rip", phase, t) / np.sqrt(nk)
+    # sum over k as one matrix product: [R, k] x [k, (I p)]
+    psi = (phase @ t.reshape(nk, -1)).reshape((nk,) + t.shape[1:])
+    return psi / np.sqrt(nk)
 
 
 def fragment_r(x, coeffs, kmesh):
@@ -194,7 +196,9 @@ def fragment_r(x, coeffs, kmesh):
     j = geo.kmesh_indices(kmesh)
     m = np.asarray(kmesh, dtype=np.float64)
     phase = np.exp(-2j * np.pi * ((j[:, None, :] * j[None, :, :]) / m).sum(-1))  # [q, R]
-    return np.einsum("QR,Ripq->Qipq", phase, pair) / np.sqrt(nk)
+    # sum over R as one matrix product: [q, R] x [R, (I p q)]
+    r = (phase @ pair.reshape(nk, -1)).reshape(pair.shape)
+    return r / np.sqrt(nk)
 
 
 def fragment_eri(x, coeffs, w, kmesh):

@@ -188,20 +188,7 @@ __global__ __launch_bounds__(256) void col_kernel(GridFftArgs a) {
     x[1] = k_axis(col / a.n3, jw[1], a.n2, a.m2, t[1]);
     x[2] = k_axis(col % a.n3, jw[2], a.n3, a.m3, t[2]);
     const double f = coef * sqrt(inv_k2_mean(x, t, a.recip));
-    const cplx v = cscale(buf[idx], f);
-    if (a.fmt == 0) {
-      base[(long long)i1 * n23 + col] = v;
-    } else {
-      const long long off = (long long)qi * a.split_q + (long long)I * a.split_ld + (long long)i1 * n23 + col;
-      store_fmt(a.split, off, a.split_plane, a.fmt, v);
-    }
-  }
-  // zero the row padding of the split output (grid points N_g .. ld-1)
-  if (a.fmt != 0 && cb == ncb - 1) {
-    const long long ng = (long long)a.n1 * n23;
-    for (long long g = ng + threadIdx.x; g < a.split_ld; g += blockDim.x)
-      store_fmt(a.split, (long long)qi * a.split_q + (long long)I * a.split_ld + g, a.split_plane, a.fmt,
-                cmk(0.0, 0.0));
+    base[(long long)i1 * n23 + col] = cscale(buf[idx], f);
   }
 }
 
@@ -366,228 +353,8 @@ __global__ __launch_bounds__(256) void col_kernel_c(GridFftArgs a) {
     x[1] = k_axis(col / N, jw[1], N, a.m2, t[1]);
     x[2] = k_axis(col % N, jw[2], N, a.m3, t[2]);
     const double f = coef * sqrt(inv_k2_mean(x, t, a.recip));
-    const cplx v = cscale(buf[idx], f);
-    if (a.fmt == 0) {
-      base[(long long)i1 * N2 + col] = v;
-    } else {
-      const long long off = (long long)qi * a.split_q + (long long)I * a.split_ld + (long long)i1 * N2 + col;
-      store_fmt(a.split, off, a.split_plane, a.fmt, v);
-    }
+    base[(long long)i1 * N2 + col] = cscale(buf[idx], f);
   }
-  if (a.fmt != 0 && cb == NCB - 1) {
-    const long long ng = (long long)N * N2;
-    for (long long g = ng + threadIdx.x; g < a.split_ld; g += blockDim.x)
-      store_fmt(a.split, (long long)qi * a.split_q + (long long)I * a.split_ld + g, a.split_plane, a.fmt,
-                cmk(0.0, 0.0));
-  }
-}
-
-// ---- one-pass variant for the mixed precisions (cubic N x N x N, N*N <= 1024,
-// N = NA * NB with both factors <= 8) ----
-// One workgroup of N*N threads per (q, I).  Every thread holds one line of N
-// points in FP32 registers and transforms it there; two transposes through a
-// padded LDS plane bring the other two axes into the registers in turn:
-//   load : thread (i2, i3) holds the i1 line (lanes run along i3: the c128
-//          input rows are read as contiguous runs), phase applied, FFT i1;
-//   LDS  : thread (k1, i2) takes the i3 line, FFT i3;
-//   LDS  : thread (k1, k3) takes the i2 line, FFT i2, Coulomb factor, and the
-//          split output is written with the lanes running along k3.
-// One HBM read of the c128 input and one write of the split output per point.
-// The FP32 rounding of the transform (a few 1e-8 relative) is far below the
-// rounding of the FP32 / bf16 hi+lo operands it feeds.
-// forward DFT of the N values in registers: v[j] -> sum_j v[j] exp(-2 pi i jk/N)
-template <int N>
-__device__ inline void fft_reg(float2 (&v)[N]) {
-  constexpr int NA = radix_a<N>(), NB = N / NA;
-  constexpr TwF<N> tw{};
-  float2 y[NA][NB];
-#pragma unroll
-  for (int j2 = 0; j2 < NB; ++j2) {
-    float2 x[NA], z[NA];
-#pragma unroll
-    for (int j1 = 0; j1 < NA; ++j1) x[j1] = v[NB * j1 + j2];
-    small_dft_f<NA>(x, z);
-#pragma unroll
-    for (int k1 = 0; k1 < NA; ++k1) y[k1][j2] = rot_f(z[k1], tw.c[(j2 * k1) % N], tw.s[(j2 * k1) % N]);
-  }
-#pragma unroll
-  for (int k1 = 0; k1 < NA; ++k1) {
-    float2 x[NB], z[NB];
-#pragma unroll
-    for (int j2 = 0; j2 < NB; ++j2) x[j2] = y[k1][j2];
-    small_dft_f<NB>(x, z);
-#pragma unroll
-    for (int k2 = 0; k2 < NB; ++k2) v[k1 + NA * k2] = z[k2];
-  }
-}
-
-// Redistribute the lines through one padded LDS plane: this thread's value j
-// goes to ex[wbase + j * wstride]; afterwards it holds ex[rbase + j * rstride].
-template <int N>
-__device__ inline void exchange(float* ex, float2 (&v)[N], int wbase, int wstride, int rbase,
-                                int rstride) {
-  float t[N];
-#pragma unroll
-  for (int j = 0; j < N; ++j) ex[wbase + j * wstride] = v[j].x;
-  __syncthreads();
-#pragma unroll
-  for (int j = 0; j < N; ++j) t[j] = ex[rbase + j * rstride];
-  __syncthreads();
-#pragma unroll
-  for (int j = 0; j < N; ++j) ex[wbase + j * wstride] = v[j].y;
-  __syncthreads();
-#pragma unroll
-  for (int j = 0; j < N; ++j) v[j] = make_float2(t[j], ex[rbase + j * rstride]);
-  __syncthreads();
-}
-
-// IN32: eta read as complex FP32 from data32 instead of c128 from data
-template <int N, bool IN32>
-__global__ __launch_bounds__(N * N) void fft3_reg_kernel(GridFftArgs a) {
-  constexpr int N2 = N * N, P = N + 1;
-  extern __shared__ cplx sm[];
-  float* ex = (float*)sm;                           // [N][N][P] floats
-  float2* ph = (float2*)(ex + N * N * P);           // [3][N] Bloch phase per axis
-  const int t = threadIdx.x;
-  const int I = (int)(blockIdx.x % (unsigned)a.n_ip);
-  const int qi = (int)(blockIdx.x / (unsigned)a.n_ip);
-  double qf[3];
-  q_frac(a, q_of(a, qi), qf);
-  if (t < 3 * N) {
-    const int ax = t / N, i = t % N;
-    const cplx e = cexpipi(-2.0 * qf[ax] * i / N);
-    ph[t] = make_float2((float)e.x, (float)e.y);
-  }
-  __syncthreads();
-  // load: thread (i2, i3) = t holds the i1 line
-  const long long src0 = (long long)qi * a.q_stride + (long long)I * N * N2 + t;
-  const int i2 = t / N, i3 = t % N;
-  const float2 p2 = ph[N + i2], p3 = ph[2 * N + i3];
-  const float2 p23 = make_float2(p2.x * p3.x - p2.y * p3.y, p2.x * p3.y + p2.y * p3.x);
-  float2 v[N];
-#pragma unroll
-  for (int i1 = 0; i1 < N; ++i1) {
-    float dx, dy;
-    if (IN32) {
-      const float2 d = a.data32[src0 + (long long)i1 * N2];
-      dx = d.x;
-      dy = d.y;
-    } else {
-      const cplx d = a.data[src0 + (long long)i1 * N2];
-      dx = (float)d.x;
-      dy = (float)d.y;
-    }
-    const float2 p1 = ph[i1];
-    const float2 pp = make_float2(p1.x * p23.x - p1.y * p23.y, p1.x * p23.y + p1.y * p23.x);
-    v[i1] = make_float2(dx * pp.x - dy * pp.y, dx * pp.y + dy * pp.x);
-  }
-  fft_reg<N>(v);                                      // along i1
-  // (k1, i2, i3) at ex[k1*N*P + i2*P + i3]; thread (k1, i2) = t takes the i3 line
-  exchange<N>(ex, v, i2 * P + i3, N * P, (t / N) * N * P + (t % N) * P, 1);
-  fft_reg<N>(v);                                      // along i3
-  // (k1, i2, k3) at ex[k1*N*P + k3*P + i2]; thread (k1, k3) = t takes the i2 line
-  exchange<N>(ex, v, (t / N) * N * P + (t % N), P, (t / N) * N * P + (t % N) * P, 1);
-  fft_reg<N>(v);                                      // along i2
-  // Coulomb factor and split store: thread (k1, k3), register k2
-  // Coulomb factor of eq. (7) from the per-q table (it depends on q and the
-  // grid index only): thread (k1, k3), register k2
-  const int k1 = t / N, k3 = t % N;
-  const float* fq = a.fac + (long long)qi * N * N2 + k1 * N2 + k3;
-#pragma unroll
-  for (int k2 = 0; k2 < N; ++k2) {
-    const float f = fq[k2 * N];
-    v[k2] = make_float2(v[k2].x * f, v[k2].y * f);
-  }
-  const long long row = (long long)qi * a.split_q + (long long)I * a.split_ld + (long long)k1 * N2 + k3;
-  if constexpr (N % 8 == 0 && 64 % N == 0) {
-    if (a.fmt == 2) {
-      // bf16 hi/lo: a wave holds 64/N whole rows (k1) of N points for every
-      // k2; rows of 8 k2 at a time are assembled in LDS (N * 8 contiguous
-      // bytes each) and written with 16-byte stores
-      constexpr int RW = 64 / N, CK = 8;
-      const int lane = t & 63, wv = t >> 6;
-      unsigned short* st = (unsigned short*)ex + wv * (CK * RW * N * 4);
-      const int kl = lane / N;
-      const int eo = (k3 >> 3) * 32 + (k3 & 7);
-      const long long base = (long long)qi * a.split_q + (long long)I * a.split_ld;
-#pragma unroll
-      for (int c0 = 0; c0 < N; c0 += CK) {
-#pragma unroll
-        for (int u = 0; u < CK; ++u) {
-          const float re = v[c0 + u].x, im = v[c0 + u].y;
-          const unsigned short rh = bf16_bits_of(re), ih = bf16_bits_of(im);
-          unsigned short* e = st + (u * RW + kl) * (N * 4) + eo;
-          e[0] = rh;
-          e[8] = bf16_bits_of(re - bf16_value(rh));
-          e[16] = ih;
-          e[24] = bf16_bits_of(im - bf16_value(ih));
-        }
-        __builtin_amdgcn_wave_barrier();
-#pragma unroll
-        for (int h = 0; h < CK * RW * (N / 2) / 64; ++h) {
-          const int c = h * 64 + lane, r = c / (N / 2), part = c % (N / 2);
-          const int u = r / RW, k1r = wv * RW + r % RW;
-          *(uint4*)((unsigned short*)a.split + 4 * (base + (long long)k1r * N2 + (long long)(c0 + u) * N) +
-                    part * 8) = *(const uint4*)(st + r * (N * 4) + part * 8);
-        }
-        __builtin_amdgcn_wave_barrier();
-      }
-      for (long long g = (long long)N * N2 + t; g < a.split_ld; g += N2)
-        store_fmt(a.split, base + g, a.split_plane, a.fmt, cmk(0.0, 0.0));
-      return;
-    }
-  }
-#pragma unroll
-  for (int k2 = 0; k2 < N; ++k2) {
-    const float re = v[k2].x, im = v[k2].y;
-    const long long off = row + (long long)k2 * N;
-    if (a.fmt == 1) {
-      float* o = (float*)a.split;
-      o[off] = re;
-      o[a.split_plane + off] = im;
-    } else {
-      store_bf16x3((unsigned short*)a.split, off, re, im);
-    }
-  }
-  // zero the row padding of the split output (grid points N^3 .. ld-1)
-  for (long long g = (long long)N * N2 + t; g < a.split_ld; g += N2)
-    store_fmt(a.split, (long long)qi * a.split_q + (long long)I * a.split_ld + g, a.split_plane, a.fmt,
-              cmk(0.0, 0.0));
-}
-
-// fac[qi][g] = sqrt(Omega 4 pi mean(1/|K|^2)) / N_g for q = q0 + qi and grid
-// index g (C order): the weight of eq. (7) on the nearest representative(s)
-// of K = G + q, in FP64 and rounded once.
-__global__ __launch_bounds__(256) void coulomb_table_kernel(GridFftArgs a) {
-  const long long ng = (long long)a.n1 * a.n2 * a.n3;
-  const int qi = blockIdx.y;
-  int jw[3];
-  q_wrapped(a, q_of(a, qi), jw);
-  const double coef = sqrt(4.0 * M_PI * a.volume) / (double)ng;
-  for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < ng; g += (long long)gridDim.x * blockDim.x) {
-    const int i1 = (int)(g / ((long long)a.n2 * a.n3)), i2 = (int)((g / a.n3) % a.n2), i3 = (int)(g % a.n3);
-    double x[3];
-    bool t[3];
-    x[0] = k_axis(i1, jw[0], a.n1, a.m1, t[0]);
-    x[1] = k_axis(i2, jw[1], a.n2, a.m2, t[1]);
-    x[2] = k_axis(i3, jw[2], a.n3, a.m3, t[2]);
-    a.fac[(long long)qi * ng + g] = (float)(coef * sqrt(inv_k2_mean(x, t, a.recip)));
-  }
-}
-
-template <int N>
-hipError_t launch_reg(const GridFftArgs& a, hipStream_t s) {
-  static_assert(N * N <= 1024 && radix_a<N>() != 0, "one-pass FFT shape");
-  const long long items = (long long)a.nq * a.n_ip;
-  if (items <= 0) return hipSuccess;
-  // transposes (N x N x (N+1) floats) + phase tables; the staged output
-  // rows of the bf16 path reuse it (N * N * 64 bytes)
-  const size_t lds = std::max(((size_t)N * N * (N + 1) + 6 * N) * sizeof(float), (size_t)N * N * 64);
-  if (!a.fac) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(coulomb_table_kernel, dim3((N * N * N + 255) / 256, a.nq), dim3(256), 0, s, a);
-  if (a.data32) hipLaunchKernelGGL((fft3_reg_kernel<N, true>), dim3((unsigned)items), dim3(N * N), lds, s, a);
-  else hipLaunchKernelGGL((fft3_reg_kernel<N, false>), dim3((unsigned)items), dim3(N * N), lds, s, a);
-  return hipGetLastError();
 }
 
 template <int N>
@@ -615,32 +382,7 @@ hipError_t launch_cubic(const GridFftArgs& a, hipStream_t s) {
 
 }  // namespace
 
-bool gridfft_reg_grid(int n1, int n2, int n3) {
-  if (n1 != n2 || n2 != n3) return false;
-  switch (n1) {
-    case 6: case 8: case 10: case 12: case 16: case 18: case 20: case 24: case 30: case 32: return true;
-    default: return false;
-  }
-}
-
 hipError_t gridfft_launch(const GridFftArgs& a, hipStream_t s) {
-  // FP32 input exists only for the register kernel of the mixed formats
-  if (a.data32 && (a.fmt == 0 || !gridfft_reg_grid(a.n1, a.n2, a.n3))) return hipErrorInvalidValue;
-  if (a.fmt != 0 && a.n1 == a.n2 && a.n2 == a.n3) {
-    switch (a.n1) {
-      case 6: return launch_reg<6>(a, s);
-      case 8: return launch_reg<8>(a, s);
-      case 10: return launch_reg<10>(a, s);
-      case 12: return launch_reg<12>(a, s);
-      case 16: return launch_reg<16>(a, s);
-      case 18: return launch_reg<18>(a, s);
-      case 20: return launch_reg<20>(a, s);
-      case 24: return launch_reg<24>(a, s);
-      case 30: return launch_reg<30>(a, s);
-      case 32: return launch_reg<32>(a, s);
-      default: break;
-    }
-  }
   if (a.n1 == a.n2 && a.n2 == a.n3) {
     switch (a.n1) {
       case 6: return launch_cubic<6>(a, s);

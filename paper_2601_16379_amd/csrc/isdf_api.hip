@@ -342,15 +342,12 @@ struct isdf_ctx_s {
   int device = 0;
   // resident device data
   DevBuf phi, ip, xt, pi, eta, lt, w, work1, work2, work3, pinv_ws, perm, rank, rchunk, flag;
-  DevBuf wt64, wt32, wt16, eta_split;   // W transposed in the three GEMM formats; split eta~
+  DevBuf wt64, wt32, wt16;              // W transposed in the three GEMM operand formats
   DevBuf dmax, cflag;                   // factorisation: largest diagonal, breakdown flags
-  DevBuf fac;                           // per-q Coulomb factors of the mixed grid FFT (FP32, N_q x N_g)
-  long long ld_ip = 0, ld_g = 0;        // row pitches of split operands (multiples of 16)
+  long long ld_ip = 0;                  // row pitch of the split operands (a multiple of 16)
   bool fitted = false, kernel_ready = false, eta_valid = false;
   bool kernel_pending = false;          // a fit whose eta (resident or per batch) the kernel has not consumed
   bool etat_valid = false;              // eta~ of every class still held after the kernel (no q batches)
-  bool eta32 = false;               // eta (and the RHS tile) held as complex FP32
-  int kernel_prec = 0;              // precision of the last isdf_coulomb_kernel
   // launch tiling of the fragment contraction (isdf_autotune / isdf_set_tiling):
   // classes per ERI launch (the K extent of one launch) and workgroups per CU
   // of its persistent GEMM launches (0: default)
@@ -465,41 +462,33 @@ long long nip2(const isdf_ctx c) { return (long long)c->nip * c->nip; }
 // --------------------------------------------------------------------------
 // eta^q_I(r) of the classes that qslot (device map q -> eta slot, or -1)
 // selects, r-tiled: T^k_I(r) = sum_mu X^k_{I mu} conj(phi^k_mu(r)), then the
-// k convolution of eq. (5) (Algorithm 1 with Y = phi); T and eta as complex
-// FP32 when c->eta32 (FP32 matrix cores for T, FP64 convolution).  The main
-// stream continues after the last convolution; the third stream starts
-// after `start` (recorded on the main stream).
+// k convolution of eq. (5) (Algorithm 1 with Y = phi), all in FP64.  Two tile
+// buffers alternate, so the k convolution of tile i (third stream) runs
+// beside the pre-product of tile i + 1.  The main stream continues after the
+// last convolution; the third stream starts after `start` (recorded on the
+// main stream).
 void rhs_eta(isdf_ctx c, const int* qslot, hipEvent_t start) {
   hipStream_t s = c->stream;
   const int nk = c->nk, norb = c->norb, nip = c->nip;
   const long long ng = c->ng;
-  float2* const t32 = c->eta32 ? c->rchunk.as<float2>() : nullptr;
-  // complex FP32 tiles take half the buffer: two of them alternate, so the
-  // k convolution of tile i (third stream) runs beside the pre-product of
-  // tile i + 1; the FP64 tile fills the buffer and the two alternate with it
-  const int nbuf = c->eta32 ? 2 : 1;
+  constexpr int nbuf = 2;
   HIPCHK(hipStreamWaitEvent(c->aux2, start, 0));
   int it = 0;
   for (long long r0 = 0; r0 < ng; r0 += c->rc, ++it) {
     const int b = it % nbuf;
-    const long long toff = (long long)b * nk * nip * c->rc;       // elements of the tile's own type
+    cplx* tile = c->rchunk.as<cplx>() + (long long)b * nk * nip * c->rc;
     if (it >= nbuf) HIPCHK(hipStreamWaitEvent(s, c->ev_kc[b], 0));   // tile b read by its convolution
     c->timer.begin("rhs_t", s);
     const int rcur = (int)std::min<long long>(c->rc, ng - r0);
-    HIPCHK(rhs_t_launch(c->xt.as<cplx>(), c->phi.as<cplx>(), c->rchunk.as<cplx>() + toff,
-                        t32 ? t32 + toff : nullptr, nk, norb, nip, ng, r0, rcur, s));
+    HIPCHK(rhs_t_launch(c->xt.as<cplx>(), c->phi.as<cplx>(), tile, nk, norb, nip, ng, r0, rcur, s));
     c->timer.end("rhs_t", s);
     HIPCHK(hipEventRecord(c->ev_rt[b], s));
     HIPCHK(hipStreamWaitEvent(c->aux2, c->ev_rt[b], 0));
     c->timer.begin("rhs_kconv", c->aux2);
     KconvArgs a;
     memset(&a, 0, sizeof(a));
-    a.in = c->rchunk.as<cplx>() + toff;
+    a.in = tile;
     a.out = c->eta.as<cplx>() + r0;
-    if (c->eta32) {
-      a.in32 = t32 + toff;
-      a.out32 = c->eta.as<float2>() + r0;
-    }
     a.in_kstride = (long long)nip * rcur;
     a.out_qstride = (long long)nip * ng;
     a.n_elem = (long long)nip * rcur;
@@ -519,11 +508,48 @@ void rhs_eta(isdf_ctx c, const int* qslot, hipEvent_t start) {
   HIPCHK(hipStreamWaitEvent(s, c->ev_kc[(it - 1) % nbuf], 0));
 }
 
+// Buffers used only inside isdf_fit and isdf_coulomb_kernel: T^k of the
+// metric and V per class (work1), the factorisation and pseudo-inverse
+// scratch (lt, work2, work3, pinv_ws), the RHS tile and eta.  Allocated at
+// create and again by a fit after a q-batched kernel released them.
+void ensure_fit_buffers(isdf_ctx c) {
+  const size_t e = sizeof(cplx);
+  const size_t m2 = (size_t)c->nh * c->nip * c->nip * e;   // one matrix per class {q, -q}
+  c->lt.ensure(m2);
+  c->work1.ensure((size_t)c->nk * c->nip * c->nip * e);    // T^k of the metric, then V per class
+  c->pinv_ws.ensure((size_t)c->nh * ((size_t)c->nip * 64 + 4096) * e);   // blocked L^{-1} scratch
+  c->work2.ensure(m2);
+  c->work3.ensure(m2);
+  c->rchunk.ensure(2 * (size_t)c->nk * c->nip * c->rc * e);   // two RHS tiles
+  c->eta.ensure((size_t)c->qb * c->nip * c->ng * e);
+}
+
+// After a kernel that ran in q batches (memory-bound cells), the transient
+// buffers go back to the device for the fragment workspaces; X, Pi^q, W^q
+// and its operand copies stay.
+void release_fit_buffers(isdf_ctx c) {
+  for (DevBuf* b : {&c->lt, &c->work1, &c->pinv_ws, &c->work2, &c->work3, &c->rchunk, &c->eta})
+    b->release();
+}
+
+// The fit reclaims the memory of idle fragment workspaces (the context is
+// held exclusively: no batch is in flight).
+void release_workspaces(isdf_ctx c) {
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->sync_ws.mem.release();
+  std::lock_guard<std::mutex> lk(c->mu);
+  for (Workspace* w : c->ws_pool) w->mem.release();
+}
+
 void do_fit(isdf_ctx c, int prec) {
   hipStream_t s = c->stream;
   const int nk = c->nk, norb = c->norb, nip = c->nip;
   const int nh = c->nh;                 // classes {q, -q}: Pi, eta, W are kept for one q of each
   const long long ng = c->ng;
+  if (!c->eta.p) {
+    release_workspaces(c);
+    ensure_fit_buffers(c);
+  }
   c->arena.reset(s);
   c->arena.reserve(((size_t)1 << 20) + (size_t)c->nh * 1024);
   // the second stream may still be forming the previous fit's pseudo-inverse
@@ -567,9 +593,8 @@ void do_fit(isdf_ctx c, int prec) {
   HIPCHK(hipEventRecord(c->ev_fork, s));
   HIPCHK(hipStreamWaitEvent(c->aux, c->ev_fork, 0));
   // eta^q_I(r) for every class now when they all fit (else per q batch in
-  // isdf_coulomb_kernel).  For a mixed precision kernel whose grid FFT reads
-  // FP32, T and eta are stored as complex FP32.
-  c->eta32 = prec != ISDF_FP64 && gridfft_reg_grid(c->n[0], c->n[1], c->n[2]);
+  // isdf_coulomb_kernel)
+  (void)prec;
   c->eta_batched = c->qb < nh;
   if (!c->eta_batched) rhs_eta(c, c->qmap.as<int>(), c->ev_fork);
   c->timer.begin("chol", c->aux);
@@ -692,8 +717,12 @@ void do_fit(isdf_ctx c, int prec) {
 // --------------------------------------------------------------------------
 void do_kernel(isdf_ctx c, int prec) {
   if (!c->fitted || !c->kernel_pending) throw Fail{ISDF_E_STATE, "isdf_fit must run before isdf_coulomb_kernel"};
-  if (c->eta32 && prec == ISDF_FP64)
-    throw Fail{ISDF_E_STATE, "eta was stored in FP32 by a mixed-precision fit; fit with ISDF_FP64 first"};
+  // The kernel is FP64 in every precision: W^q = Pi^+ V^q Pi^+ amplifies the
+  // rounding of eta and V^q by up to cond(Pi^q) on each side, and at the
+  // conditioning of the workloads (1e4-5e5) FP32 or bf16 hi+lo eta / V^q move
+  // the ERIs by 3e-6-2e-5 Eh.  The mixed precisions apply to the fragment
+  // GEMMs, whose error with an FP64 W^q stays far smaller.
+  (void)prec;
   hipStream_t s = c->stream;
   const int nk = c->nk, nip = c->nip;
   const int nh = c->nh;                 // one q per class {q, -q}: W^{-q} = conj W^q
@@ -706,10 +735,6 @@ void do_kernel(isdf_ctx c, int prec) {
   // q batches of qb classes (one batch, eta formed by the fit, when they all
   // fit); per batch: eta (when batched), the grid FFT, V^q
   const int qb = c->eta_batched ? c->qb : nh;
-  const long long split_plane = (long long)qb * nip * c->ld_g;
-  if (prec != ISDF_FP64) c->eta_split.ensure((size_t)split_plane * 8);
-  const bool reg = prec != ISDF_FP64 && gridfft_reg_grid(c->n[0], c->n[1], c->n[2]);
-  if (reg) c->fac.ensure((size_t)qb * ng * sizeof(float));
   std::vector<int> bslot(nk);
   for (int h0 = 0; h0 < nh; h0 += qb) {
     const int nb = std::min(qb, nh - h0);
@@ -723,20 +748,12 @@ void do_kernel(isdf_ctx c, int prec) {
       HIPCHK(hipEventRecord(c->ev_fork, s));   // the previous batch's FFT has read eta
       rhs_eta(c, bs, c->ev_fork);
     }
-    // eta~^q_I(G) = sqrt(Omega 4pi/|K|^2)/N_g FFT[eta^q_I(r) exp(-iq.r)]   (eqs. (6)-(7));
-    // in place (FP64) or into the split operand format of the V GEMM (mixed)
+    // eta~^q_I(G) = sqrt(Omega 4pi/|K|^2)/N_g FFT[eta^q_I(r) exp(-iq.r)]   (eqs. (6)-(7)), in place
     c->timer.begin("grid_fft", s);
     {
       GridFftArgs a;
       memset(&a, 0, sizeof(a));
       a.data = c->eta.as<cplx>();
-      a.data32 = c->eta32 ? c->eta.as<float2>() : nullptr;
-      if (reg) a.fac = c->fac.as<float>();   // per-q Coulomb factors of the one-pass FFT
-      a.fmt = prec;
-      a.split = c->eta_split.p;
-      a.split_ld = c->ld_g;
-      a.split_plane = split_plane;
-      a.split_q = (long long)nip * c->ld_g;
       a.n1 = c->n[0]; a.n2 = c->n[1]; a.n3 = c->n[2];
       a.m1 = c->m[0]; a.m2 = c->m[1]; a.m3 = c->m[2];
       a.q0 = 0;
@@ -749,37 +766,17 @@ void do_kernel(isdf_ctx c, int prec) {
       HIPCHK(gridfft_launch(a, s));
     }
     c->timer.end("grid_fft", s);
-    // V^q = eta~ eta~^H  (Hermitian; lower tiles computed and mirrored); in the
-    // mixed precisions FP32 partial sums over 8192 grid points, FP64 across them
+    // V^q = eta~ eta~^H  (Hermitian; lower tiles computed and mirrored), FP64 MFMA
     c->timer.begin("v_gemm", s);
     {
       cplx* vout = c->work1.as<cplx>() + (long long)h0 * nip2(c);
       std::vector<NtDesc> d(1);
-      if (prec == ISDF_FP64) {
-        d[0] = mknt(c->eta.p, ng, c->eta.p, ng, vout, nip, nip, nip, (int)ng);
-        d[0].sA_bat = d[0].sB_bat = (long long)nip * ng;
-        d[0].batch = nb;
-        d[0].sC_bat = nip2(c);
-        d[0].herm = 1;
-        run_nt(c->arena, prec, 2, d, s, 1);
-      } else {
-        // one large-tile launch per block of 8192 grid points: FP32 inside a
-        // block, FP64 accumulation into V across blocks; lower tiles, then mirror
-        d[0] = mknt(c->eta_split.p, c->ld_g, c->eta_split.p, c->ld_g, vout, nip, nip, nip, (int)ng);
-        d[0].a_plane = d[0].b_plane = split_plane;
-        const int kseg = 8192;
-        d[0].Kseg = (int)std::min<long long>(kseg, ng);
-        d[0].nseg = (int)((ng + d[0].Kseg - 1) / d[0].Kseg);
-        d[0].Klast = (int)(ng - (long long)(d[0].nseg - 1) * d[0].Kseg);
-        d[0].sA_seg = d[0].sB_seg = d[0].Kseg;
-        d[0].sA_bat = d[0].sB_bat = (long long)nip * c->ld_g;
-        d[0].batch = nb;
-        d[0].sC_bat = nip2(c);
-        d[0].herm = 2;
-        d[0].epi = 1;
-        run_big(c->arena, prec, 2, d, d[0].nseg, s, 1);
-        HIPCHK(herm_fill_launch(vout, nip, nip, nip2(c), nb, s));
-      }
+      d[0] = mknt(c->eta.p, ng, c->eta.p, ng, vout, nip, nip, nip, (int)ng);
+      d[0].sA_bat = d[0].sB_bat = (long long)nip * ng;
+      d[0].batch = nb;
+      d[0].sC_bat = nip2(c);
+      d[0].herm = 1;
+      run_nt(c->arena, ISDF_FP64, 2, d, s, 1);
     }
     c->timer.end("v_gemm", s);
   }
@@ -829,7 +826,7 @@ void do_kernel(isdf_ctx c, int prec) {
     c->timer.collect(&c->totals);
   }
   if (bad) throw Fail{ISDF_E_NUMERIC, "non-finite entries in W^q"};
-  c->kernel_prec = prec;
+  if (c->eta_batched) release_fit_buffers(c);
   c->kernel_ready = true;
 }
 
@@ -1413,7 +1410,7 @@ int64_t isdf_storage_model_bytes(int64_t n_k, int64_t n_ip, int64_t n_ao) {
 }
 
 #ifndef ISDF_RHS_TILE_BYTES
-#define ISDF_RHS_TILE_BYTES (2LL << 30)
+#define ISDF_RHS_TILE_BYTES (1LL << 30)
 #endif
 
 static long long rchunk_len(long long ng, int nk, int nip) {
@@ -1533,40 +1530,39 @@ isdf_status isdf_create(isdf_ctx* out, const double* lattice, const int32_t grid
     const int nh = c->nh;
     const size_t m2 = (size_t)nh * n_ip * n_ip * e;   // one matrix per class {q, -q}
     c->pi.alloc(m2);
-    c->lt.alloc(m2);
     c->w.alloc(m2);
-    c->work1.alloc((size_t)nk * n_ip * n_ip * e);      // T^k of the metric, then V per class
-    c->pinv_ws.alloc((size_t)nh * ((size_t)n_ip * 64 + 4096) * e);   // blocked L^{-1} scratch
     // row pitches of the split operands: multiples of 16 elements, so that in
     // the bf16 hi/lo format every 16-k step of a row is one aligned 128-byte line
     c->ld_ip = (n_ip + 15) / 16 * 16;
-    c->ld_g = (ng + 15) / 16 * 16;
-    c->work2.alloc(m2);
-    c->work3.alloc(m2);
     c->wt64.alloc((size_t)nh * n_ip * c->ld_ip * e);
     c->wt32.alloc((size_t)nh * n_ip * c->ld_ip * 8);
     c->wt16.alloc((size_t)nh * n_ip * c->ld_ip * 8);
-    c->rchunk.alloc((size_t)nk * n_ip * c->rc * e);
     c->perm.alloc(sizeof(int) * nh * n_ip);
     c->rank.alloc(sizeof(int) * nh);
     c->flag.alloc(sizeof(int));
     c->dmax.alloc(sizeof(double) * nh);
     c->cflag.alloc(sizeof(int) * nh);
-    // classes per q batch of eta (FP64 size), the split eta~ and the factor
-    // table: all of them when that fits in 60 % of the memory left, else the
-    // largest batch that does (ISDF_Q_BATCH(n) caps it); the rest of the
-    // memory is for fragment workspaces
+    // classes per q batch of eta: all of them when that fits in 60 % of the memory left after the
+    // resident and the other transient buffers (the rest is for fragment
+    // workspaces), else the largest batch that fits in 85 % of it -- a
+    // q-batched kernel hands the transient buffers back to the fragment
+    // workspaces when it ends.  ISDF_Q_BATCH(n) caps the batch.
     {
-      const size_t per_class = (size_t)n_ip * ng * e + (size_t)n_ip * c->ld_g * 8 + (size_t)ng * 4;
+      const size_t per_class = (size_t)n_ip * ng * e;
+      const size_t m2 = (size_t)nh * n_ip * n_ip * e;
+      const size_t transient = 3 * m2 + (size_t)nk * n_ip * n_ip * e +
+                               (size_t)nh * ((size_t)n_ip * 64 + 4096) * e + 2 * (size_t)nk * n_ip * c->rc * e;
       size_t fr = 0, tot = 0;
       HIPCHK(hipMemGetInfo(&fr, &tot));
-      long long qb = (long long)(0.6 * (double)fr / (double)per_class);
+      const double avail = fr > transient ? (double)(fr - transient) : 0.0;
+      long long qb = (long long)(0.6 * avail / (double)per_class);
+      if (qb < nh) qb = (long long)(0.85 * avail / (double)per_class);
       const int cap = (int)((flags >> 16) & 0xFFFFu);
       if (cap > 0) qb = std::min<long long>(qb, cap);
       if (qb < 1) throw Fail{ISDF_E_NOMEM, "no room for the eta of one q class"};
       c->qb = (int)std::min<long long>(qb, nh);
     }
-    c->eta.alloc((size_t)c->qb * n_ip * ng * e);
+    ensure_fit_buffers(c);
     c->qmap.alloc(sizeof(int) * (nk + 2 * c->nh));
     {
       std::vector<int> qm(c->qslot_h);
@@ -1608,10 +1604,6 @@ isdf_status isdf_fit(isdf_ctx ctx, isdf_precision prec) {
   });
 }
 
-int32_t isdf_fit_eta_fp32(const int32_t grid[3]) {
-  if (!grid) return 0;
-  return gridfft_reg_grid(grid[0], grid[1], grid[2]) ? 1 : 0;
-}
 
 isdf_status isdf_coulomb_kernel(isdf_ctx ctx, isdf_precision prec) {
   return guarded(ctx, [&] {
@@ -1695,17 +1687,9 @@ isdf_status isdf_get_rhs(isdf_ctx ctx, int32_t q, void* out) {
   const int hs = class_slot(ctx, q, &cj);
   return guarded(ctx, [&] {
     cplx* o = (cplx*)out;
-    if (!ctx->eta32) {
-      HIPCHK(hipMemcpyAsync(o, ctx->eta.as<cplx>() + (long long)hs * n, n * sizeof(cplx), hipMemcpyDeviceToHost,
-                            ctx->stream));
-      HIPCHK(hipStreamSynchronize(ctx->stream));
-    } else {
-      std::vector<float2> h(n);
-      HIPCHK(hipMemcpyAsync(h.data(), ctx->eta.as<float2>() + (long long)hs * n, n * sizeof(float2),
-                            hipMemcpyDeviceToHost, ctx->stream));
-      HIPCHK(hipStreamSynchronize(ctx->stream));
-      for (size_t i = 0; i < n; ++i) o[i] = cmk((double)h[i].x, (double)h[i].y);
-    }
+    HIPCHK(hipMemcpyAsync(o, ctx->eta.as<cplx>() + (long long)hs * n, n * sizeof(cplx), hipMemcpyDeviceToHost,
+                          ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
     if (cj)
       for (size_t i = 0; i < n; ++i) o[i].y = -o[i].y;
   });
@@ -1716,76 +1700,34 @@ isdf_status isdf_get_eta_tilde(isdf_ctx ctx, int32_t q, void* out) {
   if (!ctx->kernel_ready) return fail(ctx, ISDF_E_STATE, "eta~ not computed (isdf_coulomb_kernel first)");
   if (!ctx->etat_valid) return fail(ctx, ISDF_E_STATE, "eta~ is not kept when the kernel runs in q batches");
   if (q < 0 || q >= ctx->nk || !out) return fail(ctx, ISDF_E_INVALID, "bad q");
-  const long long nip = ctx->nip, ng = ctx->ng, ldg = ctx->ld_g;
+  const long long nip = ctx->nip, ng = ctx->ng;
   // a q of no stored class: eta~^q(G) = conj(eta~^{-q}(G')) with G' the
   // index of -(G + q) - (-q) (per axis -s, or 1 - s where q sits on the
   // zone boundary of an even mesh), which the symmetric kernel weighs alike
   bool cj;
   const int hs = class_slot(ctx, q, &cj);
-  auto reflect = [&](cplx* o) {
-    if (!cj) return;
-    const int j[3] = {q / (ctx->m[1] * ctx->m[2]), (q / ctx->m[2]) % ctx->m[1], q % ctx->m[2]};
-    int dl[3];
-    for (int d = 0; d < 3; ++d) dl[d] = (ctx->m[d] % 2 == 0 && 2 * j[d] == ctx->m[d]) ? 1 : 0;
-    std::vector<cplx> row(ng);
-    for (long long i = 0; i < nip; ++i) {
-      cplx* r = o + i * ng;
-      for (long long g = 0; g < ng; ++g) {
-        const int s1 = (int)(g / ((long long)ctx->n[1] * ctx->n[2])), s2 = (int)((g / ctx->n[2]) % ctx->n[1]),
-                  s3 = (int)(g % ctx->n[2]);
-        const int t1 = ((dl[0] - s1) % ctx->n[0] + ctx->n[0]) % ctx->n[0];
-        const int t2 = ((dl[1] - s2) % ctx->n[1] + ctx->n[1]) % ctx->n[1];
-        const int t3 = ((dl[2] - s3) % ctx->n[2] + ctx->n[2]) % ctx->n[2];
-        const cplx v = r[((long long)t1 * ctx->n[1] + t2) * ctx->n[2] + t3];
-        row[g] = cmk(v.x, -v.y);
-      }
-      memcpy(r, row.data(), ng * sizeof(cplx));
+  const size_t b = (size_t)nip * ng * sizeof(cplx);
+  isdf_status st = get_mat(ctx, ctx->eta, (long long)hs * b, b, out);
+  if (st != ISDF_OK || !cj) return st;
+  const int j[3] = {q / (ctx->m[1] * ctx->m[2]), (q / ctx->m[2]) % ctx->m[1], q % ctx->m[2]};
+  int dl[3];
+  for (int d = 0; d < 3; ++d) dl[d] = (ctx->m[d] % 2 == 0 && 2 * j[d] == ctx->m[d]) ? 1 : 0;
+  cplx* o = (cplx*)out;
+  std::vector<cplx> row(ng);
+  for (long long i = 0; i < nip; ++i) {
+    cplx* r = o + i * ng;
+    for (long long g = 0; g < ng; ++g) {
+      const int s1 = (int)(g / ((long long)ctx->n[1] * ctx->n[2])), s2 = (int)((g / ctx->n[2]) % ctx->n[1]),
+                s3 = (int)(g % ctx->n[2]);
+      const int t1 = ((dl[0] - s1) % ctx->n[0] + ctx->n[0]) % ctx->n[0];
+      const int t2 = ((dl[1] - s2) % ctx->n[1] + ctx->n[1]) % ctx->n[1];
+      const int t3 = ((dl[2] - s3) % ctx->n[2] + ctx->n[2]) % ctx->n[2];
+      const cplx v = r[((long long)t1 * ctx->n[1] + t2) * ctx->n[2] + t3];
+      row[g] = cmk(v.x, -v.y);
     }
-  };
-  if (ctx->kernel_prec == ISDF_FP64) {
-    const size_t b = (size_t)nip * ng * sizeof(cplx);
-    isdf_status st = get_mat(ctx, ctx->eta, (long long)hs * b, b, out);
-    if (st == ISDF_OK) reflect((cplx*)out);
-    return st;
+    memcpy(r, row.data(), ng * sizeof(cplx));
   }
-  return guarded(ctx, [&] {
-    // the split operand of the V^q product, converted exactly to c128
-    // (FP32: two planes; bf16x3: hi/lo interleaved by groups of 8 elements)
-    const bool f32 = ctx->kernel_prec == ISDF_MIXED_FP32;
-    const long long plane = (long long)ctx->nh * nip * ldg;
-    const size_t rows = (size_t)nip * ldg;
-    std::vector<unsigned char> h(rows * 8);
-    if (f32) {
-      for (int pl = 0; pl < 2; ++pl)
-        HIPCHK(hipMemcpyAsync(h.data() + pl * rows * 4,
-                              ctx->eta_split.as<char>() + ((long long)pl * plane + (long long)hs * nip * ldg) * 4,
-                              rows * 4, hipMemcpyDeviceToHost, ctx->stream));
-    } else {
-      HIPCHK(hipMemcpyAsync(h.data(), ctx->eta_split.as<char>() + (long long)hs * nip * ldg * 8, rows * 8,
-                            hipMemcpyDeviceToHost, ctx->stream));
-    }
-    HIPCHK(hipStreamSynchronize(ctx->stream));
-    auto bf = [](const unsigned short* p, size_t i) {
-      uint32_t u = (uint32_t)p[i] << 16;
-      float f;
-      memcpy(&f, &u, 4);
-      return (double)f;
-    };
-    cplx* o = (cplx*)out;
-    for (long long i = 0; i < nip; ++i)
-      for (long long g = 0; g < ng; ++g) {
-        const long long e = i * ldg + g;
-        if (f32) {
-          const float* f = (const float*)h.data();
-          o[i * ng + g] = cmk((double)f[e], (double)f[rows + e]);
-        } else {
-          const unsigned short* u = (const unsigned short*)h.data();
-          o[i * ng + g] = cmk(bf(u, bf16x3_index(e, 0)) + bf(u, bf16x3_index(e, 1)),
-                              bf(u, bf16x3_index(e, 2)) + bf(u, bf16x3_index(e, 3)));
-        }
-      }
-    reflect(o);
-  });
+  return ISDF_OK;
 }
 
 isdf_status isdf_fragment_eri(isdf_ctx ctx, isdf_precision prec, int32_t n_frag, const int32_t* n_f,
@@ -1799,7 +1741,14 @@ isdf_status isdf_fragment_eri(isdf_ctx ctx, isdf_precision prec, int32_t n_frag,
         throw Fail{ISDF_E_INVALID, "bad fragment " + std::to_string(f)};
       fr.push_back(FragIn{n_f[f], C[f], eri[f], flags});
     }
-    enqueue_fragments(ctx, ctx->sync_ws, prec, fr, true, sync_cap(ctx->sync_ws));
+    const int forced = (int)((flags >> 8) & 0xFFu);
+    if (forced > 1) {
+      for (const FragIn& f : fr)
+        enqueue_batch(ctx, ctx->sync_ws, prec, std::vector<FragIn>(1, f), true,
+                      (int)std::min<long long>(forced, (long long)f.nf * f.nf));
+    } else {
+      enqueue_fragments(ctx, ctx->sync_ws, prec, fr, true, sync_cap(ctx->sync_ws));
+    }
     HIPCHK(hipStreamSynchronize(ctx->stream));
     std::lock_guard<std::mutex> lk(ctx->mu);
     ctx->sync_ws.timer.collect(&ctx->totals);

@@ -125,7 +125,6 @@ struct KconvArgs {
   int sign;        // +1 / -1 for mode 1
   double scale;
   float2* out32;        // when set, the result goes here as complex FP32 (same offsets), not to out
-  const float2* in32;   // when set, the input is read from here as complex FP32 (same offsets), not from in
   const int* qslot;     // mode 0, device, optional: output q goes to block qslot[q] (skipped if < 0)
 };
 hipError_t kconv_launch(const KconvArgs& a, hipStream_t s);
@@ -164,13 +163,11 @@ hipError_t pair_launch(const PairArgs& a, hipStream_t s);
 
 // out[k][I][r] = sum_mu xt[k][mu][I] conj(phi[k][mu][r0 + r]), r < rcur
 // (the right-hand side's T^k_I(r) on one tile of grid points); FP64 vector
-// units.  With out32 set the sums are computed on the FP32 matrix cores and
-// stored there as complex FP32 (same offsets) instead of in out.  xt must
-// stay readable for RHS_X_PAD elements past its end (blocks of points read
-// whole rows; the extra outputs are not stored).
+// units.  xt must stay readable for RHS_X_PAD elements past its end (blocks
+// of points read whole rows; the extra outputs are not stored).
 constexpr int RHS_X_PAD = 16;
-hipError_t rhs_t_launch(const cplx* xt, const cplx* phi, cplx* out, float2* out32, int nk, int norb, int nip,
-                        long long ng, long long r0, int rcur, hipStream_t s);
+hipError_t rhs_t_launch(const cplx* xt, const cplx* phi, cplx* out, int nk, int norb, int nip, long long ng,
+                        long long r0, int rcur, hipStream_t s);
 // true when pair_launch takes the register path (needs item_off / nitems)
 bool pair_reg_supported(int fmt, int m1, int m2, int m3);
 
@@ -181,12 +178,7 @@ bool pair_reg_supported(int fmt, int m1, int m2, int m3);
 // ---------------------------------------------------------------------------
 struct GridFftArgs {
   cplx* data;
-  const float2* data32;   // mixed formats on the register grids: complex FP32 input (same offsets) instead of data
-  float* fac;             // mixed formats on the register grids: scratch of nq * N_g floats for the Coulomb factors
   const int* qlist;       // device, optional: item qi is momentum qlist[qi] (else q0 + qi)
-  void* split;            // optional split output (fmt 1 / 2) instead of writing data back
-  int fmt;                // 0: in place c128; 1 float planes; 2 bf16 hi/lo planes
-  long long split_ld, split_plane, split_q;   // row pitch, plane stride, q stride
   int n1, n2, n3;
   int m1, m2, m3;
   int q0, nq, n_ip;
@@ -195,9 +187,6 @@ struct GridFftArgs {
   double volume;
 };
 hipError_t gridfft_launch(const GridFftArgs& a, hipStream_t s);
-// true when the mixed-format grid FFT of this grid is the one-pass register
-// kernel (which alone reads data32)
-bool gridfft_reg_grid(int n1, int n2, int n3);
 
 // ---------------------------------------------------------------------------
 // FP64 pivoted Cholesky of Pi^q (one workgroup per q) and the two-sided

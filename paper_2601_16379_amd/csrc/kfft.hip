@@ -134,12 +134,7 @@ __global__ __launch_bounds__(256) void kconv_kernel(KconvArgs a, int etile) {
             const long long ee = e0 + e;
             off = (ee / a.in_inner) * a.in_outer + ee % a.in_inner;
           }
-          if (a.in32) {
-            const float2 f = a.in32[(long long)k * a.in_kstride + off];
-            v[u] = cmk((double)f.x, (double)f.y);
-          } else {
-            v[u] = a.in[(long long)k * a.in_kstride + off];
-          }
+          v[u] = a.in[(long long)k * a.in_kstride + off];
         }
       }
     }
@@ -329,8 +324,7 @@ __device__ inline cplx bfly(cplx v, bool hi) {
   return cmk(fma(sg, v.x, p.x), fma(sg, v.y, p.y));
 }
 
-// F32: input from in32 and output to out32 (complex FP32, FP64 arithmetic)
-template <int M1, int M2, int M3, bool F32>
+template <int M1, int M2, int M3>
 __global__ __launch_bounds__(256) void kconv_reg_kernel(KconvArgs a) {
   constexpr int NV = M2 * M3, EPW = 64 / M1;
   const int lane = threadIdx.x & 63;
@@ -344,13 +338,7 @@ __global__ __launch_bounds__(256) void kconv_reg_kernel(KconvArgs a) {
     // every lane loads (ie = 0 is in bounds for lanes past the end, whose
     // quads only exchange among themselves and store nothing): a load under
     // a branch is waited for inside it, one round trip per value
-    const long long off = (long long)(k1 * NV + v) * a.in_kstride + ie;
-    if (F32) {
-      const float2 f = a.in32[off];
-      x[v] = cmk((double)f.x, (double)f.y);
-    } else {
-      x[v] = a.in[off];
-    }
+    x[v] = a.in[(long long)(k1 * NV + v) * a.in_kstride + ie];
   }
   dft23_pos<M2, M3>(x);
   // k1 axis across the quad; M1 = 4 leaves the lanes in bit-reversed order
@@ -406,9 +394,7 @@ __global__ __launch_bounds__(256) void kconv_reg_kernel(KconvArgs a) {
     const int slot = a.qslot ? a.qslot[k1 * NV + v] : k1 * NV + v;
     if (slot < 0) continue;
     const long long off = (long long)slot * a.out_qstride + oe;
-    const cplx r = cscale(x[v], a.scale);
-    if (F32) a.out32[off] = make_float2((float)r.x, (float)r.y);
-    else a.out[off] = r;
+    a.out[off] = cscale(x[v], a.scale);
   }
 }
 
@@ -417,8 +403,7 @@ hipError_t launch_kconv_reg(const KconvArgs& a, hipStream_t s) {
   constexpr int EPB = 4 * (64 / M1);
   const long long blocks = (a.n_elem + EPB - 1) / EPB;
   if (blocks <= 0) return hipSuccess;
-  if (a.in32) hipLaunchKernelGGL((kconv_reg_kernel<M1, M2, M3, true>), dim3((unsigned)blocks), dim3(256), 0, s, a);
-  else hipLaunchKernelGGL((kconv_reg_kernel<M1, M2, M3, false>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((kconv_reg_kernel<M1, M2, M3>), dim3((unsigned)blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 template <int M1, int M2>
@@ -628,9 +613,7 @@ hipError_t pair_reg_m2(const PairArgs& a, hipStream_t s) {
 }  // namespace
 
 hipError_t kconv_launch(const KconvArgs& a, hipStream_t s) {
-  // the register path converts both ends or neither
-  const bool io_same = (a.in32 != nullptr) == (a.out32 != nullptr);
-  if (a.mode == 0 && io_same && (a.m1 == 1 || a.m1 == 2 || a.m1 == 4) && a.m2 <= 4 && a.m3 <= 4) {
+  if (a.mode == 0 && !a.out32 && (a.m1 == 1 || a.m1 == 2 || a.m1 == 4) && a.m2 <= 4 && a.m3 <= 4) {
     if (a.m1 == 1) return kconv_reg_m2<1>(a, s);
     if (a.m1 == 2) return kconv_reg_m2<2>(a, s);
     return kconv_reg_m2<4>(a, s);

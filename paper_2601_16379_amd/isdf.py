@@ -25,7 +25,7 @@ ISDF_NO_PIVOT = 0x2
 ISDF_FRAG_DEVICE = 0x1
 REQ_STATES = {0: "QUEUED", 1: "RUNNING", 2: "DONE", 3: "FAILED", 4: "CANCELLED"}
 
-EXPORTS = ["isdf_create", "isdf_fit", "isdf_fit_eta_fp32", "isdf_coulomb_kernel", "isdf_get_metric",
+EXPORTS = ["isdf_create", "isdf_fit", "isdf_coulomb_kernel", "isdf_get_metric",
            "isdf_get_kernel", "isdf_get_ivs", "isdf_get_rhs", "isdf_get_eta_tilde", "isdf_fragment_eri",
            "isdf_serve_start", "isdf_submit", "isdf_submit_n", "isdf_poll", "isdf_cancel",
            "isdf_serve_stop", "isdf_stats", "isdf_stage_ms", "isdf_stage_total", "isdf_stage_reset", "isdf_plan_bytes", "isdf_storage_model_bytes",
@@ -72,7 +72,6 @@ def load_library(path=LIB_PATH):
     sig = {
         "isdf_create": (I32, [ctypes.POINTER(P), P, P, P, I32, P, P, I32, U32, P]),
         "isdf_fit": (I32, [P, I32]),
-        "isdf_fit_eta_fp32": (I32, [P]),
         "isdf_coulomb_kernel": (I32, [P, I32]),
         "isdf_get_metric": (I32, [P, I32, P]),
         "isdf_get_kernel": (I32, [P, I32, P]),
@@ -137,12 +136,6 @@ def isdf_plan_bytes(grid, kmesh, n_orb, n_ip):
     g = np.asarray(grid, dtype=np.int32)
     k = np.asarray(kmesh, dtype=np.int32)
     return int(lib.isdf_plan_bytes(g.ctypes.data, k.ctypes.data, int(n_orb), int(n_ip)))
-
-
-def isdf_fit_eta_fp32(grid):
-    """True if a mixed-precision fit stores eta as complex FP32 on this grid."""
-    g = np.ascontiguousarray(np.asarray(grid, dtype=np.int32))
-    return bool(load_library().isdf_fit_eta_fp32(g.ctypes.data))
 
 
 def isdf_storage_model_bytes(n_k, n_ip, n_ao):
@@ -234,10 +227,11 @@ class Isdf:
     def get_eta_tilde(self, q):
         return self._get(self.lib.isdf_get_eta_tilde, q, (self.n_ip, self.n_g))
 
-    def fragment_eri(self, coeffs, prec="fp64", out=None):
+    def fragment_eri(self, coeffs, prec="fp64", out=None, pair_blocks=0):
         """ERIs of a batch of fragments in one pass.  ``coeffs``: list of
         [N_k, n_orb, n_f] complex128 arrays (numpy = host, torch cuda tensors =
-        device).  Returns the list of [n_f]^4 outputs (same kind)."""
+        device).  ``pair_blocks`` > 1 runs every fragment alone with its pairs
+        in that many blocks.  Returns the list of [n_f]^4 outputs (same kind)."""
         n = len(coeffs)
         nfs = np.array([c.shape[2] for c in coeffs], dtype=np.int32)
         dev = [(_ptr(c)[1]) for c in coeffs]
@@ -252,7 +246,7 @@ class Isdf:
                 out = [np.empty((f, f, f, f), dtype=np.complex128) for f in nfs]
         cptr = (ctypes.c_void_p * n)(*[_ptr(c)[0] for c in coeffs])
         eptr = (ctypes.c_void_p * n)(*[_ptr(e)[0] for e in out])
-        flags = ISDF_FRAG_DEVICE if dev[0] else 0
+        flags = (ISDF_FRAG_DEVICE if dev[0] else 0) | ((int(pair_blocks) & 0xFF) << 8)
         self._check(self.lib.isdf_fragment_eri(self.h, PRECISIONS.get(prec, prec), n,
                                                nfs.ctypes.data, cptr, eptr, flags),
                     "isdf_fragment_eri")

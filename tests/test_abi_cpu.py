@@ -52,15 +52,6 @@ def test_plan_bytes_at_most_linear_in_nk():
     assert b5 > 53e9 + 504 * 1040 * 64000 * 16
 
 
-def test_fp32_eta_only_on_register_fft_grids():
-    # the mixed grid FFT reads FP32 eta only in its one-pass register kernel
-    for n in (6, 8, 10, 12, 16, 18, 20, 24, 30, 32):
-        assert pkg.isdf_fit_eta_fp32((n, n, n))
-    for g in ((36, 36, 36), (40, 40, 40), (16, 16, 24), (64, 64, 64)):
-        assert not pkg.isdf_fit_eta_fp32(g)
-    assert pkg.load_library().isdf_fit_eta_fp32(None) == 0
-
-
 def test_create_rejects_invalid_arguments_without_device():
     lib = pkg.load_library()
     h = ctypes.c_void_p()
