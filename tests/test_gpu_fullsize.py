@@ -131,3 +131,140 @@ def test_workload3_kernel_and_fragments(w3):
     assert max(errs) < 1e-6
     for f in pick:
         assert float(np.max(np.abs(mixed[f] - ref[f]))) < 1e-6
+
+
+# --------------------------------------------------------------------------
+# Workloads 4 (6x6x6 mesh, 36^3 grid, 40 orbitals, 800 points) and 5
+# (10x10x10 mesh, 40^3 grid, 52 orbitals, 1040 points): sampled checks, the
+# plain oracle being too large to run whole (eta of workload 5 is 1 TB).
+# * X bit for bit at sampled k; rows of Pi^q at sampled q against the
+#   oracle's direct k sums, all rows at three q (q = 0, a generic q, a
+#   zone-boundary q);
+# * W^q at those q through V^q = Pi^q W^q Pi^q on sampled rows S: the
+#   oracle forms eta^q_S on the whole grid and V_SS from it (eqs. (5), (7)),
+#   the GPU W^q is contracted with the oracle's rows of Pi^q (eq. (8));
+# * fragments of 4 and 8 orbitals from the oracle's eqs. (19)-(20) given the
+#   GPU FP64 W^q (the fragment step checked on its own), FP64 and bf16x3;
+# * a stream fragment and one of 120 orbitals ((pq)-blocked at this size)
+#   in bf16x3 against the GPU FP64 path, 1e-6 Eh.
+# --------------------------------------------------------------------------
+class Big:
+    def __init__(self, name):
+        import paper_2601_16379_amd as pkg
+        print("%s: generating inputs" % name, flush=True)
+        self.d = inp.make_inputs(name)
+        cfg = self.d.cfg
+        print("%s: creating the context" % name, flush=True)
+        self.ctx = pkg.Isdf(self.d.lattice, cfg.grid, cfg.kmesh, self.d.orbitals, self.d.ip_index)
+        self.ctx.fit("fp64")
+        self.ctx.coulomb_kernel("fp64")
+        print("%s: fit + kernel done" % name, flush=True)
+        self.x = ko.ip_values(self.d.orbitals, self.d.ip_index)
+        self._w = None
+
+    def w_all(self):
+        if self._w is None:
+            n = self.d.cfg.n_k
+            self._w = np.stack([self.ctx.get_kernel(q) for q in range(n)])
+        return self._w
+
+
+BIG = ["c4_k6_36", "c5_k10_40"]
+
+
+@pytest.fixture(scope="module", params=BIG)
+def bigcell(request):
+    """One large cell at a time (pytest runs every test of one parameter
+    before the next)."""
+    b = Big(request.param)
+    yield b
+    b.ctx.close()
+
+
+def _qs_of(cfg):
+    """q = 0, a generic q and a zone-boundary q (every axis m/2)."""
+    m = cfg.kmesh
+    gen = geo.mesh_index(np.array([1, 2, 3]) % np.array(m), m)
+    bnd = geo.mesh_index(np.array([m[0] // 2, m[1] // 2, m[2] // 2]), m)
+    return [0, int(gen), int(bnd)]
+
+
+@pytest.mark.timeout(900)
+def test_large_cell_metric_and_ivs(bigcell):
+    b = bigcell
+    name = b.d.cfg.name
+    cfg = b.d.cfg
+    for k in (0, 1, cfg.n_k // 2, cfg.n_k - 1):
+        assert np.array_equal(b.ctx.get_ivs(k), b.x[k])
+    assert b.ctx.stats()["rank"] == [cfg.n_ip] * cfg.n_k
+    rng = np.random.default_rng(7)
+    rows = sorted(rng.choice(cfg.n_ip, 6, replace=False).tolist())
+    qs = sorted(set(_qs_of(cfg) + rng.choice(cfg.n_k, 13, replace=False).tolist()))
+    ref = ko.metric_rows(b.x, cfg.kmesh, rows, qs)
+    for i, q in enumerate(qs):
+        got = b.ctx.get_metric(q)[rows]
+        assert _rel(got, ref[i]) < 1e-12, q
+
+
+@pytest.mark.timeout(900)
+def test_large_cell_kernel_through_v(bigcell):
+    b = bigcell
+    name = b.d.cfg.name
+    cfg = b.d.cfg
+    rng = np.random.default_rng(8)
+    rows = sorted(rng.choice(cfg.n_ip, 6, replace=False).tolist())
+    qs = _qs_of(cfg)
+    print("%s: oracle Pi^q for q = %s" % (name, qs), flush=True)
+    pi = ko.metric_rows(b.x, cfg.kmesh, list(range(cfg.n_ip)), qs)
+    print("%s: oracle eta^q on rows %s" % (name, rows), flush=True)
+    eta_s = ko.rhs_chunked(b.x[:, rows], b.d.orbitals, cfg.kmesh, qs)
+    for i, q in enumerate(qs):
+        v_ss = ko.coulomb_kernel_of(eta_s[i], b.d.lattice, cfg.grid, cfg.kmesh, q)
+        w = b.ctx.get_kernel(q)
+        p_s = pi[i][rows]                                  # rows S of Pi^q
+        got = p_s @ w @ p_s.conj().T                        # (Pi W Pi)_SS
+        cond = np.linalg.cond(pi[i])
+        tol = max(1e-10, 8 * cfg.n_ip * np.finfo(float).eps * cond)
+        err = _rel(got, v_ss)
+        print("%s q=%d: |(Pi W Pi)_SS - V_SS| / max|V_SS| = %.2e (cond(Pi) %.2e, bound %.2e)"
+              % (name, q, err, cond, tol))
+        assert err < tol, q
+
+
+@pytest.mark.timeout(900)
+def test_large_cell_small_fragments_oracle(bigcell):
+    b = bigcell
+    name = b.d.cfg.name
+    cfg = b.d.cfg
+    frags = [inp.make_fragment(cfg, 20_000 + n, n) for n in (4, 8)]
+    w = b.w_all()
+    ref = [ko.fragment_eri(b.x, c, w, cfg.kmesh) for c in frags]
+    out64 = b.ctx.fragment_eri(frags, "fp64")
+    out16 = b.ctx.fragment_eri(frags, "bf16x3")
+    for c, r, o64, o16 in zip(frags, ref, out64, out16):
+        rel = _rel(o64, r)
+        err = float(np.max(np.abs(o16 - r)))
+        print("%s n_f %d: FP64 rel %.2e, bf16x3 max|dV| %.2e Eh (max|V| %.2e)"
+              % (name, c.shape[2], rel, err, np.abs(r).max()))
+        assert rel < 1e-10
+        assert err < 1e-6
+
+
+@pytest.mark.timeout(900)
+def test_large_cell_stream_fragments_mixed_vs_fp64(bigcell):
+    import torch
+    b = bigcell
+    name = b.d.cfg.name
+    cfg = b.d.cfg
+    nfs = inp.fragment_sizes(cfg)
+    frags = [inp.make_fragment(cfg, 0, int(nfs[0])), inp.make_fragment(cfg, 30_000, cfg.frag_hi)]
+    dev = [torch.from_numpy(c).cuda() for c in frags]
+    o64 = b.ctx.fragment_eri(dev, "fp64")
+    o16 = b.ctx.fragment_eri(dev, "bf16x3")
+    for c, a, m in zip(frags, o64, o16):
+        err = float((a - m).abs().max().item())
+        print("%s n_f %d: bf16x3 vs FP64 max|dV| %.2e Eh (max|V| %.2e)"
+              % (name, c.shape[2], err, float(a.abs().max().item())))
+        assert err < 1e-6
+    del o64, o16, dev
+    torch.cuda.empty_cache()
