@@ -309,9 +309,37 @@ int64_t isdf_plan_bytes(const int32_t grid[3], const int32_t kmesh[3], int32_t n
                         int32_t n_ip);
 int64_t isdf_storage_model_bytes(int64_t n_k, int64_t n_ip, int64_t n_ao);
 
+/*
+ * Checkpoint and resume of the fitted cell: the W^q of the paper's storage
+ * model (section on the diamond cell at N_k = 1000) together with what the
+ * fragment ERIs need besides it.  isdf_save writes, after isdf_coulomb_kernel,
+ * a little-endian file: a 144-byte header
+ *   char magic[8] = "ISDFCKP1"; uint32 version = 1; uint32 header_bytes = 144;
+ *   int32 grid[3], kmesh[3], n_orb, n_ip, nh; uint32 flags;
+ *   float64 lattice[9]; uint64 payload_bytes; uint64 checksum
+ * then the payload
+ *   int32 ip_index[n_ip]; int32 rank[nh] (rank of each Pi^q factor);
+ *   c128 X[N_k][n_orb][n_ip]; c128 Pi[nh][n_ip][n_ip]; c128 W[nh][n_ip][n_ip]
+ * where nh is the number of classes {q, -q} and class h holds the h-th q (C
+ * order over the mesh) whose -q is not smaller; checksum = FNV-1a 64 of the
+ * payload bytes.  isdf_load reads and checks the whole file on the host
+ * (magic, version, sizes against the k mesh, length, checksum, ranks,
+ * interpolation points) before any device call, then creates a context on
+ * `hip_stream` whose fragment ERIs, served requests, graphs and test hooks
+ * (isdf_get_metric, isdf_get_kernel, isdf_get_ivs) equal those of the saved
+ * context bit for bit.  The restored context holds no orbitals: isdf_fit on it
+ * is ISDF_E_STATE.  Errors: isdf_save ISDF_E_STATE before isdf_coulomb_kernel,
+ * ISDF_E_INVALID when the file cannot be written; isdf_load ISDF_E_INVALID
+ * for a missing, truncated, corrupted or inconsistent file (*out NULL, message
+ * from isdf_last_error(NULL)), ISDF_E_NOMEM / ISDF_E_DEVICE as isdf_create.
+ */
+isdf_status isdf_save(isdf_ctx ctx, const char* path);
+isdf_status isdf_load(isdf_ctx* out, const char* path, void* hip_stream);
+
 isdf_status isdf_destroy(isdf_ctx ctx);
 /* Message of the last failed call on ctx; with ctx == NULL, the message of the
- * last failed isdf_create on the calling thread ("null context" if none). */
+ * last failed isdf_create or isdf_load on the calling thread ("null context"
+ * if none). */
 const char* isdf_last_error(isdf_ctx ctx);
 const char* isdf_version(void);
 

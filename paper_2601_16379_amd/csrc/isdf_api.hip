@@ -345,6 +345,7 @@ struct isdf_ctx_s {
   DevBuf wt64, wt32, wt16;              // W transposed in the three GEMM operand formats
   DevBuf dmax, cflag;                   // factorisation: largest diagonal, breakdown flags
   long long ld_ip = 0;                  // row pitch of the split operands (a multiple of 16)
+  bool has_orbitals = false;            // false for a context restored by isdf_load
   bool fitted = false, kernel_ready = false, eta_valid = false;
   bool kernel_pending = false;          // a fit whose eta (resident or per batch) the kernel has not consumed
   bool etat_valid = false;              // eta~ of every class still held after the kernel (no q batches)
@@ -1396,6 +1397,186 @@ void serve_loop(isdf_ctx c) {
   }
 }
 
+#ifndef ISDF_RHS_TILE_BYTES
+#define ISDF_RHS_TILE_BYTES (1LL << 30)
+#endif
+
+long long rchunk_len(long long ng, int nk, int nip) {
+  // r tile of the right-hand side: T^k_I(r) for all k of one tile
+  long long rc = (long long)(ISDF_RHS_TILE_BYTES) / ((long long)nk * nip * (long long)sizeof(cplx));
+  rc = std::max<long long>(64, std::min<long long>(rc, ng));
+  return rc;
+}
+
+// Sizes, reciprocal lattice, classes {q, -q}, the resident buffers (X, Pi,
+// W and its operand copies, the factor's rank and permutation), the
+// streams and events.  with_orbitals: also the orbitals and the fit's
+// transient buffers (a context restored by isdf_load has neither).
+void setup_context(isdf_ctx c, const double* lattice, const int32_t grid[3], const int32_t kmesh[3], int n_orb,
+                   int n_ip, uint32_t flags, void* hip_stream, bool with_orbitals) {
+  for (int d = 0; d < 3; ++d) { c->n[d] = grid[d]; c->m[d] = kmesh[d]; }
+  c->nk = kmesh[0] * kmesh[1] * kmesh[2];
+  c->ng = (long long)grid[0] * grid[1] * grid[2];
+  c->norb = n_orb;
+  c->nip = n_ip;
+  c->flags = flags;
+  c->stream = (hipStream_t)hip_stream;
+  c->has_orbitals = with_orbitals;
+  HIPCHK(hipGetDevice(&c->device));
+  memcpy(c->lattice, lattice, sizeof(c->lattice));
+  // reciprocal rows b_i: 2 pi (A^-1)^T
+  const double* A = lattice;
+  const double det = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+                     A[2] * (A[3] * A[7] - A[4] * A[6]);
+  if (!(std::fabs(det) > 1e-12)) throw Fail{ISDF_E_INVALID, "singular lattice"};
+  c->volume = std::fabs(det);
+  double inv[9];
+  inv[0] = (A[4] * A[8] - A[5] * A[7]) / det;
+  inv[1] = (A[2] * A[7] - A[1] * A[8]) / det;
+  inv[2] = (A[1] * A[5] - A[2] * A[4]) / det;
+  inv[3] = (A[5] * A[6] - A[3] * A[8]) / det;
+  inv[4] = (A[0] * A[8] - A[2] * A[6]) / det;
+  inv[5] = (A[2] * A[3] - A[0] * A[5]) / det;
+  inv[6] = (A[3] * A[7] - A[4] * A[6]) / det;
+  inv[7] = (A[1] * A[6] - A[0] * A[7]) / det;
+  inv[8] = (A[0] * A[4] - A[1] * A[3]) / det;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) c->recip[3 * i + j] = 2.0 * M_PI * inv[3 * j + i];
+  const int nk = c->nk;
+  const long long ng = c->ng;
+  const size_t e = sizeof(cplx);
+  c->qslot_h.assign(nk, -1);
+  for (int q = 0; q < nk; ++q) {
+    const int j1 = q / (c->m[1] * c->m[2]), j2 = (q / c->m[2]) % c->m[1], j3 = q % c->m[2];
+    const int mq = (((c->m[0] - j1) % c->m[0]) * c->m[1] + (c->m[1] - j2) % c->m[1]) * c->m[2] +
+                   (c->m[2] - j3) % c->m[2];
+    if (mq < q) continue;
+    c->qslot_h[q] = (int)c->hq_h.size();
+    c->hq_h.push_back(q);
+    c->hself_h.push_back(mq == q ? 1 : 0);
+  }
+  c->nh = (int)c->hq_h.size();
+  c->rc = rchunk_len(ng, nk, n_ip);
+  if (with_orbitals) c->phi.alloc((size_t)nk * n_orb * ng * e);
+  c->ip.alloc(sizeof(int) * n_ip);
+  // + RHS_X_PAD elements: rhs_t_launch reads whole blocks of points
+  c->xt.alloc(((size_t)nk * n_orb * n_ip + RHS_X_PAD) * e);
+  const int nh = c->nh;
+  const size_t m2 = (size_t)nh * n_ip * n_ip * e;   // one matrix per class {q, -q}
+  c->pi.alloc(m2);
+  c->w.alloc(m2);
+  // row pitches of the split operands: multiples of 16 elements, so that in
+  // the bf16 hi/lo format every 16-k step of a row is one aligned 128-byte line
+  c->ld_ip = (n_ip + 15) / 16 * 16;
+  c->wt64.alloc((size_t)nh * n_ip * c->ld_ip * e);
+  c->wt32.alloc((size_t)nh * n_ip * c->ld_ip * 8);
+  c->wt16.alloc((size_t)nh * n_ip * c->ld_ip * 8);
+  c->perm.alloc(sizeof(int) * nh * n_ip);
+  c->rank.alloc(sizeof(int) * nh);
+  c->flag.alloc(sizeof(int));
+  c->dmax.alloc(sizeof(double) * nh);
+  c->cflag.alloc(sizeof(int) * nh);
+  if (with_orbitals) {
+    // classes per q batch of eta: all of them when that fits in 60 % of the
+    // memory left after the resident and the other transient buffers (the
+    // rest is for fragment workspaces), else the largest batch that fits in
+    // 85 % of it -- a q-batched kernel hands the transient buffers back to
+    // the fragment workspaces when it ends.  ISDF_Q_BATCH(n) caps the batch.
+    const size_t per_class = (size_t)n_ip * ng * e;
+    const size_t transient = 3 * m2 + (size_t)nk * n_ip * n_ip * e +
+                             (size_t)nh * ((size_t)n_ip * 64 + 4096) * e + 2 * (size_t)nk * n_ip * c->rc * e;
+    size_t fr = 0, tot = 0;
+    HIPCHK(hipMemGetInfo(&fr, &tot));
+    const double avail = fr > transient ? (double)(fr - transient) : 0.0;
+    long long qb = (long long)(0.6 * avail / (double)per_class);
+    if (qb < nh) qb = (long long)(0.85 * avail / (double)per_class);
+    const int cap = (int)((flags >> 16) & 0xFFFFu);
+    if (cap > 0) qb = std::min<long long>(qb, cap);
+    if (qb < 1) throw Fail{ISDF_E_NOMEM, "no room for the eta of one q class"};
+    c->qb = (int)std::min<long long>(qb, nh);
+    ensure_fit_buffers(c);
+  }
+  c->qmap.alloc(sizeof(int) * (nk + 2 * c->nh));
+  {
+    std::vector<int> qm(c->qslot_h);
+    qm.insert(qm.end(), c->hq_h.begin(), c->hq_h.end());
+    qm.insert(qm.end(), c->hself_h.begin(), c->hself_h.end());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipMemcpy(c->qmap.p, qm.data(), sizeof(int) * qm.size(), hipMemcpyHostToDevice));
+  }
+  c->sync_ws.stream = c->stream;
+  HIPCHK(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+  HIPCHK(hipStreamCreateWithFlags(&c->aux2, hipStreamNonBlocking));
+  for (int b = 0; b < 2; ++b) {
+    HIPCHK(hipEventCreateWithFlags(&c->ev_rt[b], hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&c->ev_kc[b], hipEventDisableTiming));
+  }
+  HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&c->ev_pinv, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&c->sync_ws.done, hipEventDisableTiming));
+}
+
+const char* check_sizes(const int32_t grid[3], const int32_t kmesh[3], int32_t n_orb, int32_t n_ip) {
+  for (int d = 0; d < 3; ++d) {
+    if (!good_grid(grid[d])) return "grid size must be 2..64 with factors 2,3,5,7";
+    if (kmesh[d] < 1 || kmesh[d] > 16) return "k mesh must be 1..16 per axis";
+  }
+  if (n_orb < 1 || n_orb > 256 || n_ip < 1 || n_ip > 2048) return "n_orb must be 1..256 and n_ip 1..2048";
+  return nullptr;
+}
+
+// Interpolation points: in range and distinct.
+void check_ips(const std::vector<int32_t>& iph, long long ng) {
+  std::vector<int32_t> srt(iph);
+  std::sort(srt.begin(), srt.end());
+  if (srt.front() < 0 || srt.back() >= ng) throw Fail{ISDF_E_INVALID, "interpolation point index out of range"};
+  for (size_t i = 1; i < srt.size(); ++i)
+    if (srt[i] == srt[i - 1]) throw Fail{ISDF_E_INVALID, "duplicate interpolation point"};
+}
+
+// --------------------------------------------------------------------------
+// checkpoint files (isdf_save / isdf_load)
+// --------------------------------------------------------------------------
+// Little-endian.  Header (CkHeader), then the payload:
+//   int32 ip_index[n_ip]; int32 rank[nh];
+//   c128 X[N_k][n_orb][n_ip] (the context's layout);
+//   c128 Pi[nh][n_ip][n_ip]; c128 W[nh][n_ip][n_ip] (one q per class {q, -q},
+//   class h = the h-th q of the mesh whose -q is not smaller)
+// checksum = FNV-1a 64 over the payload bytes.
+struct CkHeader {
+  char magic[8];            // "ISDFCKP1"
+  uint32_t version;         // 1
+  uint32_t header_bytes;    // sizeof(CkHeader)
+  int32_t grid[3], kmesh[3], n_orb, n_ip, nh;
+  uint32_t flags;           // isdf_create flags of the saved context
+  double lattice[9];
+  uint64_t payload_bytes;
+  uint64_t checksum;
+};
+static_assert(sizeof(CkHeader) == 8 + 4 + 4 + 4 * 9 + 4 + 72 + 8 + 8, "checkpoint header layout");
+const char kCkMagic[8] = {'I', 'S', 'D', 'F', 'C', 'K', 'P', '1'};
+
+uint64_t fnv1a(uint64_t h, const unsigned char* p, size_t n) {
+  for (size_t i = 0; i < n; ++i) {
+    h ^= p[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+constexpr uint64_t kFnvInit = 1469598103934665603ull;
+
+int classes_of(const int32_t kmesh[3]) {
+  long long nself = 1;
+  for (int d = 0; d < 3; ++d) nself *= (kmesh[d] % 2 == 0) ? 2 : 1;
+  return (int)(((long long)kmesh[0] * kmesh[1] * kmesh[2] + nself) / 2);
+}
+
+uint64_t ck_payload_bytes(const CkHeader& h) {
+  const uint64_t nk = (uint64_t)h.kmesh[0] * h.kmesh[1] * h.kmesh[2];
+  return 4ull * h.n_ip + 4ull * h.nh + 16ull * nk * h.n_orb * h.n_ip + 2ull * 16 * h.nh * h.n_ip * h.n_ip;
+}
+
 }  // namespace
 
 // ==========================================================================
@@ -1409,17 +1590,6 @@ int64_t isdf_storage_model_bytes(int64_t n_k, int64_t n_ip, int64_t n_ao) {
   return (n_k * n_ip * n_ip + n_k * n_ip * n_ao) * 16;
 }
 
-#ifndef ISDF_RHS_TILE_BYTES
-#define ISDF_RHS_TILE_BYTES (1LL << 30)
-#endif
-
-static long long rchunk_len(long long ng, int nk, int nip) {
-  // r tile of the right-hand side: T^k_I(r) for all k of one tile
-  long long rc = (long long)(ISDF_RHS_TILE_BYTES) / ((long long)nk * nip * (long long)sizeof(cplx));
-  rc = std::max<long long>(64, std::min<long long>(rc, ng));
-  return rc;
-}
-
 int64_t isdf_plan_bytes(const int32_t grid[3], const int32_t kmesh[3], int32_t n_orb, int32_t n_ip) {
   if (!grid || !kmesh) return -1;
   const long long ng = (long long)grid[0] * grid[1] * grid[2];
@@ -1429,7 +1599,7 @@ int64_t isdf_plan_bytes(const int32_t grid[3], const int32_t kmesh[3], int32_t n
   for (int d = 0; d < 3; ++d) nself *= (kmesh[d] % 2 == 0) ? 2 : 1;
   const long long nh = (nk + nself) / 2;
   const long long e = sizeof(cplx);
-  const long long ld = (n_ip + 15) / 16 * 16, ldg = (ng + 15) / 16 * 16;
+  const long long ld = (n_ip + 15) / 16 * 16;
   long long b = 0;
   b += nk * n_orb * ng * e;              // orbitals
   b += nk * n_orb * n_ip * e;            // X
@@ -1437,13 +1607,12 @@ int64_t isdf_plan_bytes(const int32_t grid[3], const int32_t kmesh[3], int32_t n
   b += 5 * nh * (long long)n_ip * n_ip * e;  // Pi, L, W, two work buffers (per class)
   b += nh * ((long long)n_ip * 64 + 4096) * e;  // L^{-1} scratch
   b += nh * (long long)n_ip * ld * (16 + 8 + 8);  // W^T in the three operand formats
-  b += nh * (long long)n_ip * ng * e;    // eta of every class (FP64 size; q batches need less)
-  b += nh * (long long)n_ip * ldg * 8;   // split eta~ (mixed precisions)
-  b += nk * (long long)n_ip * rchunk_len(ng, (int)nk, n_ip) * e;  // RHS tile
+  b += nh * (long long)n_ip * ng * e;    // eta of every class (q batches need less)
+  b += 2 * nk * (long long)n_ip * rchunk_len(ng, (int)nk, n_ip) * e;  // two RHS tiles
   b += n_ip * 4 + 2 * nh * (long long)n_ip * 4;
-  b += nh * ng * 4;                      // Coulomb factors of the mixed grid FFT
   return b;
 }
+
 
 isdf_status isdf_create(isdf_ctx* out, const double* lattice, const int32_t grid[3],
                         const int32_t kmesh[3], int32_t n_orb, const void* orbitals,
@@ -1455,44 +1624,13 @@ isdf_status isdf_create(isdf_ctx* out, const double* lattice, const int32_t grid
     t_create_err = "null argument";
     return ISDF_E_INVALID;
   }
-  for (int d = 0; d < 3; ++d) {
-    if (!good_grid(grid[d])) { t_create_err = "grid size must be 2..64 with factors 2,3,5,7"; return ISDF_E_INVALID; }
-    if (kmesh[d] < 1 || kmesh[d] > 16) { t_create_err = "k mesh must be 1..16 per axis"; return ISDF_E_INVALID; }
-  }
-  if (n_orb < 1 || n_orb > 256 || n_ip < 1 || n_ip > 2048) {
-    t_create_err = "n_orb must be 1..256 and n_ip 1..2048";
+  if (const char* m = check_sizes(grid, kmesh, n_orb, n_ip)) {
+    t_create_err = m;
     return ISDF_E_INVALID;
   }
   isdf_ctx c = new (std::nothrow) isdf_ctx_s();
   if (!c) return ISDF_E_NOMEM;
   isdf_status st = guarded(c, [&] {
-    for (int d = 0; d < 3; ++d) { c->n[d] = grid[d]; c->m[d] = kmesh[d]; }
-    c->nk = kmesh[0] * kmesh[1] * kmesh[2];
-    c->ng = (long long)grid[0] * grid[1] * grid[2];
-    c->norb = n_orb;
-    c->nip = n_ip;
-    c->flags = flags;
-    c->stream = (hipStream_t)hip_stream;
-    HIPCHK(hipGetDevice(&c->device));
-    memcpy(c->lattice, lattice, sizeof(c->lattice));
-    // reciprocal rows b_i: 2 pi (A^-1)^T
-    const double* A = lattice;
-    const double det = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
-                       A[2] * (A[3] * A[7] - A[4] * A[6]);
-    if (!(std::fabs(det) > 1e-12)) throw Fail{ISDF_E_INVALID, "singular lattice"};
-    c->volume = std::fabs(det);
-    double inv[9];
-    inv[0] = (A[4] * A[8] - A[5] * A[7]) / det;
-    inv[1] = (A[2] * A[7] - A[1] * A[8]) / det;
-    inv[2] = (A[1] * A[5] - A[2] * A[4]) / det;
-    inv[3] = (A[5] * A[6] - A[3] * A[8]) / det;
-    inv[4] = (A[0] * A[8] - A[2] * A[6]) / det;
-    inv[5] = (A[2] * A[3] - A[0] * A[5]) / det;
-    inv[6] = (A[3] * A[7] - A[4] * A[6]) / det;
-    inv[7] = (A[1] * A[6] - A[0] * A[7]) / det;
-    inv[8] = (A[0] * A[4] - A[1] * A[3]) / det;
-    for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j) c->recip[3 * i + j] = 2.0 * M_PI * inv[3 * j + i];
     // validate interpolation points (host copy if needed)
     std::vector<int32_t> iph(n_ip);
     if (flags & ISDF_INPUT_DEVICE) {
@@ -1500,92 +1638,12 @@ isdf_status isdf_create(isdf_ctx* out, const double* lattice, const int32_t grid
     } else {
       memcpy(iph.data(), ip_index, sizeof(int32_t) * n_ip);
     }
-    {
-      std::vector<int32_t> srt(iph);
-      std::sort(srt.begin(), srt.end());
-      if (srt.front() < 0 || srt.back() >= c->ng)
-        throw Fail{ISDF_E_INVALID, "interpolation point index out of range"};
-      for (int i = 1; i < n_ip; ++i)
-        if (srt[i] == srt[i - 1]) throw Fail{ISDF_E_INVALID, "duplicate interpolation point"};
-    }
-    const int nk = c->nk;
-    const long long ng = c->ng;
-    const size_t e = sizeof(cplx);
-    c->qslot_h.assign(nk, -1);
-    for (int q = 0; q < nk; ++q) {
-      const int j1 = q / (c->m[1] * c->m[2]), j2 = (q / c->m[2]) % c->m[1], j3 = q % c->m[2];
-      const int mq = (((c->m[0] - j1) % c->m[0]) * c->m[1] + (c->m[1] - j2) % c->m[1]) * c->m[2] +
-                     (c->m[2] - j3) % c->m[2];
-      if (mq < q) continue;
-      c->qslot_h[q] = (int)c->hq_h.size();
-      c->hq_h.push_back(q);
-      c->hself_h.push_back(mq == q ? 1 : 0);
-    }
-    c->nh = (int)c->hq_h.size();
-    c->rc = rchunk_len(ng, nk, n_ip);
-    c->phi.alloc((size_t)nk * n_orb * ng * e);
-    c->ip.alloc(sizeof(int) * n_ip);
-    // + RHS_X_PAD elements: rhs_t_launch reads whole blocks of points
-    c->xt.alloc(((size_t)nk * n_orb * n_ip + RHS_X_PAD) * e);
-    const int nh = c->nh;
-    const size_t m2 = (size_t)nh * n_ip * n_ip * e;   // one matrix per class {q, -q}
-    c->pi.alloc(m2);
-    c->w.alloc(m2);
-    // row pitches of the split operands: multiples of 16 elements, so that in
-    // the bf16 hi/lo format every 16-k step of a row is one aligned 128-byte line
-    c->ld_ip = (n_ip + 15) / 16 * 16;
-    c->wt64.alloc((size_t)nh * n_ip * c->ld_ip * e);
-    c->wt32.alloc((size_t)nh * n_ip * c->ld_ip * 8);
-    c->wt16.alloc((size_t)nh * n_ip * c->ld_ip * 8);
-    c->perm.alloc(sizeof(int) * nh * n_ip);
-    c->rank.alloc(sizeof(int) * nh);
-    c->flag.alloc(sizeof(int));
-    c->dmax.alloc(sizeof(double) * nh);
-    c->cflag.alloc(sizeof(int) * nh);
-    // classes per q batch of eta: all of them when that fits in 60 % of the memory left after the
-    // resident and the other transient buffers (the rest is for fragment
-    // workspaces), else the largest batch that fits in 85 % of it -- a
-    // q-batched kernel hands the transient buffers back to the fragment
-    // workspaces when it ends.  ISDF_Q_BATCH(n) caps the batch.
-    {
-      const size_t per_class = (size_t)n_ip * ng * e;
-      const size_t m2 = (size_t)nh * n_ip * n_ip * e;
-      const size_t transient = 3 * m2 + (size_t)nk * n_ip * n_ip * e +
-                               (size_t)nh * ((size_t)n_ip * 64 + 4096) * e + 2 * (size_t)nk * n_ip * c->rc * e;
-      size_t fr = 0, tot = 0;
-      HIPCHK(hipMemGetInfo(&fr, &tot));
-      const double avail = fr > transient ? (double)(fr - transient) : 0.0;
-      long long qb = (long long)(0.6 * avail / (double)per_class);
-      if (qb < nh) qb = (long long)(0.85 * avail / (double)per_class);
-      const int cap = (int)((flags >> 16) & 0xFFFFu);
-      if (cap > 0) qb = std::min<long long>(qb, cap);
-      if (qb < 1) throw Fail{ISDF_E_NOMEM, "no room for the eta of one q class"};
-      c->qb = (int)std::min<long long>(qb, nh);
-    }
-    ensure_fit_buffers(c);
-    c->qmap.alloc(sizeof(int) * (nk + 2 * c->nh));
-    {
-      std::vector<int> qm(c->qslot_h);
-      qm.insert(qm.end(), c->hq_h.begin(), c->hq_h.end());
-      qm.insert(qm.end(), c->hself_h.begin(), c->hself_h.end());
-      HIPCHK(hipStreamSynchronize(c->stream));
-      HIPCHK(hipMemcpy(c->qmap.p, qm.data(), sizeof(int) * qm.size(), hipMemcpyHostToDevice));
-    }
+    check_ips(iph, (long long)grid[0] * grid[1] * grid[2]);
+    setup_context(c, lattice, grid, kmesh, n_orb, n_ip, flags, hip_stream, true);
     const hipMemcpyKind kind = (flags & ISDF_INPUT_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-    HIPCHK(hipMemcpyAsync(c->phi.p, orbitals, (size_t)nk * n_orb * ng * e, kind, c->stream));
+    HIPCHK(hipMemcpyAsync(c->phi.p, orbitals, (size_t)c->nk * n_orb * c->ng * sizeof(cplx), kind, c->stream));
     HIPCHK(hipMemcpyAsync(c->ip.p, iph.data(), sizeof(int) * n_ip, hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
-    c->sync_ws.stream = c->stream;
-    HIPCHK(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
-    HIPCHK(hipStreamCreateWithFlags(&c->aux2, hipStreamNonBlocking));
-    for (int b = 0; b < 2; ++b) {
-      HIPCHK(hipEventCreateWithFlags(&c->ev_rt[b], hipEventDisableTiming));
-      HIPCHK(hipEventCreateWithFlags(&c->ev_kc[b], hipEventDisableTiming));
-    }
-    HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&c->ev_pinv, hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&c->sync_ws.done, hipEventDisableTiming));
   });
   if (st != ISDF_OK) {
     t_create_err = c->err;
@@ -1599,6 +1657,7 @@ isdf_status isdf_create(isdf_ctx* out, const double* lattice, const int32_t grid
 isdf_status isdf_fit(isdf_ctx ctx, isdf_precision prec) {
   return guarded(ctx, [&] {
     if (prec < ISDF_FP64 || prec > ISDF_MIXED_BF16X3) throw Fail{ISDF_E_INVALID, "bad precision"};
+    if (!ctx->has_orbitals) throw Fail{ISDF_E_STATE, "context restored from a checkpoint has no orbitals to fit"};
     Exclusive ex(ctx, true);
     do_fit(ctx, prec);
   });
@@ -2094,6 +2153,128 @@ isdf_status isdf_destroy(isdf_ctx ctx) {
 const char* isdf_last_error(isdf_ctx ctx) {
   if (!ctx) return t_create_err.empty() ? "null context" : t_create_err.c_str();
   return ctx->err.c_str();
+}
+
+isdf_status isdf_save(isdf_ctx ctx, const char* path) {
+  return guarded(ctx, [&] {
+    if (!path) throw Fail{ISDF_E_INVALID, "null path"};
+    if (!ctx->kernel_ready) throw Fail{ISDF_E_STATE, "no Coulomb kernel to save (isdf_coulomb_kernel first)"};
+    CkHeader h;
+    memset(&h, 0, sizeof(h));
+    memcpy(h.magic, kCkMagic, 8);
+    h.version = 1;
+    h.header_bytes = sizeof(CkHeader);
+    for (int d = 0; d < 3; ++d) { h.grid[d] = ctx->n[d]; h.kmesh[d] = ctx->m[d]; }
+    h.n_orb = ctx->norb;
+    h.n_ip = ctx->nip;
+    h.nh = ctx->nh;
+    h.flags = ctx->flags & ~(uint32_t)ISDF_INPUT_DEVICE;
+    memcpy(h.lattice, ctx->lattice, sizeof(h.lattice));
+    h.payload_bytes = ck_payload_bytes(h);
+    FILE* f = fopen(path, "wb");
+    if (!f) throw Fail{ISDF_E_INVALID, std::string("cannot open ") + path + " for writing"};
+    std::unique_ptr<FILE, int (*)(FILE*)> guard(f, fclose);
+    if (fwrite(&h, sizeof(h), 1, f) != 1) throw Fail{ISDF_E_INVALID, "write failed"};
+    uint64_t sum = kFnvInit;
+    auto put_host = [&](const void* p, size_t n) {
+      if (n && fwrite(p, 1, n, f) != n) throw Fail{ISDF_E_INVALID, "write failed"};
+      sum = fnv1a(sum, (const unsigned char*)p, n);
+    };
+    // device arrays go through one pinned staging buffer
+    PinnedBuf stage;
+    const size_t chunk = (size_t)64 << 20;
+    stage.ensure(chunk);
+    auto put_dev = [&](const void* dp, size_t n) {
+      for (size_t o = 0; o < n; o += chunk) {
+        const size_t b = std::min(chunk, n - o);
+        HIPCHK(hipMemcpyAsync(stage.p, (const char*)dp + o, b, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        put_host(stage.p, b);
+      }
+    };
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    put_dev(ctx->ip.p, 4ull * ctx->nip);
+    put_host(ctx->rank_h.data(), 4ull * ctx->nh);
+    put_dev(ctx->xt.p, 16ull * ctx->nk * ctx->norb * ctx->nip);
+    put_dev(ctx->pi.p, 16ull * ctx->nh * ctx->nip * ctx->nip);
+    put_dev(ctx->w.p, 16ull * ctx->nh * ctx->nip * ctx->nip);
+    h.checksum = sum;
+    if (fseek(f, 0, SEEK_SET) != 0 || fwrite(&h, sizeof(h), 1, f) != 1) throw Fail{ISDF_E_INVALID, "write failed"};
+  });
+}
+
+isdf_status isdf_load(isdf_ctx* out, const char* path, void* hip_stream) {
+  t_create_err.clear();
+  if (!out) { t_create_err = "null output handle"; return ISDF_E_INVALID; }
+  *out = nullptr;
+  if (!path) { t_create_err = "null path"; return ISDF_E_INVALID; }
+  // the whole file is read and checked on the host before any device call
+  CkHeader h;
+  std::vector<unsigned char> pay;
+  {
+    FILE* f = fopen(path, "rb");
+    if (!f) { t_create_err = std::string("cannot open ") + path; return ISDF_E_INVALID; }
+    std::unique_ptr<FILE, int (*)(FILE*)> guard(f, fclose);
+    if (fread(&h, sizeof(h), 1, f) != 1) { t_create_err = "truncated checkpoint header"; return ISDF_E_INVALID; }
+    if (memcmp(h.magic, kCkMagic, 8) != 0) { t_create_err = "not an isdf checkpoint"; return ISDF_E_INVALID; }
+    if (h.version != 1 || h.header_bytes != sizeof(CkHeader)) {
+      t_create_err = "unsupported checkpoint version";
+      return ISDF_E_INVALID;
+    }
+    if (const char* m = check_sizes(h.grid, h.kmesh, h.n_orb, h.n_ip)) {
+      t_create_err = std::string("checkpoint sizes: ") + m;
+      return ISDF_E_INVALID;
+    }
+    if (h.nh != classes_of(h.kmesh) || h.payload_bytes != ck_payload_bytes(h)) {
+      t_create_err = "checkpoint sizes do not match its k mesh";
+      return ISDF_E_INVALID;
+    }
+    try {
+      pay.resize(h.payload_bytes);
+    } catch (const std::bad_alloc&) {
+      t_create_err = "host allocation failed";
+      return ISDF_E_NOMEM;
+    }
+    if (fread(pay.data(), 1, pay.size(), f) != pay.size()) { t_create_err = "truncated checkpoint"; return ISDF_E_INVALID; }
+    unsigned char extra;
+    if (fread(&extra, 1, 1, f) != 0) { t_create_err = "trailing bytes after the checkpoint"; return ISDF_E_INVALID; }
+  }
+  if (fnv1a(kFnvInit, pay.data(), pay.size()) != h.checksum) {
+    t_create_err = "checkpoint checksum mismatch";
+    return ISDF_E_INVALID;
+  }
+  std::vector<int32_t> iph(h.n_ip), rk(h.nh);
+  memcpy(iph.data(), pay.data(), 4ull * h.n_ip);
+  memcpy(rk.data(), pay.data() + 4ull * h.n_ip, 4ull * h.nh);
+  for (int r : rk)
+    if (r < 1 || r > h.n_ip) { t_create_err = "checkpoint rank out of range"; return ISDF_E_INVALID; }
+  isdf_ctx c = new (std::nothrow) isdf_ctx_s();
+  if (!c) return ISDF_E_NOMEM;
+  isdf_status st = guarded(c, [&] {
+    check_ips(iph, (long long)h.grid[0] * h.grid[1] * h.grid[2]);
+    setup_context(c, h.lattice, h.grid, h.kmesh, h.n_orb, h.n_ip, h.flags, hip_stream, false);
+    const unsigned char* p = pay.data() + 4ull * h.n_ip + 4ull * h.nh;
+    const size_t xb = 16ull * c->nk * c->norb * c->nip, mb = 16ull * c->nh * c->nip * c->nip;
+    HIPCHK(hipMemcpy(c->ip.p, iph.data(), 4ull * h.n_ip, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->rank.p, rk.data(), 4ull * h.nh, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->xt.p, p, xb, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->pi.p, p + xb, mb, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->w.p, p + xb + mb, mb, hipMemcpyHostToDevice));
+    c->rank_h = rk;
+    // the operand copies of W for the fragment GEMMs
+    HIPCHK(wt_convert_launch(c->w.as<cplx>(), c->wt64.as<cplx>(), c->wt32.as<float>(), c->wt16.as<unsigned short>(),
+                             c->nip, (int)c->ld_ip, c->nh, c->qmap.as<int>() + c->nk + c->nh, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->fitted = true;
+    c->kernel_ready = true;
+  });
+  if (st != ISDF_OK) {
+    t_create_err = c->err;
+    delete c;
+    return st;
+  }
+  *out = c;
+  return ISDF_OK;
 }
 
 }  // extern "C"

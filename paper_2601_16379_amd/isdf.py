@@ -30,7 +30,7 @@ EXPORTS = ["isdf_create", "isdf_fit", "isdf_coulomb_kernel", "isdf_get_metric",
            "isdf_serve_start", "isdf_submit", "isdf_submit_n", "isdf_poll", "isdf_cancel",
            "isdf_serve_stop", "isdf_stats", "isdf_stage_ms", "isdf_stage_total", "isdf_stage_reset", "isdf_plan_bytes", "isdf_storage_model_bytes",
            "isdf_graph_create", "isdf_graph_launch", "isdf_graph_destroy", "isdf_autotune", "isdf_set_tiling",
-           "isdf_destroy", "isdf_last_error", "isdf_version"]
+           "isdf_save", "isdf_load", "isdf_destroy", "isdf_last_error", "isdf_version"]
 
 
 class IsdfError(RuntimeError):
@@ -96,6 +96,8 @@ def load_library(path=LIB_PATH):
         "isdf_autotune": (I32, [P, I32, I32, P, P, P, ctypes.POINTER(TuneReport)]),
         "isdf_set_tiling": (I32, [P, I32, I32]),
         "isdf_graph_destroy": (I32, [P]),
+        "isdf_save": (I32, [P, ctypes.c_char_p]),
+        "isdf_load": (I32, [ctypes.POINTER(P), ctypes.c_char_p, P]),
         "isdf_destroy": (I32, [P]),
         "isdf_last_error": (ctypes.c_char_p, [P]),
         "isdf_version": (ctypes.c_char_p, []),
@@ -150,8 +152,14 @@ class Isdf:
     """One library context: ``isdf_create`` at construction, the other calls
     as methods with the C names (``fit``, ``coulomb_kernel``, ...)."""
 
-    def __init__(self, lattice, grid, kmesh, orbitals, ip_index, no_pivot=False, stream=None, q_batch=0):
+    def __init__(self, lattice, grid, kmesh, orbitals, ip_index, no_pivot=False, stream=None, q_batch=0,
+                 _handle=None):
         self.lib = load_library()
+        if _handle is not None:             # a context restored by isdf_load
+            self.h, (self.grid, self.kmesh, self.n_orb, self.n_ip, self.stream) = _handle
+            self.n_k = int(np.prod(self.kmesh))
+            self.n_g = int(np.prod(self.grid))
+            return
         lat = np.ascontiguousarray(np.asarray(lattice, dtype=np.float64))
         self.grid = np.ascontiguousarray(np.asarray(grid, dtype=np.int32))
         self.kmesh = np.ascontiguousarray(np.asarray(kmesh, dtype=np.int32))
@@ -178,6 +186,27 @@ class Isdf:
         if st != ISDF_OK:
             raise IsdfError(st, "isdf_create: " + self.lib.isdf_last_error(None).decode())
         self.h = h
+
+    @classmethod
+    def load(cls, path, stream=None):
+        """A context restored from a checkpoint written by ``save`` (no
+        orbitals: it serves fragment ERIs with the saved W^q)."""
+        import struct
+        lib = load_library()
+        with open(path, "rb") as f:
+            head = f.read(144)
+        st_ = current_stream() if stream is None else stream
+        h = ctypes.c_void_p()
+        st = lib.isdf_load(ctypes.byref(h), os.fsencode(path), st_)
+        if st != ISDF_OK:
+            raise IsdfError(st, "isdf_load: " + lib.isdf_last_error(None).decode())
+        grid = np.array(struct.unpack_from("<3i", head, 16), dtype=np.int32)
+        kmesh = np.array(struct.unpack_from("<3i", head, 28), dtype=np.int32)
+        n_orb, n_ip = struct.unpack_from("<2i", head, 40)
+        return cls(None, None, None, None, None, _handle=(h, (grid, kmesh, n_orb, n_ip, st_)))
+
+    def save(self, path):
+        self._check(self.lib.isdf_save(self.h, os.fsencode(path)), "isdf_save")
 
     # -- helpers -------------------------------------------------------------
     def _check(self, st, what):
