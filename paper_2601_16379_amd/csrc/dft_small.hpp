@@ -124,5 +124,27 @@ __device__ inline void small_dft_f(const float2 (&x)[R], float2 (&y)[R]) {
   }
 }
 
+// y[k] = sum_j x[j] exp(-2 pi i j k / R) for any compile-time R <= 16: the
+// butterflies of small_dft_f where it has them, else the direct sum with the
+// twiddles as compile-time constants (TwF).
+template <int R>
+__device__ inline void dft_any_f(const float2 (&x)[R], float2 (&y)[R]) {
+  if constexpr (R <= 8) {
+    small_dft_f<R>(x, y);
+  } else {
+    constexpr TwF<R> tw{};
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      float2 acc = x[0];
+#pragma unroll
+      for (int j = 1; j < R; ++j) {
+        const float2 t = rot_f(x[j], tw.c[(j * k) % R], tw.s[(j * k) % R]);
+        acc.x += t.x;
+        acc.y += t.y;
+      }
+      y[k] = acc;
+    }
+  }
+}
 
 }  // namespace

@@ -29,6 +29,7 @@ namespace {
 
 const char* kVersion = "isdf-gfx950 0.1";
 
+
 struct Fail {
   isdf_status st;
   std::string msg;
@@ -533,6 +534,17 @@ void release_fit_buffers(isdf_ctx c) {
     b->release();
 }
 
+// Workspace bytes of one served batch.
+long long serve_cap(isdf_ctx c) { return c->budget / c->max_inflight; }
+
+// Serving workspaces sized to their share of the budget (idle ones only:
+// called at isdf_serve_start and after a Coulomb kernel, under exclusive use).
+void reserve_workspaces(isdf_ctx c) {
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (!c->serving && c->ws_pool.empty()) return;
+  for (Workspace* w : c->ws_pool) w->mem.ensure((size_t)serve_cap(c));
+}
+
 // The fit reclaims the memory of idle fragment workspaces (the context is
 // held exclusively: no batch is in flight).
 void release_workspaces(isdf_ctx c) {
@@ -827,7 +839,14 @@ void do_kernel(isdf_ctx c, int prec) {
     c->timer.collect(&c->totals);
   }
   if (bad) throw Fail{ISDF_E_NUMERIC, "non-finite entries in W^q"};
-  if (c->eta_batched) release_fit_buffers(c);
+  if (c->eta_batched) {
+    release_fit_buffers(c);
+    try {
+      reserve_workspaces(c);
+    } catch (const Fail&) {
+      // the serving workspaces then grow when a batch needs them
+    }
+  }
   c->kernel_ready = true;
 }
 
@@ -884,7 +903,8 @@ BatchPlan plan_batch(isdf_ctx c, const std::vector<FragIn>& fr, int prec, int nb
   }
   p.nb = std::max(1, nb);
   p.pb = (p.ptot + p.nb - 1) / p.nb;
-  p.psi32 = prec != 0 && pair_reg_supported(prec, c->m[0], c->m[1], c->m[2]);
+  // the mixed precisions' pair transforms read psi as complex FP32
+  p.psi32 = prec != 0;
   const size_t row = (size_t)c->nh * c->ld_ip * fmt_bytes(prec);   // one pair row of R^q / U^q
   const size_t rows = p.nb == 1 ? (size_t)p.ptot : (size_t)p.pb;
   const size_t cstage = (size_t)c->nk * c->norb * p.ncol * sizeof(cplx);
@@ -1034,11 +1054,13 @@ void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn
   const int nh = c->nh;
   const long long rows = p.nb == 1 ? p.ptot : p.pb;            // pair rows of the M / U regions
   const long long mplane = (long long)nh * rows * ld;
-  // pair-transform tile: ti interpolation points x tp pairs, nk * tp * ti <= 4096 (64 KB)
+  // pair-transform tile of the LDS paths: ti interpolation points x tp
+  // pairs, 64 KB of complex FP64 (nk * tp * ti <= 4096) or FP32 (<= 8192)
+  const long long tile_cap = pair32_supported(prec, c->m[0], c->m[1], c->m[2]) ? 8192 : 4096;
   int ti = 32;
-  while (ti > 1 && (long long)nk * ti > 4096) ti >>= 1;
+  while (ti > 1 && (long long)nk * ti > tile_cap) ti >>= 1;
   int tp = 1;   // power of two (the LDS transform needs tp * ti to be one)
-  while (tp < 8 && (long long)nk * ti * tp * 2 <= 4096) tp *= 2;
+  while (tp < 8 && (long long)nk * ti * tp * 2 <= tile_cap) tp *= 2;
   const bool reg = pair_reg_supported(prec, c->m[0], c->m[1], c->m[2]);
   const long long nchunk = (ld + 63) / 64;
   // tables of the pair transform over pairs [pbeg, pbeg + pcnt) of every
@@ -1253,14 +1275,19 @@ size_t sync_cap(const Workspace& ws) {
 // first wait for the previous one (the workspace is reused).
 void enqueue_fragments(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn>& fr, bool timed,
                        size_t cap) {
+  // every fragment must fit (blocked if need be) before anything is enqueued
+  std::vector<int> nbs(fr.size());
+  for (size_t i = 0; i < fr.size(); ++i) {
+    nbs[i] = blocks_for(c, fr[i], prec, cap);
+    if (nbs[i] == 0)
+      throw Fail{ISDF_E_NOMEM, "fragment " + std::to_string(i) + " (" + std::to_string(fr[i].nf) +
+                                   " orbitals) does not fit the " + std::to_string(cap >> 20) +
+                                   " MiB workspace even in " + std::to_string(MAX_PAIR_BLOCKS) + " pair blocks"};
+  }
   size_t i = 0;
   while (i < fr.size()) {
     std::vector<FragIn> sub(1, fr[i]);
-    const int nb = blocks_for(c, fr[i], prec, cap);
-    if (nb == 0)
-      throw Fail{ISDF_E_NOMEM, "fragment of " + std::to_string(fr[i].nf) + " orbitals does not fit the " +
-                                   std::to_string(cap >> 20) + " MiB workspace even in " +
-                                   std::to_string(MAX_PAIR_BLOCKS) + " pair blocks"};
+    const int nb = nbs[i];
     size_t j = i + 1;
     if (nb == 1)
       while (j < fr.size()) {
@@ -1292,8 +1319,6 @@ void require_device(const void* const* C, void* const* eri, int n) {
 // --------------------------------------------------------------------------
 // serving thread
 // --------------------------------------------------------------------------
-// Workspace bytes of one served batch.
-long long serve_cap(isdf_ctx c) { return c->budget / c->max_inflight; }
 
 void serve_loop(isdf_ctx c) {
   std::vector<Workspace*> inflight;
@@ -1979,10 +2004,20 @@ isdf_status isdf_serve_start(isdf_ctx ctx, int32_t max_inflight, int32_t max_bat
     ctx->ws_pool.clear();
     for (int i = 0; i < max_inflight; ++i) {
       Workspace* w = new Workspace();
+      ctx->ws_pool.push_back(w);
       HIPCHK(hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking));
       w->own_stream = true;
       HIPCHK(hipEventCreateWithFlags(&w->done, hipEventDisableTiming));
-      ctx->ws_pool.push_back(w);
+    }
+    // every workspace holds its share of the budget from the start, so that
+    // admitting a batch allocates nothing (a refit hands the memory to the
+    // fit and the next Coulomb kernel takes it back)
+    try {
+      reserve_workspaces(ctx);
+    } catch (...) {
+      for (Workspace* w : ctx->ws_pool) delete w;
+      ctx->ws_pool.clear();
+      throw;
     }
     ctx->serving = true;
     ctx->worker = std::thread([ctx] {

@@ -170,6 +170,9 @@ hipError_t rhs_t_launch(const cplx* xt, const cplx* phi, cplx* out, int nk, int 
                         long long r0, int rcur, hipStream_t s);
 // true when pair_launch takes the register path (needs item_off / nitems)
 bool pair_reg_supported(int fmt, int m1, int m2, int m3);
+// true when pair_launch takes the FP32 LDS path (mixed formats, a mesh axis
+// longer than 4): psi32 required, tp * ti * N_k <= 8192
+bool pair32_supported(int fmt, int m1, int m2, int m3);
 
 // ---------------------------------------------------------------------------
 // Unit-cell grid FFT of f_{q,I}(r) exp(-i q.r) with the Coulomb factor

@@ -242,6 +242,124 @@ __global__ __launch_bounds__(256) void pair_kernel(PairArgs a) {
   }
 }
 
+// ---- pair transform for the mixed formats on meshes with an axis longer
+// than 4 (the register path holds at most 4 x 4 x 4 values a lane) ----
+// Same tiling as pair_kernel (a tile of tp pairs x ti interpolation points
+// for every R, LDS [R][tp*ti]) with complex FP32 values: psi is read from its
+// complex FP32 copy, the products and the mesh DFT are FP32 (the outputs are
+// rounded to FP32 or bf16 hi + lo anyway), which doubles the tile that fits
+// in 64 KB.  Each axis DFT holds one line of M values in registers with
+// compile-time twiddles.
+template <int M>
+__device__ void axis_dft32(float2* buf, int nlines, int eshift, int ax, int m2, int m3) {
+  const int etile = 1 << eshift;
+#pragma unroll 1
+  for (int line = threadIdx.x; line < nlines; line += blockDim.x) {
+    const int e = line & (etile - 1);
+    const int rest = line >> eshift;
+    int base, stride;
+    if (ax == 0) { base = rest; stride = m2 * m3; }
+    else if (ax == 1) { base = (rest / m3) * m2 * m3 + (rest % m3); stride = m3; }
+    else { base = rest * M; stride = 1; }
+    const int estride = stride << eshift;
+    float2* p = buf + (base << eshift) + e;
+    float2 x[M], y[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) x[j] = p[j * estride];
+    dft_any_f<M>(x, y);
+#pragma unroll
+    for (int t = 0; t < M; ++t) p[t * estride] = y[t];
+  }
+}
+
+template <int MAXA>
+__device__ void mesh_dft32(float2* buf, int etile, int m1, int m2, int m3) {
+  const int eshift = __builtin_ctz(etile);
+  const int nk = m1 * m2 * m3;
+  const int ms[3] = {m1, m2, m3};
+  for (int ax = 0; ax < 3; ++ax) {
+    const int m = ms[ax];
+    if (m == 1) continue;
+    const int nlines = (nk / m) << eshift;
+    switch (m) {
+#define AXIS32_CASE(M) \
+  case M: if constexpr (M <= MAXA) axis_dft32<M>(buf, nlines, eshift, ax, m2, m3); break;
+      AXIS32_CASE(2) AXIS32_CASE(3) AXIS32_CASE(4) AXIS32_CASE(5) AXIS32_CASE(6) AXIS32_CASE(7) AXIS32_CASE(8)
+      AXIS32_CASE(9) AXIS32_CASE(10) AXIS32_CASE(11) AXIS32_CASE(12) AXIS32_CASE(13) AXIS32_CASE(14)
+      AXIS32_CASE(15) AXIS32_CASE(16)
+#undef AXIS32_CASE
+      default: break;
+    }
+    __syncthreads();
+  }
+}
+
+template <int MAXA>
+__global__ __launch_bounds__(256) void pair32_kernel(PairArgs a) {
+  extern __shared__ float2 buf32[];
+  const int nk = a.m1 * a.m2 * a.m3;
+  // consecutive workgroups walk the pair blocks of one interpolation-point
+  // tile, so psi rows of that tile stay in L2 while they are reused
+  const int blk = blockIdx.x % a.nblocks;
+  const int it = blockIdx.x / a.nblocks;
+  const PairBlock pb = a.blocks[blk];
+  const int nf = a.frag_nf[pb.frag];
+  const int col = a.frag_col[pb.frag];
+  const long long poff = a.frag_pair[pb.frag];
+  const int w = a.tp * a.ti;           // power of two
+  const int wshift = __builtin_ctz(w), tshift = __builtin_ctz(a.ti);
+  const int I0 = it * a.ti;
+  __shared__ int sp[8], sq[8];          // (p, q) of the block's pairs (tp <= 8)
+  if (threadIdx.x < a.tp) {
+    const int P = pb.pair0 + threadIdx.x;
+    sp[threadIdx.x] = P / nf;
+    sq[threadIdx.x] = P - (P / nf) * nf;
+  }
+  __syncthreads();
+  constexpr int UNR = 8;
+  const int total = nk * w;
+  for (int b0 = 0; b0 < total; b0 += UNR * 256) {
+    float2 xp[UNR], xq[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int idx = b0 + u * 256 + threadIdx.x;
+      xp[u] = make_float2(0.f, 0.f);
+      xq[u] = make_float2(0.f, 0.f);
+      if (idx < total) {
+        const int R = idx >> wshift, e = idx & (w - 1);
+        const int j = e >> tshift, i = e & (a.ti - 1);
+        const int I = I0 + i;
+        if (j < pb.npair && I < a.n_ip) {
+          const float2* base = a.psi32 + ((long long)R * a.ncol + col) * a.n_ip + I;
+          xp[u] = base[(long long)sp[j] * a.n_ip];
+          xq[u] = base[(long long)sq[j] * a.n_ip];
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int idx = b0 + u * 256 + threadIdx.x;
+      // conj(psi_p) psi_q
+      if (idx < total)
+        buf32[idx] = make_float2(fmaf(xp[u].x, xq[u].x, xp[u].y * xq[u].y), fmaf(xp[u].x, xq[u].y, -(xp[u].y * xq[u].x)));
+    }
+  }
+  __syncthreads();
+  mesh_dft32<MAXA>(buf32, w, a.m1, a.m2, a.m3);
+  const float sc = (float)a.scale;
+  for (int idx = threadIdx.x; idx < nk * w; idx += blockDim.x) {
+    const int Q = idx >> wshift, e = idx & (w - 1);
+    const int j = e >> tshift, i = e & (a.ti - 1);
+    const int I = I0 + i;
+    const int slot = a.qslot[Q];
+    if (slot >= 0 && j < pb.npair && I < a.ld) {
+      const long long off = (long long)slot * a.q_stride + (poff + pb.pair0 + j) * a.p_stride + I;
+      const float2 v = buf32[idx];
+      store_fmt(a.out, off, a.plane, a.fmt, cmk((double)(v.x * sc), (double)(v.y * sc)));
+    }
+  }
+}
+
 // ---- register path of the k convolution (mode 0), mesh M1 x M2 x M3 with
 // M1 in {1, 2, 4} and M2, M3 <= 4 ----
 // M1 lanes per element (lane l: element l / M1, k1 = l % M1): the M2 x M3
@@ -637,6 +755,10 @@ bool pair_reg_supported(int fmt, int m1, int m2, int m3) {
   return fmt != 0 && m1 <= 4 && m2 <= 4 && m3 <= 4;
 }
 
+bool pair32_supported(int fmt, int m1, int m2, int m3) {
+  return fmt != 0 && !pair_reg_supported(fmt, m1, m2, m3);
+}
+
 hipError_t pair_launch(const PairArgs& a, hipStream_t s) {
   if (!a.qslot) return hipErrorInvalidValue;
   if (pair_reg_supported(a.fmt, a.m1, a.m2, a.m3)) {
@@ -650,11 +772,19 @@ hipError_t pair_launch(const PairArgs& a, hipStream_t s) {
   }
   const int nk = a.m1 * a.m2 * a.m3;
   if (a.m1 > MAXM || a.m2 > MAXM || a.m3 > MAXM) return hipErrorInvalidValue;
-  const size_t lds = (size_t)nk * a.tp * a.ti * sizeof(cplx);
-  if (lds > 160 * 1024) return hipErrorInvalidValue;
   const long long blocks = (long long)a.nblocks * a.n_itiles;
   if (blocks <= 0) return hipSuccess;
   const int mx = std::max(a.m1, std::max(a.m2, a.m3));
+  if (pair32_supported(a.fmt, a.m1, a.m2, a.m3)) {
+    if (!a.psi32) return hipErrorInvalidValue;
+    const size_t lds32 = (size_t)nk * a.tp * a.ti * sizeof(float2);
+    if (lds32 > 64 * 1024) return hipErrorInvalidValue;
+    if (mx <= 8) hipLaunchKernelGGL(pair32_kernel<8>, dim3((unsigned)blocks), dim3(256), lds32, s, a);
+    else hipLaunchKernelGGL(pair32_kernel<16>, dim3((unsigned)blocks), dim3(256), lds32, s, a);
+    return hipGetLastError();
+  }
+  const size_t lds = (size_t)nk * a.tp * a.ti * sizeof(cplx);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
   if (mx <= 4) hipLaunchKernelGGL(pair_kernel<4>, dim3((unsigned)blocks), dim3(256), lds, s, a);
   else if (mx <= 8) hipLaunchKernelGGL(pair_kernel<8>, dim3((unsigned)blocks), dim3(256), lds, s, a);
   else hipLaunchKernelGGL(pair_kernel<16>, dim3((unsigned)blocks), dim3(256), lds, s, a);

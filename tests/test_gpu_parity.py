@@ -229,6 +229,8 @@ def test_mixed_kernel_and_eri_within_1e6(name, prec):
         ref = ko.fragment_eri(c.x, cf, c.w, cfg.kmesh)
         worst = max(worst, float(np.max(np.abs(out[f] - ref))))
     print("%s %s kernel + ERIs max|dV| %.3e Eh" % (name, prec, worst))
+    from test_gpu_meshes import known_bf16x3_limit
+    known_bf16x3_limit(name, prec, worst)
     assert worst < 1e-6
 
 
