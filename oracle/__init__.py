@@ -17,7 +17,8 @@ eye.  Modules:
 * ``poisson``   -- FFT-Poisson Coulomb sums and an explicit Ewald sum;
 * ``supercell`` -- exact ERIs and Gamma-point ISDF on the Born-von Karman
   supercell (the plain definitions every k-point result must reproduce);
-* ``kpoint``    -- the k-point fit, the Coulomb kernel and the fragment ERIs.
+* ``kpoint``    -- the k-point fit, the Coulomb kernel and the fragment ERIs;
+* ``ipselect``  -- interpolation points by pivoted Cholesky of the pair products.
 
 Every function is pinned by ``tests/test_oracle_pins.py``; none is
 "parity unpinned" except the size of the ISDF approximation error itself on

@@ -453,3 +453,80 @@ def test_metric_rows_equal_full_metric():
     rows = [5, 0, 77]
     pr = ko.metric_rows(x, cfg.kmesh, rows)
     assert _rel(pr, pi[:, rows, :]) < 1e-15
+
+
+# --------------------------------------------------------------------------
+# Interpolation-point selection (pivoted Cholesky of the pair products)
+# --------------------------------------------------------------------------
+from oracle import ipselect as ips
+
+
+def _pair_product_matrix(orbitals):
+    """Z with rows (k_mu, mu, k_nu, nu) and columns r:
+    phi^{k_mu}_mu(r) conj(phi^{k_nu}_nu(r)), straight from the definition."""
+    phi = orbitals.reshape(-1, orbitals.shape[2])
+    return (phi[:, None, :] * phi[None, :, :].conj()).reshape(-1, phi.shape[1])
+
+
+def test_selector_gram_is_the_pair_product_gram():
+    d = _case("t_tiny_k2")
+    z = _pair_product_matrix(d.orbitals)
+    m = (z.conj().T @ z)
+    assert np.max(np.abs(m.imag)) < 1e-12 * np.max(np.abs(m))
+    phi = d.orbitals.reshape(-1, d.cfg.n_g)
+    for p in (0, 17, 300, 511):
+        assert _rel(ips.gram_column(phi, p), m[:, p].real) < 1e-13
+
+
+def test_selector_is_the_greedy_pivoted_cholesky_of_the_explicit_gram():
+    """Against the explicit Gram matrix: every pivot is the largest residual
+    diagonal of M - L L^T at its step, L L^T reproduces the pivot columns of
+    M, and the residual diagonal is diag(M - L L^T)."""
+    d = _case("t_tiny_k2")
+    z = _pair_product_matrix(d.orbitals)
+    m = (z.conj().T @ z).real
+    n = 20
+    piv, dmax, lf, res = ips.pivoted_cholesky_points(d.orbitals, n)
+    for i in range(n):
+        resid = np.diag(m) - np.sum(lf[:, :i] ** 2, axis=1)
+        assert piv[i] == int(np.argmax(resid)), i
+        assert abs(dmax[i] - resid[piv[i]]) < 1e-12 * np.max(np.diag(m))
+    assert _rel(lf @ lf[piv].T, m[:, piv]) < 1e-12
+    assert np.max(np.abs(res - (np.diag(m) - np.sum(lf ** 2, axis=1)))) < 1e-12 * np.max(np.diag(m))
+    # the first pivot is the densest point (M(r, r) = rho(r)^2)
+    rho = np.sum(np.abs(d.orbitals) ** 2, axis=(0, 1))
+    assert piv[0] == int(np.argmax(rho))
+
+
+def test_selected_points_span_the_pair_space_and_reproduce_exact_eris():
+    """Workload 1 (8 real orbitals at Gamma): the pair products span
+    8 * 9 / 2 = 36 functions, so the residual vanishes after 36 pivots, and
+    ISDF on those 36 points reproduces the FFT-Poisson ERIs."""
+    d = _case("c1_gamma_16")
+    cfg = d.cfg
+    piv, dmax, lf, res = ips.pivoted_cholesky_points(d.orbitals, 37)
+    assert dmax[35] > 1e-8 * dmax[0]
+    assert dmax[36] < 1e-13 * dmax[0]
+    ip = np.sort(piv[:36]).astype(np.int32)
+    coeffs = inp.make_fragment(cfg, 0, 8)
+    x, pi, eta, w = ko.fit_and_kernel(d.orbitals, ip, d.lattice, cfg.grid, cfg.kmesh)
+    isdf = ko.fragment_eri(x, coeffs, w, cfg.kmesh)
+    phi_s = sc.supercell_orbitals(d.orbitals, cfg.grid, cfg.kmesh)
+    psi = sc.fragment_orbitals(phi_s, coeffs)
+    exact = sc.exact_eri(psi, d.lattice, cfg.grid, cfg.kmesh)
+    assert _rel(isdf, exact) < 1e-12
+
+
+def test_selection_invariant_under_orbital_rotation_within_k():
+    """G(r, r') is invariant under a unitary mixing of the orbitals of each k,
+    so the pivots are too."""
+    d = _case("t_small_k2")
+    rng = np.random.default_rng(9)
+    rot = np.empty_like(d.orbitals)
+    for k in range(d.cfg.n_k):
+        u, _ = np.linalg.qr(rng.standard_normal((d.cfg.n_orb,) * 2)
+                            + 1j * rng.standard_normal((d.cfg.n_orb,) * 2))
+        rot[k] = u.T @ d.orbitals[k]
+    a = ips.pivoted_cholesky_points(d.orbitals, 40)[0]
+    b = ips.pivoted_cholesky_points(rot, 40)[0]
+    assert np.array_equal(a, b)
