@@ -202,6 +202,27 @@ isdf_status isdf_fragment_eri(isdf_ctx ctx, isdf_precision prec, int32_t n_frag,
                               uint32_t flags);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * fragment ERIs as isdf_fragment_eri (same kernels, bit-identical results),
+ * with the whole workspace -- coefficient gather, psi, R^q, U^q, the FP64
+ * contraction and the launch descriptors -- in a static device array of
+ * ISDF_STATIC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends (4 MiB of it for descriptors).  The call allocates
+ * and frees no device memory.  C[f] and eri[f] must be device pointers
+ * (flags must include ISDF_FRAG_DEVICE).  Fragments run in sub-batches and
+ * (pq) blocks that fit the array; a fragment that does not fit even in 32
+ * pair blocks is refused with ISDF_E_NOMEM before any launch.  No part of
+ * the array needs to start at zero.  Every call on a GPU shares that GPU's
+ * array (also across contexts): calls that overlap in time on one GPU race
+ * and must be serialised by the caller.  Synchronous.  Errors as
+ * isdf_fragment_eri, ISDF_E_INVALID for host pointers.
+ */
+#define ISDF_STATIC_SCRATCH_BYTES (256ull << 20)
+isdf_status isdf_fragment_eri_static(isdf_ctx ctx, isdf_precision prec, int32_t n_frag, const int32_t* n_f,
+                                     const void* const* C, void* const* eri, uint32_t flags);
+
+/*
  * A fragment batch captured as a HIP graph (the batched persistent launch of
  * Algorithm 2 replayed without host-side launch work, for callers that run the
  * same batch shape repeatedly).  isdf_graph_create runs the batch once on a

@@ -46,11 +46,52 @@ double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+// Workspace of isdf_fragment_eri_static: a file-scope device array that the
+// library never allocates or frees (each GPU that loads the library holds
+// its own copy for the life of the process).  Its first STATIC_DESC_BYTES
+// hold the descriptors of a call, the rest the fragment workspace.  Host
+// code never passes `scratch` itself to a kernel: it takes the device
+// address of this GPU's copy from hipGetSymbolAddress once per device
+// (scratch_ptr) and passes that.
+constexpr size_t STATIC_SCRATCH_BYTES = ISDF_STATIC_SCRATCH_BYTES;
+constexpr size_t STATIC_DESC_BYTES = (size_t)4 << 20;
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;    // device -> address of its copy of scratch
+
+// Address of the current device's copy of scratch (looked up once per device).
+void* scratch_ptr(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(device);
+  if (it != g_scratch_ptr.end()) return it->second;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    (void)hipGetLastError();
+    throw Fail{ISDF_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e)};
+  }
+  g_scratch_ptr[device] = ptr;
+  return ptr;
+}
+
 // Device allocation that is freed with its owner.
+// A buffer attached to caller-provided memory (attach) never allocates or
+// frees: asking it for more than it holds is ISDF_E_NOMEM.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  bool fixed = false;
+  void attach(void* ptr, size_t b) {
+    release();
+    p = ptr;
+    bytes = b;
+    fixed = true;
+  }
   void alloc(size_t b) {
+    if (fixed)
+      throw Fail{ISDF_E_NOMEM, "needs " + std::to_string(b) + " bytes of the " + std::to_string(bytes) +
+                                   "-byte static workspace"};
     release();
     if (b == 0) return;
     hipError_t e = hipMalloc(&p, b);
@@ -65,9 +106,10 @@ struct DevBuf {
     if (b > bytes) alloc(b);
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p && !fixed) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
+    fixed = false;
   }
   ~DevBuf() { release(); }
   template <class T> T* as() const { return reinterpret_cast<T*>(p); }
@@ -104,6 +146,16 @@ struct Arena {
   PinnedBuf host;
   DevBuf dev;
   size_t used = 0;
+  // attached to caller-provided device memory: descriptors are staged in
+  // pageable host memory and nothing is allocated on the device
+  std::vector<char> pageable;
+  void attach(void* dev_ptr, size_t cap) {
+    dev.attach(dev_ptr, cap);
+    pageable.assign(cap, 0);
+    used = 0;
+  }
+  char* host_ptr() { return dev.fixed ? pageable.data() : (char*)host.p; }
+  size_t host_cap() const { return dev.fixed ? pageable.size() : host.bytes; }
   void reset(hipStream_t s) {
     HIPCHK(hipStreamSynchronize(s));
     used = 0;
@@ -112,6 +164,12 @@ struct Arena {
   // alignment); the stream has drained (reset) and nothing was put yet.
   void reserve(size_t bytes) {
     if (used != 0) throw Fail{ISDF_E_INVALID, "descriptor arena reserved after a put"};
+    if (dev.fixed) {
+      if (bytes > dev.bytes)
+        throw Fail{ISDF_E_NOMEM, "descriptors need " + std::to_string(bytes) + " bytes of the " +
+                                     std::to_string(dev.bytes) + "-byte static descriptor region"};
+      return;
+    }
     const size_t cap = std::max<size_t>(1 << 20, bytes);
     if (host.bytes < cap) host.ensure(cap);
     if (dev.bytes < cap) dev.ensure(cap);
@@ -119,15 +177,15 @@ struct Arena {
   template <class T> T* put(const T* src, size_t n, hipStream_t s) {
     size_t bytes = n * sizeof(T);
     size_t off = (used + 255) & ~size_t(255);
-    if (off + bytes > host.bytes || off + bytes > dev.bytes) {
-      if (used != 0) throw Fail{ISDF_E_NOMEM, "descriptor arena exhausted"};
+    if (off + bytes > host_cap() || off + bytes > dev.bytes) {
+      if (used != 0 || dev.fixed) throw Fail{ISDF_E_NOMEM, "descriptor arena exhausted"};
       size_t cap = std::max<size_t>(1 << 20, 2 * bytes);
       host.ensure(cap);
       dev.ensure(cap);
       off = 0;
     }
-    memcpy((char*)host.p + off, src, bytes);
-    HIPCHK(hipMemcpyAsync((char*)dev.p + off, (char*)host.p + off, bytes, hipMemcpyHostToDevice, s));
+    memcpy(host_ptr() + off, src, bytes);
+    HIPCHK(hipMemcpyAsync((char*)dev.p + off, host_ptr() + off, bytes, hipMemcpyHostToDevice, s));
     used = off + bytes;
     return reinterpret_cast<T*>((char*)dev.p + off);
   }
@@ -374,6 +432,10 @@ struct isdf_ctx_s {
   std::string err;
   // fragment workspace of the synchronous call
   Workspace sync_ws;
+  // workspace of isdf_fragment_eri_static: attached to this device's copy of
+  // the static scratch array (address from set-up), never allocated
+  Workspace static_ws;
+  void* scratch = nullptr;
   // serving
   std::mutex mu;
   std::condition_variable cv;
@@ -1530,6 +1592,8 @@ void setup_context(isdf_ctx c, const double* lattice, const int32_t grid[3], con
     HIPCHK(hipMemcpy(c->qmap.p, qm.data(), sizeof(int) * qm.size(), hipMemcpyHostToDevice));
   }
   c->sync_ws.stream = c->stream;
+  // this device's copy of the static workspace array
+  c->scratch = scratch_ptr(c->device);
   HIPCHK(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
   HIPCHK(hipStreamCreateWithFlags(&c->aux2, hipStreamNonBlocking));
   for (int b = 0; b < 2; ++b) {
@@ -1837,6 +1901,34 @@ isdf_status isdf_fragment_eri(isdf_ctx ctx, isdf_precision prec, int32_t n_frag,
     std::lock_guard<std::mutex> lk(ctx->mu);
     ctx->sync_ws.timer.collect(&ctx->totals);
     for (auto& kv : ctx->sync_ws.timer.ms) ctx->timer.ms[kv.first] = kv.second;
+  });
+}
+
+isdf_status isdf_fragment_eri_static(isdf_ctx ctx, isdf_precision prec, int32_t n_frag, const int32_t* n_f,
+                                     const void* const* C, void* const* eri, uint32_t flags) {
+  return guarded(ctx, [&] {
+    if (n_frag < 1 || !n_f || !C || !eri) throw Fail{ISDF_E_INVALID, "bad fragment arguments"};
+    if (prec < ISDF_FP64 || prec > ISDF_MIXED_BF16X3) throw Fail{ISDF_E_INVALID, "bad precision"};
+    if (!(flags & ISDF_FRAG_DEVICE)) throw Fail{ISDF_E_INVALID, "the static variant takes device pointers only"};
+    if (!ctx->kernel_ready) throw Fail{ISDF_E_STATE, "isdf_coulomb_kernel must run before fragment ERIs"};
+    if (!ctx->scratch) throw Fail{ISDF_E_STATE, "static workspace not set up"};
+    std::vector<FragIn> fr;
+    for (int f = 0; f < n_frag; ++f) {
+      if (n_f[f] < 1 || n_f[f] > ctx->nk * ctx->norb || !C[f] || !eri[f])
+        throw Fail{ISDF_E_INVALID, "bad fragment " + std::to_string(f)};
+      fr.push_back(FragIn{n_f[f], C[f], eri[f], ISDF_FRAG_DEVICE});
+    }
+    require_device(C, eri, n_frag);
+    Workspace& ws = ctx->static_ws;
+    if (ws.mem.p != (char*)ctx->scratch + STATIC_DESC_BYTES) {
+      ws.stream = ctx->stream;
+      ws.arena.attach(ctx->scratch, STATIC_DESC_BYTES);
+      ws.mem.attach((char*)ctx->scratch + STATIC_DESC_BYTES, STATIC_SCRATCH_BYTES - STATIC_DESC_BYTES);
+    }
+    // sub-batches and (pq)-blocking within the array; a fragment that does
+    // not fit even in the largest blocking is refused before any launch
+    enqueue_fragments(ctx, ws, prec, fr, false, STATIC_SCRATCH_BYTES - STATIC_DESC_BYTES);
+    HIPCHK(hipStreamSynchronize(ctx->stream));
   });
 }
 

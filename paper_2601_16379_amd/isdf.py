@@ -30,7 +30,8 @@ EXPORTS = ["isdf_create", "isdf_fit", "isdf_coulomb_kernel", "isdf_get_metric",
            "isdf_serve_start", "isdf_submit", "isdf_submit_n", "isdf_poll", "isdf_cancel",
            "isdf_serve_stop", "isdf_stats", "isdf_stage_ms", "isdf_stage_total", "isdf_stage_reset", "isdf_plan_bytes", "isdf_storage_model_bytes",
            "isdf_graph_create", "isdf_graph_launch", "isdf_graph_destroy", "isdf_autotune", "isdf_set_tiling",
-           "isdf_save", "isdf_load", "isdf_destroy", "isdf_last_error", "isdf_version"]
+           "isdf_save", "isdf_load", "isdf_fragment_eri_static", "isdf_destroy", "isdf_last_error",
+           "isdf_version"]
 
 
 class IsdfError(RuntimeError):
@@ -79,6 +80,7 @@ def load_library(path=LIB_PATH):
         "isdf_get_rhs": (I32, [P, I32, P]),
         "isdf_get_eta_tilde": (I32, [P, I32, P]),
         "isdf_fragment_eri": (I32, [P, I32, I32, P, P, P, U32]),
+        "isdf_fragment_eri_static": (I32, [P, I32, I32, P, P, P, U32]),
         "isdf_serve_start": (I32, [P, I32, I32, I64]),
         "isdf_submit": (I32, [P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
         "isdf_submit_n": (I32, [P, I32, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
