@@ -486,11 +486,14 @@ def test_selector_is_the_greedy_pivoted_cholesky_of_the_explicit_gram():
     z = _pair_product_matrix(d.orbitals)
     m = (z.conj().T @ z).real
     n = 20
-    piv, dmax, lf, res = ips.pivoted_cholesky_points(d.orbitals, n)
+    piv, dmax, lf, res, gap = ips.pivoted_cholesky_points(d.orbitals, n, with_gaps=True)
     for i in range(n):
         resid = np.diag(m) - np.sum(lf[:, :i] ** 2, axis=1)
+        resid[piv[:i]] = 0.0                       # chosen points leave the candidate set
         assert piv[i] == int(np.argmax(resid)), i
         assert abs(dmax[i] - resid[piv[i]]) < 1e-12 * np.max(np.diag(m))
+        top = np.sort(resid)[::-1]
+        assert abs(gap[i] - (top[0] - top[1])) < 1e-12 * np.max(np.diag(m))
     assert _rel(lf @ lf[piv].T, m[:, piv]) < 1e-12
     assert np.max(np.abs(res - (np.diag(m) - np.sum(lf ** 2, axis=1)))) < 1e-12 * np.max(np.diag(m))
     # the first pivot is the densest point (M(r, r) = rho(r)^2)
@@ -508,6 +511,11 @@ def test_selected_points_span_the_pair_space_and_reproduce_exact_eris():
     assert dmax[35] > 1e-8 * dmax[0]
     assert dmax[36] < 1e-13 * dmax[0]
     ip = np.sort(piv[:36]).astype(np.int32)
+    # beyond the rank the residuals are rounding noise, and no point is
+    # chosen twice
+    piv48, dmax48 = ips.pivoted_cholesky_points(d.orbitals, 48)[:2]
+    assert len(set(piv48.tolist())) == 48
+    assert np.all(dmax48[36:] < 1e-13 * dmax48[0])
     coeffs = inp.make_fragment(cfg, 0, 8)
     x, pi, eta, w = ko.fit_and_kernel(d.orbitals, ip, d.lattice, cfg.grid, cfg.kmesh)
     isdf = ko.fragment_eri(x, coeffs, w, cfg.kmesh)
