@@ -78,6 +78,9 @@ typedef enum {
 /* flags for isdf_create */
 #define ISDF_INPUT_DEVICE 0x1u   /* orbitals / ip_index are device pointers      */
 #define ISDF_NO_PIVOT 0x2u       /* plain Cholesky: a singular Pi^q is an error  */
+/* isdf_coulomb_kernel takes the zeta route of eqs. (3) and (6) (xi^q = Pi^{q+}
+ * eta^q, FFT, W^q = xihat^H c xihat) instead of eqs. (7)-(8) */
+#define ISDF_ZETA_ROUTE 0x4u
 /* at most n classes {q, -q} of eta per q batch (bits 16-31; 0 = as many as
  * fit, see isdf_fit) */
 #define ISDF_Q_BATCH(n) ((((uint32_t)(n)) & 0xFFFFu) << 16)
@@ -119,6 +122,40 @@ isdf_status isdf_create(isdf_ctx* out, const double* lattice, const int32_t grid
                         void* hip_stream);
 
 /*
+ * Interpolation points by pivoted Cholesky of the pair products (the
+ * IP-selection paragraph of the section "Periodic k-point FFTISDF
+ * representation of integrals"): the products
+ * phi^{k_mu}_mu(r) conj(phi^{k_nu}_nu(r)) have the Gram matrix
+ * M(x, y) = |sum_k sum_mu phi^k_mu(x) conj(phi^k_mu(y))|^2 over grid points,
+ * and the greedy Cholesky of M with diagonal pivoting selects its first n_ip
+ * pivots: start from the residual d(x) = M(x, x) = rho(x)^2; at each step take
+ * the point p of largest residual (lowest index among equals), form the
+ * factor column L(x) = (M(x, p) - sum of the previous columns' L(x) L(p)) /
+ * sqrt(d(p)), lower d by L(x)^2 and set d(p) = 0.  M is never formed: a step
+ * reads the orbitals once.  FP64.
+ *   grid, kmesh, n_orb  as isdf_create (n_ip <= N_g).
+ *   orbitals   c128 [N_k][n_orb][N_g], host or device (ISDF_INPUT_DEVICE),
+ *              the layout isdf_create takes.
+ *   ip_out     int32 [n_ip], host: the pivots in selection order, ready to
+ *              pass to isdf_create as ip_index.
+ *   residual_out  float64 [n_ip], host, or NULL: the residual d(p) of each
+ *              pivot when it was chosen (non-increasing in exact arithmetic;
+ *              its decay measures how well the first i points span the pair
+ *              products).
+ *   hip_stream  stream of the launches (0 = null stream).
+ * Synchronous; device workspace n_ip N_g 8 bytes plus a few grid-sized
+ * vectors (and a copy of host orbitals), freed on return.  Errors
+ * (message from isdf_last_error(NULL)): ISDF_E_INVALID for bad sizes or
+ * pointers; ISDF_E_NUMERIC when a step's largest residual is not positive
+ * (the products span fewer than n_ip grid columns, or the orbitals are not
+ * finite): ip_out / residual_out then hold the pivots found before it and -1
+ * / 0 after; ISDF_E_NOMEM, ISDF_E_DEVICE.
+ */
+isdf_status isdf_select_points(const int32_t grid[3], const int32_t kmesh[3], int32_t n_orb,
+                               const void* orbitals, int32_t n_ip, int32_t* ip_out,
+                               double* residual_out, uint32_t flags, void* hip_stream);
+
+/*
  * The fit: X^k_{I mu} = phi^k_mu(r_I); T^k = X^k X^{k H}; Pi^q by the k
  * convolution of Algorithm 1 (|FFT_k^{-1} T|^2, FFT_k); eta^q_I(r) by the same
  * convolution of T^k_I(r) = sum_mu X^k_{I mu} conj(phi^k_mu(r)), r-tiled; then
@@ -152,6 +189,14 @@ isdf_status isdf_fit(isdf_ctx ctx, isdf_precision prec);
  * the error with an FP64 W^q stays within the 1e-6 Eh bound.  `prec` is
  * accepted for symmetry with isdf_fragment_eri.
  * Consumes eta (isdf_get_rhs is invalid afterwards).  Synchronous.
+ * With ISDF_ZETA_ROUTE (isdf_create flags) the kernel follows eqs. (3) and
+ * (6) instead: xi^q = Pi^{q+} eta^q for every grid point (one FP64 MFMA
+ * product per class with the pseudo-inverse P G P^T of the pivoted factor),
+ * the same scaled grid FFT of xi^q(r) exp(-i q.r), and W^q = xi~ xi~^H
+ * directly (FP64 MFMA); W^q equals the default route's in exact arithmetic.
+ * It needs eta of every class resident (isdf_fit formed it) and a second
+ * eta-sized buffer for xi (freed on return), else ISDF_E_NOMEM; eta stays
+ * valid.
  * Error: ISDF_E_STATE before isdf_fit.
  */
 isdf_status isdf_coulomb_kernel(isdf_ctx ctx, isdf_precision prec);

@@ -790,6 +790,102 @@ void do_fit(isdf_ctx c, int prec) {
 // --------------------------------------------------------------------------
 // Coulomb kernel
 // --------------------------------------------------------------------------
+// Common end of both routes: W^q in the fragment GEMMs' operand formats, the
+// finiteness check, and the fit's transient buffers handed back.
+void kernel_finish(isdf_ctx c) {
+  hipStream_t s = c->stream;
+  const int nk = c->nk, nip = c->nip, nh = c->nh;
+  // transposed copies of W in the three operand formats of the fragment GEMMs
+  // (one per class {q, -q}, weight 1/2 where q = -q: the fragment contraction
+  // adds the conjugate term of -q itself)
+  HIPCHK(wt_convert_launch(c->w.as<cplx>(), c->wt64.as<cplx>(), c->wt32.as<float>(),
+                           c->wt16.as<unsigned short>(), nip, (int)c->ld_ip, nh, c->qmap.as<int>() + nk + nh, s));
+  HIPCHK(hipMemsetAsync(c->flag.p, 0, sizeof(int), s));
+  HIPCHK(nonfinite_launch(c->w.as<cplx>(), (long long)nh * nip2(c), c->flag.as<int>(), s));
+  int bad = 0;
+  HIPCHK(hipMemcpyAsync(&bad, c->flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->timer.collect(&c->totals);
+  }
+  if (bad) throw Fail{ISDF_E_NUMERIC, "non-finite entries in W^q"};
+  if (c->eta_batched) {
+    release_fit_buffers(c);
+    try {
+      reserve_workspaces(c);
+    } catch (const Fail&) {
+      // the serving workspaces then grow when a batch needs them
+    }
+  }
+  c->kernel_ready = true;
+}
+
+// The zeta route (eqs. (3), (6)), all FP64:
+//   xi^q = Pi^{q+} eta^q  with Pi^{q+} = P G P^T (G = L^{-H} L^{-1} on the rank
+//   block of the pivoted factor, formed by isdf_fit), one MFMA product
+//   [N_IP x N_IP] [N_IP x N_g] per class;
+//   xi~^q_I(G) = sqrt(Omega 4pi/|K|^2)/N_g FFT[xi^q_I(r) exp(-iq.r)], in place;
+//   W^q = xi~ xi~^H (lower tiles, mirrored).
+// eta is left in place (it stays valid); xi lives in a buffer of eta's size
+// that is freed on return.
+void kernel_zeta_route(isdf_ctx c) {
+  hipStream_t s = c->stream;
+  const int nip = c->nip, nh = c->nh, nk = c->nk;
+  const long long ng = c->ng;
+  if (c->eta_batched || !c->eta_valid)
+    throw Fail{ISDF_E_NOMEM, "the zeta route needs eta of every class resident (isdf_fit formed it per q batch)"};
+  DevBuf xi;
+  xi.alloc(sizeof(cplx) * (size_t)nh * nip * ng);
+  HIPCHK(hipStreamWaitEvent(s, c->ev_pinv, 0));   // G from isdf_fit's second stream
+  c->timer.begin("zeta_solve", s);
+  {
+    // Pi^+ in natural order (zero outside the rank block before the scatter)
+    HIPCHK(permute_launch(c->work3.as<cplx>(), c->work2.as<cplx>(), c->perm.as<int>(), c->rank.as<int>(), nip, nh,
+                          1, s));
+    std::vector<GemmDesc> d(1);
+    d[0] = mkdesc(c->work2.as<cplx>(), nip, c->eta.as<cplx>(), ng, xi.as<cplx>(), ng, nip, (int)ng, nip);
+    d[0].batch = nh;
+    d[0].sA_bat = nip2(c);
+    d[0].sB_bat = d[0].sC_bat = (long long)nip * ng;
+    run_gemm(c->arena, 0, GEMM_B_KN, d, s);
+  }
+  c->timer.end("zeta_solve", s);
+  c->timer.begin("grid_fft", s);
+  {
+    GridFftArgs a;
+    memset(&a, 0, sizeof(a));
+    a.data = xi.as<cplx>();
+    a.n1 = c->n[0]; a.n2 = c->n[1]; a.n3 = c->n[2];
+    a.m1 = c->m[0]; a.m2 = c->m[1]; a.m3 = c->m[2];
+    a.q0 = 0;
+    a.nq = nh;
+    a.qlist = c->qmap.as<int>() + nk;
+    a.n_ip = nip;
+    a.q_stride = (long long)nip * ng;
+    memcpy(a.recip, c->recip, sizeof(a.recip));
+    a.volume = c->volume;
+    HIPCHK(gridfft_launch(a, s));
+  }
+  c->timer.end("grid_fft", s);
+  c->timer.begin("w_gemm", s);
+  {
+    std::vector<NtDesc> d(1);
+    d[0] = mknt(xi.p, ng, xi.p, ng, c->w.p, nip, nip, nip, (int)ng);
+    d[0].sA_bat = d[0].sB_bat = (long long)nip * ng;
+    d[0].batch = nh;
+    d[0].sC_bat = nip2(c);
+    d[0].herm = 1;
+    run_nt(c->arena, ISDF_FP64, 2, d, s, 1);
+  }
+  c->timer.end("w_gemm", s);
+  c->kernel_pending = false;
+  c->etat_valid = false;
+  kernel_finish(c);
+  // xi is freed with its buffer once the stream has drained (kernel_finish
+  // synchronised it)
+}
+
 void do_kernel(isdf_ctx c, int prec) {
   if (!c->fitted || !c->kernel_pending) throw Fail{ISDF_E_STATE, "isdf_fit must run before isdf_coulomb_kernel"};
   // The kernel is FP64 in every precision: W^q = Pi^+ V^q Pi^+ amplifies the
@@ -807,6 +903,11 @@ void do_kernel(isdf_ctx c, int prec) {
   // descriptor per class for each of its two products
   c->arena.reserve(((size_t)1 << 20) + (size_t)nh * 2 * (sizeof(NtDesc) + 256) +
                    (size_t)((nh + std::max(c->qb, 1) - 1) / std::max(c->qb, 1)) * (nk * sizeof(int) + 4096));
+  // the zeta route of eqs. (3) and (6): xi^q = Pi^{q+} eta^q, FFT, W^q = xi~ xi~^H
+  if (c->flags & ISDF_ZETA_ROUTE) {
+    kernel_zeta_route(c);
+    return;
+  }
   // q batches of qb classes (one batch, eta formed by the fit, when they all
   // fit); per batch: eta (when batched), the grid FFT, V^q
   const int qb = c->eta_batched ? c->qb : nh;
@@ -886,30 +987,7 @@ void do_kernel(isdf_ctx c, int prec) {
                           nip, nh, 1, s));
   }
   c->timer.end("w_solve", s);
-  // transposed copies of W in the three operand formats of the fragment GEMMs
-  // (one per class {q, -q}, weight 1/2 where q = -q: the fragment contraction
-  // adds the conjugate term of -q itself)
-  HIPCHK(wt_convert_launch(c->w.as<cplx>(), c->wt64.as<cplx>(), c->wt32.as<float>(),
-                           c->wt16.as<unsigned short>(), nip, (int)c->ld_ip, nh, c->qmap.as<int>() + nk + nh, s));
-  HIPCHK(hipMemsetAsync(c->flag.p, 0, sizeof(int), s));
-  HIPCHK(nonfinite_launch(c->w.as<cplx>(), (long long)nh * nip2(c), c->flag.as<int>(), s));
-  int bad = 0;
-  HIPCHK(hipMemcpyAsync(&bad, c->flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  {
-    std::lock_guard<std::mutex> lk(c->mu);
-    c->timer.collect(&c->totals);
-  }
-  if (bad) throw Fail{ISDF_E_NUMERIC, "non-finite entries in W^q"};
-  if (c->eta_batched) {
-    release_fit_buffers(c);
-    try {
-      reserve_workspaces(c);
-    } catch (const Fail&) {
-      // the serving workspaces then grow when a batch needs them
-    }
-  }
-  c->kernel_ready = true;
+  kernel_finish(c);
 }
 
 // --------------------------------------------------------------------------
@@ -1740,6 +1818,83 @@ isdf_status isdf_create(isdf_ctx* out, const double* lattice, const int32_t grid
     return st;
   }
   *out = c;
+  return ISDF_OK;
+}
+
+isdf_status isdf_select_points(const int32_t grid[3], const int32_t kmesh[3], int32_t n_orb, const void* orbitals,
+                               int32_t n_ip, int32_t* ip_out, double* residual_out, uint32_t flags,
+                               void* hip_stream) {
+  t_create_err.clear();
+  if (!grid || !kmesh || !orbitals || !ip_out) {
+    t_create_err = "null argument";
+    return ISDF_E_INVALID;
+  }
+  if (const char* m = check_sizes(grid, kmesh, n_orb, n_ip)) {
+    t_create_err = m;
+    return ISDF_E_INVALID;
+  }
+  const long long ng = (long long)grid[0] * grid[1] * grid[2];
+  const long long nrows = (long long)kmesh[0] * kmesh[1] * kmesh[2] * n_orb;
+  if (n_ip > ng) {
+    t_create_err = "n_ip exceeds the number of grid points";
+    return ISDF_E_INVALID;
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  try {
+    if (flags & ISDF_INPUT_DEVICE) {
+      hipPointerAttribute_t at;
+      if (hipPointerGetAttributes(&at, orbitals) != hipSuccess || at.type != hipMemoryTypeDevice) {
+        (void)hipGetLastError();
+        throw Fail{ISDF_E_INVALID, "ISDF_INPUT_DEVICE orbitals are not device memory"};
+      }
+    }
+    const SelPlan pl = sel_plan(nrows, ng);
+    DevBuf phi, part, lf, d, bv, bi, piv, dmax;
+    const cplx* ph = (const cplx*)orbitals;
+    if (!(flags & ISDF_INPUT_DEVICE)) {
+      phi.alloc(sizeof(cplx) * nrows * ng);
+      HIPCHK(hipMemcpyAsync(phi.p, orbitals, sizeof(cplx) * nrows * ng, hipMemcpyHostToDevice, s));
+      ph = phi.as<cplx>();
+    }
+    part.alloc(sizeof(cplx) * pl.nslice * ng);
+    lf.alloc(sizeof(double) * n_ip * ng);
+    d.alloc(sizeof(double) * ng);
+    bv.alloc(sizeof(double) * pl.xblocks);
+    bi.alloc(sizeof(long long) * pl.xblocks);
+    piv.alloc(sizeof(int) * n_ip);
+    dmax.alloc(sizeof(double) * n_ip);
+    HIPCHK(sel_start_launch(pl, ph, nrows, ng, part.as<cplx>(), d.as<double>(), bv.as<double>(),
+                            bi.as<long long>(), piv.as<int>(), dmax.as<double>(), s));
+    for (int i = 0; i < n_ip; ++i)
+      HIPCHK(sel_step_launch(pl, ph, nrows, ng, part.as<cplx>(), lf.as<double>(), d.as<double>(), bv.as<double>(),
+                             bi.as<long long>(), piv.as<int>(), dmax.as<double>(), i, i + 1 < n_ip, s));
+    std::vector<int32_t> ph_piv(n_ip);
+    std::vector<double> ph_dmax(n_ip);
+    HIPCHK(hipMemcpyAsync(ph_piv.data(), piv.p, sizeof(int) * n_ip, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(ph_dmax.data(), dmax.p, sizeof(double) * n_ip, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    // a step whose largest residual is not positive (the products span fewer
+    // columns, or the orbitals hold non-finite values) ends the selection
+    int good = 0;
+    while (good < n_ip && ph_dmax[good] > 0.0 && ph_piv[good] >= 0 && ph_piv[good] < ng) ++good;
+    for (int i = 0; i < n_ip; ++i) {
+      ip_out[i] = i < good ? ph_piv[i] : -1;
+      if (residual_out) residual_out[i] = i < good ? ph_dmax[i] : 0.0;
+    }
+    if (good < n_ip)
+      throw Fail{ISDF_E_NUMERIC, "the pair products span only " + std::to_string(good) +
+                                     " grid columns (largest residual not positive at step " +
+                                     std::to_string(good) + ")"};
+  } catch (const Fail& e) {
+    t_create_err = e.msg;
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    t_create_err = "host allocation failed";
+    return ISDF_E_NOMEM;
+  } catch (...) {
+    t_create_err = "unexpected exception";
+    return ISDF_E_INVALID;
+  }
   return ISDF_OK;
 }
 

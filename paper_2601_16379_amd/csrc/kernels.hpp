@@ -242,3 +242,24 @@ hipError_t copy_cols_launch(const cplx* in, cplx* out, int nk, int norb, int nf,
 hipError_t zero_launch(cplx* x, long long n, hipStream_t s);
 // count non-finite entries (real or imaginary) of n complex values into *flag
 hipError_t nonfinite_launch(const cplx* x, long long n, int* flag, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// interpolation-point selection (pivoted Cholesky of the pair products)
+// ---------------------------------------------------------------------------
+// Launch shape of one step: xblocks workgroups of 256 grid points, each of
+// the nslice row slices rows_per rows long.
+struct SelPlan {
+  int xblocks = 0;
+  int nslice = 0;
+  long long rows_per = 0;
+};
+SelPlan sel_plan(long long nrows, long long ng);
+// phi [nrows][ng]; part [nslice][ng]; d [ng]; bv, bi [xblocks]; piv, dmax
+// [n_ip].  Start: d = rho^2, piv[0] / dmax[0] = first pivot and its residual.
+hipError_t sel_start_launch(const SelPlan& pl, const cplx* phi, long long nrows, long long ng, cplx* part, double* d,
+                            double* bv, long long* bi, int* piv, double* dmax, hipStream_t s);
+// Step `step`: column lf[step][ng] and residual update; with pick_next the
+// pivot of step + 1 into piv / dmax.
+hipError_t sel_step_launch(const SelPlan& pl, const cplx* phi, long long nrows, long long ng, cplx* part, double* lf,
+                           double* d, double* bv, long long* bi, int* piv, double* dmax, int step, bool pick_next,
+                           hipStream_t s);

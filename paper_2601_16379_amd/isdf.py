@@ -22,6 +22,7 @@ ISDF_FP64, ISDF_MIXED_FP32, ISDF_MIXED_BF16X3 = 0, 1, 2
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 ISDF_INPUT_DEVICE = 0x1
 ISDF_NO_PIVOT = 0x2
+ISDF_ZETA_ROUTE = 0x4
 ISDF_FRAG_DEVICE = 0x1
 REQ_STATES = {0: "QUEUED", 1: "RUNNING", 2: "DONE", 3: "FAILED", 4: "CANCELLED"}
 
@@ -30,8 +31,8 @@ EXPORTS = ["isdf_create", "isdf_fit", "isdf_coulomb_kernel", "isdf_get_metric",
            "isdf_serve_start", "isdf_submit", "isdf_submit_n", "isdf_poll", "isdf_cancel",
            "isdf_serve_stop", "isdf_stats", "isdf_stage_ms", "isdf_stage_total", "isdf_stage_reset", "isdf_plan_bytes", "isdf_storage_model_bytes",
            "isdf_graph_create", "isdf_graph_launch", "isdf_graph_destroy", "isdf_autotune", "isdf_set_tiling",
-           "isdf_save", "isdf_load", "isdf_fragment_eri_static", "isdf_destroy", "isdf_last_error",
-           "isdf_version"]
+           "isdf_save", "isdf_load", "isdf_fragment_eri_static", "isdf_select_points", "isdf_destroy",
+           "isdf_last_error", "isdf_version"]
 
 
 class IsdfError(RuntimeError):
@@ -81,6 +82,7 @@ def load_library(path=LIB_PATH):
         "isdf_get_eta_tilde": (I32, [P, I32, P]),
         "isdf_fragment_eri": (I32, [P, I32, I32, P, P, P, U32]),
         "isdf_fragment_eri_static": (I32, [P, I32, I32, P, P, P, U32]),
+        "isdf_select_points": (I32, [P, P, I32, P, I32, P, P, U32, P]),
         "isdf_serve_start": (I32, [P, I32, I32, I64]),
         "isdf_submit": (I32, [P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
         "isdf_submit_n": (I32, [P, I32, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
@@ -150,12 +152,34 @@ def isdf_version():
     return load_library().isdf_version().decode()
 
 
+def select_points(grid, kmesh, orbitals, n_ip, stream=None):
+    """``isdf_select_points``: the first n_ip pivots of the pivoted Cholesky
+    of the pair products of ``orbitals`` ([N_k, n_orb, N_g] c128, numpy or
+    torch, host or device).  Returns (ip_index int32 [n_ip] in selection
+    order, residual float64 [n_ip]: d(p) of each pivot when chosen)."""
+    lib = load_library()
+    g = np.ascontiguousarray(np.asarray(grid, dtype=np.int32))
+    k = np.ascontiguousarray(np.asarray(kmesh, dtype=np.int32))
+    shape = tuple(orbitals.shape)
+    if len(shape) != 3 or shape[0] != int(np.prod(k)) or shape[2] != int(np.prod(g)):
+        raise ValueError("orbitals must be [N_k, n_orb, N_g]")
+    optr, odev = _ptr(orbitals)
+    ip = np.zeros(int(n_ip), dtype=np.int32)
+    res = np.zeros(int(n_ip), dtype=np.float64)
+    st_ = current_stream() if stream is None else stream
+    st = lib.isdf_select_points(g.ctypes.data, k.ctypes.data, int(shape[1]), optr, int(n_ip), ip.ctypes.data,
+                                res.ctypes.data, ISDF_INPUT_DEVICE if odev else 0, st_)
+    if st != ISDF_OK:
+        raise IsdfError(st, "isdf_select_points: " + lib.isdf_last_error(None).decode())
+    return ip, res
+
+
 class Isdf:
     """One library context: ``isdf_create`` at construction, the other calls
     as methods with the C names (``fit``, ``coulomb_kernel``, ...)."""
 
     def __init__(self, lattice, grid, kmesh, orbitals, ip_index, no_pivot=False, stream=None, q_batch=0,
-                 _handle=None):
+                 zeta_route=False, _handle=None):
         self.lib = load_library()
         if _handle is not None:             # a context restored by isdf_load
             self.h, (self.grid, self.kmesh, self.n_orb, self.n_ip, self.stream) = _handle
@@ -179,7 +203,7 @@ class Isdf:
         self.n_orb = int(shape[1])
         self.n_ip = int(ip_index.shape[0])
         flags = (ISDF_INPUT_DEVICE if odev else 0) | (ISDF_NO_PIVOT if no_pivot else 0) \
-            | ((int(q_batch) & 0xFFFF) << 16)
+            | (ISDF_ZETA_ROUTE if zeta_route else 0) | ((int(q_batch) & 0xFFFF) << 16)
         self.stream = current_stream() if stream is None else stream
         h = ctypes.c_void_p()
         st = self.lib.isdf_create(ctypes.byref(h), lat.ctypes.data, self.grid.ctypes.data,

@@ -100,3 +100,27 @@ def test_calls_on_null_context_fail_cleanly():
     assert lib.isdf_graph_destroy(None) == -1
     assert lib.isdf_autotune(None, 2, 1, nf, ptrs, ptrs, None) == -1
     assert lib.isdf_set_tiling(None, 12, 2) == -1
+
+
+def test_select_points_rejects_invalid_arguments_without_device():
+    lib = pkg.load_library()
+    grid = np.array([8, 8, 8], np.int32)
+    km = np.array([1, 1, 1], np.int32)
+    orb = np.zeros((1, 2, 512), np.complex128)
+    ip = np.zeros(4, np.int32)
+    assert lib.isdf_select_points(None, km.ctypes.data, 2, orb.ctypes.data, 4, ip.ctypes.data, None, 0,
+                                  None) == -1
+    assert lib.isdf_select_points(grid.ctypes.data, km.ctypes.data, 2, orb.ctypes.data, 4, None, None, 0,
+                                  None) == -1
+    assert b"null" in lib.isdf_last_error(None)
+    # more points than grid points; bad grid; bad orbital count
+    assert lib.isdf_select_points(grid.ctypes.data, km.ctypes.data, 2, orb.ctypes.data, 513,
+                                  ip.ctypes.data, None, 0, None) == -1
+    assert b"exceeds" in lib.isdf_last_error(None)
+    bad = np.array([8, 8, 13], np.int32)
+    assert lib.isdf_select_points(bad.ctypes.data, km.ctypes.data, 2, orb.ctypes.data, 4, ip.ctypes.data,
+                                  None, 0, None) == -1
+    assert lib.isdf_select_points(grid.ctypes.data, km.ctypes.data, 0, orb.ctypes.data, 4, ip.ctypes.data,
+                                  None, 0, None) == -1
+    with pytest.raises(ValueError):
+        pkg.select_points([8, 8, 8], [1, 1, 1], np.zeros((1, 2, 500), np.complex128), 4)

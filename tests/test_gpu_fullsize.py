@@ -207,6 +207,29 @@ def test_large_cell_metric_and_ivs(bigcell):
 
 
 @pytest.mark.timeout(900)
+def test_large_cell_select_points(bigcell):
+    """All N_IP pivots of the pivoted Cholesky of the pair products at the
+    cell's full size; the first three against the oracle (one orbital pass
+    each), every pivot distinct, residuals non-increasing to rounding."""
+    import time
+    import paper_2601_16379_amd as pkg
+    from oracle import ipselect as ips
+    b = bigcell
+    cfg = b.d.cfg
+    t0 = time.time()
+    ip, res = pkg.select_points(cfg.grid, cfg.kmesh, b.d.orbitals, cfg.n_ip)
+    print("%s: %d points selected on the GPU in %.1f s (residual %.3e -> %.3e)"
+          % (cfg.name, cfg.n_ip, time.time() - t0, res[0], res[-1]), flush=True)
+    assert len(set(ip.tolist())) == cfg.n_ip
+    assert np.all(res[1:] <= res[:-1] * (1 + 1e-12))
+    piv, dmax, _, _, gap = ips.pivoted_cholesky_points(b.d.orbitals, 3, with_gaps=True)
+    print("%s: oracle pivots %s, gaps %s" % (cfg.name, piv.tolist(), (gap / dmax[0]).tolist()), flush=True)
+    assert np.all(gap > 1e-9 * dmax[0])
+    assert np.array_equal(ip[:3], piv)
+    assert np.max(np.abs(res[:3] - dmax)) < 1e-10 * dmax[0]
+
+
+@pytest.mark.timeout(900)
 def test_large_cell_kernel_through_v(bigcell):
     b = bigcell
     name = b.d.cfg.name
