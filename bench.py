@@ -63,6 +63,8 @@ def parse():
                     help="fragments per serving batch (0: all of a step in one batch)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device copy first (reference for HBM byte counters)")
+    ap.add_argument("--no-peaks", action="store_true",
+                    help="skip the measured HBM / GEMM peaks (timed after the steps)")
     return ap.parse_args()
 
 
@@ -319,6 +321,42 @@ def stage_rows(stage_tot, cfg, nfs, prec, per):
             row["frac"] = rate / w[3]
         rows[s] = row
     return rows
+
+
+def measured_peaks(torch):
+    """Achievable rates on this GPU, timed with events: HBM as a device copy
+    of 4 GiB (read + write bytes / time) and dense GEMMs of the vendor BLAS
+    (torch.matmul) per dtype, best of three after a warm-up."""
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        best = 1e30
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            b.synchronize()
+            best = min(best, a.elapsed_time(b) / 1e3)
+        return best
+    out = {}
+    src = torch.empty(1 << 29, dtype=torch.float64, device="cuda")   # 4 GiB
+    src.fill_(1.0)
+    dst = torch.empty_like(src)
+    t = timed(lambda: dst.copy_(src))
+    out["hbm_copy_GBps"] = 2 * src.numel() * 8 / t / 1e9
+    del src, dst
+    for name, dt, n in (("fp64", torch.float64, 8192), ("fp32", torch.float32, 8192),
+                        ("bf16", torch.bfloat16, 16384)):
+        a = torch.randn(n, n, dtype=torch.float32, device="cuda").to(dt)
+        b = torch.randn(n, n, dtype=torch.float32, device="cuda").to(dt)
+        t = timed(lambda: torch.matmul(a, b))
+        out["gemm_%s_TFLOPs" % name] = 2.0 * n ** 3 / t / 1e12
+        del a, b
+    torch.cuda.empty_cache()
+    out["how"] = ("device copy of 4 GiB (2 x 4 GiB moved); torch.matmul of square n x n matrices "
+                  "(n = 8192 fp64/fp32, 16384 bf16), best of 3 timed with events")
+    return out
 
 
 def collect_stages(ctx, names):
@@ -690,6 +728,14 @@ def main():
     else:
         res = run_whole(args, cfg, pkg, inp, np, torch)
     value, wall, erisum, lat_ms, roof, stages, cpu, extra, cfgd, nreq = res
+    if not args.no_peaks:
+        pk = measured_peaks(torch)
+        extra["measured_peaks"] = pk
+        if roof and roof["unit"] == "TFLOP/s":
+            ref = pk["gemm_bf16_TFLOPs"] if args.prec == "bf16x3" else pk["gemm_%s_TFLOPs" % args.prec]
+            roof["frac_of_measured_peak"] = roof["achieved"] / ref
+        elif roof:
+            roof["frac_of_measured_peak"] = roof["achieved"] / pk["hbm_copy_GBps"]
     steps = args.steps if not (cfg.n_k >= STREAM_MIN_NK and args.arrivals > 0) else nreq
     out = {
         "metric": "fragment ERIs/s + p50/p99 latency, mixed vs FP64 at <=1e-6 Eh max error",
