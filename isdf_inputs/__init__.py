@@ -45,6 +45,7 @@ STREAM_IPS = 2
 STREAM_FRAG_SIZES = 3
 STREAM_FRAG_COEFFS = 4
 STREAM_ARRIVALS = 5
+STREAM_DENSITY = 6
 
 
 @dataclasses.dataclass(frozen=True)
@@ -310,6 +311,24 @@ def make_fragment(cfg: Config, f: int, n_f: int) -> np.ndarray:
         q, r = np.linalg.qr(zr)
         q = (q * np.sign(np.diag(r))[None, :]).astype(np.complex128)
     return q.reshape(cfg.n_k, cfg.n_orb, n_f)
+
+
+def make_density(cfg: Config, n_occ: Optional[int] = None, seed: int = 0) -> np.ndarray:
+    """Closed-shell k-point density matrices ``P[k, mu, nu]`` (complex128
+    ``[N_k, N_orb, N_orb]``): per k, 2 U U^H with U the first n_occ columns of
+    a Haar-random unitary (QR of a complex Gaussian with the phases of R's
+    diagonal removed); n_occ = N_orb // 2 (at least 1) unless given.
+    Hermitian, positive semidefinite, trace 2 n_occ per k."""
+    n = cfg.n_orb
+    n_occ = max(1, n // 2) if n_occ is None else int(n_occ)
+    rng = _seed(cfg, STREAM_DENSITY, seed)
+    out = np.empty((cfg.n_k, n, n), dtype=np.complex128)
+    for k in range(cfg.n_k):
+        z = (rng.standard_normal((n, n_occ)) + 1j * rng.standard_normal((n, n_occ))) * np.sqrt(0.5)
+        q, r = np.linalg.qr(z)
+        q = q * (np.diag(r) / np.abs(np.diag(r)))[None, :]
+        out[k] = 2.0 * (q @ q.conj().T)
+    return out
 
 
 def make_fragments(cfg: Config, n_frag: Optional[int] = None):

@@ -18,7 +18,9 @@ eye.  Modules:
 * ``supercell`` -- exact ERIs and Gamma-point ISDF on the Born-von Karman
   supercell (the plain definitions every k-point result must reproduce);
 * ``kpoint``    -- the k-point fit, the Coulomb kernel and the fragment ERIs;
-* ``ipselect``  -- interpolation points by pivoted Cholesky of the pair products.
+* ``ipselect``  -- interpolation points by pivoted Cholesky of the pair products;
+* ``hf``        -- k-point Hartree-Fock Coulomb and exchange matrices from W^q
+  (eq. (10)).
 
 Every function is pinned by ``tests/test_oracle_pins.py``; none is
 "parity unpinned" except the size of the ISDF approximation error itself on

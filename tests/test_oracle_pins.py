@@ -538,3 +538,91 @@ def test_selection_invariant_under_orbital_rotation_within_k():
     a = ips.pivoted_cholesky_points(d.orbitals, 40)[0]
     b = ips.pivoted_cholesky_points(rot, 40)[0]
     assert np.array_equal(a, b)
+
+
+# --------------------------------------------------------------------------
+# k-point Hartree-Fock Coulomb and exchange matrices (eq. (10))
+# --------------------------------------------------------------------------
+from oracle import hf
+
+
+def _supercell_jk(d, dm):
+    """J and K of gamma on the supercell from the exact FFT-Poisson ERIs of
+    every supercell orbital N_k^{-1/2} phi^k_mu, contracted with the
+    block-diagonal density matrix: J_ab = sum_cd (ab|dc) g_cd,
+    K_ab = sum_cd (ac|db) g_cd.  Returns full supercell matrices."""
+    cfg = d.cfg
+    n = cfg.n_k * cfg.n_orb
+    ident = np.eye(n, dtype=np.complex128).reshape(cfg.n_k, cfg.n_orb, n)
+    phi_s = sc.supercell_orbitals(d.orbitals, cfg.grid, cfg.kmesh)
+    psi = sc.fragment_orbitals(phi_s, ident)
+    eri = sc.exact_eri(psi, d.lattice, cfg.grid, cfg.kmesh)
+    g = np.zeros((n, n), dtype=np.complex128)
+    for k in range(cfg.n_k):
+        s = slice(k * cfg.n_orb, (k + 1) * cfg.n_orb)
+        g[s, s] = dm[k]
+    j = np.einsum("abdc,cd->ab", eri, g)
+    kk = np.einsum("acdb,cd->ab", eri, g)
+    return j, kk
+
+
+@pytest.mark.parametrize("name", ["t_tiny_k2", "t_k10_line"])
+def test_jk_equal_contraction_of_eq9_eris(name):
+    """Eq. (10) as a sum over q (and J as the q = 0 term) against the plain
+    element-by-element contraction of the crystalline ERIs of eq. (9); the
+    10-point mesh axis tells q from -q."""
+    d = _case(name)
+    cfg = d.cfg
+    x, pi, eta, w = ko.fit_and_kernel(d.orbitals, d.ip_index, d.lattice, cfg.grid, cfg.kmesh)
+    dm = inp.make_density(cfg)
+    j_ref, k_ref = hf.jk_from_eri(x, w, dm, cfg.kmesh)
+    assert _rel(hf.exchange(x, w, dm, cfg.kmesh), k_ref) < 1e-13
+    assert _rel(hf.coulomb(x, w, dm), j_ref) < 1e-13
+    ks = [cfg.n_k - 1, 1]
+    assert _rel(hf.exchange_at(x, w, dm, cfg.kmesh, ks), k_ref[ks]) < 1e-13
+
+
+@pytest.mark.parametrize("name", ["t_tiny_k2", "t_k10_line"])
+def test_jk_with_full_grid_ips_equal_exact_supercell_jk(name):
+    """With every grid point an interpolation point the fit is exact, so J
+    and K from W^q equal the FFT-Poisson Coulomb and exchange matrices of
+    the supercell density matrix; the supercell matrices have no blocks
+    between different k (crystal momentum)."""
+    cfg = inp.get_config(name)
+    d = _case(name, n_ip=cfg.n_g)
+    x, pi, eta, w = ko.fit_and_kernel(d.orbitals, d.ip_index, d.lattice, cfg.grid, cfg.kmesh)
+    dm = inp.make_density(cfg)
+    j_s, k_s = _supercell_jk(d, dm)
+    kk = hf.exchange(x, w, dm, cfg.kmesh)
+    jj = hf.coulomb(x, w, dm)
+    no = cfg.n_orb
+    for k in range(cfg.n_k):
+        s = slice(k * no, (k + 1) * no)
+        assert _rel(kk[k], k_s[s, s]) < 1e-11
+        assert _rel(jj[k], j_s[s, s]) < 1e-11
+        for k2 in range(cfg.n_k):
+            if k2 != k:
+                s2 = slice(k2 * no, (k2 + 1) * no)
+                assert np.max(np.abs(k_s[s, s2])) < 1e-13 * np.max(np.abs(k_s))
+                assert np.max(np.abs(j_s[s, s2])) < 1e-13 * np.max(np.abs(j_s))
+
+
+def test_jk_hermitian_and_exchange_psd():
+    """For Hermitian PSD P^k: J^k and K^k are Hermitian, K^k is PSD (the
+    exchange kernel gamma(x, y) v(x - y) is a product of PSD kernels), and
+    the Coulomb and exchange energies sum_k tr(P^k J^k), sum_k tr(P^k K^k)
+    are real and positive."""
+    d = _case("t_small_k2")
+    cfg = d.cfg
+    x, pi, eta, w = ko.fit_and_kernel(d.orbitals, d.ip_index, d.lattice, cfg.grid, cfg.kmesh)
+    dm = inp.make_density(cfg)
+    kk = hf.exchange(x, w, dm, cfg.kmesh)
+    jj = hf.coulomb(x, w, dm)
+    for k in range(cfg.n_k):
+        assert _rel(kk[k], kk[k].conj().T) < 1e-13
+        assert _rel(jj[k], jj[k].conj().T) < 1e-13
+        assert np.linalg.eigvalsh(kk[k]).min() > -1e-12 * np.abs(kk[k]).max()
+    ej = np.einsum("kab,kba->", dm, jj)
+    ek = np.einsum("kab,kba->", dm, kk)
+    assert abs(ej.imag) < 1e-12 * abs(ej) and ej.real > 0
+    assert abs(ek.imag) < 1e-12 * abs(ek) and ek.real > 0
