@@ -402,6 +402,33 @@ int64_t isdf_storage_model_bytes(int64_t n_k, int64_t n_ip, int64_t n_ao);
 isdf_status isdf_save(isdf_ctx ctx, const char* path);
 isdf_status isdf_load(isdf_ctx* out, const char* path, void* hip_stream);
 
+/*
+ * k-point Hartree-Fock Coulomb and exchange matrices from the resident W^q
+ * (eq. (10) and the q = 0 term of eq. (9)), for density matrices P^k:
+ *   rho^k_{IJ} = sum_{la sg} X^k_{I la} P^k_{la sg} conj(X^k_{J sg})
+ *   K^k_{mu nu} = N_k^-1 sum_IJ conj(X^k_{I mu}) X^k_{J nu} sum_q W^q_{IJ} rho^{k+q}_{IJ}
+ *   J^k_{mu nu} = N_k^-1 sum_I conj(X^k_{I mu}) X^k_{I nu} sum_J W^0_{IJ} n_J,
+ *                 n_J = sum_k rho^k_{JJ}
+ * i.e. J_{mu nu} = sum (mu nu|sg la) P_{la sg} and K_{mu nu} = sum
+ * (mu la|sg nu) P_{la sg} over the supercell orbitals N_k^{-1/2} phi^k, for
+ * the density matrix gamma(x, y) = N_k^-1 sum_k phi^k(x) P^k phi^k(y)^H.  K
+ * is returned without the minus sign with which eq. (10) enters the Fock
+ * matrix; q is counted as in W^q of this library.  The q sum is a
+ * convolution over the k mesh, done in place on rho (FP64 k transforms in
+ * LDS); the other steps are FP64 MFMA products.  FP64 throughout.
+ *   dm     c128 [N_k][n_orb][n_orb], row mu column nu.
+ *   j_out, k_out  c128 [N_k][n_orb][n_orb], either may be NULL (not computed).
+ *   flags  ISDF_HF_DEVICE: dm, j_out, k_out are device pointers (else host).
+ * Device workspace N_k N_IP^2 + N_k n_orb N_IP complex numbers (17.3 + 0.9 GB
+ * at N_k = 1000, N_IP = 1040), freed on return; the idle workspace of
+ * isdf_fragment_eri is handed back first when the device is full.
+ * Synchronous.  Errors: ISDF_E_STATE before isdf_coulomb_kernel,
+ * ISDF_E_INVALID for null or (with ISDF_HF_DEVICE) non-device pointers and
+ * for K on meshes of more than 2048 k points, ISDF_E_NOMEM, ISDF_E_DEVICE.
+ */
+#define ISDF_HF_DEVICE 0x1u
+isdf_status isdf_hf_jk(isdf_ctx ctx, const void* dm, void* j_out, void* k_out, uint32_t flags);
+
 isdf_status isdf_destroy(isdf_ctx ctx);
 /* Message of the last failed call on ctx; with ctx == NULL, the message of the
  * last failed isdf_create or isdf_load on the calling thread ("null context"

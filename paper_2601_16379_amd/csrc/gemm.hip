@@ -281,9 +281,9 @@ hipError_t launch_p(int flags, const GemmDesc* descs, int ndesc, long long total
     hipLaunchKernelGGL((zgemm_kernel<P, (F & 1) != 0, (F & 2) != 0, (F & 4) != 0, (F & 8) != 0>), \
                        g, b, 0, s, descs, ndesc, total);                                           \
     break;
-    // layouts used by the path: A_KM|B_KN, B_CONJ, A_KM|B_KN|B_CONJ, and B_KN
-    // (the zeta route's Pi^+ eta)
-    CASE(2) CASE(3) CASE(8) CASE(11)
+    // layouts used by the path: A_KM|B_KN, B_CONJ, A_KM|B_KN|B_CONJ, B_KN (the
+    // zeta route's Pi^+ eta) and B_KN|B_CONJ (P^k X^{k H} of the exchange)
+    CASE(2) CASE(3) CASE(8) CASE(10) CASE(11)
     default: return hipErrorInvalidValue;
 #undef CASE
   }

@@ -2432,6 +2432,153 @@ isdf_status isdf_destroy(isdf_ctx ctx) {
   return ISDF_OK;
 }
 
+// Device buffer for a synchronous call; when the device is full, the idle
+// workspace of synchronous fragment calls is handed back and the allocation
+// tried once more.
+static void alloc_reclaim(isdf_ctx c, DevBuf& b, size_t bytes) {
+  try {
+    b.alloc(bytes);
+  } catch (const Fail& f) {
+    if (f.st != ISDF_E_NOMEM) throw;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->sync_ws.mem.release();
+    b.alloc(bytes);
+  }
+}
+
+isdf_status isdf_hf_jk(isdf_ctx ctx, const void* dm, void* j_out, void* k_out, uint32_t flags) {
+  return guarded(ctx, [&] {
+    if (!dm || (!j_out && !k_out)) throw Fail{ISDF_E_INVALID, "null density matrix or no output"};
+    if (!ctx->kernel_ready) throw Fail{ISDF_E_STATE, "isdf_coulomb_kernel must run before isdf_hf_jk"};
+    if (k_out && ctx->nk > 2048)
+      throw Fail{ISDF_E_INVALID, "the exchange convolution holds two k columns in LDS: at most 2048 k points"};
+    isdf_ctx c = ctx;
+    hipStream_t s = c->stream;
+    const int nk = c->nk, norb = c->norb, nip = c->nip;
+    const bool dev = (flags & ISDF_HF_DEVICE) != 0;
+    if (dev) {
+      for (const void* ptr : {dm, (const void*)j_out, (const void*)k_out}) {
+        if (!ptr) continue;
+        hipPointerAttribute_t at;
+        if (hipPointerGetAttributes(&at, ptr) != hipSuccess || at.type != hipMemoryTypeDevice) {
+          (void)hipGetLastError();
+          throw Fail{ISDF_E_INVALID, "ISDF_HF_DEVICE buffers must be device memory"};
+        }
+      }
+    }
+    const size_t mb = (size_t)nk * norb * norb * sizeof(cplx);
+    const long long nn = (long long)nip * nip, on = (long long)norb * nip, oo = (long long)norb * norb;
+    DevBuf dmd, jd, kd, rho, zb, nv, vv;
+    const cplx* P = (const cplx*)dm;
+    cplx* J = (cplx*)j_out;
+    cplx* K = (cplx*)k_out;
+    if (!dev) {
+      alloc_reclaim(c, dmd, mb);
+      HIPCHK(hipMemcpyAsync(dmd.p, dm, mb, hipMemcpyHostToDevice, s));
+      P = dmd.as<cplx>();
+      if (J) { alloc_reclaim(c, jd, mb); J = jd.as<cplx>(); }
+      if (K) { alloc_reclaim(c, kd, mb); K = kd.as<cplx>(); }
+    }
+    alloc_reclaim(c, rho, sizeof(cplx) * (size_t)nk * nn);
+    alloc_reclaim(c, zb, sizeof(cplx) * (size_t)nk * on);
+    c->arena.reset(s);
+    c->arena.reserve(((size_t)1 << 20) + (size_t)nk * sizeof(int));
+    const cplx* xt = c->xt.as<cplx>();
+    // rho^k_{IJ} = sum_{la sg} X^k_{I la} P^k_{la sg} conj(X^k_{J sg}) as
+    // Z^k = P^k X^{k H} ([la][J]) and rho^k = X^k Z^k, FP64 MFMA
+    c->timer.begin("hf_rho", s);
+    {
+      std::vector<GemmDesc> d(1);
+      d[0] = mkdesc(P, norb, xt, nip, zb.as<cplx>(), nip, norb, nip, norb);
+      d[0].batch = nk;
+      d[0].sA_bat = oo;
+      d[0].sB_bat = d[0].sC_bat = on;
+      run_gemm(c->arena, 0, GEMM_B_KN | GEMM_B_CONJ, d, s);
+    }
+    {
+      std::vector<GemmDesc> d(1);
+      d[0] = mkdesc(xt, nip, zb.as<cplx>(), nip, rho.as<cplx>(), nip, nip, nip, norb);
+      d[0].batch = nk;
+      d[0].sA_bat = d[0].sB_bat = on;
+      d[0].sC_bat = nn;
+      run_gemm(c->arena, 0, GEMM_A_KM | GEMM_B_KN, d, s);
+    }
+    c->timer.end("hf_rho", s);
+    if (J) {
+      // J^k_{mu nu} = N_k^-1 sum_I conj(X^k_{I mu}) X^k_{I nu} (W^0 n)_I,
+      // n_J = sum_k rho^k_{JJ} (before the exchange convolution reuses rho)
+      c->timer.begin("hf_j", s);
+      alloc_reclaim(c, nv, sizeof(cplx) * nip);
+      alloc_reclaim(c, vv, sizeof(cplx) * nip);
+      HIPCHK(hf_diag_sum_launch(rho.as<cplx>(), nk, nip, nv.as<cplx>(), s));
+      bool cj;
+      const int h0 = class_slot(c, 0, &cj);
+      HIPCHK(hf_matvec_launch(c->w.as<cplx>() + (long long)h0 * nn, cj ? 1 : 0, nv.as<cplx>(), nip, 1.0 / nk,
+                              vv.as<cplx>(), s));
+      HIPCHK(hf_scale_launch(xt, vv.as<cplx>(), (long long)nk * norb, nip, zb.as<cplx>(), s));
+      std::vector<NtDesc> d(1);
+      d[0] = mknt(xt, nip, zb.p, nip, J, norb, norb, norb, nip);
+      d[0].batch = nk;
+      d[0].sA_bat = d[0].sB_bat = on;
+      d[0].sC_bat = oo;
+      run_nt(c->arena, 0, 1, d, s);
+      c->timer.end("hf_j", s);
+    }
+    if (K) {
+      // M^k = N_k^-1 sum_q W^q o rho^{k+q} by the convolution over k (eq. (10)),
+      // in place, then K^k = X^{k H} M^k X^k as two NT products
+      c->timer.begin("hf_kconv", s);
+      std::vector<int> wsel(nk);
+      for (int q = 0; q < nk; ++q) {
+        bool cq;
+        const int h = class_slot(c, q, &cq);
+        wsel[q] = (h << 1) | (cq ? 1 : 0);
+      }
+      const int* wsel_d = c->arena.put(wsel.data(), wsel.size(), s);
+      XconvArgs a;
+      memset(&a, 0, sizeof(a));
+      a.rho = rho.as<cplx>();
+      a.w = c->w.as<cplx>();
+      a.wsel = wsel_d;
+      a.n_elem = nn;
+      a.m1 = c->m[0];
+      a.m2 = c->m[1];
+      a.m3 = c->m[2];
+      a.scale = 1.0 / ((double)nk * nk);
+      HIPCHK(xconv_launch(a, s));
+      c->timer.end("hf_kconv", s);
+      c->timer.begin("hf_k", s);
+      {
+        // Zt^k[nu][I] = sum_J X^k_{J nu} M^k_{IJ}
+        std::vector<NtDesc> d(1);
+        d[0] = mknt(xt, nip, rho.p, nip, zb.p, nip, norb, nip, nip);
+        d[0].batch = nk;
+        d[0].sA_bat = on;
+        d[0].sB_bat = nn;
+        d[0].sC_bat = on;
+        run_nt(c->arena, 0, 0, d, s);
+      }
+      {
+        // K^k[mu][nu] = sum_I conj(X^k_{I mu}) Zt^k[nu][I]
+        std::vector<NtDesc> d(1);
+        d[0] = mknt(xt, nip, zb.p, nip, K, norb, norb, norb, nip);
+        d[0].batch = nk;
+        d[0].sA_bat = d[0].sB_bat = on;
+        d[0].sC_bat = oo;
+        run_nt(c->arena, 0, 1, d, s);
+      }
+      c->timer.end("hf_k", s);
+    }
+    if (!dev) {
+      if (j_out) HIPCHK(hipMemcpyAsync(j_out, J, mb, hipMemcpyDeviceToHost, s));
+      if (k_out) HIPCHK(hipMemcpyAsync(k_out, K, mb, hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->timer.collect(&c->totals);
+  });
+}
+
 const char* isdf_last_error(isdf_ctx ctx) {
   if (!ctx) return t_create_err.empty() ? "null context" : t_create_err.c_str();
   return ctx->err.c_str();

@@ -129,6 +129,19 @@ struct KconvArgs {
 };
 hipError_t kconv_launch(const KconvArgs& a, hipStream_t s);
 
+// Exchange convolution of eq. (10), in place over rho [N_k][n_elem]:
+//   rho[k][e] <- scale * N_k * sum_q W^q[e] rho[k+q][e]   (k + q on the mesh),
+// W^q[e] = w[wsel[q] >> 1][e], conjugated when wsel[q] & 1 (device table).
+struct XconvArgs {
+  cplx* rho;
+  const cplx* w;
+  const int* wsel;
+  long long n_elem;
+  int m1, m2, m3;
+  double scale;
+};
+hipError_t xconv_launch(const XconvArgs& a, hipStream_t s);
+
 // Fragment pair transform (eq. (20)):
 //   R[Q][pair_off_f + p*nf + q][I] =
 //     scale * sum_R exp(-2 pi i jQ.jR/m) conj(psi[R][col_f + p][I]) psi[R][col_f + q][I]
@@ -263,3 +276,13 @@ hipError_t sel_start_launch(const SelPlan& pl, const cplx* phi, long long nrows,
 hipError_t sel_step_launch(const SelPlan& pl, const cplx* phi, long long nrows, long long ng, cplx* part, double* lf,
                            double* d, double* bv, long long* bi, int* piv, double* dmax, int step, bool pick_next,
                            hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// k-point Hartree-Fock Coulomb matrix helpers
+// ---------------------------------------------------------------------------
+// n[J] = sum_k rho[k][J][J]   (rho [nk][nip][nip])
+hipError_t hf_diag_sum_launch(const cplx* rho, int nk, int nip, cplx* n, hipStream_t s);
+// v[I] = scale * sum_J W[I][J] n[J], W conjugated when conj
+hipError_t hf_matvec_launch(const cplx* w, int conj, const cplx* n, int nip, double scale, cplx* v, hipStream_t s);
+// out[r][I] = v[I] xt[r][I] for rows r < rows
+hipError_t hf_scale_launch(const cplx* xt, const cplx* v, long long rows, int nip, cplx* out, hipStream_t s);

@@ -175,6 +175,50 @@ __global__ __launch_bounds__(256) void kconv_kernel(KconvArgs a, int etile) {
   }
 }
 
+// The exchange convolution of eq. (10), in place:
+//   rho[k][e] <- scale * sum_R exp(+i k.R) Wt(R) rhot(R),
+//   rhot(R) = sum_k exp(-i k.R) rho[k][e],  Wt(R) = sum_q exp(+i q.R) W^q[e],
+// which is scale * N_k * sum_q W^q[e] rho[k+q][e].  W^q is read from the
+// class storage: W^q[e] = w[wsel[q] >> 1][e], conjugated when wsel[q] & 1.
+// Both mesh columns of a tile of `etile` elements sit in LDS ([k][etile]
+// each); a workgroup reads and writes only its own elements.
+template <int MAXA>
+__global__ __launch_bounds__(256) void xconv_kernel(XconvArgs a, int etile) {
+  extern __shared__ cplx xbuf[];
+  __shared__ cplx tw[3][MAXM];
+  init_twiddles(tw, a.m1, a.m2, a.m3);
+  const int eshift = __builtin_ctz(etile);
+  const int nk = a.m1 * a.m2 * a.m3;
+  const int total = nk << eshift;
+  cplx* br = xbuf;
+  cplx* bw = xbuf + total;
+  const long long e0 = (long long)blockIdx.x * etile;
+  const long long rem = a.n_elem - e0;
+  const int ne = rem < etile ? (int)rem : etile;
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    const int k = idx >> eshift, e = idx & (etile - 1);
+    cplx r = cmk(0.0, 0.0), w = cmk(0.0, 0.0);
+    if (e < ne) {
+      r = a.rho[(long long)k * a.n_elem + e0 + e];
+      const int sel = a.wsel[k];
+      w = a.w[(long long)(sel >> 1) * a.n_elem + e0 + e];
+      if (sel & 1) w.y = -w.y;
+    }
+    br[idx] = r;
+    bw[idx] = w;
+  }
+  __syncthreads();
+  mesh_dft<MAXA>(br, tw, etile, a.m1, a.m2, a.m3, -1);
+  mesh_dft<MAXA>(bw, tw, etile, a.m1, a.m2, a.m3, +1);
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) br[idx] = cmul(br[idx], bw[idx]);
+  __syncthreads();
+  mesh_dft<MAXA>(br, tw, etile, a.m1, a.m2, a.m3, +1);
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    const int k = idx >> eshift, e = idx & (etile - 1);
+    if (e < ne) a.rho[(long long)k * a.n_elem + e0 + e] = cscale(br[idx], a.scale);
+  }
+}
+
 // One workgroup: a tile of `tp` pairs of one fragment times `ti` consecutive
 // interpolation points; LDS holds [R][tp*ti] so that the output rows (pair,
 // I-range) are written as contiguous runs of I.
@@ -748,6 +792,24 @@ hipError_t kconv_launch(const KconvArgs& a, hipStream_t s) {
   if (mx <= 4) hipLaunchKernelGGL(kconv_kernel<4>, dim3((unsigned)blocks), dim3(256), lds, s, a, etile);
   else if (mx <= 8) hipLaunchKernelGGL(kconv_kernel<8>, dim3((unsigned)blocks), dim3(256), lds, s, a, etile);
   else hipLaunchKernelGGL(kconv_kernel<16>, dim3((unsigned)blocks), dim3(256), lds, s, a, etile);
+  return hipGetLastError();
+}
+
+hipError_t xconv_launch(const XconvArgs& a, hipStream_t s) {
+  if (!a.rho || !a.w || !a.wsel) return hipErrorInvalidValue;
+  if (a.m1 > MAXM || a.m2 > MAXM || a.m3 > MAXM || a.m1 < 1 || a.m2 < 1 || a.m3 < 1) return hipErrorInvalidValue;
+  const int nk = a.m1 * a.m2 * a.m3;
+  int etile = 1;                        // two [nk][etile] columns in at most 64 KB
+  while (etile < 256 && (long long)nk * etile * 2 <= 2048) etile *= 2;
+  const long long blocks = (a.n_elem + etile - 1) / etile;
+  if (blocks <= 0) return hipSuccess;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  const size_t lds = 2 * (size_t)nk * etile * sizeof(cplx);
+  if (lds > 64 * 1024) return hipErrorInvalidValue;
+  const int mx = std::max(a.m1, std::max(a.m2, a.m3));
+  if (mx <= 4) hipLaunchKernelGGL(xconv_kernel<4>, dim3((unsigned)blocks), dim3(256), lds, s, a, etile);
+  else if (mx <= 8) hipLaunchKernelGGL(xconv_kernel<8>, dim3((unsigned)blocks), dim3(256), lds, s, a, etile);
+  else hipLaunchKernelGGL(xconv_kernel<16>, dim3((unsigned)blocks), dim3(256), lds, s, a, etile);
   return hipGetLastError();
 }
 

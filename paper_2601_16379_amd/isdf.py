@@ -24,6 +24,7 @@ ISDF_INPUT_DEVICE = 0x1
 ISDF_NO_PIVOT = 0x2
 ISDF_ZETA_ROUTE = 0x4
 ISDF_FRAG_DEVICE = 0x1
+ISDF_HF_DEVICE = 0x1
 REQ_STATES = {0: "QUEUED", 1: "RUNNING", 2: "DONE", 3: "FAILED", 4: "CANCELLED"}
 
 EXPORTS = ["isdf_create", "isdf_fit", "isdf_coulomb_kernel", "isdf_get_metric",
@@ -31,8 +32,8 @@ EXPORTS = ["isdf_create", "isdf_fit", "isdf_coulomb_kernel", "isdf_get_metric",
            "isdf_serve_start", "isdf_submit", "isdf_submit_n", "isdf_poll", "isdf_cancel",
            "isdf_serve_stop", "isdf_stats", "isdf_stage_ms", "isdf_stage_total", "isdf_stage_reset", "isdf_plan_bytes", "isdf_storage_model_bytes",
            "isdf_graph_create", "isdf_graph_launch", "isdf_graph_destroy", "isdf_autotune", "isdf_set_tiling",
-           "isdf_save", "isdf_load", "isdf_fragment_eri_static", "isdf_select_points", "isdf_destroy",
-           "isdf_last_error", "isdf_version"]
+           "isdf_save", "isdf_load", "isdf_fragment_eri_static", "isdf_select_points", "isdf_hf_jk",
+           "isdf_destroy", "isdf_last_error", "isdf_version"]
 
 
 class IsdfError(RuntimeError):
@@ -83,6 +84,7 @@ def load_library(path=LIB_PATH):
         "isdf_fragment_eri": (I32, [P, I32, I32, P, P, P, U32]),
         "isdf_fragment_eri_static": (I32, [P, I32, I32, P, P, P, U32]),
         "isdf_select_points": (I32, [P, P, I32, P, I32, P, P, U32, P]),
+        "isdf_hf_jk": (I32, [P, P, P, P, U32]),
         "isdf_serve_start": (I32, [P, I32, I32, I64]),
         "isdf_submit": (I32, [P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
         "isdf_submit_n": (I32, [P, I32, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
@@ -306,6 +308,26 @@ class Isdf:
                                                nfs.ctypes.data, cptr, eptr, flags),
                     "isdf_fragment_eri")
         return out
+
+    def hf_jk(self, dm, want_j=True, want_k=True):
+        """``isdf_hf_jk``: Coulomb and exchange matrices of the k-point density
+        matrices ``dm`` ([N_k, n_orb, n_orb] complex128, numpy = host, torch
+        cuda tensor = device).  Returns (J, K) of the same kind (None where not
+        asked for)."""
+        if tuple(dm.shape) != (self.n_k, self.n_orb, self.n_orb):
+            raise ValueError("dm must be [N_k, n_orb, n_orb]")
+        dptr, dev = _ptr(dm)
+        if dev:
+            import torch
+            mk = lambda: torch.empty(tuple(dm.shape), dtype=torch.complex128, device=dm.device)  # noqa: E731
+        else:
+            mk = lambda: np.empty(tuple(dm.shape), dtype=np.complex128)  # noqa: E731
+        j = mk() if want_j else None
+        k = mk() if want_k else None
+        self._check(self.lib.isdf_hf_jk(self.h, dptr, _ptr(j)[0] if j is not None else None,
+                                        _ptr(k)[0] if k is not None else None, ISDF_HF_DEVICE if dev else 0),
+                    "isdf_hf_jk")
+        return j, k
 
     def graph(self, coeffs, out, prec="bf16x3"):
         """The fragment pipeline of this batch (device tensors ``coeffs``, ERIs

@@ -255,6 +255,29 @@ def test_large_cell_kernel_through_v(bigcell):
 
 
 @pytest.mark.timeout(900)
+def test_large_cell_hf_jk_sampled(bigcell):
+    """Coulomb and exchange matrices (eq. (10)) at the cell's full size from
+    the GPU's W^q: J at every k against the oracle, K at two sampled k
+    against the oracle's direct sum over all q."""
+    import torch
+    from oracle import hf
+    b = bigcell
+    cfg = b.d.cfg
+    dm = inp.make_density(cfg)
+    jd, kd = b.ctx.hf_jk(torch.from_numpy(dm).cuda())
+    torch.cuda.synchronize()
+    j, k = jd.cpu().numpy(), kd.cpu().numpy()
+    del jd, kd
+    w = b.w_all()
+    ks = [0, cfg.n_k // 2 + 1]
+    k_ref = hf.exchange_at(b.x, w, dm, cfg.kmesh, ks)
+    j_ref = hf.coulomb(b.x, w, dm)
+    ek, ej = _rel(k[ks], k_ref), _rel(j, j_ref)
+    print("%s: K at k = %s rel %.2e, J rel %.2e" % (cfg.name, ks, ek, ej), flush=True)
+    assert ek < 1e-11 and ej < 1e-11
+
+
+@pytest.mark.timeout(900)
 def test_large_cell_small_fragments_oracle(bigcell):
     b = bigcell
     name = b.d.cfg.name
