@@ -46,6 +46,7 @@ STREAM_FRAG_SIZES = 3
 STREAM_FRAG_COEFFS = 4
 STREAM_ARRIVALS = 5
 STREAM_DENSITY = 6
+STREAM_MO = 7
 
 
 @dataclasses.dataclass(frozen=True)
@@ -329,6 +330,36 @@ def make_density(cfg: Config, n_occ: Optional[int] = None, seed: int = 0) -> np.
         q = q * (np.diag(r) / np.abs(np.diag(r)))[None, :]
         out[k] = 2.0 * (q @ q.conj().T)
     return out
+
+
+def make_mo(cfg: Config, n_occ: Optional[int] = None, seed: int = 0):
+    """Synthetic canonical orbitals of a k-point mean-field calculation:
+    per k a Haar-random unitary ``C[k, mu, p]`` (complex128
+    ``[N_k, N_orb, N_orb]``) and sorted energies ``e[k, p]`` (float64
+    ``[N_k, N_orb]``), the first n_occ (N_orb // 2, at least 1) occupied,
+    uniform in [-1.0, -0.3] Eh, the rest uniform in [0.2, 1.5] Eh (a gap of
+    at least 0.5 Eh, as an insulator's).  Returns (C, e, n_occ)."""
+    n = cfg.n_orb
+    n_occ = max(1, n // 2) if n_occ is None else int(n_occ)
+    rng = _seed(cfg, STREAM_MO, seed)
+    c = np.empty((cfg.n_k, n, n), dtype=np.complex128)
+    e = np.empty((cfg.n_k, n))
+    for k in range(cfg.n_k):
+        z = (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) * np.sqrt(0.5)
+        q, r = np.linalg.qr(z)
+        c[k] = q * (np.diag(r) / np.abs(np.diag(r)))[None, :]
+        e[k, :n_occ] = np.sort(rng.uniform(-1.0, -0.3, n_occ))
+        e[k, n_occ:] = np.sort(rng.uniform(0.2, 1.5, n - n_occ))
+    return c, e, n_occ
+
+
+def laplace_grid(n: int, scale: float):
+    """Quadrature for integrals over tau in [0, inf) of decaying exponentials:
+    n-point Gauss-Legendre on x in (-1, 1) mapped by tau = scale (1 + x)/(1 - x)
+    (weights times dtau/dx = 2 scale/(1 - x)^2).  Returns (tau, weight)."""
+    x, w = np.polynomial.legendre.leggauss(int(n))
+    tau = scale * (1.0 + x) / (1.0 - x)
+    return tau, w * 2.0 * scale / (1.0 - x) ** 2
 
 
 def make_fragments(cfg: Config, n_frag: Optional[int] = None):

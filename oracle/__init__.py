@@ -20,7 +20,9 @@ eye.  Modules:
 * ``kpoint``    -- the k-point fit, the Coulomb kernel and the fragment ERIs;
 * ``ipselect``  -- interpolation points by pivoted Cholesky of the pair products;
 * ``hf``        -- k-point Hartree-Fock Coulomb and exchange matrices from W^q
-  (eq. (10)).
+  (eq. (10));
+* ``mp2``       -- k-point opposite-spin MP2 in the imaginary-time form
+  (eqs. (11)-(15)).
 
 Every function is pinned by ``tests/test_oracle_pins.py``; none is
 "parity unpinned" except the size of the ISDF approximation error itself on

@@ -626,3 +626,75 @@ def test_jk_hermitian_and_exchange_psd():
     ek = np.einsum("kab,kba->", dm, kk)
     assert abs(ej.imag) < 1e-12 * abs(ej) and ej.real > 0
     assert abs(ek.imag) < 1e-12 * abs(ek) and ek.real > 0
+
+
+# --------------------------------------------------------------------------
+# k-point SOS-MP2 in the imaginary-time form (eqs. (11)-(15))
+# --------------------------------------------------------------------------
+from oracle import mp2
+
+
+@pytest.mark.parametrize("name", ["t_small_k3", "t_k10_line"])
+def test_os_integrand_equals_closed_form_at_every_tau(name):
+    """F(tau) from the polarisabilities (k convolutions of the Green's
+    functions at the points, traces with W^q) equals the closed-form sum
+    over ijab of |(ia|jb)|^2 exp(-tau Delta) from the crystalline ERIs of
+    eq. (9), with no quadrature; the chemical potential cancels."""
+    d = _case(name)
+    cfg = d.cfg
+    x, pi, eta, w = ko.fit_and_kernel(d.orbitals, d.ip_index, d.lattice, cfg.grid, cfg.kmesh)
+    c, e, n_occ = inp.make_mo(cfg)
+    for tau in (0.0, 0.37, 1.9):
+        f = mp2.os_integrand(x, w, c, e, n_occ, cfg.kmesh, tau)
+        ref = mp2.os_closed_form(x, w, c, e, n_occ, cfg.kmesh, tau)
+        assert abs(f.imag) < 1e-12 * abs(ref)
+        assert abs(f.real - ref) < 1e-12 * abs(ref), tau
+    y = mp2.mo_at_ips(x, c)
+    go, gv = mp2.greens(y, e, n_occ, 0.8, 0.1)
+    go2, gv2 = mp2.greens(y, e, n_occ, 0.8, -0.2)
+    chi, chit = mp2.polarisabilities(go, gv, cfg.kmesh)
+    chi2, chit2 = mp2.polarisabilities(go2, gv2, cfg.kmesh)
+    assert _rel(chi, chi2) < 1e-12 and _rel(chit, chit2) < 1e-12
+    # chit^q = conj(chi^{-q})
+    mq = geo.minus_q(cfg.kmesh)
+    assert _rel(chit, chi[mq].conj()) < 1e-13
+
+
+def test_os_energy_quadrature_converges_to_closed_form():
+    d = _case("t_small_k3")
+    cfg = d.cfg
+    x, pi, eta, w = ko.fit_and_kernel(d.orbitals, d.ip_index, d.lattice, cfg.grid, cfg.kmesh)
+    c, e, n_occ = inp.make_mo(cfg)
+    exact = mp2.os_closed_form(x, w, c, e, n_occ, cfg.kmesh)
+    assert exact < 0
+    errs = []
+    for n in (12, 24, 36):
+        t, wt = inp.laplace_grid(n, 1.0)
+        errs.append(abs(mp2.os_energy(x, w, c, e, n_occ, cfg.kmesh, t, wt) - exact) / abs(exact))
+    assert errs[2] < 1e-9 and errs[1] < errs[0]
+
+
+@pytest.mark.parametrize("name", ["t_tiny_k2", "t_k10_line"])
+def test_os_energy_with_full_grid_ips_equals_supercell_mp2(name):
+    """With every grid point an interpolation point the ISDF ERIs are exact,
+    so E_OS equals the opposite-spin MP2 energy of the supercell canonical
+    orbitals from the FFT-Poisson ERIs, -sum |(ia|jb)|^2 / Delta, per cell."""
+    cfg = inp.get_config(name)
+    d = _case(name, n_ip=cfg.n_g)
+    x, pi, eta, w = ko.fit_and_kernel(d.orbitals, d.ip_index, d.lattice, cfg.grid, cfg.kmesh)
+    c, e, n_occ = inp.make_mo(cfg)
+    nk, no = cfg.n_k, cfg.n_orb
+    coeffs = np.zeros((nk, no, nk * no), dtype=np.complex128)
+    for k in range(nk):
+        coeffs[k, :, k * no:(k + 1) * no] = c[k]
+    phi_s = sc.supercell_orbitals(d.orbitals, cfg.grid, cfg.kmesh)
+    psi = sc.fragment_orbitals(phi_s, coeffs)
+    eri = sc.exact_eri(psi, d.lattice, cfg.grid, cfg.kmesh)
+    occ = np.array([k * no + p for k in range(nk) for p in range(n_occ)])
+    vir = np.array([k * no + p for k in range(nk) for p in range(n_occ, no)])
+    ef = e.reshape(-1)
+    v = eri[np.ix_(occ, vir, occ, vir)]
+    delta = (ef[vir][None, :, None, None] - ef[occ][:, None, None, None]
+             + ef[vir][None, None, None, :] - ef[occ][None, None, :, None])
+    e_sc = -np.sum(np.abs(v) ** 2 / delta) / nk
+    assert _rel(mp2.os_closed_form(x, w, c, e, n_occ, cfg.kmesh), e_sc) < 1e-11
