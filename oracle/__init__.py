@@ -22,7 +22,8 @@ eye.  Modules:
 * ``hf``        -- k-point Hartree-Fock Coulomb and exchange matrices from W^q
   (eq. (10));
 * ``mp2``       -- k-point opposite-spin MP2 in the imaginary-time form
-  (eqs. (11)-(15)).
+  (eqs. (11)-(15));
+* ``rpa``       -- k-point direct RPA correlation energy (eq. (16)).
 
 Every function is pinned by ``tests/test_oracle_pins.py``; none is
 "parity unpinned" except the size of the ISDF approximation error itself on

@@ -698,3 +698,69 @@ def test_os_energy_with_full_grid_ips_equals_supercell_mp2(name):
              + ef[vir][None, None, None, :] - ef[occ][None, None, :, None])
     e_sc = -np.sum(np.abs(v) ** 2 / delta) / nk
     assert _rel(mp2.os_closed_form(x, w, c, e, n_occ, cfg.kmesh), e_sc) < 1e-11
+
+
+# --------------------------------------------------------------------------
+# k-point direct RPA (eq. (16))
+# --------------------------------------------------------------------------
+from oracle import rpa
+
+
+def test_drpa_second_order_term_is_the_os_mp2_energy():
+    """The second-order term of the logarithm of eq. (16) is the
+    opposite-spin MP2 energy (closed form over ijab), on a frequency
+    quadrature fine enough for its Lorentzians; the full dRPA energy is
+    negative and smaller in magnitude (screening)."""
+    d = _case("t_small_k3")
+    cfg = d.cfg
+    x, pi, eta, w = ko.fit_and_kernel(d.orbitals, d.ip_index, d.lattice, cfg.grid, cfg.kmesh)
+    c, e, n_occ = inp.make_mo(cfg)
+    om, ow = inp.laplace_grid(40, 1.0)
+    e_rpa, e_2 = rpa.drpa_energy(x, w, c, e, n_occ, cfg.kmesh, om, ow)
+    e_os = mp2.os_closed_form(x, w, c, e, n_occ, cfg.kmesh)
+    assert abs(e_2 - e_os) < 1e-8 * abs(e_os)
+    assert e_os < e_rpa < 0
+
+
+@pytest.mark.parametrize("name", ["t_k10_line", "t_small_k3"])
+def test_chi_omega_from_time_quadrature_matches_closed_form(name):
+    """chi^q(iw) as the quadrature of the time integral of the Green's-function
+    polarisabilities converges to the Lorentzian closed form (a 128-point
+    mapped Gauss-Legendre grid resolves exp(i w tau) up to w = 1.5 Eh);
+    chi^q(-iw) is chi^q(iw)^H; chi^{-q}(iw) = conj(chi^q(iw))."""
+    d = _case(name)
+    cfg = d.cfg
+    x = ko.ip_values(d.orbitals, d.ip_index)
+    c, e, n_occ = inp.make_mo(cfg)
+    y = mp2.mo_at_ips(x, c)
+    tau, tw = inp.laplace_grid(128, 1.0)
+    omegas = [0.0, 0.6, 1.5]
+    qs = [0, 1, cfg.n_k - 1]
+    got = rpa.chi_omega_from_tau(y, e, n_occ, cfg.kmesh, omegas, tau, tw, qs)
+    mq = geo.minus_q(cfg.kmesh)
+    for m, om in enumerate(omegas):
+        for i, q in enumerate(qs):
+            ref = rpa.chi_omega_exact(y, e, n_occ, cfg.kmesh, q, om)
+            assert _rel(got[m, i], ref) < 1e-7, (om, q)
+            assert _rel(rpa.chi_omega_exact(y, e, n_occ, cfg.kmesh, q, -om), ref.conj().T) < 1e-13
+            assert _rel(rpa.chi_omega_exact(y, e, n_occ, cfg.kmesh, int(mq[q]), om), ref.conj()) < 1e-13
+
+
+def test_drpa_log_det_against_the_ring_series():
+    """With W scaled so that the ring series converges, Re ln det(1 - P) +
+    Re tr P equals -sum_{n >= 2} Re tr(P^n) / n."""
+    d = _case("t_k10_line")
+    cfg = d.cfg
+    x, pi, eta, w = ko.fit_and_kernel(d.orbitals, d.ip_index, d.lattice, cfg.grid, cfg.kmesh)
+    c, e, n_occ = inp.make_mo(cfg)
+    y = mp2.mo_at_ips(x, c)
+    p = rpa.chi_omega_exact(y, e, n_occ, cfg.kmesh, 3, 0.4) @ w[3]
+    p = p * (0.5 / np.max(np.abs(np.linalg.eigvals(p))))
+    full, second = rpa.rpa_terms(p)
+    series = 0.0
+    pn = p @ p
+    for n in range(2, 80):
+        series -= np.trace(pn).real / n
+        pn = pn @ p
+    assert abs(full - series) < 1e-12 * abs(series)
+    assert abs(second + 0.5 * np.trace(p @ p).real) < 1e-15
