@@ -362,6 +362,42 @@ def laplace_grid(n: int, scale: float):
     return tau, w * 2.0 * scale / (1.0 - x) ** 2
 
 
+def quadrature_transform(tau, tau_weight, omega):
+    """Time-to-frequency transform of a plain quadrature:
+    gamma[m, n] = tau_weight[n] exp(i omega[m] tau[n]) (complex128
+    [n_omega, n_tau]), so that sum_n gamma[m, n] exp(-D tau_n) approximates
+    int_0^inf exp(-(D - i omega_m) tau) dtau = 1 / (D - i omega_m); accurate
+    only while the grid resolves exp(i omega tau)."""
+    return np.asarray(tau_weight)[None, :] * np.exp(1j * np.outer(omega, tau))
+
+
+def fitted_transform(tau, omega, d_min: float, d_max: float, n_d: int = 400):
+    """Time-to-frequency transform fitted by least squares: for every omega_m
+    the coefficients gamma[m, :] minimise the relative error of
+    sum_n gamma[m, n] exp(-D tau_n) against 1 / (D - i omega_m) over D on
+    n_d log-spaced points of [d_min, d_max] (the range of the excitation
+    energies), singular values below 1e-14 of the largest dropped.  Accurate
+    at every omega, including those a plain quadrature cannot resolve.
+    Returns complex128 [n_omega, n_tau]."""
+    tau = np.asarray(tau, dtype=np.float64)
+    d = np.geomspace(d_min, d_max, int(n_d))
+    basis = np.exp(-np.outer(d, tau))
+    out = np.empty((len(omega), tau.size), dtype=np.complex128)
+    for m, w in enumerate(omega):
+        target = 1.0 / (d - 1j * w)
+        scale = 1.0 / np.abs(target)
+        u, sv, vh = np.linalg.svd(basis * scale[:, None], full_matrices=False)
+        keep = sv > 1e-14 * sv[0]
+        out[m] = vh[keep].conj().T @ ((u[:, keep].conj().T @ (target * scale)) / sv[keep])
+    return out
+
+
+def excitation_range(e: np.ndarray, n_occ: int):
+    """(smallest, largest) e_a - e_i over all k of canonical energies e[k, p]."""
+    occ, vir = e[:, :n_occ], e[:, n_occ:]
+    return float(vir.min() - occ.max()), float(vir.max() - occ.min())
+
+
 def make_fragments(cfg: Config, n_frag: Optional[int] = None):
     sizes = fragment_sizes(cfg, n_frag)
     return [make_fragment(cfg, f, int(nf)) for f, nf in enumerate(sizes)]

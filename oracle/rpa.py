@@ -12,7 +12,10 @@ of ``oracle.mp2``:
     chi^q(iw)  = -int_0^inf [exp(+i w tau) chi^q(tau) + exp(-i w tau) chit^q(tau)] dtau
                = -N_k^-1 sum_k [ sum_{a in k, i in k+q} v v^H / (D - i w)
                                + sum_{i in k, a in k+q} u u^H / (D + i w) ],
-      v = Y^k_a o conj(Y^{k+q}_i),  u = Y^k_i o conj(Y^{k+q}_a),  D = e_a - e_i > 0
+      v = Y^k_a o conj(Y^{k+q}_i),  u = Y^k_i o conj(Y^{k+q}_a),  D = e_a - e_i > 0,
+      evaluated from the time polarisabilities with a transform gamma[m, n]
+      that maps exp(-D tau_n) to 1 / (D - i w_m) (a quadrature, or fitted):
+      chi^q(iw_m) = -sum_n [gamma[m, n] chi^q(tau_n) + conj(gamma[m, n]) chit^q(tau_n)];
     E_dRPA     = sum_q int_{-inf}^{inf} dw / (2 pi N_k) [ln det(1 - chi^q W^q) + tr(chi^q W^q)]
                = sum_q int_0^inf dw / (pi N_k) Re[ln det(1 - chi^q W^q) + tr(chi^q W^q)]
 
@@ -47,18 +50,21 @@ def chi_omega_exact(y, e, n_occ, kmesh, q, omega):
     return out / nk
 
 
-def chi_omega_from_tau(y, e, n_occ, kmesh, omegas, tau, weight, qs=None):
-    """chi^q(iw) for every w in ``omegas`` by the quadrature (tau, weight) of
-    the time integral of the mp2 polarisabilities.  Returns [n_w, n_q, N_IP, N_IP]."""
+def chi_omega_from_tau(y, e, n_occ, kmesh, transform, tau, qs=None):
+    """chi^q(iw_m) = -sum_n [gamma[m, n] chi^q(tau_n) + conj(gamma[m, n])
+    chit^q(tau_n)] with the mp2 polarisabilities at the times ``tau`` and the
+    time-to-frequency transform gamma = ``transform`` [n_w, n_tau].  Returns
+    [n_w, n_q, N_IP, N_IP]."""
     nk = y.shape[0]
     qs = list(range(nk)) if qs is None else list(qs)
     mu = mp2.chemical_potential(e, n_occ)
-    out = np.zeros((len(omegas), len(qs), y.shape[1], y.shape[1]), dtype=np.complex128)
-    for t, wt in zip(tau, weight):
+    out = np.zeros((transform.shape[0], len(qs), y.shape[1], y.shape[1]), dtype=np.complex128)
+    for n, t in enumerate(tau):
         go, gv = mp2.greens(y, e, n_occ, t, mu)
         chi, chit = mp2.polarisabilities(go, gv, kmesh, qs)
-        for m, om in enumerate(omegas):
-            out[m] -= wt * (np.exp(1j * om * t) * chi + np.exp(-1j * om * t) * chit)
+        for m in range(transform.shape[0]):
+            g = transform[m, n]
+            out[m] -= g * chi + np.conj(g) * chit
     return out
 
 
@@ -68,15 +74,15 @@ def rpa_terms(p):
     return (ld + np.log(sgn)).real + np.trace(p).real, -0.5 * np.trace(p @ p).real
 
 
-def drpa_energy(x, w, c, e, n_occ, kmesh, omega, omega_weight, tau=None, tau_weight=None):
+def drpa_energy(x, w, c, e, n_occ, kmesh, omega, omega_weight, tau=None, transform=None):
     """(E_dRPA, its second-order term) on the frequency quadrature
     (omega, omega_weight) of [0, inf); chi^q(iw) from the closed form, or,
-    with (tau, tau_weight), from the time quadrature of the polarisabilities
-    (what the library computes)."""
+    with (tau, transform), from the polarisabilities at the times tau and the
+    time-to-frequency transform (what the library computes)."""
     nk = x.shape[0]
     y = mp2.mo_at_ips(x, c)
     if tau is not None:
-        chis = chi_omega_from_tau(y, e, n_occ, kmesh, omega, tau, tau_weight)
+        chis = chi_omega_from_tau(y, e, n_occ, kmesh, transform, tau)
     e_rpa = e_2 = 0.0
     for q in range(nk):
         for m, (om, wo) in enumerate(zip(omega, omega_weight)):

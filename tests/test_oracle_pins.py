@@ -720,6 +720,12 @@ def test_drpa_second_order_term_is_the_os_mp2_energy():
     e_os = mp2.os_closed_form(x, w, c, e, n_occ, cfg.kmesh)
     assert abs(e_2 - e_os) < 1e-8 * abs(e_os)
     assert e_os < e_rpa < 0
+    # the same energies from the time polarisabilities with a fitted transform
+    tau, _ = inp.laplace_grid(32, 0.5)
+    lo, hi = inp.excitation_range(e, n_occ)
+    e_rpa_t, e_2_t = rpa.drpa_energy(x, w, c, e, n_occ, cfg.kmesh, om, ow, tau,
+                                     inp.fitted_transform(tau, om, lo, hi))
+    assert abs(e_rpa_t - e_rpa) < 1e-6 * abs(e_rpa) and abs(e_2_t - e_2) < 1e-6 * abs(e_2)
 
 
 @pytest.mark.parametrize("name", ["t_k10_line", "t_small_k3"])
@@ -736,7 +742,7 @@ def test_chi_omega_from_time_quadrature_matches_closed_form(name):
     tau, tw = inp.laplace_grid(128, 1.0)
     omegas = [0.0, 0.6, 1.5]
     qs = [0, 1, cfg.n_k - 1]
-    got = rpa.chi_omega_from_tau(y, e, n_occ, cfg.kmesh, omegas, tau, tw, qs)
+    got = rpa.chi_omega_from_tau(y, e, n_occ, cfg.kmesh, inp.quadrature_transform(tau, tw, omegas), tau, qs)
     mq = geo.minus_q(cfg.kmesh)
     for m, om in enumerate(omegas):
         for i, q in enumerate(qs):
@@ -744,6 +750,15 @@ def test_chi_omega_from_time_quadrature_matches_closed_form(name):
             assert _rel(got[m, i], ref) < 1e-7, (om, q)
             assert _rel(rpa.chi_omega_exact(y, e, n_occ, cfg.kmesh, q, -om), ref.conj().T) < 1e-13
             assert _rel(rpa.chi_omega_exact(y, e, n_occ, cfg.kmesh, int(mq[q]), om), ref.conj()) < 1e-13
+    # a fitted transform on 32 times is accurate at every frequency, up to
+    # those a plain quadrature cannot resolve
+    tau2, _ = inp.laplace_grid(32, 0.5)
+    om2, _ = inp.laplace_grid(12, 1.0)
+    lo, hi = inp.excitation_range(e, n_occ)
+    fit = rpa.chi_omega_from_tau(y, e, n_occ, cfg.kmesh, inp.fitted_transform(tau2, om2, lo, hi), tau2, qs)
+    for m, om in enumerate(om2):
+        for i, q in enumerate(qs):
+            assert _rel(fit[m, i], rpa.chi_omega_exact(y, e, n_occ, cfg.kmesh, q, om)) < 1e-6, (om, q)
 
 
 def test_drpa_log_det_against_the_ring_series():
