@@ -63,6 +63,8 @@ def parse():
                     help="fragments per serving batch (0: all of a step in one batch)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device copy first (reference for HBM byte counters)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="large cells: skip the Coulomb/exchange and interpolation-point legs")
     ap.add_argument("--no-peaks", action="store_true",
                     help="skip the measured HBM / GEMM peaks (timed after the steps)")
     return ap.parse_args()
@@ -359,6 +361,147 @@ def measured_peaks(torch):
     return out
 
 
+HF_STAGES = ["hf_rho", "hf_j", "hf_kconv", "hf_k"]
+
+
+def hf_leg(ctx, cfg, d, inp, np, torch, reps, oracle):
+    """Coulomb and exchange matrices (isdf_hf_jk, eq. (10)) of a seeded
+    closed-shell density matrix with W^q resident: one untimed call, then
+    `reps` timed calls (device buffers); per-stage times from the library's
+    events; the exchange k convolution against its algorithmic bytes (read
+    rho and W of every class, write M once); with `oracle`, the oracle's K
+    at one k point timed on the host and scaled by N_k."""
+    dm = torch.from_numpy(inp.make_density(cfg)).cuda()
+    ctx.hf_jk(dm)
+    torch.cuda.synchronize()
+    before = collect_stages(ctx, HF_STAGES)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.hf_jk(dm)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps
+    after = collect_stages(ctx, HF_STAGES)
+    st = {k: (after[k][0] - before.get(k, (0.0, 0))[0]) / reps for k in after}
+    nh = n_classes(cfg.kmesh)
+    nn = cfg.n_ip * cfg.n_ip
+    kconv_bytes = (2 * cfg.n_k + nh) * nn * 16
+    gemm_flops = 2 * 8.0 * cfg.n_k * (cfg.n_ip * cfg.n_orb ** 2 + nn * cfg.n_orb)
+    out = {"ms_per_call": 1e3 * wall, "stages_ms": st,
+           "kconv": {"bytes": kconv_bytes, "GBps": kconv_bytes / (st.get("hf_kconv", 0) / 1e3) / 1e9
+                     if st.get("hf_kconv") else None, "bound": "hbm"},
+           "rho_and_k_gemm_tflops": gemm_flops / ((st.get("hf_rho", 0) + st.get("hf_k", 0)) / 1e3) / 1e12
+           if st.get("hf_rho") else None,
+           "density": "closed shell, N_orb/2 occupied per k (seeded)"}
+    if oracle:
+        from oracle import hf as ohf
+        from oracle import kpoint as ko
+        x = ko.ip_values(d.orbitals, d.ip_index)
+        ks = [0]
+        w = np.stack([ctx.get_kernel(q) for q in range(cfg.n_k)])
+        dmh = dm.cpu().numpy()
+        t0 = time.perf_counter()
+        ohf.exchange_at(x, w, dmh, cfg.kmesh, ks)
+        tk = time.perf_counter() - t0
+        out["oracle"] = {"exchange_one_k_s": tk, "exchange_all_k_s_estimate": tk * cfg.n_k,
+                         "sample": "K at one k point (all q), scaled by N_k"}
+        del w
+    return out
+
+
+def select_leg(cfg, d, pkg, np, torch, oracle):
+    """Interpolation points by pivoted Cholesky (isdf_select_points) on the
+    cell's device-resident orbitals, all N_IP points, timed once; the step's
+    algorithmic bytes (read the orbitals once, the earlier factor columns at
+    their values once) against HBM; with `oracle`, two oracle steps on the
+    host scaled to N_IP steps."""
+    orb = torch.from_numpy(d.orbitals).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ip, res = pkg.select_points(cfg.grid, cfg.kmesh, orb, cfg.n_ip)
+    t = time.perf_counter() - t0
+    del orb
+    torch.cuda.empty_cache()
+    nrows = cfg.n_k * cfg.n_orb
+    n = cfg.n_ip
+    byts = n * nrows * cfg.n_g * 16.0 + cfg.n_g * 8.0 * (n * (n - 1) / 2 + 3 * n)
+    out = {"s": t, "points": n, "ms_per_step": 1e3 * t / n, "bytes": byts, "GBps": byts / t / 1e9,
+           "frac_of_8TBps": byts / t / 8e12, "residual_first_last": [float(res[0]), float(res[-1])]}
+    if oracle:
+        from oracle import ipselect as ips
+        t0 = time.perf_counter()
+        ips.pivoted_cholesky_points(d.orbitals, 2)
+        t2 = time.perf_counter() - t0
+        out["oracle"] = {"two_steps_s": t2, "all_steps_s_estimate": t2 / 2 * n,
+                         "sample": "two greedy steps (with the residual start), scaled to N_IP steps"}
+    return out
+
+
+MP2_STAGES = ["mp2_green", "mp2_pconv", "mp2_wchi", "mp2_trace"]
+
+
+def mp2_leg(ctx, cfg, d, inp, np, torch, n_tau, oracle):
+    """Opposite-spin MP2 (isdf_sos_mp2) of seeded canonical orbitals on an
+    n_tau-point Laplace grid, timed once after an untimed call; per-stage
+    times; the W chi products against the FP64 MFMA peak (16 nh N_IP^3 flops
+    per tau); with `oracle`, the oracle's Green's functions at 8 k points
+    timed on the host and scaled to N_k and n_tau (the dominant host cost)."""
+    c, e, n_occ = inp.make_mo(cfg)
+    tau, wt = inp.laplace_grid(n_tau, 1.0)
+    cdev = torch.from_numpy(c).cuda()
+    ctx.sos_mp2(cdev, e, n_occ, tau[:1], wt[:1])
+    torch.cuda.synchronize()
+    before = collect_stages(ctx, MP2_STAGES)
+    t0 = time.perf_counter()
+    r = ctx.sos_mp2(cdev, e, n_occ, tau, wt)
+    t = time.perf_counter() - t0
+    after = collect_stages(ctx, MP2_STAGES)
+    st = {k: after[k][0] - before.get(k, (0.0, 0))[0] for k in after}
+    nh = n_classes(cfg.kmesh)
+    wflops = 16.0 * nh * cfg.n_ip ** 3 * n_tau
+    out = {"s": t, "n_tau": n_tau, "ms_per_tau": 1e3 * t / n_tau, "e_os": r["e_os"], "e_sos_mp2": r["e_sos_mp2"],
+           "stages_ms": st,
+           "w_chi_tflops": wflops / (st["mp2_wchi"] / 1e3) / 1e12 if st.get("mp2_wchi") else None,
+           "orbitals": "seeded canonical orbitals, N_orb/2 occupied, gap >= 0.5 Eh; Laplace grid "
+                       "Gauss-Legendre mapped by tau = (1 + x)/(1 - x)"}
+    if oracle:
+        from oracle import kpoint as ko
+        from oracle import mp2 as omp2
+        ks = list(range(min(8, cfg.n_k)))
+        x = ko.ip_values(d.orbitals[ks], d.ip_index)
+        y = omp2.mo_at_ips(x, c[ks])
+        t0 = time.perf_counter()
+        omp2.greens(y, e[ks], n_occ, float(tau[0]), omp2.chemical_potential(e, n_occ))
+        tg = time.perf_counter() - t0
+        out["oracle"] = {"greens_8k_s": tg, "greens_all_tau_s_estimate": tg * cfg.n_k / len(ks) * n_tau,
+                         "sample": "the oracle's Green's functions at 8 k points for one tau, scaled to "
+                                   "N_k and n_tau (the k convolutions and traces not included)"}
+    return out
+
+
+DRPA_STAGES = ["mp2_green", "mp2_pconv", "drpa_accum", "drpa_p", "drpa_logdet"]
+
+
+def drpa_leg(ctx, cfg, inp, np, torch, n_tau, n_omega):
+    """Direct RPA (isdf_drpa) of the same seeded canonical orbitals: n_tau
+    times (mapped Gauss-Legendre) for the frequency polarisabilities, a
+    time-to-frequency transform fitted over the excitation energies, n_omega
+    frequency points, timed once; per-stage times."""
+    c, e, n_occ = inp.make_mo(cfg)
+    tau, _ = inp.laplace_grid(n_tau, 0.5)
+    om, ow = inp.laplace_grid(n_omega, 1.0)
+    g = inp.fitted_transform(tau, om, *inp.excitation_range(e, n_occ))
+    cdev = torch.from_numpy(c).cuda()
+    before = collect_stages(ctx, DRPA_STAGES)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = ctx.drpa(cdev, e, n_occ, tau, ow, g)
+    t = time.perf_counter() - t0
+    after = collect_stages(ctx, DRPA_STAGES)
+    st = {k: after[k][0] - before.get(k, (0.0, 0))[0] for k in after}
+    return {"s": t, "n_tau": n_tau, "n_omega": n_omega, "e_drpa": r["e_drpa"], "e_second": r["e_second"],
+            "stages_ms": st}
+
+
 def collect_stages(ctx, names):
     out = {}
     for s in names:
@@ -471,6 +614,16 @@ def run_stream(args, cfg, pkg, inp, np, torch):
     ctx.serve_stop()
     roof = roofline_entry(ctx, frag_tot, cfg, timed_nfs, args.prec, args.steps)
     stages = stage_rows(frag_tot, cfg, timed_nfs, args.prec, args.steps)
+    if not args.no_extras:
+        log("Coulomb / exchange matrices and interpolation-point selection")
+        extra["hf_jk"] = hf_leg(ctx, cfg, d, inp, np, torch, 3, not args.no_cpu_baseline)
+        log("hf_jk %.1f ms per call" % extra["hf_jk"]["ms_per_call"])
+        extra["select_points"] = select_leg(cfg, d, pkg, np, torch, not args.no_cpu_baseline)
+        log("select_points %.2f s" % extra["select_points"]["s"])
+        extra["sos_mp2"] = mp2_leg(ctx, cfg, d, inp, np, torch, 4, not args.no_cpu_baseline)
+        log("sos_mp2 %.2f s for 4 tau points" % extra["sos_mp2"]["s"])
+        extra["drpa"] = drpa_leg(ctx, cfg, inp, np, torch, 16, 4)
+        log("drpa %.2f s for 16 tau and 4 omega points" % extra["drpa"]["s"])
     if not args.no_fp64_ref and args.prec != "fp64":
         # the plain FP64 GPU path on the same cell: fit + kernel, and the
         # first timed slice; speedup on that slice and max error per result

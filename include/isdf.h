@@ -429,6 +429,85 @@ isdf_status isdf_load(isdf_ctx* out, const char* path, void* hip_stream);
 #define ISDF_HF_DEVICE 0x1u
 isdf_status isdf_hf_jk(isdf_ctx ctx, const void* dm, void* j_out, void* k_out, uint32_t flags);
 
+/*
+ * k-point opposite-spin MP2 energy in the imaginary-time form (eqs. (11)-(15))
+ * from the resident W^q, per unit cell in Hartree (E_SOS-MP2 = 1.3 E_OS, eq.
+ * (11)).  Canonical orbitals psi^k_p = sum_mu C^k_{mu p} phi^k_mu with
+ * energies e^k_p, the first n_occ of every k occupied; Y^k = X^k C^k; m the
+ * midpoint between the highest occupied and the lowest virtual energy:
+ *   Go^k(tau) = Y_o e^{+tau (e_i - m)} Y_o^H,  Gv^k(tau) = Y_v e^{-tau (e_a - m)} Y_v^H
+ *   chi^q  = N_k^-1 sum_k Gv^k o conj(Go^{k+q}),  chit^q = N_k^-1 sum_k Go^k o conj(Gv^{k+q})
+ *   F(tau) = N_k^-1 sum_q tr[W^q chi^q W^q chit^q],   E_OS = -sum_n weight_n F(tau_n)
+ * (the Green's functions are the decaying ones; q as in W^q of this
+ * library; E_OS < 0).  Per tau: the Green's functions as Hermitian FP64 MFMA
+ * products, chi and chit of one q per class {q, -q} by one in-place
+ * convolution over the k mesh (LDS), W chi and chit W as FP64 MFMA products,
+ * the trace as an element-wise dot; a class with q != -q counts twice (its
+ * -q term is the conjugate).  FP64 throughout.
+ *   mo_coeff    c128 [N_k][n_orb][n_mo] (ISDF_MP2_DEVICE: device, else host).
+ *   mo_energy   float64 [N_k][n_mo], host; occupied below virtual.
+ *   tau, weight float64 [n_tau], host: a quadrature of [0, inf) (caller's).
+ *   integrand_out  float64 [n_tau] or NULL: F(tau_n).
+ *   class_out   float64 [n_tau][nh] or NULL: the contribution of class h to
+ *               F(tau_n) (class h = the h-th q of the mesh in C order whose -q
+ *               is not smaller).
+ *   e_os_out    float64: E_OS.
+ * Device workspace 2 N_k N_IP^2 + nh N_IP^2 complex numbers plus
+ * N_k N_IP n_mo x 2 (34.6 + 8.7 + 1.7 GB at N_k = 1000, N_IP = 1040),
+ * freed on return.  Synchronous.  Errors: ISDF_E_STATE before
+ * isdf_coulomb_kernel; ISDF_E_INVALID for null pointers, bad counts, energies
+ * without a gap, negative or non-finite tau, more than 2048 k points;
+ * ISDF_E_NOMEM, ISDF_E_DEVICE.
+ */
+#define ISDF_MP2_DEVICE 0x1u
+isdf_status isdf_sos_mp2(isdf_ctx ctx, const void* mo_coeff, const double* mo_energy, int32_t n_mo,
+                         int32_t n_occ, int32_t n_tau, const double* tau, const double* weight,
+                         double* integrand_out, double* class_out, double* e_os_out, uint32_t flags);
+
+/*
+ * k-point direct RPA correlation energy (eq. (16)) from the resident W^q,
+ * per unit cell in Hartree, with the polarisabilities of isdf_sos_mp2:
+ *   chi^q(iw_m) = -sum_n [gamma_mn chi^q(tau_n) + conj(gamma_mn) chit^q(tau_n)],
+ *             the time integral of both orderings with the caller's transform
+ *             gamma_mn, which maps exp(-D tau_n) to 1/(D - i w_m) for the
+ *             excitation energies D of the system: a plain quadrature
+ *             (gamma_mn = weight_n exp(i w_m tau_n), accurate only where the
+ *             time grid resolves exp(i w tau)) or a least-squares fit over the
+ *             range of D (accurate at every frequency),
+ *   E_dRPA    = sum_m omega_weight_m F(w_m),
+ *   F(w)      = (pi N_k)^-1 sum_q Re[ln det(1 - chi^q(iw) W^q) + tr(chi^q(iw) W^q)]
+ * (the integral over w in (-inf, inf) of eq. (16) folded onto [0, inf):
+ * chi^q(-iw) = chi^q(iw)^H), and its second-order term
+ * (pi N_k)^-1 sum_q -1/2 Re tr[(chi W)^2], which is the opposite-spin MP2
+ * energy.  chi^q(iw) is not Hermitian without time-reversal symmetry, so
+ * Re ln det(1 - P) is taken as 1/2 ln det(A^H A), A = 1 - P, from a blocked
+ * FP64 Cholesky factor; P, A^H A and the time convolutions are FP64 (MFMA for
+ * the products).  One q per class {q, -q} (the -q term is the conjugate).
+ * The frequencies are processed in batches that fit the device memory (the
+ * time loop runs once per batch).
+ *   mo_coeff, mo_energy, n_mo, n_occ  as isdf_sos_mp2 (ISDF_DRPA_DEVICE:
+ *               mo_coeff in device memory).
+ *   tau        float64 [n_tau], host: the times of the polarisabilities.
+ *   omega_weight  float64 [n_omega], host: weights of a quadrature of [0, inf)
+ *               in frequency.
+ *   transform  c128 [n_omega][n_tau], host: gamma_mn.
+ *   integrand_out  float64 [n_omega] or NULL: F(w_m).
+ *   class_out   float64 [n_omega][nh] or NULL: the contribution of class h to
+ *               F(w_m) (class order as isdf_sos_mp2).
+ *   e_drpa_out  float64: E_dRPA;  e_second_out  float64 or NULL: the
+ *               second-order term on the same grids.
+ * Device workspace as isdf_sos_mp2 plus 3 nh N_IP^2 and, per frequency of a
+ * batch, nh N_IP^2 complex numbers; freed on return.  Synchronous.  Errors:
+ * as isdf_sos_mp2 (non-finite transform or weights: ISDF_E_INVALID);
+ * ISDF_E_NUMERIC when 1 - chi W is singular; ISDF_E_NOMEM when not even one
+ * frequency fits.
+ */
+#define ISDF_DRPA_DEVICE 0x1u
+isdf_status isdf_drpa(isdf_ctx ctx, const void* mo_coeff, const double* mo_energy, int32_t n_mo, int32_t n_occ,
+                      int32_t n_tau, const double* tau, int32_t n_omega, const double* omega_weight,
+                      const void* transform, double* integrand_out, double* class_out, double* e_drpa_out,
+                      double* e_second_out, uint32_t flags);
+
 isdf_status isdf_destroy(isdf_ctx ctx);
 /* Message of the last failed call on ctx; with ctx == NULL, the message of the
  * last failed isdf_create or isdf_load on the calling thread ("null context"

@@ -83,8 +83,65 @@ template <int N> struct TwF {
   }
 };
 
+// cos and sin of 2 pi t / N in double, t = 0..N-1 (Taylor series at |x| <= pi)
+template <int N> struct TwD {
+  double c[N], s[N];
+  constexpr TwD() : c(), s() {
+    for (int t = 0; t < N; ++t) {
+      double x = 2.0 * kPiD * t / N;
+      if (x > kPiD) x -= 2.0 * kPiD;
+      c[t] = series_cos(x);
+      s[t] = series_sin(x);
+    }
+  }
+};
+
+// In-place DFT of a length-M line in registers with compile-time M and sign S:
+// x[k] <- sum_j x[j] exp(S 2 pi i j k / M).  Even M > 4 split into even and
+// odd halves (radix 2, recursively); other M summed directly; the twiddles
+// are compile-time constants.
+template <int M, int S>
+__host__ __device__ inline void dft_line(cplx (&x)[M]) {
+  constexpr TwD<M> tw{};
+  if constexpr (M == 1) {
+    return;
+  } else if constexpr (M % 2 == 0 && M > 4) {
+    constexpr int H = M / 2;
+    cplx e[H], o[H];
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+      e[j] = x[2 * j];
+      o[j] = x[2 * j + 1];
+    }
+    dft_line<H, S>(e);
+    dft_line<H, S>(o);
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+      const double c = tw.c[k], sn = S * tw.s[k];
+      const cplx t = cmk(o[k].x * c - o[k].y * sn, o[k].x * sn + o[k].y * c);
+      x[k] = cadd(e[k], t);
+      x[k + H] = csub(e[k], t);
+    }
+  } else {
+    cplx y[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      double re = x[0].x, im = x[0].y;
+#pragma unroll
+      for (int j = 1; j < M; ++j) {
+        const double c = tw.c[(j * k) % M], sn = S * tw.s[(j * k) % M];
+        re = fma(x[j].x, c, fma(-x[j].y, sn, re));
+        im = fma(x[j].y, c, fma(x[j].x, sn, im));
+      }
+      y[k] = cmk(re, im);
+    }
+#pragma unroll
+    for (int k = 0; k < M; ++k) x[k] = y[k];
+  }
+}
+
 // a * (c - i s) with compile-time c, s (the trivial factors fold away)
-__device__ inline float2 rot_f(float2 a, float c, float s) {
+__host__ __device__ inline float2 rot_f(float2 a, float c, float s) {
   if (c == 1.0f && s == 0.0f) return a;
   if (c == 0.0f && s == 1.0f) return make_float2(a.y, -a.x);
   if (c == -1.0f && s == 0.0f) return make_float2(-a.x, -a.y);
@@ -93,7 +150,7 @@ __device__ inline float2 rot_f(float2 a, float c, float s) {
 }
 
 template <int R>
-__device__ inline void small_dft_f(const float2 (&x)[R], float2 (&y)[R]) {
+__host__ __device__ inline void small_dft_f(const float2 (&x)[R], float2 (&y)[R]) {
   if constexpr (R == 2) {
     y[0] = make_float2(x[0].x + x[1].x, x[0].y + x[1].y);
     y[1] = make_float2(x[0].x - x[1].x, x[0].y - x[1].y);
@@ -125,12 +182,32 @@ __device__ inline void small_dft_f(const float2 (&x)[R], float2 (&y)[R]) {
 }
 
 // y[k] = sum_j x[j] exp(-2 pi i j k / R) for any compile-time R <= 16: the
-// butterflies of small_dft_f where it has them, else the direct sum with the
-// twiddles as compile-time constants (TwF).
+// butterflies of small_dft_f for R = 2, 4; even R split into even and odd
+// halves (radix 2, recursively); other R by the direct sum with the twiddles
+// as compile-time constants (TwF).
 template <int R>
-__device__ inline void dft_any_f(const float2 (&x)[R], float2 (&y)[R]) {
-  if constexpr (R <= 8) {
+__host__ __device__ inline void dft_any_f(const float2 (&x)[R], float2 (&y)[R]) {
+  if constexpr (R == 1) {
+    y[0] = x[0];
+  } else if constexpr (R == 2 || R == 4) {
     small_dft_f<R>(x, y);
+  } else if constexpr (R % 2 == 0) {
+    constexpr int H = R / 2;
+    constexpr TwF<R> tw{};
+    float2 e[H], o[H], fe[H], fo[H];
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+      e[j] = x[2 * j];
+      o[j] = x[2 * j + 1];
+    }
+    dft_any_f<H>(e, fe);
+    dft_any_f<H>(o, fo);
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+      const float2 t = rot_f(fo[k], tw.c[k], tw.s[k]);
+      y[k] = make_float2(fe[k].x + t.x, fe[k].y + t.y);
+      y[k + H] = make_float2(fe[k].x - t.x, fe[k].y - t.y);
+    }
   } else {
     constexpr TwF<R> tw{};
 #pragma unroll

@@ -282,8 +282,9 @@ hipError_t launch_p(int flags, const GemmDesc* descs, int ndesc, long long total
                        g, b, 0, s, descs, ndesc, total);                                           \
     break;
     // layouts used by the path: A_KM|B_KN, B_CONJ, A_KM|B_KN|B_CONJ, B_KN (the
-    // zeta route's Pi^+ eta) and B_KN|B_CONJ (P^k X^{k H} of the exchange)
-    CASE(2) CASE(3) CASE(8) CASE(10) CASE(11)
+    // zeta route's Pi^+ eta), B_KN|B_CONJ (P^k X^{k H} of the exchange) and
+    // A_KM|B_KN|A_CONJ (A^H A of the RPA determinant)
+    CASE(2) CASE(3) CASE(7) CASE(8) CASE(10) CASE(11)
     default: return hipErrorInvalidValue;
 #undef CASE
   }

@@ -616,6 +616,31 @@ void release_workspaces(isdf_ctx c) {
   for (Workspace* w : c->ws_pool) w->mem.release();
 }
 
+// Blocked right-looking Cholesky of nq Hermitian n x n matrices at once
+// (64-wide diagonal blocks in LDS, panel solves, FP64 MFMA trailing
+// updates), no pivoting: the factor in the lower triangle of A and, transposed,
+// in lt; flag[q] set where a pivot is not above rtol * max diagonal.
+void chol_blocked(Arena& ar, const cplx* in, cplx* A, cplx* lt, int* perm, int* rank, double* dmax, int* flag, int n,
+                  int nq, double rtol, hipStream_t s) {
+  const long long nn = (long long)n * n;
+  HIPCHK(bchol_setup_launch(in, A, perm, rank, dmax, flag, n, nq, s));
+  for (int jb = 0; jb < n; jb += CHOL_NB) {
+    HIPCHK(bchol_diag_launch(A, lt, dmax, flag, n, nq, jb, rtol, s));
+    HIPCHK(bchol_panel_launch(A, lt, flag, n, nq, jb, s));
+    const int rest = n - jb - CHOL_NB;
+    if (rest > 0) {
+      std::vector<NtDesc> d(1);
+      const cplx* L21 = A + (long long)(jb + CHOL_NB) * n + jb;
+      d[0] = mknt(L21, n, L21, n, A + (long long)(jb + CHOL_NB) * (n + 1), n, rest, rest, CHOL_NB);
+      d[0].batch = nq;
+      d[0].sA_bat = d[0].sB_bat = d[0].sC_bat = nn;
+      d[0].herm = 2;
+      d[0].epi = 4;
+      run_nt(ar, 0, 2, d, s);
+    }
+  }
+}
+
 void do_fit(isdf_ctx c, int prec) {
   hipStream_t s = c->stream;
   const int nk = c->nk, norb = c->norb, nip = c->nip;
@@ -678,25 +703,8 @@ void do_fit(isdf_ctx c, int prec) {
     // diagonal blocks in LDS, panel solves, FP64 MFMA trailing updates
     cplx* A = c->work2.as<cplx>();
     const double rtol = 1e-13;
-    HIPCHK(bchol_setup_launch(c->pi.as<cplx>(), A, c->perm.as<int>(), c->rank.as<int>(),
-                              c->dmax.as<double>(), c->cflag.as<int>(), nip, nh, c->aux));
-    for (int jb = 0; jb < nip; jb += CHOL_NB) {
-      HIPCHK(bchol_diag_launch(A, c->lt.as<cplx>(), c->dmax.as<double>(), c->cflag.as<int>(), nip, nh,
-                               jb, rtol, c->aux));
-      HIPCHK(bchol_panel_launch(A, c->lt.as<cplx>(), c->cflag.as<int>(), nip, nh, jb, c->aux));
-      const int rest = nip - jb - CHOL_NB;
-      if (rest > 0) {
-        std::vector<NtDesc> d(1);
-        const cplx* L21 = A + (long long)(jb + CHOL_NB) * nip + jb;
-        d[0] = mknt(L21, nip, L21, nip, A + (long long)(jb + CHOL_NB) * (nip + 1), nip, rest, rest,
-                    CHOL_NB);
-        d[0].batch = nh;
-        d[0].sA_bat = d[0].sB_bat = d[0].sC_bat = nip2(c);
-        d[0].herm = 2;
-        d[0].epi = 4;
-        run_nt(c->arena_aux, 0, 2, d, c->aux);
-      }
-    }
+    chol_blocked(c->arena_aux, c->pi.as<cplx>(), A, c->lt.as<cplx>(), c->perm.as<int>(), c->rank.as<int>(),
+                 c->dmax.as<double>(), c->cflag.as<int>(), nip, nh, rtol, c->aux);
     // matrices whose pivots fell below the rank tolerance (singular metrics)
     // are refactored with diagonal pivoting
     std::vector<int> fl(nh, 0);
@@ -2574,6 +2582,321 @@ isdf_status isdf_hf_jk(isdf_ctx ctx, const void* dm, void* j_out, void* k_out, u
       if (k_out) HIPCHK(hipMemcpyAsync(k_out, K, mb, hipMemcpyDeviceToHost, s));
     }
     HIPCHK(hipStreamSynchronize(s));
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->timer.collect(&c->totals);
+  });
+}
+
+// The polarisabilities at one tau (eqs. (13)-(15)): Go^k = Yo e^{tau (e_i - mu)}
+// Yo^H and Gv^k = Yv e^{-tau (e_a - mu)} Yv^H into bo, bv (Hermitian FP64
+// MFMA products of the scaled orbitals at the points), then chi^q into bv and
+// chit^q into bo, one q per class in class order, by the convolution over k.
+static void tau_polarisabilities(isdf_ctx c, const cplx* y, const double* ed, int n_mo, int n_occ, double tau,
+                                 double mu, cplx* yo, cplx* yv, cplx* bo, cplx* bv) {
+  hipStream_t s = c->stream;
+  const int nk = c->nk, nip = c->nip, nvir = n_mo - n_occ;
+  const long long nn = (long long)nip * nip;
+  c->timer.begin("mp2_green", s);
+  HIPCHK(mp2_scale_launch(y, ed, nk, nip, n_mo, n_occ, tau, mu, yo, yv, s));
+  for (int which = 0; which < 2; ++which) {
+    const int kk = which == 0 ? n_occ : nvir;
+    void* src = which == 0 ? (void*)yo : (void*)yv;
+    std::vector<NtDesc> d(1);
+    d[0] = mknt(src, kk, src, kk, which == 0 ? (void*)bo : (void*)bv, nip, nip, nip, kk);
+    d[0].batch = nk;
+    d[0].sA_bat = d[0].sB_bat = (long long)nip * kk;
+    d[0].sC_bat = nn;
+    d[0].herm = 1;
+    run_nt(c->arena, 0, 2, d, s);
+  }
+  c->timer.end("mp2_green", s);
+  c->timer.begin("mp2_pconv", s);
+  PconvArgs a;
+  memset(&a, 0, sizeof(a));
+  a.gv = bv;
+  a.go = bo;
+  a.n_elem = nn;
+  a.m1 = c->m[0];
+  a.m2 = c->m[1];
+  a.m3 = c->m[2];
+  a.scale = 1.0 / ((double)nk * nk);
+  a.qslot = c->qmap.as<int>();
+  HIPCHK(pconv_launch(a, s));
+  c->timer.end("mp2_pconv", s);
+}
+
+// Shared checks of the correlation-energy calls; returns the chemical
+// potential between the occupied and virtual energies.
+static double check_mo(isdf_ctx c, const void* mo_coeff, const double* mo_energy, int n_mo, int n_occ, int n_tau,
+                       const double* tau, const double* weight, uint32_t flags, const char* name) {
+  // weight: the time weights (MP2) or the time points again (dRPA, whose
+  // transform is checked by the caller)
+  if (!mo_coeff || !mo_energy || !tau || !weight) throw Fail{ISDF_E_INVALID, "null argument"};
+  if (n_mo < 2 || n_mo > c->norb || n_occ < 1 || n_occ >= n_mo)
+    throw Fail{ISDF_E_INVALID, "need 1 <= n_occ < n_mo <= n_orb"};
+  if (n_tau < 1 || n_tau > 4096) throw Fail{ISDF_E_INVALID, "n_tau must be 1..4096"};
+  for (int n = 0; n < n_tau; ++n)
+    if (!(tau[n] >= 0.0) || !std::isfinite(tau[n]) || !std::isfinite(weight[n]))
+      throw Fail{ISDF_E_INVALID, "tau must be finite and >= 0, weights finite"};
+  if (!c->kernel_ready) throw Fail{ISDF_E_STATE, std::string("isdf_coulomb_kernel must run before ") + name};
+  if (c->nk > 2048)
+    throw Fail{ISDF_E_INVALID, "the polarisability convolution holds two k columns in LDS: at most 2048 k points"};
+  double homo = -INFINITY, lumo = INFINITY;
+  for (int k = 0; k < c->nk; ++k)
+    for (int p = 0; p < n_mo; ++p) {
+      const double e = mo_energy[(long long)k * n_mo + p];
+      if (!std::isfinite(e)) throw Fail{ISDF_E_INVALID, "non-finite orbital energy"};
+      if (p < n_occ) homo = std::max(homo, e);
+      else lumo = std::min(lumo, e);
+    }
+  if (!(homo < lumo)) throw Fail{ISDF_E_INVALID, "occupied and virtual energies overlap (no gap)"};
+  if (flags & 0x1u) {
+    hipPointerAttribute_t at;
+    if (hipPointerGetAttributes(&at, mo_coeff) != hipSuccess || at.type != hipMemoryTypeDevice) {
+      (void)hipGetLastError();
+      throw Fail{ISDF_E_INVALID, "device-flagged coefficients must be device memory"};
+    }
+  }
+  return 0.5 * (homo + lumo);
+}
+
+isdf_status isdf_sos_mp2(isdf_ctx ctx, const void* mo_coeff, const double* mo_energy, int32_t n_mo, int32_t n_occ,
+                         int32_t n_tau, const double* tau, const double* weight, double* integrand_out,
+                         double* class_out, double* e_os_out, uint32_t flags) {
+  return guarded(ctx, [&] {
+    isdf_ctx c = ctx;
+    if (!e_os_out) throw Fail{ISDF_E_INVALID, "null argument"};
+    // chemical potential between the occupied and virtual energies (it cancels)
+    const double mu = check_mo(c, mo_coeff, mo_energy, n_mo, n_occ, n_tau, tau, weight, flags, "isdf_sos_mp2");
+    const int nk = c->nk, norb = c->norb, nip = c->nip, nh = c->nh, nvir = n_mo - n_occ;
+    const bool dev = (flags & ISDF_MP2_DEVICE) != 0;
+    hipStream_t s = c->stream;
+    const long long nn = (long long)nip * nip;
+    const int nblk = std::max(1, std::min(64, (2048 + nh - 1) / nh));
+    DevBuf cd, ed, y, yo, yv, bo, bv, t1, part;
+    const cplx* C = (const cplx*)mo_coeff;
+    if (!dev) {
+      alloc_reclaim(c, cd, sizeof(cplx) * (size_t)nk * norb * n_mo);
+      HIPCHK(hipMemcpyAsync(cd.p, mo_coeff, sizeof(cplx) * (size_t)nk * norb * n_mo, hipMemcpyHostToDevice, s));
+      C = cd.as<cplx>();
+    }
+    alloc_reclaim(c, ed, sizeof(double) * (size_t)nk * n_mo);
+    HIPCHK(hipMemcpyAsync(ed.p, mo_energy, sizeof(double) * (size_t)nk * n_mo, hipMemcpyHostToDevice, s));
+    alloc_reclaim(c, y, sizeof(cplx) * (size_t)nk * nip * n_mo);
+    alloc_reclaim(c, yo, sizeof(cplx) * (size_t)nk * nip * n_occ);
+    alloc_reclaim(c, yv, sizeof(cplx) * (size_t)nk * nip * nvir);
+    alloc_reclaim(c, bo, sizeof(cplx) * (size_t)nk * nn);
+    alloc_reclaim(c, bv, sizeof(cplx) * (size_t)nk * nn);
+    alloc_reclaim(c, t1, sizeof(cplx) * (size_t)nh * nn);
+    alloc_reclaim(c, part, sizeof(cplx) * (size_t)nh * nblk);
+    const cplx* xt = c->xt.as<cplx>();
+    // Y^k = X^k C^k (canonical orbitals at the interpolation points)
+    c->arena.reset(s);
+    c->arena.reserve((size_t)1 << 20);
+    {
+      std::vector<GemmDesc> d(1);
+      d[0] = mkdesc(xt, nip, C, n_mo, y.as<cplx>(), n_mo, nip, n_mo, norb);
+      d[0].batch = nk;
+      d[0].sA_bat = (long long)norb * nip;
+      d[0].sB_bat = (long long)norb * n_mo;
+      d[0].sC_bat = (long long)nip * n_mo;
+      run_gemm(c->arena, 0, GEMM_A_KM | GEMM_B_KN, d, s);
+    }
+    std::vector<cplx> ph((size_t)nh * nblk);
+    double e_os = 0.0;
+    for (int n = 0; n < n_tau; ++n) {
+      c->arena.reset(s);
+      c->arena.reserve((size_t)1 << 20);
+      tau_polarisabilities(c, y.as<cplx>(), ed.as<double>(), n_mo, n_occ, tau[n], mu, yo.as<cplx>(),
+                           yv.as<cplx>(), bo.as<cplx>(), bv.as<cplx>());
+      // T1 = W chi, T2 = chit W (FP64 MFMA), tr[W chi W chit] = sum T1 o conj(T2)
+      c->timer.begin("mp2_wchi", s);
+      {
+        std::vector<GemmDesc> d(1);
+        d[0] = mkdesc(c->w.as<cplx>(), nip, bv.as<cplx>(), nip, t1.as<cplx>(), nip, nip, nip, nip);
+        d[0].batch = nh;
+        d[0].sA_bat = d[0].sB_bat = d[0].sC_bat = nn;
+        run_gemm(c->arena, 0, GEMM_B_KN, d, s);
+        std::vector<GemmDesc> d2(1);
+        d2[0] = mkdesc(bo.as<cplx>(), nip, c->w.as<cplx>(), nip, bv.as<cplx>(), nip, nip, nip, nip);
+        d2[0].batch = nh;
+        d2[0].sA_bat = d2[0].sB_bat = d2[0].sC_bat = nn;
+        run_gemm(c->arena, 0, GEMM_B_KN, d2, s);
+      }
+      c->timer.end("mp2_wchi", s);
+      c->timer.begin("mp2_trace", s);
+      HIPCHK(mp2_dot_launch(t1.as<cplx>(), bv.as<cplx>(), nn, nh, nblk, part.as<cplx>(), s));
+      c->timer.end("mp2_trace", s);
+      HIPCHK(hipMemcpyAsync(ph.data(), part.p, sizeof(cplx) * ph.size(), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      // classes {q, -q} with q != -q stand for two equal-real-part terms
+      double f = 0.0;
+      for (int h = 0; h < nh; ++h) {
+        double re = 0.0;
+        for (int b = 0; b < nblk; ++b) re += ph[(size_t)h * nblk + b].x;
+        const double term = (c->hself_h[h] ? 1.0 : 2.0) * re / nk;
+        if (class_out) class_out[(size_t)n * nh + h] = term;
+        f += term;
+      }
+      if (integrand_out) integrand_out[n] = f;
+      e_os -= weight[n] * f;
+    }
+    *e_os_out = e_os;
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->timer.collect(&c->totals);
+  });
+}
+
+isdf_status isdf_drpa(isdf_ctx ctx, const void* mo_coeff, const double* mo_energy, int32_t n_mo, int32_t n_occ,
+                      int32_t n_tau, const double* tau, int32_t n_omega, const double* omega_weight,
+                      const void* transform, double* integrand_out, double* class_out, double* e_drpa_out,
+                      double* e_second_out, uint32_t flags) {
+  return guarded(ctx, [&] {
+    isdf_ctx c = ctx;
+    if (!e_drpa_out || !omega_weight || !transform) throw Fail{ISDF_E_INVALID, "null argument"};
+    if (n_omega < 1 || n_omega > 1024) throw Fail{ISDF_E_INVALID, "n_omega must be 1..1024"};
+    const cplx* gam = (const cplx*)transform;
+    for (int m = 0; m < n_omega; ++m) {
+      if (!std::isfinite(omega_weight[m])) throw Fail{ISDF_E_INVALID, "frequency weights must be finite"};
+      for (int n = 0; n < std::max(n_tau, 0); ++n) {
+        const cplx g = gam[(size_t)m * n_tau + n];
+        if (!std::isfinite(g.x) || !std::isfinite(g.y)) throw Fail{ISDF_E_INVALID, "non-finite transform entry"};
+      }
+    }
+    const double mu = check_mo(c, mo_coeff, mo_energy, n_mo, n_occ, n_tau, tau, tau, flags, "isdf_drpa");
+    const int nk = c->nk, norb = c->norb, nip = c->nip, nh = c->nh, nvir = n_mo - n_occ;
+    const bool dev = (flags & ISDF_DRPA_DEVICE) != 0;
+    hipStream_t s = c->stream;
+    const long long nn = (long long)nip * nip, hn = (long long)nh * nn;
+    const int ntile = drpa_trace2_tiles(nip);
+    DevBuf cd, ed, y, yo, yv, bo, bv, pm, gm, lt, perm, rank, dmax, flag, tr, tr2, ld, ph, chiw;
+    const cplx* C = (const cplx*)mo_coeff;
+    if (!dev) {
+      alloc_reclaim(c, cd, sizeof(cplx) * (size_t)nk * norb * n_mo);
+      HIPCHK(hipMemcpyAsync(cd.p, mo_coeff, sizeof(cplx) * (size_t)nk * norb * n_mo, hipMemcpyHostToDevice, s));
+      C = cd.as<cplx>();
+    }
+    alloc_reclaim(c, ed, sizeof(double) * (size_t)nk * n_mo);
+    HIPCHK(hipMemcpyAsync(ed.p, mo_energy, sizeof(double) * (size_t)nk * n_mo, hipMemcpyHostToDevice, s));
+    alloc_reclaim(c, y, sizeof(cplx) * (size_t)nk * nip * n_mo);
+    alloc_reclaim(c, yo, sizeof(cplx) * (size_t)nk * nip * n_occ);
+    alloc_reclaim(c, yv, sizeof(cplx) * (size_t)nk * nip * nvir);
+    alloc_reclaim(c, bo, sizeof(cplx) * (size_t)nk * nn);
+    alloc_reclaim(c, bv, sizeof(cplx) * (size_t)nk * nn);
+    alloc_reclaim(c, pm, sizeof(cplx) * (size_t)hn);
+    alloc_reclaim(c, gm, sizeof(cplx) * (size_t)hn);
+    alloc_reclaim(c, lt, sizeof(cplx) * (size_t)hn);
+    alloc_reclaim(c, perm, sizeof(int) * (size_t)nh * nip);
+    alloc_reclaim(c, rank, sizeof(int) * (size_t)nh);
+    alloc_reclaim(c, dmax, sizeof(double) * (size_t)nh);
+    alloc_reclaim(c, flag, sizeof(int) * (size_t)nh);
+    alloc_reclaim(c, tr, sizeof(cplx) * (size_t)nh);
+    alloc_reclaim(c, tr2, sizeof(cplx) * (size_t)nh * ntile);
+    alloc_reclaim(c, ld, sizeof(double) * (size_t)nh);
+    alloc_reclaim(c, ph, sizeof(cplx) * (size_t)n_omega);
+    // frequency polarisabilities of as many frequencies at once as fit in 90 %
+    // of the free device memory (the time loop runs once per batch)
+    size_t fr = 0, tot = 0;
+    HIPCHK(hipMemGetInfo(&fr, &tot));
+    const long long per_w = hn * (long long)sizeof(cplx);
+    int nbw = (int)std::min<long long>(n_omega, (long long)(0.9 * (double)fr) / per_w);
+    if (nbw < 1) {
+      HIPCHK(hipStreamSynchronize(s));
+      c->sync_ws.mem.release();
+      HIPCHK(hipMemGetInfo(&fr, &tot));
+      nbw = (int)std::min<long long>(n_omega, (long long)(0.9 * (double)fr) / per_w);
+    }
+    if (nbw < 1) throw Fail{ISDF_E_NOMEM, "no room for one frequency of polarisabilities"};
+    alloc_reclaim(c, chiw, (size_t)nbw * per_w);
+    const cplx* xt = c->xt.as<cplx>();
+    c->arena.reset(s);
+    c->arena.reserve((size_t)1 << 20);
+    {
+      std::vector<GemmDesc> d(1);
+      d[0] = mkdesc(xt, nip, C, n_mo, y.as<cplx>(), n_mo, nip, n_mo, norb);
+      d[0].batch = nk;
+      d[0].sA_bat = (long long)norb * nip;
+      d[0].sB_bat = (long long)norb * n_mo;
+      d[0].sC_bat = (long long)nip * n_mo;
+      run_gemm(c->arena, 0, GEMM_A_KM | GEMM_B_KN, d, s);
+    }
+    std::vector<cplx> h_tr(nh), h_tr2((size_t)nh * ntile), h_ph(nbw);
+    std::vector<double> h_ld(nh);
+    double e_rpa = 0.0, e_2 = 0.0;
+    for (int m0 = 0; m0 < n_omega; m0 += nbw) {
+      const int nb = std::min(nbw, n_omega - m0);
+      // chi^q(iw_m) = -sum_n tw_n [exp(i w_m tau_n) chi^q(tau_n) + exp(-i w_m tau_n) chit^q(tau_n)]
+      HIPCHK(zero_launch(chiw.as<cplx>(), (long long)nb * hn, s));
+      for (int n = 0; n < n_tau; ++n) {
+        c->arena.reset(s);
+        c->arena.reserve((size_t)1 << 20);
+        tau_polarisabilities(c, y.as<cplx>(), ed.as<double>(), n_mo, n_occ, tau[n], mu, yo.as<cplx>(),
+                             yv.as<cplx>(), bo.as<cplx>(), bv.as<cplx>());
+        for (int m = 0; m < nb; ++m) h_ph[m] = gam[(size_t)(m0 + m) * n_tau + n];
+        HIPCHK(hipMemcpyAsync(ph.p, h_ph.data(), sizeof(cplx) * nb, hipMemcpyHostToDevice, s));
+        c->timer.begin("drpa_accum", s);
+        HIPCHK(drpa_accum_launch(bv.as<cplx>(), bo.as<cplx>(), hn, ph.as<cplx>(), nb, chiw.as<cplx>(), s));
+        c->timer.end("drpa_accum", s);
+        HIPCHK(hipStreamSynchronize(s));   // h_ph is reused by the next tau
+      }
+      for (int m = 0; m < nb; ++m) {
+        c->arena.reset(s);
+        c->arena.reserve((size_t)1 << 20);
+        cplx* chi = chiw.as<cplx>() + (long long)m * hn;
+        // P = chi W; tr P, tr P^2; A = 1 - P; G = A^H A = L L^H; ln|det A|^2 = ln det G
+        c->timer.begin("drpa_p", s);
+        {
+          std::vector<GemmDesc> d(1);
+          d[0] = mkdesc(chi, nip, c->w.as<cplx>(), nip, pm.as<cplx>(), nip, nip, nip, nip);
+          d[0].batch = nh;
+          d[0].sA_bat = d[0].sB_bat = d[0].sC_bat = nn;
+          run_gemm(c->arena, 0, GEMM_B_KN, d, s);
+        }
+        HIPCHK(drpa_trace_launch(pm.as<cplx>(), nip, nh, tr.as<cplx>(), s));
+        HIPCHK(drpa_trace2_launch(pm.as<cplx>(), nip, nh, tr2.as<cplx>(), s));
+        HIPCHK(drpa_one_minus_launch(pm.as<cplx>(), nip, nh, s));
+        c->timer.end("drpa_p", s);
+        c->timer.begin("drpa_logdet", s);
+        {
+          std::vector<GemmDesc> d(1);
+          d[0] = mkdesc(pm.as<cplx>(), nip, pm.as<cplx>(), nip, gm.as<cplx>(), nip, nip, nip, nip);
+          d[0].batch = nh;
+          d[0].sA_bat = d[0].sB_bat = d[0].sC_bat = nn;
+          d[0].herm = 1;
+          run_gemm(c->arena, 0, GEMM_A_KM | GEMM_B_KN | GEMM_A_CONJ, d, s);
+        }
+        chol_blocked(c->arena, gm.as<cplx>(), pm.as<cplx>(), lt.as<cplx>(), perm.as<int>(), rank.as<int>(),
+                     dmax.as<double>(), flag.as<int>(), nip, nh, 0.0, s);
+        HIPCHK(drpa_logdet_launch(pm.as<cplx>(), flag.as<int>(), nip, nh, ld.as<double>(), s));
+        c->timer.end("drpa_logdet", s);
+        HIPCHK(hipMemcpyAsync(h_tr.data(), tr.p, sizeof(cplx) * nh, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(h_tr2.data(), tr2.p, sizeof(cplx) * h_tr2.size(), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(h_ld.data(), ld.p, sizeof(double) * nh, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        // per class: Re ln det(1 - P) + Re tr P and -1/2 Re tr P^2; a class with
+        // q != -q stands for two equal real parts
+        double f = 0.0, f2 = 0.0;
+        for (int h = 0; h < nh; ++h) {
+          if (!std::isfinite(h_ld[h]))
+            throw Fail{ISDF_E_NUMERIC, "1 - chi W singular at frequency point " + std::to_string(m0 + m) +
+                                           ", q = " + std::to_string(c->hq_h[h])};
+          double t2 = 0.0;
+          for (int t = 0; t < ntile; ++t) t2 += h_tr2[(size_t)h * ntile + t].x;
+          const double wt = c->hself_h[h] ? 1.0 : 2.0;
+          const double term = wt * (0.5 * h_ld[h] + h_tr[h].x);
+          if (class_out) class_out[(size_t)(m0 + m) * nh + h] = term / (M_PI * nk);
+          f += term;
+          f2 += wt * (-0.5 * t2);
+        }
+        f /= M_PI * nk;
+        f2 /= M_PI * nk;
+        if (integrand_out) integrand_out[m0 + m] = f;
+        e_rpa += omega_weight[m0 + m] * f;
+        e_2 += omega_weight[m0 + m] * f2;
+      }
+    }
+    *e_drpa_out = e_rpa;
+    if (e_second_out) *e_second_out = e_2;
     std::lock_guard<std::mutex> lk(c->mu);
     c->timer.collect(&c->totals);
   });

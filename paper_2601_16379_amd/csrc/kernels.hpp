@@ -142,6 +142,20 @@ struct XconvArgs {
 };
 hipError_t xconv_launch(const XconvArgs& a, hipStream_t s);
 
+// Polarisabilities of the opposite-spin MP2 energy, in place over gv, go
+// [N_k][n_elem]: for every q with qslot[q] >= 0 (device table),
+//   gv[qslot[q]][e] <- scale * N_k * sum_k gv[k][e] conj(go[k+q][e])
+//   go[qslot[q]][e] <- scale * N_k * sum_k go[k][e] conj(gv[k+q][e])
+struct PconvArgs {
+  cplx* gv;
+  cplx* go;
+  long long n_elem;
+  int m1, m2, m3;
+  double scale;
+  const int* qslot;
+};
+hipError_t pconv_launch(const PconvArgs& a, hipStream_t s);
+
 // Fragment pair transform (eq. (20)):
 //   R[Q][pair_off_f + p*nf + q][I] =
 //     scale * sum_R exp(-2 pi i jQ.jR/m) conj(psi[R][col_f + p][I]) psi[R][col_f + q][I]
@@ -286,3 +300,30 @@ hipError_t hf_diag_sum_launch(const cplx* rho, int nk, int nip, cplx* n, hipStre
 hipError_t hf_matvec_launch(const cplx* w, int conj, const cplx* n, int nip, double scale, cplx* v, hipStream_t s);
 // out[r][I] = v[I] xt[r][I] for rows r < rows
 hipError_t hf_scale_launch(const cplx* xt, const cplx* v, long long rows, int nip, cplx* out, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// opposite-spin MP2 helpers
+// ---------------------------------------------------------------------------
+// y [nk][nip][nmo] -> yo [nk][nip][nocc] (x exp(tau (e - mu)/2)) and
+// yv [nk][nip][nmo - nocc] (x exp(-tau (e - mu)/2)); e [nk][nmo]
+hipError_t mp2_scale_launch(const cplx* y, const double* e, int nk, int nip, int nmo, int nocc, double tau, double mu,
+                            cplx* yo, cplx* yv, hipStream_t s);
+// part[h][b] = partial sums over nblk chunks of sum_i t1[h][i] conj(t2[h][i])
+hipError_t mp2_dot_launch(const cplx* t1, const cplx* t2, long long n_elem, int nclass, int nblk, cplx* part,
+                          hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// direct RPA helpers
+// ---------------------------------------------------------------------------
+// out[m][e] -= ph[m] chi[e] + conj(ph[m]) chit[e] for m < nw (ph device)
+hipError_t drpa_accum_launch(const cplx* chi, const cplx* chit, long long n_elem, const cplx* ph, int nw, cplx* out,
+                             hipStream_t s);
+// a[h] <- 1 - a[h] for nmat n x n matrices
+hipError_t drpa_one_minus_launch(cplx* a, int n, int nmat, hipStream_t s);
+// tr[h] = trace of a[h]
+hipError_t drpa_trace_launch(const cplx* a, int n, int nmat, cplx* tr, hipStream_t s);
+// part[h][t] (drpa_trace2_tiles(n) per matrix): partial sums of tr(a[h] a[h])
+int drpa_trace2_tiles(int n);
+hipError_t drpa_trace2_launch(const cplx* a, int n, int nmat, cplx* part, hipStream_t s);
+// ld[h] = 2 sum_j ln a[h][j][j] (Cholesky factor in the lower triangle), NaN where flag[h]
+hipError_t drpa_logdet_launch(const cplx* a, const int* flag, int n, int nmat, double* ld, hipStream_t s);

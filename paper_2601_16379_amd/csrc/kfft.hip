@@ -14,32 +14,11 @@ namespace {
 
 constexpr int MAXM = 16;
 
-// In-place 3-D DFT over the mesh for every element column of buf[k][etile]:
-// buf[k][e] <- sum_j exp(sign * 2 pi i sum_d j_d k_d / m_d) buf[j][e].
-// tw[ax][t] = exp(2 pi i t / m_ax), filled by init_twiddles.
-__device__ void init_twiddles(cplx (*tw)[MAXM], int m1, int m2, int m3) {
-  const int ms[3] = {m1, m2, m3};
-  if (threadIdx.x < 3 * MAXM) {
-    const int ax = threadIdx.x / MAXM, t = threadIdx.x % MAXM;
-    if (t < ms[ax]) tw[ax][t] = cexpipi(2.0 * (double)t / (double)ms[ax]);
-  }
-}
-
 // Length-M DFT of lines p[j * estride], j < M, for the lines `line` owned by
-// this thread; M is a compile-time constant so the loops unroll and the
-// twiddle indices (j t mod M) are constants; twiddles live in registers for
-// M <= 8 and are read from the LDS table (one broadcast read) above.
-template <int M>
-__device__ void axis_dft(cplx* buf, const cplx* twa, int nlines, int eshift, int ax, int m2, int m3,
-                         int sign) {
-  constexpr int MW = M <= 8 ? M : 1;
-  cplx w[MW];
-#pragma unroll
-  for (int t = 0; t < MW; ++t) {
-    w[t] = twa[t];
-    if (sign < 0) w[t].y = -w[t].y;
-  }
-  const double sy = sign < 0 ? -1.0 : 1.0;
+// this thread: each line in registers, transformed by dft_line with
+// compile-time length, sign and twiddles.
+template <int M, int S>
+__device__ void axis_dft_s(cplx* buf, int nlines, int eshift, int ax, int m2, int m3) {
   const int etile = 1 << eshift;
 #pragma unroll 1
   for (int line = threadIdx.x; line < nlines; line += blockDim.x) {
@@ -54,32 +33,26 @@ __device__ void axis_dft(cplx* buf, const cplx* twa, int nlines, int eshift, int
     cplx x[M];
 #pragma unroll
     for (int j = 0; j < M; ++j) x[j] = p[j * estride];
+    dft_line<M, S>(x);
 #pragma unroll
-    for (int t = 0; t < M; ++t) {
-      cplx acc = x[0];
-#pragma unroll
-      for (int j = 1; j < M; ++j) {
-        if constexpr (M <= 8) {
-          cfma(acc, x[j], w[(j * t) % M]);
-        } else {
-          const cplx wt = twa[(j * t) % M];
-          cfma(acc, x[j], cmk(wt.x, sy * wt.y));
-        }
-      }
-      p[t * estride] = acc;
-    }
+    for (int t = 0; t < M; ++t) p[t * estride] = x[t];
   }
+}
+
+template <int M>
+__device__ void axis_dft(cplx* buf, int nlines, int eshift, int ax, int m2, int m3, int sign) {
+  if (sign > 0) axis_dft_s<M, 1>(buf, nlines, eshift, ax, m2, m3);
+  else axis_dft_s<M, -1>(buf, nlines, eshift, ax, m2, m3);
 }
 
 // In-place 3-D DFT over the mesh for every element column of buf[k][etile]:
 // buf[k][e] <- sum_j exp(sign * 2 pi i sum_d j_d k_d / m_d) buf[j][e].
-// etile is a power of two; tw[ax][t] = exp(2 pi i t / m_ax).
+// etile is a power of two.
 // MAXA: largest axis length of the mesh (4, 8 or 16): only the axis
 // transforms up to it are instantiated, which keeps the register count of
 // the kernels (and so their occupancy) set by the mesh actually used.
 template <int MAXA>
-__device__ void mesh_dft(cplx* buf, const cplx (*tw)[MAXM], int etile, int m1, int m2, int m3,
-                         int sign) {
+__device__ void mesh_dft(cplx* buf, int etile, int m1, int m2, int m3, int sign) {
   const int eshift = __builtin_ctz(etile);
   const int nk = m1 * m2 * m3;
   const int ms[3] = {m1, m2, m3};
@@ -89,7 +62,7 @@ __device__ void mesh_dft(cplx* buf, const cplx (*tw)[MAXM], int etile, int m1, i
     const int nlines = (nk / m) << eshift;
     switch (m) {
 #define AXIS_CASE(M) \
-  case M: if constexpr (M <= MAXA) axis_dft<M>(buf, tw[ax], nlines, eshift, ax, m2, m3, sign); break;
+  case M: if constexpr (M <= MAXA) axis_dft<M>(buf, nlines, eshift, ax, m2, m3, sign); break;
       AXIS_CASE(2) AXIS_CASE(3) AXIS_CASE(4) AXIS_CASE(5) AXIS_CASE(6) AXIS_CASE(7) AXIS_CASE(8)
       AXIS_CASE(9) AXIS_CASE(10) AXIS_CASE(11) AXIS_CASE(12) AXIS_CASE(13) AXIS_CASE(14)
       AXIS_CASE(15) AXIS_CASE(16)
@@ -104,8 +77,6 @@ template <int MAXA>
 __global__ __launch_bounds__(256) void kconv_kernel(KconvArgs a, int etile) {
   // blockDim.x == 256; etile a power of two
   extern __shared__ cplx buf[];
-  __shared__ cplx tw[3][MAXM];
-  init_twiddles(tw, a.m1, a.m2, a.m3);
   const int eshift = __builtin_ctz(etile);
   const int nk = a.m1 * a.m2 * a.m3;
   const long long e0 = (long long)blockIdx.x * etile;
@@ -147,15 +118,15 @@ __global__ __launch_bounds__(256) void kconv_kernel(KconvArgs a, int etile) {
   __syncthreads();
   if (a.mode == 0) {
     // T^R = sum_k exp(+i k.R) T^k ;  Z^R = |T^R|^2 ;  out^q = scale * sum_R exp(+i q.R) Z^R
-    mesh_dft<MAXA>(buf, tw, etile, a.m1, a.m2, a.m3, +1);
+    mesh_dft<MAXA>(buf, etile, a.m1, a.m2, a.m3, +1);
     for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
       cplx v = buf[idx];
       buf[idx] = cmk(v.x * v.x + v.y * v.y, 0.0);
     }
     __syncthreads();
-    mesh_dft<MAXA>(buf, tw, etile, a.m1, a.m2, a.m3, +1);
+    mesh_dft<MAXA>(buf, etile, a.m1, a.m2, a.m3, +1);
   } else {
-    mesh_dft<MAXA>(buf, tw, etile, a.m1, a.m2, a.m3, a.sign);
+    mesh_dft<MAXA>(buf, etile, a.m1, a.m2, a.m3, a.sign);
   }
   for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
     const int q0 = idx >> eshift, e = idx & (etile - 1);
@@ -185,8 +156,6 @@ __global__ __launch_bounds__(256) void kconv_kernel(KconvArgs a, int etile) {
 template <int MAXA>
 __global__ __launch_bounds__(256) void xconv_kernel(XconvArgs a, int etile) {
   extern __shared__ cplx xbuf[];
-  __shared__ cplx tw[3][MAXM];
-  init_twiddles(tw, a.m1, a.m2, a.m3);
   const int eshift = __builtin_ctz(etile);
   const int nk = a.m1 * a.m2 * a.m3;
   const int total = nk << eshift;
@@ -208,14 +177,65 @@ __global__ __launch_bounds__(256) void xconv_kernel(XconvArgs a, int etile) {
     bw[idx] = w;
   }
   __syncthreads();
-  mesh_dft<MAXA>(br, tw, etile, a.m1, a.m2, a.m3, -1);
-  mesh_dft<MAXA>(bw, tw, etile, a.m1, a.m2, a.m3, +1);
+  mesh_dft<MAXA>(br, etile, a.m1, a.m2, a.m3, -1);
+  mesh_dft<MAXA>(bw, etile, a.m1, a.m2, a.m3, +1);
   for (int idx = threadIdx.x; idx < total; idx += blockDim.x) br[idx] = cmul(br[idx], bw[idx]);
   __syncthreads();
-  mesh_dft<MAXA>(br, tw, etile, a.m1, a.m2, a.m3, +1);
+  mesh_dft<MAXA>(br, etile, a.m1, a.m2, a.m3, +1);
   for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
     const int k = idx >> eshift, e = idx & (etile - 1);
     if (e < ne) a.rho[(long long)k * a.n_elem + e0 + e] = cscale(br[idx], a.scale);
+  }
+}
+
+// The two polarisabilities of the opposite-spin MP2 energy, in place:
+//   A(R) = sum_k exp(+i k.R) gv[k][e],  B(R) = sum_k exp(+i k.R) go[k][e],
+//   Z(R) = A(R) conj(B(R)),
+//   chi^q  = scale * sum_R exp(+i q.R) Z(R)        -> gv[qslot[q]][e]
+//   chit^q = scale * sum_R exp(+i q.R) conj(Z(R))  -> go[qslot[q]][e]
+// (with scale N_k^-2: chi^q = N_k^-1 sum_k gv^k conj(go^{k+q}), chit^q the
+// same with gv and go exchanged), for the q with qslot[q] >= 0.  Both mesh
+// columns of a tile of `etile` elements sit in LDS; a workgroup reads and
+// writes only its own elements.
+template <int MAXA>
+__global__ __launch_bounds__(256) void pconv_kernel(PconvArgs a, int etile) {
+  extern __shared__ cplx pbuf[];
+  const int eshift = __builtin_ctz(etile);
+  const int nk = a.m1 * a.m2 * a.m3;
+  const int total = nk << eshift;
+  cplx* ba = pbuf;
+  cplx* bb = pbuf + total;
+  const long long e0 = (long long)blockIdx.x * etile;
+  const long long rem = a.n_elem - e0;
+  const int ne = rem < etile ? (int)rem : etile;
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    const int k = idx >> eshift, e = idx & (etile - 1);
+    cplx v = cmk(0.0, 0.0), o = cmk(0.0, 0.0);
+    if (e < ne) {
+      v = a.gv[(long long)k * a.n_elem + e0 + e];
+      o = a.go[(long long)k * a.n_elem + e0 + e];
+    }
+    ba[idx] = v;
+    bb[idx] = o;
+  }
+  __syncthreads();
+  mesh_dft<MAXA>(ba, etile, a.m1, a.m2, a.m3, +1);
+  mesh_dft<MAXA>(bb, etile, a.m1, a.m2, a.m3, +1);
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    const cplx z = cmulc(ba[idx], bb[idx]);
+    ba[idx] = z;
+    bb[idx] = cmk(z.x, -z.y);
+  }
+  __syncthreads();
+  mesh_dft<MAXA>(ba, etile, a.m1, a.m2, a.m3, +1);
+  mesh_dft<MAXA>(bb, etile, a.m1, a.m2, a.m3, +1);
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    const int q = idx >> eshift, e = idx & (etile - 1);
+    const int slot = a.qslot[q];
+    if (slot >= 0 && e < ne) {
+      a.gv[(long long)slot * a.n_elem + e0 + e] = cscale(ba[idx], a.scale);
+      a.go[(long long)slot * a.n_elem + e0 + e] = cscale(bb[idx], a.scale);
+    }
   }
 }
 
@@ -225,8 +245,6 @@ __global__ __launch_bounds__(256) void xconv_kernel(XconvArgs a, int etile) {
 template <int MAXA>
 __global__ __launch_bounds__(256) void pair_kernel(PairArgs a) {
   extern __shared__ cplx buf[];
-  __shared__ cplx tw[3][MAXM];
-  init_twiddles(tw, a.m1, a.m2, a.m3);
   const int nk = a.m1 * a.m2 * a.m3;
   // consecutive workgroups walk the pair blocks of one interpolation-point
   // tile, so psi rows of that tile stay in L2 while they are reused
@@ -273,7 +291,7 @@ __global__ __launch_bounds__(256) void pair_kernel(PairArgs a) {
     }
   }
   __syncthreads();
-  mesh_dft<MAXA>(buf, tw, w, a.m1, a.m2, a.m3, -1);
+  mesh_dft<MAXA>(buf, w, a.m1, a.m2, a.m3, -1);
   for (int idx = threadIdx.x; idx < nk * w; idx += blockDim.x) {
     const int Q = idx >> wshift, e = idx & (w - 1);
     const int j = e >> tshift, i = e & (a.ti - 1);
@@ -810,6 +828,24 @@ hipError_t xconv_launch(const XconvArgs& a, hipStream_t s) {
   if (mx <= 4) hipLaunchKernelGGL(xconv_kernel<4>, dim3((unsigned)blocks), dim3(256), lds, s, a, etile);
   else if (mx <= 8) hipLaunchKernelGGL(xconv_kernel<8>, dim3((unsigned)blocks), dim3(256), lds, s, a, etile);
   else hipLaunchKernelGGL(xconv_kernel<16>, dim3((unsigned)blocks), dim3(256), lds, s, a, etile);
+  return hipGetLastError();
+}
+
+hipError_t pconv_launch(const PconvArgs& a, hipStream_t s) {
+  if (!a.gv || !a.go || !a.qslot) return hipErrorInvalidValue;
+  if (a.m1 > MAXM || a.m2 > MAXM || a.m3 > MAXM || a.m1 < 1 || a.m2 < 1 || a.m3 < 1) return hipErrorInvalidValue;
+  const int nk = a.m1 * a.m2 * a.m3;
+  int etile = 1;                        // two [nk][etile] columns in at most 64 KB
+  while (etile < 256 && (long long)nk * etile * 2 <= 2048) etile *= 2;
+  const long long blocks = (a.n_elem + etile - 1) / etile;
+  if (blocks <= 0) return hipSuccess;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  const size_t lds = 2 * (size_t)nk * etile * sizeof(cplx);
+  if (lds > 64 * 1024) return hipErrorInvalidValue;
+  const int mx = std::max(a.m1, std::max(a.m2, a.m3));
+  if (mx <= 4) hipLaunchKernelGGL(pconv_kernel<4>, dim3((unsigned)blocks), dim3(256), lds, s, a, etile);
+  else if (mx <= 8) hipLaunchKernelGGL(pconv_kernel<8>, dim3((unsigned)blocks), dim3(256), lds, s, a, etile);
+  else hipLaunchKernelGGL(pconv_kernel<16>, dim3((unsigned)blocks), dim3(256), lds, s, a, etile);
   return hipGetLastError();
 }
 

@@ -25,6 +25,9 @@ ISDF_NO_PIVOT = 0x2
 ISDF_ZETA_ROUTE = 0x4
 ISDF_FRAG_DEVICE = 0x1
 ISDF_HF_DEVICE = 0x1
+ISDF_MP2_DEVICE = 0x1
+ISDF_DRPA_DEVICE = 0x1
+C_SOS = 1.3
 REQ_STATES = {0: "QUEUED", 1: "RUNNING", 2: "DONE", 3: "FAILED", 4: "CANCELLED"}
 
 EXPORTS = ["isdf_create", "isdf_fit", "isdf_coulomb_kernel", "isdf_get_metric",
@@ -33,7 +36,7 @@ EXPORTS = ["isdf_create", "isdf_fit", "isdf_coulomb_kernel", "isdf_get_metric",
            "isdf_serve_stop", "isdf_stats", "isdf_stage_ms", "isdf_stage_total", "isdf_stage_reset", "isdf_plan_bytes", "isdf_storage_model_bytes",
            "isdf_graph_create", "isdf_graph_launch", "isdf_graph_destroy", "isdf_autotune", "isdf_set_tiling",
            "isdf_save", "isdf_load", "isdf_fragment_eri_static", "isdf_select_points", "isdf_hf_jk",
-           "isdf_destroy", "isdf_last_error", "isdf_version"]
+           "isdf_sos_mp2", "isdf_drpa", "isdf_destroy", "isdf_last_error", "isdf_version"]
 
 
 class IsdfError(RuntimeError):
@@ -85,6 +88,8 @@ def load_library(path=LIB_PATH):
         "isdf_fragment_eri_static": (I32, [P, I32, I32, P, P, P, U32]),
         "isdf_select_points": (I32, [P, P, I32, P, I32, P, P, U32, P]),
         "isdf_hf_jk": (I32, [P, P, P, P, U32]),
+        "isdf_sos_mp2": (I32, [P, P, P, I32, I32, I32, P, P, P, P, P, U32]),
+        "isdf_drpa": (I32, [P, P, P, I32, I32, I32, P, I32, P, P, P, P, P, P, U32]),
         "isdf_serve_start": (I32, [P, I32, I32, I64]),
         "isdf_submit": (I32, [P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
         "isdf_submit_n": (I32, [P, I32, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
@@ -174,6 +179,19 @@ def select_points(grid, kmesh, orbitals, n_ip, stream=None):
     if st != ISDF_OK:
         raise IsdfError(st, "isdf_select_points: " + lib.isdf_last_error(None).decode())
     return ip, res
+
+
+def _n_classes(kmesh):
+    """Number of classes {q, -q} of a k mesh (q with -q not smaller)."""
+    m = [int(v) for v in kmesh]
+    n = 0
+    for j1 in range(m[0]):
+        for j2 in range(m[1]):
+            for j3 in range(m[2]):
+                q = (j1 * m[1] + j2) * m[2] + j3
+                mq = (((-j1) % m[0]) * m[1] + (-j2) % m[1]) * m[2] + (-j3) % m[2]
+                n += mq >= q
+    return n
 
 
 class Isdf:
@@ -328,6 +346,69 @@ class Isdf:
                                         _ptr(k)[0] if k is not None else None, ISDF_HF_DEVICE if dev else 0),
                     "isdf_hf_jk")
         return j, k
+
+    def sos_mp2(self, mo_coeff, mo_energy, n_occ, tau, weight, per_class=False):
+        """``isdf_sos_mp2``: opposite-spin MP2 energy per cell from canonical
+        orbitals ``mo_coeff`` ([N_k, n_orb, n_mo] complex128, numpy or torch
+        cuda) with energies ``mo_energy`` ([N_k, n_mo]) and the first n_occ
+        occupied, on the quadrature (tau, weight) of [0, inf).  Returns a dict:
+        e_os, e_sos_mp2 (= 1.3 e_os), integrand (F at every tau) and, with
+        per_class, classes ([n_tau, nh] contributions)."""
+        cptr, dev = _ptr(mo_coeff)
+        nmo = int(mo_coeff.shape[2])
+        if tuple(mo_coeff.shape[:2]) != (self.n_k, self.n_orb):
+            raise ValueError("mo_coeff must be [N_k, n_orb, n_mo]")
+        e = np.ascontiguousarray(np.asarray(mo_energy, dtype=np.float64))
+        if e.shape != (self.n_k, nmo):
+            raise ValueError("mo_energy must be [N_k, n_mo]")
+        t = np.ascontiguousarray(np.asarray(tau, dtype=np.float64))
+        w = np.ascontiguousarray(np.asarray(weight, dtype=np.float64))
+        if t.shape != w.shape or t.ndim != 1:
+            raise ValueError("tau and weight must be matching 1-d arrays")
+        f = np.zeros(t.size)
+        nh = _n_classes(self.kmesh)
+        cls = np.zeros((t.size, nh)) if per_class else None
+        eos = ctypes.c_double()
+        self._check(self.lib.isdf_sos_mp2(self.h, cptr, e.ctypes.data, nmo, int(n_occ), int(t.size), t.ctypes.data,
+                                          w.ctypes.data, f.ctypes.data,
+                                          cls.ctypes.data if cls is not None else None, ctypes.byref(eos),
+                                          ISDF_MP2_DEVICE if dev else 0), "isdf_sos_mp2")
+        out = {"e_os": eos.value, "e_sos_mp2": C_SOS * eos.value, "integrand": f}
+        if per_class:
+            out["classes"] = cls
+        return out
+
+    def drpa(self, mo_coeff, mo_energy, n_occ, tau, omega_weight, transform, per_class=False):
+        """``isdf_drpa``: direct RPA correlation energy per cell (eq. (16)) of
+        the canonical orbitals: polarisabilities at the times ``tau``, mapped
+        to the frequencies by ``transform`` ([n_omega, n_tau] complex128,
+        gamma[m, n] ~ the weight of exp(-D tau_n) in 1/(D - i w_m)), the
+        frequency quadrature weights ``omega_weight``.  Returns a dict:
+        e_drpa, e_second (the second-order term), integrand (F at every
+        frequency) and, with per_class, classes ([n_omega, nh])."""
+        cptr, dev = _ptr(mo_coeff)
+        nmo = int(mo_coeff.shape[2])
+        if tuple(mo_coeff.shape[:2]) != (self.n_k, self.n_orb):
+            raise ValueError("mo_coeff must be [N_k, n_orb, n_mo]")
+        e = np.ascontiguousarray(np.asarray(mo_energy, dtype=np.float64))
+        if e.shape != (self.n_k, nmo):
+            raise ValueError("mo_energy must be [N_k, n_mo]")
+        t = np.ascontiguousarray(np.asarray(tau, dtype=np.float64))
+        ow = np.ascontiguousarray(np.asarray(omega_weight, dtype=np.float64))
+        g = np.ascontiguousarray(np.asarray(transform, dtype=np.complex128))
+        if t.ndim != 1 or ow.ndim != 1 or g.shape != (ow.size, t.size):
+            raise ValueError("transform must be [n_omega, n_tau] for tau [n_tau], omega_weight [n_omega]")
+        f = np.zeros(ow.size)
+        cls = np.zeros((ow.size, _n_classes(self.kmesh))) if per_class else None
+        e_r, e_2 = ctypes.c_double(), ctypes.c_double()
+        self._check(self.lib.isdf_drpa(self.h, cptr, e.ctypes.data, nmo, int(n_occ), int(t.size), t.ctypes.data,
+                                       int(ow.size), ow.ctypes.data, g.ctypes.data, f.ctypes.data,
+                                       cls.ctypes.data if cls is not None else None, ctypes.byref(e_r),
+                                       ctypes.byref(e_2), ISDF_DRPA_DEVICE if dev else 0), "isdf_drpa")
+        out = {"e_drpa": e_r.value, "e_second": e_2.value, "integrand": f}
+        if per_class:
+            out["classes"] = cls
+        return out
 
     def graph(self, coeffs, out, prec="bf16x3"):
         """The fragment pipeline of this batch (device tensors ``coeffs``, ERIs

@@ -277,6 +277,76 @@ def test_large_cell_hf_jk_sampled(bigcell):
     assert ek < 1e-11 and ej < 1e-11
 
 
+def _class_of(kmesh, q):
+    """Class index of q (classes: the q of the mesh, C order, whose -q is not
+    smaller)."""
+    mq = geo.minus_q(kmesh)
+    reps = [p for p in range(int(np.prod(kmesh))) if mq[p] >= p]
+    return reps.index(q if mq[q] >= q else int(mq[q]))
+
+
+@pytest.mark.timeout(900)
+def test_large_cell_sos_mp2_sampled(bigcell):
+    """Opposite-spin MP2 at the cell's full size from the GPU's W^q, two
+    tau points: the class contributions of q = 0, a generic q and a
+    zone-boundary q against the oracle's polarisabilities of those q (their
+    k sums over the whole mesh), and the integrand = the sum of the classes."""
+    from oracle import mp2
+    b = bigcell
+    cfg = b.d.cfg
+    c, e, n_occ = inp.make_mo(cfg)
+    tau = np.array([0.4, 1.3])
+    wt = np.array([0.5, 0.5])
+    r = b.ctx.sos_mp2(c, e, n_occ, tau, wt, per_class=True)
+    assert np.allclose(r["classes"].sum(axis=1), r["integrand"], rtol=1e-12, atol=0)
+    w = b.w_all()
+    y = mp2.mo_at_ips(b.x, c)
+    mu = mp2.chemical_potential(e, n_occ)
+    mq = geo.minus_q(cfg.kmesh)
+    qs = _qs_of(cfg)
+    for n, t in enumerate(tau):
+        go, gv = mp2.greens(y, e, n_occ, t, mu)
+        chi, chit = mp2.polarisabilities(go, gv, cfg.kmesh, qs)
+        del go, gv
+        for i, q in enumerate(qs):
+            term = np.trace(w[q] @ chi[i] @ w[q] @ chit[i]).real / cfg.n_k * (1 if mq[q] == q else 2)
+            got = r["classes"][n, _class_of(cfg.kmesh, q)]
+            rel = abs(got - term) / abs(term)
+            print("%s tau %.1f q %d: class term %.6e rel %.2e" % (cfg.name, t, q, term, rel), flush=True)
+            assert rel < 1e-10
+
+
+@pytest.mark.timeout(900)
+def test_large_cell_drpa_sampled(bigcell):
+    """Direct RPA at the cell's full size from the GPU's W^q (two tau and
+    two omega points): the class contributions of q = 0, a generic q and a
+    zone-boundary q against the oracle's frequency polarisabilities of those
+    q and ln det(1 - chi W) by LU."""
+    from oracle import mp2
+    from oracle import rpa
+    b = bigcell
+    cfg = b.d.cfg
+    c, e, n_occ = inp.make_mo(cfg)
+    tau, tw = np.array([0.4, 1.3]), np.array([0.6, 0.9])
+    om, ow = np.array([0.0, 0.7]), np.array([0.5, 0.5])
+    g = inp.quadrature_transform(tau, tw, om)
+    r = b.ctx.drpa(c, e, n_occ, tau, ow, g, per_class=True)
+    assert np.allclose(r["classes"].sum(axis=1), r["integrand"], rtol=1e-12, atol=0)
+    w = b.w_all()
+    y = mp2.mo_at_ips(b.x, c)
+    mq = geo.minus_q(cfg.kmesh)
+    qs = _qs_of(cfg)
+    chis = rpa.chi_omega_from_tau(y, e, n_occ, cfg.kmesh, g, tau, qs)
+    for m in range(len(om)):
+        for i, q in enumerate(qs):
+            full, _ = rpa.rpa_terms(chis[m, i] @ w[q])
+            term = full * (1 if mq[q] == q else 2) / (np.pi * cfg.n_k)
+            got = r["classes"][m, _class_of(cfg.kmesh, q)]
+            rel = abs(got - term) / abs(term)
+            print("%s omega %.1f q %d: class term %.6e rel %.2e" % (cfg.name, om[m], q, term, rel), flush=True)
+            assert rel < 1e-9
+
+
 @pytest.mark.timeout(900)
 def test_large_cell_small_fragments_oracle(bigcell):
     b = bigcell
