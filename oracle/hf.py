@@ -78,8 +78,8 @@ def coulomb(x, w, dm):
     n_J = sum_k rho^k_{JJ} (the q = 0 term of eq. (9) contracted with P).
     Returns [N_k, N_orb, N_orb]."""
     nk = x.shape[0]
-    rho = density_at_ips(x, dm)
-    n = np.einsum("kjj->j", rho)
+    # diagonal of rho^k only: n_J = sum_k sum_{la sg} X^k_{J la} P^k_{la sg} conj(X^k_{J sg})
+    n = np.einsum("kjl,kls,kjs->j", x, dm, x.conj(), optimize=True)
     v = w[0] @ n
     return np.stack([x[k].conj().T @ (v[:, None] * x[k]) for k in range(nk)]) / nk
 
