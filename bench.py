@@ -13,7 +13,10 @@ Two kinds of workload:
   W^q resident and polled to completion.  After the timed steps the same
   cell is fitted in FP64 and one slice is run in FP64: the speedup of the
   mixed precision over the plain FP64 GPU path and the max |mixed - FP64| of
-  every result of that slice.  The N_k = 216 cell can instead be served to
+  every result of that slice.  The same timed slices are also run in a
+  second precision (--alt-prec, single bf16 by default) and reported apart
+  with their own rate and error against FP64; the headline value stays the
+  --prec one.  The N_k = 216 cell can instead be served to
   open Poisson arrivals (--arrivals).
 * the small cells (N_k <= 64): one step is the whole path, fit + kernel + all
   fragments of the cell.
@@ -36,7 +39,7 @@ sys.path.insert(0, ROOT)
 
 # Peak rates of MI355X (dense; TFLOP/s and GB/s)
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "hbm": 8000.0}
-PREC_PEAK = {"fp64": ("fp64", 78.6), "fp32": ("fp32", 157.3), "bf16x3": ("bf16", 2500.0)}
+PREC_PEAK = {"fp64": ("fp64", 78.6), "fp32": ("fp32", 157.3), "bf16x3": ("bf16", 2500.0), "bf16": ("bf16", 2500.0)}
 STREAM_MIN_NK = 216
 
 
@@ -46,7 +49,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c5_k10_40")
-    ap.add_argument("--prec", default="bf16x3", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--prec", default="bf16x3", choices=["fp64", "fp32", "bf16x3", "bf16"])
+    ap.add_argument("--alt-prec", default="bf16", choices=["", "fp64", "fp32", "bf16x3", "bf16"],
+                    help="second precision timed on the same slices of the fragment stream (reported "
+                         "apart, with its own error against FP64); '' for none")
     ap.add_argument("--slice", type=int, default=4,
                     help="fragments per timed step of the large cells (a fixed slice of the stream)")
     ap.add_argument("--no-fp64-ref", action="store_true")
@@ -147,10 +153,11 @@ KERNEL_OF_STAGE = {"frag_eri": ("zgemm_nt_kernel<0, false, true, 3>", "{x}false,
 
 def kernel_name(stage, prec):
     """Name (prefix) of a stage's main kernel as the profiler lists it: the
-    FP32 path runs the two-plane big-tile kernel, bf16x3 its own MFMA kernel."""
+    FP32 path runs the two-plane big-tile kernel, bf16x3 and bf16 their own
+    MFMA kernels."""
     if stage not in KERNEL_OF_STAGE:
         return stage
-    x = {"fp32": "zgemm_big_kernel<1, ", "bf16x3": "zgemm_x3_kernel<"}.get(prec, "")
+    x = {"fp32": "zgemm_big_kernel<1, ", "bf16x3": "zgemm_x3_kernel<", "bf16": "zgemm_x1_kernel<"}.get(prec, "")
     return KERNEL_OF_STAGE[stage][0 if prec == "fp64" else 1].format(x=x)
 
 
@@ -611,6 +618,32 @@ def run_stream(args, cfg, pkg, inp, np, torch):
                                      / (t_fit + t_kernel + est_stream_s),
                                      "basis": "fit + kernel measured once; the 500-fragment stream at the "
                                               "measured fragment flop rate of the timed slices"}}
+    alt = None
+    if args.alt_prec and args.alt_prec != args.prec:
+        # the same timed slices in a second precision (reported apart)
+        step(slices[0], args.alt_prec, out_buf)
+        torch.cuda.synchronize()
+        ctx.stage_reset()
+        alat, ast = [], []
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            ts = time.perf_counter()
+            sl = slices[args.warmup + i]
+            alat += step(sl, args.alt_prec, out_buf)
+            ast.append(time.perf_counter() - ts)
+            if i == 0:
+                alt_keep = out_buf[:sum(nfs_all[f] ** 4 for f in sl)].clone()
+        torch.cuda.synchronize()
+        awall = time.perf_counter() - t0
+        atot = collect_stages(ctx, FRAG_STAGES + [s + "_kernel" for s in FRAG_STAGES])
+        aroof = roofline_entry(ctx, atot, cfg, timed_nfs, args.alt_prec, args.steps)
+        alt = {"prec": args.alt_prec, "value": erisum / awall, "unit": "ERIs/s", "ms_per_step": 1e3 * awall / args.steps,
+               "latency_ms": {"p50": float(np.percentile(1e3 * np.asarray(alat), 50)),
+                              "p99": float(np.percentile(1e3 * np.asarray(alat), 99))},
+               "slice0_s": ast[0],
+               "roofline": {k: aroof[k] for k in ("stage", "kernel", "achieved", "peak", "unit", "frac")},
+               "stages": stage_rows(atot, cfg, timed_nfs, args.alt_prec, args.steps)}
+        log("%s: %.3e ERIs/s (%.1f ms per step)" % (args.alt_prec, alt["value"], alt["ms_per_step"]))
     ctx.serve_stop()
     roof = roofline_entry(ctx, frag_tot, cfg, timed_nfs, args.prec, args.steps)
     stages = stage_rows(frag_tot, cfg, timed_nfs, args.prec, args.steps)
@@ -656,6 +689,12 @@ def run_stream(args, cfg, pkg, inp, np, torch):
             "max_err_eh_per_result": [{"n_f": nfs_all[f], "err": e, "max_abs_v": v}
                                       for f, e, v in zip(sl, errs, vmax)],
             "err_bound_eh": 1e-6, "err_reference": "GPU FP64 path, same slice"})
+        if alt is not None:
+            aerr = [float((a - b).abs().max().item()) for a, b in zip(outs_of(sl, alt_keep), ref64)]
+            alt.update({"speedup_vs_fp64": t64 / alt["slice0_s"], "max_err_eh": max(aerr),
+                        "max_err_rel_of_max_v": max(e / v for e, v in zip(aerr, vmax))})
+    if alt is not None:
+        extra["alt_precision"] = alt
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(d, [nfs_all[f] for f in slices[args.warmup]], args.cpu_budget_s)

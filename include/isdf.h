@@ -71,8 +71,14 @@ typedef enum {
                            in FP32 MFMA, FP32 accumulation within one class of q
                            (or one K segment), FP64 across them; the fit and the
                            Coulomb kernel stay FP64                              */
-  ISDF_MIXED_BF16X3 = 2 /* the same GEMMs with operands split hi+lo in bf16 and
+  ISDF_MIXED_BF16X3 = 2, /* the same GEMMs with operands split hi+lo in bf16 and
                            three bf16 MFMA products (hi*hi + hi*lo + lo*hi)     */
+  ISDF_MIXED_BF16 = 3   /* the same GEMMs with operands rounded to bf16, one bf16
+                           MFMA per real product, no split correction: error
+                           measured at 3e-4 to 2e-2 of the largest ERI, so
+                           within 1e-6 Eh only where the ERIs are small (a
+                           1000-k cell with max |V| 1.6e-5 Eh: 4.5e-8 Eh);
+                           callers check their own bound                     */
 } isdf_precision;
 
 /* flags for isdf_create */

@@ -40,7 +40,10 @@ static inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) 
 //      of 8 elements: element off at u16 index bf16x3_index(off, p) with
 //      p = 0 re_hi, 1 re_lo, 2 im_hi, 3 im_lo, so that the 16 k of one
 //      matrix-core step of a row are 128 contiguous bytes (rows start at
-//      multiples of 8 elements; `plane` is not used).
+//      multiples of 8 elements; `plane` is not used);
+//   3  single bf16 (re, im), interleaved by groups of 8 elements: element off
+//      at u16 index (off >> 3) * 16 + p * 8 + (off & 7), p = 0 re, 1 im, so
+//      that the 32 k of one stage of a row are 128 contiguous bytes.
 __device__ inline unsigned short bf16_bits_of(float x) {
   __bf16 h = (__bf16)x;
   return __builtin_bit_cast(unsigned short, h);
@@ -64,7 +67,12 @@ __device__ inline void store_fmt(void* out, long long off, long long plane, int 
     float* o = (float*)out;
     o[off] = (float)v.x;
     o[plane + off] = (float)v.y;
-  } else {
+  } else if (fmt == 2) {
     store_bf16x3((unsigned short*)out, off, (float)v.x, (float)v.y);
+  } else {
+    unsigned short* o = (unsigned short*)out;
+    const long long b = (off >> 3) * 16 + (off & 7);
+    o[b] = bf16_bits_of((float)v.x);
+    o[b + 8] = bf16_bits_of((float)v.y);
   }
 }

@@ -1,11 +1,15 @@
-// Complex "NT" GEMM on bf16 hi+lo operands (the bf16x3 precision) with the
-// 32x32x16 bf16 matrix cores of gfx950:
+// Complex "NT" GEMM on bf16 operands with the 32x32x16 bf16 matrix cores of
+// gfx950, in two operand formats: F = 2, bf16 hi+lo (the bf16x3 precision),
+// and F = 3, single bf16 (re, im) (the bf16 precision):
 //
 //   C[m][n] (+)= sum_k opA(A_seg[m][k]) opB(B_seg[n][k])
 //
-// x = hi + lo per real component; every real product keeps hi*hi + hi*lo +
-// lo*hi (three bf16 MFMAs, FP32 accumulation), and a complex product is four
-// real ones, so one 32x32 complex block costs 12 MFMAs per 16 k.
+// F = 2: x = hi + lo per real component; every real product keeps hi*hi +
+// hi*lo + lo*hi (three bf16 MFMAs, FP32 accumulation), and a complex product
+// is four real ones, so one 32x32 complex block costs 12 MFMAs per 16 k.
+// F = 3: one bf16 MFMA per real product, 8 MFMAs per 32 k.  In both formats
+// one row of one stage is 128 contiguous bytes: 16 k x 4 planes (F = 2) or
+// 32 k x 2 planes (F = 3), so the copies and the LDS layout are shared.
 //
 // Workgroup: 256 threads (4 waves, 2 x 2), 128 x 128 output tile, each wave
 // 64 x 64 (2 x 2 blocks of 32 x 32); two workgroups per CU.  K advances in
@@ -39,10 +43,15 @@ typedef __attribute__((address_space(3))) void lds_void;
 typedef __attribute__((address_space(1))) void glb_void;
 
 constexpr int XT = 128;               // tile edge
-constexpr int XK = 16;                // k per stage
+constexpr int XK = 16;                // k per stage of the hi+lo format
+// k per stage, u16 per element in the global layout, and log2 of the
+// planes per 8-element group, by format
+template <int F> struct Fmt;
+template <> struct Fmt<2> { static constexpr int K = 16, EU = 4, PL = 2; };
+template <> struct Fmt<3> { static constexpr int K = 32, EU = 2, PL = 1; };
 constexpr int NBUF = 2;               // LDS stages (two workgroups per CU)
 constexpr int XNT = 256;              // threads
-constexpr int ROW_B = XK * 8;          // bytes of one row of one stage (128)
+constexpr int ROW_B = 128;             // bytes of one row of one stage
 constexpr int OPER_B = XT * ROW_B;     // one operand tile of a stage (16 KB)
 constexpr int STAGE_B = 2 * OPER_B;    // A and B (32 KB)
 constexpr int NCOPY = 4;               // copy instructions per wave per operand and stage
@@ -76,14 +85,15 @@ __device__ __attribute__((aligned(16))) unsigned short kZeroVec[8];
 // slot gslot[j] whose LDS position is this lane's); the address advances by
 // 4 u16 an element of k.  In the last stage of a segment, vectors that start
 // at or past its end are copied from the zero block.
+template <int F>
 __device__ inline void stage_copy(const unsigned short* const (&src)[NCOPY], const int (&gslot)[NCOPY], int k0,
                                   int kcur, char* dst, int wave) {
-  const bool tail = k0 + XK > kcur;       // the same for the whole workgroup
+  const bool tail = k0 + Fmt<F>::K > kcur;    // the same for the whole workgroup
 #pragma unroll
   for (int j = 0; j < NCOPY; ++j) {
     const int rc = wave + 4 * j;          // rows rc*8 .. rc*8+7
-    const unsigned short* g = src[j] + 4 * k0;
-    if (tail && k0 + 8 * (gslot[j] >> 2) >= kcur) g = kZeroVec;
+    const unsigned short* g = src[j] + Fmt<F>::EU * k0;
+    if (tail && k0 + 8 * (gslot[j] >> Fmt<F>::PL) >= kcur) g = kZeroVec;
     __builtin_amdgcn_global_load_lds((glb_void*)g, (lds_void*)(dst + rc * 8 * ROW_B), 16, 0, 0);
   }
 }
@@ -99,24 +109,31 @@ struct Frag {
   u4 a[NI][4], b[NJ][4];
 };
 
-template <int NI, int NJ>
+// The four 16-byte slots of a lane's row: F = 2, planes rh rl ih il of k-group
+// lk; F = 3, (re, im) of k-group lk for the first MFMA step, then of k-group
+// 2 + lk for the second.
+template <int F>
+__device__ inline int frag_slot(int lk, int x) {
+  return F == 2 ? 4 * lk + x : 4 * (x >> 1) + 2 * lk + (x & 1);
+}
+template <int F, int NI, int NJ>
 __device__ inline void read_frags_a(const char* buf, Frag<NI, NJ>& f, int rb0, int lr, int lk) {
 #pragma unroll
   for (int i = 0; i < NI; ++i) {
     const int row = rb0 + i * 32 + lr;
     const char* p = buf + row * ROW_B;
 #pragma unroll
-    for (int pl = 0; pl < 4; ++pl) f.a[i][pl] = *(const u4*)(p + (lds_slot(row, 4 * lk + pl) << 4));
+    for (int pl = 0; pl < 4; ++pl) f.a[i][pl] = *(const u4*)(p + (lds_slot(row, frag_slot<F>(lk, pl)) << 4));
   }
 }
-template <int NI, int NJ>
+template <int F, int NI, int NJ>
 __device__ inline void read_frags_b(const char* buf, Frag<NI, NJ>& f, int cb0, int lr, int lk) {
 #pragma unroll
   for (int j = 0; j < NJ; ++j) {
     const int row = cb0 + j * 32 + lr;
     const char* p = buf + OPER_B + row * ROW_B;
 #pragma unroll
-    for (int pl = 0; pl < 4; ++pl) f.b[j][pl] = *(const u4*)(p + (lds_slot(row, 4 * lk + pl) << 4));
+    for (int pl = 0; pl < 4; ++pl) f.b[j][pl] = *(const u4*)(p + (lds_slot(row, frag_slot<F>(lk, pl)) << 4));
   }
 }
 
@@ -195,13 +212,54 @@ __device__ inline void mma_half(const Frag<NI, NJ>& f, int j, f16v (&c_re)[NI][N
 }
 #undef X3_TERMS
 
+// The 8 MFMAs of one stage of the single-bf16 format for the wave's column
+// block j: two k steps (fragment slots 0, 1 and 2, 3 hold re, im), each
+// re += a_r b_r - a_i b_i, im += a_r b_i + a_i b_r.
+// The accumulator chains (re and im of each row block) are issued round
+// robin, so that dependent MFMAs are 2 NI apart.
+template <int NI, int NJ, bool A_CONJ, bool B_CONJ>
+__device__ inline void mma_single(const Frag<NI, NJ>& f, int j, f16v (&c_re)[NI][NJ], f16v (&c_im)[NI][NJ]) {
+  f16v cr[NI], ci[NI];
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    cr[i] = c_re[i][j];
+    ci[i] = c_im[i][j];
+  }
+#pragma unroll
+  for (int st = 0; st < 2; ++st) {
+    const u4 bi = B_CONJ ? neg_bf(f.b[j][2 * st + 1]) : f.b[j][2 * st + 1];
+    const bf8 br = as_bf8(f.b[j][2 * st]), bim = as_bf8(bi);
+    bf8 ar[NI], aim[NI], naim[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      const u4 ai = A_CONJ ? neg_bf(f.a[i][2 * st + 1]) : f.a[i][2 * st + 1];
+      ar[i] = as_bf8(f.a[i][2 * st]);
+      aim[i] = as_bf8(ai);
+      naim[i] = as_bf8(neg_bf(ai));
+    }
+#pragma unroll
+    for (int i = 0; i < NI; ++i) cr[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar[i], br, cr[i], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < NI; ++i) ci[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar[i], bim, ci[i], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < NI; ++i) cr[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(naim[i], bim, cr[i], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < NI; ++i) ci[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aim[i], br, ci[i], 0, 0, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    c_re[i][j] = cr[i];
+    c_im[i][j] = ci[i];
+  }
+}
+
 // Epilogue of one tile (32x32 layout: lane l, register v -> row
 // 8(v/4) + 4(l/32) + v%4, column l%32).  epi 3: each wave assembles its
 // block 32 rows at a time in LDS (16 KB a wave) in the operand format (a row
 // of NJ*32 points is NJ*256 contiguous bytes) and writes it with 16-byte
 // stores; otherwise FP64 accumulation across launches (the first K segment,
 // `first`, stores).
-template <int NI, int NJ>
+template <int F, int NI, int NJ>
 __device__ inline void tile_epilogue(const NtDesc& d, int b, int m0, int n0, int rb0, int cb0,
                                      const f16v (&c_re)[NI][NJ], const f16v (&c_im)[NI][NJ], char* smem, int wave,
                                      int lane, bool first) {
@@ -210,9 +268,10 @@ __device__ inline void tile_epilogue(const NtDesc& d, int b, int m0, int n0, int
     __syncthreads();                      // every wave is past its last stage reads
     unsigned short* st = (unsigned short*)(smem + wave * 16384);
     const int npad = d.npad ? d.npad : (int)d.ldc;
-    constexpr int RU = NJ * 128;          // u16 per staged row
-    constexpr int PPR = NJ * 16;          // 16-byte parts per row
-    unsigned short* C = (unsigned short*)d.C + 4 * ((long long)b * d.sC_bat + n0 + cb0);
+    constexpr int EU = Fmt<F>::EU;
+    constexpr int RU = NJ * 32 * EU;      // u16 per staged row
+    constexpr int PPR = NJ * 4 * EU;      // 16-byte parts per row
+    unsigned short* C = (unsigned short*)d.C + EU * ((long long)b * d.sC_bat + n0 + cb0);
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
 #pragma unroll
@@ -224,19 +283,25 @@ __device__ inline void tile_epilogue(const NtDesc& d, int b, int m0, int n0, int
           const bool in = n0 + cb0 + nl < d.N;
           const float re = in ? c_re[i][j][v] : 0.f, im = in ? c_im[i][j][v] : 0.f;
           const unsigned short rh = bf16_bits_of(re), ih = bf16_bits_of(im);
-          unsigned short* e = st + ml * RU + (nl >> 3) * 32 + (nl & 7);
-          e[0] = rh;
-          e[8] = bf16_bits_of(re - bf16_value(rh));
-          e[16] = ih;
-          e[24] = bf16_bits_of(im - bf16_value(ih));
+          unsigned short* e = st + ml * RU + (nl >> 3) * (8 * EU) + (nl & 7);
+          if constexpr (F == 2) {
+            e[0] = rh;
+            e[8] = bf16_bits_of(re - bf16_value(rh));
+            e[16] = ih;
+            e[24] = bf16_bits_of(im - bf16_value(ih));
+          } else {
+            e[0] = rh;
+            e[8] = ih;
+          }
         }
       __builtin_amdgcn_wave_barrier();
+      // 32 staged rows of PPR parts, 64 lanes a pass
 #pragma unroll 4
-      for (int h = 0; h < NJ * 8; ++h) {
+      for (int h = 0; h < PPR / 2; ++h) {
         const int c = h * 64 + lane, ml = c / PPR, part = c % PPR;
         const int m = m0 + rb0 + i * 32 + ml;
-        if (m < d.M && n0 + cb0 + (part >> 2) * 8 < npad)
-          *(u4*)(C + 4 * (long long)m * d.ldc + part * 8) = *(const u4*)(st + ml * RU + part * 8);
+        if (m < d.M && n0 + cb0 + (part >> Fmt<F>::PL) * 8 < npad)
+          *(u4*)(C + EU * (long long)m * d.ldc + part * 8) = *(const u4*)(st + ml * RU + part * 8);
       }
       __builtin_amdgcn_wave_barrier();
     }
@@ -267,7 +332,7 @@ __device__ inline void tile_epilogue(const NtDesc& d, int b, int m0, int n0, int
 // each): two LDS stages, each stage's fragments read from LDS at its start
 // (the waves of the other workgroup keep the matrix cores busy meanwhile),
 // copies two stages ahead.
-template <int NI, int NJ, bool A_CONJ, bool B_CONJ>
+template <int F, int NI, int NJ, bool A_CONJ, bool B_CONJ>
 __device__ inline void tile_body(const NtDesc& d, int b, int m0, int n0, int kcur,
                                  const unsigned short* const (&asrc)[NCOPY], const unsigned short* const (&bsrc)[NCOPY],
                                  const int (&gslot)[NCOPY], int rb0, int cb0, char* smem, int wave, int lane,
@@ -283,13 +348,14 @@ __device__ inline void tile_body(const NtDesc& d, int b, int m0, int n0, int kcu
         c_re[i][j][v] = 0.f;
         c_im[i][j][v] = 0.f;
       }
-  const int nst = (kcur + XK - 1) / XK;
+  constexpr int SK = Fmt<F>::K;
+  const int nst = (kcur + SK - 1) / SK;
   __syncthreads();                        // LDS of the previous tile no longer read
 #pragma unroll
   for (int s = 0; s < NBUF; ++s)
     if (s < nst) {
-      stage_copy(asrc, gslot, s * XK, kcur, smem + s * STAGE_B, wave);
-      stage_copy(bsrc, gslot, s * XK, kcur, smem + s * STAGE_B + OPER_B, wave);
+      stage_copy<F>(asrc, gslot, s * SK, kcur, smem + s * STAGE_B, wave);
+      stage_copy<F>(bsrc, gslot, s * SK, kcur, smem + s * STAGE_B + OPER_B, wave);
     }
   for (int s = 0; s < nst; ++s) {
     char* buf = smem + (s & 1) * STAGE_B;
@@ -298,28 +364,32 @@ __device__ inline void tile_body(const NtDesc& d, int b, int m0, int n0, int kcu
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
     Frag<NI, NJ> f;
-    read_frags_a(buf, f, rb0, lr, lk);
-    read_frags_b(buf, f, cb0, lr, lk);
+    read_frags_a<F>(buf, f, rb0, lr, lk);
+    read_frags_b<F>(buf, f, cb0, lr, lk);
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     settle(f);
     // every wave holds its fragments of stage s: its buffer takes stage s+2
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
     if (s + NBUF < nst) {
-      stage_copy(asrc, gslot, (s + NBUF) * XK, kcur, buf, wave);
-      stage_copy(bsrc, gslot, (s + NBUF) * XK, kcur, buf + OPER_B, wave);
+      stage_copy<F>(asrc, gslot, (s + NBUF) * SK, kcur, buf, wave);
+      stage_copy<F>(bsrc, gslot, (s + NBUF) * SK, kcur, buf + OPER_B, wave);
     }
     if (!idle) {
-      mma_half<NI, NJ, A_CONJ, B_CONJ>(f, 0, c_re, c_im);
-      if (NJ == 2) mma_half<NI, NJ, A_CONJ, B_CONJ>(f, NJ - 1, c_re, c_im);
+      if constexpr (F == 2) {
+        mma_half<NI, NJ, A_CONJ, B_CONJ>(f, 0, c_re, c_im);
+        if (NJ == 2) mma_half<NI, NJ, A_CONJ, B_CONJ>(f, NJ - 1, c_re, c_im);
+      } else {
+        mma_single<NI, NJ, A_CONJ, B_CONJ>(f, 0, c_re, c_im);
+        if (NJ == 2) mma_single<NI, NJ, A_CONJ, B_CONJ>(f, NJ - 1, c_re, c_im);
+      }
     }
   }
-  if (!idle) tile_epilogue<NI, NJ>(d, b, m0, n0, rb0, cb0, c_re, c_im, smem, wave, lane, first);
+  if (!idle) tile_epilogue<F, NI, NJ>(d, b, m0, n0, rb0, cb0, c_re, c_im, smem, wave, lane, first);
 }
 
-template <bool A_CONJ, bool B_CONJ, int KIND>
-__global__ __launch_bounds__(XNT, 2) void zgemm_x3_kernel(const NtDesc* __restrict__ descs, int ndesc,
-                                                          long long total_tiles, int seg) {
+template <int F, bool A_CONJ, bool B_CONJ, int KIND>
+__device__ inline void x3_tiles(const NtDesc* __restrict__ descs, int ndesc, long long total_tiles, int seg) {
   extern __shared__ __attribute__((aligned(16))) char smem[];   // NBUF stages x (A, B)
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -349,9 +419,10 @@ __global__ __launch_bounds__(XNT, 2) void zgemm_x3_kernel(const NtDesc* __restri
       tn = lt - tm * d.tiles_n;
     }
     const int m0 = tm * XT, n0 = tn * XT;
-    // interleaved bf16 hi/lo: logical element e at u16 4*e (e a multiple of 8)
-    const unsigned short* As = (const unsigned short*)d.A + 4 * (b * d.sA_bat + (long long)seg * d.sA_seg);
-    const unsigned short* Bs = (const unsigned short*)d.B + 4 * (b * d.sB_bat + (long long)seg * d.sB_seg);
+    // interleaved formats: logical element e at u16 EU*e (e a multiple of 8)
+    constexpr int EU = Fmt<F>::EU;
+    const unsigned short* As = (const unsigned short*)d.A + EU * (b * d.sA_bat + (long long)seg * d.sA_seg);
+    const unsigned short* Bs = (const unsigned short*)d.B + EU * (b * d.sB_bat + (long long)seg * d.sB_seg);
     const int kcur = (seg == d.nseg - 1) ? d.Klast : d.Kseg;
 
     // this lane's sources and slots in its copy instructions; rows past M / N
@@ -364,8 +435,8 @@ __global__ __launch_bounds__(XNT, 2) void zgemm_x3_kernel(const NtDesc* __restri
       const int row = (wave + 4 * j) * 8 + (lane >> 3);
       gslot[j] = lds_slot(row, lane & 7);     // the slot whose LDS position is lane & 7
       const int ra = min(m0 + row, d.M - 1), rb = min(n0 + row, d.N - 1);
-      asrc[j] = As + 4 * ((long long)ra * d.lda) + 8 * gslot[j];
-      bsrc[j] = Bs + 4 * ((long long)rb * d.ldb) + 8 * gslot[j];
+      asrc[j] = As + EU * ((long long)ra * d.lda) + 8 * gslot[j];
+      bsrc[j] = Bs + EU * ((long long)rb * d.ldb) + 8 * gslot[j];
     }
     // Hermitian outputs (lower tiles; the upper triangle is mirrored later):
     // in a diagonal tile, a wave whose block lies strictly above the
@@ -374,15 +445,27 @@ __global__ __launch_bounds__(XNT, 2) void zgemm_x3_kernel(const NtDesc* __restri
     const bool diag = d.herm && tm == tn && d.epi != 3;
     const bool first = seg == 0;
     if (d.M - m0 <= 32)
-      tile_body<1, 1, A_CONJ, B_CONJ>(d, b, m0, n0, kcur, asrc, bsrc, gslot, 0, wave * 32, smem, wave, lane,
-                                      diag && wave > 0, first);
+      tile_body<F, 1, 1, A_CONJ, B_CONJ>(d, b, m0, n0, kcur, asrc, bsrc, gslot, 0, wave * 32, smem, wave, lane,
+                                         diag && wave > 0, first);
     else if (d.N - n0 <= 32)
-      tile_body<1, 1, A_CONJ, B_CONJ>(d, b, m0, n0, kcur, asrc, bsrc, gslot, wave * 32, 0, smem, wave, lane, false,
-                                      first);
+      tile_body<F, 1, 1, A_CONJ, B_CONJ>(d, b, m0, n0, kcur, asrc, bsrc, gslot, wave * 32, 0, smem, wave, lane,
+                                         false, first);
     else
-      tile_body<2, 2, A_CONJ, B_CONJ>(d, b, m0, n0, kcur, asrc, bsrc, gslot, wm * 64, wn * 64, smem, wave, lane,
-                                      diag && wm < wn, first);
+      tile_body<F, 2, 2, A_CONJ, B_CONJ>(d, b, m0, n0, kcur, asrc, bsrc, gslot, wm * 64, wn * 64, smem, wave, lane,
+                                         diag && wm < wn, first);
   }
+}
+
+template <bool A_CONJ, bool B_CONJ, int KIND>
+__global__ __launch_bounds__(XNT, 2) void zgemm_x3_kernel(const NtDesc* __restrict__ descs, int ndesc,
+                                                          long long total_tiles, int seg) {
+  x3_tiles<2, A_CONJ, B_CONJ, KIND>(descs, ndesc, total_tiles, seg);
+}
+
+template <bool A_CONJ, bool B_CONJ, int KIND>
+__global__ __launch_bounds__(XNT, 2) void zgemm_x1_kernel(const NtDesc* __restrict__ descs, int ndesc,
+                                                          long long total_tiles, int seg) {
+  x3_tiles<3, A_CONJ, B_CONJ, KIND>(descs, ndesc, total_tiles, seg);
 }
 
 template <int KIND>
@@ -399,7 +482,31 @@ hipError_t launch_x3(int conj, const NtDesc* descs, int ndesc, long long total, 
   return hipGetLastError();
 }
 
+// single-bf16 format: the two call sites of the path (U^q = R^q W^q, kind 2,
+// no conjugation; the fragment contraction, kind 3, B conjugated)
+hipError_t launch_x1(int conj, const NtDesc* descs, int ndesc, long long total, int blocks, int seg, int kind,
+                     hipStream_t s) {
+  dim3 g(blocks), b(XNT);
+  const size_t lds = NBUF * STAGE_B;
+  if (kind == 2 && (conj & 3) == 0)
+    hipLaunchKernelGGL((zgemm_x1_kernel<false, false, 2>), g, b, lds, s, descs, ndesc, total, seg);
+  else if (kind == 3 && (conj & 3) == 2)
+    hipLaunchKernelGGL((zgemm_x1_kernel<false, true, 3>), g, b, lds, s, descs, ndesc, total, seg);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t x1_launch(int conj, const NtDesc* descs_dev, int ndesc, long long total, int max_blocks, int seg,
+                     hipStream_t s, int kind) {
+  if (total <= 0) return hipSuccess;
+  const long long t8 = (total + 7) / 8 * 8;
+  max_blocks = max_blocks / 8 * 8;
+  const int blocks = (int)(t8 < max_blocks ? t8 : max_blocks);
+  return launch_x1(conj, descs_dev, ndesc, total, blocks, seg, kind, s);
+}
 
 hipError_t x3_launch(int conj, const NtDesc* descs_dev, int ndesc, long long total, int max_blocks, int seg,
                      hipStream_t s, int kind) {

@@ -246,8 +246,9 @@ void run_big(Arena& ar, int prec, int conj, std::vector<NtDesc>& d, int nseg, hi
   NtDesc* dd = ar.put(d.data(), d.size(), s);
   for (int seg = 0; seg < nseg; ++seg) {
     if (mark) mark(true);
-    HIPCHK(prec == 2 ? x3_launch(conj, dd, (int)d.size(), total, gemm_blocks(), seg, s, kind)
-                     : big_launch(prec, conj, dd, (int)d.size(), total, gemm_blocks(), seg, s, kind));
+    HIPCHK(prec == 2   ? x3_launch(conj, dd, (int)d.size(), total, gemm_blocks(), seg, s, kind)
+           : prec == 3 ? x1_launch(conj, dd, (int)d.size(), total, gemm_blocks(), seg, s, kind)
+                       : big_launch(prec, conj, dd, (int)d.size(), total, gemm_blocks(), seg, s, kind));
     if (mark) mark(false);
   }
 }
@@ -272,10 +273,11 @@ NtDesc mknt(const void* A, long long lda, const void* B, long long ldb, void* C,
 }
 
 // bytes per complex element of the GEMM operand format of a precision
-size_t fmt_bytes(int prec) { return prec == 0 ? 16 : 8; }
+size_t fmt_bytes(int prec) { return prec == 0 ? 16 : (prec == 3 ? 4 : 8); }
 // bytes between consecutive elements of one row as addressed by pointers:
-// c128, one FP32 plane (planes separate), bf16 hi/lo interleaved (8 bytes)
-size_t fmt_scalar(int prec) { return prec == 0 ? 16 : (prec == 1 ? 4 : 8); }
+// c128, one FP32 plane (planes separate), bf16 hi/lo interleaved (8 bytes),
+// single bf16 interleaved (4 bytes)
+size_t fmt_scalar(int prec) { return prec == 0 ? 16 : (prec == 1 ? 4 : (prec == 2 ? 8 : 4)); }
 
 GemmDesc mkdesc(const cplx* A, long long lda, const cplx* B, long long ldb, cplx* C, long long ldc,
                 int M, int N, int K) {
@@ -401,7 +403,7 @@ struct isdf_ctx_s {
   int device = 0;
   // resident device data
   DevBuf phi, ip, xt, pi, eta, lt, w, work1, work2, work3, pinv_ws, perm, rank, rchunk, flag;
-  DevBuf wt64, wt32, wt16;              // W transposed in the three GEMM operand formats
+  DevBuf wt64, wt32, wt16, wt16s;       // W transposed in the four GEMM operand formats
   DevBuf dmax, cflag;                   // factorisation: largest diagonal, breakdown flags
   long long ld_ip = 0;                  // row pitch of the split operands (a multiple of 16)
   bool has_orbitals = false;            // false for a context restored by isdf_load
@@ -807,7 +809,7 @@ void kernel_finish(isdf_ctx c) {
   // (one per class {q, -q}, weight 1/2 where q = -q: the fragment contraction
   // adds the conjugate term of -q itself)
   HIPCHK(wt_convert_launch(c->w.as<cplx>(), c->wt64.as<cplx>(), c->wt32.as<float>(),
-                           c->wt16.as<unsigned short>(), nip, (int)c->ld_ip, nh, c->qmap.as<int>() + nk + nh, s));
+                           c->wt16.as<unsigned short>(), c->wt16s.as<unsigned short>(), nip, (int)c->ld_ip, nh, c->qmap.as<int>() + nk + nh, s));
   HIPCHK(hipMemsetAsync(c->flag.p, 0, sizeof(int), s));
   HIPCHK(nonfinite_launch(c->w.as<cplx>(), (long long)nh * nip2(c), c->flag.as<int>(), s));
   int bad = 0;
@@ -1281,7 +1283,7 @@ void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn
   };
   // U^q_{P,J} = sum_I R^q_{P,I} W^q_{IJ}   (eq. (19), first contraction)
   auto u_gemm = [&](const char* m, long long nrows) {
-    const void* wt = prec == 0 ? c->wt64.p : (prec == 1 ? c->wt32.p : c->wt16.p);
+    const void* wt = prec == 0 ? c->wt64.p : (prec == 1 ? c->wt32.p : (prec == 2 ? c->wt16.p : c->wt16s.p));
     std::vector<NtDesc> d(1);
     d[0] = mknt(m, (long long)nh * ld, wt, ld, Uq, (long long)nh * ld, (int)nrows, nip, nip);
     d[0].batch = nh;
@@ -1644,6 +1646,7 @@ void setup_context(isdf_ctx c, const double* lattice, const int32_t grid[3], con
   c->wt64.alloc((size_t)nh * n_ip * c->ld_ip * e);
   c->wt32.alloc((size_t)nh * n_ip * c->ld_ip * 8);
   c->wt16.alloc((size_t)nh * n_ip * c->ld_ip * 8);
+  c->wt16s.alloc((size_t)nh * n_ip * c->ld_ip * 4);
   c->perm.alloc(sizeof(int) * nh * n_ip);
   c->rank.alloc(sizeof(int) * nh);
   c->flag.alloc(sizeof(int));
@@ -1781,7 +1784,7 @@ int64_t isdf_plan_bytes(const int32_t grid[3], const int32_t kmesh[3], int32_t n
   b += nk * (long long)n_ip * n_ip * e;  // T^k of the metric, then V
   b += 5 * nh * (long long)n_ip * n_ip * e;  // Pi, L, W, two work buffers (per class)
   b += nh * ((long long)n_ip * 64 + 4096) * e;  // L^{-1} scratch
-  b += nh * (long long)n_ip * ld * (16 + 8 + 8);  // W^T in the three operand formats
+  b += nh * (long long)n_ip * ld * (16 + 8 + 8 + 4);  // W^T in the four operand formats
   b += nh * (long long)n_ip * ng * e;    // eta of every class (q batches need less)
   b += 2 * nk * (long long)n_ip * rchunk_len(ng, (int)nk, n_ip) * e;  // two RHS tiles
   b += n_ip * 4 + 2 * nh * (long long)n_ip * 4;
@@ -1908,7 +1911,7 @@ isdf_status isdf_select_points(const int32_t grid[3], const int32_t kmesh[3], in
 
 isdf_status isdf_fit(isdf_ctx ctx, isdf_precision prec) {
   return guarded(ctx, [&] {
-    if (prec < ISDF_FP64 || prec > ISDF_MIXED_BF16X3) throw Fail{ISDF_E_INVALID, "bad precision"};
+    if (prec < ISDF_FP64 || prec > ISDF_MIXED_BF16) throw Fail{ISDF_E_INVALID, "bad precision"};
     if (!ctx->has_orbitals) throw Fail{ISDF_E_STATE, "context restored from a checkpoint has no orbitals to fit"};
     Exclusive ex(ctx, true);
     do_fit(ctx, prec);
@@ -1918,7 +1921,7 @@ isdf_status isdf_fit(isdf_ctx ctx, isdf_precision prec) {
 
 isdf_status isdf_coulomb_kernel(isdf_ctx ctx, isdf_precision prec) {
   return guarded(ctx, [&] {
-    if (prec < ISDF_FP64 || prec > ISDF_MIXED_BF16X3) throw Fail{ISDF_E_INVALID, "bad precision"};
+    if (prec < ISDF_FP64 || prec > ISDF_MIXED_BF16) throw Fail{ISDF_E_INVALID, "bad precision"};
     if (!ctx->fitted || !ctx->kernel_pending)
       throw Fail{ISDF_E_STATE, "isdf_fit must run before isdf_coulomb_kernel"};
     Exclusive ex(ctx, true);
@@ -2045,7 +2048,7 @@ isdf_status isdf_fragment_eri(isdf_ctx ctx, isdf_precision prec, int32_t n_frag,
                               const void* const* C, void* const* eri, uint32_t flags) {
   return guarded(ctx, [&] {
     if (n_frag < 1 || !n_f || !C || !eri) throw Fail{ISDF_E_INVALID, "bad fragment arguments"};
-    if (prec < ISDF_FP64 || prec > ISDF_MIXED_BF16X3) throw Fail{ISDF_E_INVALID, "bad precision"};
+    if (prec < ISDF_FP64 || prec > ISDF_MIXED_BF16) throw Fail{ISDF_E_INVALID, "bad precision"};
     std::vector<FragIn> fr;
     for (int f = 0; f < n_frag; ++f) {
       if (n_f[f] < 1 || n_f[f] > ctx->nk * ctx->norb || !C[f] || !eri[f])
@@ -2071,7 +2074,7 @@ isdf_status isdf_fragment_eri_static(isdf_ctx ctx, isdf_precision prec, int32_t 
                                      const void* const* C, void* const* eri, uint32_t flags) {
   return guarded(ctx, [&] {
     if (n_frag < 1 || !n_f || !C || !eri) throw Fail{ISDF_E_INVALID, "bad fragment arguments"};
-    if (prec < ISDF_FP64 || prec > ISDF_MIXED_BF16X3) throw Fail{ISDF_E_INVALID, "bad precision"};
+    if (prec < ISDF_FP64 || prec > ISDF_MIXED_BF16) throw Fail{ISDF_E_INVALID, "bad precision"};
     if (!(flags & ISDF_FRAG_DEVICE)) throw Fail{ISDF_E_INVALID, "the static variant takes device pointers only"};
     if (!ctx->kernel_ready) throw Fail{ISDF_E_STATE, "isdf_coulomb_kernel must run before fragment ERIs"};
     if (!ctx->scratch) throw Fail{ISDF_E_STATE, "static workspace not set up"};
@@ -2114,7 +2117,7 @@ isdf_status isdf_graph_create(isdf_ctx ctx, isdf_precision prec, int32_t n_frag,
   return guarded(ctx, [&] {
     if (!out || n_frag < 1 || !n_f || !C || !eri) throw Fail{ISDF_E_INVALID, "bad graph arguments"};
     *out = nullptr;
-    if (prec < ISDF_FP64 || prec > ISDF_MIXED_BF16X3) throw Fail{ISDF_E_INVALID, "bad precision"};
+    if (prec < ISDF_FP64 || prec > ISDF_MIXED_BF16) throw Fail{ISDF_E_INVALID, "bad precision"};
     if (!ctx->kernel_ready) throw Fail{ISDF_E_STATE, "isdf_coulomb_kernel must run before fragment ERIs"};
     std::vector<FragIn> fr;
     for (int f = 0; f < n_frag; ++f) {
@@ -2179,7 +2182,7 @@ isdf_status isdf_autotune(isdf_ctx ctx, isdf_precision prec, int32_t n_frag, con
                           const void* const* C, void* const* eri, isdf_tune_report* report) {
   return guarded(ctx, [&] {
     if (n_frag < 1 || !n_f || !C || !eri) throw Fail{ISDF_E_INVALID, "bad fragment arguments"};
-    if (prec < ISDF_FP64 || prec > ISDF_MIXED_BF16X3) throw Fail{ISDF_E_INVALID, "bad precision"};
+    if (prec < ISDF_FP64 || prec > ISDF_MIXED_BF16) throw Fail{ISDF_E_INVALID, "bad precision"};
     if (!ctx->kernel_ready) throw Fail{ISDF_E_STATE, "isdf_coulomb_kernel must run before fragment ERIs"};
     std::vector<FragIn> fr;
     for (int f = 0; f < n_frag; ++f) {
@@ -2295,7 +2298,7 @@ isdf_status isdf_submit_n(isdf_ctx ctx, int32_t n, const isdf_request* reqs, uin
   for (int i = 0; i < n; ++i) {
     const isdf_request* req = reqs + i;
     if (req->n_f < 1 || req->n_f > ctx->nk * ctx->norb || !req->C || !req->eri ||
-        req->prec < ISDF_FP64 || req->prec > ISDF_MIXED_BF16X3)
+        req->prec < ISDF_FP64 || req->prec > ISDF_MIXED_BF16)
       return fail(ctx, ISDF_E_INVALID, "bad request " + std::to_string(i));
     const bool host_out = !(req->flags & ISDF_FRAG_DEVICE);
     if ((long long)request_bytes(ctx, req->n_f, host_out, req->prec) > ctx->budget / ctx->max_inflight)
@@ -3014,7 +3017,7 @@ isdf_status isdf_load(isdf_ctx* out, const char* path, void* hip_stream) {
     HIPCHK(hipMemcpy(c->w.p, p + xb + mb, mb, hipMemcpyHostToDevice));
     c->rank_h = rk;
     // the operand copies of W for the fragment GEMMs
-    HIPCHK(wt_convert_launch(c->w.as<cplx>(), c->wt64.as<cplx>(), c->wt32.as<float>(), c->wt16.as<unsigned short>(),
+    HIPCHK(wt_convert_launch(c->w.as<cplx>(), c->wt64.as<cplx>(), c->wt32.as<float>(), c->wt16.as<unsigned short>(), c->wt16s.as<unsigned short>(),
                              c->nip, (int)c->ld_ip, c->nh, c->qmap.as<int>() + c->nk + c->nh, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     c->fitted = true;

@@ -91,6 +91,10 @@ hipError_t eri_scatter_batch_launch(const cplx* e, const long long* eoff, cplx* 
 // big_launch for precision 2; plan with big_plan.
 hipError_t x3_launch(int conj, const NtDesc* descs_dev, int ndesc, long long total, int max_blocks, int seg,
                      hipStream_t s, int kind);
+// The same kernel on the single-bf16 operand format (fmt 3): kind 2 without
+// conjugation (U^q) and kind 3 with B conjugated (the contraction) only.
+hipError_t x1_launch(int conj, const NtDesc* descs_dev, int ndesc, long long total, int max_blocks, int seg,
+                     hipStream_t s, int kind);
 // mixed-precision fragment contraction: classes {q, -q} summed in FP32 per
 // launch (one contiguous K range of at most ERI_QGROUP * ld, the classes
 // split into balanced groups), FP64 across launches (the max ERI error at
@@ -105,10 +109,10 @@ constexpr int FRAG_WG_PER_CU = 2;
 
 // W (c128 [h][n][n], one q per class {q, -q}) -> transposed copies
 // Wt[h][J][I] = w_h W[h][I][J], w_h = 1/2 where q = -q (hself: device), with
-// row pitch ld in c128, two-float-plane and four-bf16-plane formats (any
-// output pointer may be null); pad columns are zero.
-hipError_t wt_convert_launch(const cplx* w, cplx* wt64, float* wt32, unsigned short* wt16, int n,
-                             int ld, int nh, const int* hself, hipStream_t s);
+// row pitch ld in c128, two-float-plane, four-bf16-plane and two-bf16-plane
+// formats (any output pointer may be null); pad columns are zero.
+hipError_t wt_convert_launch(const cplx* w, cplx* wt64, float* wt32, unsigned short* wt16, unsigned short* wt16s,
+                             int n, int ld, int nh, const int* hself, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // k-mesh transforms (Algorithm 1 and 2 in the k/R domain), LDS-staged.

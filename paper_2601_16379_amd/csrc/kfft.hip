@@ -727,6 +727,34 @@ __global__ __launch_bounds__(256, 2) void pair_reg_kernel(PairArgs a, int nblock
     }
     return;
   }
+  if (a.fmt == 3) {
+    // single bf16: each row (q) of the chunk is 64 points x 4 bytes = 256
+    // contiguous bytes; rows assembled in LDS, 8 at a time, written with
+    // 16-byte stores (four rows per wave instruction)
+    unsigned short (*st3)[256] = stage[threadIdx.x >> 6];
+    const int e3 = (lane >> 3) * 16 + (lane & 7);
+#pragma unroll
+    for (int Q0 = 0; Q0 < NK; Q0 += 8) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (Q0 + u >= NK) break;
+        st3[u][e3] = bf16_bits_of(x[Q0 + u].x * sc);
+        st3[u][e3 + 8] = bf16_bits_of(x[Q0 + u].y * sc);
+      }
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int u = 4 * h + (lane >> 4), part = lane & 15;   // row u, 16-byte part
+        const int sq = Q0 + u < NK ? a.qslot[Q0 + u] : -1;
+        if (sq >= 0 && (part >> 1) * 8 < nI) {
+          const uint4 v = *(const uint4*)&st3[u][part * 8];
+          *(uint4*)((unsigned short*)a.out + 2 * (base + (long long)sq * a.q_stride) + part * 8) = v;
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+    return;
+  }
   // bf16 hi/lo: each row (q) of the chunk is 64 points x 8 bytes = 512
   // contiguous bytes; rows are assembled in LDS, 8 at a time, and written
   // with 16-byte stores (two rows per wave instruction)

@@ -51,10 +51,10 @@ __global__ void nonfinite_kernel(const cplx* __restrict__ x, long long n, int* f
   if (bad) atomicOr(flag, 1);
 }
 
-// Wt[h][J][I] = w_h W[h][I][J] in the three operand formats (row pitch ld,
+// Wt[h][J][I] = w_h W[h][I][J] in the four operand formats (row pitch ld,
 // zero padding for I >= n), w_h = 1/2 where q = -q (hself[h]).
 __global__ void wt_convert_kernel(const cplx* __restrict__ w, cplx* wt64, float* wt32, unsigned short* wt16,
-                                  int n, int ld, int nh, const int* __restrict__ hself) {
+                                  unsigned short* wt16s, int n, int ld, int nh, const int* __restrict__ hself) {
   const long long total = (long long)nh * n * ld;
   for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
        idx += (long long)gridDim.x * blockDim.x) {
@@ -68,6 +68,7 @@ __global__ void wt_convert_kernel(const cplx* __restrict__ w, cplx* wt64, float*
     if (wt64) wt64[idx] = v;
     if (wt32) store_fmt(wt32, idx, total, 1, v);
     if (wt16) store_fmt(wt16, idx, total, 2, v);
+    if (wt16s) store_fmt(wt16s, idx, total, 3, v);
   }
 }
 
@@ -114,10 +115,10 @@ hipError_t nonfinite_launch(const cplx* x, long long n, int* flag, hipStream_t s
   return hipGetLastError();
 }
 
-hipError_t wt_convert_launch(const cplx* w, cplx* wt64, float* wt32, unsigned short* wt16, int n,
-                             int ld, int nh, const int* hself, hipStream_t s) {
+hipError_t wt_convert_launch(const cplx* w, cplx* wt64, float* wt32, unsigned short* wt16, unsigned short* wt16s,
+                             int n, int ld, int nh, const int* hself, hipStream_t s) {
   hipLaunchKernelGGL(wt_convert_kernel, dim3(grid_for((long long)nh * n * ld)), dim3(256), 0, s, w,
-                     wt64, wt32, wt16, n, ld, nh, hself);
+                     wt64, wt32, wt16, wt16s, n, ld, nh, hself);
   return hipGetLastError();
 }
 

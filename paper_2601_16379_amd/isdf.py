@@ -18,8 +18,8 @@ ISDF_OK = 0
 STATUS = {0: "ISDF_OK", -1: "ISDF_E_INVALID", -2: "ISDF_E_NOMEM", -3: "ISDF_E_STATE",
           -4: "ISDF_E_NUMERIC", -5: "ISDF_E_DEVICE", -6: "ISDF_E_BUSY",
           -7: "ISDF_E_NOTFOUND", -8: "ISDF_E_CANCELLED"}
-ISDF_FP64, ISDF_MIXED_FP32, ISDF_MIXED_BF16X3 = 0, 1, 2
-PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+ISDF_FP64, ISDF_MIXED_FP32, ISDF_MIXED_BF16X3, ISDF_MIXED_BF16 = 0, 1, 2, 3
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16": 3}
 ISDF_INPUT_DEVICE = 0x1
 ISDF_NO_PIVOT = 0x2
 ISDF_ZETA_ROUTE = 0x4

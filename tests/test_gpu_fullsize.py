@@ -357,13 +357,16 @@ def test_large_cell_small_fragments_oracle(bigcell):
     ref = [ko.fragment_eri(b.x, c, w, cfg.kmesh) for c in frags]
     out64 = b.ctx.fragment_eri(frags, "fp64")
     out16 = b.ctx.fragment_eri(frags, "bf16x3")
-    for c, r, o64, o16 in zip(frags, ref, out64, out16):
+    out1 = b.ctx.fragment_eri(frags, "bf16")
+    for c, r, o64, o16, o1 in zip(frags, ref, out64, out16, out1):
         rel = _rel(o64, r)
         err = float(np.max(np.abs(o16 - r)))
-        print("%s n_f %d: FP64 rel %.2e, bf16x3 max|dV| %.2e Eh (max|V| %.2e)"
-              % (name, c.shape[2], rel, err, np.abs(r).max()))
+        err1 = float(np.max(np.abs(o1 - r)))
+        print("%s n_f %d: FP64 rel %.2e, bf16x3 max|dV| %.2e Eh, bf16 %.2e Eh (max|V| %.2e)"
+              % (name, c.shape[2], rel, err, err1, np.abs(r).max()))
         assert rel < 1e-10
         assert err < 1e-6
+        assert err1 < 1e-6
 
 
 @pytest.mark.timeout(900)
@@ -377,10 +380,13 @@ def test_large_cell_stream_fragments_mixed_vs_fp64(bigcell):
     dev = [torch.from_numpy(c).cuda() for c in frags]
     o64 = b.ctx.fragment_eri(dev, "fp64")
     o16 = b.ctx.fragment_eri(dev, "bf16x3")
-    for c, a, m in zip(frags, o64, o16):
+    o1 = b.ctx.fragment_eri(dev, "bf16")
+    for c, a, m, m1 in zip(frags, o64, o16, o1):
         err = float((a - m).abs().max().item())
-        print("%s n_f %d: bf16x3 vs FP64 max|dV| %.2e Eh (max|V| %.2e)"
-              % (name, c.shape[2], err, float(a.abs().max().item())))
+        err1 = float((a - m1).abs().max().item())
+        print("%s n_f %d: vs FP64 max|dV| bf16x3 %.2e Eh, bf16 %.2e Eh (max|V| %.2e)"
+              % (name, c.shape[2], err, err1, float(a.abs().max().item())))
         assert err < 1e-6
-    del o64, o16, dev
+        assert err1 < 1e-6
+    del o64, o16, o1, dev
     torch.cuda.empty_cache()

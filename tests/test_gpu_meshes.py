@@ -135,7 +135,35 @@ def test_mixed_path_on_mesh_within_1e6(name, prec):
     ctx.close()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "bf16x3", "fp32"])
+# single-bf16 fragment GEMMs (operands rounded to bf16, 2^-9 relative): the
+# error is a fraction of the largest ERI, not an absolute bound.  The CPU
+# emulation of the same rounding (bf16 operands, FP32 products) on these
+# cells gives 6e-4-9e-3 of max |V| (the larger values where cond(Pi^q) is
+# 5e5 and W has large entries that cancel), the GPU 3.5e-4-1.6e-2; 3e-2
+# allows for the accumulation order.  Any error in the kernel's indexing,
+# conjugation or format is O(1).
+BF16_REL = 3e-2
+
+
+@pytest.mark.parametrize("name", MESHES + ["t_cond_k8", "t_grid18_k2", "t_grid20_k3"])
+def test_single_bf16_path_on_mesh(name):
+    """Single-bf16 fragment GEMMs (register and LDS pair transforms, the
+    single-bf16 GEMM format) against the FP64 oracle, relative to the
+    largest ERI."""
+    f = fit(name)
+    ctx = f.ctx()
+    ctx.fit("bf16")
+    ctx.coulomb_kernel("bf16")
+    out = ctx.fragment_eri(f.frags, "bf16")
+    for i, cf in enumerate(f.frags):
+        vmax = float(np.max(np.abs(f.ref[i])))
+        rel = float(np.max(np.abs(out[i] - f.ref[i]))) / vmax
+        print("%s bf16 frag %d n_f %d max|dV| / max|V| %.2e (max|V| %.3e Eh)" % (name, i, cf.shape[2], rel, vmax))
+        assert rel < BF16_REL
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3", "fp32", "bf16"])
 @pytest.mark.parametrize("name,blocks", [("t_small_k3", 3), ("t_m4_k16", 4), ("t_k10_line", 5),
                                          ("t_k6_cube", 2)])
 def test_pair_blocks_equal_unblocked_bitwise(name, blocks, prec):
@@ -152,6 +180,8 @@ def test_pair_blocks_equal_unblocked_bitwise(name, blocks, prec):
         assert np.array_equal(blk[i], ref[i]), (i, cf.shape[2])
         if prec == "fp64":
             assert _rel(blk[i], f.ref[i]) < FP64_REL
+        elif prec == "bf16":
+            assert _rel(blk[i], f.ref[i]) < BF16_REL
         else:
             assert float(np.max(np.abs(blk[i] - f.ref[i]))) < MIXED_EH
     ctx.close()
