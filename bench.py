@@ -102,12 +102,13 @@ def frag_flops(cfg, n):
     return 8.0 * nh * nip * nip * n * n + 8.0 * nh * nip * (n * n) * (n * n + 1) / 2
 
 
-def stage_work(stage, cfg, nfs, prec):
+def stage_work(stage, cfg, nfs, prec, passes=1):
     """(bound, algorithmic amount, unit, peak) of a stage over the fragments
     nfs (fragment stages) or one fit + kernel.  The k-space stages (T^k, the
     k convolutions' inputs) count all N_k; everything indexed by q counts the
     nh classes {q, -q} it runs over.  The fit and the kernel are FP64 in
-    every precision (16 bytes a value)."""
+    every precision (16 bytes a value).  passes: q batches of a kernel whose
+    eta does not fit at once (the RHS is formed again in each)."""
     nk, nip, ng, norb = cfg.n_k, cfg.n_ip, cfg.n_g, cfg.n_orb
     nh = n_classes(cfg.kmesh)
     s2 = sum(n * n for n in nfs)
@@ -125,10 +126,10 @@ def stage_work(stage, cfg, nfs, prec):
         return "mfma", 8.0 * nh * nip * nip * ng / 2 / 1e12, "TFLOP", PEAK["fp64"]
     if stage == "grid_fft":   # two read+write passes over eta (c128)
         return "hbm", 4.0 * nh * nip * ng * 16 / 1e9, "GB", PEAK["hbm"]
-    if stage == "rhs_t":      # T^k_I(r) = X^k conj(phi^k): written once per q batch pass
-        return "hbm", 1.0 * nk * nip * ng * 16 / 1e9, "GB", PEAK["hbm"]
-    if stage == "rhs_kconv":  # T^k_I(r) read (all k), eta written once (nh classes)
-        return "hbm", (nk + nh) * nip * ng * 16 / 1e9, "GB", PEAK["hbm"]
+    if stage == "rhs_t":      # T^k_I(r) = X^k conj(phi^k): formed once per q-batch pass (FP64 FMAs)
+        return "fp64", passes * 8.0 * nk * nip * ng * norb / 1e12, "TFLOP", PEAK["fp64"]
+    if stage == "rhs_kconv":  # T^k_I(r) read (all k) once per q-batch pass, eta written once (nh classes)
+        return "hbm", (passes * nk + nh) * nip * ng * 16 / 1e9, "GB", PEAK["hbm"]
     if stage == "metric_kconv":
         return "hbm", (nk + nh) * nip * nip * 16 / 1e9, "GB", PEAK["hbm"]
     if stage == "chol":       # blocked factor: n^3/3 complex MACs
@@ -313,14 +314,14 @@ def roofline_entry(ctx, stage_tot, cfg, nfs, prec, steps):
     return roof
 
 
-def stage_rows(stage_tot, cfg, nfs, prec, per):
+def stage_rows(stage_tot, cfg, nfs, prec, per, passes=1):
     rows = {}
     tot_ms = sum(stage_tot[k][0] for k in STAGES if k in stage_tot)
     for s in STAGES:
         if s not in stage_tot:
             continue
         tot, cnt = stage_tot[s]
-        w = stage_work(s, cfg, nfs if s in FRAG_STAGES else [], prec)
+        w = stage_work(s, cfg, nfs if s in FRAG_STAGES else [], prec, passes)
         row = {"ms": tot / per, "intervals": cnt / per, "share": tot / tot_ms if tot_ms else 0.0}
         if w and tot > 0:
             amount = w[1] * (1 if s in FRAG_STAGES else per)
@@ -573,6 +574,8 @@ def run_stream(args, cfg, pkg, inp, np, torch):
     ctx.coulomb_kernel(args.prec)
     t_kernel = time.perf_counter() - t0 - t_fit
     fit_stages = collect_stages(ctx, FIT_STAGES)
+    st = ctx.stats()
+    rhs_passes = -(-st["classes"] // st["q_batch"])   # q batches of the kernel (eta formed in each)
     log("fit %.2f s, Coulomb kernel %.2f s" % (t_fit, t_kernel))
     free, total = torch.cuda.mem_get_info()
     budget = int(0.9 * free)
@@ -609,7 +612,8 @@ def run_stream(args, cfg, pkg, inp, np, torch):
     # fragment rate: an estimate, stated as one
     est_stream_s = sum(frag_flops(cfg, n) for n in nfs_all) / (flops_timed / wall)
     extra = {"fit_s": t_fit, "kernel_s": t_kernel,
-             "fit_kernel_stages": stage_rows(fit_stages, cfg, [], args.prec, 1),
+             "fit_kernel_stages": stage_rows(fit_stages, cfg, [], args.prec, 1, rhs_passes),
+             "rhs_passes": rhs_passes,
              "step_s": {"min": min(step_s), "median": float(np.median(step_s)), "max": max(step_s)},
              "fragment_tflops_per_s": flops_timed / wall / 1e12,
              "whole_cell_estimate": {"fragments": len(nfs_all), "stream_s": est_stream_s,

@@ -164,7 +164,10 @@ isdf_status isdf_select_points(const int32_t grid[3], const int32_t kmesh[3], in
 /*
  * The fit: X^k_{I mu} = phi^k_mu(r_I); T^k = X^k X^{k H}; Pi^q by the k
  * convolution of Algorithm 1 (|FFT_k^{-1} T|^2, FFT_k); eta^q_I(r) by the same
- * convolution of T^k_I(r) = sum_mu X^k_{I mu} conj(phi^k_mu(r)), r-tiled; then
+ * convolution of T^k_I(r) = sum_mu X^k_{I mu} conj(phi^k_mu(r)), on tiles of
+ * grid points and interpolation points of about 1 GiB each (the environment
+ * variable ISDF_RHS_TILE_BYTES, read by isdf_create, sets another size; the
+ * result does not depend on it; isdf_stats reports r_tile and ip_tile); then
  * the FP64 Cholesky factor of every Pi^q with diagonal pivoting (relative
  * tolerance 1e-13; the rank is reported by isdf_stats).  Synchronous.
  * Pi^{-q}, eta^{-q} and W^{-q} are the complex conjugates of those at q, so

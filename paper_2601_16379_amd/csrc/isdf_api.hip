@@ -9,6 +9,7 @@
 #include <cmath>
 #include <condition_variable>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <functional>
@@ -427,7 +428,8 @@ struct isdf_ctx_s {
   // isdf_coulomb_kernel instead of in isdf_fit (eta_batched)
   int qb = 0;
   bool eta_batched = false;
-  long long rc = 0;   // r-chunk of the RHS
+  long long rc = 0;   // RHS tile: rc grid points x ri interpolation points
+  int ri = 0;
   Arena arena;
   Arena arena_aux;                      // descriptors of the second stream (chol, pinv)
   StageTimer timer;
@@ -540,13 +542,15 @@ void rhs_eta(isdf_ctx c, const int* qslot, hipEvent_t start) {
   constexpr int nbuf = 2;
   HIPCHK(hipStreamWaitEvent(c->aux2, start, 0));
   int it = 0;
-  for (long long r0 = 0; r0 < ng; r0 += c->rc, ++it) {
+  for (long long r0 = 0; r0 < ng; r0 += c->rc)
+  for (int i0 = 0; i0 < nip; i0 += c->ri, ++it) {
     const int b = it % nbuf;
-    cplx* tile = c->rchunk.as<cplx>() + (long long)b * nk * nip * c->rc;
+    cplx* tile = c->rchunk.as<cplx>() + (long long)b * nk * c->ri * c->rc;
     if (it >= nbuf) HIPCHK(hipStreamWaitEvent(s, c->ev_kc[b], 0));   // tile b read by its convolution
     c->timer.begin("rhs_t", s);
     const int rcur = (int)std::min<long long>(c->rc, ng - r0);
-    HIPCHK(rhs_t_launch(c->xt.as<cplx>(), c->phi.as<cplx>(), tile, nk, norb, nip, ng, r0, rcur, s));
+    const int icur = std::min(c->ri, nip - i0);
+    HIPCHK(rhs_t_launch(c->xt.as<cplx>(), c->phi.as<cplx>(), tile, nk, norb, nip, ng, r0, rcur, i0, icur, s));
     c->timer.end("rhs_t", s);
     HIPCHK(hipEventRecord(c->ev_rt[b], s));
     HIPCHK(hipStreamWaitEvent(c->aux2, c->ev_rt[b], 0));
@@ -554,10 +558,10 @@ void rhs_eta(isdf_ctx c, const int* qslot, hipEvent_t start) {
     KconvArgs a;
     memset(&a, 0, sizeof(a));
     a.in = tile;
-    a.out = c->eta.as<cplx>() + r0;
-    a.in_kstride = (long long)nip * rcur;
+    a.out = c->eta.as<cplx>() + (long long)i0 * ng + r0;
+    a.in_kstride = (long long)icur * rcur;
     a.out_qstride = (long long)nip * ng;
-    a.n_elem = (long long)nip * rcur;
+    a.n_elem = (long long)icur * rcur;
     a.in_inner = a.n_elem;
     a.in_outer = 0;
     a.out_inner = rcur;
@@ -586,7 +590,7 @@ void ensure_fit_buffers(isdf_ctx c) {
   c->pinv_ws.ensure((size_t)c->nh * ((size_t)c->nip * 64 + 4096) * e);   // blocked L^{-1} scratch
   c->work2.ensure(m2);
   c->work3.ensure(m2);
-  c->rchunk.ensure(2 * (size_t)c->nk * c->nip * c->rc * e);   // two RHS tiles
+  c->rchunk.ensure(2 * (size_t)c->nk * c->ri * c->rc * e);   // two RHS tiles
   c->eta.ensure((size_t)c->qb * c->nip * c->ng * e);
 }
 
@@ -1576,11 +1580,27 @@ void serve_loop(isdf_ctx c) {
 #define ISDF_RHS_TILE_BYTES (1LL << 30)
 #endif
 
-long long rchunk_len(long long ng, int nk, int nip) {
-  // r tile of the right-hand side: T^k_I(r) for all k of one tile
-  long long rc = (long long)(ISDF_RHS_TILE_BYTES) / ((long long)nk * nip * (long long)sizeof(cplx));
-  rc = std::max<long long>(64, std::min<long long>(rc, ng));
-  return rc;
+// Tile of the right-hand side, T^k_I(r) for every k of rc grid points x ri
+// interpolation points, within ISDF_RHS_TILE_BYTES (the environment variable
+// of that name overrides it): every point and as many grid points as fit,
+// else (fewer than 256 grid points would fit) 256 grid points and a balanced
+// range of points, a multiple of 16 -- the pre-product reuses each X value
+// over the tile's grid points, so the grid points are kept.
+struct RhsTile { long long rc; int ri; };
+RhsTile rhs_tile(long long ng, int nk, int nip) {
+  long long budget = ISDF_RHS_TILE_BYTES;
+  if (const char* v = std::getenv("ISDF_RHS_TILE_BYTES")) {
+    const long long x = std::atoll(v);
+    if (x > 0) budget = x;
+  }
+  const long long per_point = (long long)nk * (long long)sizeof(cplx);
+  const long long rmin = std::min<long long>(ng, 256);
+  const long long rc = budget / (per_point * nip);
+  if (rc >= rmin) return {std::min(rc, ng), nip};
+  long long ri = std::max<long long>(16, budget / (per_point * rmin) / 16 * 16);
+  const long long nt = (nip + ri - 1) / ri;
+  ri = std::min<long long>(nip, ((nip + nt - 1) / nt + 15) / 16 * 16);
+  return {rmin, (int)ri};
 }
 
 // Sizes, reciprocal lattice, classes {q, -q}, the resident buffers (X, Pi,
@@ -1631,7 +1651,11 @@ void setup_context(isdf_ctx c, const double* lattice, const int32_t grid[3], con
     c->hself_h.push_back(mq == q ? 1 : 0);
   }
   c->nh = (int)c->hq_h.size();
-  c->rc = rchunk_len(ng, nk, n_ip);
+  {
+    const RhsTile t = rhs_tile(ng, nk, n_ip);
+    c->rc = t.rc;
+    c->ri = t.ri;
+  }
   if (with_orbitals) c->phi.alloc((size_t)nk * n_orb * ng * e);
   c->ip.alloc(sizeof(int) * n_ip);
   // + RHS_X_PAD elements: rhs_t_launch reads whole blocks of points
@@ -1660,7 +1684,7 @@ void setup_context(isdf_ctx c, const double* lattice, const int32_t grid[3], con
     // the fragment workspaces when it ends.  ISDF_Q_BATCH(n) caps the batch.
     const size_t per_class = (size_t)n_ip * ng * e;
     const size_t transient = 3 * m2 + (size_t)nk * n_ip * n_ip * e +
-                             (size_t)nh * ((size_t)n_ip * 64 + 4096) * e + 2 * (size_t)nk * n_ip * c->rc * e;
+                             (size_t)nh * ((size_t)n_ip * 64 + 4096) * e + 2 * (size_t)nk * c->ri * c->rc * e;
     size_t fr = 0, tot = 0;
     HIPCHK(hipMemGetInfo(&fr, &tot));
     const double avail = fr > transient ? (double)(fr - transient) : 0.0;
@@ -1786,7 +1810,10 @@ int64_t isdf_plan_bytes(const int32_t grid[3], const int32_t kmesh[3], int32_t n
   b += nh * ((long long)n_ip * 64 + 4096) * e;  // L^{-1} scratch
   b += nh * (long long)n_ip * ld * (16 + 8 + 8 + 4);  // W^T in the four operand formats
   b += nh * (long long)n_ip * ng * e;    // eta of every class (q batches need less)
-  b += 2 * nk * (long long)n_ip * rchunk_len(ng, (int)nk, n_ip) * e;  // two RHS tiles
+  {
+    const RhsTile t = rhs_tile(ng, (int)nk, n_ip);
+    b += 2 * nk * (long long)t.ri * t.rc * e;  // two RHS tiles
+  }
   b += n_ip * 4 + 2 * nh * (long long)n_ip * 4;
   return b;
 }
@@ -2373,7 +2400,8 @@ isdf_status isdf_stats(isdf_ctx ctx, char* json, int64_t cap) {
   if (!json || cap <= 0) return fail(ctx, ISDF_E_INVALID, "bad buffer");
   std::string s = "{\"n_k\":" + std::to_string(ctx->nk) + ",\"n_g\":" + std::to_string(ctx->ng) +
                   ",\"n_orb\":" + std::to_string(ctx->norb) + ",\"n_ip\":" + std::to_string(ctx->nip) +
-                  ",\"r_tile\":" + std::to_string(ctx->rc) + ",\"rank\":[";
+                  ",\"r_tile\":" + std::to_string(ctx->rc) + ",\"ip_tile\":" + std::to_string(ctx->ri) +
+                  ",\"classes\":" + std::to_string(ctx->nh) + ",\"q_batch\":" + std::to_string(ctx->qb) + ",\"rank\":[";
   // per q (the class of q or of -q; the factor of conj Pi has the same rank)
   if (!ctx->rank_h.empty())
     for (int q = 0; q < ctx->nk; ++q) {

@@ -192,13 +192,14 @@ struct PairArgs {
 };
 hipError_t pair_launch(const PairArgs& a, hipStream_t s);
 
-// out[k][I][r] = sum_mu xt[k][mu][I] conj(phi[k][mu][r0 + r]), r < rcur
-// (the right-hand side's T^k_I(r) on one tile of grid points); FP64 vector
-// units.  xt must stay readable for RHS_X_PAD elements past its end (blocks
-// of points read whole rows; the extra outputs are not stored).
+// out[k][I - i0][r] = sum_mu xt[k][mu][I] conj(phi[k][mu][r0 + r]), r < rcur,
+// i0 <= I < i0 + icur (the right-hand side's T^k_I(r) on one tile of points
+// and grid points); FP64 vector units.  xt must stay readable for RHS_X_PAD
+// elements past its end (blocks of points read whole rows; the extra outputs
+// are not stored).
 constexpr int RHS_X_PAD = 16;
 hipError_t rhs_t_launch(const cplx* xt, const cplx* phi, cplx* out, int nk, int norb, int nip, long long ng,
-                        long long r0, int rcur, hipStream_t s);
+                        long long r0, int rcur, int i0, int icur, hipStream_t s);
 // true when pair_launch takes the register path (needs item_off / nitems)
 bool pair_reg_supported(int fmt, int m1, int m2, int m3);
 // true when pair_launch takes the FP32 LDS path (mixed formats, a mesh axis

@@ -146,6 +146,130 @@ __global__ __launch_bounds__(256) void kconv_kernel(KconvArgs a, int etile) {
   }
 }
 
+// The convolution of mode 0 on a fixed M1 x M2 x M3 mesh with every line in
+// registers.  LDS holds the tile [k][etile] with one pad element after each
+// (k1, k2) row (rows of M3 etile + 1 elements, an odd stride, so the
+// lanes of a line pass fall on distinct banks).  One thread per line:
+//   axis-3 lines straight from HBM, forward DFT, to LDS;
+//   axis-2 lines, forward DFT;
+//   axis-1 lines, forward DFT, |.|^2, inverse DFT (the same line);
+//   axis-2 lines, inverse DFT;
+//   axis-3 lines, inverse DFT, straight to HBM (classes that qslot selects).
+// Four LDS passes and four barriers in all; each workgroup reads its
+// elements once and writes them once.  Tiles are mapped XCD-contiguously
+// (workgroup b runs on XCD b mod 8), so neighbouring element tiles, which
+// share cache lines, are read through one L2.
+template <int M1, int M2, int M3>
+__global__ __launch_bounds__(512) void kconv_lines_kernel(KconvArgs a, int etile, int ntiles) {
+  extern __shared__ cplx buf[];
+  constexpr int NK = M1 * M2 * M3;
+  const int per = (ntiles + 7) >> 3;
+  const int tile = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  if (tile >= ntiles) return;
+  const int eshift = __builtin_ctz(etile);
+  const int rs = M3 * etile + 1;                 // LDS row of one (k1, k2)
+  const long long e0 = (long long)tile * etile;
+  const long long rem = a.n_elem - e0;
+  const int ne = rem < etile ? (int)rem : etile;
+  const bool fast = (a.in_inner % etile == 0) && (a.out_inner % etile == 0);
+  const long long in0 = (e0 / a.in_inner) * a.in_outer + e0 % a.in_inner;
+  const long long out0 = (e0 / a.out_inner) * a.out_outer + e0 % a.out_inner;
+  const int tid = threadIdx.x, nt = blockDim.x;
+
+  // axis 3 from HBM: line (k1, k2, e)
+  for (int l = tid; l < (NK / M3) << eshift; l += nt) {
+    const int e = l & (etile - 1), k12 = l >> eshift;
+    cplx x[M3];
+    long long off = 0;
+    if (e < ne) off = fast ? in0 + e : ((e0 + e) / a.in_inner) * a.in_outer + (e0 + e) % a.in_inner;
+#pragma unroll
+    for (int j = 0; j < M3; ++j)
+      x[j] = e < ne ? a.in[(long long)(k12 * M3 + j) * a.in_kstride + off] : cmk(0.0, 0.0);
+    dft_line<M3, 1>(x);
+    cplx* p = buf + k12 * rs + e;
+#pragma unroll
+    for (int j = 0; j < M3; ++j) p[j * etile] = x[j];
+  }
+  __syncthreads();
+  // axis 2: line (k1, k3, e)
+  for (int l = tid; l < (NK / M2) << eshift; l += nt) {
+    const int e = l & (etile - 1), r = l >> eshift;
+    cplx* p = buf + (r / M3) * M2 * rs + (r % M3) * etile + e;
+    cplx x[M2];
+#pragma unroll
+    for (int j = 0; j < M2; ++j) x[j] = p[j * rs];
+    dft_line<M2, 1>(x);
+#pragma unroll
+    for (int j = 0; j < M2; ++j) p[j * rs] = x[j];
+  }
+  __syncthreads();
+  // axis 1: line (k2, k3, e); T^R -> |T^R|^2 -> back along the same line
+  for (int l = tid; l < (NK / M1) << eshift; l += nt) {
+    const int e = l & (etile - 1), r = l >> eshift;
+    cplx* p = buf + (r / M3) * rs + (r % M3) * etile + e;
+    cplx x[M1];
+#pragma unroll
+    for (int j = 0; j < M1; ++j) x[j] = p[j * M2 * rs];
+    dft_line<M1, 1>(x);
+#pragma unroll
+    for (int j = 0; j < M1; ++j) x[j] = cmk(x[j].x * x[j].x + x[j].y * x[j].y, 0.0);
+    dft_line<M1, 1>(x);
+#pragma unroll
+    for (int j = 0; j < M1; ++j) p[j * M2 * rs] = x[j];
+  }
+  __syncthreads();
+  for (int l = tid; l < (NK / M2) << eshift; l += nt) {
+    const int e = l & (etile - 1), r = l >> eshift;
+    cplx* p = buf + (r / M3) * M2 * rs + (r % M3) * etile + e;
+    cplx x[M2];
+#pragma unroll
+    for (int j = 0; j < M2; ++j) x[j] = p[j * rs];
+    dft_line<M2, 1>(x);
+#pragma unroll
+    for (int j = 0; j < M2; ++j) p[j * rs] = x[j];
+  }
+  __syncthreads();
+  // axis 3 to HBM: line (q1, q2, e)
+  for (int l = tid; l < (NK / M3) << eshift; l += nt) {
+    const int e = l & (etile - 1), q12 = l >> eshift;
+    if (e >= ne) continue;
+    const cplx* p = buf + q12 * rs + e;
+    cplx x[M3];
+#pragma unroll
+    for (int j = 0; j < M3; ++j) x[j] = p[j * etile];
+    dft_line<M3, 1>(x);
+    const long long off = fast ? out0 + e : ((e0 + e) / a.out_inner) * a.out_outer + (e0 + e) % a.out_inner;
+#pragma unroll
+    for (int j = 0; j < M3; ++j) {
+      const int q0 = q12 * M3 + j;
+      const int q = a.qslot ? a.qslot[q0] : q0;
+      if (q < 0) continue;
+      const cplx r = cscale(x[j], a.scale);
+      if (a.out32) a.out32[(long long)q * a.out_qstride + off] = make_float2((float)r.x, (float)r.y);
+      else a.out[(long long)q * a.out_qstride + off] = r;
+    }
+  }
+}
+
+template <int M1, int M2, int M3>
+hipError_t kconv_lines_launch(const KconvArgs& a, hipStream_t s) {
+  constexpr int NK = M1 * M2 * M3;
+  constexpr int LMAX = NK / (M1 < M2 ? (M1 < M3 ? M1 : M3) : (M2 < M3 ? M2 : M3));   // most lines of one axis
+  // largest power-of-two element tile with at most 512 lines an axis pass
+  // and at most 80 KB of LDS (two workgroups a CU)
+  int etile = 1;
+  while (LMAX * etile * 2 <= 512 && (size_t)M1 * M2 * (M3 * etile * 2 + 1) * sizeof(cplx) <= 80 * 1024) etile *= 2;
+  const long long ntiles = (a.n_elem + etile - 1) / etile;
+  if (ntiles <= 0) return hipSuccess;
+  if (ntiles > (1LL << 28)) return hipErrorInvalidValue;
+  const long long blocks = ((ntiles + 7) / 8) * 8;
+  const int threads = (LMAX * etile + 63) / 64 * 64;
+  const size_t lds = (size_t)M1 * M2 * (M3 * etile + 1) * sizeof(cplx);
+  hipLaunchKernelGGL((kconv_lines_kernel<M1, M2, M3>), dim3((unsigned)blocks), dim3(threads), lds, s, a, etile,
+                     (int)ntiles);
+  return hipGetLastError();
+}
+
 // The exchange convolution of eq. (10), in place:
 //   rho[k][e] <- scale * sum_R exp(+i k.R) Wt(R) rhot(R),
 //   rhot(R) = sum_k exp(-i k.R) rho[k][e],  Wt(R) = sum_q exp(+i q.R) W^q[e],
@@ -825,6 +949,11 @@ hipError_t kconv_launch(const KconvArgs& a, hipStream_t s) {
     if (a.m1 == 1) return kconv_reg_m2<1>(a, s);
     if (a.m1 == 2) return kconv_reg_m2<2>(a, s);
     return kconv_reg_m2<4>(a, s);
+  }
+  if (a.mode == 0 && a.m1 == a.m2 && a.m2 == a.m3) {
+    if (a.m1 == 6) return kconv_lines_launch<6, 6, 6>(a, s);
+    if (a.m1 == 8) return kconv_lines_launch<8, 8, 8>(a, s);
+    if (a.m1 == 10) return kconv_lines_launch<10, 10, 10>(a, s);
   }
   const int nk = a.m1 * a.m2 * a.m3;
   if (a.m1 > MAXM || a.m2 > MAXM || a.m3 > MAXM) return hipErrorInvalidValue;
