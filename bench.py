@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--alt-prec", default="bf16", choices=["", "fp64", "fp32", "bf16x3", "bf16"],
                     help="second precision timed on the same slices of the fragment stream (reported "
                          "apart, with its own error against FP64); '' for none")
+    ap.add_argument("--wg-per-cu", type=int, default=0,
+                    help="workgroups per CU of the fragment GEMMs (1: ring pipeline; 0: the context's default)")
     ap.add_argument("--slice", type=int, default=4,
                     help="fragments per timed step of the large cells (a fixed slice of the stream)")
     ap.add_argument("--no-fp64-ref", action="store_true")
@@ -579,6 +581,10 @@ def run_stream(args, cfg, pkg, inp, np, torch):
     log("fit %.2f s, Coulomb kernel %.2f s" % (t_fit, t_kernel))
     free, total = torch.cuda.mem_get_info()
     budget = int(0.9 * free)
+    if args.wg_per_cu:
+        nh = n_classes(cfg.kmesh)
+        nl = -(-nh // 12)
+        ctx.set_tiling(-(-nh // nl), args.wg_per_cu)   # the initial classes per launch
     ctx.serve_start(max_inflight=1, max_batch=args.max_batch or S, budget_bytes=budget)
 
     def step(sl, prec, buf):

@@ -306,10 +306,13 @@ isdf_status isdf_graph_destroy(isdf_graph g);
  * CU of the persistent tile loops.  isdf_autotune runs the batch (device
  * pointers, as isdf_graph_create) under each candidate -- the N_h classes in
  * one, two or three launches and the initial tiling (at most 12 classes a
- * launch), times {2, 4, 8} workgroups per CU --, twice each after a warm-up,
- * keeps the fastest
- * for this context and, when `report` is not NULL, fills it.  The eri[f] hold
- * the last candidate's results afterwards.  isdf_set_tiling sets the two
+ * launch), times {1, 2, 4, 8} workgroups per CU --, twice each after a
+ * warm-up, keeps the fastest for this context and, when `report` is not
+ * NULL, fills it.  One workgroup per CU selects the ring pipeline of the
+ * mixed-precision fragment GEMMs (four LDS stages, the next stage's
+ * fragments read during the current stage's MFMAs, one barrier a stage);
+ * its results equal those of the two-stage pipeline bit for bit.  The eri[f]
+ * hold the last candidate's results afterwards.  isdf_set_tiling sets the two
  * values directly (wg_per_cu 0 = 8 per CU).  A context starts at 12 classes
  * a launch and 2 workgroups per CU, the tuner's choice on a 4x4x4 mesh with
  * 64 fragments of 12-40 orbitals.  Results of every tiling

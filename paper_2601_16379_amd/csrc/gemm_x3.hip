@@ -64,9 +64,13 @@ __device__ inline bf8 as_bf8(u4 v) { return __builtin_bit_cast(bf8, v); }
 // wait until at most n stages of copies (2 * NCOPY instructions each) are in flight
 __device__ inline void wait_copies(int n) {
   static_assert(2 * NCOPY == 8, "vmcnt below counts 8 copies a stage");
-  if (n >= 1) asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
+  if (n >= 2) asm volatile("s_waitcnt vmcnt(16)" ::: "memory");
+  else if (n == 1) asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
   else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
+
+// The ring pipeline: one workgroup a CU, RING LDS stage buffers
+constexpr int RING = 4;
 
 __device__ inline int isqrt_floor(long long x) {
   long long r = (long long)sqrt((double)x);
@@ -388,9 +392,103 @@ __device__ inline void tile_body(const NtDesc& d, int b, int m0, int n0, int kcu
   if (!idle) tile_epilogue<F, NI, NJ>(d, b, m0, n0, rb0, cb0, c_re, c_im, smem, wave, lane, first);
 }
 
-template <int F, bool A_CONJ, bool B_CONJ, int KIND>
+// The MFMAs of one stage of fragments (both column blocks).
+template <int F, int NI, int NJ, bool A_CONJ, bool B_CONJ>
+__device__ inline void stage_mma(const Frag<NI, NJ>& f, f16v (&c_re)[NI][NJ], f16v (&c_im)[NI][NJ]) {
+  if constexpr (F == 2) {
+    mma_half<NI, NJ, A_CONJ, B_CONJ>(f, 0, c_re, c_im);
+    if (NJ == 2) mma_half<NI, NJ, A_CONJ, B_CONJ>(f, NJ - 1, c_re, c_im);
+  } else {
+    mma_single<NI, NJ, A_CONJ, B_CONJ>(f, 0, c_re, c_im);
+    if (NJ == 2) mma_single<NI, NJ, A_CONJ, B_CONJ>(f, NJ - 1, c_re, c_im);
+  }
+}
+
+// One step of the ring pipeline: the MFMAs of stage s (fragments in `cur`)
+// while the fragments of stage s + 1 are read from LDS into `nxt`.  Before
+// them: stage s + 1 has landed (this wave's copies, then the barrier for
+// everyone's), and every wave has read stage s, so its buffer takes the
+// copies of stage s + RING.  One barrier a stage; the copies run up to
+// RING - 1 stages ahead of the MFMAs.
+template <int F, int NI, int NJ, bool A_CONJ, bool B_CONJ>
+__device__ inline void ring_step(int s, int nst, int kcur, Frag<NI, NJ>& cur, Frag<NI, NJ>& nxt,
+                                 f16v (&c_re)[NI][NJ], f16v (&c_im)[NI][NJ],
+                                 const unsigned short* const (&asrc)[NCOPY],
+                                 const unsigned short* const (&bsrc)[NCOPY], const int (&gslot)[NCOPY],
+                                 int rb0, int cb0, char* smem, int wave, int lr, int lk, bool idle) {
+  constexpr int SK = Fmt<F>::K;
+  const bool more = s + 1 < nst;
+  if (more) {
+    // copies issued so far: stages up to min(nst, s + RING) - 1
+    const int last = (nst < s + RING ? nst : s + RING) - 1;
+    wait_copies(last - (s + 1));
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    if (s + RING < nst) {
+      char* buf = smem + (s % RING) * STAGE_B;
+      stage_copy<F>(asrc, gslot, (s + RING) * SK, kcur, buf, wave);
+      stage_copy<F>(bsrc, gslot, (s + RING) * SK, kcur, buf + OPER_B, wave);
+    }
+    const char* nb = smem + ((s + 1) % RING) * STAGE_B;
+    read_frags_a<F>(nb, nxt, rb0, lr, lk);
+    read_frags_b<F>(nb, nxt, cb0, lr, lk);
+  }
+  if (!idle) stage_mma<F, NI, NJ, A_CONJ, B_CONJ>(cur, c_re, c_im);
+  if (more) {
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    settle(nxt);
+  }
+}
+
+// K loop and epilogue of one tile on the ring pipeline (same blocks, MFMA
+// order and epilogues as tile_body, so the same results bit for bit).
+template <int F, int NI, int NJ, bool A_CONJ, bool B_CONJ>
+__device__ inline void tile_body_ring(const NtDesc& d, int b, int m0, int n0, int kcur,
+                                      const unsigned short* const (&asrc)[NCOPY],
+                                      const unsigned short* const (&bsrc)[NCOPY], const int (&gslot)[NCOPY],
+                                      int rb0, int cb0, char* smem, int wave, int lane, bool idle, bool first) {
+  const int lr = lane & 31, lk = lane >> 5;
+  f16v c_re[NI][NJ], c_im[NI][NJ];
+#pragma unroll
+  for (int i = 0; i < NI; ++i)
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        c_re[i][j][v] = 0.f;
+        c_im[i][j][v] = 0.f;
+      }
+  constexpr int SK = Fmt<F>::K;
+  const int nst = (kcur + SK - 1) / SK;
+  __syncthreads();                        // LDS of the previous tile no longer read
+#pragma unroll
+  for (int s = 0; s < RING; ++s)
+    if (s < nst) {
+      stage_copy<F>(asrc, gslot, s * SK, kcur, smem + s * STAGE_B, wave);
+      stage_copy<F>(bsrc, gslot, s * SK, kcur, smem + s * STAGE_B + OPER_B, wave);
+    }
+  // stage 0 landed: the later stages of the prologue may be in flight
+  wait_copies((nst < RING ? nst : RING) - 1);
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+  Frag<NI, NJ> f0, f1;
+  read_frags_a<F>(smem, f0, rb0, lr, lk);
+  read_frags_b<F>(smem, f0, cb0, lr, lk);
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  settle(f0);
+  for (int s = 0; s < nst; s += 2) {
+    ring_step<F, NI, NJ, A_CONJ, B_CONJ>(s, nst, kcur, f0, f1, c_re, c_im, asrc, bsrc, gslot, rb0, cb0, smem, wave,
+                                         lr, lk, idle);
+    if (s + 1 < nst)
+      ring_step<F, NI, NJ, A_CONJ, B_CONJ>(s + 1, nst, kcur, f1, f0, c_re, c_im, asrc, bsrc, gslot, rb0, cb0, smem,
+                                           wave, lr, lk, idle);
+  }
+  if (!idle) tile_epilogue<F, NI, NJ>(d, b, m0, n0, rb0, cb0, c_re, c_im, smem, wave, lane, first);
+}
+
+template <int F, bool A_CONJ, bool B_CONJ, int KIND, bool RINGP>
 __device__ inline void x3_tiles(const NtDesc* __restrict__ descs, int ndesc, long long total_tiles, int seg) {
-  extern __shared__ __attribute__((aligned(16))) char smem[];   // NBUF stages x (A, B)
+  extern __shared__ __attribute__((aligned(16))) char smem[];   // NBUF (RING) stages x (A, B)
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -444,28 +542,47 @@ __device__ inline void x3_tiles(const NtDesc* __restrict__ descs, int ndesc, lon
     // skips lie above the diagonal, which the consumers never read)
     const bool diag = d.herm && tm == tn && d.epi != 3;
     const bool first = seg == 0;
-    if (d.M - m0 <= 32)
-      tile_body<F, 1, 1, A_CONJ, B_CONJ>(d, b, m0, n0, kcur, asrc, bsrc, gslot, 0, wave * 32, smem, wave, lane,
-                                         diag && wave > 0, first);
-    else if (d.N - n0 <= 32)
-      tile_body<F, 1, 1, A_CONJ, B_CONJ>(d, b, m0, n0, kcur, asrc, bsrc, gslot, wave * 32, 0, smem, wave, lane,
-                                         false, first);
-    else
-      tile_body<F, 2, 2, A_CONJ, B_CONJ>(d, b, m0, n0, kcur, asrc, bsrc, gslot, wm * 64, wn * 64, smem, wave, lane,
-                                         diag && wm < wn, first);
+    if constexpr (RINGP) {
+      if (d.M - m0 <= 32)
+        tile_body_ring<F, 1, 1, A_CONJ, B_CONJ>(d, b, m0, n0, kcur, asrc, bsrc, gslot, 0, wave * 32, smem, wave,
+                                                lane, diag && wave > 0, first);
+      else if (d.N - n0 <= 32)
+        tile_body_ring<F, 1, 1, A_CONJ, B_CONJ>(d, b, m0, n0, kcur, asrc, bsrc, gslot, wave * 32, 0, smem, wave,
+                                                lane, false, first);
+      else
+        tile_body_ring<F, 2, 2, A_CONJ, B_CONJ>(d, b, m0, n0, kcur, asrc, bsrc, gslot, wm * 64, wn * 64, smem,
+                                                wave, lane, diag && wm < wn, first);
+    } else {
+      if (d.M - m0 <= 32)
+        tile_body<F, 1, 1, A_CONJ, B_CONJ>(d, b, m0, n0, kcur, asrc, bsrc, gslot, 0, wave * 32, smem, wave, lane,
+                                           diag && wave > 0, first);
+      else if (d.N - n0 <= 32)
+        tile_body<F, 1, 1, A_CONJ, B_CONJ>(d, b, m0, n0, kcur, asrc, bsrc, gslot, wave * 32, 0, smem, wave, lane,
+                                           false, first);
+      else
+        tile_body<F, 2, 2, A_CONJ, B_CONJ>(d, b, m0, n0, kcur, asrc, bsrc, gslot, wm * 64, wn * 64, smem, wave,
+                                           lane, diag && wm < wn, first);
+    }
   }
 }
 
 template <bool A_CONJ, bool B_CONJ, int KIND>
 __global__ __launch_bounds__(XNT, 2) void zgemm_x3_kernel(const NtDesc* __restrict__ descs, int ndesc,
                                                           long long total_tiles, int seg) {
-  x3_tiles<2, A_CONJ, B_CONJ, KIND>(descs, ndesc, total_tiles, seg);
+  x3_tiles<2, A_CONJ, B_CONJ, KIND, false>(descs, ndesc, total_tiles, seg);
 }
 
 template <bool A_CONJ, bool B_CONJ, int KIND>
 __global__ __launch_bounds__(XNT, 2) void zgemm_x1_kernel(const NtDesc* __restrict__ descs, int ndesc,
                                                           long long total_tiles, int seg) {
-  x3_tiles<3, A_CONJ, B_CONJ, KIND>(descs, ndesc, total_tiles, seg);
+  x3_tiles<3, A_CONJ, B_CONJ, KIND, false>(descs, ndesc, total_tiles, seg);
+}
+
+// ring pipeline (one workgroup a CU): the fragment GEMMs, both formats
+template <int F, bool A_CONJ, bool B_CONJ, int KIND>
+__global__ __launch_bounds__(XNT, 1) void zgemm_ring_kernel(const NtDesc* __restrict__ descs, int ndesc,
+                                                            long long total_tiles, int seg) {
+  x3_tiles<F, A_CONJ, B_CONJ, KIND, true>(descs, ndesc, total_tiles, seg);
 }
 
 template <int KIND>
@@ -497,23 +614,44 @@ hipError_t launch_x1(int conj, const NtDesc* descs, int ndesc, long long total, 
   return hipGetLastError();
 }
 
+// ring pipeline: the same two call sites, either format
+template <int F>
+hipError_t launch_ring(int conj, const NtDesc* descs, int ndesc, long long total, int blocks, int seg, int kind,
+                       hipStream_t s) {
+  dim3 g(blocks), b(XNT);
+  const size_t lds = RING * STAGE_B;
+  if (kind == 2 && (conj & 3) == 0)
+    hipLaunchKernelGGL((zgemm_ring_kernel<F, false, false, 2>), g, b, lds, s, descs, ndesc, total, seg);
+  else if (kind == 3 && (conj & 3) == 2)
+    hipLaunchKernelGGL((zgemm_ring_kernel<F, false, true, 3>), g, b, lds, s, descs, ndesc, total, seg);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
 }  // namespace
 
+bool ring_supported(int conj, int kind) {
+  return (kind == 2 && (conj & 3) == 0) || (kind == 3 && (conj & 3) == 2);
+}
+
 hipError_t x1_launch(int conj, const NtDesc* descs_dev, int ndesc, long long total, int max_blocks, int seg,
-                     hipStream_t s, int kind) {
+                     hipStream_t s, int kind, bool ring) {
   if (total <= 0) return hipSuccess;
   const long long t8 = (total + 7) / 8 * 8;
   max_blocks = max_blocks / 8 * 8;
   const int blocks = (int)(t8 < max_blocks ? t8 : max_blocks);
+  if (ring) return launch_ring<3>(conj, descs_dev, ndesc, total, blocks, seg, kind, s);
   return launch_x1(conj, descs_dev, ndesc, total, blocks, seg, kind, s);
 }
 
 hipError_t x3_launch(int conj, const NtDesc* descs_dev, int ndesc, long long total, int max_blocks, int seg,
-                     hipStream_t s, int kind) {
+                     hipStream_t s, int kind, bool ring) {
   if (total <= 0) return hipSuccess;
   const long long t8 = (total + 7) / 8 * 8;
   max_blocks = max_blocks / 8 * 8;
   const int blocks = (int)(t8 < max_blocks ? t8 : max_blocks);
+  if (ring) return launch_ring<2>(conj, descs_dev, ndesc, total, blocks, seg, kind, s);
   switch (kind) {
     case 1: return launch_x3<1>(conj, descs_dev, ndesc, total, blocks, seg, s);
     case 2: return launch_x3<2>(conj, descs_dev, ndesc, total, blocks, seg, s);

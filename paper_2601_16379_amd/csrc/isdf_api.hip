@@ -247,8 +247,13 @@ void run_big(Arena& ar, int prec, int conj, std::vector<NtDesc>& d, int nseg, hi
   NtDesc* dd = ar.put(d.data(), d.size(), s);
   for (int seg = 0; seg < nseg; ++seg) {
     if (mark) mark(true);
-    HIPCHK(prec == 2   ? x3_launch(conj, dd, (int)d.size(), total, gemm_blocks(), seg, s, kind)
-           : prec == 3 ? x1_launch(conj, dd, (int)d.size(), total, gemm_blocks(), seg, s, kind)
+    // the ring pipeline of the bf16 kernels (one workgroup a CU): always for
+    // U^q = R^q W^q (kind 2), for the contraction when the tiling asks for
+    // one workgroup a CU
+    const bool ring = (prec == 2 || prec == 3) && ring_supported(conj, kind) && (kind == 2 || t_wg_per_cu == 1);
+    const int blocks = ring ? max_gemm_blocks() / 8 : gemm_blocks();
+    HIPCHK(prec == 2   ? x3_launch(conj, dd, (int)d.size(), total, blocks, seg, s, kind, ring)
+           : prec == 3 ? x1_launch(conj, dd, (int)d.size(), total, blocks, seg, s, kind, ring)
                        : big_launch(prec, conj, dd, (int)d.size(), total, gemm_blocks(), seg, s, kind));
     if (mark) mark(false);
   }
@@ -2228,7 +2233,7 @@ isdf_status isdf_autotune(isdf_ctx ctx, isdf_precision prec, int32_t n_frag, con
     for (int nl = 1; nl <= 3 && nl <= nh; ++nl) groups.push_back((nh + nl - 1) / nl);
     std::sort(groups.begin(), groups.end());
     groups.erase(std::unique(groups.begin(), groups.end()), groups.end());
-    const int wgs[] = {2, 4, 8};
+    const int wgs[] = {1, 2, 4, 8};
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
@@ -2271,7 +2276,7 @@ isdf_status isdf_autotune(isdf_ctx ctx, isdf_precision prec, int32_t n_frag, con
       report->wg_per_cu = best_w;
       report->ms = best;
       report->ms_default = def_ms;
-      report->n_tried = (int32_t)(groups.size() * 3);
+      report->n_tried = (int32_t)(groups.size() * 4);
     }
   });
 }

@@ -89,12 +89,16 @@ hipError_t eri_scatter_batch_launch(const cplx* e, const long long* eoff, cplx* 
 // bf16x3 NT GEMM on the 32x32x16 matrix cores (128 x 128 tiles, 256
 // threads, direct-to-LDS operand copies): same descriptors and epilogues as
 // big_launch for precision 2; plan with big_plan.
+// ring: the ring pipeline (four LDS stages, one workgroup a CU, the next
+// stage's fragments read during the MFMAs; same results bit for bit), for
+// the call sites ring_supported accepts.
 hipError_t x3_launch(int conj, const NtDesc* descs_dev, int ndesc, long long total, int max_blocks, int seg,
-                     hipStream_t s, int kind);
+                     hipStream_t s, int kind, bool ring = false);
 // The same kernel on the single-bf16 operand format (fmt 3): kind 2 without
 // conjugation (U^q) and kind 3 with B conjugated (the contraction) only.
 hipError_t x1_launch(int conj, const NtDesc* descs_dev, int ndesc, long long total, int max_blocks, int seg,
-                     hipStream_t s, int kind);
+                     hipStream_t s, int kind, bool ring = false);
+bool ring_supported(int conj, int kind);
 // mixed-precision fragment contraction: classes {q, -q} summed in FP32 per
 // launch (one contiguous K range of at most ERI_QGROUP * ld, the classes
 // split into balanced groups), FP64 across launches (the max ERI error at

@@ -2,7 +2,10 @@
 through the C ABI: every tiling the tuner may pick meets the mixed bound
 against the FP64 oracle (1e-6 Eh), the tuner's choice is one of its
 candidates and sticks to the context, a graph captured after tuning equals
-the eager batch with that tiling bit for bit, and bad tilings are refused."""
+the eager batch with that tiling bit for bit, and bad tilings are refused.
+The ring pipeline of the bf16 fragment GEMMs (one workgroup a CU) issues the
+same MFMAs in the same order per accumulator as the two-stage pipeline, so
+its results are equal bit for bit."""
 import numpy as np
 import pytest
 
@@ -30,7 +33,7 @@ def test_every_tiling_within_bound(name):
     cdev = [torch.from_numpy(f).cuda() for f in frags]
     nh = (cfg.n_k + sum(1 for q in range(cfg.n_k) if _self_conj(q, cfg.kmesh))) // 2
     for nl in (1, 2, 3):
-        for wg in (2, 8):
+        for wg in (1, 2, 8):
             ctx.set_tiling((nh + nl - 1) // nl, wg)
             got = ctx.fragment_eri(cdev, "bf16x3")
             for f in range(len(frags)):
@@ -39,8 +42,8 @@ def test_every_tiling_within_bound(name):
     out = [torch.empty((f.shape[2],) * 4, dtype=torch.complex128, device="cuda") for f in frags]
     rep = ctx.autotune(cdev, out, "bf16x3")
     print(name, rep, flush=True)
-    assert rep["n_tried"] >= 3 and rep["ms"] > 0 and rep["ms_default"] > 0
-    assert rep["wg_per_cu"] in (2, 4, 8)
+    assert rep["n_tried"] >= 4 and rep["ms"] > 0 and rep["ms_default"] > 0
+    assert rep["wg_per_cu"] in (1, 2, 4, 8)
     n_init = -(-nh // 12)                   # launches of the initial tiling (<= 12 classes each)
     assert rep["eri_qgroup"] in {-(-nh // nl) for nl in (1, 2, 3, n_init)}
     assert rep["ms"] <= rep["ms_default"]
@@ -65,3 +68,30 @@ def _self_conj(q, kmesh):
     m1, m2, m3 = kmesh
     j = (q // (m2 * m3), (q // m3) % m2, q % m3)
     return all((2 * jj) % m == 0 for jj, m in zip(j, kmesh))
+
+
+@pytest.mark.parametrize("name", ["t_small_k3", "t_m4_k16", "t_k6_cube", "t_cond_k8"])
+@pytest.mark.parametrize("prec", ["bf16x3", "bf16"])
+def test_ring_pipeline_equals_two_stage_bitwise(name, prec):
+    import torch
+    import paper_2601_16379_amd as pkg
+    print("ring case", name, prec, flush=True)
+    d = inp.make_inputs(name)
+    cfg = d.cfg
+    frags = inp.make_fragments(cfg)
+    ctx = pkg.Isdf(d.lattice, cfg.grid, cfg.kmesh, d.orbitals, d.ip_index)
+    ctx.fit(prec)
+    ctx.coulomb_kernel(prec)
+    cdev = [torch.from_numpy(f).cuda() for f in frags]
+    nh = (cfg.n_k + sum(1 for q in range(cfg.n_k) if _self_conj(q, cfg.kmesh))) // 2
+    nl = -(-nh // 12)
+    g = -(-nh // nl)                        # the initial tiling's classes per launch
+    ctx.set_tiling(g, 2)
+    two = [e.cpu().numpy() for e in ctx.fragment_eri(cdev, prec)]
+    ctx.set_tiling(g, 1)
+    ring = [e.cpu().numpy() for e in ctx.fragment_eri(cdev, prec)]
+    ring2 = [e.cpu().numpy() for e in ctx.fragment_eri(cdev, prec)]
+    for f in range(len(frags)):
+        assert np.array_equal(ring[f], two[f]), (f, frags[f].shape[2])
+        assert np.array_equal(ring2[f], two[f]), f
+    ctx.close()
