@@ -1220,6 +1220,11 @@ void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn
   while (ti > 1 && (long long)nk * ti > tile_cap) ti >>= 1;
   int tp = 1;   // power of two (the LDS transform needs tp * ti to be one)
   while (tp < 8 && (long long)nk * ti * tp * 2 <= tile_cap) tp *= 2;
+  if (pair_lines_supported(prec, c->m[0], c->m[1], c->m[2])) {
+    // the line transform: one value a thread an axis pass
+    ti = std::min(32, pair_lines_wmax(c->m[0], c->m[1], c->m[2]));
+    tp = 1;
+  }
   const bool reg = pair_reg_supported(prec, c->m[0], c->m[1], c->m[2]);
   const long long nchunk = (ld + 63) / 64;
   // tables of the pair transform over pairs [pbeg, pbeg + pcnt) of every
@@ -1237,8 +1242,18 @@ void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn
       fp0[f] = (int)b0;
       fnp[f] = (int)np;
       fpair[f] = p.nb == 1 ? p.poff[f] : -b0;
-      for (long long q0 = 0; q0 < np; q0 += tp)
-        blocks.push_back(PairBlock{(int)f, (int)(b0 + q0), (int)std::min<long long>(tp, np - q0)});
+      if (p.nb == 1 && tp == 1) {
+        // single pairs of a whole fragment in windows of 8 rows p: for each
+        // q, the pairs (p, q) of the window, so that consecutive blocks (run
+        // together on one XCD) need 8 + a few orbitals of the point tile
+        const int nfr = p.nf[f];
+        for (int p0 = 0; p0 < nfr; p0 += 8)
+          for (int q = 0; q < nfr; ++q)
+            for (int pp = p0; pp < std::min(p0 + 8, nfr); ++pp) blocks.push_back(PairBlock{(int)f, pp * nfr + q, 1});
+      } else {
+        for (long long q0 = 0; q0 < np; q0 += tp)
+          blocks.push_back(PairBlock{(int)f, (int)(b0 + q0), (int)std::min<long long>(tp, np - q0)});
+      }
       ioff[f + 1] = ioff[f] + nchunk * np;
     }
     t.nblocks = (int)blocks.size();

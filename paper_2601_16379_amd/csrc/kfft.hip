@@ -546,6 +546,109 @@ __global__ __launch_bounds__(256) void pair32_kernel(PairArgs a) {
   }
 }
 
+// ---- pair transform of the mixed formats on the 6^3, 8^3 and 10^3 meshes,
+// one line a thread ----
+// The tile of pair_kernel (tp pairs x ti interpolation points for every R)
+// in complex FP32: the axis-3 lines of conj(psi_p) psi_q are formed from HBM
+// in registers and transformed, the axis-2 lines pass once through LDS
+// (rows padded by one value to an odd stride), and the axis-1 lines are
+// transformed and written straight to the operand format: two LDS passes
+// and two barriers a tile.  Tiles are mapped XCD-contiguously (workgroup b
+// on XCD b mod 8 takes a contiguous range), so that consecutive pair blocks
+// of one point tile, which share orbitals, are read through one L2.
+template <int M1, int M2, int M3>
+__global__ __launch_bounds__(1024) void pair_lines_kernel(PairArgs a, int ntot) {
+  extern __shared__ float2 pl[];
+  constexpr int NK = M1 * M2 * M3;
+  const int per = (ntot + 7) >> 3;
+  const int v = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  if (v >= ntot) return;
+  const int blk = v % a.nblocks, it = v / a.nblocks;
+  const PairBlock pb = a.blocks[blk];
+  const int nf = a.frag_nf[pb.frag];
+  const int col = a.frag_col[pb.frag];
+  const long long poff = a.frag_pair[pb.frag];
+  const int w = a.tp * a.ti;           // power of two
+  const int wshift = __builtin_ctz(w), tshift = __builtin_ctz(a.ti);
+  const int I0 = it * a.ti;
+  const int rs = M3 * w + 1;           // LDS row of one (R1, R2)
+  const long long rstride = (long long)a.ncol * a.n_ip;   // psi32 between consecutive R
+  const int tid = threadIdx.x, nt = blockDim.x;
+  // axis 3 from HBM: line (R1, R2, e)
+  for (int l = tid; l < (NK / M3) << wshift; l += nt) {
+    const int e = l & (w - 1), r12 = l >> wshift;
+    const int j = e >> tshift, I = I0 + (e & (a.ti - 1));
+    float2 x[M3];
+    if (j < pb.npair && I < a.n_ip) {
+      const int P = pb.pair0 + j, pp = P / nf, qq = P - pp * nf;
+      const float2* bp = a.psi32 + ((long long)r12 * M3 * a.ncol + col + pp) * a.n_ip + I;
+      const float2* bq = a.psi32 + ((long long)r12 * M3 * a.ncol + col + qq) * a.n_ip + I;
+#pragma unroll
+      for (int t = 0; t < M3; ++t) {
+        const float2 xp = bp[t * rstride], xq = bq[t * rstride];
+        // conj(psi_p) psi_q
+        x[t] = make_float2(fmaf(xp.x, xq.x, xp.y * xq.y), fmaf(xp.x, xq.y, -(xp.y * xq.x)));
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < M3; ++t) x[t] = make_float2(0.f, 0.f);
+    }
+    float2 y[M3];
+    dft_any_f<M3>(x, y);
+    float2* p = pl + r12 * rs + e;
+#pragma unroll
+    for (int t = 0; t < M3; ++t) p[t * w] = y[t];
+  }
+  __syncthreads();
+  // axis 2: line (R1, R3, e)
+  for (int l = tid; l < (NK / M2) << wshift; l += nt) {
+    const int e = l & (w - 1), r = l >> wshift;
+    float2* p = pl + (r / M3) * M2 * rs + (r % M3) * w + e;
+    float2 x[M2], y[M2];
+#pragma unroll
+    for (int t = 0; t < M2; ++t) x[t] = p[t * rs];
+    dft_any_f<M2>(x, y);
+#pragma unroll
+    for (int t = 0; t < M2; ++t) p[t * rs] = y[t];
+  }
+  __syncthreads();
+  // axis 1 to the output: line (Q2, Q3, e)
+  const float sc = (float)a.scale;
+  for (int l = tid; l < (NK / M1) << wshift; l += nt) {
+    const int e = l & (w - 1), r = l >> wshift;
+    const int j = e >> tshift, I = I0 + (e & (a.ti - 1));
+    if (j >= pb.npair || I >= a.ld) continue;
+    const float2* p = pl + (r / M3) * rs + (r % M3) * w + e;
+    float2 x[M1], y[M1];
+#pragma unroll
+    for (int t = 0; t < M1; ++t) x[t] = p[t * M2 * rs];
+    dft_any_f<M1>(x, y);
+    const long long row = (poff + pb.pair0 + j) * a.p_stride + I;
+#pragma unroll
+    for (int t = 0; t < M1; ++t) {
+      const int slot = a.qslot[t * M2 * M3 + r];
+      if (slot < 0) continue;
+      store_fmt(a.out, (long long)slot * a.q_stride + row, a.plane, a.fmt,
+                cmk((double)(y[t].x * sc), (double)(y[t].y * sc)));
+    }
+  }
+}
+
+template <int M1, int M2, int M3>
+hipError_t pair_lines_launch(const PairArgs& a, hipStream_t s) {
+  constexpr int NK = M1 * M2 * M3;
+  const int w = a.tp * a.ti;
+  const long long ntot = (long long)a.nblocks * a.n_itiles;
+  if (ntot <= 0) return hipSuccess;
+  if (ntot > (1LL << 30) || w > pair_lines_wmax(M1, M2, M3)) return hipErrorInvalidValue;
+  const int lmax = NK / (M1 < M2 ? (M1 < M3 ? M1 : M3) : (M2 < M3 ? M2 : M3)) * w;
+  const int threads = (lmax + 63) / 64 * 64;
+  const size_t lds = (size_t)M1 * M2 * (M3 * w + 1) * sizeof(float2);
+  const long long blocks = (ntot + 7) / 8 * 8;
+  hipLaunchKernelGGL((pair_lines_kernel<M1, M2, M3>), dim3((unsigned)blocks), dim3(threads), lds, s, a, (int)ntot);
+  return hipGetLastError();
+}
+
 // ---- register path of the k convolution (mode 0), mesh M1 x M2 x M3 with
 // M1 in {1, 2, 4} and M2, M3 <= 4 ----
 // M1 lanes per element (lane l: element l / M1, k1 = l % M1): the M2 x M3
@@ -1014,6 +1117,10 @@ bool pair32_supported(int fmt, int m1, int m2, int m3) {
   return fmt != 0 && !pair_reg_supported(fmt, m1, m2, m3);
 }
 
+bool pair_lines_supported(int fmt, int m1, int m2, int m3) {
+  return fmt != 0 && m1 == m2 && m2 == m3 && (m1 == 6 || m1 == 8 || m1 == 10);
+}
+
 hipError_t pair_launch(const PairArgs& a, hipStream_t s) {
   if (!a.qslot) return hipErrorInvalidValue;
   if (pair_reg_supported(a.fmt, a.m1, a.m2, a.m3)) {
@@ -1030,6 +1137,12 @@ hipError_t pair_launch(const PairArgs& a, hipStream_t s) {
   const long long blocks = (long long)a.nblocks * a.n_itiles;
   if (blocks <= 0) return hipSuccess;
   const int mx = std::max(a.m1, std::max(a.m2, a.m3));
+  if (pair_lines_supported(a.fmt, a.m1, a.m2, a.m3)) {
+    if (!a.psi32) return hipErrorInvalidValue;
+    if (a.m1 == 6) return pair_lines_launch<6, 6, 6>(a, s);
+    if (a.m1 == 8) return pair_lines_launch<8, 8, 8>(a, s);
+    return pair_lines_launch<10, 10, 10>(a, s);
+  }
   if (pair32_supported(a.fmt, a.m1, a.m2, a.m3)) {
     if (!a.psi32) return hipErrorInvalidValue;
     const size_t lds32 = (size_t)nk * a.tp * a.ti * sizeof(float2);
