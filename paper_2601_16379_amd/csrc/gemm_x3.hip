@@ -17,13 +17,14 @@
 // interleaved by 8-element groups) the 16 k of one row are 128 contiguous
 // bytes, so a stage of a 128-row operand tile is 128 whole cache lines; it is
 // copied from global memory straight into LDS (global_load_lds_dwordx4, no
-// register staging) into one of two LDS stage buffers, two stages ahead of
-// the one being multiplied.  Each stage: wait for its copies, barrier, read
-// the fragments, barrier (the buffer then takes the copy two stages ahead),
+// register staging) into one of two LDS stage buffers, one stage ahead of
+// the one being multiplied.  Each stage: wait for its copies, one barrier
+// (after it every wave has also read the previous stage, whose buffer then
+// takes the copies of the next stage, issued first), read the fragments,
 // MFMAs.  The stalls of one workgroup's waves are filled by the other
-// workgroup's MFMAs (with one workgroup per CU and the next stage's
-// fragments prefetched instead, the matrix cores were busy about half the
-// time).  In LDS a row keeps its eight 16-byte slots (2 k-groups x 4 planes)
+// workgroup's MFMAs.  (Two barriers a stage with the copies two stages
+// ahead measured 8 % slower on the 1000-k contraction; so did issuing the
+// fragment reads before the copies.)  In LDS a row keeps its eight 16-byte slots (2 k-groups x 4 planes)
 // in an order XOR-permuted by the row, so that the 32x32 fragment reads
 // (lane -> row l%32, k-group l/32) hit distinct banks.
 //
@@ -328,6 +329,18 @@ __device__ inline void tile_epilogue(const NtDesc& d, int b, int m0, int n0, int
   }
 }
 
+// The MFMAs of one stage of fragments (both column blocks).
+template <int F, int NI, int NJ, bool A_CONJ, bool B_CONJ>
+__device__ inline void stage_mma(const Frag<NI, NJ>& f, f16v (&c_re)[NI][NJ], f16v (&c_im)[NI][NJ]) {
+  if constexpr (F == 2) {
+    mma_half<NI, NJ, A_CONJ, B_CONJ>(f, 0, c_re, c_im);
+    if (NJ == 2) mma_half<NI, NJ, A_CONJ, B_CONJ>(f, NJ - 1, c_re, c_im);
+  } else {
+    mma_single<NI, NJ, A_CONJ, B_CONJ>(f, 0, c_re, c_im);
+    if (NJ == 2) mma_single<NI, NJ, A_CONJ, B_CONJ>(f, NJ - 1, c_re, c_im);
+  }
+}
+
 // K loop and epilogue of one tile.  The wave owns the (NI*32) x (NJ*32)
 // block at rows rb0, columns cb0 of the tile: 64 x 64 in full tiles (2 x 2
 // waves); in tiles with at most 32 valid rows (columns) each wave takes a
@@ -335,7 +348,7 @@ __device__ inline void tile_epilogue(const NtDesc& d, int b, int m0, int n0, int
 // quarter of the matrix-core work.  Two workgroups share a CU (64 KB of LDS
 // each): two LDS stages, each stage's fragments read from LDS at its start
 // (the waves of the other workgroup keep the matrix cores busy meanwhile),
-// copies two stages ahead.
+// copies one stage ahead, one barrier a stage.
 template <int F, int NI, int NJ, bool A_CONJ, bool B_CONJ>
 __device__ inline void tile_body(const NtDesc& d, int b, int m0, int n0, int kcur,
                                  const unsigned short* const (&asrc)[NCOPY], const unsigned short* const (&bsrc)[NCOPY],
@@ -355,53 +368,28 @@ __device__ inline void tile_body(const NtDesc& d, int b, int m0, int n0, int kcu
   constexpr int SK = Fmt<F>::K;
   const int nst = (kcur + SK - 1) / SK;
   __syncthreads();                        // LDS of the previous tile no longer read
-#pragma unroll
-  for (int s = 0; s < NBUF; ++s)
-    if (s < nst) {
-      stage_copy<F>(asrc, gslot, s * SK, kcur, smem + s * STAGE_B, wave);
-      stage_copy<F>(bsrc, gslot, s * SK, kcur, smem + s * STAGE_B + OPER_B, wave);
-    }
+  stage_copy<F>(asrc, gslot, 0, kcur, smem, wave);
+  stage_copy<F>(bsrc, gslot, 0, kcur, smem + OPER_B, wave);
   for (int s = 0; s < nst; ++s) {
     char* buf = smem + (s & 1) * STAGE_B;
-    // stage s landed: at most the copies of stage s+1 still in flight
-    wait_copies(s + 1 < nst ? 1 : 0);
+    // stage s landed (nothing else in flight); after the barrier every wave
+    // has read stage s - 1, so its buffer takes stage s + 1
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
+    if (s + 1 < nst) {
+      char* nb = smem + ((s + 1) & 1) * STAGE_B;
+      stage_copy<F>(asrc, gslot, (s + 1) * SK, kcur, nb, wave);
+      stage_copy<F>(bsrc, gslot, (s + 1) * SK, kcur, nb + OPER_B, wave);
+    }
     Frag<NI, NJ> f;
     read_frags_a<F>(buf, f, rb0, lr, lk);
     read_frags_b<F>(buf, f, cb0, lr, lk);
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     settle(f);
-    // every wave holds its fragments of stage s: its buffer takes stage s+2
-    __builtin_amdgcn_s_barrier();
-    asm volatile("" ::: "memory");
-    if (s + NBUF < nst) {
-      stage_copy<F>(asrc, gslot, (s + NBUF) * SK, kcur, buf, wave);
-      stage_copy<F>(bsrc, gslot, (s + NBUF) * SK, kcur, buf + OPER_B, wave);
-    }
-    if (!idle) {
-      if constexpr (F == 2) {
-        mma_half<NI, NJ, A_CONJ, B_CONJ>(f, 0, c_re, c_im);
-        if (NJ == 2) mma_half<NI, NJ, A_CONJ, B_CONJ>(f, NJ - 1, c_re, c_im);
-      } else {
-        mma_single<NI, NJ, A_CONJ, B_CONJ>(f, 0, c_re, c_im);
-        if (NJ == 2) mma_single<NI, NJ, A_CONJ, B_CONJ>(f, NJ - 1, c_re, c_im);
-      }
-    }
+    if (!idle) stage_mma<F, NI, NJ, A_CONJ, B_CONJ>(f, c_re, c_im);
   }
   if (!idle) tile_epilogue<F, NI, NJ>(d, b, m0, n0, rb0, cb0, c_re, c_im, smem, wave, lane, first);
-}
-
-// The MFMAs of one stage of fragments (both column blocks).
-template <int F, int NI, int NJ, bool A_CONJ, bool B_CONJ>
-__device__ inline void stage_mma(const Frag<NI, NJ>& f, f16v (&c_re)[NI][NJ], f16v (&c_im)[NI][NJ]) {
-  if constexpr (F == 2) {
-    mma_half<NI, NJ, A_CONJ, B_CONJ>(f, 0, c_re, c_im);
-    if (NJ == 2) mma_half<NI, NJ, A_CONJ, B_CONJ>(f, NJ - 1, c_re, c_im);
-  } else {
-    mma_single<NI, NJ, A_CONJ, B_CONJ>(f, 0, c_re, c_im);
-    if (NJ == 2) mma_single<NI, NJ, A_CONJ, B_CONJ>(f, NJ - 1, c_re, c_im);
-  }
 }
 
 // One step of the ring pipeline: the MFMAs of stage s (fragments in `cur`)
