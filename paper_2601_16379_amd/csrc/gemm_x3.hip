@@ -24,7 +24,12 @@
 // MFMAs.  The stalls of one workgroup's waves are filled by the other
 // workgroup's MFMAs.  (Two barriers a stage with the copies two stages
 // ahead measured 8 % slower on the 1000-k contraction; so did issuing the
-// fragment reads before the copies.)  In LDS a row keeps its eight 16-byte slots (2 k-groups x 4 planes)
+// fragment reads before the copies.)  A launch with fewer tiles than two
+// rounds of workgroups leaves workgroups alone on their CUs; its
+// contraction runs the two-barrier loop, which hides more latency
+// (zgemm_c2b_kernel: 0.143 against 0.126 of peak at 216 k).  Both loops
+// issue the same MFMAs in the same order: the results do not depend on the
+// choice.  In LDS a row keeps its eight 16-byte slots (2 k-groups x 4 planes)
 // in an order XOR-permuted by the row, so that the 32x32 fragment reads
 // (lane -> row l%32, k-group l/32) hit distinct banks.
 //
@@ -474,7 +479,75 @@ __device__ inline void tile_body_ring(const NtDesc& d, int b, int m0, int n0, in
   if (!idle) tile_epilogue<F, NI, NJ>(d, b, m0, n0, rb0, cb0, c_re, c_im, smem, wave, lane, first);
 }
 
-template <int F, bool A_CONJ, bool B_CONJ, int KIND, bool RINGP>
+// The same K loop with two barriers a stage and the copies two stages
+// ahead (a buffer is refilled only after every wave has read the stage it
+// holds): more tolerant of a workgroup that has its CU to itself, the case
+// of launches with fewer tiles than two rounds of workgroups.
+// K loop and epilogue of one tile.  The wave owns the (NI*32) x (NJ*32)
+// block at rows rb0, columns cb0 of the tile: 64 x 64 in full tiles (2 x 2
+// waves); in tiles with at most 32 valid rows (columns) each wave takes a
+// 32 x 32 block of the one 32-row (32-column) strip, so edge tiles cost a
+// quarter of the matrix-core work.  Two workgroups share a CU (64 KB of LDS
+// each): two LDS stages, each stage's fragments read from LDS at its start
+// (the waves of the other workgroup keep the matrix cores busy meanwhile),
+// copies two stages ahead.
+template <int F, int NI, int NJ, bool A_CONJ, bool B_CONJ>
+__device__ inline void tile_body_2b(const NtDesc& d, int b, int m0, int n0, int kcur,
+                                 const unsigned short* const (&asrc)[NCOPY], const unsigned short* const (&bsrc)[NCOPY],
+                                 const int (&gslot)[NCOPY], int rb0, int cb0, char* smem, int wave, int lane,
+                                 bool idle, bool first) {
+  const int lr = lane & 31, lk = lane >> 5;
+  f16v c_re[NI][NJ], c_im[NI][NJ];
+#pragma unroll
+  for (int i = 0; i < NI; ++i)
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        c_re[i][j][v] = 0.f;
+        c_im[i][j][v] = 0.f;
+      }
+  constexpr int SK = Fmt<F>::K;
+  const int nst = (kcur + SK - 1) / SK;
+  __syncthreads();                        // LDS of the previous tile no longer read
+#pragma unroll
+  for (int s = 0; s < NBUF; ++s)
+    if (s < nst) {
+      stage_copy<F>(asrc, gslot, s * SK, kcur, smem + s * STAGE_B, wave);
+      stage_copy<F>(bsrc, gslot, s * SK, kcur, smem + s * STAGE_B + OPER_B, wave);
+    }
+  for (int s = 0; s < nst; ++s) {
+    char* buf = smem + (s & 1) * STAGE_B;
+    // stage s landed: at most the copies of stage s+1 still in flight
+    wait_copies(s + 1 < nst ? 1 : 0);
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    Frag<NI, NJ> f;
+    read_frags_a<F>(buf, f, rb0, lr, lk);
+    read_frags_b<F>(buf, f, cb0, lr, lk);
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    settle(f);
+    // every wave holds its fragments of stage s: its buffer takes stage s+2
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    if (s + NBUF < nst) {
+      stage_copy<F>(asrc, gslot, (s + NBUF) * SK, kcur, buf, wave);
+      stage_copy<F>(bsrc, gslot, (s + NBUF) * SK, kcur, buf + OPER_B, wave);
+    }
+    if (!idle) {
+      if constexpr (F == 2) {
+        mma_half<NI, NJ, A_CONJ, B_CONJ>(f, 0, c_re, c_im);
+        if (NJ == 2) mma_half<NI, NJ, A_CONJ, B_CONJ>(f, NJ - 1, c_re, c_im);
+      } else {
+        mma_single<NI, NJ, A_CONJ, B_CONJ>(f, 0, c_re, c_im);
+        if (NJ == 2) mma_single<NI, NJ, A_CONJ, B_CONJ>(f, NJ - 1, c_re, c_im);
+      }
+    }
+  }
+  if (!idle) tile_epilogue<F, NI, NJ>(d, b, m0, n0, rb0, cb0, c_re, c_im, smem, wave, lane, first);
+}
+
+template <int F, bool A_CONJ, bool B_CONJ, int KIND, bool RINGP, bool TWOB = false>
 __device__ inline void x3_tiles(const NtDesc* __restrict__ descs, int ndesc, long long total_tiles, int seg) {
   extern __shared__ __attribute__((aligned(16))) char smem[];   // NBUF (RING) stages x (A, B)
   const int tid = threadIdx.x;
@@ -540,6 +613,16 @@ __device__ inline void x3_tiles(const NtDesc* __restrict__ descs, int ndesc, lon
       else
         tile_body_ring<F, 2, 2, A_CONJ, B_CONJ>(d, b, m0, n0, kcur, asrc, bsrc, gslot, wm * 64, wn * 64, smem,
                                                 wave, lane, diag && wm < wn, first);
+    } else if constexpr (TWOB) {
+      if (d.M - m0 <= 32)
+        tile_body_2b<F, 1, 1, A_CONJ, B_CONJ>(d, b, m0, n0, kcur, asrc, bsrc, gslot, 0, wave * 32, smem, wave, lane,
+                                              diag && wave > 0, first);
+      else if (d.N - n0 <= 32)
+        tile_body_2b<F, 1, 1, A_CONJ, B_CONJ>(d, b, m0, n0, kcur, asrc, bsrc, gslot, wave * 32, 0, smem, wave, lane,
+                                              false, first);
+      else
+        tile_body_2b<F, 2, 2, A_CONJ, B_CONJ>(d, b, m0, n0, kcur, asrc, bsrc, gslot, wm * 64, wn * 64, smem, wave,
+                                              lane, diag && wm < wn, first);
     } else {
       if (d.M - m0 <= 32)
         tile_body<F, 1, 1, A_CONJ, B_CONJ>(d, b, m0, n0, kcur, asrc, bsrc, gslot, 0, wave * 32, smem, wave, lane,
@@ -564,6 +647,14 @@ template <bool A_CONJ, bool B_CONJ, int KIND>
 __global__ __launch_bounds__(XNT, 2) void zgemm_x1_kernel(const NtDesc* __restrict__ descs, int ndesc,
                                                           long long total_tiles, int seg) {
   x3_tiles<3, A_CONJ, B_CONJ, KIND, false>(descs, ndesc, total_tiles, seg);
+}
+
+// two barriers a stage: the fragment contraction (kind 3, B conjugated) of
+// launches with few tiles, both formats
+template <int F>
+__global__ __launch_bounds__(XNT, 2) void zgemm_c2b_kernel(const NtDesc* __restrict__ descs, int ndesc,
+                                                           long long total_tiles, int seg) {
+  x3_tiles<F, false, true, 3, false, true>(descs, ndesc, total_tiles, seg);
 }
 
 // ring pipeline (one workgroup a CU): the fragment GEMMs, both formats
@@ -630,6 +721,11 @@ hipError_t x1_launch(int conj, const NtDesc* descs_dev, int ndesc, long long tot
   max_blocks = max_blocks / 8 * 8;
   const int blocks = (int)(t8 < max_blocks ? t8 : max_blocks);
   if (ring) return launch_ring<3>(conj, descs_dev, ndesc, total, blocks, seg, kind, s);
+  if (kind == 3 && (conj & 3) == 2 && total < 2LL * blocks) {
+    hipLaunchKernelGGL((zgemm_c2b_kernel<3>), dim3(blocks), dim3(XNT), NBUF * STAGE_B, s, descs_dev, ndesc, total,
+                       seg);
+    return hipGetLastError();
+  }
   return launch_x1(conj, descs_dev, ndesc, total, blocks, seg, kind, s);
 }
 
@@ -640,6 +736,11 @@ hipError_t x3_launch(int conj, const NtDesc* descs_dev, int ndesc, long long tot
   max_blocks = max_blocks / 8 * 8;
   const int blocks = (int)(t8 < max_blocks ? t8 : max_blocks);
   if (ring) return launch_ring<2>(conj, descs_dev, ndesc, total, blocks, seg, kind, s);
+  if (kind == 3 && (conj & 3) == 2 && total < 2LL * blocks) {
+    hipLaunchKernelGGL((zgemm_c2b_kernel<2>), dim3(blocks), dim3(XNT), NBUF * STAGE_B, s, descs_dev, ndesc, total,
+                       seg);
+    return hipGetLastError();
+  }
   switch (kind) {
     case 1: return launch_x3<1>(conj, descs_dev, ndesc, total, blocks, seg, s);
     case 2: return launch_x3<2>(conj, descs_dev, ndesc, total, blocks, seg, s);
