@@ -104,13 +104,15 @@ def frag_flops(cfg, n):
     return 8.0 * nh * nip * nip * n * n + 8.0 * nh * nip * (n * n) * (n * n + 1) / 2
 
 
-def stage_work(stage, cfg, nfs, prec, passes=1):
+def stage_work(stage, cfg, nfs, prec, passes=1, yform=False):
     """(bound, algorithmic amount, unit, peak) of a stage over the fragments
     nfs (fragment stages) or one fit + kernel.  The k-space stages (T^k, the
     k convolutions' inputs) count all N_k; everything indexed by q counts the
     nh classes {q, -q} it runs over.  The fit and the kernel are FP64 in
     every precision (16 bytes a value).  passes: q batches of a kernel whose
-    eta does not fit at once (the RHS is formed again in each)."""
+    eta does not fit at once (the RHS is formed again in each).  yform: the
+    mixed fragment GEMMs run in the factor form (W = L L^H): U^q = R^q W^q is
+    the triangular Y^q = R^q L^q, whose work is the triangle's."""
     nk, nip, ng, norb = cfg.n_k, cfg.n_ip, cfg.n_g, cfg.n_orb
     nh = n_classes(cfg.kmesh)
     s2 = sum(n * n for n in nfs)
@@ -118,8 +120,9 @@ def stage_work(stage, cfg, nfs, prec, passes=1):
     if stage == "frag_eri":   # Hermitian half of sum_q U^q R^{qH} per fragment
         fl = sum(8.0 * nh * nip * (n * n) * (n * n + 1) / 2 for n in nfs)
         return "mfma", fl / 1e12, "TFLOP", pk
-    if stage == "frag_u":     # U^q = W^q R^q
-        return "mfma", 8.0 * nh * nip * nip * s2 / 1e12, "TFLOP", pk
+    if stage == "frag_u":     # U^q = W^q R^q, or the triangular Y^q = R^q L^q
+        tri = (nip + 1) / (2.0 * nip) if yform else 1.0
+        return "mfma", 8.0 * nh * nip * nip * s2 * tri / 1e12, "TFLOP", pk
     if stage == "frag_pair":  # write R^q once (c128 in FP64, 8 B a point in the mixed formats)
         return "hbm", nh * nip * s2 * (16 if prec == "fp64" else 8) / 1e9, "GB", PEAK["hbm"]
     if stage == "frag_t":
@@ -316,14 +319,14 @@ def roofline_entry(ctx, stage_tot, cfg, nfs, prec, steps):
     return roof
 
 
-def stage_rows(stage_tot, cfg, nfs, prec, per, passes=1):
+def stage_rows(stage_tot, cfg, nfs, prec, per, passes=1, yform=False):
     rows = {}
     tot_ms = sum(stage_tot[k][0] for k in STAGES if k in stage_tot)
     for s in STAGES:
         if s not in stage_tot:
             continue
         tot, cnt = stage_tot[s]
-        w = stage_work(s, cfg, nfs if s in FRAG_STAGES else [], prec, passes)
+        w = stage_work(s, cfg, nfs if s in FRAG_STAGES else [], prec, passes, yform)
         row = {"ms": tot / per, "intervals": cnt / per, "share": tot / tot_ms if tot_ms else 0.0}
         if w and tot > 0:
             amount = w[1] * (1 if s in FRAG_STAGES else per)
@@ -578,6 +581,7 @@ def run_stream(args, cfg, pkg, inp, np, torch):
     fit_stages = collect_stages(ctx, FIT_STAGES)
     st = ctx.stats()
     rhs_passes = -(-st["classes"] // st["q_batch"])   # q batches of the kernel (eta formed in each)
+    wfac = bool(st.get("w_factor"))                  # mixed fragment GEMMs in the factor form
     log("fit %.2f s, Coulomb kernel %.2f s" % (t_fit, t_kernel))
     free, total = torch.cuda.mem_get_info()
     budget = int(0.9 * free)
@@ -652,11 +656,13 @@ def run_stream(args, cfg, pkg, inp, np, torch):
                               "p99": float(np.percentile(1e3 * np.asarray(alat), 99))},
                "slice0_s": ast[0],
                "roofline": {k: aroof[k] for k in ("stage", "kernel", "achieved", "peak", "unit", "frac")},
-               "stages": stage_rows(atot, cfg, timed_nfs, args.alt_prec, args.steps)}
+               "stages": stage_rows(atot, cfg, timed_nfs, args.alt_prec, args.steps, 1,
+                                    wfac and args.alt_prec != "fp64")}
         log("%s: %.3e ERIs/s (%.1f ms per step)" % (args.alt_prec, alt["value"], alt["ms_per_step"]))
     ctx.serve_stop()
     roof = roofline_entry(ctx, frag_tot, cfg, timed_nfs, args.prec, args.steps)
-    stages = stage_rows(frag_tot, cfg, timed_nfs, args.prec, args.steps)
+    stages = stage_rows(frag_tot, cfg, timed_nfs, args.prec, args.steps, 1, wfac and args.prec != "fp64")
+    extra["w_factor"] = wfac
     if not args.no_extras:
         log("Coulomb / exchange matrices and interpolation-point selection")
         extra["hf_jk"] = hf_leg(ctx, cfg, d, inp, np, torch, 3, not args.no_cpu_baseline)
@@ -845,8 +851,9 @@ def run_whole(args, cfg, pkg, inp, np, torch):
     tot = collect_stages(ctx, STAGES + [s + "_kernel" for s in FRAG_STAGES])
     erisum = float(sum(n ** 4 for n in nfs)) * args.steps
     roof = roofline_entry(ctx, tot, cfg, nfs * args.steps, args.prec, args.steps)
-    stages = stage_rows(tot, cfg, nfs * args.steps, args.prec, args.steps)
-    extra = {}
+    wfac = bool(ctx.stats().get("w_factor"))
+    stages = stage_rows(tot, cfg, nfs * args.steps, args.prec, args.steps, 1, wfac and args.prec != "fp64")
+    extra = {"w_factor": wfac}
     rates = [float(r) for r in (args.poisson_rates if args.poisson_rates is not None else "200,1000,4000").split(",")
              if r.strip()]
     if rates:

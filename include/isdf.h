@@ -87,6 +87,8 @@ typedef enum {
 /* isdf_coulomb_kernel takes the zeta route of eqs. (3) and (6) (xi^q = Pi^{q+}
  * eta^q, FFT, W^q = xihat^H c xihat) instead of eqs. (7)-(8) */
 #define ISDF_ZETA_ROUTE 0x4u
+/* the mixed fragment GEMMs keep U^q = R^q W^q (no factor form, below) */
+#define ISDF_W_PLAIN 0x8u
 /* at most n classes {q, -q} of eta per q batch (bits 16-31; 0 = as many as
  * fit, see isdf_fit) */
 #define ISDF_Q_BATCH(n) ((((uint32_t)(n)) & 0xFFFFu) << 16)
@@ -235,6 +237,12 @@ isdf_status isdf_get_eta_tilde(isdf_ctx ctx, int32_t q, void* out);
  * transform giving R^q_{I,pq}, U^q = W^q R^q, then the Hermitian contraction
  * sum_q R^{q H}-weighted products accumulated over q (FP64 accumulation across
  * q in every precision), one grouped persistent launch for all fragments.
+ * Factor form (mixed precisions): isdf_coulomb_kernel also factors every
+ * W^q = L L^H (FP64, no pivoting); when every pivot is above 1e-13 of its
+ * matrix's largest diagonal entry (isdf_stats: "w_factor"), the mixed paths
+ * form Y^q = R^q L^q (a triangular product: half the work of U^q) and the
+ * contraction sum_q Y^q Y^{qH} (same ERIs up to rounding); otherwise, or
+ * with ISDF_W_PLAIN, they use U^q.  The FP64 path always uses U^q.
  *   n_frag    number of fragments (>= 1).
  *   n_f       [n_frag] orbitals per fragment (>= 1), host memory.
  *   C         [n_frag] pointers, fragment f: c128 [N_k][n_orb][n_f[f]].

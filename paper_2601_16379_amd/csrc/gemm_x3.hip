@@ -580,9 +580,13 @@ __device__ inline void x3_tiles(const NtDesc* __restrict__ descs, int ndesc, lon
     const int m0 = tm * XT, n0 = tn * XT;
     // interleaved formats: logical element e at u16 EU*e (e a multiple of 8)
     constexpr int EU = Fmt<F>::EU;
-    const unsigned short* As = (const unsigned short*)d.A + EU * (b * d.sA_bat + (long long)seg * d.sA_seg);
-    const unsigned short* Bs = (const unsigned short*)d.B + EU * (b * d.sB_bat + (long long)seg * d.sB_seg);
-    const int kcur = (seg == d.nseg - 1) ? d.Klast : d.Kseg;
+    // a triangular B (zero for k < n) contributes from k = n0 on
+    const int kstart = d.ktri ? n0 : 0;
+    const unsigned short* As =
+        (const unsigned short*)d.A + EU * (b * d.sA_bat + (long long)seg * d.sA_seg + kstart);
+    const unsigned short* Bs =
+        (const unsigned short*)d.B + EU * (b * d.sB_bat + (long long)seg * d.sB_seg + kstart);
+    const int kcur = ((seg == d.nseg - 1) ? d.Klast : d.Kseg) - kstart;
 
     // this lane's sources and slots in its copy instructions; rows past M / N
     // read the last valid row (their outputs are not stored)

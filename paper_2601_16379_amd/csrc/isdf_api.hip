@@ -414,6 +414,9 @@ struct isdf_ctx_s {
   long long ld_ip = 0;                  // row pitch of the split operands (a multiple of 16)
   bool has_orbitals = false;            // false for a context restored by isdf_load
   bool fitted = false, kernel_ready = false, eta_valid = false;
+  // the mixed operand copies hold sqrt(w_h) L^T (W^h = L L^H) instead of W^T:
+  // U^q = R^q W^q becomes Y^q = R^q L^q and the contraction sum_q Y Y^H
+  bool wfac = false;
   bool kernel_pending = false;          // a fit whose eta (resident or per batch) the kernel has not consumed
   bool etat_valid = false;              // eta~ of every class still held after the kernel (no q batches)
   // launch tiling of the fragment contraction (isdf_autotune / isdf_set_tiling):
@@ -809,21 +812,69 @@ void do_fit(isdf_ctx c, int prec) {
 // --------------------------------------------------------------------------
 // Coulomb kernel
 // --------------------------------------------------------------------------
+// The fragment GEMMs' operands from W^q: transposed copies in the four
+// formats (one per class {q, -q}, weight 1/2 where q = -q: the fragment
+// contraction adds the conjugate term of -q itself).  Then every W^h (FP64,
+// Hermitian positive semidefinite) is factored W^h = L L^H without pivoting;
+// when every pivot is above WFAC_RTOL times the largest diagonal entry of its
+// matrix, the mixed copies take sqrt(w_h) L^T instead, so that U^q = R^q W^q
+// becomes the triangular product Y^q = R^q L^q (half the work) and the
+// contraction sum_q U R^H becomes sum_q Y Y^H.  Otherwise (a singular or
+// too ill-conditioned W^h: a rank-deficient metric) the copies stay W^T.
+// work, lt: two [nh][n][n] c128 buffers, or null (allocated here).
+constexpr double WFAC_RTOL = 1e-13;
+void operand_copies(isdf_ctx c, cplx* work, cplx* lt, hipStream_t s) {
+  const int nk = c->nk, nip = c->nip, nh = c->nh;
+  const int* hself = c->qmap.as<int>() + nk + nh;
+  HIPCHK(wt_convert_launch(c->w.as<cplx>(), c->wt64.as<cplx>(), c->wt32.as<float>(), c->wt16.as<unsigned short>(),
+                           c->wt16s.as<unsigned short>(), nip, (int)c->ld_ip, nh, hself, s));
+  c->wfac = false;
+  if (c->flags & ISDF_W_PLAIN) {
+    HIPCHK(hipStreamSynchronize(s));
+    return;
+  }
+  const size_t m2 = (size_t)nh * nip * nip * sizeof(cplx);
+  DevBuf wa, wl, perm, rank, dmax, flag;
+  try {
+    if (!work) { wa.alloc(m2); work = wa.as<cplx>(); }
+    if (!lt) { wl.alloc(m2); lt = wl.as<cplx>(); }
+    perm.alloc(sizeof(int) * nh * (size_t)nip);
+    rank.alloc(sizeof(int) * nh);
+    dmax.alloc(sizeof(double) * nh);
+    flag.alloc(sizeof(int) * nh);
+  } catch (const Fail&) {
+    (void)hipGetLastError();
+    return;                               // no room for the factor: W^T copies
+  }
+  chol_blocked(c->arena, c->w.as<cplx>(), work, lt, perm.as<int>(), rank.as<int>(), dmax.as<double>(),
+               flag.as<int>(), nip, nh, WFAC_RTOL, s);
+  std::vector<int> fl(nh);
+  HIPCHK(hipMemcpyAsync(fl.data(), flag.p, sizeof(int) * nh, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int f : fl)
+    if (f) return;
+  HIPCHK(lt_convert_launch(lt, c->wt32.as<float>(), c->wt16.as<unsigned short>(), c->wt16s.as<unsigned short>(), nip,
+                           (int)c->ld_ip, nh, hself, s));
+  HIPCHK(hipStreamSynchronize(s));
+  c->wfac = true;
+}
+
 // Common end of both routes: W^q in the fragment GEMMs' operand formats, the
 // finiteness check, and the fit's transient buffers handed back.
 void kernel_finish(isdf_ctx c) {
   hipStream_t s = c->stream;
   const int nk = c->nk, nip = c->nip, nh = c->nh;
-  // transposed copies of W in the three operand formats of the fragment GEMMs
-  // (one per class {q, -q}, weight 1/2 where q = -q: the fragment contraction
-  // adds the conjugate term of -q itself)
-  HIPCHK(wt_convert_launch(c->w.as<cplx>(), c->wt64.as<cplx>(), c->wt32.as<float>(),
-                           c->wt16.as<unsigned short>(), c->wt16s.as<unsigned short>(), nip, (int)c->ld_ip, nh, c->qmap.as<int>() + nk + nh, s));
   HIPCHK(hipMemsetAsync(c->flag.p, 0, sizeof(int), s));
   HIPCHK(nonfinite_launch(c->w.as<cplx>(), (long long)nh * nip2(c), c->flag.as<int>(), s));
   int bad = 0;
   HIPCHK(hipMemcpyAsync(&bad, c->flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  if (!bad) {
+    // the factorisation scratch of the fit, when it is there
+    const size_t m2 = (size_t)nh * nip * nip * sizeof(cplx);
+    operand_copies(c, c->work2.bytes >= m2 ? c->work2.as<cplx>() : nullptr,
+                   c->work3.bytes >= m2 ? c->work3.as<cplx>() : nullptr, s);
+  }
   {
     std::lock_guard<std::mutex> lk(c->mu);
     c->timer.collect(&c->totals);
@@ -1306,10 +1357,14 @@ void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn
     HIPCHK(pair_launch(a, s));
   };
   // U^q_{P,J} = sum_I R^q_{P,I} W^q_{IJ}   (eq. (19), first contraction)
-  auto u_gemm = [&](const char* m, long long nrows) {
+  // With the factor (wfac, mixed precisions) the same product with W^T
+  // replaced by sqrt(w_h) L^T: Y^q_{P,j} = sum_{a >= j} R^q_{P,a} L^q_{a,j}.
+  const bool yform = prec != 0 && c->wfac;
+  auto u_gemm = [&](const char* m, long long nrows, char* dst) {
     const void* wt = prec == 0 ? c->wt64.p : (prec == 1 ? c->wt32.p : (prec == 2 ? c->wt16.p : c->wt16s.p));
     std::vector<NtDesc> d(1);
-    d[0] = mknt(m, (long long)nh * ld, wt, ld, Uq, (long long)nh * ld, (int)nrows, nip, nip);
+    d[0] = mknt(m, (long long)nh * ld, wt, ld, dst, (long long)nh * ld, (int)nrows, nip, nip);
+    d[0].ktri = yform ? 1 : 0;
     d[0].batch = nh;
     d[0].a_plane = mplane;
     d[0].b_plane = (long long)nh * nip * ld;
@@ -1367,14 +1422,15 @@ void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn
     pair_transform(make_tables(0, 0), Mq);
     if (timed) ws.timer.end("frag_pair", s);
     if (timed) ws.timer.begin("frag_u", s);
-    u_gemm(Mq, p.ptot);
+    u_gemm(Mq, p.ptot, Uq);
     if (timed) ws.timer.end("frag_u", s);
     if (timed) ws.timer.begin("frag_eri", s);
     std::vector<NtDesc> d;
     for (size_t f = 0; f < fr.size(); ++f) {
       const int nf2 = p.nf[f] * p.nf[f];
       const size_t o = (size_t)p.poff[f] * nh * ld * sc;
-      d.push_back(eri_desc(Uq + o, Mq + o, acc + p.aoff[f], nf2, nf2, nf2, 2));
+      // G = U R^H, or Y Y^H with the factor
+      d.push_back(eri_desc(Uq + o, (yform ? Uq : Mq) + o, acc + p.aoff[f], nf2, nf2, nf2, 2));
     }
     // largest fragments first so the persistent launch ends balanced
     std::stable_sort(d.begin(), d.end(), [](const NtDesc& a, const NtDesc& b) { return a.M > b.M; });
@@ -1396,16 +1452,24 @@ void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn
       pair_transform(tabs[i], Mq);
       if (timed) ws.timer.end("frag_pair", s);
       if (timed) ws.timer.begin("frag_u", s);
-      u_gemm(Mq, ni);
+      u_gemm(Mq, ni, Uq);
       if (timed) ws.timer.end("frag_u", s);
       for (int j = 0; j <= i; ++j) {
         const long long j0 = (long long)j * p.pb, nj = std::min<long long>(p.pb, nf2 - j0);
-        const char* rj = Mq;
+        // column operand: R_j, or with the factor Y_j (Y_i for j == i; else
+        // Y_j = R_j L into the first R region, whose R_i is no longer read)
+        const char* rj = yform ? Uq : Mq;
         if (j != i) {
           if (timed) ws.timer.begin("frag_pair", s);
           pair_transform(tabs[j], Mq2);
           if (timed) ws.timer.end("frag_pair", s);
           rj = Mq2;
+          if (yform) {
+            if (timed) ws.timer.begin("frag_u", s);
+            u_gemm(Mq2, nj, Mq);
+            if (timed) ws.timer.end("frag_u", s);
+            rj = Mq;
+          }
         }
         if (timed) ws.timer.begin("frag_eri", s);
         std::vector<NtDesc> d(1, eri_desc(Uq, rj, acc + i0 * nf2 + j0, nf2, (int)ni, (int)nj, j == i ? 2 : 0));
@@ -2421,7 +2485,8 @@ isdf_status isdf_stats(isdf_ctx ctx, char* json, int64_t cap) {
   std::string s = "{\"n_k\":" + std::to_string(ctx->nk) + ",\"n_g\":" + std::to_string(ctx->ng) +
                   ",\"n_orb\":" + std::to_string(ctx->norb) + ",\"n_ip\":" + std::to_string(ctx->nip) +
                   ",\"r_tile\":" + std::to_string(ctx->rc) + ",\"ip_tile\":" + std::to_string(ctx->ri) +
-                  ",\"classes\":" + std::to_string(ctx->nh) + ",\"q_batch\":" + std::to_string(ctx->qb) + ",\"rank\":[";
+                  ",\"classes\":" + std::to_string(ctx->nh) + ",\"q_batch\":" + std::to_string(ctx->qb) +
+                  ",\"w_factor\":" + (ctx->wfac ? "true" : "false") + ",\"rank\":[";
   // per q (the class of q or of -q; the factor of conj Pi has the same rank)
   if (!ctx->rank_h.empty())
     for (int q = 0; q < ctx->nk; ++q) {
@@ -3065,9 +3130,9 @@ isdf_status isdf_load(isdf_ctx* out, const char* path, void* hip_stream) {
     HIPCHK(hipMemcpy(c->w.p, p + xb + mb, mb, hipMemcpyHostToDevice));
     c->rank_h = rk;
     // the operand copies of W for the fragment GEMMs
-    HIPCHK(wt_convert_launch(c->w.as<cplx>(), c->wt64.as<cplx>(), c->wt32.as<float>(), c->wt16.as<unsigned short>(), c->wt16s.as<unsigned short>(),
-                             c->nip, (int)c->ld_ip, c->nh, c->qmap.as<int>() + c->nk + c->nh, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
+    c->arena.reset(c->stream);
+    c->arena.reserve(((size_t)1 << 20) + (size_t)c->nh * 1024);
+    operand_copies(c, nullptr, nullptr, c->stream);
     c->fitted = true;
     c->kernel_ready = true;
   });

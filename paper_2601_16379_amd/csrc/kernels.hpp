@@ -61,6 +61,8 @@ struct NtDesc {
   int tiles_m, tiles_n, tiles_per_batch;
   int herm, epi, nf;
   int npad;               // epi 3: columns written (zeros from N on); 0 = ldc
+  int ktri;               // B[n][k] = 0 for k < n: the bf16 kernels start each column
+                          // tile's K range at its first column (others read the zeros)
   long long tile_begin;
 };
 long long nt_plan(NtDesc* d, int n);
@@ -115,6 +117,11 @@ constexpr int FRAG_WG_PER_CU = 2;
 // Wt[h][J][I] = w_h W[h][I][J], w_h = 1/2 where q = -q (hself: device), with
 // row pitch ld in c128, two-float-plane, four-bf16-plane and two-bf16-plane
 // formats (any output pointer may be null); pad columns are zero.
+// The mixed operand copies of the Cholesky factor of W (W^h = L L^H): the
+// operand B of Y = R L, Bt[h][j][a] = sqrt(w_h) L^h[a][j] (a >= j, zero
+// elsewhere and for a >= n), from lt[h][j][a] = L^h[a][j].
+hipError_t lt_convert_launch(const cplx* lt, float* wt32, unsigned short* wt16, unsigned short* wt16s, int n, int ld,
+                             int nh, const int* hself, hipStream_t s);
 hipError_t wt_convert_launch(const cplx* w, cplx* wt64, float* wt32, unsigned short* wt16, unsigned short* wt16s,
                              int n, int ld, int nh, const int* hself, hipStream_t s);
 

@@ -72,6 +72,27 @@ __global__ void wt_convert_kernel(const cplx* __restrict__ w, cplx* wt64, float*
   }
 }
 
+// Bt[h][j][a] = sqrt(w_h) L^h[a][j] for a >= j, zero above it and for
+// a >= n (row pitch ld), from lt[h][j][a] = L^h[a][j] (the transposed
+// Cholesky factor; its entries below the diagonal are not read), in the
+// three mixed operand formats.
+__global__ void lt_convert_kernel(const cplx* __restrict__ lt, float* wt32, unsigned short* wt16,
+                                  unsigned short* wt16s, int n, int ld, int nh, const int* __restrict__ hself) {
+  const long long total = (long long)nh * n * ld;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const long long hj = idx / ld;
+    const int a = (int)(idx - hj * ld);
+    const int j = (int)(hj % n);
+    const int h = (int)(hj / n);
+    const double wgt = hself[h] ? 0.7071067811865476 : 1.0;   // sqrt(1/2) where q = -q
+    const cplx v = (a < n && a >= j) ? cscale(lt[((long long)h * n + j) * n + a], wgt) : cmk(0.0, 0.0);
+    store_fmt(wt32, idx, total, 1, v);
+    store_fmt(wt16, idx, total, 2, v);
+    store_fmt(wt16s, idx, total, 3, v);
+  }
+}
+
 __global__ void zero_c_kernel(cplx* x, long long n) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
@@ -119,6 +140,13 @@ hipError_t wt_convert_launch(const cplx* w, cplx* wt64, float* wt32, unsigned sh
                              int n, int ld, int nh, const int* hself, hipStream_t s) {
   hipLaunchKernelGGL(wt_convert_kernel, dim3(grid_for((long long)nh * n * ld)), dim3(256), 0, s, w,
                      wt64, wt32, wt16, wt16s, n, ld, nh, hself);
+  return hipGetLastError();
+}
+
+hipError_t lt_convert_launch(const cplx* lt, float* wt32, unsigned short* wt16, unsigned short* wt16s, int n, int ld,
+                             int nh, const int* hself, hipStream_t s) {
+  hipLaunchKernelGGL(lt_convert_kernel, dim3(grid_for((long long)nh * n * ld)), dim3(256), 0, s, lt, wt32, wt16,
+                     wt16s, n, ld, nh, hself);
   return hipGetLastError();
 }
 

@@ -23,6 +23,7 @@ PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16": 3}
 ISDF_INPUT_DEVICE = 0x1
 ISDF_NO_PIVOT = 0x2
 ISDF_ZETA_ROUTE = 0x4
+ISDF_W_PLAIN = 0x8
 ISDF_FRAG_DEVICE = 0x1
 ISDF_HF_DEVICE = 0x1
 ISDF_MP2_DEVICE = 0x1
@@ -199,7 +200,7 @@ class Isdf:
     as methods with the C names (``fit``, ``coulomb_kernel``, ...)."""
 
     def __init__(self, lattice, grid, kmesh, orbitals, ip_index, no_pivot=False, stream=None, q_batch=0,
-                 zeta_route=False, _handle=None):
+                 zeta_route=False, w_plain=False, _handle=None):
         self.lib = load_library()
         if _handle is not None:             # a context restored by isdf_load
             self.h, (self.grid, self.kmesh, self.n_orb, self.n_ip, self.stream) = _handle
@@ -223,7 +224,8 @@ class Isdf:
         self.n_orb = int(shape[1])
         self.n_ip = int(ip_index.shape[0])
         flags = (ISDF_INPUT_DEVICE if odev else 0) | (ISDF_NO_PIVOT if no_pivot else 0) \
-            | (ISDF_ZETA_ROUTE if zeta_route else 0) | ((int(q_batch) & 0xFFFF) << 16)
+            | (ISDF_ZETA_ROUTE if zeta_route else 0) | (ISDF_W_PLAIN if w_plain else 0) \
+            | ((int(q_batch) & 0xFFFF) << 16)
         self.stream = current_stream() if stream is None else stream
         h = ctypes.c_void_p()
         st = self.lib.isdf_create(ctypes.byref(h), lat.ctypes.data, self.grid.ctypes.data,
