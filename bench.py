@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--alt-prec", default="bf16", choices=["", "fp64", "fp32", "bf16x3", "bf16"],
                     help="second precision timed on the same slices of the fragment stream (reported "
                          "apart, with its own error against FP64); '' for none")
+    ap.add_argument("--qgroup", type=int, default=0,
+                    help="classes {q, -q} per launch of the fragment contraction (0: the context's default)")
     ap.add_argument("--wg-per-cu", type=int, default=0,
                     help="workgroups per CU of the fragment GEMMs (1: ring pipeline; 0: the context's default)")
     ap.add_argument("--slice", type=int, default=4,
@@ -167,6 +169,10 @@ def kernel_name(stage, prec):
     return KERNEL_OF_STAGE[stage][0 if prec == "fp64" else 1].format(x=x)
 
 
+# other kernels of a stage (the contraction of launches with few tiles)
+KERNEL_ALT = {("frag_eri", "bf16x3"): "zgemm_c2b_kernel<2>", ("frag_eri", "bf16"): "zgemm_c2b_kernel<3>"}
+
+
 def counter_traffic(stage, workload, prec):
     """HBM bytes per launch of a stage's main kernel from the committed
     rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, scaled by a 1 GiB
@@ -182,11 +188,14 @@ def counter_traffic(stage, workload, prec):
         fp = os.path.join(csrc, f)
         if not os.path.exists(fp) or hashlib.sha256(open(fp, "rb").read()).hexdigest() != h:
             return None
-    key = kernel_name(stage, prec)
+    # bytes per launch over every kernel of the stage, weighted by dispatches
+    keys = [kernel_name(stage, prec)] + ([KERNEL_ALT[(stage, prec)]] if (stage, prec) in KERNEL_ALT else [])
+    tot = n = 0
     for name, v in prof["kernels"].items():
-        if key in name:
-            return v.get("launch_bytes")
-    return None
+        if any(k in name for k in keys):
+            tot += v.get("launch_bytes", 0.0) * v.get("dispatches", 1)
+            n += v.get("dispatches", 1)
+    return tot / n if n else None
 
 
 FIT_STAGES = ["metric_t", "metric_kconv", "rhs_t", "rhs_kconv", "chol", "pinv", "grid_fft", "v_gemm", "w_solve"]
@@ -310,6 +319,8 @@ def roofline_entry(ctx, stage_tot, cfg, nfs, prec, steps):
     roof["traffic"] = counter_traffic(dom, cfg.name, prec)
     roof["stage"] = dom
     roof["kernel"] = kernel_name(dom, prec)
+    if (dom, prec) in KERNEL_ALT:
+        roof["kernel"] += " (" + KERNEL_ALT[(dom, prec)] + " for launches of fewer tiles than two rounds)"
     roof["avg_launch_ms"] = avg_ms
     roof["launches_per_step"] = kn / steps
     roof["algorithmic_per_launch"] = amount / kn * (1e9 if unit == "GB" else 1e12)
@@ -585,10 +596,10 @@ def run_stream(args, cfg, pkg, inp, np, torch):
     log("fit %.2f s, Coulomb kernel %.2f s" % (t_fit, t_kernel))
     free, total = torch.cuda.mem_get_info()
     budget = int(0.9 * free)
-    if args.wg_per_cu:
+    if args.wg_per_cu or args.qgroup:
         nh = n_classes(cfg.kmesh)
         nl = -(-nh // 12)
-        ctx.set_tiling(-(-nh // nl), args.wg_per_cu)   # the initial classes per launch
+        ctx.set_tiling(args.qgroup or -(-nh // nl), args.wg_per_cu or 2)   # defaults: the initial tiling
     ctx.serve_start(max_inflight=1, max_batch=args.max_batch or S, budget_bytes=budget)
 
     def step(sl, prec, buf):
