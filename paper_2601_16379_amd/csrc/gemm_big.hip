@@ -114,9 +114,11 @@ __global__ __launch_bounds__(NT) void zgemm_big_kernel(const NtDesc* __restrict_
     }
     const int m0 = tm * BT, n0 = tn * BT;
     const size_t esz = sizeof(T);
-    const char* As = (const char*)d.A + ((long long)b * d.sA_bat + (long long)seg * d.sA_seg) * esz;
-    const char* Bs = (const char*)d.B + ((long long)b * d.sB_bat + (long long)seg * d.sB_seg) * esz;
-    const int kcur = (seg == d.nseg - 1) ? d.Klast : d.Kseg;
+    // a triangular B (zero for k < n) contributes from k = n0 on
+    const int kstart = d.ktri ? n0 : 0;
+    const char* As = (const char*)d.A + ((long long)b * d.sA_bat + (long long)seg * d.sA_seg + kstart) * esz;
+    const char* Bs = (const char*)d.B + ((long long)b * d.sB_bat + (long long)seg * d.sB_seg + kstart) * esz;
+    const int kcur = ((seg == d.nseg - 1) ? d.Klast : d.Kseg) - kstart;
 
     f4 c_re[2][4], c_im[2][4];
 #pragma unroll

@@ -61,8 +61,8 @@ struct NtDesc {
   int tiles_m, tiles_n, tiles_per_batch;
   int herm, epi, nf;
   int npad;               // epi 3: columns written (zeros from N on); 0 = ldc
-  int ktri;               // B[n][k] = 0 for k < n: the bf16 kernels start each column
-                          // tile's K range at its first column (others read the zeros)
+  int ktri;               // B[n][k] = 0 for k < n: the mixed kernels start each column
+                          // tile's K range at its first column (FP64 reads the zeros)
   long long tile_begin;
 };
 long long nt_plan(NtDesc* d, int n);

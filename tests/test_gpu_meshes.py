@@ -39,9 +39,10 @@ def fp64_eri_tol(pi):
 def known_bf16x3_limit(name, prec, err):
     """bf16x3 fragment GEMMs (operands split hi + lo, about 2^-17 relative
     each) on the 4-orbital 20^3 cell, whose fragment ERIs are large (max |V|
-    0.033 Eh) and whose metric has cond(Pi^q) up to 3e4, reach 1.6e-6 Eh with
-    the FP64 Coulomb kernel; FP32 fragment GEMMs stay near 5e-8 Eh there.
-    Reported as an expected failure with the measured error, not skipped."""
+    0.033 Eh) and whose metric has cond(Pi^q) up to 3e4, reach 1.6e-6 Eh in
+    the plain form U^q = R^q W^q; the factor form (the default) measures
+    1.9e-7 Eh and FP32 6.4e-9 Eh.  An error at or above the bound there is
+    reported as an expected failure with the measured number, not skipped."""
     if name == "t_grid20_k3" and prec == "bf16x3" and err >= MIXED_EH:
         pytest.xfail("bf16x3 fragment GEMMs: max|dV| %.3e Eh on t_grid20_k3 (bound 1e-6)" % err)
 
