@@ -166,11 +166,13 @@ def kernel_name(stage, prec):
     if stage not in KERNEL_OF_STAGE:
         return stage
     x = {"fp32": "zgemm_big_kernel<1, ", "bf16x3": "zgemm_x3_kernel<", "bf16": "zgemm_x1_kernel<"}.get(prec, "")
+    if stage == "frag_eri" and prec == "bf16":
+        return "zgemm_c2b_kernel<3>"
     return KERNEL_OF_STAGE[stage][0 if prec == "fp64" else 1].format(x=x)
 
 
 # other kernels of a stage (the contraction of launches with few tiles)
-KERNEL_ALT = {("frag_eri", "bf16x3"): "zgemm_c2b_kernel<2>", ("frag_eri", "bf16"): "zgemm_c2b_kernel<3>"}
+KERNEL_ALT = {("frag_eri", "bf16x3"): "zgemm_c2b_kernel<2>"}
 
 
 def counter_traffic(stage, workload, prec):

@@ -29,7 +29,7 @@
 // contraction runs the two-barrier loop, which hides more latency
 // (zgemm_c2b_kernel: 0.143 against 0.126 of peak at 216 k).  Both loops
 // issue the same MFMAs in the same order: the results do not depend on the
-// choice.  In LDS a row keeps its eight 16-byte slots (2 k-groups x 4 planes)
+// choice.  The single-bf16 contraction always runs the two-barrier loop.  In LDS a row keeps its eight 16-byte slots (2 k-groups x 4 planes)
 // in an order XOR-permuted by the row, so that the 32x32 fragment reads
 // (lane -> row l%32, k-group l/32) hit distinct banks.
 //
@@ -725,7 +725,10 @@ hipError_t x1_launch(int conj, const NtDesc* descs_dev, int ndesc, long long tot
   max_blocks = max_blocks / 8 * 8;
   const int blocks = (int)(t8 < max_blocks ? t8 : max_blocks);
   if (ring) return launch_ring<3>(conj, descs_dev, ndesc, total, blocks, seg, kind, s);
-  if (kind == 3 && (conj & 3) == 2 && total < 2LL * blocks) {
+  // single bf16: 32 MFMAs a stage (against 48 in bf16x3) leave less time to
+  // cover a one-stage prefetch; the contraction always takes the two-barrier
+  // loop (0.378 against 0.354 of bf16 peak on the 120-orbital 1000-k shape)
+  if (kind == 3 && (conj & 3) == 2) {
     hipLaunchKernelGGL((zgemm_c2b_kernel<3>), dim3(blocks), dim3(XNT), NBUF * STAGE_B, s, descs_dev, ndesc, total,
                        seg);
     return hipGetLastError();
