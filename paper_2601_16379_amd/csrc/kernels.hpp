@@ -217,13 +217,13 @@ bool pair_reg_supported(int fmt, int m1, int m2, int m3);
 // longer than 4): psi32 required, tp * ti * N_k <= 8192
 bool pair32_supported(int fmt, int m1, int m2, int m3);
 // the line pair transform (mixed formats, 6^3, 8^3 and 10^3 meshes) and the
-// largest tile (tp * ti, a power of two) it takes: at most 1024 lines an
-// axis pass and 80 KB of LDS
+// largest tile (tp * ti, a power of two) it takes: at most 2048 lines an
+// axis pass (two a thread) and 160 KB of LDS
 bool pair_lines_supported(int fmt, int m1, int m2, int m3);
 constexpr int pair_lines_wmax(int m1, int m2, int m3) {
   int w = 1;
   const int nk = m1 * m2 * m3, mn = m1 < m2 ? (m1 < m3 ? m1 : m3) : (m2 < m3 ? m2 : m3);
-  while (nk / mn * w * 2 <= 1024 && m1 * m2 * (m3 * w * 2 + 1) * 8 <= 80 * 1024) w *= 2;
+  while (w < 16 && nk / mn * w * 2 <= 2048 && m1 * m2 * (m3 * w * 2 + 1) * 8 <= 160 * 1024) w *= 2;
   return w;
 }
 

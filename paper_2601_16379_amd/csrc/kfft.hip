@@ -642,7 +642,7 @@ hipError_t pair_lines_launch(const PairArgs& a, hipStream_t s) {
   if (ntot <= 0) return hipSuccess;
   if (ntot > (1LL << 30) || w > pair_lines_wmax(M1, M2, M3)) return hipErrorInvalidValue;
   const int lmax = NK / (M1 < M2 ? (M1 < M3 ? M1 : M3) : (M2 < M3 ? M2 : M3)) * w;
-  const int threads = (lmax + 63) / 64 * 64;
+  const int threads = lmax <= 1024 ? (lmax + 63) / 64 * 64 : ((lmax + 1) / 2 + 63) / 64 * 64;   // <= 1024
   const size_t lds = (size_t)M1 * M2 * (M3 * w + 1) * sizeof(float2);
   const long long blocks = (ntot + 7) / 8 * 8;
   hipLaunchKernelGGL((pair_lines_kernel<M1, M2, M3>), dim3((unsigned)blocks), dim3(threads), lds, s, a, (int)ntot);
