@@ -312,6 +312,132 @@ __global__ __launch_bounds__(256) void xconv_kernel(XconvArgs a, int etile) {
   }
 }
 
+// The exchange convolution on a fixed M1 x M2 x M3 mesh with every line in
+// registers (as kconv_lines_kernel): LDS holds the tiles of rho and W, each
+// [k][etile] with rows padded to an odd stride.  The axis-3 lines of rho
+// and of W come straight from HBM and are transformed (rho with exp(-i k.R),
+// W with exp(+i q.R)), the axis-2 lines of both pass through LDS, the
+// axis-1 lines of both are transformed, multiplied and transformed back in
+// registers, and the product goes back along axes 2 and 3, the last
+// straight to HBM: five LDS passes and four barriers a tile.
+template <int M1, int M2, int M3>
+__global__ __launch_bounds__(512) void xconv_lines_kernel(XconvArgs a, int etile, int ntiles) {
+  extern __shared__ cplx xl[];
+  constexpr int NK = M1 * M2 * M3;
+  const int per = (ntiles + 7) >> 3;
+  const int tile = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  if (tile >= ntiles) return;
+  const int eshift = __builtin_ctz(etile);
+  const int rs = M3 * etile + 1;
+  cplx* br = xl;
+  cplx* bw = xl + M1 * M2 * rs;
+  const long long e0 = (long long)tile * etile;
+  const long long rem = a.n_elem - e0;
+  const int ne = rem < etile ? (int)rem : etile;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int l = tid; l < (NK / M3) << eshift; l += nt) {
+    const int e = l & (etile - 1), k12 = l >> eshift;
+    cplx x[M3], y[M3];
+#pragma unroll
+    for (int j = 0; j < M3; ++j) {
+      x[j] = y[j] = cmk(0.0, 0.0);
+      if (e < ne) {
+        const int k = k12 * M3 + j;
+        x[j] = a.rho[(long long)k * a.n_elem + e0 + e];
+        const int sel = a.wsel[k];
+        y[j] = a.w[(long long)(sel >> 1) * a.n_elem + e0 + e];
+        if (sel & 1) y[j].y = -y[j].y;
+      }
+    }
+    dft_line<M3, -1>(x);
+    dft_line<M3, 1>(y);
+    const int o = k12 * rs + e;
+#pragma unroll
+    for (int j = 0; j < M3; ++j) {
+      br[o + j * etile] = x[j];
+      bw[o + j * etile] = y[j];
+    }
+  }
+  __syncthreads();
+  for (int l = tid; l < (NK / M2) << eshift; l += nt) {
+    const int e = l & (etile - 1), r = l >> eshift;
+    const int o = (r / M3) * M2 * rs + (r % M3) * etile + e;
+    cplx x[M2], y[M2];
+#pragma unroll
+    for (int j = 0; j < M2; ++j) {
+      x[j] = br[o + j * rs];
+      y[j] = bw[o + j * rs];
+    }
+    dft_line<M2, -1>(x);
+    dft_line<M2, 1>(y);
+#pragma unroll
+    for (int j = 0; j < M2; ++j) {
+      br[o + j * rs] = x[j];
+      bw[o + j * rs] = y[j];
+    }
+  }
+  __syncthreads();
+  for (int l = tid; l < (NK / M1) << eshift; l += nt) {
+    const int e = l & (etile - 1), r = l >> eshift;
+    const int o = (r / M3) * rs + (r % M3) * etile + e;
+    cplx x[M1], y[M1];
+#pragma unroll
+    for (int j = 0; j < M1; ++j) {
+      x[j] = br[o + j * M2 * rs];
+      y[j] = bw[o + j * M2 * rs];
+    }
+    dft_line<M1, -1>(x);
+    dft_line<M1, 1>(y);
+#pragma unroll
+    for (int j = 0; j < M1; ++j) x[j] = cmul(x[j], y[j]);
+    dft_line<M1, 1>(x);
+#pragma unroll
+    for (int j = 0; j < M1; ++j) br[o + j * M2 * rs] = x[j];
+  }
+  __syncthreads();
+  for (int l = tid; l < (NK / M2) << eshift; l += nt) {
+    const int e = l & (etile - 1), r = l >> eshift;
+    const int o = (r / M3) * M2 * rs + (r % M3) * etile + e;
+    cplx x[M2];
+#pragma unroll
+    for (int j = 0; j < M2; ++j) x[j] = br[o + j * rs];
+    dft_line<M2, 1>(x);
+#pragma unroll
+    for (int j = 0; j < M2; ++j) br[o + j * rs] = x[j];
+  }
+  __syncthreads();
+  for (int l = tid; l < (NK / M3) << eshift; l += nt) {
+    const int e = l & (etile - 1), k12 = l >> eshift;
+    if (e >= ne) continue;
+    cplx x[M3];
+#pragma unroll
+    for (int j = 0; j < M3; ++j) x[j] = br[k12 * rs + e + j * etile];
+    dft_line<M3, 1>(x);
+#pragma unroll
+    for (int j = 0; j < M3; ++j) a.rho[(long long)(k12 * M3 + j) * a.n_elem + e0 + e] = cscale(x[j], a.scale);
+  }
+}
+
+template <int M1, int M2, int M3>
+hipError_t xconv_lines_launch(const XconvArgs& a, hipStream_t s) {
+  constexpr int NK = M1 * M2 * M3;
+  constexpr int LMAX = NK / (M1 < M2 ? (M1 < M3 ? M1 : M3) : (M2 < M3 ? M2 : M3));
+  // largest power-of-two element tile with at most 512 lines an axis pass
+  // and both padded tiles in at most 160 KB of LDS
+  int etile = 1;
+  while (LMAX * etile * 2 <= 512 && 2 * (size_t)M1 * M2 * (M3 * etile * 2 + 1) * sizeof(cplx) <= 160 * 1024)
+    etile *= 2;
+  const long long ntiles = (a.n_elem + etile - 1) / etile;
+  if (ntiles <= 0) return hipSuccess;
+  if (ntiles > (1LL << 28)) return hipErrorInvalidValue;
+  const long long blocks = ((ntiles + 7) / 8) * 8;
+  const int threads = (LMAX * etile + 63) / 64 * 64;
+  const size_t lds = 2 * (size_t)M1 * M2 * (M3 * etile + 1) * sizeof(cplx);
+  hipLaunchKernelGGL((xconv_lines_kernel<M1, M2, M3>), dim3((unsigned)blocks), dim3(threads), lds, s, a, etile,
+                     (int)ntiles);
+  return hipGetLastError();
+}
+
 // The two polarisabilities of the opposite-spin MP2 energy, in place:
 //   A(R) = sum_k exp(+i k.R) gv[k][e],  B(R) = sum_k exp(+i k.R) go[k][e],
 //   Z(R) = A(R) conj(B(R)),
@@ -366,6 +492,141 @@ __global__ __launch_bounds__(256) void pconv_kernel(PconvArgs a, int etile) {
 // One workgroup: a tile of `tp` pairs of one fragment times `ti` consecutive
 // interpolation points; LDS holds [R][tp*ti] so that the output rows (pair,
 // I-range) are written as contiguous runs of I.
+// The polarisabilities on a fixed M1 x M2 x M3 mesh with every line in
+// registers (as kconv_lines_kernel): the axis-3 lines of gv and go come from
+// HBM and are transformed, the axis-2 lines of both pass through LDS, the
+// axis-1 lines of both are transformed, Z = A conj(B) formed and transformed
+// back, and Z goes back along axes 2 and 3 inside LDS.  chit^q, the
+// transform of conj(Z), is conj(chi^{-q}), so one inverse transform serves
+// both: the store pass reads q and -q from LDS.
+template <int M1, int M2, int M3>
+__global__ __launch_bounds__(512) void pconv_lines_kernel(PconvArgs a, int etile, int ntiles) {
+  extern __shared__ cplx pl2[];
+  constexpr int NK = M1 * M2 * M3;
+  const int per = (ntiles + 7) >> 3;
+  const int tile = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  if (tile >= ntiles) return;
+  const int eshift = __builtin_ctz(etile);
+  const int rs = M3 * etile + 1;
+  cplx* ba = pl2;
+  cplx* bb = pl2 + M1 * M2 * rs;
+  const long long e0 = (long long)tile * etile;
+  const long long rem = a.n_elem - e0;
+  const int ne = rem < etile ? (int)rem : etile;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int l = tid; l < (NK / M3) << eshift; l += nt) {
+    const int e = l & (etile - 1), k12 = l >> eshift;
+    cplx x[M3], y[M3];
+#pragma unroll
+    for (int j = 0; j < M3; ++j) {
+      x[j] = y[j] = cmk(0.0, 0.0);
+      if (e < ne) {
+        const long long off = (long long)(k12 * M3 + j) * a.n_elem + e0 + e;
+        x[j] = a.gv[off];
+        y[j] = a.go[off];
+      }
+    }
+    dft_line<M3, 1>(x);
+    dft_line<M3, 1>(y);
+    const int o = k12 * rs + e;
+#pragma unroll
+    for (int j = 0; j < M3; ++j) {
+      ba[o + j * etile] = x[j];
+      bb[o + j * etile] = y[j];
+    }
+  }
+  __syncthreads();
+  for (int l = tid; l < (NK / M2) << eshift; l += nt) {
+    const int e = l & (etile - 1), r = l >> eshift;
+    const int o = (r / M3) * M2 * rs + (r % M3) * etile + e;
+    cplx x[M2], y[M2];
+#pragma unroll
+    for (int j = 0; j < M2; ++j) {
+      x[j] = ba[o + j * rs];
+      y[j] = bb[o + j * rs];
+    }
+    dft_line<M2, 1>(x);
+    dft_line<M2, 1>(y);
+#pragma unroll
+    for (int j = 0; j < M2; ++j) {
+      ba[o + j * rs] = x[j];
+      bb[o + j * rs] = y[j];
+    }
+  }
+  __syncthreads();
+  for (int l = tid; l < (NK / M1) << eshift; l += nt) {
+    const int e = l & (etile - 1), r = l >> eshift;
+    const int o = (r / M3) * rs + (r % M3) * etile + e;
+    cplx x[M1], y[M1];
+#pragma unroll
+    for (int j = 0; j < M1; ++j) {
+      x[j] = ba[o + j * M2 * rs];
+      y[j] = bb[o + j * M2 * rs];
+    }
+    dft_line<M1, 1>(x);
+    dft_line<M1, 1>(y);
+#pragma unroll
+    for (int j = 0; j < M1; ++j) x[j] = cmulc(x[j], y[j]);
+    dft_line<M1, 1>(x);
+#pragma unroll
+    for (int j = 0; j < M1; ++j) ba[o + j * M2 * rs] = x[j];
+  }
+  __syncthreads();
+  for (int l = tid; l < (NK / M2) << eshift; l += nt) {
+    const int e = l & (etile - 1), r = l >> eshift;
+    const int o = (r / M3) * M2 * rs + (r % M3) * etile + e;
+    cplx x[M2];
+#pragma unroll
+    for (int j = 0; j < M2; ++j) x[j] = ba[o + j * rs];
+    dft_line<M2, 1>(x);
+#pragma unroll
+    for (int j = 0; j < M2; ++j) ba[o + j * rs] = x[j];
+  }
+  __syncthreads();
+  for (int l = tid; l < (NK / M3) << eshift; l += nt) {
+    const int e = l & (etile - 1), k12 = l >> eshift;
+    cplx x[M3];
+    const int o = k12 * rs + e;
+#pragma unroll
+    for (int j = 0; j < M3; ++j) x[j] = ba[o + j * etile];
+    dft_line<M3, 1>(x);
+#pragma unroll
+    for (int j = 0; j < M3; ++j) ba[o + j * etile] = x[j];
+  }
+  __syncthreads();
+  // chi^q -> gv[qslot[q]], chit^q = conj(chi^{-q}) -> go[qslot[q]]
+  for (int l = tid; l < NK << eshift; l += nt) {
+    const int e = l & (etile - 1), q = l >> eshift;
+    const int slot = a.qslot[q];
+    if (slot < 0 || e >= ne) continue;
+    const int q1 = q / (M2 * M3), q2 = (q / M3) % M2, q3 = q % M3;
+    const int n1 = (M1 - q1) % M1, n2 = (M2 - q2) % M2, n3 = (M3 - q3) % M3;
+    const cplx v = ba[(q1 * M2 + q2) * rs + q3 * etile + e];
+    const cplx w = ba[(n1 * M2 + n2) * rs + n3 * etile + e];
+    const long long off = (long long)slot * a.n_elem + e0 + e;
+    a.gv[off] = cscale(v, a.scale);
+    a.go[off] = cmk(a.scale * w.x, -a.scale * w.y);
+  }
+}
+
+template <int M1, int M2, int M3>
+hipError_t pconv_lines_launch(const PconvArgs& a, hipStream_t s) {
+  constexpr int NK = M1 * M2 * M3;
+  constexpr int LMAX = NK / (M1 < M2 ? (M1 < M3 ? M1 : M3) : (M2 < M3 ? M2 : M3));
+  int etile = 1;
+  while (LMAX * etile * 2 <= 512 && 2 * (size_t)M1 * M2 * (M3 * etile * 2 + 1) * sizeof(cplx) <= 160 * 1024)
+    etile *= 2;
+  const long long ntiles = (a.n_elem + etile - 1) / etile;
+  if (ntiles <= 0) return hipSuccess;
+  if (ntiles > (1LL << 28)) return hipErrorInvalidValue;
+  const long long blocks = ((ntiles + 7) / 8) * 8;
+  const int threads = (LMAX * etile + 63) / 64 * 64;
+  const size_t lds = 2 * (size_t)M1 * M2 * (M3 * etile + 1) * sizeof(cplx);
+  hipLaunchKernelGGL((pconv_lines_kernel<M1, M2, M3>), dim3((unsigned)blocks), dim3(threads), lds, s, a, etile,
+                     (int)ntiles);
+  return hipGetLastError();
+}
+
 template <int MAXA>
 __global__ __launch_bounds__(256) void pair_kernel(PairArgs a) {
   extern __shared__ cplx buf[];
@@ -1076,6 +1337,11 @@ hipError_t kconv_launch(const KconvArgs& a, hipStream_t s) {
 hipError_t xconv_launch(const XconvArgs& a, hipStream_t s) {
   if (!a.rho || !a.w || !a.wsel) return hipErrorInvalidValue;
   if (a.m1 > MAXM || a.m2 > MAXM || a.m3 > MAXM || a.m1 < 1 || a.m2 < 1 || a.m3 < 1) return hipErrorInvalidValue;
+  if (a.m1 == a.m2 && a.m2 == a.m3) {
+    if (a.m1 == 6) return xconv_lines_launch<6, 6, 6>(a, s);
+    if (a.m1 == 8) return xconv_lines_launch<8, 8, 8>(a, s);
+    if (a.m1 == 10) return xconv_lines_launch<10, 10, 10>(a, s);
+  }
   const int nk = a.m1 * a.m2 * a.m3;
   int etile = 1;                        // two [nk][etile] columns in at most 64 KB
   while (etile < 256 && (long long)nk * etile * 2 <= 2048) etile *= 2;
@@ -1094,6 +1360,11 @@ hipError_t xconv_launch(const XconvArgs& a, hipStream_t s) {
 hipError_t pconv_launch(const PconvArgs& a, hipStream_t s) {
   if (!a.gv || !a.go || !a.qslot) return hipErrorInvalidValue;
   if (a.m1 > MAXM || a.m2 > MAXM || a.m3 > MAXM || a.m1 < 1 || a.m2 < 1 || a.m3 < 1) return hipErrorInvalidValue;
+  if (a.m1 == a.m2 && a.m2 == a.m3) {
+    if (a.m1 == 6) return pconv_lines_launch<6, 6, 6>(a, s);
+    if (a.m1 == 8) return pconv_lines_launch<8, 8, 8>(a, s);
+    if (a.m1 == 10) return pconv_lines_launch<10, 10, 10>(a, s);
+  }
   const int nk = a.m1 * a.m2 * a.m3;
   int etile = 1;                        // two [nk][etile] columns in at most 64 KB
   while (etile < 256 && (long long)nk * etile * 2 <= 2048) etile *= 2;
