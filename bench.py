@@ -321,6 +321,8 @@ def roofline_entry(ctx, stage_tot, cfg, nfs, prec, steps):
     roof["traffic"] = counter_traffic(dom, cfg.name, prec)
     roof["stage"] = dom
     roof["kernel"] = kernel_name(dom, prec)
+    if roof["kernel"].count("<") > roof["kernel"].count(">"):   # a prefix of the profiler's name
+        roof["kernel"] += ">"
     if (dom, prec) in KERNEL_ALT:
         roof["kernel"] += " (" + KERNEL_ALT[(dom, prec)] + " for launches of fewer tiles than two rounds)"
     roof["avg_launch_ms"] = avg_ms
