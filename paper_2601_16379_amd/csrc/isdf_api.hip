@@ -247,11 +247,17 @@ void run_big(Arena& ar, int prec, int conj, std::vector<NtDesc>& d, int nseg, hi
   NtDesc* dd = ar.put(d.data(), d.size(), s);
   for (int seg = 0; seg < nseg; ++seg) {
     if (mark) mark(true);
-    // the ring pipeline of the bf16 kernels (one workgroup a CU): always for
-    // U^q = R^q W^q (kind 2), for the contraction when the tiling asks for
-    // one workgroup a CU
-    const bool ring = (prec == 2 || prec == 3) && ring_supported(conj, kind) && (kind == 2 || t_wg_per_cu == 1);
-    const int blocks = ring ? max_gemm_blocks() / 8 : gemm_blocks();
+    // the ring pipeline of the bf16 kernels (one workgroup a CU): for U^q =
+    // R^q W^q (kind 2) in single bf16, for the contraction when the tiling
+    // asks for one workgroup a CU.  bf16x3 U^q runs the two-stage pipeline
+    // with two workgroups a CU whatever the tiling (1000-k shape, 14400 pair
+    // rows: 0.127 against 0.119 of bf16 peak for the triangular factor
+    // product, 0.146 against 0.141 for the full one; single bf16 0.274 on
+    // the ring against 0.255).
+    const bool ring = (prec == 2 || prec == 3) && ring_supported(conj, kind) &&
+                      ((kind == 2 && prec == 3) || (kind == 3 && t_wg_per_cu == 1));
+    const int blocks = ring ? max_gemm_blocks() / 8
+                            : (prec == 2 && kind == 2 ? max_gemm_blocks() / 8 * 2 : gemm_blocks());
     HIPCHK(prec == 2   ? x3_launch(conj, dd, (int)d.size(), total, blocks, seg, s, kind, ring)
            : prec == 3 ? x1_launch(conj, dd, (int)d.size(), total, blocks, seg, s, kind, ring)
                        : big_launch(prec, conj, dd, (int)d.size(), total, gemm_blocks(), seg, s, kind));
