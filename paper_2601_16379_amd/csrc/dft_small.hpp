@@ -37,22 +37,6 @@ template <> struct Rot<8> {
 };
 
 
-// y[k] = sum_j x[j] exp(-2 pi i j k / R), compile-time R <= 8
-template <int R>
-__device__ inline void small_dft(const cplx (&x)[R], cplx (&y)[R]) {
-#pragma unroll
-  for (int k = 0; k < R; ++k) {
-    double re = x[0].x, im = x[0].y;
-#pragma unroll
-    for (int j = 1; j < R; ++j) {
-      const double c = Rot<R>::c[(j * k) % R], sn = Rot<R>::s[(j * k) % R];
-      re = fma(x[j].x, c, fma(x[j].y, sn, re));
-      im = fma(x[j].y, c, fma(-x[j].x, sn, im));
-    }
-    y[k] = cmk(re, im);
-  }
-}
-
 constexpr double kPiD = 3.141592653589793;
 constexpr double series_cos(double x) {
   double term = 1.0, sum = 1.0;
@@ -79,6 +63,11 @@ template <int N> struct TwF {
       if (x > kPiD) x -= 2.0 * kPiD;
       c[t] = (float)series_cos(x);
       s[t] = (float)series_sin(x);
+      if ((4 * t) % N == 0) {                  // quarter turns exactly
+        const int q = 4 * t / N;
+        c[t] = q == 0 ? 1.f : (q == 2 ? -1.f : 0.f);
+        s[t] = q == 1 ? 1.f : (q == 3 ? -1.f : 0.f);
+      }
     }
   }
 };
@@ -92,20 +81,76 @@ template <int N> struct TwD {
       if (x > kPiD) x -= 2.0 * kPiD;
       c[t] = series_cos(x);
       s[t] = series_sin(x);
+      if ((4 * t) % N == 0) {                  // quarter turns exactly
+        const int q = 4 * t / N;
+        c[t] = q == 0 ? 1.0 : (q == 2 ? -1.0 : 0.0);
+        s[t] = q == 1 ? 1.0 : (q == 3 ? -1.0 : 0.0);
+      }
     }
   }
 };
 
+// Lengths 3 and 5 in place, x[k] <- sum_j x[j] w^{jk} with w = exp(S 2 pi i
+// / M), from the symmetric pairs a = x_j + x_{M-j}, b = x_j - x_{M-j}: the
+// outputs k and M - k share t = x0 + sum_j cos(2 pi jk / M) a_j and differ
+// in the sign of i u, u = S sum_j sin(2 pi jk / M) b_j (i u = (-u.y, u.x)).
+template <int S>
+__host__ __device__ inline void dft3_d(cplx (&x)[3]) {
+  constexpr TwD<3> tw{};
+  constexpr double sn = S * tw.s[1];
+  const cplx a = cadd(x[1], x[2]), b = csub(x[1], x[2]);
+  const cplx t = cmk(fma(-0.5, a.x, x[0].x), fma(-0.5, a.y, x[0].y));
+  const cplx u = cmk(sn * b.x, sn * b.y);
+  x[0] = cadd(x[0], a);
+  x[1] = cmk(t.x - u.y, t.y + u.x);
+  x[2] = cmk(t.x + u.y, t.y - u.x);
+}
+template <int S>
+__host__ __device__ inline void dft5_d(cplx (&x)[5]) {
+  constexpr TwD<5> tw{};
+  constexpr double c1 = tw.c[1], c2 = tw.c[2], s1 = S * tw.s[1], s2 = S * tw.s[2];
+  const cplx a1 = cadd(x[1], x[4]), b1 = csub(x[1], x[4]);
+  const cplx a2 = cadd(x[2], x[3]), b2 = csub(x[2], x[3]);
+  const cplx t1 = cmk(fma(c2, a2.x, fma(c1, a1.x, x[0].x)), fma(c2, a2.y, fma(c1, a1.y, x[0].y)));
+  const cplx t2 = cmk(fma(c1, a2.x, fma(c2, a1.x, x[0].x)), fma(c1, a2.y, fma(c2, a1.y, x[0].y)));
+  const cplx u1 = cmk(fma(s2, b2.x, s1 * b1.x), fma(s2, b2.y, s1 * b1.y));
+  const cplx u2 = cmk(fma(-s1, b2.x, s2 * b1.x), fma(-s1, b2.y, s2 * b1.y));
+  x[0] = cadd(x[0], cadd(a1, a2));
+  x[1] = cmk(t1.x - u1.y, t1.y + u1.x);
+  x[4] = cmk(t1.x + u1.y, t1.y - u1.x);
+  x[2] = cmk(t2.x - u2.y, t2.y + u2.x);
+  x[3] = cmk(t2.x + u2.y, t2.y - u2.x);
+}
+
 // In-place DFT of a length-M line in registers with compile-time M and sign S:
-// x[k] <- sum_j x[j] exp(S 2 pi i j k / M).  Even M > 4 split into even and
-// odd halves (radix 2, recursively); other M summed directly; the twiddles
-// are compile-time constants.
+// x[k] <- sum_j x[j] exp(S 2 pi i j k / M).  Lengths 2 and 4 by butterflies,
+// 3 and 5 from symmetric pairs (dft3_d, dft5_d); even M > 4 split into even
+// and odd halves (radix 2, recursively); other M summed directly; the
+// twiddles are compile-time constants.
 template <int M, int S>
 __host__ __device__ inline void dft_line(cplx (&x)[M]) {
   constexpr TwD<M> tw{};
   if constexpr (M == 1) {
     return;
-  } else if constexpr (M % 2 == 0 && M > 4) {
+  } else if constexpr (M == 2) {
+    const cplx a = x[0];
+    x[0] = cadd(a, x[1]);
+    x[1] = csub(a, x[1]);
+  } else if constexpr (M == 3) {
+    dft3_d<S>(x);
+  } else if constexpr (M == 4) {
+    // a = x0 + x2, b = x0 - x2, c = x1 + x3, d = S (x1 - x3):
+    // y0 = a + c, y2 = a - c, y1 = b + i d, y3 = b - i d
+    const cplx a = cadd(x[0], x[2]), b = csub(x[0], x[2]);
+    const cplx c = cadd(x[1], x[3]), d0 = csub(x[1], x[3]);
+    const cplx d = cmk(S * d0.x, S * d0.y);
+    x[0] = cadd(a, c);
+    x[2] = csub(a, c);
+    x[1] = cmk(b.x - d.y, b.y + d.x);
+    x[3] = cmk(b.x + d.y, b.y - d.x);
+  } else if constexpr (M == 5) {
+    dft5_d<S>(x);
+  } else if constexpr (M % 2 == 0) {
     constexpr int H = M / 2;
     cplx e[H], o[H];
 #pragma unroll
@@ -117,8 +162,15 @@ __host__ __device__ inline void dft_line(cplx (&x)[M]) {
     dft_line<H, S>(o);
 #pragma unroll
     for (int k = 0; k < H; ++k) {
-      const double c = tw.c[k], sn = S * tw.s[k];
-      const cplx t = cmk(o[k].x * c - o[k].y * sn, o[k].x * sn + o[k].y * c);
+      cplx t;
+      if (k == 0) {
+        t = o[k];
+      } else if (4 * k == M) {               // times i S
+        t = cmk(-S * o[k].y, S * o[k].x);
+      } else {
+        const double c = tw.c[k], sn = S * tw.s[k];
+        t = cmk(o[k].x * c - o[k].y * sn, o[k].x * sn + o[k].y * c);
+      }
       x[k] = cadd(e[k], t);
       x[k + H] = csub(e[k], t);
     }
@@ -140,6 +192,15 @@ __host__ __device__ inline void dft_line(cplx (&x)[M]) {
   }
 }
 
+// y[k] = sum_j x[j] exp(-2 pi i j k / R), compile-time R <= 8 (the line
+// transform with S = -1)
+template <int R>
+__device__ inline void small_dft(const cplx (&x)[R], cplx (&y)[R]) {
+#pragma unroll
+  for (int k = 0; k < R; ++k) y[k] = x[k];
+  dft_line<R, -1>(y);
+}
+
 // a * (c - i s) with compile-time c, s (the trivial factors fold away)
 __host__ __device__ inline float2 rot_f(float2 a, float c, float s) {
   if (c == 1.0f && s == 0.0f) return a;
@@ -149,9 +210,43 @@ __host__ __device__ inline float2 rot_f(float2 a, float c, float s) {
   return make_float2(fmaf(a.x, c, a.y * s), fmaf(a.y, c, -a.x * s));
 }
 
+// Lengths 3 and 5 in FP32, y[k] = sum_j x[j] exp(-2 pi i jk / M), from the
+// symmetric pairs as dft3_d / dft5_d (here S = -1)
+__host__ __device__ inline void dft3_f(const float2 (&x)[3], float2 (&y)[3]) {
+  constexpr TwF<3> tw{};
+  constexpr float sn = -tw.s[1];
+  const float2 a = make_float2(x[1].x + x[2].x, x[1].y + x[2].y);
+  const float2 b = make_float2(x[1].x - x[2].x, x[1].y - x[2].y);
+  const float2 t = make_float2(fmaf(-0.5f, a.x, x[0].x), fmaf(-0.5f, a.y, x[0].y));
+  const float2 u = make_float2(sn * b.x, sn * b.y);
+  y[0] = make_float2(x[0].x + a.x, x[0].y + a.y);
+  y[1] = make_float2(t.x - u.y, t.y + u.x);
+  y[2] = make_float2(t.x + u.y, t.y - u.x);
+}
+__host__ __device__ inline void dft5_f(const float2 (&x)[5], float2 (&y)[5]) {
+  constexpr TwF<5> tw{};
+  constexpr float c1 = tw.c[1], c2 = tw.c[2], s1 = -tw.s[1], s2 = -tw.s[2];
+  const float2 a1 = make_float2(x[1].x + x[4].x, x[1].y + x[4].y);
+  const float2 b1 = make_float2(x[1].x - x[4].x, x[1].y - x[4].y);
+  const float2 a2 = make_float2(x[2].x + x[3].x, x[2].y + x[3].y);
+  const float2 b2 = make_float2(x[2].x - x[3].x, x[2].y - x[3].y);
+  const float2 t1 = make_float2(fmaf(c2, a2.x, fmaf(c1, a1.x, x[0].x)), fmaf(c2, a2.y, fmaf(c1, a1.y, x[0].y)));
+  const float2 t2 = make_float2(fmaf(c1, a2.x, fmaf(c2, a1.x, x[0].x)), fmaf(c1, a2.y, fmaf(c2, a1.y, x[0].y)));
+  const float2 u1 = make_float2(fmaf(s2, b2.x, s1 * b1.x), fmaf(s2, b2.y, s1 * b1.y));
+  const float2 u2 = make_float2(fmaf(-s1, b2.x, s2 * b1.x), fmaf(-s1, b2.y, s2 * b1.y));
+  y[0] = make_float2(x[0].x + (a1.x + a2.x), x[0].y + (a1.y + a2.y));
+  y[1] = make_float2(t1.x - u1.y, t1.y + u1.x);
+  y[4] = make_float2(t1.x + u1.y, t1.y - u1.x);
+  y[2] = make_float2(t2.x - u2.y, t2.y + u2.x);
+  y[3] = make_float2(t2.x + u2.y, t2.y - u2.x);
+}
+
 template <int R>
 __host__ __device__ inline void small_dft_f(const float2 (&x)[R], float2 (&y)[R]) {
-  if constexpr (R == 2) {
+  if constexpr (R == 3) {
+    dft3_f(x, y);
+    return;
+  } else if constexpr (R == 2) {
     y[0] = make_float2(x[0].x + x[1].x, x[0].y + x[1].y);
     y[1] = make_float2(x[0].x - x[1].x, x[0].y - x[1].y);
     return;
@@ -182,15 +277,19 @@ __host__ __device__ inline void small_dft_f(const float2 (&x)[R], float2 (&y)[R]
 }
 
 // y[k] = sum_j x[j] exp(-2 pi i j k / R) for any compile-time R <= 16: the
-// butterflies of small_dft_f for R = 2, 4; even R split into even and odd
-// halves (radix 2, recursively); other R by the direct sum with the twiddles
-// as compile-time constants (TwF).
+// butterflies of small_dft_f for R = 2, 4, the symmetric pairs for R = 3, 5;
+// even R split into even and odd halves (radix 2, recursively); other R by
+// the direct sum with the twiddles as compile-time constants (TwF).
 template <int R>
 __host__ __device__ inline void dft_any_f(const float2 (&x)[R], float2 (&y)[R]) {
   if constexpr (R == 1) {
     y[0] = x[0];
   } else if constexpr (R == 2 || R == 4) {
     small_dft_f<R>(x, y);
+  } else if constexpr (R == 3) {
+    dft3_f(x, y);
+  } else if constexpr (R == 5) {
+    dft5_f(x, y);
   } else if constexpr (R % 2 == 0) {
     constexpr int H = R / 2;
     constexpr TwF<R> tw{};

@@ -1330,6 +1330,8 @@ hipError_t kconv_launch(const KconvArgs& a, hipStream_t s) {
   const int mx = std::max(a.m1, std::max(a.m2, a.m3));
   if (mx <= 4) hipLaunchKernelGGL(kconv_kernel<4>, dim3((unsigned)blocks), dim3(256), lds, s, a, etile);
   else if (mx <= 8) hipLaunchKernelGGL(kconv_kernel<8>, dim3((unsigned)blocks), dim3(256), lds, s, a, etile);
+  // axes up to 12 (the 10^3 mesh) without the registers of the longer lines
+  else if (mx <= 12) hipLaunchKernelGGL(kconv_kernel<12>, dim3((unsigned)blocks), dim3(256), lds, s, a, etile);
   else hipLaunchKernelGGL(kconv_kernel<16>, dim3((unsigned)blocks), dim3(256), lds, s, a, etile);
   return hipGetLastError();
 }
