@@ -601,9 +601,8 @@ def run_stream(args, cfg, pkg, inp, np, torch):
     free, total = torch.cuda.mem_get_info()
     budget = int(0.9 * free)
     if args.wg_per_cu or args.qgroup:
-        nh = n_classes(cfg.kmesh)
-        nl = -(-nh // 12)
-        ctx.set_tiling(args.qgroup or -(-nh // nl), args.wg_per_cu or 2)   # defaults: the initial tiling
+        # defaults: the context's initial tiling
+        ctx.set_tiling(args.qgroup or st["eri_qgroup_initial"], args.wg_per_cu or 2)
     ctx.serve_start(max_inflight=1, max_batch=args.max_batch or S, budget_bytes=budget)
 
     def step(sl, prec, buf):

@@ -313,17 +313,22 @@ isdf_status isdf_graph_destroy(isdf_graph g);
  * then go into the FP64 accumulation once per launch) and the workgroups per
  * CU of the persistent tile loops.  isdf_autotune runs the batch (device
  * pointers, as isdf_graph_create) under each candidate -- the N_h classes in
- * one, two or three launches and the initial tiling (at most 12 classes a
- * launch), times {1, 2, 4, 8} workgroups per CU --, twice each after a
+ * one, two or three launches and the initial tiling, times {1, 2, 4, 8}
+ * workgroups per CU --, twice each after a
  * warm-up, keeps the fastest for this context and, when `report` is not
  * NULL, fills it.  One workgroup per CU selects the ring pipeline of the
  * mixed-precision fragment GEMMs (four LDS stages, the next stage's
  * fragments read during the current stage's MFMAs, one barrier a stage);
  * its results equal those of the two-stage pipeline bit for bit.  The eri[f]
  * hold the last candidate's results afterwards.  isdf_set_tiling sets the two
- * values directly (wg_per_cu 0 = 8 per CU).  A context starts at 12 classes
- * a launch and 2 workgroups per CU, the tuner's choice on a 4x4x4 mesh with
- * 64 fragments of 12-40 orbitals.  Results of every tiling
+ * values directly (wg_per_cu 0 = 8 per CU).  A context starts at the most
+ * classes a launch, at most 12, whose K range of one operand row in the
+ * 8-byte mixed formats stays within 72 KB (12 up to N_IP = 768, 11 at
+ * 800, 8 at 1040; balanced groups), and 2 workgroups per CU; at 12 classes that
+ * is the tuner's choice on a 4x4x4 mesh with 64 fragments of 12-40
+ * orbitals.  isdf_stats reports the current and the initial classes per
+ * launch (eri_qgroup, eri_qgroup_initial) and wg_per_cu.  Results of every
+ * tiling
  * meet the same error bounds; the FP32 partial sums change with the classes
  * per launch, so mixed results are bitwise reproducible for a fixed tiling
  * only.  Error: ISDF_E_STATE without a Coulomb kernel, ISDF_E_BUSY while
@@ -333,7 +338,7 @@ typedef struct {
   int32_t eri_qgroup;   /* classes per ERI launch chosen */
   int32_t wg_per_cu;    /* workgroups per CU chosen */
   double ms;            /* batch time with the chosen tiling (best of two) */
-  double ms_default;    /* batch time with the context's initial tiling (12 classes, 2 per CU) */
+  double ms_default;    /* batch time with the context's initial tiling (2 per CU) */
   int32_t n_tried;      /* candidates timed */
 } isdf_tune_report;
 isdf_status isdf_autotune(isdf_ctx ctx, isdf_precision prec, int32_t n_frag, const int32_t* n_f,

@@ -429,6 +429,7 @@ struct isdf_ctx_s {
   // classes per ERI launch (the K extent of one launch) and workgroups per CU
   // of its persistent GEMM launches (0: default)
   int eri_qgroup = ERI_QGROUP, frag_wg_per_cu = FRAG_WG_PER_CU;
+  int eri_qgroup0 = ERI_QGROUP;         // the initial classes per launch (initial_qgroup of ld_ip)
   std::vector<int> rank_h;
   // q <-> -q: Pi^{-q}, W^{-q} and R^{-q}_{pq} are conjugates of those at q,
   // so the fragment contraction runs over the classes {q, -q}: hq[h] is the
@@ -1757,6 +1758,7 @@ void setup_context(isdf_ctx c, const double* lattice, const int32_t grid[3], con
   // row pitches of the split operands: multiples of 16 elements, so that in
   // the bf16 hi/lo format every 16-k step of a row is one aligned 128-byte line
   c->ld_ip = (n_ip + 15) / 16 * 16;
+  c->eri_qgroup = c->eri_qgroup0 = initial_qgroup(c->ld_ip);
   c->wt64.alloc((size_t)nh * n_ip * c->ld_ip * e);
   c->wt32.alloc((size_t)nh * n_ip * c->ld_ip * 8);
   c->wt16.alloc((size_t)nh * n_ip * c->ld_ip * 8);
@@ -2312,8 +2314,9 @@ isdf_status isdf_autotune(isdf_ctx ctx, isdf_precision prec, int32_t n_frag, con
     Exclusive ex(ctx, false);
     const int nh = ctx->nh;
     // classes per launch for one, two and three launches over the classes,
-    // and the initial tiling (at most ERI_QGROUP per launch)
-    const int def_g = (nh + ((nh + ERI_QGROUP - 1) / ERI_QGROUP) - 1) / ((nh + ERI_QGROUP - 1) / ERI_QGROUP);
+    // and the initial tiling (balanced groups of at most eri_qgroup0)
+    const int g0 = ctx->eri_qgroup0, nl0 = (nh + g0 - 1) / g0;
+    const int def_g = (nh + nl0 - 1) / nl0;
     std::vector<int> groups = {def_g};
     for (int nl = 1; nl <= 3 && nl <= nh; ++nl) groups.push_back((nh + nl - 1) / nl);
     std::sort(groups.begin(), groups.end());
@@ -2492,7 +2495,10 @@ isdf_status isdf_stats(isdf_ctx ctx, char* json, int64_t cap) {
                   ",\"n_orb\":" + std::to_string(ctx->norb) + ",\"n_ip\":" + std::to_string(ctx->nip) +
                   ",\"r_tile\":" + std::to_string(ctx->rc) + ",\"ip_tile\":" + std::to_string(ctx->ri) +
                   ",\"classes\":" + std::to_string(ctx->nh) + ",\"q_batch\":" + std::to_string(ctx->qb) +
-                  ",\"w_factor\":" + (ctx->wfac ? "true" : "false") + ",\"rank\":[";
+                  ",\"w_factor\":" + (ctx->wfac ? "true" : "false") +
+                  ",\"eri_qgroup\":" + std::to_string(ctx->eri_qgroup) +
+                  ",\"eri_qgroup_initial\":" + std::to_string(ctx->eri_qgroup0) +
+                  ",\"wg_per_cu\":" + std::to_string(ctx->frag_wg_per_cu) + ",\"rank\":[";
   // per q (the class of q or of -q; the factor of conj Pi has the same rank)
   if (!ctx->rank_h.empty())
     for (int q = 0; q < ctx->nk; ++q) {

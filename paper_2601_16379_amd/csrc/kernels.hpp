@@ -102,15 +102,22 @@ hipError_t x1_launch(int conj, const NtDesc* descs_dev, int ndesc, long long tot
                      hipStream_t s, int kind, bool ring = false);
 bool ring_supported(int conj, int kind);
 // mixed-precision fragment contraction: classes {q, -q} summed in FP32 per
-// launch (one contiguous K range of at most ERI_QGROUP * ld, the classes
-// split into balanced groups), FP64 across launches (the max ERI error at
-// the benchmark workload was 2.426e-7 Eh with 8, 2.428e-7 with 16 and
-// 2.429e-7 with 32 q per launch, set by the V^q rounding).  The initial
-// tiling of a context -- at most 12 classes a launch (three launches for the
-// 36 classes of a 4x4x4 mesh) and 2 workgroups per CU for the fragment GEMMs
-// (one resident wave of workgroups) -- is what the launch-tiling autotuner
-// picks on a 4x4x4 mesh with 64 fragments of 12-40 orbitals.
+// launch (one contiguous K range of the classes of a group, the classes
+// split into balanced groups), FP64 across launches.  The initial tiling of
+// a context: the most classes a launch, at most ERI_QGROUP, whose K range
+// of one operand row in the 8-byte mixed formats stays within ERI_ROW_BYTES
+// (12 up to N_IP = 768, 11 at 800, 8 at 1040: the rows of the tiles an XCD runs
+// together then stay within the last-level cache; at the 1000-k workload 8
+// classes measured 1.7 % faster than 12, and 24 or 42 slower), and 2
+// workgroups per CU for the fragment GEMMs (one resident wave of
+// workgroups).  At 12 classes and 2 per CU it is also what the launch-tiling
+// autotuner picks on a 4x4x4 mesh with 64 fragments of 12-40 orbitals.
 constexpr int ERI_QGROUP = 12;
+constexpr long long ERI_ROW_BYTES = 73728;
+inline int initial_qgroup(long long ld) {
+  const long long g = ERI_ROW_BYTES / (ld * 8);
+  return (int)(g < 1 ? 1 : (g > ERI_QGROUP ? ERI_QGROUP : g));
+}
 constexpr int FRAG_WG_PER_CU = 2;
 
 // W (c128 [h][n][n], one q per class {q, -q}) -> transposed copies

@@ -44,8 +44,11 @@ def test_every_tiling_within_bound(name):
     print(name, rep, flush=True)
     assert rep["n_tried"] >= 4 and rep["ms"] > 0 and rep["ms_default"] > 0
     assert rep["wg_per_cu"] in (1, 2, 4, 8)
-    n_init = -(-nh // 12)                   # launches of the initial tiling (<= 12 classes each)
+    g0 = ctx.stats()["eri_qgroup_initial"]
+    assert 1 <= g0 <= 12
+    n_init = -(-nh // g0)                   # launches of the initial tiling (balanced groups)
     assert rep["eri_qgroup"] in {-(-nh // nl) for nl in (1, 2, 3, n_init)}
+    assert ctx.stats()["eri_qgroup"] == rep["eri_qgroup"] and ctx.stats()["wg_per_cu"] == rep["wg_per_cu"]
     assert rep["ms"] <= rep["ms_default"]
     eager = [e.cpu().numpy() for e in ctx.fragment_eri(cdev, "bf16x3")]
     for f in range(len(frags)):
@@ -84,7 +87,7 @@ def test_ring_pipeline_equals_two_stage_bitwise(name, prec):
     ctx.coulomb_kernel(prec)
     cdev = [torch.from_numpy(f).cuda() for f in frags]
     nh = (cfg.n_k + sum(1 for q in range(cfg.n_k) if _self_conj(q, cfg.kmesh))) // 2
-    nl = -(-nh // 12)
+    nl = -(-nh // ctx.stats()["eri_qgroup_initial"])
     g = -(-nh // nl)                        # the initial tiling's classes per launch
     ctx.set_tiling(g, 2)
     two = [e.cpu().numpy() for e in ctx.fragment_eri(cdev, prec)]
@@ -95,3 +98,20 @@ def test_ring_pipeline_equals_two_stage_bitwise(name, prec):
         assert np.array_equal(ring[f], two[f]), (f, frags[f].shape[2])
         assert np.array_equal(ring2[f], two[f]), f
     ctx.close()
+
+
+def test_initial_classes_per_launch():
+    """The initial classes per ERI launch: the most, at most 12, whose K range
+    of one operand row (8 bytes an element) stays within 72 KB: 12 up to 768
+    interpolation points, 11 at 800, 8 at 1040."""
+    import paper_2601_16379_amd as pkg
+    rng = np.random.default_rng(5)
+    lat = 6.0 * np.eye(3)
+    grid = (16, 16, 16)
+    orb = (rng.standard_normal((1, 4, 4096)) + 1j * rng.standard_normal((1, 4, 4096))).astype(np.complex128)
+    for n_ip, want in ((520, 12), (768, 12), (800, 11), (1040, 8)):
+        ctx = pkg.Isdf(lat, grid, (1, 1, 1), orb, np.arange(n_ip, dtype=np.int32) * 3)
+        st = ctx.stats()
+        print("n_ip %d: %d classes a launch" % (n_ip, st["eri_qgroup_initial"]), flush=True)
+        assert st["eri_qgroup_initial"] == want and st["eri_qgroup"] == want and st["wg_per_cu"] == 2
+        ctx.close()
