@@ -1278,10 +1278,18 @@ void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn
   while (ti > 1 && (long long)nk * ti > tile_cap) ti >>= 1;
   int tp = 1;   // power of two (the LDS transform needs tp * ti to be one)
   while (tp < 8 && (long long)nk * ti * tp * 2 <= tile_cap) tp *= 2;
+  int ipair = 0;
   if (pair_lines_supported(prec, c->m[0], c->m[1], c->m[2])) {
-    // the line transform: one value a thread an axis pass
+    // the line transform: one value a thread an axis pass.  A tile whose LDS
+    // would leave one workgroup a CU (the 10^3 mesh: 129 KB at 16 points) is
+    // halved, the halves of each 16-point range run by neighbouring
+    // workgroups (ipair; 86.6 against 91.1 ms a step at the 1000-k workload)
     ti = std::min(32, pair_lines_wmax(c->m[0], c->m[1], c->m[2]));
     tp = 1;
+    if (ti >= 16 && pair_lines_lds(c->m[0], c->m[1], c->m[2], ti) > 80 * 1024) {
+      ti /= 2;
+      ipair = 1;
+    }
   }
   const bool reg = pair_reg_supported(prec, c->m[0], c->m[1], c->m[2]);
   const long long nchunk = (ld + 63) / 64;
@@ -1356,6 +1364,7 @@ void enqueue_batch(isdf_ctx c, Workspace& ws, int prec, const std::vector<FragIn
     a.fmt = prec;
     a.m1 = c->m[0]; a.m2 = c->m[1]; a.m3 = c->m[2];
     a.scale = 1.0 / std::sqrt((double)nk);
+    a.ipair = ipair;
     if (reg) {
       a.item_off = t.item_off;
       a.nfrag = (int)fr.size();

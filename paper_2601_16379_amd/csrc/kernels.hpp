@@ -207,6 +207,10 @@ struct PairArgs {
   long long nitems;
   int m1, m2, m3;
   double scale;
+  // line path: 1 = consecutive workgroups take the two halves (ti points
+  // each) of one 2 ti point range, so that two neighbouring workgroups
+  // complete each 2 ti x 8-byte line of psi and of the output between them
+  int ipair;
 };
 hipError_t pair_launch(const PairArgs& a, hipStream_t s);
 
@@ -233,6 +237,8 @@ constexpr int pair_lines_wmax(int m1, int m2, int m3) {
   while (w < 16 && nk / mn * w * 2 <= 2048 && m1 * m2 * (m3 * w * 2 + 1) * 8 <= 160 * 1024) w *= 2;
   return w;
 }
+// LDS bytes of one line pair-transform tile of w values a mesh point
+constexpr long long pair_lines_lds(int m1, int m2, int m3, int w) { return (long long)m1 * m2 * (m3 * w + 1) * 8; }
 
 // ---------------------------------------------------------------------------
 // Unit-cell grid FFT of f_{q,I}(r) exp(-i q.r) with the Coulomb factor

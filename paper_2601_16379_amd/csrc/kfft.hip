@@ -816,7 +816,11 @@ __global__ __launch_bounds__(256) void pair32_kernel(PairArgs a) {
 // transformed and written straight to the operand format: two LDS passes
 // and two barriers a tile.  Tiles are mapped XCD-contiguously (workgroup b
 // on XCD b mod 8 takes a contiguous range), so that consecutive pair blocks
-// of one point tile, which share orbitals, are read through one L2.
+// of one point tile, which share orbitals, are read through one L2.  With
+// ipair the point tiles come in pairs (the two halves of a 2 ti range,
+// neighbours in that order): half tiles, whose LDS lets two workgroups
+// share a CU, still read and write whole cache lines between two
+// workgroups that run together.
 template <int M1, int M2, int M3>
 __global__ __launch_bounds__(1024) void pair_lines_kernel(PairArgs a, int ntot) {
   extern __shared__ float2 pl[];
@@ -824,7 +828,15 @@ __global__ __launch_bounds__(1024) void pair_lines_kernel(PairArgs a, int ntot) 
   const int per = (ntot + 7) >> 3;
   const int v = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
   if (v >= ntot) return;
-  const int blk = v % a.nblocks, it = v / a.nblocks;
+  int blk, it;
+  if (a.ipair) {
+    const int rest = v >> 1;
+    blk = rest % a.nblocks;
+    it = (rest / a.nblocks) * 2 + (v & 1);
+  } else {
+    blk = v % a.nblocks;
+    it = v / a.nblocks;
+  }
   const PairBlock pb = a.blocks[blk];
   const int nf = a.frag_nf[pb.frag];
   const int col = a.frag_col[pb.frag];
@@ -899,7 +911,8 @@ template <int M1, int M2, int M3>
 hipError_t pair_lines_launch(const PairArgs& a, hipStream_t s) {
   constexpr int NK = M1 * M2 * M3;
   const int w = a.tp * a.ti;
-  const long long ntot = (long long)a.nblocks * a.n_itiles;
+  // with ipair, point tiles in pairs (an odd count gains one empty tile)
+  const long long ntot = (long long)a.nblocks * (a.ipair ? (a.n_itiles + 1) / 2 * 2 : a.n_itiles);
   if (ntot <= 0) return hipSuccess;
   if (ntot > (1LL << 30) || w > pair_lines_wmax(M1, M2, M3)) return hipErrorInvalidValue;
   const int lmax = NK / (M1 < M2 ? (M1 < M3 ? M1 : M3) : (M2 < M3 ? M2 : M3)) * w;
