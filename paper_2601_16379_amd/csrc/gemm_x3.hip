@@ -346,6 +346,29 @@ __device__ inline void stage_mma(const Frag<NI, NJ>& f, f16v (&c_re)[NI][NJ], f1
   }
 }
 
+// The same with a triangular B (U^q in the factor form, kind 2): a column
+// block whose B rows are all zero over the stage's k range (live0 / live1
+// false) is skipped; it would add exact zeros.
+template <int F, int NI, int NJ, bool A_CONJ, bool B_CONJ>
+__device__ inline void stage_mma_tri(const Frag<NI, NJ>& f, f16v (&c_re)[NI][NJ], f16v (&c_im)[NI][NJ],
+                                     bool live0, bool live1) {
+  if constexpr (F == 2) {
+    if (live0) mma_half<NI, NJ, A_CONJ, B_CONJ>(f, 0, c_re, c_im);
+    if (NJ == 2 && live1) mma_half<NI, NJ, A_CONJ, B_CONJ>(f, NJ - 1, c_re, c_im);
+  } else {
+    if (live0) mma_single<NI, NJ, A_CONJ, B_CONJ>(f, 0, c_re, c_im);
+    if (NJ == 2 && live1) mma_single<NI, NJ, A_CONJ, B_CONJ>(f, NJ - 1, c_re, c_im);
+  }
+}
+
+// With a triangular B (B[n][k] = 0 for k < n; the K range starts at the
+// tile's first column), column block j of the wave (columns cb0 + 32 j on)
+// has only zeros in B over stage s when (s + 1) SK <= cb0 + 32 j.
+__device__ inline void tri_live(bool tri, int s, int sk, int cb0, bool& l0, bool& l1) {
+  l0 = !tri || (s + 1) * sk > cb0;
+  l1 = !tri || (s + 1) * sk > cb0 + 32;
+}
+
 // K loop and epilogue of one tile.  The wave owns the (NI*32) x (NJ*32)
 // block at rows rb0, columns cb0 of the tile: 64 x 64 in full tiles (2 x 2
 // waves); in tiles with at most 32 valid rows (columns) each wave takes a
@@ -354,7 +377,7 @@ __device__ inline void stage_mma(const Frag<NI, NJ>& f, f16v (&c_re)[NI][NJ], f1
 // each): two LDS stages, each stage's fragments read from LDS at its start
 // (the waves of the other workgroup keep the matrix cores busy meanwhile),
 // copies one stage ahead, one barrier a stage.
-template <int F, int NI, int NJ, bool A_CONJ, bool B_CONJ>
+template <int F, int NI, int NJ, bool A_CONJ, bool B_CONJ, bool TRI>
 __device__ inline void tile_body(const NtDesc& d, int b, int m0, int n0, int kcur,
                                  const unsigned short* const (&asrc)[NCOPY], const unsigned short* const (&bsrc)[NCOPY],
                                  const int (&gslot)[NCOPY], int rb0, int cb0, char* smem, int wave, int lane,
@@ -392,7 +415,13 @@ __device__ inline void tile_body(const NtDesc& d, int b, int m0, int n0, int kcu
     read_frags_b<F>(buf, f, cb0, lr, lk);
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     settle(f);
-    if (!idle) stage_mma<F, NI, NJ, A_CONJ, B_CONJ>(f, c_re, c_im);
+    if constexpr (TRI) {
+      bool l0, l1;
+      tri_live(d.ktri != 0, s, SK, cb0, l0, l1);
+      if (!idle) stage_mma_tri<F, NI, NJ, A_CONJ, B_CONJ>(f, c_re, c_im, l0, l1);
+    } else {
+      if (!idle) stage_mma<F, NI, NJ, A_CONJ, B_CONJ>(f, c_re, c_im);
+    }
   }
   if (!idle) tile_epilogue<F, NI, NJ>(d, b, m0, n0, rb0, cb0, c_re, c_im, smem, wave, lane, first);
 }
@@ -403,8 +432,8 @@ __device__ inline void tile_body(const NtDesc& d, int b, int m0, int n0, int kcu
 // everyone's), and every wave has read stage s, so its buffer takes the
 // copies of stage s + RING.  One barrier a stage; the copies run up to
 // RING - 1 stages ahead of the MFMAs.
-template <int F, int NI, int NJ, bool A_CONJ, bool B_CONJ>
-__device__ inline void ring_step(int s, int nst, int kcur, Frag<NI, NJ>& cur, Frag<NI, NJ>& nxt,
+template <int F, int NI, int NJ, bool A_CONJ, bool B_CONJ, bool TRI>
+__device__ inline void ring_step(int s, int nst, int kcur, bool tri, Frag<NI, NJ>& cur, Frag<NI, NJ>& nxt,
                                  f16v (&c_re)[NI][NJ], f16v (&c_im)[NI][NJ],
                                  const unsigned short* const (&asrc)[NCOPY],
                                  const unsigned short* const (&bsrc)[NCOPY], const int (&gslot)[NCOPY],
@@ -426,7 +455,13 @@ __device__ inline void ring_step(int s, int nst, int kcur, Frag<NI, NJ>& cur, Fr
     read_frags_a<F>(nb, nxt, rb0, lr, lk);
     read_frags_b<F>(nb, nxt, cb0, lr, lk);
   }
-  if (!idle) stage_mma<F, NI, NJ, A_CONJ, B_CONJ>(cur, c_re, c_im);
+  if constexpr (TRI) {
+    bool l0, l1;
+    tri_live(tri, s, SK, cb0, l0, l1);
+    if (!idle) stage_mma_tri<F, NI, NJ, A_CONJ, B_CONJ>(cur, c_re, c_im, l0, l1);
+  } else {
+    if (!idle) stage_mma<F, NI, NJ, A_CONJ, B_CONJ>(cur, c_re, c_im);
+  }
   if (more) {
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     settle(nxt);
@@ -435,7 +470,7 @@ __device__ inline void ring_step(int s, int nst, int kcur, Frag<NI, NJ>& cur, Fr
 
 // K loop and epilogue of one tile on the ring pipeline (same blocks, MFMA
 // order and epilogues as tile_body, so the same results bit for bit).
-template <int F, int NI, int NJ, bool A_CONJ, bool B_CONJ>
+template <int F, int NI, int NJ, bool A_CONJ, bool B_CONJ, bool TRI>
 __device__ inline void tile_body_ring(const NtDesc& d, int b, int m0, int n0, int kcur,
                                       const unsigned short* const (&asrc)[NCOPY],
                                       const unsigned short* const (&bsrc)[NCOPY], const int (&gslot)[NCOPY],
@@ -470,11 +505,11 @@ __device__ inline void tile_body_ring(const NtDesc& d, int b, int m0, int n0, in
   asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
   settle(f0);
   for (int s = 0; s < nst; s += 2) {
-    ring_step<F, NI, NJ, A_CONJ, B_CONJ>(s, nst, kcur, f0, f1, c_re, c_im, asrc, bsrc, gslot, rb0, cb0, smem, wave,
-                                         lr, lk, idle);
+    ring_step<F, NI, NJ, A_CONJ, B_CONJ, TRI>(s, nst, kcur, d.ktri != 0, f0, f1, c_re, c_im, asrc, bsrc, gslot, rb0,
+                                              cb0, smem, wave, lr, lk, idle);
     if (s + 1 < nst)
-      ring_step<F, NI, NJ, A_CONJ, B_CONJ>(s + 1, nst, kcur, f1, f0, c_re, c_im, asrc, bsrc, gslot, rb0, cb0, smem,
-                                           wave, lr, lk, idle);
+      ring_step<F, NI, NJ, A_CONJ, B_CONJ, TRI>(s + 1, nst, kcur, d.ktri != 0, f1, f0, c_re, c_im, asrc, bsrc, gslot,
+                                                rb0, cb0, smem, wave, lr, lk, idle);
   }
   if (!idle) tile_epilogue<F, NI, NJ>(d, b, m0, n0, rb0, cb0, c_re, c_im, smem, wave, lane, first);
 }
@@ -491,7 +526,7 @@ __device__ inline void tile_body_ring(const NtDesc& d, int b, int m0, int n0, in
 // each): two LDS stages, each stage's fragments read from LDS at its start
 // (the waves of the other workgroup keep the matrix cores busy meanwhile),
 // copies two stages ahead.
-template <int F, int NI, int NJ, bool A_CONJ, bool B_CONJ>
+template <int F, int NI, int NJ, bool A_CONJ, bool B_CONJ, bool TRI>
 __device__ inline void tile_body_2b(const NtDesc& d, int b, int m0, int n0, int kcur,
                                  const unsigned short* const (&asrc)[NCOPY], const unsigned short* const (&bsrc)[NCOPY],
                                  const int (&gslot)[NCOPY], int rb0, int cb0, char* smem, int wave, int lane,
@@ -534,7 +569,11 @@ __device__ inline void tile_body_2b(const NtDesc& d, int b, int m0, int n0, int 
       stage_copy<F>(asrc, gslot, (s + NBUF) * SK, kcur, buf, wave);
       stage_copy<F>(bsrc, gslot, (s + NBUF) * SK, kcur, buf + OPER_B, wave);
     }
-    if (!idle) {
+    if constexpr (TRI) {
+      bool l0, l1;
+      tri_live(d.ktri != 0, s, SK, cb0, l0, l1);
+      if (!idle) stage_mma_tri<F, NI, NJ, A_CONJ, B_CONJ>(f, c_re, c_im, l0, l1);
+    } else if (!idle) {
       if constexpr (F == 2) {
         mma_half<NI, NJ, A_CONJ, B_CONJ>(f, 0, c_re, c_im);
         if (NJ == 2) mma_half<NI, NJ, A_CONJ, B_CONJ>(f, NJ - 1, c_re, c_im);
@@ -609,33 +648,33 @@ __device__ inline void x3_tiles(const NtDesc* __restrict__ descs, int ndesc, lon
     const bool first = seg == 0;
     if constexpr (RINGP) {
       if (d.M - m0 <= 32)
-        tile_body_ring<F, 1, 1, A_CONJ, B_CONJ>(d, b, m0, n0, kcur, asrc, bsrc, gslot, 0, wave * 32, smem, wave,
+        tile_body_ring<F, 1, 1, A_CONJ, B_CONJ, KIND == 2>(d, b, m0, n0, kcur, asrc, bsrc, gslot, 0, wave * 32, smem, wave,
                                                 lane, diag && wave > 0, first);
       else if (d.N - n0 <= 32)
-        tile_body_ring<F, 1, 1, A_CONJ, B_CONJ>(d, b, m0, n0, kcur, asrc, bsrc, gslot, wave * 32, 0, smem, wave,
+        tile_body_ring<F, 1, 1, A_CONJ, B_CONJ, KIND == 2>(d, b, m0, n0, kcur, asrc, bsrc, gslot, wave * 32, 0, smem, wave,
                                                 lane, false, first);
       else
-        tile_body_ring<F, 2, 2, A_CONJ, B_CONJ>(d, b, m0, n0, kcur, asrc, bsrc, gslot, wm * 64, wn * 64, smem,
+        tile_body_ring<F, 2, 2, A_CONJ, B_CONJ, KIND == 2>(d, b, m0, n0, kcur, asrc, bsrc, gslot, wm * 64, wn * 64, smem,
                                                 wave, lane, diag && wm < wn, first);
     } else if constexpr (TWOB) {
       if (d.M - m0 <= 32)
-        tile_body_2b<F, 1, 1, A_CONJ, B_CONJ>(d, b, m0, n0, kcur, asrc, bsrc, gslot, 0, wave * 32, smem, wave, lane,
+        tile_body_2b<F, 1, 1, A_CONJ, B_CONJ, KIND == 2>(d, b, m0, n0, kcur, asrc, bsrc, gslot, 0, wave * 32, smem, wave, lane,
                                               diag && wave > 0, first);
       else if (d.N - n0 <= 32)
-        tile_body_2b<F, 1, 1, A_CONJ, B_CONJ>(d, b, m0, n0, kcur, asrc, bsrc, gslot, wave * 32, 0, smem, wave, lane,
+        tile_body_2b<F, 1, 1, A_CONJ, B_CONJ, KIND == 2>(d, b, m0, n0, kcur, asrc, bsrc, gslot, wave * 32, 0, smem, wave, lane,
                                               false, first);
       else
-        tile_body_2b<F, 2, 2, A_CONJ, B_CONJ>(d, b, m0, n0, kcur, asrc, bsrc, gslot, wm * 64, wn * 64, smem, wave,
+        tile_body_2b<F, 2, 2, A_CONJ, B_CONJ, KIND == 2>(d, b, m0, n0, kcur, asrc, bsrc, gslot, wm * 64, wn * 64, smem, wave,
                                               lane, diag && wm < wn, first);
     } else {
       if (d.M - m0 <= 32)
-        tile_body<F, 1, 1, A_CONJ, B_CONJ>(d, b, m0, n0, kcur, asrc, bsrc, gslot, 0, wave * 32, smem, wave, lane,
+        tile_body<F, 1, 1, A_CONJ, B_CONJ, KIND == 2>(d, b, m0, n0, kcur, asrc, bsrc, gslot, 0, wave * 32, smem, wave, lane,
                                            diag && wave > 0, first);
       else if (d.N - n0 <= 32)
-        tile_body<F, 1, 1, A_CONJ, B_CONJ>(d, b, m0, n0, kcur, asrc, bsrc, gslot, wave * 32, 0, smem, wave, lane,
+        tile_body<F, 1, 1, A_CONJ, B_CONJ, KIND == 2>(d, b, m0, n0, kcur, asrc, bsrc, gslot, wave * 32, 0, smem, wave, lane,
                                            false, first);
       else
-        tile_body<F, 2, 2, A_CONJ, B_CONJ>(d, b, m0, n0, kcur, asrc, bsrc, gslot, wm * 64, wn * 64, smem, wave,
+        tile_body<F, 2, 2, A_CONJ, B_CONJ, KIND == 2>(d, b, m0, n0, kcur, asrc, bsrc, gslot, wm * 64, wn * 64, smem, wave,
                                            lane, diag && wm < wn, first);
     }
   }
