@@ -317,9 +317,11 @@ isdf_status isdf_graph_destroy(isdf_graph g);
  * workgroups per CU --, twice each after a
  * warm-up, keeps the fastest for this context and, when `report` is not
  * NULL, fills it.  One workgroup per CU selects the ring pipeline of the
- * mixed-precision fragment GEMMs (four LDS stages, the next stage's
- * fragments read during the current stage's MFMAs, one barrier a stage);
- * its results equal those of the two-stage pipeline bit for bit.  The eri[f]
+ * mixed-precision contraction (four LDS stages, the next stage's fragments
+ * read during the current stage's MFMAs, one barrier a stage); its results
+ * equal those of the two-stage pipeline bit for bit.  U^q keeps its own
+ * pipeline whatever the tiling: two-stage with two workgroups a CU in
+ * bf16x3, the ring in single bf16.  The eri[f]
  * hold the last candidate's results afterwards.  isdf_set_tiling sets the two
  * values directly (wg_per_cu 0 = 8 per CU).  A context starts at the most
  * classes a launch, at most 12, whose K range of one operand row in the
