@@ -69,6 +69,8 @@ def parse():
                     help="small cells: skip the fragment-batch comparison (eager / HIP graph / tuned tiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=25.0)
+    ap.add_argument("--max-inflight", type=int, default=0,
+                    help="batches in flight at once in the served stream (0: 1 for the stream slices)")
     ap.add_argument("--max-batch", type=int, default=0,
                     help="fragments per serving batch (0: all of a step in one batch)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -603,7 +605,7 @@ def run_stream(args, cfg, pkg, inp, np, torch):
     if args.wg_per_cu or args.qgroup:
         # defaults: the context's initial tiling
         ctx.set_tiling(args.qgroup or st["eri_qgroup_initial"], args.wg_per_cu or 2)
-    ctx.serve_start(max_inflight=1, max_batch=args.max_batch or S, budget_bytes=budget)
+    ctx.serve_start(max_inflight=args.max_inflight or 1, max_batch=args.max_batch or S, budget_bytes=budget)
 
     def step(sl, prec, buf):
         return poll_all(ctx, ctx.submit_n([coeffs[f] for f in sl], outs_of(sl, buf), prec))
