@@ -279,6 +279,9 @@ __device__ inline void fft_axis(cplx* buf, cplx* tmp, const cplx* tw, int nlines
   else fft_lines_c<N, L1, S1, S2, ES>(buf, tmp, tw, nlines);
 }
 
+// The Bloch phase exp(-2 pi i (qf0 i1 + qf1 i2 + qf2 i3) / N) of a slab is
+// the product of an (i1, i2) factor and an i3 factor, 2 N values a slab
+// computed once into LDS (a sine and cosine per value, not per point).
 template <int N>
 __global__ __launch_bounds__(256) void slab_kernel_c(GridFftArgs a, int S) {
   constexpr int N2 = N * N;
@@ -286,74 +289,110 @@ __global__ __launch_bounds__(256) void slab_kernel_c(GridFftArgs a, int S) {
   cplx* buf = sm;
   cplx* tmp = sm + S * N2;
   cplx* tw = tmp + S * N2;
+  cplx* ph = tw + N;                    // [S][2N]: (i1, i2) factors, then i3 factors
   for (int t = threadIdx.x; t < N; t += blockDim.x) tw[t] = cexpipi(-2.0 * t / N);
   const long long nslab = (long long)a.nq * a.n_ip * N;
   const long long s0 = (long long)blockIdx.x * S;
   const int ns = (int)((nslab - s0) < S ? (nslab - s0) : S);
-  for (int idx = threadIdx.x; idx < ns * N2; idx += blockDim.x) {
-    const int s = idx / N2, p = idx % N2;
+  for (int t = threadIdx.x; t < ns * 2 * N; t += blockDim.x) {
+    const int s = t / (2 * N), r = t % (2 * N);
+    const long long slab = s0 + s;
+    const int i1 = (int)(slab % N);
+    const int qi = (int)(slab / N / a.n_ip);
+    double qf[3];
+    q_frac(a, q_of(a, qi), qf);
+    ph[t] = r < N ? cexpipi(-2.0 * (qf[0] * i1 + qf[1] * r) / N) : cexpipi(-2.0 * (qf[2] * (r - N)) / N);
+  }
+  __syncthreads();
+  for (int s = 0; s < ns; ++s) {
     const long long slab = s0 + s;
     const int i1 = (int)(slab % N);
     const long long qI = slab / N;
     const int I = (int)(qI % a.n_ip);
     const int qi = (int)(qI / a.n_ip);
-    double qf[3];
-    q_frac(a, q_of(a, qi), qf);
-    const int i2 = p / N, i3 = p % N;
-    const double ph = (qf[0] * i1 + qf[1] * i2 + qf[2] * i3) / N;
-    const cplx v = a.data[(long long)qi * a.q_stride + ((long long)I * N + i1) * N2 + p];
-    buf[idx] = cmul(v, cexpipi(-2.0 * ph));
+    const cplx* src = a.data + (long long)qi * a.q_stride + ((long long)I * N + i1) * N2;
+    const cplx* phs = ph + s * 2 * N;
+    for (int p = threadIdx.x; p < N2; p += blockDim.x) {
+      const int i2 = p / N, i3 = p % N;
+      buf[s * N2 + p] = cmul(src[p], cmul(phs[i2], phs[N + i3]));
+    }
   }
   __syncthreads();
   fft_axis<N, 1, N, 0, 1>(buf, tmp, tw, ns * N);    // along i3
   fft_axis<N, N, N2, 1, N>(buf, tmp, tw, ns * N);   // along i2
-  for (int idx = threadIdx.x; idx < ns * N2; idx += blockDim.x) {
-    const int s = idx / N2, p = idx % N2;
+  for (int s = 0; s < ns; ++s) {
     const long long slab = s0 + s;
     const int i1 = (int)(slab % N);
     const long long qI = slab / N;
     const int I = (int)(qI % a.n_ip);
     const int qi = (int)(qI / a.n_ip);
-    a.data[(long long)qi * a.q_stride + ((long long)I * N + i1) * N2 + p] = buf[idx];
+    cplx* dst = a.data + (long long)qi * a.q_stride + ((long long)I * N + i1) * N2;
+    for (int p = threadIdx.x; p < N2; p += blockDim.x) dst[p] = buf[s * N2 + p];
   }
 }
 
+// One workgroup takes a block of COLS_C columns of one q for up to `ipb`
+// interpolation points in turn: the Coulomb factor of its elements depends on
+// (q, i1, column) only, so it is formed once and kept in registers.  32
+// columns (512-byte rows) keep the LDS at 42 KB for N = 40, three workgroups
+// a CU.
+constexpr int COLS_C = 32;
 template <int N>
-__global__ __launch_bounds__(256) void col_kernel_c(GridFftArgs a) {
+__global__ __launch_bounds__(256) void col_kernel_c(GridFftArgs a, int ipb) {
   constexpr int N2 = N * N;
-  constexpr int NCB = (N2 + COLS - 1) / COLS;
+  constexpr int NCB = (N2 + COLS_C - 1) / COLS_C;
+  constexpr int PER = (N * COLS_C + 255) / 256;   // elements of a thread
   extern __shared__ cplx sm[];
   cplx* buf = sm;
-  cplx* tmp = sm + N * COLS;
-  cplx* tw = tmp + N * COLS;
+  cplx* tmp = sm + N * COLS_C;
+  cplx* tw = tmp + N * COLS_C;
   for (int t = threadIdx.x; t < N; t += blockDim.x) tw[t] = cexpipi(-2.0 * t / N);
   const int cb = blockIdx.x % NCB;
-  const long long qI = blockIdx.x / NCB;
-  const int I = (int)(qI % a.n_ip);
-  const int qi = (int)(qI / a.n_ip);
-  const int c0 = cb * COLS;
-  const int nc = (N2 - c0) < COLS ? (N2 - c0) : COLS;
-  cplx* base = a.data + (long long)qi * a.q_stride + (long long)I * N * N2;
-  for (int idx = threadIdx.x; idx < N * COLS; idx += blockDim.x) {
-    const int i1 = idx / COLS, c = idx % COLS;
-    buf[idx] = (c < nc) ? base[(long long)i1 * N2 + c0 + c] : cmk(0.0, 0.0);
-  }
-  __syncthreads();
-  fft_axis<N, 1, 1, 0, COLS>(buf, tmp, tw, COLS);   // along i1
+  const long long rest = blockIdx.x / NCB;
+  const int nib = (a.n_ip + ipb - 1) / ipb;
+  const int ib = (int)(rest % nib);
+  const int qi = (int)(rest / nib);
+  const int I0 = ib * ipb, I1 = min(I0 + ipb, a.n_ip);
+  const int c0 = cb * COLS_C;
+  const int nc = (N2 - c0) < COLS_C ? (N2 - c0) : COLS_C;
   int jw[3];
   q_wrapped(a, q_of(a, qi), jw);
   const double coef = sqrt(4.0 * M_PI * a.volume) / ((double)N * N2);
-  for (int idx = threadIdx.x; idx < N * COLS; idx += blockDim.x) {
-    const int i1 = idx / COLS, c = idx % COLS;
-    if (c >= nc) continue;
-    const int col = c0 + c;
-    double x[3];
-    bool t[3];
-    x[0] = k_axis(i1, jw[0], N, a.m1, t[0]);
-    x[1] = k_axis(col / N, jw[1], N, a.m2, t[1]);
-    x[2] = k_axis(col % N, jw[2], N, a.m3, t[2]);
-    const double f = coef * sqrt(inv_k2_mean(x, t, a.recip));
-    base[(long long)i1 * N2 + col] = cscale(buf[idx], f);
+  double fac[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int idx = threadIdx.x + 256 * u;
+    fac[u] = 0.0;
+    const int i1 = idx / COLS_C, c = idx % COLS_C;
+    if (idx < N * COLS_C && c < nc) {
+      const int col = c0 + c;
+      double x[3];
+      bool t[3];
+      x[0] = k_axis(i1, jw[0], N, a.m1, t[0]);
+      x[1] = k_axis(col / N, jw[1], N, a.m2, t[1]);
+      x[2] = k_axis(col % N, jw[2], N, a.m3, t[2]);
+      fac[u] = coef * sqrt(inv_k2_mean(x, t, a.recip));
+    }
+  }
+  for (int I = I0; I < I1; ++I) {
+    cplx* base = a.data + (long long)qi * a.q_stride + (long long)I * N * N2;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int idx = threadIdx.x + 256 * u;
+      if (idx < N * COLS_C) {
+        const int i1 = idx / COLS_C, c = idx % COLS_C;
+        buf[idx] = (c < nc) ? base[(long long)i1 * N2 + c0 + c] : cmk(0.0, 0.0);
+      }
+    }
+    __syncthreads();
+    fft_axis<N, 1, 1, 0, COLS_C>(buf, tmp, tw, COLS_C);   // along i1
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int idx = threadIdx.x + 256 * u;
+      const int i1 = idx / COLS_C, c = idx % COLS_C;
+      if (idx < N * COLS_C && c < nc) base[(long long)i1 * N2 + c0 + c] = cscale(buf[idx], fac[u]);
+    }
+    __syncthreads();                      // buf is read before the next point's loads
   }
 }
 
@@ -362,10 +401,10 @@ hipError_t launch_cubic(const GridFftArgs& a, hipStream_t s) {
   constexpr int N2 = N * N;
   int S = 2048 / N2;
   if (S < 1) S = 1;
-  size_t ldsA = (2 * (size_t)S * N2 + N) * sizeof(cplx);
+  size_t ldsA = (2 * (size_t)S * N2 + N + 2 * (size_t)S * N) * sizeof(cplx);
   while (ldsA > 150 * 1024 && S > 1) {
     --S;
-    ldsA = (2 * (size_t)S * N2 + N) * sizeof(cplx);
+    ldsA = (2 * (size_t)S * N2 + N + 2 * (size_t)S * N) * sizeof(cplx);
   }
   if (ldsA > 160 * 1024) return hipErrorInvalidValue;
   const long long nslab = (long long)a.nq * a.n_ip * N;
@@ -373,10 +412,14 @@ hipError_t launch_cubic(const GridFftArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(slab_kernel_c<N>, dim3((unsigned)((nslab + S - 1) / S)), dim3(256), ldsA, s, a, S);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const size_t ldsB = (2 * (size_t)N * COLS + N) * sizeof(cplx);
+  const size_t ldsB = (2 * (size_t)N * COLS_C + N) * sizeof(cplx);
   if (ldsB > 160 * 1024) return hipErrorInvalidValue;
-  const long long ncb = (N2 + COLS - 1) / COLS;
-  hipLaunchKernelGGL(col_kernel_c<N>, dim3((unsigned)(ncb * a.nq * a.n_ip)), dim3(256), ldsB, s, a);
+  const long long ncb = (N2 + COLS_C - 1) / COLS_C;
+  const int ipb = 8;                    // interpolation points a workgroup (Coulomb factor reused)
+  const long long nib = (a.n_ip + ipb - 1) / ipb;
+  const long long nblk = ncb * a.nq * nib;
+  if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(col_kernel_c<N>, dim3((unsigned)nblk), dim3(256), ldsB, s, a, ipb);
   return hipGetLastError();
 }
 
